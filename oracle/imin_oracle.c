@@ -1,0 +1,572 @@
+/*
+ * CPU oracle for the sampling estimator of influence minimization by node
+ * blocking (Wang et al., "Efficient Influence Minimization via Node
+ * Blocking", PVLDB).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file exists to check the GPU library.  It
+ * is plain, slow and written for a reader holding the paper: every function
+ * follows one passage and cites it.  It shares no code, header, table or
+ * constant with the GPU path; only the tests, the smoke check and the CPU leg
+ * of the benchmark load it.
+ *
+ * What it computes, per query (G, p, S, k, theta, rng_seed):
+ *
+ *   thr[e]     integer coin threshold of edge e from its float32 probability
+ *              (the live-edge process of Section 2.1, Eq. 1: an edge is kept
+ *              with probability p(u, v)); p == 1 is "always live", otherwise
+ *              thr = floor(p * 2^32) computed exactly in double.
+ *   coin(w,e)  word (e mod 4) of Philox4x32-10 (Salmon et al., SC'11) at
+ *              counter (floor(e/4), w, 0, 0), key (lo32(seed), hi32(seed));
+ *              edge e is live in world w iff thr[e] is "always live" or
+ *              coin < thr[e].
+ *   R_w(B)     nodes reachable from S in world w once the blockers B are
+ *              removed (Section 2.1: a blocker's in-edges get probability 0;
+ *              blockers are never seeds; the spread counts S itself).
+ *   c_w(u|B)   |R_w(B)| - |R_w(B + u)|: the nodes that u protects.  By the
+ *              dominator-tree lemma quoted in Section 2.2 this equals the size
+ *              of u's subtree in the dominator tree of world w rooted at the
+ *              virtual source s, whose edges to every seed have probability 1
+ *              (Section 3.1).  It counts u itself (Example 1).
+ *   gain_r[u]  sum over worlds w < theta of c_w(u|B_r)   (Section 2.2, the
+ *              estimator of Xie et al.: D_s(u) is estimated by the average
+ *              subtree size; the sum is that average times theta).
+ *   T_r        sum over worlds of |R_w(B_r)|.
+ *   greedy     the greedy framework of Section 2.2 (AdvancedGreedy): k
+ *              iterations, each adding argmax_u gain_r[u] over V \ (S + B_r),
+ *              ties to the smaller id; stop early when no candidate is left
+ *              or the best gain is 0 ("at most k" blockers, problem
+ *              statement).  Worlds are shared by every round.
+ *
+ * Two ways to get c_w are provided and must agree:
+ *   mode 0 (dominator): breadth-first reachability, then the iterative
+ *          dominator algorithm of Cooper, Harvey and Kennedy ("A Simple, Fast
+ *          Dominance Algorithm", 2001) over the reached live subgraph plus
+ *          the virtual source, then subtree sizes;
+ *   mode 1 (definition): one extra reachability pass per reached candidate u.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, from Salmon, Moraes, Dror and Shaw, "Parallel random        */
+/* numbers: as easy as 1, 2, 3" (SC'11): a 4x32-bit counter, a 2x32-bit key,  */
+/* ten rounds of two 32x32->64 multiplies (multipliers 0xD2511F53 and         */
+/* 0xCD9E8D57) with the key bumped by the Weyl increments 0x9E3779B9 and      */
+/* 0xBB67AE85 between rounds.                                                 */
+/* ------------------------------------------------------------------------ */
+void oracle_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+    uint32_t x0 = ctr_in[0], x1 = ctr_in[1], x2 = ctr_in[2], x3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+        uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+        uint32_t y0 = hi1 ^ x1 ^ k0;
+        uint32_t y1 = lo1;
+        uint32_t y2 = hi0 ^ x3 ^ k1;
+        uint32_t y3 = lo0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Edge thresholds.  Section 2.1 keeps each edge with probability p(u, v).    */
+/* The coin is a uniform 32-bit word, so the edge is kept when the word is    */
+/* below floor(p * 2^32); p == 1 must always keep the edge, which no 32-bit   */
+/* word can express as a strict bound, so it gets the reserved value          */
+/* 0xFFFFFFFF ("always live").  The largest float32 below 1 maps to           */
+/* 0xFFFFFF00, so the reserved value is never produced by the floor.          */
+/* Returns -1 when every p is in [0, 1], else the first offending index.      */
+/* ------------------------------------------------------------------------ */
+#define ORACLE_ALWAYS_LIVE 0xFFFFFFFFu
+
+int64_t oracle_thresholds(int64_t m, const float* p, uint32_t* thr) {
+    for (int64_t e = 0; e < m; ++e) {
+        float pe = p[e];
+        if (!(pe >= 0.0f && pe <= 1.0f)) return e; /* also catches NaN */
+        if (pe == 1.0f) {
+            thr[e] = ORACLE_ALWAYS_LIVE;
+        } else {
+            double scaled = (double)pe * 4294967296.0; /* exact: 24-bit mantissa times 2^32 */
+            thr[e] = (uint32_t)scaled;                 /* truncation == floor for scaled >= 0 */
+        }
+    }
+    return -1;
+}
+
+uint32_t oracle_coin(uint64_t seed, uint64_t w, int64_t e) {
+    uint32_t ctr[4] = {(uint32_t)((uint64_t)e >> 2), (uint32_t)w, 0u, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, key, out);
+    return out[(uint64_t)e & 3u];
+}
+
+static int edge_live(uint32_t thr, uint64_t seed, uint64_t w, int64_t e) {
+    if (thr == ORACLE_ALWAYS_LIVE) return 1;
+    return oracle_coin(seed, w, e) < thr;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Query and per-thread scratch                                               */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n;
+    int64_t m;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const uint32_t* thr;
+    const int32_t* seeds;
+    int32_t n_seeds;
+    uint64_t rng_seed;
+} query_t;
+
+typedef struct {
+    int32_t n;
+    int32_t* stamp;     /* [n] world visit stamps                     */
+    int32_t stamp_now;
+    int32_t* local_of;  /* [n] node -> local id (1-based; 0 = root)  */
+    int32_t* queue;     /* [n] BFS order of reached nodes             */
+    uint8_t* blocked;   /* [n] private copy of the blocked set        */
+    /* live subgraph over local ids 0..R (0 = virtual source s) */
+    int64_t cap_e;
+    int32_t* e_src;
+    int32_t* e_dst;
+    int32_t* pred_off; /* [n+2] */
+    int32_t* pred;     /* [cap_e] */
+    int32_t* succ_off; /* [n+2] */
+    int32_t* succ;     /* [cap_e] */
+    int32_t* fill;     /* [n+2] */
+    int32_t* po;       /* [n+1] postorder number of each local id */
+    int32_t* rpo;      /* [n+1] local ids in reverse postorder     */
+    int32_t* idom;     /* [n+1] */
+    int32_t* size;     /* [n+1] dominator subtree sizes */
+    int32_t* stack;    /* [n+1] DFS stack: local ids */
+    int32_t* it;       /* [n+1] DFS stack: next successor index */
+    int32_t* c;        /* [n] per-node counts of the current world  */
+    int oom;
+} scratch_t;
+
+static void scratch_free(scratch_t* s) {
+    free(s->stamp); free(s->local_of); free(s->queue); free(s->blocked);
+    free(s->e_src); free(s->e_dst); free(s->pred_off); free(s->pred);
+    free(s->succ_off); free(s->succ); free(s->fill); free(s->po); free(s->rpo);
+    free(s->idom); free(s->size); free(s->stack); free(s->it); free(s->c);
+    memset(s, 0, sizeof(*s));
+}
+
+static int scratch_init(scratch_t* s, int32_t n, const uint8_t* blocked) {
+    memset(s, 0, sizeof(*s));
+    s->n = n;
+    size_t nn = (size_t)n + 2;
+    s->stamp = calloc(nn, sizeof(int32_t));
+    s->local_of = calloc(nn, sizeof(int32_t));
+    s->queue = calloc(nn, sizeof(int32_t));
+    s->blocked = calloc(nn, 1);
+    s->pred_off = calloc(nn + 1, sizeof(int32_t));
+    s->succ_off = calloc(nn + 1, sizeof(int32_t));
+    s->fill = calloc(nn + 1, sizeof(int32_t));
+    s->po = calloc(nn, sizeof(int32_t));
+    s->rpo = calloc(nn, sizeof(int32_t));
+    s->idom = calloc(nn, sizeof(int32_t));
+    s->size = calloc(nn, sizeof(int32_t));
+    s->stack = calloc(nn, sizeof(int32_t));
+    s->it = calloc(nn, sizeof(int32_t));
+    s->c = calloc(nn, sizeof(int32_t));
+    s->cap_e = 1024;
+    s->e_src = malloc(s->cap_e * sizeof(int32_t));
+    s->e_dst = malloc(s->cap_e * sizeof(int32_t));
+    s->pred = malloc(s->cap_e * sizeof(int32_t));
+    s->succ = malloc(s->cap_e * sizeof(int32_t));
+    if (!s->stamp || !s->local_of || !s->queue || !s->blocked || !s->pred_off || !s->succ_off ||
+        !s->fill || !s->po || !s->rpo || !s->idom || !s->size || !s->stack || !s->it || !s->c ||
+        !s->e_src || !s->e_dst || !s->pred || !s->succ) {
+        scratch_free(s);
+        return -1;
+    }
+    if (blocked) memcpy(s->blocked, blocked, (size_t)n);
+    return 0;
+}
+
+static int push_edge(scratch_t* s, int64_t* ne, int32_t a, int32_t b) {
+    if (*ne == s->cap_e) {
+        int64_t cap = s->cap_e * 2;
+        int32_t* p1 = realloc(s->e_src, cap * sizeof(int32_t));
+        if (p1) s->e_src = p1;
+        int32_t* p2 = realloc(s->e_dst, cap * sizeof(int32_t));
+        if (p2) s->e_dst = p2;
+        int32_t* p3 = realloc(s->pred, cap * sizeof(int32_t));
+        if (p3) s->pred = p3;
+        int32_t* p4 = realloc(s->succ, cap * sizeof(int32_t));
+        if (p4) s->succ = p4;
+        if (!p1 || !p2 || !p3 || !p4) { s->oom = 1; return -1; }
+        s->cap_e = cap;
+    }
+    s->e_src[*ne] = a;
+    s->e_dst[*ne] = b;
+    ++*ne;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* R_w(B): breadth-first search from S over live edges of world w, never     */
+/* entering a blocked node (Section 2.1, live-edge process and blocking;     */
+/* Section 3.1, the virtual source reaches every seed with probability 1).   */
+/* Fills s->queue with the reached nodes in BFS order and returns |R_w(B)|.  */
+/* ------------------------------------------------------------------------ */
+static int32_t reach(const query_t* q, scratch_t* s, uint64_t w) {
+    int32_t stamp = ++s->stamp_now;
+    int32_t head = 0, tail = 0;
+    for (int32_t i = 0; i < q->n_seeds; ++i) {
+        int32_t v = q->seeds[i];
+        if (s->stamp[v] != stamp) {
+            s->stamp[v] = stamp;
+            s->queue[tail++] = v;
+        }
+    }
+    while (head < tail) {
+        int32_t u = s->queue[head++];
+        for (int64_t e = q->row_ptr[u]; e < q->row_ptr[u + 1]; ++e) {
+            int32_t v = q->col[e];
+            if (s->blocked[v]) continue;
+            if (!edge_live(q->thr[e], q->rng_seed, w, e)) continue;
+            if (s->stamp[v] == stamp) continue;
+            s->stamp[v] = stamp;
+            s->queue[tail++] = v;
+        }
+    }
+    return tail;
+}
+
+/* Cooper-Harvey-Kennedy intersect: walk the two fingers up the current tree,  */
+/* always moving the one with the smaller postorder number.                    */
+static int32_t intersect(const int32_t* idom, const int32_t* po, int32_t a, int32_t b) {
+    while (a != b) {
+        while (po[a] < po[b]) a = idom[a];
+        while (po[b] < po[a]) b = idom[b];
+    }
+    return a;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mode 0: c_w(u|B) for every node as dominator-subtree sizes (Section 2.2,   */
+/* the estimator of Xie et al.: sample a realization, build its dominator     */
+/* tree rooted at s, measure every subtree).  Writes s->c[v] for all v in     */
+/* R_w (seeds included; callers skip them) and returns |R_w(B)|.              */
+/* ------------------------------------------------------------------------ */
+static int32_t world_counts_dominator(const query_t* q, scratch_t* s, uint64_t w) {
+    int32_t R = reach(q, s, w);
+    int32_t N = R + 1; /* local ids: 0 = s, 1..R = reached nodes in BFS order */
+    for (int32_t i = 0; i < R; ++i) s->local_of[s->queue[i]] = i + 1;
+
+    /* live subgraph: s -> every seed, and every live edge u -> v with u      */
+    /* reached and v not blocked (v is then reached too).  Self-loops never   */
+    /* change reachability or dominance and are left out.                     */
+    int64_t ne = 0;
+    for (int32_t i = 0; i < q->n_seeds; ++i)
+        if (push_edge(s, &ne, 0, s->local_of[q->seeds[i]])) return -1;
+    for (int32_t i = 0; i < R; ++i) {
+        int32_t u = s->queue[i];
+        for (int64_t e = q->row_ptr[u]; e < q->row_ptr[u + 1]; ++e) {
+            int32_t v = q->col[e];
+            if (v == u || s->blocked[v]) continue;
+            if (!edge_live(q->thr[e], q->rng_seed, w, e)) continue;
+            if (push_edge(s, &ne, i + 1, s->local_of[v])) return -1;
+        }
+    }
+    /* predecessor and successor lists (CSR over local ids) */
+    for (int32_t v = 0; v <= N; ++v) { s->pred_off[v] = 0; s->succ_off[v] = 0; }
+    for (int64_t i = 0; i < ne; ++i) { s->pred_off[s->e_dst[i] + 1]++; s->succ_off[s->e_src[i] + 1]++; }
+    for (int32_t v = 0; v < N; ++v) { s->pred_off[v + 1] += s->pred_off[v]; s->succ_off[v + 1] += s->succ_off[v]; }
+    for (int32_t v = 0; v < N; ++v) s->fill[v] = s->pred_off[v];
+    for (int64_t i = 0; i < ne; ++i) s->pred[s->fill[s->e_dst[i]]++] = s->e_src[i];
+    for (int32_t v = 0; v < N; ++v) s->fill[v] = s->succ_off[v];
+    for (int64_t i = 0; i < ne; ++i) s->succ[s->fill[s->e_src[i]]++] = s->e_dst[i];
+
+    /* depth-first postorder from s (iterative) */
+    for (int32_t v = 0; v < N; ++v) s->po[v] = -1;
+    int32_t top = 0, counter = 0;
+    int32_t* onstack = s->idom; /* reuse as a visited flag before idom is computed */
+    for (int32_t v = 0; v < N; ++v) onstack[v] = 0;
+    s->stack[top] = 0; s->it[top] = s->succ_off[0]; top = 1; onstack[0] = 1;
+    while (top > 0) {
+        int32_t v = s->stack[top - 1];
+        if (s->it[top - 1] < s->succ_off[v + 1]) {
+            int32_t x = s->succ[s->it[top - 1]++];
+            if (!onstack[x]) {
+                onstack[x] = 1;
+                s->stack[top] = x;
+                s->it[top] = s->succ_off[x];
+                ++top;
+            }
+        } else {
+            s->po[v] = counter++;
+            --top;
+        }
+    }
+    /* every local id is reachable from s by construction */
+    for (int32_t v = 0; v < N; ++v) s->rpo[N - 1 - s->po[v]] = v;
+
+    /* Cooper-Harvey-Kennedy: iterate idom(v) = intersection over the        */
+    /* processed predecessors until nothing changes.                          */
+    for (int32_t v = 0; v < N; ++v) s->idom[v] = -1;
+    s->idom[0] = 0;
+    int changed = 1;
+    while (changed) {
+        changed = 0;
+        for (int32_t i = 1; i < N; ++i) {
+            int32_t v = s->rpo[i];
+            int32_t nd = -1;
+            for (int32_t j = s->pred_off[v]; j < s->pred_off[v + 1]; ++j) {
+                int32_t p = s->pred[j];
+                if (s->idom[p] == -1) continue;
+                nd = (nd == -1) ? p : intersect(s->idom, s->po, p, nd);
+            }
+            if (s->idom[v] != nd) { s->idom[v] = nd; changed = 1; }
+        }
+    }
+
+    /* subtree sizes: children before parents = increasing postorder */
+    for (int32_t v = 0; v < N; ++v) s->size[v] = 1;
+    for (int32_t i = N - 1; i >= 1; --i) {
+        int32_t v = s->rpo[i];
+        s->size[s->idom[v]] += s->size[v];
+    }
+    for (int32_t i = 0; i < R; ++i) s->c[s->queue[i]] = s->size[i + 1];
+    return R;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mode 1: c_w(u|B) = |R_w(B)| - |R_w(B + u)| literally (Section 2.1, the     */
+/* decreased spread D_S(B) = E[I_G(S)] - E[I_{G[V\B]}(S)] on one world).     */
+/* ------------------------------------------------------------------------ */
+static int32_t world_counts_definition(const query_t* q, scratch_t* s, uint64_t w, int32_t* reached_buf) {
+    int32_t R = reach(q, s, w);
+    memcpy(reached_buf, s->queue, (size_t)R * sizeof(int32_t));
+    for (int32_t i = 0; i < R; ++i) {
+        int32_t u = reached_buf[i];
+        s->c[u] = 0;
+        int is_seed = 0;
+        for (int32_t j = 0; j < q->n_seeds; ++j) is_seed |= (q->seeds[j] == u);
+        if (is_seed) continue;
+        s->blocked[u] = 1;
+        int32_t R2 = reach(q, s, w);
+        s->blocked[u] = 0;
+        s->c[u] = R - R2;
+    }
+    /* leave queue holding R_w(B) for the caller */
+    memcpy(s->queue, reached_buf, (size_t)R * sizeof(int32_t));
+    return R;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Evaluation over a world range, threaded over contiguous sub-ranges.       */
+/* gain[u] += sum_w c_w(u|B) for u not in S; *total += sum_w |R_w(B)|.       */
+/* Optional per-world outputs: rsize[w - w0] = |R_w(B)| and                  */
+/* rsum[w - w0] = sum of the reached node ids (an order-free fingerprint).   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const query_t* q;
+    const uint8_t* blocked;
+    const uint8_t* is_seed;
+    int mode;
+    int count_gain; /* 0: reachability only */
+    uint64_t w_begin, w_end, w0;
+    int64_t* gain;  /* [n] private partial */
+    int64_t total;
+    int32_t* rsize;
+    int64_t* rsum;
+    int status;
+} job_t;
+
+static void* eval_job(void* arg) {
+    job_t* j = (job_t*)arg;
+    const query_t* q = j->q;
+    scratch_t s;
+    if (scratch_init(&s, q->n, j->blocked)) { j->status = -1; return NULL; }
+    int32_t* buf = NULL;
+    if (j->mode == 1) {
+        buf = malloc(((size_t)q->n + 1) * sizeof(int32_t));
+        if (!buf) { scratch_free(&s); j->status = -1; return NULL; }
+    }
+    for (uint64_t w = j->w_begin; w < j->w_end; ++w) {
+        int32_t R;
+        if (!j->count_gain) R = reach(q, &s, w);
+        else if (j->mode == 1) R = world_counts_definition(q, &s, w, buf);
+        else R = world_counts_dominator(q, &s, w);
+        if (R < 0 || s.oom) { j->status = -1; break; }
+        j->total += R;
+        int64_t sum = 0;
+        for (int32_t i = 0; i < R; ++i) {
+            int32_t v = s.queue[i];
+            sum += v;
+            if (j->count_gain && !j->is_seed[v]) j->gain[v] += s.c[v];
+        }
+        if (j->rsize) j->rsize[w - j->w0] = R;
+        if (j->rsum) j->rsum[w - j->w0] = sum;
+    }
+    free(buf);
+    scratch_free(&s);
+    return NULL;
+}
+
+static int run_eval(const query_t* q, const uint8_t* blocked, int mode, int count_gain,
+                    uint64_t w0, uint64_t nw, int nthreads, int64_t* gain, int64_t* total,
+                    int32_t* rsize, int64_t* rsum) {
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > nw && nw > 0) nthreads = (int)nw;
+    uint8_t* is_seed = calloc((size_t)q->n + 1, 1);
+    job_t* jobs = calloc((size_t)nthreads, sizeof(job_t));
+    pthread_t* th = calloc((size_t)nthreads, sizeof(pthread_t));
+    if (!is_seed || !jobs || !th) { free(is_seed); free(jobs); free(th); return -1; }
+    for (int32_t i = 0; i < q->n_seeds; ++i) is_seed[q->seeds[i]] = 1;
+    int status = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].q = q;
+        jobs[t].blocked = blocked;
+        jobs[t].is_seed = is_seed;
+        jobs[t].mode = mode;
+        jobs[t].count_gain = count_gain;
+        jobs[t].w0 = w0;
+        jobs[t].w_begin = w0 + nw * (uint64_t)t / (uint64_t)nthreads;
+        jobs[t].w_end = w0 + nw * (uint64_t)(t + 1) / (uint64_t)nthreads;
+        jobs[t].rsize = rsize;
+        jobs[t].rsum = rsum;
+        jobs[t].gain = count_gain ? calloc((size_t)q->n, sizeof(int64_t)) : NULL;
+        if (count_gain && !jobs[t].gain) status = -1;
+    }
+    if (status == 0) {
+        for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, eval_job, &jobs[t]);
+        eval_job(&jobs[0]);
+        for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+    }
+    /* merge in thread order; integer sums make the order immaterial */
+    for (int t = 0; t < nthreads; ++t) {
+        if (jobs[t].status) status = -1;
+        *total += jobs[t].total;
+        if (count_gain && jobs[t].gain) {
+            for (int32_t v = 0; v < q->n; ++v) gain[v] += jobs[t].gain[v];
+        }
+        free(jobs[t].gain);
+    }
+    free(is_seed); free(jobs); free(th);
+    return status;
+}
+
+static int check_query(int32_t n, const int32_t* seeds, int32_t n_seeds, const uint8_t* blocked) {
+    if (n < 1 || n_seeds < 1 || n_seeds > n) return -1;
+    uint8_t* seen = calloc((size_t)n, 1);
+    if (!seen) return -1;
+    int bad = 0;
+    for (int32_t i = 0; i < n_seeds && !bad; ++i) {
+        int32_t v = seeds[i];
+        if (v < 0 || v >= n || seen[v]) bad = 1;
+        else {
+            seen[v] = 1;
+            if (blocked && blocked[v]) bad = 1; /* blockers are never seeds */
+        }
+    }
+    free(seen);
+    return bad ? -1 : 0;
+}
+
+/* Public: evaluate gains under a given blocked set over worlds [w0, w0+nw).  */
+/* gain[n] and *total are overwritten.  rsize/rsum may be NULL.               */
+int oracle_eval(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                const int32_t* seeds, int32_t n_seeds, const uint8_t* blocked, uint64_t rng_seed,
+                uint64_t w0, uint64_t nw, int mode, int nthreads,
+                int64_t* gain, int64_t* total, int32_t* rsize, int64_t* rsum) {
+    if (check_query(n, seeds, n_seeds, blocked)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* blk = calloc((size_t)n, 1);
+    if (!blk) return -1;
+    if (blocked) memcpy(blk, blocked, (size_t)n);
+    memset(gain, 0, (size_t)n * sizeof(int64_t));
+    *total = 0;
+    int st = run_eval(&q, blk, mode, 1, w0, nw, nthreads, gain, total, rsize, rsum);
+    free(blk);
+    return st;
+}
+
+/* Public: per-node counts and reached list of one world (for fixtures).      */
+/* c_out[n] gets c_w(v|B) for reached non-seeds and 0 elsewhere; reached_out  */
+/* (capacity n) gets R_w(B) in BFS order.  Returns |R_w(B)| or -1.            */
+int32_t oracle_world(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                     const int32_t* seeds, int32_t n_seeds, const uint8_t* blocked, uint64_t rng_seed,
+                     uint64_t w, int mode, int32_t* c_out, int32_t* reached_out) {
+    if (check_query(n, seeds, n_seeds, blocked)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    scratch_t s;
+    if (scratch_init(&s, n, blocked)) return -1;
+    int32_t* buf = malloc(((size_t)n + 1) * sizeof(int32_t));
+    if (!buf) { scratch_free(&s); return -1; }
+    int32_t R = (mode == 1) ? world_counts_definition(&q, &s, w, buf) : world_counts_dominator(&q, &s, w);
+    if (R >= 0) {
+        memset(c_out, 0, (size_t)n * sizeof(int32_t));
+        for (int32_t i = 0; i < R; ++i) {
+            int32_t v = s.queue[i];
+            reached_out[i] = v;
+            c_out[v] = s.c[v];
+        }
+        for (int32_t i = 0; i < n_seeds; ++i) c_out[seeds[i]] = 0;
+    }
+    free(buf);
+    scratch_free(&s);
+    return R;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The greedy framework of Section 2.2 driven by the dominator-tree           */
+/* estimator (AdvancedGreedy), on worlds shared by every round.               */
+/* Outputs: blockers[k] in selection order, gains[k] = gain_r[u*_r],          */
+/* totals[k+1] = T_0 .. T_{n_selected}, *n_selected <= k.                     */
+/* ------------------------------------------------------------------------ */
+int oracle_solve(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                 const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
+                 int mode, int nthreads,
+                 int32_t* blockers, int64_t* gains, int64_t* totals, int32_t* n_selected) {
+    if (k < 0 || theta < 1) return -1;
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* blk = calloc((size_t)n, 1);
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    int64_t* gain = calloc((size_t)n, sizeof(int64_t));
+    if (!blk || !is_seed || !gain) { free(blk); free(is_seed); free(gain); return -1; }
+    for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+    int status = 0;
+    int32_t r = 0;
+    int64_t T = 0;
+    for (;;) {
+        if (r == k) {
+            /* T_k by definition: reachability under the final blocked set */
+            T = 0;
+            status = run_eval(&q, blk, mode, 0, 0, theta, nthreads, NULL, &T, NULL, NULL);
+            totals[r] = T;
+            break;
+        }
+        memset(gain, 0, (size_t)n * sizeof(int64_t));
+        T = 0;
+        status = run_eval(&q, blk, mode, 1, 0, theta, nthreads, gain, &T, NULL, NULL);
+        if (status) break;
+        totals[r] = T;
+        int32_t best = -1;
+        for (int32_t u = 0; u < n; ++u) {
+            if (is_seed[u] || blk[u]) continue;
+            if (best < 0 || gain[u] > gain[best]) best = u; /* strict: ties keep the smaller id */
+        }
+        if (best < 0 || gain[best] == 0) break;
+        blockers[r] = best;
+        gains[r] = gain[best];
+        blk[best] = 1;
+        ++r;
+    }
+    *n_selected = r;
+    free(blk); free(is_seed); free(gain);
+    return status;
+}

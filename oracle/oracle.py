@@ -1,0 +1,161 @@
+"""Python handle on the C oracle (``imin_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the oracle checks the GPU library and is loaded by
+the tests, the smoke check and the CPU leg of the benchmark, never by the
+library itself.  It is compiled with gcc into ``liboracle.so`` next to this
+file; :func:`build` recompiles it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "imin_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+ALWAYS_LIVE = 0xFFFFFFFF
+MODE_DOMINATOR = 0
+MODE_DEFINITION = 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc -O2 (pthreads)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+                               "-pthread", "-o", tmp, SRC])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(LIB)
+        P = ctypes.c_void_p
+        i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        lib.oracle_philox4x32_10.argtypes = [P, P, P]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_thresholds.argtypes = [i64, P, P]
+        lib.oracle_thresholds.restype = i64
+        lib.oracle_coin.argtypes = [u64, u64, i64]
+        lib.oracle_coin.restype = ctypes.c_uint32
+        lib.oracle_eval.argtypes = [i32, i64, P, P, P, P, i32, P, u64, u64, u64, ctypes.c_int,
+                                    ctypes.c_int, P, P, P, P]
+        lib.oracle_eval.restype = ctypes.c_int
+        lib.oracle_world.argtypes = [i32, i64, P, P, P, P, i32, P, u64, u64, ctypes.c_int, P, P]
+        lib.oracle_world.restype = i32
+        lib.oracle_solve.argtypes = [i32, i64, P, P, P, P, i32, i32, u64, u64, ctypes.c_int,
+                                     ctypes.c_int, P, P, P, P]
+        lib.oracle_solve.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_threads() -> int:
+    return max(1, len(os.sched_getaffinity(0)))
+
+
+def philox4x32_10(counter, key):
+    """One Philox4x32-10 block: four uint32 words."""
+    lib = _load()
+    c = np.asarray(counter, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def coin(seed: int, w: int, e: int) -> int:
+    return int(_load().oracle_coin(seed, w, e))
+
+
+def thresholds(p) -> np.ndarray:
+    """uint32 coin thresholds; raises ValueError on p outside [0, 1] or NaN."""
+    lib = _load()
+    p = np.ascontiguousarray(p, dtype=np.float32)
+    thr = np.zeros(p.shape[0], dtype=np.uint32)
+    bad = lib.oracle_thresholds(p.shape[0], _ptr(p), _ptr(thr))
+    if bad >= 0:
+        raise ValueError(f"edge {bad}: probability {p[bad]!r} is not in [0, 1]")
+    return thr
+
+
+class Query:
+    """A graph plus seed set, with thresholds computed once."""
+
+    def __init__(self, g, seeds):
+        self.n = int(g.n)
+        self.m = int(g.m)
+        self.row_ptr = np.ascontiguousarray(g.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(g.col, dtype=np.int32)
+        self.thr = thresholds(g.p)
+        self.seeds = np.ascontiguousarray(seeds, dtype=np.int32)
+
+    def _blocked(self, blocked):
+        if blocked is None:
+            return None
+        b = np.zeros(self.n, dtype=np.uint8)
+        b[np.asarray(list(blocked), dtype=np.int64)] = 1
+        return b
+
+    def eval(self, rng_seed: int, w0: int, nw: int, blocked=(), mode: int = MODE_DOMINATOR,
+             threads: int | None = None, per_world: bool = False):
+        """gain int64[n] and total over worlds [w0, w0+nw) under ``blocked``."""
+        lib = _load()
+        blk = self._blocked(blocked)
+        gain = np.zeros(self.n, dtype=np.int64)
+        total = np.zeros(1, dtype=np.int64)
+        rsize = np.zeros(nw, dtype=np.int32) if per_world else None
+        rsum = np.zeros(nw, dtype=np.int64) if per_world else None
+        st = lib.oracle_eval(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                             _ptr(self.seeds), len(self.seeds), _ptr(blk), rng_seed, w0, nw, mode,
+                             threads or default_threads(), _ptr(gain), _ptr(total), _ptr(rsize),
+                             _ptr(rsum))
+        if st != 0:
+            raise ValueError("oracle_eval rejected the query")
+        if per_world:
+            return gain, int(total[0]), rsize, rsum
+        return gain, int(total[0])
+
+    def world(self, rng_seed: int, w: int, blocked=(), mode: int = MODE_DOMINATOR):
+        """(c int32[n], reached list in BFS order) for one world."""
+        lib = _load()
+        blk = self._blocked(blocked)
+        c = np.zeros(self.n, dtype=np.int32)
+        reached = np.zeros(self.n, dtype=np.int32)
+        R = lib.oracle_world(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                             _ptr(self.seeds), len(self.seeds), _ptr(blk), rng_seed, w, mode,
+                             _ptr(c), _ptr(reached))
+        if R < 0:
+            raise ValueError("oracle_world rejected the query")
+        return c, reached[:R].copy()
+
+    def solve(self, k: int, theta: int, rng_seed: int, mode: int = MODE_DOMINATOR,
+              threads: int | None = None):
+        """Greedy selection; returns dict(blockers, gains, spread_totals, n_selected)."""
+        lib = _load()
+        blockers = np.zeros(max(k, 1), dtype=np.int32)
+        gains = np.zeros(max(k, 1), dtype=np.int64)
+        totals = np.zeros(k + 1, dtype=np.int64)
+        nsel = np.zeros(1, dtype=np.int32)
+        st = lib.oracle_solve(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                              _ptr(self.seeds), len(self.seeds), k, theta, rng_seed, mode,
+                              threads or default_threads(), _ptr(blockers), _ptr(gains),
+                              _ptr(totals), _ptr(nsel))
+        if st != 0:
+            raise ValueError("oracle_solve rejected the query")
+        r = int(nsel[0])
+        return dict(blockers=blockers[:r].copy(), gains=gains[:r].copy(),
+                    spread_totals=totals[:r + 1].copy(), n_selected=r)
