@@ -1,0 +1,171 @@
+/*
+ * imin.h -- C ABI of the MI355X (gfx950) library for influence minimization
+ * by node blocking: the sampling estimator of Wang et al., "Efficient
+ * Influence Minimization via Node Blocking" (PVLDB), Section 2.2.
+ *
+ * The library picks up to k blockers for a seed set S on a directed graph
+ * with edge probabilities.  For every candidate u it counts, over theta
+ * sampled live-edge worlds (Section 2.1, Eq. 1), the nodes that lose every
+ * path from S once u is blocked; these counts are dominator-subtree sizes
+ * under a virtual source joined to every seed (Section 2.2, the estimator of
+ * Xie et al.; Section 3.1, the unified seed).  Greedy selection adds the
+ * candidate with the largest summed count, ties to the smaller node id, and
+ * stops early when no candidate protects anything (problem statement: at
+ * most k blockers).
+ *
+ * Worlds are drawn by counter-based coins: edge e (its CSR slot) is live in
+ * world w iff its threshold is 0xFFFFFFFF (p == 1) or
+ *   Philox4x32-10(counter = (e >> 2, w, 0, 0),
+ *                 key = (lo32(rng_seed), hi32(rng_seed)))[e & 3] < thr[e],
+ * with thr[e] = floor(p[e] * 2^32) for p[e] < 1.  A world is therefore a pure
+ * function of (rng_seed, w), and every greedy round reuses the same theta
+ * worlds.  All counts are exact integers; results do not depend on launch
+ * shapes, tiling or thread timing.
+ *
+ * Conventions for every call:
+ *   - array arguments are DEVICE pointers (HBM of the current HIP device)
+ *     unless stated otherwise; scalars are passed by value;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
+ *   - calls are synchronous with respect to the host: they return after the
+ *     results are in place (work is ordered on `stream`);
+ *   - no C++ exception crosses this boundary; every call returns a status.
+ */
+#ifndef IMIN_H
+#define IMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    IMIN_OK = 0,
+    IMIN_ERR_INVALID = 1, /* bad argument, detected on the host               */
+    IMIN_ERR_DATA = 2,    /* bad input data, detected on the device: a column
+                             index out of range, a probability outside [0, 1]
+                             or NaN, non-monotone row offsets, a seed out of
+                             range or repeated, a blocker that is a seed      */
+    IMIN_ERR_DEVICE = 3,  /* a HIP runtime call failed                        */
+    IMIN_ERR_NOMEM = 4,   /* device memory could not be allocated             */
+    IMIN_ERR_INTERNAL = 5 /* an internal consistency check failed             */
+} imin_status_t;
+
+typedef struct imin_graph* imin_graph_t;
+
+/*
+ * imin_graph_create -- ingest a graph (Section 2.1: G = (V, E) with
+ * p(u, v) in [0, 1] on every edge).
+ *
+ *   n        number of nodes, 1 <= n < 2^24
+ *   m        number of edges (CSR slots), 0 <= m < 2^31 - 8
+ *   row_ptr  int64[n+1], device: out-edges of u are slots row_ptr[u] ..
+ *            row_ptr[u+1]-1; row_ptr[0] == 0, row_ptr[n] == m, non-decreasing
+ *   col      int32[m], device: head of each slot, in [0, n)
+ *   p        float32[m], device: propagation probability of each slot
+ *   stream   stream the ingest runs on
+ *   out      host pointer receiving the handle
+ *
+ * The handle owns device copies of everything it needs (int32 offsets, a
+ * padded column array and the coin thresholds), so the caller's arrays may
+ * be freed once the call returns.  Parallel edges are allowed (each slot has
+ * its own coin); self-loops are allowed and never matter.  Errors:
+ * IMIN_ERR_INVALID (sizes, NULL pointers), IMIN_ERR_DATA (see above; no
+ * handle is returned), IMIN_ERR_NOMEM, IMIN_ERR_DEVICE.
+ */
+imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                                const float* p, void* stream, imin_graph_t* out);
+
+/* Release a handle and its device memory.  NULL is accepted. */
+imin_status_t imin_graph_destroy(imin_graph_t g);
+
+/* Node and edge counts of a handle (host pointers; either may be NULL). */
+imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m);
+
+/*
+ * imin_solve -- greedy blocker selection (Section 2.2: the greedy framework
+ * driven by the dominator-tree estimator; problem statement of Section 2.1).
+ *
+ *   seeds          int32[n_seeds], device: the misinformation seed set S,
+ *                  distinct ids in [0, n); 1 <= n_seeds <= n
+ *   k              budget, 0 <= k <= n
+ *   theta          worlds per round, 1 <= theta < 2^32
+ *   rng_seed       key of the coin generator
+ *   blockers       int32[max(k,1)], device, out: u*_0 .. u*_{n_selected-1}
+ *   gains          int64[max(k,1)], device, out: gains[r] = sum over worlds
+ *                  of nodes protected by u*_r given u*_0..u*_{r-1} blocked
+ *   spread_totals  int64[k+1], device, out: T_r = sum over worlds of
+ *                  |R_w(B_r)| for r = 0 .. n_selected (seeds included), so
+ *                  T_{r+1} = T_r - gains[r] and the estimated spread after
+ *                  blocking is T_{n_selected} / theta
+ *   n_selected     int32[1], device, out: number of blockers chosen (<= k;
+ *                  fewer when every remaining candidate protects nothing)
+ *
+ * Entries past n_selected are left untouched.  The call allocates its own
+ * scratch device memory and frees it before returning.  Errors:
+ * IMIN_ERR_INVALID, IMIN_ERR_DATA (bad seeds), IMIN_ERR_NOMEM,
+ * IMIN_ERR_DEVICE, IMIN_ERR_INTERNAL.
+ */
+imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
+                         int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
+                         int64_t* gains, int64_t* spread_totals, int32_t* n_selected);
+
+/*
+ * imin_evaluate -- one pass of the estimator (Section 2.2: sample worlds,
+ * build each world's dominator tree under the super-source, measure every
+ * subtree) over the worlds [w_begin, w_begin + w_count) with a given blocked
+ * set B.
+ *
+ *   seeds       int32[n_seeds], device, as for imin_solve
+ *   blocked     int32[n_blocked], device (may be NULL when n_blocked == 0):
+ *               nodes removed from the graph; never seeds; repeats allowed
+ *   w_begin, w_count  world range, w_begin + w_count <= 2^32, w_count >= 1
+ *   gain        int64[n], device, out: gain[u] = sum over the range of
+ *               c_w(u|B) = |R_w(B)| - |R_w(B + u)|; 0 for seeds and for B
+ *   total       int64[1], device, out: sum over the range of |R_w(B)|
+ *   world_size  int32[w_count], device, out, optional (NULL): |R_w(B)|
+ *   world_sum   int64[w_count], device, out, optional (NULL): sum of the
+ *               node ids in R_w(B), an order-free fingerprint of the set
+ *   world_edges int64[w_count], device, out, optional (NULL): number of CSR
+ *               slots leaving the nodes of R_w(B), i.e. the edges whose coins
+ *               the world needs (the unit of sampling work)
+ *
+ * Gains over disjoint world ranges add up to the gains over their union.
+ * Errors as for imin_solve.
+ */
+imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seeds,
+                            const int32_t* blocked, int32_t n_blocked, int64_t w_begin,
+                            int64_t w_count, uint64_t rng_seed, void* stream, int64_t* gain,
+                            int64_t* total, int32_t* world_size, int64_t* world_sum,
+                            int64_t* world_edges);
+
+/*
+ * Kernel timing, for measurement.  While enabled, the library brackets its
+ * own kernel launches with HIP events on the stream they run on and adds
+ * each launch's duration to a per-kernel tally (process-wide).  Kernel ids:
+ *   0  world evaluation, LDS path (workgroup of one wave per world)
+ *   1  world evaluation, HBM path (workgroup of four waves per world)
+ *   2  gain reduction (bucket histogram, scan, scatter, accumulate, sum)
+ *   3  greedy selection
+ * imin_timing_read returns the number of launches and their summed duration
+ * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
+ */
+imin_status_t imin_timing_enable(int on);
+imin_status_t imin_timing_reset(void);
+imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_ms);
+
+/* Static description of a status code. */
+const char* imin_status_string(imin_status_t s);
+
+/*
+ * Device status bits of the last failed call on this thread (0 if none):
+ * a host-readable detail for IMIN_ERR_DATA / IMIN_ERR_INTERNAL.
+ */
+uint32_t imin_last_device_flags(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IMIN_H */

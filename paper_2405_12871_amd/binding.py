@@ -1,0 +1,237 @@
+"""Thin Python binding of the C ABI in ``include/imin.h``.
+
+Argument marshalling only: every step of the estimator runs in the HIP
+library.  PyTorch provides device memory and the stream.  There is no
+fallback: a missing library or a missing GPU raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libimin.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "imin.h")
+
+IMIN_OK = 0
+STATUS_NAMES = {0: "IMIN_OK", 1: "IMIN_ERR_INVALID", 2: "IMIN_ERR_DATA", 3: "IMIN_ERR_DEVICE",
+                4: "IMIN_ERR_NOMEM", 5: "IMIN_ERR_INTERNAL"}
+
+_lib = None
+
+
+class IminError(RuntimeError):
+    def __init__(self, status: int, message: str, flags: int = 0):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message} (device flags 0x{flags:x})")
+        self.status = status
+        self.flags = flags
+
+
+def header_functions() -> list[str]:
+    """Names of the functions declared in include/imin.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(imin_[a-z_]+)\s*\(", text)))
+
+
+def load():
+    """Load libimin.so (built by ``paper_2405_12871_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m paper_2405_12871_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, u64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    st = ctypes.c_int
+    lib.imin_graph_create.argtypes = [i32, i64, P, P, P, P, ctypes.POINTER(P)]
+    lib.imin_graph_create.restype = st
+    lib.imin_graph_destroy.argtypes = [P]
+    lib.imin_graph_destroy.restype = st
+    lib.imin_graph_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
+    lib.imin_graph_info.restype = st
+    lib.imin_solve.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P]
+    lib.imin_solve.restype = st
+    lib.imin_evaluate.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P, P, P, P, P]
+    lib.imin_evaluate.restype = st
+    lib.imin_status_string.argtypes = [st]
+    lib.imin_status_string.restype = ctypes.c_char_p
+    lib.imin_last_device_flags.argtypes = []
+    lib.imin_last_device_flags.restype = ctypes.c_uint32
+    lib.imin_timing_enable.argtypes = [ctypes.c_int]
+    lib.imin_timing_enable.restype = st
+    lib.imin_timing_reset.argtypes = []
+    lib.imin_timing_reset.restype = st
+    lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
+    lib.imin_timing_read.restype = st
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != IMIN_OK:
+        lib = load()
+        raise IminError(status, lib.imin_status_string(status).decode(), int(lib.imin_last_device_flags()))
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the IMIN library runs on the device only")
+    return torch
+
+
+def _dev(a, dtype, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dtype).contiguous()
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Graph:
+    """A graph resident on the GPU (imin_graph_create / imin_graph_destroy)."""
+
+    def __init__(self, n: int, row_ptr, col, p, device="cuda:0"):
+        torch = _torch()
+        lib = load()
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            rp = _dev(row_ptr, torch.int64, self.device)
+            cl = _dev(col, torch.int32, self.device)
+            pp = _dev(p, torch.float32, self.device)
+            m = int(cl.numel())
+            h = ctypes.c_void_p()
+            _check(lib.imin_graph_create(int(n), m, _ptr(rp), _ptr(cl) if m else None,
+                                         _ptr(pp) if m else None, _stream(self.device), ctypes.byref(h)))
+        self._h = h
+        self.n = int(n)
+        self.m = m
+
+    @classmethod
+    def from_synth(cls, g, device="cuda:0"):
+        return cls(g.n, g.row_ptr, g.col, g.p, device=device)
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("graph already destroyed")
+        return self._h
+
+    def destroy(self):
+        if getattr(self, "_h", None) is not None:
+            load().imin_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+@dataclasses.dataclass
+class SolveResult:
+    blockers: np.ndarray
+    gains: np.ndarray
+    spread_totals: np.ndarray
+    n_selected: int
+    theta: int
+
+    @property
+    def est_spread(self) -> float:
+        """Estimated expected spread after blocking: T_final / theta."""
+        return float(self.spread_totals[self.n_selected]) / float(self.theta)
+
+    @property
+    def est_decrease(self) -> float:
+        return float(self.spread_totals[0] - self.spread_totals[self.n_selected]) / float(self.theta)
+
+
+def solve_device(graph: Graph, seeds_dev, k: int, theta: int, rng_seed: int, out=None):
+    """imin_solve on device tensors; returns the device output tensors."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    if out is None:
+        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
+               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
+               torch.zeros(k + 1, dtype=torch.int64, device=dev),
+               torch.zeros(1, dtype=torch.int32, device=dev))
+    b, g, t, ns = out
+    with torch.cuda.device(dev):
+        _check(lib.imin_solve(graph.handle, _ptr(seeds_dev), int(seeds_dev.numel()), int(k), int(theta),
+                              int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(b), _ptr(g), _ptr(t),
+                              _ptr(ns)))
+    return out
+
+
+def solve(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> SolveResult:
+    """Greedy selection of up to k blockers (imin_solve)."""
+    torch = _torch()
+    s = _dev(seeds, torch.int32, graph.device)
+    b, g, t, ns = solve_device(graph, s, k, theta, rng_seed)
+    r = int(ns.cpu()[0])
+    return SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
+                       spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=int(theta))
+
+
+def evaluate(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blocked=(),
+             per_world: bool = False, edges: bool = False):
+    """One estimator pass over worlds [w_begin, w_begin + w_count) (imin_evaluate).
+
+    Returns (gain int64[n], total) or, with ``per_world``,
+    (gain, total, world_size int32[w_count], world_sum int64[w_count]); with
+    ``edges`` the per-world scanned-edge counts int64[w_count] are appended.
+    """
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    blk = list(blocked) if not isinstance(blocked, torch.Tensor) else blocked
+    b = _dev(np.asarray(blk, dtype=np.int32), torch.int32, dev) if len(blk) else None
+    gain = torch.empty(graph.n, dtype=torch.int64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    ws = torch.empty(w_count, dtype=torch.int32, device=dev) if per_world else None
+    wsum = torch.empty(w_count, dtype=torch.int64, device=dev) if per_world else None
+    wedge = torch.empty(w_count, dtype=torch.int64, device=dev) if edges else None
+    with torch.cuda.device(dev):
+        _check(lib.imin_evaluate(graph.handle, _ptr(s), int(s.numel()), _ptr(b),
+                                 int(b.numel()) if b is not None else 0, int(w_begin), int(w_count),
+                                 int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(gain), _ptr(total),
+                                 _ptr(ws), _ptr(wsum), _ptr(wedge)))
+    res = [gain.cpu().numpy(), int(total.cpu()[0])]
+    if per_world:
+        res += [ws.cpu().numpy(), wsum.cpu().numpy()]
+    if edges:
+        res.append(wedge.cpu().numpy())
+    return tuple(res)
+
+
+def timing_enable(on: bool = True):
+    _check(load().imin_timing_enable(1 if on else 0))
+
+
+def timing_reset():
+    _check(load().imin_timing_reset())
+
+
+def timing_read(kernel_id: int):
+    """(launches, total milliseconds) of one library kernel since the last reset."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().imin_timing_read(int(kernel_id), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)

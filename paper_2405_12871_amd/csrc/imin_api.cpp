@@ -1,0 +1,491 @@
+// Host side of the C ABI declared in include/imin.h.
+#include "imin.h"
+#include "imin_internal.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <vector>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+struct imin_graph {
+    imin::GraphDev g;
+    int device;
+};
+
+namespace {
+
+thread_local uint32_t g_last_flags = 0;
+
+// ---- optional per-kernel timing with HIP events
+constexpr int kTimedKernels = 4;
+struct Timing {
+    std::atomic<bool> on{false};
+    std::mutex mu;
+    int64_t launches[kTimedKernels] = {};
+    double ms[kTimedKernels] = {};
+};
+Timing g_timing;
+
+// Event pairs recorded by one call, resolved after its final synchronisation.
+struct TimedLaunches {
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    bool on = g_timing.on.load();
+    hipEvent_t begin(hipStream_t s) {
+        if (!on) return nullptr;
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        (void)hipEventRecord(e, s);
+        return e;
+    }
+    void end(int id, hipEvent_t a, hipStream_t s) {
+        if (!on || !a) return;
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return;
+        }
+        (void)hipEventRecord(e, s);
+        recs.push_back({id, a, e});
+    }
+    void flush() {
+        if (recs.empty()) return;
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        for (auto& r : recs) {
+            float ms = 0.f;
+            if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                g_timing.launches[r.id] += 1;
+                g_timing.ms[r.id] += ms;
+            }
+            (void)hipEventDestroy(r.a);
+            (void)hipEventDestroy(r.b);
+        }
+        recs.clear();
+    }
+    ~TimedLaunches() { flush(); }
+};
+
+imin_status_t from_hip(hipError_t e) {
+    if (e == hipSuccess) return IMIN_OK;
+    return e == hipErrorOutOfMemory ? IMIN_ERR_NOMEM : IMIN_ERR_DEVICE;
+}
+
+#define IMIN_TRY(expr)                                  \
+    do {                                                \
+        const hipError_t imin_e_ = (expr);              \
+        if (imin_e_ != hipSuccess) return from_hip(imin_e_); \
+    } while (0)
+
+// Device allocation owned by a scope.
+template <class T>
+struct DevArray {
+    T* p = nullptr;
+    size_t count = 0;
+    DevArray() = default;
+    DevArray(const DevArray&) = delete;
+    DevArray& operator=(const DevArray&) = delete;
+    ~DevArray() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        count = 0;
+    }
+    hipError_t alloc(size_t c) {
+        release();
+        count = c;
+        return hipMalloc((void**)&p, std::max<size_t>(c, 1) * sizeof(T));
+    }
+};
+
+struct HostCtl {
+    imin::RoundCtl* p = nullptr;
+    ~HostCtl() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+int cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+size_t env_size(const char* name, size_t dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char* end = nullptr;
+    const unsigned long long x = std::strtoull(v, &end, 10);
+    return (end && *end == '\0' && x > 0) ? (size_t)x : dflt;
+}
+
+// Everything one query needs on the device besides the graph.
+struct Session {
+    const imin::GraphDev& g;
+    hipStream_t s;
+    DevArray<uint32_t> excl;
+    DevArray<int64_t> gain;
+    DevArray<imin::RoundCtl> ctl;
+    HostCtl hctl;
+    // tile outputs
+    DevArray<int32_t> world_size;
+    DevArray<int32_t> big_list;
+    DevArray<int32_t> pair_node, pair_cnt;
+    // reduction
+    DevArray<int32_t> hist, sorted_node, sorted_cnt;
+    DevArray<int64_t> part;
+    imin::ReduceBufs rb{};
+    // big-world path
+    DevArray<int32_t> b_lid, b_nodes, b_parent, b_idom, b_aux, b_lvl, b_xv, b_xu;
+    imin::BigSlots bs{};
+    // selection
+    DevArray<int64_t> sel_g;
+    DevArray<int32_t> sel_u;
+    int sel_parts = 0;
+    size_t tile_cap = 0;   // worlds per tile (buffer size)
+    size_t tile = 0;       // worlds per tile in use
+    int small_grid = 0;
+    TimedLaunches timed;
+
+    Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
+
+    imin_status_t init(uint64_t theta, bool need_gain_buffers) {
+        const size_t n = (size_t)g.n;
+        IMIN_TRY(excl.alloc((n + 31) / 32));
+        IMIN_TRY(gain.alloc(n));
+        IMIN_TRY(ctl.alloc(1));
+        IMIN_TRY(hipHostMalloc((void**)&hctl.p, sizeof(imin::RoundCtl), hipHostMallocDefault));
+        imin::RoundCtl c0{};
+        c0.expect_total = -1;
+        IMIN_TRY(hipMemcpyAsync(ctl.p, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
+
+        tile_cap = std::min<size_t>(theta, env_size("IMIN_TILE_WORLDS", (size_t)1 << 22));
+        tile = tile_cap;
+        IMIN_TRY(world_size.alloc(tile_cap));
+        IMIN_TRY(big_list.alloc(tile_cap));
+
+        // pair buffer: enough for the whole tile if worlds are small
+        const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
+        size_t want = tile_cap * std::min<size_t>(n, 512);
+        const size_t pcap = std::max<size_t>(std::min(want, budget), 1 << 16);
+        IMIN_TRY(pair_node.alloc(pcap));
+        IMIN_TRY(pair_cnt.alloc(pcap));
+        IMIN_TRY(sorted_node.alloc(pcap));
+        IMIN_TRY(sorted_cnt.alloc(pcap));
+
+        rb.nb = (int32_t)((n + ((size_t)1 << imin::kBucketShift) - 1) >> imin::kBucketShift);
+        rb.g1 = 1024;
+        rb.slices = std::max(1, 1024 / rb.nb);
+        IMIN_TRY(hist.alloc((size_t)rb.nb * rb.g1 + 1));
+        IMIN_TRY(part.alloc((size_t)rb.slices * ((size_t)rb.nb << imin::kBucketShift)));
+        rb.hist = hist.p;
+        rb.sorted_node = sorted_node.p;
+        rb.sorted_cnt = sorted_cnt.p;
+        rb.part = part.p;
+        (void)need_gain_buffers;
+
+        // big-world slots: per slot 6 node arrays (+lvl) and 2 edge arrays
+        const int cus = cu_count();
+        const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
+        const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * xcap * 4;
+        const size_t big_budget = env_size("IMIN_BIG_BUDGET", (size_t)6 << 30);
+        size_t slots = big_budget / slot_bytes;
+        slots = std::min<size_t>(slots, (size_t)cus * 4);
+        slots = std::min<size_t>(slots, tile_cap);
+        slots = std::max<size_t>(slots, 1);
+        bs.n_slots = (int32_t)slots;
+        bs.xcap = (int64_t)xcap;
+        IMIN_TRY(b_lid.alloc(slots * n));
+        IMIN_TRY(b_nodes.alloc(slots * n));
+        IMIN_TRY(b_parent.alloc(slots * n));
+        IMIN_TRY(b_idom.alloc(slots * n));
+        IMIN_TRY(b_aux.alloc(slots * n));
+        IMIN_TRY(b_lvl.alloc(slots * (n + 3)));
+        IMIN_TRY(b_xv.alloc(slots * xcap));
+        IMIN_TRY(b_xu.alloc(slots * xcap));
+        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, slots * n, s));
+        bs.lid_of = b_lid.p;
+        bs.nodes = b_nodes.p;
+        bs.parent = b_parent.p;
+        bs.idom = b_idom.p;
+        bs.aux = b_aux.p;
+        bs.lvl = b_lvl.p;
+        bs.xv = b_xv.p;
+        bs.xu = b_xu.p;
+
+        sel_parts = (int)std::min<size_t>(1024, (n + 255) / 256);
+        IMIN_TRY(sel_g.alloc(sel_parts));
+        IMIN_TRY(sel_u.alloc(sel_parts));
+        small_grid = cus * imin::small_world_blocks_per_cu();
+        return IMIN_OK;
+    }
+
+    imin_status_t read_ctl() {
+        IMIN_TRY(hipMemcpyAsync(hctl.p, ctl.p, sizeof(imin::RoundCtl), hipMemcpyDeviceToHost, s));
+        IMIN_TRY(hipStreamSynchronize(s));
+        return IMIN_OK;
+    }
+
+    imin_status_t clear_flag(uint32_t bit) {
+        hctl.p->flags &= ~bit;
+        IMIN_TRY(hipMemcpyAsync(&ctl.p->flags, &hctl.p->flags, sizeof(uint32_t), hipMemcpyHostToDevice, s));
+        return IMIN_OK;
+    }
+
+    imin_status_t grow_pairs(unsigned long long needed) {
+        const size_t want = (size_t)(needed + needed / 8 + 1024);
+        IMIN_TRY(pair_node.alloc(want));
+        IMIN_TRY(pair_cnt.alloc(want));
+        IMIN_TRY(sorted_node.alloc(want));
+        IMIN_TRY(sorted_cnt.alloc(want));
+        rb.sorted_node = sorted_node.p;
+        rb.sorted_cnt = sorted_cnt.p;
+        return IMIN_OK;
+    }
+
+    // Evaluate worlds [w_begin, w_begin+count) under the current excl bitmap;
+    // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
+    // outputs are written at [0, count).
+    imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
+                           int64_t* wsum_out, int64_t* wedges_out) {
+        uint64_t done = 0;
+        while (done < count) {
+            const uint64_t nw = std::min<uint64_t>(tile, count - done);
+            imin::TileOut out{};
+            out.pair_node = pair_node.p;
+            out.pair_cnt = pair_cnt.p;
+            out.pair_cap = pair_node.count;
+            out.world_size = ws_out ? ws_out + done : world_size.p;
+            out.world_sum = wsum_out ? wsum_out + done : nullptr;
+            out.world_edges = wedges_out ? wedges_out + done : nullptr;
+            out.big_list = big_list.p;
+            IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+            hipEvent_t ev = timed.begin(s);
+            IMIN_TRY(imin::launch_world_small(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, out,
+                                              small_grid, s));
+            timed.end(0, ev, s);
+            ev = timed.begin(s);
+            IMIN_TRY(imin::launch_world_big(g, q, ctl.p, (uint32_t)(w_begin + done), out, bs, s));
+            timed.end(1, ev, s);
+            imin_status_t st = read_ctl();
+            if (st != IMIN_OK) return st;
+            const uint32_t f = hctl.p->flags;
+            if (f & imin::kFlagBigCapacity) {
+                g_last_flags = f;
+                return IMIN_ERR_INTERNAL;
+            }
+            if (f & imin::kFlagPairOverflow) {
+                st = clear_flag(imin::kFlagPairOverflow);
+                if (st != IMIN_OK) return st;
+                const unsigned long long need = hctl.p->pair_count;
+                const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
+                if (need <= budget) {
+                    st = grow_pairs(need);
+                    if (st != IMIN_OK) return st;
+                } else {
+                    // shrink the tile so that its pairs fit the budget
+                    if (pair_node.count < budget) {
+                        st = grow_pairs(budget);
+                        if (st != IMIN_OK) return st;
+                    }
+                    const double per_world = (double)need / (double)nw;
+                    uint64_t t2 = (uint64_t)((double)pair_node.count * 0.9 / std::max(per_world, 1.0));
+                    tile = std::max<uint64_t>(1, std::min<uint64_t>(t2, tile));
+                }
+                continue;  // redo this tile
+            }
+            ev = timed.begin(s);
+            IMIN_TRY(imin::launch_reduce_pairs(g, out, rb, ctl.p, gain.p, s));
+            timed.end(2, ev, s);
+            IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
+            done += nw;
+        }
+        return IMIN_OK;
+    }
+};
+
+imin_status_t check_data_flags(uint32_t f) {
+    if (f & imin::kFlagDataMask) {
+        g_last_flags = f;
+        return IMIN_ERR_DATA;
+    }
+    return IMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* imin_status_string(imin_status_t s) {
+    switch (s) {
+        case IMIN_OK: return "ok";
+        case IMIN_ERR_INVALID: return "invalid argument";
+        case IMIN_ERR_DATA: return "invalid input data (offsets, columns, probabilities, seeds or blockers)";
+        case IMIN_ERR_DEVICE: return "HIP runtime error";
+        case IMIN_ERR_NOMEM: return "out of device memory";
+        case IMIN_ERR_INTERNAL: return "internal consistency check failed";
+    }
+    return "unknown status";
+}
+
+uint32_t imin_last_device_flags(void) { return g_last_flags; }
+
+imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                                const float* p, void* stream, imin_graph_t* out) {
+    g_last_flags = 0;
+    if (!out || !row_ptr) return IMIN_ERR_INVALID;
+    *out = nullptr;
+    if (n < 1 || n >= (1 << 24) || m < 0 || m > (int64_t)0x7FFFFFF0) return IMIN_ERR_INVALID;
+    if (m > 0 && (!col || !p)) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    imin_graph* h = new (std::nothrow) imin_graph();
+    if (!h) return IMIN_ERR_NOMEM;
+    h->g.n = n;
+    h->g.m = m;
+    h->g.m_pad = ((m + 3) / 4) * 4 + 4;
+    (void)hipGetDevice(&h->device);
+    hipError_t e = hipMalloc((void**)&h->g.off, ((size_t)n + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&h->g.col, (size_t)h->g.m_pad * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&h->g.thr, (size_t)h->g.m_pad * sizeof(uint32_t));
+    imin::RoundCtl* ctl = nullptr;
+    imin::RoundCtl* hc = nullptr;
+    if (e == hipSuccess) e = hipMalloc((void**)&ctl, sizeof(imin::RoundCtl));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&hc, sizeof(imin::RoundCtl), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemsetAsync(ctl, 0, sizeof(imin::RoundCtl), s);
+    if (e == hipSuccess) e = imin::launch_graph_ingest(h->g, row_ptr, col, p, ctl, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(hc, ctl, sizeof(imin::RoundCtl), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    imin_status_t st = from_hip(e);
+    if (st == IMIN_OK) st = check_data_flags(hc->flags);
+    if (ctl) (void)hipFree(ctl);
+    if (hc) (void)hipHostFree(hc);
+    if (st != IMIN_OK) {
+        imin_graph_destroy(h);
+        return st;
+    }
+    *out = h;
+    return IMIN_OK;
+}
+
+imin_status_t imin_graph_destroy(imin_graph_t g) {
+    if (!g) return IMIN_OK;
+    if (g->g.off) (void)hipFree(g->g.off);
+    if (g->g.col) (void)hipFree(g->g.col);
+    if (g->g.thr) (void)hipFree(g->g.thr);
+    delete g;
+    return IMIN_OK;
+}
+
+imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m) {
+    if (!g) return IMIN_ERR_INVALID;
+    if (n) *n = g->g.n;
+    if (m) *m = g->g.m;
+    return IMIN_OK;
+}
+
+static imin_status_t setup_query(Session& ss, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                                 int32_t n_blocked, uint64_t rng_seed, imin::QueryDev& q) {
+    IMIN_TRY(imin::launch_query_setup(ss.g, seeds, n_seeds, blocked, n_blocked, ss.excl.p, ss.ctl.p, ss.s));
+    imin_status_t st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    st = check_data_flags(ss.hctl.p->flags);
+    if (st != IMIN_OK) return st;
+    q.excl = ss.excl.p;
+    q.seeds = seeds;
+    q.n_seeds = n_seeds;
+    q.key0 = (uint32_t)rng_seed;
+    q.key1 = (uint32_t)(rng_seed >> 32);
+    return IMIN_OK;
+}
+
+imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                         uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
+                         int64_t* spread_totals, int32_t* n_selected) {
+    g_last_flags = 0;
+    if (!g || !seeds || !blockers || !gains || !spread_totals || !n_selected) return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
+    if (theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s);
+    imin_status_t st = ss.init((uint64_t)theta, true);
+    if (st != IMIN_OK) return st;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    for (int32_t r = 0; r <= k; ++r) {
+        IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+        IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+        st = ss.evaluate(q, 0, (uint64_t)theta, nullptr, nullptr, nullptr);
+        if (st != IMIN_OK) return st;
+        hipEvent_t ev = ss.timed.begin(s);
+        IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_parts, k,
+                                     blockers, gains, spread_totals, n_selected, s));
+        ss.timed.end(3, ev, s);
+        st = ss.read_ctl();
+        if (st != IMIN_OK) return st;
+        if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+            g_last_flags = ss.hctl.p->flags;
+            return IMIN_ERR_INTERNAL;
+        }
+        if (ss.hctl.p->stop) break;
+    }
+    return IMIN_OK;
+}
+
+imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                            int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed, void* stream,
+                            int64_t* gain, int64_t* total, int32_t* world_size, int64_t* world_sum,
+                            int64_t* world_edges) {
+    g_last_flags = 0;
+    if (!g || !seeds || !gain || !total) return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n || n_blocked < 0 || (n_blocked > 0 && !blocked)) return IMIN_ERR_INVALID;
+    if (w_begin < 0 || w_count < 1 || w_begin + w_count > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s);
+    imin_status_t st = ss.init((uint64_t)w_count, false);
+    if (st != IMIN_OK) return st;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, blocked, n_blocked, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+    IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    st = ss.evaluate(q, (uint64_t)w_begin, (uint64_t)w_count, world_size, world_sum, world_edges);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(hipMemcpyAsync(gain, ss.gain.p, (size_t)g->g.n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    IMIN_TRY(hipMemcpyAsync(total, &ss.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    IMIN_TRY(hipStreamSynchronize(s));
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_enable(int on) {
+    g_timing.on.store(on != 0);
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    for (int i = 0; i < kTimedKernels; ++i) {
+        g_timing.launches[i] = 0;
+        g_timing.ms[i] = 0.0;
+    }
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_ms) {
+    if (kernel_id < 0 || kernel_id >= kTimedKernels) return IMIN_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (launches) *launches = g_timing.launches[kernel_id];
+    if (total_ms) *total_ms = g_timing.ms[kernel_id];
+    return IMIN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,127 @@
+// Internal declarations shared by the device code and the host C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace imin {
+
+constexpr uint32_t kAlwaysLive = 0xFFFFFFFFu;
+
+// Device status bits (RoundCtl::flags).
+enum : uint32_t {
+    kFlagBadCol = 1u << 0,
+    kFlagBadProb = 1u << 1,
+    kFlagBadOffsets = 1u << 2,
+    kFlagBadSeed = 1u << 3,
+    kFlagDupSeed = 1u << 4,
+    kFlagBlockedSeed = 1u << 5,
+    kFlagBadBlocked = 1u << 6,
+    kFlagDataMask = 0xFFu,
+    kFlagPairOverflow = 1u << 8,   // pair buffer too small for the tile: redo
+    kFlagBigCapacity = 1u << 9,    // big-world scratch too small
+    kFlagSpreadMismatch = 1u << 10, // T_{r+1} != T_r - gain_r
+    kFlagDomPasses = 1u << 11       // dominator passes did not settle
+};
+
+// Graph as kept by a handle.  col/thr are padded with 4..7 trailing entries
+// so that 16-byte loads of any 4-aligned group of slots stay in bounds.
+struct GraphDev {
+    int32_t n;
+    int64_t m;
+    int64_t m_pad;
+    int32_t* off;  // [n+1]
+    int32_t* col;  // [m_pad]
+    uint32_t* thr; // [m_pad]
+};
+
+// Round and tile counters, one instance in device memory per call.
+struct RoundCtl {
+    uint32_t flags;
+    int32_t stop;
+    int32_t round;
+    int32_t ustar;
+    uint32_t next_world;
+    uint32_t n_big;
+    uint32_t next_big;
+    uint32_t pad0;
+    unsigned long long pair_count;
+    long long total;         // sum of |R_w| over the worlds evaluated this round
+    long long expect_total;  // T_r - gain_r from the previous selection (-1: none)
+    long long best_gain;
+};
+
+// Scratch of the workgroup-per-world path, one slot per resident workgroup.
+struct BigSlots {
+    int32_t n_slots;
+    int64_t xcap;      // extra-edge capacity per slot
+    int32_t* lid_of;   // [slots][n]   node -> local id, -1 = absent
+    int32_t* nodes;    // [slots][n]
+    int32_t* parent;   // [slots][n]
+    int32_t* idom;     // [slots][n]
+    int32_t* aux;      // [slots][n]
+    int32_t* lvl;      // [slots][n+3]
+    int32_t* xv;       // [slots][xcap]
+    int32_t* xu;       // [slots][xcap]
+};
+
+// Everything a tile of world evaluations writes.
+struct TileOut {
+    int32_t* pair_node;  // [pair_cap]
+    int32_t* pair_cnt;   // [pair_cap]
+    unsigned long long pair_cap;
+    int32_t* world_size; // [tile] or nullptr
+    int64_t* world_sum;  // [tile] or nullptr
+    int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
+    int32_t* big_list;   // [tile]
+};
+
+struct QueryDev {
+    const uint32_t* excl; // bitmap: seeds and blocked nodes
+    const int32_t* seeds;
+    int32_t n_seeds;
+    uint32_t key0, key1;
+};
+
+// Bucketed reduction scratch.
+struct ReduceBufs {
+    int32_t nb;          // node buckets
+    int32_t g1;          // chunks of the histogram pass
+    int32_t slices;      // workgroups per bucket in the accumulate pass
+    int32_t* hist;       // [nb * g1 + 1]
+    int32_t* sorted_node;
+    int32_t* sorted_cnt;
+    int64_t* part;       // [slices][nb << kBucketShift]
+};
+
+constexpr int kBucketShift = 13;  // 8192 nodes per bucket (int64 LDS accumulators: 64 KB)
+
+// ---- launchers (imin_kernels.hip) ----
+hipError_t launch_graph_ingest(const GraphDev& g, const int64_t* row_ptr, const int32_t* col_in,
+                               const float* p, RoundCtl* ctl, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t count, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t count, hipStream_t s);
+hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n_seeds,
+                              const int32_t* blocked, int32_t n_blocked, uint32_t* excl,
+                              RoundCtl* ctl, hipStream_t s);
+hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s);
+hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
+hipError_t launch_world_small(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
+                              uint32_t w_count, const TileOut& out, int grid, hipStream_t s);
+hipError_t launch_world_big(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
+                            const TileOut& out, const BigSlots& bs, hipStream_t s);
+hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
+                               RoundCtl* ctl, int64_t* gain, hipStream_t s);
+hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
+hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl, RoundCtl* ctl,
+                         int64_t* part_gain, int32_t* part_node, int parts, int32_t k,
+                         int32_t* blockers, int64_t* gains, int64_t* totals, int32_t* n_selected,
+                         hipStream_t s);
+
+int small_world_cap();
+int small_world_blocks_per_cu();
+
+} // namespace imin

@@ -31,6 +31,7 @@ pure function of its parameters; ``Graph.sha256`` fingerprints the arrays.
 from __future__ import annotations
 
 import dataclasses
+import functools
 import hashlib
 import math
 
@@ -245,8 +246,10 @@ WORKLOADS = {
 }
 
 
+@functools.lru_cache(maxsize=4)
 def workload(name: str):
-    """(graph, seeds int32, k, theta) for a named workload."""
+    """(graph, seeds int32, k, theta) for a named workload (cached per process;
+    callers must not modify the returned arrays)."""
     spec = WORKLOADS[name]
     g = chung_lu(spec["n"], spec["m"], prob=spec["prob"], gen_seed=spec["gen_seed"], name=name)
     rule, count, qseed = spec["seeds"]

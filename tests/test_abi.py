@@ -1,0 +1,52 @@
+"""The C-ABI library loads and exports every symbol the header declares;
+host-side argument checks work without a GPU (no compute calls here)."""
+import ctypes
+import os
+
+import pytest
+
+from paper_2405_12871_amd import binding
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2405_12871_amd import build
+        build.build()
+    return binding.load()
+
+
+def test_header_declares_the_boundary():
+    names = binding.header_functions()
+    for required in ("imin_graph_create", "imin_graph_destroy", "imin_graph_info", "imin_solve",
+                     "imin_evaluate", "imin_status_string", "imin_last_device_flags"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in binding.header_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(6):
+        s = lib.imin_status_string(code)
+        assert s and s.decode() != "unknown status"
+    assert lib.imin_status_string(99).decode() == "unknown status"
+
+
+def test_host_argument_checks(lib):
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(0x1000)  # never dereferenced: rejected before use
+    # n out of range, negative m, NULL outputs
+    assert lib.imin_graph_create(0, 0, dummy, None, None, None, ctypes.byref(h)) == 1
+    assert lib.imin_graph_create(1 << 24, 0, dummy, None, None, None, ctypes.byref(h)) == 1
+    assert lib.imin_graph_create(5, -1, dummy, None, None, None, ctypes.byref(h)) == 1
+    assert lib.imin_graph_create(5, 3, dummy, None, None, None, ctypes.byref(h)) == 1
+    assert lib.imin_graph_create(5, 0, None, None, None, None, ctypes.byref(h)) == 1
+    assert lib.imin_graph_create(5, 0, dummy, None, None, None, None) == 1
+    # NULL graph handles
+    assert lib.imin_solve(None, dummy, 1, 1, 10, 0, None, dummy, dummy, dummy, dummy) == 1
+    assert lib.imin_evaluate(None, dummy, 1, None, 0, 0, 10, 0, None, dummy, dummy, None, None, None) == 1
+    assert lib.imin_graph_info(None, None, None) == 1
+    assert lib.imin_graph_destroy(None) == 0

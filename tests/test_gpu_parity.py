@@ -1,0 +1,221 @@
+"""Parity of the HIP path with the CPU oracle, through the C ABI.
+
+Integer results must be identical: per-world reached-set sizes and node-id
+sums, per-node gains summed over worlds, totals, blocker sequences, gains and
+spread totals of the greedy rounds.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2405_12871_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2405_12871_amd import binding
+    binding.load()
+    return binding
+
+
+def _eval_both(B, oracle_mod, g, seeds, w0, nw, rng_seed, blocked=()):
+    _log(f"evaluate {g.name} n={g.n} m={g.m} seeds={len(seeds)} worlds=[{w0},{w0 + nw}) blocked={len(blocked)}")
+    G = B.Graph.from_synth(g)
+    gain, total, ws, wsum = B.evaluate(G, seeds, w0, nw, rng_seed, blocked=blocked, per_world=True)
+    q = oracle_mod.Query(g, seeds)
+    ogain, ototal, ows, owsum = q.eval(rng_seed, w0, nw, blocked=blocked, per_world=True)
+    return (gain, total, ws, wsum), (ogain, ototal, ows, owsum)
+
+
+def _assert_same(got, want):
+    gain, total, ws, wsum = got
+    ogain, ototal, ows, owsum = want
+    np.testing.assert_array_equal(ws, ows)
+    np.testing.assert_array_equal(wsum, owsum)
+    np.testing.assert_array_equal(gain, ogain)
+    assert total == ototal
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_evaluate_random_graphs(B, oracle_mod, case):
+    rng = np.random.default_rng(case)
+    n = int(rng.integers(3, 300))
+    m = int(rng.integers(1, 8 * n))
+    g = synth.random_small_graph(n, m, seed=3000 + case, prob=["mixed", "uniform", "wc"][case % 3],
+                                 allow_multi=bool(case % 2))
+    ns = int(rng.integers(1, max(2, n // 5)))
+    seeds = rng.choice(n, ns, replace=False).astype(np.int32)
+    others = np.setdiff1d(np.arange(n), seeds)
+    blocked = rng.choice(others, min(len(others), int(rng.integers(0, 5))), replace=False).tolist()
+    got, want = _eval_both(B, oracle_mod, g, seeds, int(rng.integers(0, 1000)), 777, 40 + case, blocked)
+    _assert_same(got, want)
+
+
+def test_evaluate_small_workload(B, oracle_mod):
+    g, seeds, k, theta = synth.workload("small")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 0, theta, 1)
+    _assert_same(got, want)
+
+
+def test_evaluate_medium_sample(B, oracle_mod):
+    """Big worlds (about 24K reached nodes each): the workgroup-per-world path."""
+    g, seeds, k, theta = synth.workload("medium")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 5000, 300, 7)
+    _assert_same(got, want)
+
+
+def test_evaluate_large_sample(B, oracle_mod):
+    g, seeds, k, theta = synth.workload("large")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 123456, 4000, 11)
+    _assert_same(got, want)
+
+
+def test_world_range_shards_add_up(B):
+    """Gains over [0, 1000) equal the sum over three disjoint sub-ranges."""
+    g, seeds, _, _ = synth.workload("small")
+    G = B.Graph.from_synth(g)
+    full = B.evaluate(G, seeds, 0, 1000, 5)
+    parts = [B.evaluate(G, seeds, a, b - a, 5) for a, b in ((0, 313), (313, 640), (640, 1000))]
+    np.testing.assert_array_equal(full[0], sum(p[0] for p in parts))
+    assert full[1] == sum(p[1] for p in parts)
+
+
+def test_tiles_and_pair_overflow(B, oracle_mod, monkeypatch):
+    """Tiny tiles and a tiny pair buffer force the tile loop and its retry."""
+    g, seeds, _, _ = synth.workload("small")
+    monkeypatch.setenv("IMIN_TILE_WORLDS", "97")
+    monkeypatch.setenv("IMIN_PAIR_CAP", "3000")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 10, 1001, 2)
+    _assert_same(got, want)
+
+
+@pytest.mark.parametrize("shape", ["path", "star", "grid"])
+def test_evaluate_deterministic_shapes(B, oracle_mod, shape):
+    """p = 1 shapes that overflow the LDS path: 1500-level path, 3000-leaf
+    star, 50x50 grid (many equal-level predecessors)."""
+    if shape == "path":
+        n = 1500
+        src, dst = np.arange(n - 1), np.arange(1, n)
+    elif shape == "star":
+        n = 3001
+        src, dst = np.zeros(n - 1, int), np.arange(1, n)
+    else:
+        s = 50
+        n = s * s
+        idx = np.arange(n).reshape(s, s)
+        src = np.concatenate([idx[:, :-1].ravel(), idx[:-1, :].ravel()])
+        dst = np.concatenate([idx[:, 1:].ravel(), idx[1:, :].ravel()])
+    g = synth.from_edges(n, src, dst, np.ones(len(src), np.float32), name=shape)
+    seeds = np.array([0], dtype=np.int32)
+    got, want = _eval_both(B, oracle_mod, g, seeds, 0, 3, 1)
+    _assert_same(got, want)
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_solve_random_graphs(B, oracle_mod, case):
+    rng = np.random.default_rng(100 + case)
+    n = int(rng.integers(5, 400))
+    g = synth.random_small_graph(n, int(rng.integers(n, 6 * n)), seed=4000 + case,
+                                 prob=["mixed", "wc", "uniform"][case % 3])
+    seeds = rng.choice(n, int(rng.integers(1, 6)), replace=False).astype(np.int32)
+    k, theta = int(rng.integers(0, 12)), int(rng.integers(1, 900))
+    _log(f"solve random case={case} n={n} k={k} theta={theta}")
+    G = B.Graph.from_synth(g)
+    res = B.solve(G, seeds, k, theta, 77 + case)
+    want = oracle_mod.Query(g, seeds).solve(k, theta, 77 + case)
+    assert res.n_selected == want["n_selected"]
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+def test_solve_small_workload(B, oracle_mod):
+    g, seeds, k, theta = synth.workload("small")
+    _log("solve small workload")
+    res = B.solve(B.Graph.from_synth(g), seeds, k, theta, 1)
+    want = oracle_mod.Query(g, seeds).solve(k, theta, 1)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+def test_example1_and_submodularity_graph(B):
+    """The paper's worked example and the submodularity-ratio construction."""
+    g = synth.from_edges(7, [0, 0, 1, 2, 3, 3, 5], [1, 2, 3, 3, 5, 6, 6], [1.0] * 7)
+    res = B.solve(B.Graph.from_synth(g), np.array([0], np.int32), 2, 13, 0)
+    assert res.blockers.tolist() == [3, 1]
+    assert res.spread_totals.tolist() == [6 * 13, 3 * 13, 2 * 13]
+    n = 30
+    g2 = synth.from_edges(n, [0, 0, 1, 2] + [3] * (n - 4), [1, 2, 3, 3] + list(range(4, n)), [1.0] * (n - 0))
+    res2 = B.solve(B.Graph.from_synth(g2), np.array([0], np.int32), 10, 5, 0)
+    assert res2.n_selected == 3
+    assert res2.blockers.tolist() == [3, 1, 2]
+    assert res2.spread_totals.tolist() == [n * 5, 15, 10, 5]
+
+
+def test_edge_cases(B):
+    import torch
+    g = synth.random_small_graph(50, 200, seed=1, prob="uniform")
+    G = B.Graph.from_synth(g)
+    # every node a seed: no candidate, nothing selected
+    res = B.solve(G, np.arange(50, dtype=np.int32), 5, 20, 0)
+    assert res.n_selected == 0 and res.spread_totals.tolist() == [50 * 20]
+    # k = 0 still reports T_0
+    res0 = B.solve(G, np.array([3], np.int32), 0, 20, 0)
+    assert res0.n_selected == 0 and len(res0.spread_totals) == 1
+    # theta = 1
+    B.solve(G, np.array([3], np.int32), 3, 1, 0)
+    # a graph without edges
+    e = synth.from_edges(4, [], [], [])
+    r = B.solve(B.Graph.from_synth(e), np.array([1], np.int32), 2, 7, 0)
+    assert r.n_selected == 0 and r.spread_totals.tolist() == [7]
+    # data errors are reported, not crashed on
+    with pytest.raises(B.IminError) as ei:
+        B.solve(G, np.array([3, 3], np.int32), 2, 5, 0)
+    assert ei.value.status == 2
+    with pytest.raises(B.IminError):
+        B.solve(G, np.array([60], np.int32), 2, 5, 0)
+    with pytest.raises(B.IminError) as ei:
+        B.evaluate(G, np.array([3], np.int32), 0, 5, 0, blocked=[3])
+    assert ei.value.status == 2
+    bad = synth.from_edges(3, [0, 1], [1, 2], [0.5, 1.5])
+    with pytest.raises(B.IminError) as ei:
+        B.Graph.from_synth(bad)
+    assert ei.value.status == 2
+    badc = synth.Graph(n=3, row_ptr=np.array([0, 1, 2, 2]), col=np.array([1, 7], np.int32),
+                       p=np.array([0.5, 0.5], np.float32))
+    with pytest.raises(B.IminError):
+        B.Graph.from_synth(badc)
+    torch.cuda.synchronize()
+
+
+def test_large_workload_first_rounds(B, oracle_mod):
+    """Full-size 1M-node workload: the first rounds equal the oracle's; all
+    rounds satisfy the exact invariants."""
+    g, seeds, k, theta = synth.workload("large")
+    _log("solve large workload (full k, theta)")
+    G = B.Graph.from_synth(g)
+    res = B.solve(G, seeds, k, theta, 2024)
+    T = res.spread_totals
+    assert res.n_selected == k
+    assert len(set(res.blockers.tolist())) == k
+    assert not set(res.blockers.tolist()) & set(seeds.tolist())
+    assert np.all(res.gains > 0)
+    np.testing.assert_array_equal(T[1:], T[:-1] - res.gains)
+    kpar = int(os.environ.get("IMIN_TEST_KPAR", "2"))
+    _log(f"oracle solve large workload k={kpar}")
+    want = oracle_mod.Query(g, seeds).solve(kpar, theta, 2024)
+    np.testing.assert_array_equal(res.blockers[:kpar], want["blockers"])
+    np.testing.assert_array_equal(res.gains[:kpar], want["gains"])
+    np.testing.assert_array_equal(T[:kpar + 1], want["spread_totals"])
