@@ -144,10 +144,11 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  * Kernel timing, for measurement.  While enabled, the library brackets its
  * own kernel launches with HIP events on the stream they run on and adds
  * each launch's duration to a per-kernel tally (process-wide).  Kernel ids:
- *   0  world evaluation, LDS path (workgroup of one wave per world)
- *   1  world evaluation, HBM path (workgroup of four waves per world)
+ *   0  world evaluation, small LDS tier (one wave per world)
+ *   1  world evaluation, HBM tier (four waves per world, any size)
  *   2  gain reduction (bucket histogram, scan, scatter, accumulate, sum)
  *   3  greedy selection
+ *   4  world evaluation, large LDS tier (four waves per world)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */

@@ -22,7 +22,7 @@ namespace {
 thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
-constexpr int kTimedKernels = 4;
+constexpr int kTimedKernels = 5;
 struct Timing {
     std::atomic<bool> on{false};
     std::mutex mu;
@@ -138,7 +138,10 @@ struct Session {
     HostCtl hctl;
     // tile outputs
     DevArray<int32_t> world_size;
-    DevArray<int32_t> big_list;
+    DevArray<int32_t> list1, list2;  // worlds handed down to tier 1 / tier 2
+    // level-0 slot groups of the seeds
+    DevArray<int32_t> seed_cnt;
+    DevArray<int4> seed_table;
     DevArray<int32_t> pair_node, pair_cnt;
     // reduction
     DevArray<int32_t> hist, sorted_node, sorted_cnt;
@@ -153,7 +156,8 @@ struct Session {
     int sel_parts = 0;
     size_t tile_cap = 0;   // worlds per tile (buffer size)
     size_t tile = 0;       // worlds per tile in use
-    int small_grid = 0;
+    int grid0 = 0, grid1 = 0;
+    int start_tier = 0;    // first tier tried for every world of a tile
     TimedLaunches timed;
 
     Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
@@ -171,7 +175,8 @@ struct Session {
         tile_cap = std::min<size_t>(theta, env_size("IMIN_TILE_WORLDS", (size_t)1 << 22));
         tile = tile_cap;
         IMIN_TRY(world_size.alloc(tile_cap));
-        IMIN_TRY(big_list.alloc(tile_cap));
+        IMIN_TRY(list1.alloc(tile_cap));
+        IMIN_TRY(list2.alloc(tile_cap));
 
         // pair buffer: enough for the whole tile if worlds are small
         const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
@@ -225,7 +230,9 @@ struct Session {
         sel_parts = (int)std::min<size_t>(1024, (n + 255) / 256);
         IMIN_TRY(sel_g.alloc(sel_parts));
         IMIN_TRY(sel_u.alloc(sel_parts));
-        small_grid = cus * imin::small_world_blocks_per_cu();
+        grid0 = cus * imin::world_tier_blocks_per_cu(0);
+        grid1 = cus * imin::world_tier_blocks_per_cu(1);
+        if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         return IMIN_OK;
     }
 
@@ -267,19 +274,25 @@ struct Session {
             out.world_size = ws_out ? ws_out + done : world_size.p;
             out.world_sum = wsum_out ? wsum_out + done : nullptr;
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
-            out.big_list = big_list.p;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            hipEvent_t ev = timed.begin(s);
-            IMIN_TRY(imin::launch_world_small(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, out,
-                                              small_grid, s));
-            timed.end(0, ev, s);
-            ev = timed.begin(s);
-            IMIN_TRY(imin::launch_world_big(g, q, ctl.p, (uint32_t)(w_begin + done), out, bs, s));
-            timed.end(1, ev, s);
+            const uint32_t wb = (uint32_t)(w_begin + done);
+            for (int tier = start_tier; tier < 3; ++tier) {
+                const uint32_t range = (tier == start_tier) ? (uint32_t)nw : 0u;
+                const int32_t* in_list = tier == 1 ? list1.p : (tier == 2 ? list2.p : nullptr);
+                int32_t* next_list = tier == 0 ? list1.p : list2.p;
+                const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
+                hipEvent_t ev = timed.begin(s);
+                IMIN_TRY(imin::launch_world_tier(tier, g, q, ctl.p, wb, range, in_list, next_list, out, bs,
+                                                 tier == 0 ? grid0 : grid1, s));
+                timed.end(timer_id, ev, s);
+            }
             imin_status_t st = read_ctl();
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
-            if (f & imin::kFlagBigCapacity) {
+            // route later tiles straight to the tier most worlds end up in
+            if (start_tier < 2 && hctl.p->list_n[2] * 2 > nw) start_tier = 2;
+            else if (start_tier < 1 && hctl.p->list_n[1] * 2 > nw) start_tier = 1;
+            if (f & (imin::kFlagBigCapacity | imin::kFlagDomPasses)) {
                 g_last_flags = f;
                 return IMIN_ERR_INTERNAL;
             }
@@ -303,7 +316,7 @@ struct Session {
                 }
                 continue;  // redo this tile
             }
-            ev = timed.begin(s);
+            hipEvent_t ev = timed.begin(s);
             IMIN_TRY(imin::launch_reduce_pairs(g, out, rb, ctl.p, gain.p, s));
             timed.end(2, ev, s);
             IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
@@ -399,11 +412,23 @@ static imin_status_t setup_query(Session& ss, const int32_t* seeds, int32_t n_se
     if (st != IMIN_OK) return st;
     st = check_data_flags(ss.hctl.p->flags);
     if (st != IMIN_OK) return st;
+    // level-0 table: slot groups of every seed's row
+    IMIN_TRY(ss.seed_cnt.alloc((size_t)n_seeds));
+    IMIN_TRY(imin::launch_seed_count(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.ctl.p, ss.s));
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    const int32_t chunks = ss.hctl.p->seed_chunks;
+    IMIN_TRY(ss.seed_table.alloc((size_t)std::max(chunks, 1)));
+    if (chunks > 0) IMIN_TRY(imin::launch_seed_fill(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.seed_table.p, ss.s));
     q.excl = ss.excl.p;
     q.seeds = seeds;
     q.n_seeds = n_seeds;
     q.key0 = (uint32_t)rng_seed;
     q.key1 = (uint32_t)(rng_seed >> 32);
+    q.seed_chunk = ss.seed_table.p;
+    q.n_seed_chunks = chunks;
+    q.seed_sum = ss.hctl.p->seed_sum;
+    q.seed_edges = ss.hctl.p->seed_edges;
     return IMIN_OK;
 }
 

@@ -1,0 +1,87 @@
+// Device helpers shared by the kernels: the coin generator, bit tests and
+// block-wide scans for wave64 workgroups.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace imin {
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter words 2 and
+// 3 fixed at zero: counter (c0, c1, 0, 0), key (k0, k1).  Ten rounds of two
+// 32x32->64 products; the key advances by the Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
+    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)x0 * 0xD2511F53ull;
+        const uint64_t b = (uint64_t)x2 * 0xCD9E8D57ull;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
+        x1 = (uint32_t)b;
+        x3 = (uint32_t)a;
+        x0 = n0;
+        x2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(x0, x1, x2, x3);
+}
+
+__device__ __forceinline__ bool bit_set(const uint32_t* bits, int32_t v) {
+    return (bits[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64);
+// `tmp` holds NT/64 ints of LDS.  All threads must call it.
+template <int NT>
+__device__ __forceinline__ int block_excl_scan(int x, int* tmp, int& total) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    int inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if constexpr (NT == 64) {
+        total = __shfl(inc, 63, 64);
+        return inc - x;
+    } else {
+        if (lane == 63) tmp[wid] = inc;
+        __syncthreads();
+        int pre = 0, tot = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) {
+            const int v = tmp[i];
+            pre += (i < wid) ? v : 0;
+            tot += v;
+        }
+        __syncthreads();
+        total = tot;
+        return pre + inc - x;
+    }
+}
+
+// Sum over a workgroup of NT threads; `tmp` holds NT/64 values of LDS.
+template <int NT>
+__device__ __forceinline__ long long block_sum_ll(long long x, long long* tmp) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    if constexpr (NT == 64) {
+        return x;
+    } else {
+        if (lane == 0) tmp[wid] = x;
+        __syncthreads();
+        long long s = 0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += tmp[i];
+        __syncthreads();
+        return s;
+    }
+}
+
+}  // namespace imin

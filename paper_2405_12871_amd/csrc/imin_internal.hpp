@@ -43,14 +43,16 @@ struct RoundCtl {
     int32_t stop;
     int32_t round;
     int32_t ustar;
-    uint32_t next_world;
-    uint32_t n_big;
-    uint32_t next_big;
-    uint32_t pad0;
+    uint32_t next[3];        // work counters of the three world tiers
+    uint32_t list_n[3];      // worlds handed down to tier 1 and tier 2
     unsigned long long pair_count;
     long long total;         // sum of |R_w| over the worlds evaluated this round
     long long expect_total;  // T_r - gain_r from the previous selection (-1: none)
     long long best_gain;
+    long long seed_sum;      // sum of the seed ids
+    long long seed_edges;    // CSR slots leaving the seeds
+    int32_t seed_chunks;     // entries of the level-0 slot-group table
+    int32_t pad1;
 };
 
 // Scratch of the workgroup-per-world path, one slot per resident workgroup.
@@ -75,14 +77,17 @@ struct TileOut {
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
-    int32_t* big_list;   // [tile]
 };
 
 struct QueryDev {
-    const uint32_t* excl; // bitmap: seeds and blocked nodes
+    const uint32_t* excl;    // bitmap: seeds and blocked nodes
     const int32_t* seeds;
     int32_t n_seeds;
     uint32_t key0, key1;
+    const int4* seed_chunk;  // level-0 slot groups {blk, seed lid, e0, e1}
+    int32_t n_seed_chunks;
+    long long seed_sum;
+    long long seed_edges;
 };
 
 // Bucketed reduction scratch.
@@ -109,10 +114,14 @@ hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n
                               RoundCtl* ctl, hipStream_t s);
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
-hipError_t launch_world_small(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                              uint32_t w_count, const TileOut& out, int grid, hipStream_t s);
-hipError_t launch_world_big(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                            const TileOut& out, const BigSlots& bs, hipStream_t s);
+hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
+                             uint32_t range_count, const int32_t* in_list, int32_t* next_list,
+                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
+hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
+                             hipStream_t s);
+hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
+                            int4* table, hipStream_t s);
+int world_tier_blocks_per_cu(int tier);
 hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
                                RoundCtl* ctl, int64_t* gain, hipStream_t s);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
@@ -121,7 +130,5 @@ hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl,
                          int32_t* blockers, int64_t* gains, int64_t* totals, int32_t* n_selected,
                          hipStream_t s);
 
-int small_world_cap();
-int small_world_blocks_per_cu();
 
 } // namespace imin

@@ -1,506 +1,15 @@
-// Device code for the IMIN sampling estimator on gfx950 (wave64).
+// Device code around the world evaluation: graph ingest (offsets, coin
+// thresholds, validation), query set-up, the atomic-free per-node gain
+// reduction and the greedy selection.
 //
-// One world is one live-edge realization (Section 2.1, Eq. 1).  A workgroup
-// evaluates a world end to end:
-//   1. level-synchronous BFS from the seeds over live edges, never entering a
-//      blocked node; edge coins are Philox4x32-10 blocks drawn lazily, only
-//      for the out-edges of reached nodes (unscanned edges cannot change the
-//      reached set); each claimed node gets a local id in BFS order and its
-//      BFS parent, and every other live edge between reached nodes is kept;
-//   2. immediate dominators under the virtual source (Section 3.1) by
-//      level-ordered passes: idom(v) = lowest common ancestor of all of v's
-//      live predecessors in the current tree (a node whose only predecessor
-//      is its BFS parent keeps it);
-//   3. subtree sizes c(v) = 1 + sum over children, deepest level first
-//      (Section 2.2: the estimator measures every subtree);
-//   4. (node, c) pairs for the reached non-seeds go to a pair buffer.
-// The per-node sums over worlds are formed without global atomics: pairs are
-// counting-sorted into node buckets, each bucket is accumulated in LDS, and
-// per-slice partial vectors are added in a fixed order.
+// The per-node sums over worlds are formed without global atomics: a tile's
+// (node, count) pairs are counting-sorted into node buckets of 8192 nodes,
+// each (bucket, slice) is accumulated in LDS, and the slices' partial vectors
+// are added in a fixed order.
+#include "imin_device.hpp"
 #include "imin_internal.hpp"
 
-#include <hip/hip_runtime.h>
-
 namespace imin {
-
-// ---------------------------------------------------------------- Philox
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter words 2 and
-// 3 fixed at zero: counter (c0, c1, 0, 0), key (k0, k1).
-__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
-    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t a = (uint64_t)x0 * 0xD2511F53ull;
-        const uint64_t b = (uint64_t)x2 * 0xCD9E8D57ull;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ x1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ x3 ^ k1;
-        x1 = (uint32_t)b;
-        x3 = (uint32_t)a;
-        x0 = n0;
-        x2 = n2;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return make_uint4(x0, x1, x2, x3);
-}
-
-__device__ __forceinline__ bool bit_set(const uint32_t* bits, int32_t v) {
-    return (bits[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u;
-}
-
-// --------------------------------------------------------- block helpers
-template <int NT>
-__device__ __forceinline__ int block_excl_scan(int x, int* tmp, int& total) {
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    int inc = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += y;
-    }
-    if constexpr (NT == 64) {
-        total = __shfl(inc, 63, 64);
-        return inc - x;
-    } else {
-        if (lane == 63) tmp[wid] = inc;
-        __syncthreads();
-        int pre = 0, tot = 0;
-#pragma unroll
-        for (int i = 0; i < NT / 64; ++i) {
-            const int v = tmp[i];
-            pre += (i < wid) ? v : 0;
-            tot += v;
-        }
-        __syncthreads();
-        total = tot;
-        return pre + inc - x;
-    }
-}
-
-template <int NT>
-__device__ __forceinline__ long long block_sum_ll(long long x, long long* tmp) {
-    const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    if constexpr (NT == 64) {
-        return x;
-    } else {
-        if (lane == 0) tmp[wid] = x;
-        __syncthreads();
-        long long s = 0;
-#pragma unroll
-        for (int i = 0; i < NT / 64; ++i) s += tmp[i];
-        __syncthreads();
-        return s;
-    }
-}
-
-// ------------------------------------------------------ per-world shared
-template <int NT>
-struct WorldShared {
-    int count;    // local ids handed out (= nodes reached so far)
-    int n_extra;  // non-tree live edges recorded
-    int overflow; // capacity exceeded: abandon the world
-    int changed;
-    int nonfwd;   // some non-tree edge does not go one level down
-    int widx;
-    unsigned long long pair_base;
-    int row_lid[NT];
-    int row_node[NT];
-    int row_e0[NT];
-    int row_e1[NT];
-    int row_start[NT];
-    int scan_tmp[NT / 64 > 0 ? NT / 64 : 1];
-    long long sum_tmp[NT / 64 > 0 ? NT / 64 : 1];
-    long long edges;  // CSR slots of reached nodes (coins this world needs)
-};
-
-// ---------------------------------------------------- small-world store
-// Everything in LDS: an open-addressing node -> local id table and the
-// per-local-id arrays.  Capacities bound the world; a world that exceeds any
-// of them is handed to the big-world path.
-constexpr int kMaxDomPasses = 4096;
-constexpr int kSmallCap = 1024;      // reached nodes
-constexpr int kSmallHashBits = 11;   // 2048 slots, load <= 1/2
-constexpr int kSmallXCap = 256;      // non-tree live edges
-constexpr int kSmallLvCap = 62;      // BFS levels
-
-struct SmallStore {
-    static constexpr int kHash = 1 << kSmallHashBits;
-    int32_t keys[kHash];
-    int16_t vals[kHash];
-    int32_t nodes[kSmallCap];
-    int16_t parent[kSmallCap];
-    int16_t idom[kSmallCap];
-    int32_t aux[kSmallCap];
-    int32_t xv[kSmallXCap];
-    int16_t xu[kSmallXCap];
-    int32_t lvl[kSmallLvCap + 2];
-
-    __device__ static constexpr int cap_r() { return kSmallCap; }
-    __device__ static constexpr int cap_x() { return kSmallXCap; }
-    __device__ static constexpr int cap_lv() { return kSmallLvCap; }
-
-    __device__ __forceinline__ static uint32_t hash(int32_t v) {
-        return ((uint32_t)v * 0x9E3779B1u) >> (32 - kSmallHashBits);
-    }
-    __device__ void seed(int32_t v, int lid) {
-        uint32_t h = hash(v);
-        for (int probe = 0; probe < kHash; ++probe) {
-            if (atomicCAS(&keys[h], -1, v) == -1) {
-                vals[h] = (int16_t)lid;
-                return;
-            }
-            h = (h + 1) & (kHash - 1);
-        }
-    }
-    // New node: its local id.  Already present: -1.  Out of room: -2.
-    __device__ int claim(int32_t v, int* counter) {
-        uint32_t h = hash(v);
-        for (int probe = 0; probe < kHash; ++probe) {
-            const int32_t old = atomicCAS(&keys[h], -1, v);
-            if (old == -1) {
-                const int lid = atomicAdd(counter, 1);
-                if (lid >= kSmallCap) return -2;
-                vals[h] = (int16_t)lid;
-                return lid;
-            }
-            if (old == v) return -1;
-            h = (h + 1) & (kHash - 1);
-        }
-        return -2;
-    }
-    __device__ int lookup(int32_t v) const {
-        uint32_t h = hash(v);
-        for (int probe = 0; probe < kHash; ++probe) {
-            if (keys[h] == v) return vals[h];
-            h = (h + 1) & (kHash - 1);
-        }
-        return -1;
-    }
-    __device__ int get_parent(int i) const { return parent[i]; }
-    __device__ void set_parent(int i, int v) { parent[i] = (int16_t)v; }
-    __device__ int get_idom(int i) const { return idom[i]; }
-    __device__ void set_idom(int i, int v) { idom[i] = (int16_t)v; }
-    __device__ int get_xu(int x) const { return xu[x]; }
-    __device__ void set_xu(int x, int v) { xu[x] = (int16_t)v; }
-    template <int NT>
-    __device__ void reset(int /*count*/) {
-        for (int i = threadIdx.x; i < kHash; i += NT) keys[i] = -1;
-    }
-};
-
-// ------------------------------------------------------ big-world store
-// Per-slot arrays in HBM, sized for the whole graph (a world can reach every
-// node and keep every edge), so this path never runs out of room.
-struct BigStore {
-    int32_t* lid_of;
-    int32_t* nodes;
-    int32_t* parent_;
-    int32_t* idom_;
-    int32_t* aux;
-    int32_t* lvl;
-    int32_t* xv;
-    int32_t* xu_;
-    int32_t cap_r_;
-    int32_t cap_lv_;
-    int64_t cap_x_;
-
-    __device__ int cap_r() const { return cap_r_; }
-    __device__ int64_t cap_x() const { return cap_x_; }
-    __device__ int cap_lv() const { return cap_lv_; }
-    __device__ void seed(int32_t v, int lid) { lid_of[v] = lid; }
-    __device__ int claim(int32_t v, int* counter) {
-        if (atomicCAS(&lid_of[v], -1, -2) != -1) return -1;
-        const int lid = atomicAdd(counter, 1);
-        lid_of[v] = lid;
-        return lid;
-    }
-    __device__ int lookup(int32_t v) const { return lid_of[v]; }
-    __device__ int get_parent(int i) const { return parent_[i]; }
-    __device__ void set_parent(int i, int v) { parent_[i] = v; }
-    __device__ int get_idom(int i) const { return idom_[i]; }
-    __device__ void set_idom(int i, int v) { idom_[i] = v; }
-    __device__ int get_xu(int64_t x) const { return xu_[x]; }
-    __device__ void set_xu(int64_t x, int v) { xu_[x] = v; }
-    template <int NT>
-    __device__ void reset(int count) {
-        for (int i = threadIdx.x; i < count; i += NT) lid_of[nodes[i]] = -1;
-    }
-};
-
-// ------------------------------------------------------- one world
-// Returns false when the store ran out of room (the world is then redone by
-// the big-world path).  On success writes the world's pairs and size.
-template <int NT, class Store>
-__device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w,
-                               uint32_t wi, const TileOut& out, Store& st, WorldShared<NT>& sh) {
-    const int t = threadIdx.x;
-    const int ns = q.n_seeds;
-    if (ns > st.cap_r()) return false;  // uniform
-
-    // ---- seeds: level 0, parent = virtual source (-1)
-    for (int i = t; i < ns; i += NT) {
-        const int32_t v = q.seeds[i];
-        st.seed(v, i);
-        st.nodes[i] = v;
-        st.set_parent(i, -1);
-    }
-    if (t == 0) {
-        sh.count = ns;
-        sh.edges = 0;
-        sh.n_extra = 0;
-        sh.overflow = 0;
-        st.lvl[0] = 0;
-        st.lvl[1] = ns;
-    }
-    __syncthreads();
-
-    // ---- level-synchronous BFS with lazy coins
-    int nlev = 1;  // closed levels: lvl[0..nlev]
-    for (;;) {
-        const int f0 = st.lvl[nlev - 1];
-        const int f1 = st.lvl[nlev];
-        if (f0 == f1) break;
-        for (int base = f0; base < f1; base += NT) {
-            const int i = base + t;
-            int nb = 0, u = 0, e0 = 0, e1 = 0;
-            if (i < f1) {
-                u = st.nodes[i];
-                e0 = g.off[u];
-                e1 = g.off[u + 1];
-                nb = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
-            }
-            int total;
-            const int start = block_excl_scan<NT>(nb, sh.scan_tmp, total);
-            if (out.world_edges && e1 > e0) atomicAdd((unsigned long long*)&sh.edges, (unsigned long long)(e1 - e0));
-            sh.row_lid[t] = i;
-            sh.row_node[t] = u;
-            sh.row_e0[t] = e0;
-            sh.row_e1[t] = e1;
-            sh.row_start[t] = start;
-            __syncthreads();
-            const int nrows = (f1 - base < NT) ? (f1 - base) : NT;
-            for (int j = t; j < total; j += NT) {
-                int lo = 0, hi = nrows - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (sh.row_start[mid] <= j) lo = mid; else hi = mid - 1;
-                }
-                const int re0 = sh.row_e0[lo];
-                const int re1 = sh.row_e1[lo];
-                const int ulid = sh.row_lid[lo];
-                const int32_t unode = sh.row_node[lo];
-                const uint32_t blk = (uint32_t)(re0 >> 2) + (uint32_t)(j - sh.row_start[lo]);
-                const uint4 coin = philox_block(blk, w, q.key0, q.key1);
-                const int4 cv = *reinterpret_cast<const int4*>(g.col + 4 * (size_t)blk);
-                const uint4 tv = *reinterpret_cast<const uint4*>(g.thr + 4 * (size_t)blk);
-                const int ebase = (int)(4 * blk);
-                const int32_t vv[4] = {cv.x, cv.y, cv.z, cv.w};
-                const uint32_t tt[4] = {tv.x, tv.y, tv.z, tv.w};
-                const uint32_t cc[4] = {coin.x, coin.y, coin.z, coin.w};
-#pragma unroll
-                for (int qd = 0; qd < 4; ++qd) {
-                    const int e = ebase + qd;
-                    if (e < re0 || e >= re1) continue;
-                    const uint32_t th = tt[qd];
-                    if (!(th == kAlwaysLive || cc[qd] < th)) continue;
-                    const int32_t v = vv[qd];
-                    if (v == unode || bit_set(q.excl, v)) continue;
-                    const int lid = st.claim(v, &sh.count);
-                    if (lid >= 0) {
-                        st.nodes[lid] = v;
-                        st.set_parent(lid, ulid);
-                    } else if (lid == -1) {
-                        const int x = atomicAdd(&sh.n_extra, 1);
-                        if (x < st.cap_x()) {
-                            st.xv[x] = v;
-                            st.set_xu(x, ulid);
-                        } else {
-                            sh.overflow = 1;
-                        }
-                    } else {
-                        sh.overflow = 1;
-                    }
-                }
-            }
-            __syncthreads();
-            if (sh.overflow) break;
-        }
-        if (sh.overflow) break;
-        if (nlev + 1 > st.cap_lv()) {
-            sh.overflow = 1;  // every thread sees the same nlev: uniform
-            break;
-        }
-        if (t == 0) st.lvl[nlev + 1] = sh.count;
-        __syncthreads();
-        ++nlev;
-    }
-    __syncthreads();
-    if (sh.overflow) return false;
-    // The last closed level is empty: levels 0..nlev-2 hold nodes.
-    const int nlevels = nlev - 1;
-    const int R = sh.count;
-    const int nx = sh.n_extra;
-
-    // ---- dominators
-    for (int x = t; x < nx; x += NT) st.xv[x] = st.lookup(st.xv[x]);
-    for (int i = t; i < R; i += NT) {
-        const int p = st.get_parent(i);
-        st.set_idom(i, p);
-        st.aux[i] = p;
-    }
-    if (t == 0) sh.nonfwd = 0;
-    __syncthreads();
-    for (int x = t; x < nx; x += NT) {
-        // forward edge: u sits exactly one level above v
-        const int v = st.xv[x];
-        const int u = st.get_xu(x);
-        int lo = 0, hi = nlevels - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (st.lvl[mid] <= v) lo = mid; else hi = mid - 1;
-        }
-        const bool fwd = (lo >= 1) && (u >= st.lvl[lo - 1]) && (u < st.lvl[lo]);
-        if (!fwd) sh.nonfwd = 1;
-    }
-    __syncthreads();
-    if (nx > 0) {
-        // Each pass that changes anything lowers some idom index, so the loop
-        // ends; the cap only guards against a broken invariant.
-        for (int pass = 0;; ++pass) {
-            if (pass >= kMaxDomPasses) {
-                if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagDomPasses);
-                break;
-            }
-            if (t == 0) sh.changed = 0;
-            __syncthreads();
-            for (int L = 1; L < nlevels; ++L) {
-                const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
-                for (int x = t; x < nx; x += NT) {
-                    const int v = st.xv[x];
-                    if (v < v0 || v >= v1) continue;
-                    int a = st.get_parent(v);
-                    int b = st.get_xu(x);
-                    while (a != b) {
-                        if (a > b) a = st.get_idom(a); else b = st.get_idom(b);
-                    }
-                    atomicMin(&st.aux[v], a);
-                }
-                __syncthreads();
-                for (int x = t; x < nx; x += NT) {
-                    const int v = st.xv[x];
-                    if (v < v0 || v >= v1) continue;
-                    const int nv = st.aux[v];
-                    if (nv != st.get_idom(v)) {
-                        st.set_idom(v, nv);
-                        sh.changed = 1;
-                    }
-                }
-                __syncthreads();
-            }
-            const bool again = sh.nonfwd && sh.changed;
-            __syncthreads();
-            if (!again) break;
-        }
-    }
-
-    // ---- subtree sizes, deepest level first
-    for (int i = t; i < R; i += NT) st.aux[i] = 1;
-    __syncthreads();
-    for (int L = nlevels - 1; L >= 1; --L) {
-        for (int i = st.lvl[L] + t; i < st.lvl[L + 1]; i += NT) {
-            const int p = st.get_idom(i);
-            if (p >= 0) atomicAdd(&st.aux[p], st.aux[i]);
-        }
-        __syncthreads();
-    }
-
-    // ---- outputs
-    const int len = R - ns;
-    if (t == 0) sh.pair_base = atomicAdd(&ctl->pair_count, (unsigned long long)len);
-    __syncthreads();
-    const unsigned long long pb = sh.pair_base;
-    if (pb + (unsigned long long)len <= out.pair_cap) {
-        for (int i = t; i < len; i += NT) {
-            out.pair_node[pb + i] = st.nodes[ns + i];
-            out.pair_cnt[pb + i] = st.aux[ns + i];
-        }
-    } else if (t == 0) {
-        atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
-    }
-    long long s = 0;
-    for (int i = t; i < R; i += NT) s += st.nodes[i];
-    s = block_sum_ll<NT>(s, sh.sum_tmp);
-    if (t == 0) {
-        if (out.world_size) out.world_size[wi] = R;
-        if (out.world_sum) out.world_sum[wi] = s;
-        if (out.world_edges) out.world_edges[wi] = sh.edges;
-    }
-    return true;
-}
-
-// ------------------------------------------------------- world kernels
-constexpr int kSmallNT = 64;
-constexpr int kBigNT = 256;
-
-__global__ __launch_bounds__(kSmallNT) void k_world_small(GraphDev g, QueryDev q, RoundCtl* ctl,
-                                                          uint32_t w_begin, uint32_t w_count,
-                                                          TileOut out) {
-    __shared__ SmallStore st;
-    __shared__ WorldShared<kSmallNT> sh;
-    const int t = threadIdx.x;
-    for (int i = t; i < SmallStore::kHash; i += kSmallNT) st.keys[i] = -1;
-    __syncthreads();
-    for (;;) {
-        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next_world, 1u);
-        __syncthreads();
-        const uint32_t wi = (uint32_t)sh.widx;
-        if (wi >= w_count) break;
-        const bool ok = evaluate_world<kSmallNT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
-        if (!ok && t == 0) {
-            const uint32_t pos = atomicAdd(&ctl->n_big, 1u);
-            out.big_list[pos] = (int32_t)wi;
-        }
-        st.reset<kSmallNT>(0);
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(kBigNT) void k_world_big(GraphDev g, QueryDev q, RoundCtl* ctl,
-                                                      uint32_t w_begin, TileOut out, BigSlots bs) {
-    __shared__ WorldShared<kBigNT> sh;
-    const int t = threadIdx.x;
-    const size_t slot = blockIdx.x;
-    const size_t n = (size_t)g.n;
-    BigStore st;
-    st.lid_of = bs.lid_of + slot * n;
-    st.nodes = bs.nodes + slot * n;
-    st.parent_ = bs.parent + slot * n;
-    st.idom_ = bs.idom + slot * n;
-    st.aux = bs.aux + slot * n;
-    st.lvl = bs.lvl + slot * (n + 3);
-    st.xv = bs.xv + slot * (size_t)bs.xcap;
-    st.xu_ = bs.xu + slot * (size_t)bs.xcap;
-    st.cap_r_ = g.n;
-    st.cap_lv_ = g.n + 1;
-    st.cap_x_ = bs.xcap;
-    const uint32_t n_big = ctl->n_big;
-    for (;;) {
-        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next_big, 1u);
-        __syncthreads();
-        const uint32_t k = (uint32_t)sh.widx;
-        if (k >= n_big) break;
-        const uint32_t wi = (uint32_t)out.big_list[k];
-        const bool ok = evaluate_world<kBigNT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
-        if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
-        __syncthreads();
-        st.reset<kBigNT>(sh.count < g.n ? sh.count : g.n);
-        __syncthreads();
-    }
-}
 
 // ------------------------------------------------------ graph ingest
 // Offsets to int32, thresholds from probabilities (p == 1: always live;
@@ -630,9 +139,10 @@ __global__ void k_ctl_reset_round(RoundCtl* ctl) {
     ctl->best_gain = 0;
 }
 __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
-    ctl->next_world = 0;
-    ctl->n_big = 0;
-    ctl->next_big = 0;
+    for (int i = 0; i < 3; ++i) {
+        ctl->next[i] = 0;
+        ctl->list_n[i] = 0;
+    }
     ctl->pair_count = 0;
 }
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
@@ -641,25 +151,6 @@ hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
 }
 hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_tile<<<1, 1, 0, s>>>(ctl);
-    return hipGetLastError();
-}
-
-int small_world_cap() { return kSmallCap; }
-int small_world_blocks_per_cu() {
-    const size_t lds = sizeof(SmallStore) + sizeof(WorldShared<kSmallNT>);
-    int b = (int)((160 * 1024) / lds);
-    return b < 1 ? 1 : b;
-}
-
-hipError_t launch_world_small(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                              uint32_t w_count, const TileOut& out, int grid, hipStream_t s) {
-    k_world_small<<<grid, kSmallNT, 0, s>>>(g, q, ctl, w_begin, w_count, out);
-    return hipGetLastError();
-}
-
-hipError_t launch_world_big(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                            const TileOut& out, const BigSlots& bs, hipStream_t s) {
-    k_world_big<<<bs.n_slots, kBigNT, 0, s>>>(g, q, ctl, w_begin, out, bs);
     return hipGetLastError();
 }
 

@@ -1,0 +1,556 @@
+// World evaluation on gfx950: one workgroup evaluates one live-edge world
+// (a realization, Section 2.1, Eq. 1) end to end.
+//
+//   1. Level-synchronous BFS from the seeds over live edges, never entering a
+//      seed again or a blocked node.  Coins are Philox4x32-10 blocks drawn
+//      lazily, one block per 4-aligned group of CSR slots of a reached row
+//      (unscanned edges cannot change the reached set).  Level 0 walks a
+//      per-query table of the seeds' slot groups; deeper levels lay their
+//      rows out with a block-wide scan.  A claimed node gets a local id in
+//      BFS order and its BFS parent; every other live edge into a reached
+//      non-seed is kept ("extra" edge).  Edges into seeds never matter: a
+//      seed's only dominator is the virtual source (Section 3.1).
+//   2. Immediate dominators under the virtual source: every dominator of v
+//      lies on a shortest path, so a strict dominator has a smaller BFS level
+//      and a smaller local id.  Starting from the BFS tree, levels are swept
+//      in order and each v with extra edges gets
+//        idom(v) = lowest common ancestor of {parent(v)} and its extra
+//                  predecessors in the current tree,
+//      computed as the smallest id among LCA(parent(v), u) (all lie on
+//      parent(v)'s chain).  Sweeps repeat until nothing changes; one sweep
+//      suffices when every extra edge goes exactly one level down.
+//   3. Subtree sizes c(v) = 1 + sum over children, deepest level first
+//      (Section 2.2: c(v) is the number of nodes v protects in this world).
+//   4. (node, c) pairs of the reached non-seeds go to the tile's pair buffer.
+//
+// Three tiers share this code: a one-wave workgroup with everything in LDS
+// (worlds of up to 384 non-seed nodes), a four-wave workgroup with a larger
+// LDS store (up to 2048), and a four-wave workgroup whose per-world arrays
+// live in HBM (any size).  A world that outgrows a tier is redone by the next
+// one; every tier gives the same integers.
+#include "imin_device.hpp"
+#include "imin_internal.hpp"
+
+namespace imin {
+
+constexpr int kMaxDomPasses = 4096;
+
+template <int NT>
+struct WorldShared {
+    int count;    // local ids handed out (= nodes reached so far)
+    int n_extra;  // extra edges recorded
+    int overflow; // store out of room: hand the world to the next tier
+    int changed;
+    int nonfwd;   // some extra edge does not go exactly one level down
+    int widx;
+    unsigned long long pair_base;
+    long long edges;  // CSR slots of reached rows
+    int row_lid[NT];
+    int row_node[NT];
+    int row_e0[NT];
+    int row_e1[NT];
+    int row_start[NT];
+    int scan_tmp[NT / 64];
+    long long sum_tmp[NT / 64];
+};
+
+// ------------------------------------------------------------ LDS store
+// Seeds are implicit (local ids 0..ns-1, nodes read from the seed array,
+// parent and idom = virtual source); only non-seed nodes are stored, at
+// index lid - ns.  Node -> local id is an open-addressing table.
+template <int CAPNS, int HBITS, int XCAP, int LVCAP>
+struct LdsStore {
+    static constexpr int kHash = 1 << HBITS;
+    static constexpr int kMaxSeeds = 32767 - CAPNS;  // local ids fit int16
+    int32_t keys[kHash];
+    int16_t vals[kHash];
+    int32_t nodes[CAPNS];
+    int16_t parent[CAPNS];
+    int16_t idom[CAPNS];
+    int32_t aux[CAPNS];
+    int32_t xv[XCAP];
+    int16_t xu[XCAP];
+    int32_t lvl[LVCAP + 2];
+    int32_t ns;
+    const int32_t* seeds;
+
+    __device__ static constexpr int cap_lv() { return LVCAP; }
+    __device__ static constexpr int cap_x() { return XCAP; }
+    __device__ bool fits(int n_seeds) const { return n_seeds <= kMaxSeeds; }
+
+    __device__ __forceinline__ static uint32_t hash(int32_t v) {
+        return ((uint32_t)v * 0x9E3779B1u) >> (32 - HBITS);
+    }
+    template <int NT>
+    __device__ void clear() {
+        for (int i = threadIdx.x; i < kHash; i += NT) keys[i] = -1;
+    }
+    template <int NT>
+    __device__ void init_seeds(const QueryDev& q) {
+        if (threadIdx.x == 0) {
+            ns = q.n_seeds;
+            seeds = q.seeds;
+        }
+    }
+    // New node: its local id.  Already present: -1.  Out of room: -2.
+    __device__ int claim(int32_t v, int* counter) {
+        uint32_t h = hash(v);
+        for (int probe = 0; probe < kHash; ++probe) {
+            const int32_t old = atomicCAS(&keys[h], -1, v);
+            if (old == -1) {
+                const int lid = atomicAdd(counter, 1);
+                if (lid - ns >= CAPNS) return -2;
+                vals[h] = (int16_t)(lid - ns);
+                return lid;
+            }
+            if (old == v) return -1;
+            h = (h + 1) & (kHash - 1);
+        }
+        return -2;
+    }
+    __device__ int lookup(int32_t v) const {
+        uint32_t h = hash(v);
+        for (int probe = 0; probe < kHash; ++probe) {
+            if (keys[h] == v) return (int)vals[h] + ns;
+            h = (h + 1) & (kHash - 1);
+        }
+        return -1;
+    }
+    __device__ int32_t node(int lid) const { return lid < ns ? seeds[lid] : nodes[lid - ns]; }
+    __device__ void set_node(int lid, int32_t v) { nodes[lid - ns] = v; }
+    __device__ int get_parent(int lid) const { return lid < ns ? -1 : (int)parent[lid - ns]; }
+    __device__ void set_parent(int lid, int p) { parent[lid - ns] = (int16_t)p; }
+    __device__ int get_idom(int lid) const { return lid < ns ? -1 : (int)idom[lid - ns]; }
+    __device__ void set_idom(int lid, int p) { idom[lid - ns] = (int16_t)p; }
+    __device__ int32_t* aux_ptr(int lid) { return &aux[lid - ns]; }
+    __device__ int get_xu(int64_t x) const { return xu[x]; }
+    __device__ void set_xu(int64_t x, int u) { xu[x] = (int16_t)u; }
+    template <int NT>
+    __device__ void reset(int /*count*/) { clear<NT>(); }
+};
+
+// ------------------------------------------------------------ HBM store
+// Per-slot arrays sized for the whole graph, so a world never outgrows it.
+struct HbmStore {
+    int32_t* lid_of;  // node -> local id, -1 = absent
+    int32_t* nodes;
+    int32_t* parent_;
+    int32_t* idom_;
+    int32_t* aux;
+    int32_t* lvl;
+    int32_t* xv;
+    int32_t* xu_;
+    int32_t cap_lv_;
+    int64_t cap_x_;
+
+    __device__ int cap_lv() const { return cap_lv_; }
+    __device__ int64_t cap_x() const { return cap_x_; }
+    __device__ bool fits(int) const { return true; }
+    template <int NT>
+    __device__ void init_seeds(const QueryDev& q) {
+        for (int i = threadIdx.x; i < q.n_seeds; i += NT) {
+            const int32_t v = q.seeds[i];
+            lid_of[v] = i;
+            nodes[i] = v;
+            parent_[i] = -1;
+            idom_[i] = -1;
+        }
+    }
+    __device__ int claim(int32_t v, int* counter) {
+        if (atomicCAS(&lid_of[v], -1, -2) != -1) return -1;
+        const int lid = atomicAdd(counter, 1);
+        lid_of[v] = lid;
+        return lid;
+    }
+    __device__ int lookup(int32_t v) const { return lid_of[v]; }
+    __device__ int32_t node(int lid) const { return nodes[lid]; }
+    __device__ void set_node(int lid, int32_t v) { nodes[lid] = v; }
+    __device__ int get_parent(int lid) const { return parent_[lid]; }
+    __device__ void set_parent(int lid, int p) { parent_[lid] = p; }
+    __device__ int get_idom(int lid) const { return idom_[lid]; }
+    __device__ void set_idom(int lid, int p) { idom_[lid] = p; }
+    __device__ int32_t* aux_ptr(int lid) { return &aux[lid]; }
+    __device__ int get_xu(int64_t x) const { return xu_[x]; }
+    __device__ void set_xu(int64_t x, int u) { xu_[x] = u; }
+    template <int NT>
+    __device__ void reset(int count) {
+        for (int i = threadIdx.x; i < count; i += NT) lid_of[nodes[i]] = -1;
+    }
+};
+
+// One 4-aligned group of CSR slots [4*blk, 4*blk+4) of row ulid, restricted
+// to [e0, e1): draw the block's coins and claim or record every live edge.
+template <int NT, class Store>
+__device__ __forceinline__ void scan_slot_group(const GraphDev& g, const QueryDev& q, uint32_t w, uint32_t blk,
+                                                int ulid, int32_t unode, int e0, int e1, Store& st,
+                                                WorldShared<NT>& sh) {
+    const uint4 coin = philox_block(blk, w, q.key0, q.key1);
+    const int4 cv = *reinterpret_cast<const int4*>(g.col + 4 * (size_t)blk);
+    const uint4 tv = *reinterpret_cast<const uint4*>(g.thr + 4 * (size_t)blk);
+    const int ebase = (int)(4 * blk);
+    const int32_t vv[4] = {cv.x, cv.y, cv.z, cv.w};
+    const uint32_t tt[4] = {tv.x, tv.y, tv.z, tv.w};
+    const uint32_t cc[4] = {coin.x, coin.y, coin.z, coin.w};
+#pragma unroll
+    for (int qd = 0; qd < 4; ++qd) {
+        const int e = ebase + qd;
+        if (e < e0 || e >= e1) continue;
+        const uint32_t th = tt[qd];
+        if (!(th == kAlwaysLive || cc[qd] < th)) continue;
+        const int32_t v = vv[qd];
+        if (v == unode || bit_set(q.excl, v)) continue;
+        const int lid = st.claim(v, &sh.count);
+        if (lid >= 0) {
+            st.set_node(lid, v);
+            st.set_parent(lid, ulid);
+        } else if (lid == -1) {
+            const int x = atomicAdd(&sh.n_extra, 1);
+            if (x < st.cap_x()) {
+                st.xv[x] = v;
+                st.set_xu(x, ulid);
+            } else {
+                sh.overflow = 1;
+            }
+        } else {
+            sh.overflow = 1;
+        }
+    }
+}
+
+// Returns false when the store ran out of room.  On success writes the
+// world's pairs, size, id sum and scanned-slot count.
+template <int NT, class Store>
+__device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
+                               const TileOut& out, Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    if (!st.fits(ns)) return false;  // uniform
+
+    st.template init_seeds<NT>(q);
+    if (t == 0) {
+        sh.count = ns;
+        sh.edges = q.seed_edges;
+        sh.n_extra = 0;
+        sh.overflow = 0;
+        st.lvl[0] = 0;
+        st.lvl[1] = ns;
+    }
+    __syncthreads();
+
+    // ---- level 0: the seeds' slot groups from the per-query table
+    for (int j = t; j < q.n_seed_chunks; j += NT) {
+        const int4 d = q.seed_chunk[j];  // {blk, seed lid, e0, e1}
+        scan_slot_group<NT>(g, q, w, (uint32_t)d.x, d.y, -1, d.z, d.w, st, sh);
+    }
+    __syncthreads();
+    if (sh.overflow) return false;
+    if (t == 0) st.lvl[2] = sh.count;
+    __syncthreads();
+
+    // ---- deeper levels
+    int nlev = 2;  // closed levels: lvl[0..nlev]
+    for (;;) {
+        const int f0 = st.lvl[nlev - 1];
+        const int f1 = st.lvl[nlev];
+        if (f0 == f1) break;
+        for (int base = f0; base < f1; base += NT) {
+            const int i = base + t;
+            int nb = 0, u = 0, e0 = 0, e1 = 0;
+            if (i < f1) {
+                u = st.node(i);
+                e0 = g.off[u];
+                e1 = g.off[u + 1];
+                nb = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
+            }
+            int total;
+            const int start = block_excl_scan<NT>(nb, sh.scan_tmp, total);
+            if (out.world_edges && e1 > e0) atomicAdd((unsigned long long*)&sh.edges, (unsigned long long)(e1 - e0));
+            sh.row_lid[t] = i;
+            sh.row_node[t] = u;
+            sh.row_e0[t] = e0;
+            sh.row_e1[t] = e1;
+            sh.row_start[t] = start;
+            __syncthreads();
+            const int nrows = (f1 - base < NT) ? (f1 - base) : NT;
+            for (int j = t; j < total; j += NT) {
+                int lo = 0, hi = nrows - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (sh.row_start[mid] <= j) lo = mid; else hi = mid - 1;
+                }
+                const uint32_t blk = (uint32_t)(sh.row_e0[lo] >> 2) + (uint32_t)(j - sh.row_start[lo]);
+                scan_slot_group<NT>(g, q, w, blk, sh.row_lid[lo], sh.row_node[lo], sh.row_e0[lo], sh.row_e1[lo],
+                                    st, sh);
+            }
+            __syncthreads();
+            if (sh.overflow) break;
+        }
+        if (sh.overflow) break;
+        if (nlev + 1 > st.cap_lv()) {
+            sh.overflow = 1;  // same nlev in every thread: uniform
+            break;
+        }
+        if (t == 0) st.lvl[nlev + 1] = sh.count;
+        __syncthreads();
+        ++nlev;
+    }
+    __syncthreads();
+    if (sh.overflow) return false;
+    const int nlevels = nlev - 1;  // levels 0..nlevels-1 hold nodes
+    const int R = sh.count;
+    const int nx = sh.n_extra;
+
+    // ---- dominators
+    for (int x = t; x < nx; x += NT) st.xv[x] = st.lookup(st.xv[x]);
+    for (int i = ns + t; i < R; i += NT) {
+        const int p = st.get_parent(i);
+        st.set_idom(i, p);
+        *st.aux_ptr(i) = p;
+    }
+    if (t == 0) sh.nonfwd = 0;
+    __syncthreads();
+    for (int x = t; x < nx; x += NT) {
+        const int v = st.xv[x];
+        const int u = st.get_xu(x);
+        int lo = 0, hi = nlevels - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (st.lvl[mid] <= v) lo = mid; else hi = mid - 1;
+        }
+        const bool fwd = (lo >= 1) && (u >= st.lvl[lo - 1]) && (u < st.lvl[lo]);
+        if (!fwd) sh.nonfwd = 1;
+    }
+    __syncthreads();
+    if (nx > 0) {
+        // Every sweep that changes something lowers some idom id, so the
+        // sweeps end; the cap only guards a broken invariant.
+        for (int pass = 0;; ++pass) {
+            if (pass >= kMaxDomPasses) {
+                if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagDomPasses);
+                break;
+            }
+            if (t == 0) sh.changed = 0;
+            __syncthreads();
+            for (int L = 1; L < nlevels; ++L) {
+                const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
+                for (int x = t; x < nx; x += NT) {
+                    const int v = st.xv[x];
+                    if (v < v0 || v >= v1) continue;
+                    int a = st.get_parent(v);
+                    int b = st.get_xu(x);
+                    while (a != b) {
+                        if (a > b) a = st.get_idom(a); else b = st.get_idom(b);
+                    }
+                    atomicMin(st.aux_ptr(v), a);
+                }
+                __syncthreads();
+                for (int x = t; x < nx; x += NT) {
+                    const int v = st.xv[x];
+                    if (v < v0 || v >= v1) continue;
+                    const int nv = *st.aux_ptr(v);
+                    if (nv != st.get_idom(v)) {
+                        st.set_idom(v, nv);
+                        sh.changed = 1;
+                    }
+                }
+                __syncthreads();
+            }
+            const bool again = sh.nonfwd && sh.changed;
+            __syncthreads();
+            if (!again) break;
+        }
+    }
+
+    // ---- subtree sizes of non-seeds, deepest level first
+    for (int i = ns + t; i < R; i += NT) *st.aux_ptr(i) = 1;
+    __syncthreads();
+    for (int L = nlevels - 1; L >= 1; --L) {
+        for (int i = st.lvl[L] + t; i < st.lvl[L + 1]; i += NT) {
+            const int p = st.get_idom(i);
+            if (p >= ns) atomicAdd(st.aux_ptr(p), *st.aux_ptr(i));
+        }
+        __syncthreads();
+    }
+
+    // ---- outputs
+    const int len = R - ns;
+    if (t == 0) sh.pair_base = atomicAdd(&ctl->pair_count, (unsigned long long)len);
+    __syncthreads();
+    const unsigned long long pb = sh.pair_base;
+    if (pb + (unsigned long long)len <= out.pair_cap) {
+        for (int i = t; i < len; i += NT) {
+            out.pair_node[pb + i] = st.node(ns + i);
+            out.pair_cnt[pb + i] = *st.aux_ptr(ns + i);
+        }
+    } else if (t == 0) {
+        atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
+    }
+    long long s = 0;
+    for (int i = ns + t; i < R; i += NT) s += st.node(i);
+    s = block_sum_ll<NT>(s, sh.sum_tmp);
+    if (t == 0) {
+        if (out.world_size) out.world_size[wi] = R;
+        if (out.world_sum) out.world_sum[wi] = s + q.seed_sum;
+        if (out.world_edges) out.world_edges[wi] = sh.edges;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------- kernels
+// Tier 0 (one wave, small LDS store) and tier 1 (four waves, larger LDS
+// store).  With range_count > 0 the kernel takes worlds 0..range_count-1 of
+// the tile; otherwise it takes the list handed down by the previous tier.
+using Tier0Store = LdsStore<384, 10, 128, 30>;
+using Tier1Store = LdsStore<2048, 12, 1024, 254>;
+constexpr int kTier0NT = 64;
+constexpr int kTier1NT = 256;
+constexpr int kTier2NT = 256;
+
+template <int NT, class Store, int TIER>
+__global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
+                                                  uint32_t range_count, const int32_t* in_list,
+                                                  int32_t* next_list, TileOut out) {
+    __shared__ Store st;
+    __shared__ WorldShared<NT> sh;
+    const int t = threadIdx.x;
+    st.template clear<NT>();
+    const uint32_t n_items = range_count ? range_count : ctl->list_n[TIER];
+    __syncthreads();
+    for (;;) {
+        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[TIER], 1u);
+        __syncthreads();
+        const uint32_t k = (uint32_t)sh.widx;
+        if (k >= n_items) break;
+        const uint32_t wi = range_count ? k : (uint32_t)in_list[k];
+        const bool ok = evaluate_world<NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
+        if (!ok && t == 0) {
+            const uint32_t pos = atomicAdd(&ctl->list_n[TIER + 1], 1u);
+            next_list[pos] = (int32_t)wi;
+        }
+        st.template reset<NT>(0);
+        __syncthreads();
+    }
+}
+
+// Tier 2: per-world arrays in HBM, one slot per resident workgroup.
+__global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
+                                                        uint32_t range_count, const int32_t* in_list,
+                                                        TileOut out, BigSlots bs) {
+    __shared__ WorldShared<kTier2NT> sh;
+    const int t = threadIdx.x;
+    const size_t slot = blockIdx.x;
+    const size_t n = (size_t)g.n;
+    HbmStore st;
+    st.lid_of = bs.lid_of + slot * n;
+    st.nodes = bs.nodes + slot * n;
+    st.parent_ = bs.parent + slot * n;
+    st.idom_ = bs.idom + slot * n;
+    st.aux = bs.aux + slot * n;
+    st.lvl = bs.lvl + slot * (n + 3);
+    st.xv = bs.xv + slot * (size_t)bs.xcap;
+    st.xu_ = bs.xu + slot * (size_t)bs.xcap;
+    st.cap_lv_ = g.n + 1;
+    st.cap_x_ = bs.xcap;
+    const uint32_t n_items = range_count ? range_count : ctl->list_n[2];
+    for (;;) {
+        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[2], 1u);
+        __syncthreads();
+        const uint32_t k = (uint32_t)sh.widx;
+        if (k >= n_items) break;
+        const uint32_t wi = range_count ? k : (uint32_t)in_list[k];
+        const bool ok = evaluate_world<kTier2NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
+        if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
+        __syncthreads();
+        st.reset<kTier2NT>(sh.count < g.n ? sh.count : g.n);
+        __syncthreads();
+    }
+}
+
+int world_tier_blocks_per_cu(int tier) {
+    size_t lds = 0;
+    if (tier == 0) lds = sizeof(Tier0Store) + sizeof(WorldShared<kTier0NT>);
+    else if (tier == 1) lds = sizeof(Tier1Store) + sizeof(WorldShared<kTier1NT>);
+    else return 2;
+    int b = (int)((160 * 1024) / lds);
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
+                             uint32_t range_count, const int32_t* in_list, int32_t* next_list,
+                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s) {
+    if (tier == 0) {
+        k_world_lds<kTier0NT, Tier0Store, 0><<<grid, kTier0NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
+                                                                       next_list, out);
+    } else if (tier == 1) {
+        k_world_lds<kTier1NT, Tier1Store, 1><<<grid, kTier1NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
+                                                                       next_list, out);
+    } else {
+        k_world_hbm<<<bs.n_slots, kTier2NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list, out, bs);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- level-0 slot table
+// For seed i with row [e0, e1): nb_i = number of 4-aligned slot groups.
+__global__ void k_seed_count(GraphDev g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl) {
+    long long sum = 0, edges = 0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+        const int32_t v = seeds[i];
+        int nb = 0;
+        if (v >= 0 && v < g.n) {
+            const int e0 = g.off[v], e1 = g.off[v + 1];
+            nb = (e1 > e0) ? (((e1 - 1) >> 2) - (e0 >> 2) + 1) : 0;
+            sum += v;
+            edges += e1 - e0;
+        }
+        cnt[i] = nb;
+    }
+    if (sum) atomicAdd((unsigned long long*)&ctl->seed_sum, (unsigned long long)sum);
+    if (edges) atomicAdd((unsigned long long*)&ctl->seed_edges, (unsigned long long)edges);
+}
+
+// Single workgroup: exclusive scan of cnt[0..ns) in place, total to ctl.
+__global__ __launch_bounds__(1024) void k_seed_scan(int32_t* cnt, int32_t ns, RoundCtl* ctl) {
+    __shared__ int tmp[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < ns; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = (i < ns) ? cnt[i] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024>(v, tmp, tot);
+        if (i < ns) cnt[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->seed_chunks = carry;
+}
+
+__global__ void k_seed_fill(GraphDev g, const int32_t* seeds, int32_t ns, const int32_t* start, int4* table) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+        const int32_t v = seeds[i];
+        const int e0 = g.off[v], e1 = g.off[v + 1];
+        if (e1 <= e0) continue;
+        const int b0 = e0 >> 2, b1 = (e1 - 1) >> 2;
+        for (int b = b0; b <= b1; ++b) table[start[i] + (b - b0)] = make_int4(b, i, e0, e1);
+    }
+}
+
+hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
+                             hipStream_t s) {
+    k_seed_count<<<(ns + 255) / 256, 256, 0, s>>>(g, seeds, ns, cnt, ctl);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_seed_scan<<<1, 1024, 0, s>>>(cnt, ns, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
+                            int4* table, hipStream_t s) {
+    k_seed_fill<<<(ns + 255) / 256, 256, 0, s>>>(g, seeds, ns, start, table);
+    return hipGetLastError();
+}
+
+}  // namespace imin

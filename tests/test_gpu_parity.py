@@ -100,15 +100,27 @@ def test_tiles_and_pair_overflow(B, oracle_mod, monkeypatch):
     _assert_same(got, want)
 
 
-@pytest.mark.parametrize("shape", ["path", "star", "grid"])
+@pytest.mark.parametrize("tier", ["0", "1", "2"])
+def test_every_start_tier_gives_the_same_integers(B, oracle_mod, monkeypatch, tier):
+    """Worlds first tried on the LDS tiers or directly on the HBM tier."""
+    monkeypatch.setenv("IMIN_START_TIER", tier)
+    g, seeds, _, _ = synth.workload("small")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 0, 2000, 3)
+    _assert_same(got, want)
+    g2 = synth.random_small_graph(200, 900, seed=12, prob="mixed", allow_multi=True)
+    got, want = _eval_both(B, oracle_mod, g2, np.array([1, 7, 9], np.int32), 0, 500, 4, blocked=[3, 4])
+    _assert_same(got, want)
+
+
+@pytest.mark.parametrize("shape", ["path", "star", "grid", "star1000", "path100"])
 def test_evaluate_deterministic_shapes(B, oracle_mod, shape):
-    """p = 1 shapes that overflow the LDS path: 1500-level path, 3000-leaf
-    star, 50x50 grid (many equal-level predecessors)."""
-    if shape == "path":
-        n = 1500
+    """p = 1 shapes that outgrow the LDS tiers: 1500- and 100-level paths,
+    3000- and 1000-leaf stars, a 50x50 grid (many equal-level predecessors)."""
+    if shape in ("path", "path100"):
+        n = 1500 if shape == "path" else 100
         src, dst = np.arange(n - 1), np.arange(1, n)
-    elif shape == "star":
-        n = 3001
+    elif shape in ("star", "star1000"):
+        n = 3001 if shape == "star" else 1001
         src, dst = np.zeros(n - 1, int), np.arange(1, n)
     else:
         s = 50
