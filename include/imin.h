@@ -149,6 +149,7 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  *   2  gain reduction (bucket histogram, scan, scatter, accumulate, sum)
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
+ *   5  search for the worlds a new blocker changes (incremental rounds)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */

@@ -22,7 +22,7 @@ namespace {
 thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
-constexpr int kTimedKernels = 5;
+constexpr int kTimedKernels = 6;
 struct Timing {
     std::atomic<bool> on{false};
     std::mutex mu;
@@ -138,7 +138,11 @@ struct Session {
     HostCtl hctl;
     // tile outputs
     DevArray<int32_t> world_size;
-    DevArray<int32_t> list1, list2;  // worlds handed down to tier 1 / tier 2
+    DevArray<int32_t> list0, list1, list2;  // affected worlds; worlds handed down to tier 1 / 2
+    // resident per-world (node, count) lists for incremental rounds
+    DevArray<int32_t> store_node, store_cnt, store_len;
+    DevArray<int64_t> store_off;
+    bool incremental = false;
     // level-0 slot groups of the seeds
     DevArray<int32_t> seed_cnt;
     DevArray<int4> seed_table;
@@ -177,6 +181,7 @@ struct Session {
         IMIN_TRY(world_size.alloc(tile_cap));
         IMIN_TRY(list1.alloc(tile_cap));
         IMIN_TRY(list2.alloc(tile_cap));
+        IMIN_TRY(list0.alloc(1));
 
         // pair buffer: enough for the whole tile if worlds are small
         const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
@@ -262,31 +267,91 @@ struct Session {
     // Evaluate worlds [w_begin, w_begin+count) under the current excl bitmap;
     // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
     // outputs are written at [0, count).
+    // Resident store for incremental rounds: per-world offsets and lengths
+    // for all theta worlds plus room for every world's list.
+    imin_status_t enable_store(uint64_t theta) {
+        const size_t cap = env_size("IMIN_STORE_CAP", (size_t)1 << 30);
+        if (cap < 1 || theta > (1ull << 32)) return IMIN_OK;
+        if (store_node.alloc(cap) != hipSuccess || store_cnt.alloc(cap) != hipSuccess ||
+            store_off.alloc(theta) != hipSuccess || store_len.alloc(theta) != hipSuccess ||
+            list0.alloc(theta) != hipSuccess) {
+            // not enough memory for the store: plain rounds give the same integers
+            store_node.release();
+            store_cnt.release();
+            store_off.release();
+            store_len.release();
+            (void)hipGetLastError();
+            return IMIN_OK;
+        }
+        incremental = true;
+        return IMIN_OK;
+    }
+
+    imin::TileOut tile_out() const {
+        imin::TileOut out{};
+        out.mode = imin::kModePlain;
+        out.pair_node = pair_node.p;
+        out.pair_cnt = pair_cnt.p;
+        out.pair_cap = pair_node.count;
+        out.store_node = store_node.p;
+        out.store_cnt = store_cnt.p;
+        out.store_cap = store_node.count;
+        out.store_off = store_off.p;
+        out.store_len = store_len.p;
+        return out;
+    }
+
+    imin_status_t launch_tiers(const imin::QueryDev& q, uint32_t wb, uint32_t range, const int32_t* first_list,
+                               const imin::TileOut& out) {
+        for (int tier = start_tier; tier < 3; ++tier) {
+            const bool first = (tier == start_tier);
+            const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : list2.p);
+            const int count_idx = first ? 0 : tier;
+            int32_t* next_list = tier == 0 ? list1.p : list2.p;
+            const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
+            hipEvent_t ev = timed.begin(s);
+            IMIN_TRY(imin::launch_world_tier(tier, g, q, ctl.p, wb, first_list ? 0u : range, in_list, count_idx,
+                                             next_list, out, bs, tier == 0 ? grid0 : grid1, s));
+            timed.end(timer_id, ev, s);
+        }
+        return IMIN_OK;
+    }
+
+    // One incremental round: worlds holding the last blocker are re-evaluated
+    // and report their count changes; gain is updated in place.
+    imin_status_t evaluate_delta(const imin::QueryDev& q, uint64_t theta) {
+        imin::TileOut out = tile_out();
+        out.mode = imin::kModeDelta;
+        out.world_size = world_size.p;
+        IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+        hipEvent_t ev = timed.begin(s);
+        IMIN_TRY(imin::launch_affected(out, (uint32_t)theta, ctl.p, list0.p, s));
+        timed.end(5, ev, s);
+        imin_status_t st = launch_tiers(q, 0, 0, list0.p, out);
+        if (st != IMIN_OK) return st;
+        ev = timed.begin(s);
+        IMIN_TRY(imin::launch_reduce_pairs(g, out, rb, ctl.p, gain.p, s));
+        timed.end(2, ev, s);
+        IMIN_TRY(imin::launch_sum_sizes(world_size.p, (uint32_t)theta, ctl.p, s));
+        return IMIN_OK;
+    }
+
     imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
-                           int64_t* wsum_out, int64_t* wedges_out) {
+                           int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false) {
         uint64_t done = 0;
+        unsigned long long store_base = 0;
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
-            imin::TileOut out{};
-            out.pair_node = pair_node.p;
-            out.pair_cnt = pair_cnt.p;
-            out.pair_cap = pair_node.count;
+            const bool use_store = store_mode && incremental;
+            imin::TileOut out = tile_out();
+            out.mode = use_store ? imin::kModeStore : imin::kModePlain;
             out.world_size = ws_out ? ws_out + done : world_size.p;
             out.world_sum = wsum_out ? wsum_out + done : nullptr;
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            const uint32_t wb = (uint32_t)(w_begin + done);
-            for (int tier = start_tier; tier < 3; ++tier) {
-                const uint32_t range = (tier == start_tier) ? (uint32_t)nw : 0u;
-                const int32_t* in_list = tier == 1 ? list1.p : (tier == 2 ? list2.p : nullptr);
-                int32_t* next_list = tier == 0 ? list1.p : list2.p;
-                const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
-                hipEvent_t ev = timed.begin(s);
-                IMIN_TRY(imin::launch_world_tier(tier, g, q, ctl.p, wb, range, in_list, next_list, out, bs,
-                                                 tier == 0 ? grid0 : grid1, s));
-                timed.end(timer_id, ev, s);
-            }
-            imin_status_t st = read_ctl();
+            imin_status_t st = launch_tiers(q, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, out);
+            if (st != IMIN_OK) return st;
+            st = read_ctl();
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
             // route later tiles straight to the tier most worlds end up in
@@ -295,6 +360,13 @@ struct Session {
             if (f & (imin::kFlagBigCapacity | imin::kFlagDomPasses)) {
                 g_last_flags = f;
                 return IMIN_ERR_INTERNAL;
+            }
+            if (f & imin::kFlagStoreOverflow) {
+                // the resident store is full: finish with plain rounds
+                st = clear_flag(imin::kFlagStoreOverflow);
+                if (st != IMIN_OK) return st;
+                incremental = false;
+                continue;  // redo this tile without the store
             }
             if (f & imin::kFlagPairOverflow) {
                 st = clear_flag(imin::kFlagPairOverflow);
@@ -316,8 +388,16 @@ struct Session {
                 }
                 continue;  // redo this tile
             }
+            imin::TileOut red = out;
+            if (use_store) {
+                // this tile's pairs sit contiguously in the store
+                red.pair_node = store_node.p + store_base;
+                red.pair_cnt = store_cnt.p + store_base;
+                red.pair_cap = store_node.count - store_base;
+                store_base = hctl.p->store_count;
+            }
             hipEvent_t ev = timed.begin(s);
-            IMIN_TRY(imin::launch_reduce_pairs(g, out, rb, ctl.p, gain.p, s));
+            IMIN_TRY(imin::launch_reduce_pairs(g, red, rb, ctl.p, gain.p, s));
             timed.end(2, ev, s);
             IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
             done += nw;
@@ -446,10 +526,27 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
     imin::QueryDev q{};
     st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
     if (st != IMIN_OK) return st;
+    // worlds are resident: per-world sizes for all theta, and the per-world
+    // count lists when they fit (incremental rounds)
+    IMIN_TRY(ss.world_size.alloc((size_t)theta));
+    const char* inc_env = std::getenv("IMIN_INCREMENTAL");
+    if (!(inc_env && inc_env[0] == '0')) {
+        st = ss.enable_store((uint64_t)theta);
+        if (st != IMIN_OK) return st;
+    }
     for (int32_t r = 0; r <= k; ++r) {
-        IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
         IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
-        st = ss.evaluate(q, 0, (uint64_t)theta, nullptr, nullptr, nullptr);
+        if (r > 0 && ss.incremental) {
+            if (ss.pair_node.count < ss.hctl.p->store_count) {
+                // a round's changes never exceed the stored pairs
+                st = ss.grow_pairs(ss.hctl.p->store_count);
+                if (st != IMIN_OK) return st;
+            }
+            st = ss.evaluate_delta(q, (uint64_t)theta);
+        } else {
+            IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+            st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, r == 0);
+        }
         if (st != IMIN_OK) return st;
         hipEvent_t ev = ss.timed.begin(s);
         IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_parts, k,

@@ -23,7 +23,8 @@ enum : uint32_t {
     kFlagPairOverflow = 1u << 8,   // pair buffer too small for the tile: redo
     kFlagBigCapacity = 1u << 9,    // big-world scratch too small
     kFlagSpreadMismatch = 1u << 10, // T_{r+1} != T_r - gain_r
-    kFlagDomPasses = 1u << 11       // dominator passes did not settle
+    kFlagDomPasses = 1u << 11,      // dominator passes did not settle
+    kFlagStoreOverflow = 1u << 12   // resident per-world store too small
 };
 
 // Graph as kept by a handle.  col/thr are padded with 4..7 trailing entries
@@ -53,6 +54,15 @@ struct RoundCtl {
     long long seed_edges;    // CSR slots leaving the seeds
     int32_t seed_chunks;     // entries of the level-0 slot-group table
     int32_t pad1;
+    unsigned long long store_count;  // pairs held by the resident per-world store
+};
+
+// How a world evaluation reports its counts.
+enum : int {
+    kModePlain = 0,  // (node, c) pairs of the world into the tile pair buffer
+    kModeStore = 1,  // pairs into the resident store, which the reduction reads
+    kModeDelta = 2   // re-evaluation: (node, c_new - c_old) for every change
+                     // against the stored list, then the list is replaced
 };
 
 // Scratch of the workgroup-per-world path, one slot per resident workgroup.
@@ -71,9 +81,16 @@ struct BigSlots {
 
 // Everything a tile of world evaluations writes.
 struct TileOut {
+    int mode;
     int32_t* pair_node;  // [pair_cap]
     int32_t* pair_cnt;   // [pair_cap]
     unsigned long long pair_cap;
+    // resident per-world store (solve only), indexed by world id
+    int32_t* store_node;
+    int32_t* store_cnt;
+    unsigned long long store_cap;
+    int64_t* store_off;  // [theta]
+    int32_t* store_len;  // [theta]
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
@@ -115,8 +132,9 @@ hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                             uint32_t range_count, const int32_t* in_list, int32_t* next_list,
+                             uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
+hipError_t launch_affected(const TileOut& out, uint32_t theta, RoundCtl* ctl, int32_t* list, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,

@@ -108,10 +108,14 @@ struct LdsStore {
         }
         return -2;
     }
+    // Local id of v, or -1 when v was not reached (nothing is ever removed
+    // from the table within a world, so an empty slot ends the probe).
     __device__ int lookup(int32_t v) const {
         uint32_t h = hash(v);
         for (int probe = 0; probe < kHash; ++probe) {
-            if (keys[h] == v) return (int)vals[h] + ns;
+            const int32_t k = keys[h];
+            if (k == v) return (int)vals[h] + ns;
+            if (k == -1) return -1;
             h = (h + 1) & (kHash - 1);
         }
         return -1;
@@ -374,16 +378,66 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
 
     // ---- outputs
     const int len = R - ns;
-    if (t == 0) sh.pair_base = atomicAdd(&ctl->pair_count, (unsigned long long)len);
-    __syncthreads();
-    const unsigned long long pb = sh.pair_base;
-    if (pb + (unsigned long long)len <= out.pair_cap) {
-        for (int i = t; i < len; i += NT) {
-            out.pair_node[pb + i] = st.node(ns + i);
-            out.pair_cnt[pb + i] = *st.aux_ptr(ns + i);
+    if (out.mode == kModeDelta) {
+        // Blocking only removes nodes, so every reached node is in the stored
+        // list: walking the old list finds every count that changed.
+        const size_t so = (size_t)out.store_off[w];
+        const int old_len = out.store_len[w];
+        const int lane = t & 63;
+        for (int base = 0; base < old_len; base += NT) {
+            const int i = base + t;
+            int32_t u = 0;
+            int d = 0;
+            if (i < old_len) {
+                u = out.store_node[so + i];
+                const int lid = st.lookup(u);
+                const int c_new = (lid >= ns) ? *st.aux_ptr(lid) : 0;
+                d = c_new - out.store_cnt[so + i];
+            }
+            const unsigned long long mask = __ballot(d != 0);
+            const int cnt = __popcll(mask);
+            unsigned long long wbase = 0;
+            if (lane == 0 && cnt) wbase = atomicAdd(&ctl->pair_count, (unsigned long long)cnt);
+            wbase = __shfl(wbase, 0, 64);
+            if (d != 0) {
+                const unsigned long long pos = wbase + __popcll(mask & ((1ull << lane) - 1ull));
+                if (pos < out.pair_cap) {
+                    out.pair_node[pos] = u;
+                    out.pair_cnt[pos] = d;
+                } else {
+                    atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
+                }
+            }
         }
-    } else if (t == 0) {
-        atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
+        __syncthreads();  // the old list is fully read before it is replaced
+        for (int i = t; i < len; i += NT) {
+            out.store_node[so + i] = st.node(ns + i);
+            out.store_cnt[so + i] = *st.aux_ptr(ns + i);
+        }
+        if (t == 0) out.store_len[w] = len;
+    } else {
+        const bool store = (out.mode == kModeStore);
+        if (t == 0) {
+            sh.pair_base = atomicAdd(store ? &ctl->store_count : &ctl->pair_count, (unsigned long long)len);
+            if (store) atomicAdd(&ctl->pair_count, (unsigned long long)len);
+        }
+        __syncthreads();
+        const unsigned long long pb = sh.pair_base;
+        int32_t* dn = store ? out.store_node : out.pair_node;
+        int32_t* dc = store ? out.store_cnt : out.pair_cnt;
+        const unsigned long long cap = store ? out.store_cap : out.pair_cap;
+        if (pb + (unsigned long long)len <= cap) {
+            for (int i = t; i < len; i += NT) {
+                dn[pb + i] = st.node(ns + i);
+                dc[pb + i] = *st.aux_ptr(ns + i);
+            }
+            if (store && t == 0) {
+                out.store_off[w] = (int64_t)pb;
+                out.store_len[w] = len;
+            }
+        } else if (t == 0) {
+            atomicOr(&ctl->flags, (uint32_t)(store ? kFlagStoreOverflow : kFlagPairOverflow));
+        }
     }
     long long s = 0;
     for (int i = ns + t; i < R; i += NT) s += st.node(i);
@@ -408,20 +462,20 @@ constexpr int kTier2NT = 256;
 
 template <int NT, class Store, int TIER>
 __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
-                                                  uint32_t range_count, const int32_t* in_list,
+                                                  uint32_t range_count, const int32_t* in_list, int count_idx,
                                                   int32_t* next_list, TileOut out) {
     __shared__ Store st;
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
     st.template clear<NT>();
-    const uint32_t n_items = range_count ? range_count : ctl->list_n[TIER];
+    const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
     __syncthreads();
     for (;;) {
         if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[TIER], 1u);
         __syncthreads();
         const uint32_t k = (uint32_t)sh.widx;
         if (k >= n_items) break;
-        const uint32_t wi = range_count ? k : (uint32_t)in_list[k];
+        const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) {
             const uint32_t pos = atomicAdd(&ctl->list_n[TIER + 1], 1u);
@@ -435,7 +489,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
 // Tier 2: per-world arrays in HBM, one slot per resident workgroup.
 __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
                                                         uint32_t range_count, const int32_t* in_list,
-                                                        TileOut out, BigSlots bs) {
+                                                        int count_idx, TileOut out, BigSlots bs) {
     __shared__ WorldShared<kTier2NT> sh;
     const int t = threadIdx.x;
     const size_t slot = blockIdx.x;
@@ -451,13 +505,13 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     st.xu_ = bs.xu + slot * (size_t)bs.xcap;
     st.cap_lv_ = g.n + 1;
     st.cap_x_ = bs.xcap;
-    const uint32_t n_items = range_count ? range_count : ctl->list_n[2];
+    const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
     for (;;) {
         if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[2], 1u);
         __syncthreads();
         const uint32_t k = (uint32_t)sh.widx;
         if (k >= n_items) break;
-        const uint32_t wi = range_count ? k : (uint32_t)in_list[k];
+        const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<kTier2NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
         __syncthreads();
@@ -476,17 +530,42 @@ int world_tier_blocks_per_cu(int tier) {
 }
 
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
-                             uint32_t range_count, const int32_t* in_list, int32_t* next_list,
+                             uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s) {
     if (tier == 0) {
         k_world_lds<kTier0NT, Tier0Store, 0><<<grid, kTier0NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
-                                                                       next_list, out);
+                                                                       count_idx, next_list, out);
     } else if (tier == 1) {
         k_world_lds<kTier1NT, Tier1Store, 1><<<grid, kTier1NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
-                                                                       next_list, out);
+                                                                       count_idx, next_list, out);
     } else {
-        k_world_hbm<<<bs.n_slots, kTier2NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list, out, bs);
+        k_world_hbm<<<bs.n_slots, kTier2NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list, count_idx, out, bs);
     }
+    return hipGetLastError();
+}
+
+// Worlds whose stored list holds the last selected blocker: blocking it
+// changes them; every other world keeps its reached set and dominator tree.
+// One wave per world; the list goes to list_n[0].
+__global__ __launch_bounds__(256) void k_affected(TileOut out, uint32_t theta, RoundCtl* ctl, int32_t* list) {
+    if (ctl->stop) return;
+    const int32_t u = ctl->ustar;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+    for (uint32_t w = wave; w < theta; w += nwaves) {
+        const size_t so = (size_t)out.store_off[w];
+        const int len = out.store_len[w];
+        bool hit = false;
+        for (int i = lane; i < len; i += 64) hit |= (out.store_node[so + i] == u);
+        if (__ballot(hit) && lane == 0) list[atomicAdd(&ctl->list_n[0], 1u)] = (int32_t)w;
+    }
+}
+
+hipError_t launch_affected(const TileOut& out, uint32_t theta, RoundCtl* ctl, int32_t* list, hipStream_t s) {
+    unsigned blocks = (theta + 3) / 4;
+    if (blocks > 8192) blocks = 8192;
+    k_affected<<<blocks, 256, 0, s>>>(out, theta, ctl, list);
     return hipGetLastError();
 }
 

@@ -152,6 +152,27 @@ def test_solve_random_graphs(B, oracle_mod, case):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+@pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2"])
+def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
+    """Incremental rounds (default), plain rounds, a resident store too small
+    to hold round 0 (falls back to plain rounds) and re-evaluation of changed
+    worlds on the larger tiers all give the oracle's selection."""
+    if variant == "plain":
+        monkeypatch.setenv("IMIN_INCREMENTAL", "0")
+    elif variant == "store_overflow":
+        monkeypatch.setenv("IMIN_STORE_CAP", "5000")
+    else:
+        monkeypatch.setenv("IMIN_START_TIER", variant[-1])
+    g = synth.random_small_graph(300, 1500, seed=77, prob="wc")
+    seeds = np.array([3, 30, 111], np.int32)
+    _log(f"solve variant {variant}")
+    res = B.solve(B.Graph.from_synth(g), seeds, 15, 700, 5)
+    want = oracle_mod.Query(g, seeds).solve(15, 700, 5)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 def test_solve_small_workload(B, oracle_mod):
     g, seeds, k, theta = synth.workload("small")
     _log("solve small workload")
