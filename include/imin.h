@@ -157,6 +157,17 @@ imin_status_t imin_timing_enable(int on);
 imin_status_t imin_timing_reset(void);
 imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_ms);
 
+/*
+ * Work done while timing was enabled, per world tier (0 small LDS, 1 large
+ * LDS, 2 HBM): worlds finished, CSR slots of their reached rows (the edges
+ * whose coins were needed), and algorithmic HBM bytes = 8 per such slot
+ * (column and threshold) + 8 per reached non-seed (row offsets) + 16 per
+ * level-0 table entry + 8 per (node, count) entry written, plus, in
+ * incremental rounds, 8 per stored entry read back and per change reported.
+ * Host pointers; any may be NULL.
+ */
+imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes);
+
 /* Static description of a status code. */
 const char* imin_status_string(imin_status_t s);
 

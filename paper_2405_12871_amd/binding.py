@@ -69,6 +69,8 @@ def load():
     lib.imin_timing_reset.restype = st
     lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     lib.imin_timing_read.restype = st
+    lib.imin_timing_work.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.imin_timing_work.restype = st
     _lib = lib
     return lib
 
@@ -235,3 +237,10 @@ def timing_read(kernel_id: int):
     ms = ctypes.c_double()
     _check(load().imin_timing_read(int(kernel_id), ctypes.byref(n), ctypes.byref(ms)))
     return int(n.value), float(ms.value)
+
+
+def timing_work(tier: int):
+    """(worlds, CSR slots scanned, algorithmic bytes) of one world tier since the last reset."""
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().imin_timing_work(int(tier), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)

@@ -28,8 +28,34 @@ struct Timing {
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
     double ms[kTimedKernels] = {};
+    int64_t work_worlds[3] = {};
+    int64_t work_edges[3] = {};
+    int64_t work_bytes[3] = {};
 };
 Timing g_timing;
+
+// Events are created once and reused across calls.
+std::mutex g_event_mu;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t event_acquire() {
+    {
+        std::lock_guard<std::mutex> lk(g_event_mu);
+        if (!g_event_pool.empty()) {
+            hipEvent_t e = g_event_pool.back();
+            g_event_pool.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+void event_release(hipEvent_t e) {
+    if (!e) return;
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    g_event_pool.push_back(e);
+}
 
 // Event pairs recorded by one call, resolved after its final synchronisation.
 struct TimedLaunches {
@@ -41,16 +67,15 @@ struct TimedLaunches {
     bool on = g_timing.on.load();
     hipEvent_t begin(hipStream_t s) {
         if (!on) return nullptr;
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) return nullptr;
-        (void)hipEventRecord(e, s);
+        hipEvent_t e = event_acquire();
+        if (e) (void)hipEventRecord(e, s);
         return e;
     }
     void end(int id, hipEvent_t a, hipStream_t s) {
         if (!on || !a) return;
-        hipEvent_t e = nullptr;
-        if (hipEventCreate(&e) != hipSuccess) {
-            (void)hipEventDestroy(a);
+        hipEvent_t e = event_acquire();
+        if (!e) {
+            event_release(a);
             return;
         }
         (void)hipEventRecord(e, s);
@@ -65,8 +90,8 @@ struct TimedLaunches {
                 g_timing.launches[r.id] += 1;
                 g_timing.ms[r.id] += ms;
             }
-            (void)hipEventDestroy(r.a);
-            (void)hipEventDestroy(r.b);
+            event_release(r.a);
+            event_release(r.b);
         }
         recs.clear();
     }
@@ -143,6 +168,9 @@ struct Session {
     DevArray<int32_t> store_node, store_cnt, store_len;
     DevArray<int64_t> store_off;
     bool incremental = false;
+    // node -> stored entries (position, world), built after round 0
+    DevArray<int32_t> idx_off, idx_bsum, idx_cursor, idx_pos, idx_world;
+    imin::ReduceBufs rb_delta{};
     // level-0 slot groups of the seeds
     DevArray<int32_t> seed_cnt;
     DevArray<int4> seed_table;
@@ -201,6 +229,11 @@ struct Session {
         rb.sorted_node = sorted_node.p;
         rb.sorted_cnt = sorted_cnt.p;
         rb.part = part.p;
+        // incremental rounds report few changes: fewer histogram chunks and
+        // one workgroup per bucket adding straight into gain
+        rb_delta = rb;
+        rb_delta.g1 = 128;
+        rb_delta.slices = 1;
         (void)need_gain_buffers;
 
         // big-world slots: per slot 6 node arrays (+lvl) and 2 edge arrays
@@ -241,6 +274,19 @@ struct Session {
         return IMIN_OK;
     }
 
+    // Resolve this call's kernel timings and add its work tallies (after the
+    // call's final synchronisation).
+    void finish() {
+        if (!timed.on) return;
+        timed.flush();
+        std::lock_guard<std::mutex> lk(g_timing.mu);
+        for (int i = 0; i < 3; ++i) {
+            g_timing.work_worlds[i] += (int64_t)hctl.p->work_worlds[i];
+            g_timing.work_edges[i] += (int64_t)hctl.p->work_edges[i];
+            g_timing.work_bytes[i] += (int64_t)hctl.p->work_bytes[i];
+        }
+    }
+
     imin_status_t read_ctl() {
         IMIN_TRY(hipMemcpyAsync(hctl.p, ctl.p, sizeof(imin::RoundCtl), hipMemcpyDeviceToHost, s));
         IMIN_TRY(hipStreamSynchronize(s));
@@ -261,6 +307,26 @@ struct Session {
         IMIN_TRY(sorted_cnt.alloc(want));
         rb.sorted_node = sorted_node.p;
         rb.sorted_cnt = sorted_cnt.p;
+        rb_delta.sorted_node = sorted_node.p;
+        rb_delta.sorted_cnt = sorted_cnt.p;
+        return IMIN_OK;
+    }
+
+    // node -> (store position, world) of every entry written in round 0
+    imin_status_t build_index(uint64_t theta) {
+        const unsigned long long entries = hctl.p->store_count;
+        const size_t n = (size_t)g.n;
+        IMIN_TRY(idx_off.alloc(n + 1));
+        IMIN_TRY(idx_bsum.alloc((n + 4095) / 4096 + 1));
+        IMIN_TRY(idx_cursor.alloc(n + 1));
+        IMIN_TRY(idx_pos.alloc(entries));
+        IMIN_TRY(idx_world.alloc(entries));
+        IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
+        imin::TileOut out = tile_out();
+        IMIN_TRY(imin::launch_index_count(out, entries, idx_off.p, s));
+        IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
+        IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_pos.p, idx_world.p, s));
         return IMIN_OK;
     }
 
@@ -325,12 +391,12 @@ struct Session {
         out.world_size = world_size.p;
         IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
         hipEvent_t ev = timed.begin(s);
-        IMIN_TRY(imin::launch_affected(out, (uint32_t)theta, ctl.p, list0.p, s));
+        IMIN_TRY(imin::launch_affected(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, s));
         timed.end(5, ev, s);
         imin_status_t st = launch_tiers(q, 0, 0, list0.p, out);
         if (st != IMIN_OK) return st;
         ev = timed.begin(s);
-        IMIN_TRY(imin::launch_reduce_pairs(g, out, rb, ctl.p, gain.p, s));
+        IMIN_TRY(imin::launch_reduce_pairs(g, out, rb_delta, ctl.p, gain.p, s));
         timed.end(2, ev, s);
         IMIN_TRY(imin::launch_sum_sizes(world_size.p, (uint32_t)theta, ctl.p, s));
         return IMIN_OK;
@@ -534,24 +600,44 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
         st = ss.enable_store((uint64_t)theta);
         if (st != IMIN_OK) return st;
     }
-    for (int32_t r = 0; r <= k; ++r) {
-        IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    const size_t batch = env_size("IMIN_ROUND_BATCH", 32);
+    bool indexed = false;
+    for (int32_t r = 0; r <= k;) {
         if (r > 0 && ss.incremental) {
-            if (ss.pair_node.count < ss.hctl.p->store_count) {
-                // a round's changes never exceed the stored pairs
-                st = ss.grow_pairs(ss.hctl.p->store_count);
+            if (!indexed) {
+                st = ss.build_index((uint64_t)theta);
                 if (st != IMIN_OK) return st;
+                if (ss.pair_node.count < ss.hctl.p->store_count) {
+                    // a round's changes never outnumber the stored entries
+                    st = ss.grow_pairs(ss.hctl.p->store_count);
+                    if (st != IMIN_OK) return st;
+                }
+                indexed = true;
             }
-            st = ss.evaluate_delta(q, (uint64_t)theta);
+            // incremental rounds need no host decision: enqueue a batch; once
+            // the selection stops, every later kernel returns at once
+            const int32_t nb = (int32_t)std::min<size_t>(batch, (size_t)(k + 1 - r));
+            for (int32_t i = 0; i < nb; ++i) {
+                IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+                st = ss.evaluate_delta(q, (uint64_t)theta);
+                if (st != IMIN_OK) return st;
+                hipEvent_t ev = ss.timed.begin(s);
+                IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p,
+                                             ss.sel_parts, k, blockers, gains, spread_totals, n_selected, s));
+                ss.timed.end(3, ev, s);
+            }
+            r += nb;
         } else {
+            IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
             IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
             st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, r == 0);
+            if (st != IMIN_OK) return st;
+            hipEvent_t ev = ss.timed.begin(s);
+            IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_parts,
+                                         k, blockers, gains, spread_totals, n_selected, s));
+            ss.timed.end(3, ev, s);
+            ++r;
         }
-        if (st != IMIN_OK) return st;
-        hipEvent_t ev = ss.timed.begin(s);
-        IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_parts, k,
-                                     blockers, gains, spread_totals, n_selected, s));
-        ss.timed.end(3, ev, s);
         st = ss.read_ctl();
         if (st != IMIN_OK) return st;
         if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
@@ -560,6 +646,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
         }
         if (ss.hctl.p->stop) break;
     }
+    ss.finish();
     return IMIN_OK;
 }
 
@@ -584,7 +671,9 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     if (st != IMIN_OK) return st;
     IMIN_TRY(hipMemcpyAsync(gain, ss.gain.p, (size_t)g->g.n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     IMIN_TRY(hipMemcpyAsync(total, &ss.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
-    IMIN_TRY(hipStreamSynchronize(s));
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    ss.finish();
     return IMIN_OK;
 }
 
@@ -599,6 +688,16 @@ imin_status_t imin_timing_reset(void) {
         g_timing.launches[i] = 0;
         g_timing.ms[i] = 0.0;
     }
+    for (int i = 0; i < 3; ++i) g_timing.work_worlds[i] = g_timing.work_edges[i] = g_timing.work_bytes[i] = 0;
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes) {
+    if (tier < 0 || tier > 2) return IMIN_ERR_INVALID;
+    std::lock_guard<std::mutex> lk(g_timing.mu);
+    if (worlds) *worlds = g_timing.work_worlds[tier];
+    if (edges) *edges = g_timing.work_edges[tier];
+    if (bytes) *bytes = g_timing.work_bytes[tier];
     return IMIN_OK;
 }
 

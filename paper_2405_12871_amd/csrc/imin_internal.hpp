@@ -55,6 +55,12 @@ struct RoundCtl {
     int32_t seed_chunks;     // entries of the level-0 slot-group table
     int32_t pad1;
     unsigned long long store_count;  // pairs held by the resident per-world store
+    // work done per world tier: worlds finished, CSR slots of their reached
+    // rows, and algorithmic HBM bytes (slot columns and thresholds, row
+    // offsets, level-0 table entries, count lists read and written)
+    unsigned long long work_worlds[3];
+    unsigned long long work_edges[3];
+    unsigned long long work_bytes[3];
 };
 
 // How a world evaluation reports its counts.
@@ -134,7 +140,12 @@ hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
-hipError_t launch_affected(const TileOut& out, uint32_t theta, RoundCtl* ctl, int32_t* list, hipStream_t s);
+hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
+hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
+                             int32_t* idx_world, hipStream_t s);
+hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
+                           const int32_t* idx_world, int32_t* list, hipStream_t s);
+hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,

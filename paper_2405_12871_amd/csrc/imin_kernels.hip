@@ -135,10 +135,12 @@ hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n
 
 // ---------------------------------------------------------- counters
 __global__ void k_ctl_reset_round(RoundCtl* ctl) {
+    if (ctl->stop) return;
     ctl->total = 0;
     ctl->best_gain = 0;
 }
 __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
+    if (ctl->stop) return;
     for (int i = 0; i < 3; ++i) {
         ctl->next[i] = 0;
         ctl->list_n[i] = 0;
@@ -169,6 +171,7 @@ __device__ __forceinline__ void chunk_range(unsigned long long P, int g1, int c,
 __global__ __launch_bounds__(kRedNT) void k_hist(const RoundCtl* ctl, const int32_t* pair_node,
                                                  unsigned long long cap, ReduceBufs rb) {
     __shared__ int h[kMaxBuckets];
+    if (ctl->stop) return;
     unsigned long long P = ctl->pair_count;
     if (P > cap || (ctl->flags & kFlagPairOverflow)) P = 0;
     for (int i = threadIdx.x; i < rb.nb; i += kRedNT) h[i] = 0;
@@ -182,9 +185,10 @@ __global__ __launch_bounds__(kRedNT) void k_hist(const RoundCtl* ctl, const int3
 }
 
 // single-workgroup exclusive scan of hist[0 .. nb*g1) in place; hist[nb*g1] = total
-__global__ __launch_bounds__(1024) void k_scan(ReduceBufs rb) {
+__global__ __launch_bounds__(1024) void k_scan(const RoundCtl* ctl, ReduceBufs rb) {
     __shared__ int tmp[16];
     __shared__ int carry;
+    if (ctl->stop) return;
     const int total = rb.nb * rb.g1;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
@@ -217,6 +221,7 @@ __global__ __launch_bounds__(kRedNT) void k_scatter(const RoundCtl* ctl, const i
                                                     const int32_t* pair_cnt, unsigned long long cap,
                                                     ReduceBufs rb) {
     __shared__ int cur[kMaxBuckets];
+    if (ctl->stop) return;
     unsigned long long P = ctl->pair_count;
     if (P > cap || (ctl->flags & kFlagPairOverflow)) P = 0;
     for (int i = threadIdx.x; i < rb.nb; i += kRedNT) cur[i] = rb.hist[(size_t)i * rb.g1 + blockIdx.x];
@@ -231,27 +236,39 @@ __global__ __launch_bounds__(kRedNT) void k_scatter(const RoundCtl* ctl, const i
     }
 }
 
-__global__ __launch_bounds__(kRedNT) void k_accum(int32_t n, ReduceBufs rb) {
+// One workgroup per (bucket, slice): LDS accumulation of the slice's pairs.
+// With one slice the workgroup owns its bucket's nodes and adds the sums
+// straight into gain; otherwise it writes a partial vector for k_sum_slices.
+__global__ __launch_bounds__(kRedNT) void k_accum(const RoundCtl* ctl, int32_t n, ReduceBufs rb, int64_t* gain) {
     __shared__ unsigned long long acc[1 << kBucketShift];
+    if (ctl->stop) return;
     const int bucket = blockIdx.x / rb.slices;
     const int slice = blockIdx.x % rb.slices;
-    for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) acc[i] = 0ull;
-    __syncthreads();
     const long long bs = rb.hist[(size_t)bucket * rb.g1];
     const long long be = (bucket + 1 < rb.nb) ? rb.hist[(size_t)(bucket + 1) * rb.g1] : rb.hist[(size_t)rb.nb * rb.g1];
     const long long len = be - bs;
+    if (rb.slices == 1 && len == 0) return;  // nothing to add to this bucket
+    for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) acc[i] = 0ull;
+    __syncthreads();
     const long long a = bs + len * slice / rb.slices;
     const long long b = bs + len * (slice + 1) / rb.slices;
     const int32_t node0 = bucket << kBucketShift;
     for (long long i = a + threadIdx.x; i < b; i += kRedNT)
         atomicAdd(&acc[rb.sorted_node[i] - node0], (unsigned long long)(long long)rb.sorted_cnt[i]);
     __syncthreads();
+    if (rb.slices == 1) {
+        for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) {
+            const long long v = (long long)acc[i];
+            if (v != 0 && node0 + i < n) gain[node0 + i] += v;
+        }
+        return;
+    }
     int64_t* out = rb.part + (size_t)slice * ((size_t)rb.nb << kBucketShift) + ((size_t)bucket << kBucketShift);
     for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) out[i] = (int64_t)acc[i];
-    (void)n;
 }
 
-__global__ void k_sum_slices(int32_t n, ReduceBufs rb, int64_t* gain) {
+__global__ void k_sum_slices(const RoundCtl* ctl, int32_t n, ReduceBufs rb, int64_t* gain) {
+    if (ctl->stop) return;
     const size_t stride_s = (size_t)rb.nb << kBucketShift;
     for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < (size_t)n;
          u += (size_t)gridDim.x * blockDim.x) {
@@ -266,18 +283,22 @@ hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const Redu
     k_hist<<<rb.g1, kRedNT, 0, s>>>(ctl, out.pair_node, out.pair_cap, rb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_scan<<<1, 1024, 0, s>>>(rb);
+    k_scan<<<1, 1024, 0, s>>>(ctl, rb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     k_scatter<<<rb.g1, kRedNT, 0, s>>>(ctl, out.pair_node, out.pair_cnt, out.pair_cap, rb);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_accum<<<rb.nb * rb.slices, kRedNT, 0, s>>>(g.n, rb);
+    k_accum<<<rb.nb * rb.slices, kRedNT, 0, s>>>(ctl, g.n, rb, gain);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_sum_slices<<<1024, 256, 0, s>>>(g.n, rb, gain);
-    return hipGetLastError();
+    if (rb.slices > 1) {
+        k_sum_slices<<<1024, 256, 0, s>>>(ctl, g.n, rb, gain);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 __global__ void k_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl) {
     __shared__ long long tmp[4];
+    if (ctl->stop) return;
     long long s = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
         s += ws[i];
@@ -293,6 +314,68 @@ hipError_t launch_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl, hi
     return hipGetLastError();
 }
 
+// ------------------------------------------------ generic exclusive scan
+// data[0..count) -> exclusive prefix sums in place, data[count] = total.
+// Three passes: 4096-element blocks, a single-workgroup scan of the block
+// sums, and the carry-in add.  count <= 4096 * 4096.
+__global__ __launch_bounds__(1024) void k_xscan_blocks(int32_t* data, int count, int32_t* bsum) {
+    __shared__ int tmp[16];
+    const int base = blockIdx.x * 4096;
+    int v[4], loc = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = base + threadIdx.x * 4 + k;
+        v[k] = (i < count) ? data[i] : 0;
+        loc += v[k];
+    }
+    int tot;
+    int run = block_excl_scan<1024>(loc, tmp, tot);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int i = base + threadIdx.x * 4 + k;
+        if (i < count) data[i] = run;
+        run += v[k];
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_xscan_sums(int32_t* bsum, int nblocks, int32_t* data, int count) {
+    __shared__ int tmp[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nblocks; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int v = (i < nblocks) ? bsum[i] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024>(v, tmp, tot);
+        if (i < nblocks) bsum[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) data[count] = carry;
+}
+
+__global__ void k_xscan_add(int32_t* data, int count, const int32_t* bsum) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) data[i] += bsum[i / 4096];
+}
+
+hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s) {
+    const int nblocks = (count + 4095) / 4096;
+    if (nblocks > 0) {
+        k_xscan_blocks<<<nblocks, 1024, 0, s>>>(data, count, bsum);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    k_xscan_sums<<<1, 1024, 0, s>>>(bsum, nblocks, data, count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nblocks == 0) return e;
+    k_xscan_add<<<(count + 255) / 256, 256, 0, s>>>(data, count, bsum);
+    return hipGetLastError();
+}
+
 // ----------------------------------------------------------- selection
 // argmax over candidates (not seeds, not blocked) of (gain desc, id asc).
 __device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32_t u2) {
@@ -301,8 +384,9 @@ __device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32
     return g1 > g2 || (g1 == g2 && u1 < u2);
 }
 
-__global__ __launch_bounds__(256) void k_select_partial(int32_t n, const int64_t* gain, const uint32_t* excl,
-                                                        int64_t* pg, int32_t* pu) {
+__global__ __launch_bounds__(256) void k_select_partial(const RoundCtl* ctl, int32_t n, const int64_t* gain,
+                                                        const uint32_t* excl, int64_t* pg, int32_t* pu) {
+    if (ctl->stop) return;
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
     int64_t bg = 0;
@@ -385,7 +469,7 @@ hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl,
                          int64_t* part_gain, int32_t* part_node, int parts, int32_t k,
                          int32_t* blockers, int64_t* gains, int64_t* totals, int32_t* n_selected,
                          hipStream_t s) {
-    k_select_partial<<<parts, 256, 0, s>>>(g.n, gain, excl, part_gain, part_node);
+    k_select_partial<<<parts, 256, 0, s>>>(ctl, g.n, gain, excl, part_gain, part_node);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_select_final<<<1, 256, 0, s>>>(parts, part_gain, part_node, excl, ctl, k, blockers, gains, totals,

@@ -31,6 +31,8 @@
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
 
+#include <algorithm>
+
 namespace imin {
 
 constexpr int kMaxDomPasses = 4096;
@@ -45,6 +47,8 @@ struct WorldShared {
     int widx;
     unsigned long long pair_base;
     long long edges;  // CSR slots of reached rows
+    int ndelta;       // count changes reported (incremental rounds)
+    unsigned long long acc_worlds, acc_edges, acc_bytes;  // this workgroup's work so far
     int row_lid[NT];
     int row_node[NT];
     int row_e0[NT];
@@ -223,7 +227,7 @@ __device__ __forceinline__ void scan_slot_group(const GraphDev& g, const QueryDe
 
 // Returns false when the store ran out of room.  On success writes the
 // world's pairs, size, id sum and scanned-slot count.
-template <int NT, class Store>
+template <int NT, int TIER, class Store>
 __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
                                const TileOut& out, Store& st, WorldShared<NT>& sh) {
     const int t = threadIdx.x;
@@ -234,6 +238,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     if (t == 0) {
         sh.count = ns;
         sh.edges = q.seed_edges;
+        sh.ndelta = 0;
         sh.n_extra = 0;
         sh.overflow = 0;
         st.lvl[0] = 0;
@@ -268,7 +273,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
             }
             int total;
             const int start = block_excl_scan<NT>(nb, sh.scan_tmp, total);
-            if (out.world_edges && e1 > e0) atomicAdd((unsigned long long*)&sh.edges, (unsigned long long)(e1 - e0));
+            if (e1 > e0) atomicAdd((unsigned long long*)&sh.edges, (unsigned long long)(e1 - e0));
             sh.row_lid[t] = i;
             sh.row_node[t] = u;
             sh.row_e0[t] = e0;
@@ -378,26 +383,37 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
 
     // ---- outputs
     const int len = R - ns;
+    int read_len = 0;  // stored entries read back (incremental rounds)
     if (out.mode == kModeDelta) {
-        // Blocking only removes nodes, so every reached node is in the stored
-        // list: walking the old list finds every count that changed.
+        // The stored list keeps the round-0 order; an entry whose count is 0
+        // is a node no longer reached.  Blocking only removes nodes, so every
+        // node reached now has a live entry: walking the live entries finds
+        // every count that changed, and each is updated in place.
         const size_t so = (size_t)out.store_off[w];
-        const int old_len = out.store_len[w];
+        const int list_len = out.store_len[w];
+        read_len = list_len;
         const int lane = t & 63;
-        for (int base = 0; base < old_len; base += NT) {
+        for (int base = 0; base < list_len; base += NT) {
             const int i = base + t;
             int32_t u = 0;
             int d = 0;
-            if (i < old_len) {
-                u = out.store_node[so + i];
-                const int lid = st.lookup(u);
-                const int c_new = (lid >= ns) ? *st.aux_ptr(lid) : 0;
-                d = c_new - out.store_cnt[so + i];
+            if (i < list_len) {
+                const int c_old = out.store_cnt[so + i];
+                if (c_old > 0) {
+                    u = out.store_node[so + i];
+                    const int lid = st.lookup(u);
+                    const int c_new = (lid >= ns) ? *st.aux_ptr(lid) : 0;
+                    d = c_new - c_old;
+                    if (d != 0) out.store_cnt[so + i] = c_new;
+                }
             }
             const unsigned long long mask = __ballot(d != 0);
             const int cnt = __popcll(mask);
             unsigned long long wbase = 0;
-            if (lane == 0 && cnt) wbase = atomicAdd(&ctl->pair_count, (unsigned long long)cnt);
+            if (lane == 0 && cnt) {
+                wbase = atomicAdd(&ctl->pair_count, (unsigned long long)cnt);
+                atomicAdd(&sh.ndelta, cnt);
+            }
             wbase = __shfl(wbase, 0, 64);
             if (d != 0) {
                 const unsigned long long pos = wbase + __popcll(mask & ((1ull << lane) - 1ull));
@@ -409,12 +425,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
                 }
             }
         }
-        __syncthreads();  // the old list is fully read before it is replaced
-        for (int i = t; i < len; i += NT) {
-            out.store_node[so + i] = st.node(ns + i);
-            out.store_cnt[so + i] = *st.aux_ptr(ns + i);
-        }
-        if (t == 0) out.store_len[w] = len;
+        __syncthreads();
     } else {
         const bool store = (out.mode == kModeStore);
         if (t == 0) {
@@ -446,6 +457,16 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
         if (out.world_size) out.world_size[wi] = R;
         if (out.world_sum) out.world_sum[wi] = s + q.seed_sum;
         if (out.world_edges) out.world_edges[wi] = sh.edges;
+        unsigned long long bytes = 8ull * (unsigned long long)sh.edges + 8ull * (unsigned long long)(R - ns) +
+                                   16ull * (unsigned long long)q.n_seed_chunks;
+        if (out.mode == kModeDelta)
+            bytes += 8ull * (unsigned long long)read_len + 12ull * (unsigned long long)sh.ndelta;
+        else
+            bytes += 8ull * (unsigned long long)len;
+        // per-workgroup tallies, added to the device counters once at exit
+        sh.acc_worlds += 1;
+        sh.acc_edges += (unsigned long long)sh.edges;
+        sh.acc_bytes += bytes;
     }
     return true;
 }
@@ -467,8 +488,10 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     __shared__ Store st;
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
+    if (ctl->stop) return;
     st.template clear<NT>();
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
+    if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
     __syncthreads();
     for (;;) {
         if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[TIER], 1u);
@@ -476,13 +499,18 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         const uint32_t k = (uint32_t)sh.widx;
         if (k >= n_items) break;
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
-        const bool ok = evaluate_world<NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
+        const bool ok = evaluate_world<NT, TIER>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) {
             const uint32_t pos = atomicAdd(&ctl->list_n[TIER + 1], 1u);
             next_list[pos] = (int32_t)wi;
         }
         st.template reset<NT>(0);
         __syncthreads();
+    }
+    if (t == 0 && sh.acc_worlds) {
+        atomicAdd(&ctl->work_worlds[TIER], sh.acc_worlds);
+        atomicAdd(&ctl->work_edges[TIER], sh.acc_edges);
+        atomicAdd(&ctl->work_bytes[TIER], sh.acc_bytes);
     }
 }
 
@@ -505,18 +533,25 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     st.xu_ = bs.xu + slot * (size_t)bs.xcap;
     st.cap_lv_ = g.n + 1;
     st.cap_x_ = bs.xcap;
+    if (ctl->stop) return;
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
+    if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
     for (;;) {
         if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[2], 1u);
         __syncthreads();
         const uint32_t k = (uint32_t)sh.widx;
         if (k >= n_items) break;
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
-        const bool ok = evaluate_world<kTier2NT>(g, q, ctl, w_begin + wi, wi, out, st, sh);
+        const bool ok = evaluate_world<kTier2NT, 2>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
         __syncthreads();
         st.reset<kTier2NT>(sh.count < g.n ? sh.count : g.n);
         __syncthreads();
+    }
+    if (t == 0 && sh.acc_worlds) {
+        atomicAdd(&ctl->work_worlds[2], sh.acc_worlds);
+        atomicAdd(&ctl->work_edges[2], sh.acc_edges);
+        atomicAdd(&ctl->work_bytes[2], sh.acc_bytes);
     }
 }
 
@@ -544,28 +579,72 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
     return hipGetLastError();
 }
 
-// Worlds whose stored list holds the last selected blocker: blocking it
-// changes them; every other world keeps its reached set and dominator tree.
-// One wave per world; the list goes to list_n[0].
-__global__ __launch_bounds__(256) void k_affected(TileOut out, uint32_t theta, RoundCtl* ctl, int32_t* list) {
-    if (ctl->stop) return;
-    const int32_t u = ctl->ustar;
+// ----------------------------------------------- incremental-round index
+// After round 0 every stored entry (world w, position p, node u) is indexed
+// by u.  The worlds a new blocker u changes are those whose entry for u is
+// still live (count > 0): every other world keeps its reached set and its
+// dominator tree.
+
+// count entries per node
+__global__ void k_index_count(const int32_t* store_node, unsigned long long n_entries, int32_t* cnt) {
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n_entries; p += (size_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[store_node[p]], 1);
+}
+
+// one wave per world: place (position, world) of each entry at its node's cursor
+__global__ void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32_t* idx_pos, int32_t* idx_world) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * 256u) >> 6;
+    const uint32_t wave = (blockIdx.x * (uint32_t)blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * (uint32_t)blockDim.x) >> 6;
     for (uint32_t w = wave; w < theta; w += nwaves) {
         const size_t so = (size_t)out.store_off[w];
         const int len = out.store_len[w];
-        bool hit = false;
-        for (int i = lane; i < len; i += 64) hit |= (out.store_node[so + i] == u);
-        if (__ballot(hit) && lane == 0) list[atomicAdd(&ctl->list_n[0], 1u)] = (int32_t)w;
+        for (int i = lane; i < len; i += 64) {
+            const int pos = atomicAdd(&cursor[out.store_node[so + i]], 1);
+            idx_pos[pos] = (int32_t)(so + i);
+            idx_world[pos] = (int32_t)w;
+        }
     }
 }
 
-hipError_t launch_affected(const TileOut& out, uint32_t theta, RoundCtl* ctl, int32_t* list, hipStream_t s) {
+// worlds whose entry for the last selected blocker is live -> list_n[0]
+__global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
+                                                  const int32_t* idx_pos, const int32_t* idx_world,
+                                                  int32_t* list) {
+    if (ctl->stop) return;
+    const int32_t u = ctl->ustar;
+    const int32_t a = idx_off[u], b = idx_off[u + 1];
+    const int lane = threadIdx.x & 63;
+    for (int i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
+        const int k = i + lane;
+        const bool live = (k < b) && out.store_cnt[idx_pos[k]] > 0;
+        const unsigned long long mask = __ballot(live);
+        const int cnt = __popcll(mask);
+        uint32_t base = 0;
+        if (lane == 0 && cnt) base = atomicAdd(&ctl->list_n[0], (uint32_t)cnt);
+        base = __shfl(base, 0, 64);
+        if (live) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = idx_world[k];
+    }
+}
+
+hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s) {
+    unsigned blocks = (unsigned)std::min<unsigned long long>((n_entries + 255) / 256, 8192ull);
+    if (blocks == 0) return hipSuccess;
+    k_index_count<<<blocks, 256, 0, s>>>(out.store_node, n_entries, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
+                             int32_t* idx_world, hipStream_t s) {
     unsigned blocks = (theta + 3) / 4;
     if (blocks > 8192) blocks = 8192;
-    k_affected<<<blocks, 256, 0, s>>>(out, theta, ctl, list);
+    k_index_fill<<<blocks, 256, 0, s>>>(out, theta, cursor, idx_pos, idx_world);
+    return hipGetLastError();
+}
+
+hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
+                           const int32_t* idx_world, int32_t* list, hipStream_t s) {
+    k_affected<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_pos, idx_world, list);
     return hipGetLastError();
 }
 

@@ -152,7 +152,7 @@ def test_solve_random_graphs(B, oracle_mod, case):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
-@pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2"])
+@pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7"])
 def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
     """Incremental rounds (default), plain rounds, a resident store too small
     to hold round 0 (falls back to plain rounds) and re-evaluation of changed
@@ -161,6 +161,8 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
         monkeypatch.setenv("IMIN_INCREMENTAL", "0")
     elif variant == "store_overflow":
         monkeypatch.setenv("IMIN_STORE_CAP", "5000")
+    elif variant.startswith("batch"):
+        monkeypatch.setenv("IMIN_ROUND_BATCH", variant[5:])
     else:
         monkeypatch.setenv("IMIN_START_TIER", variant[-1])
     g = synth.random_small_graph(300, 1500, seed=77, prob="wc")
