@@ -161,31 +161,38 @@ struct Session {
     DevArray<int64_t> gain;
     DevArray<imin::RoundCtl> ctl;
     HostCtl hctl;
-    // tile outputs
+    // per-world outputs of a tile: sizes, scratch locations and lengths
     DevArray<int32_t> world_size;
-    DevArray<int32_t> list0, list1, list2;  // affected worlds; worlds handed down to tier 1 / 2
+    DevArray<int64_t> wloc;
+    DevArray<int32_t> wlen;
+    DevArray<int32_t> scr_node, scr_cnt;  // per-world scratch (fixed tier-0 slots + bump region)
+    size_t slot_cap0 = 0, big_cap = 0;
+    DevArray<int32_t> list0, list1, list2;  // changed worlds; worlds handed down to tier 1 / 2
+    // dense pairs and the reduction's buffers
+    DevArray<int32_t> pair_node, pair_cnt, sorted_node, sorted_cnt;
+    DevArray<int32_t> hist;
+    DevArray<int64_t> part;
+    imin::ReduceBufs rb{}, rb_delta{};
     // resident per-world (node, count) lists for incremental rounds
-    DevArray<int32_t> store_node, store_cnt, store_len;
+    DevArray<int32_t> store_node, store_cnt, store_len, dl_node, dl_cnt;
     DevArray<int64_t> store_off;
     bool incremental = false;
+    size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
     DevArray<int32_t> idx_off, idx_bsum, idx_cursor, idx_pos, idx_world;
-    imin::ReduceBufs rb_delta{};
     // level-0 slot groups of the seeds
     DevArray<int32_t> seed_cnt;
     DevArray<int4> seed_table;
-    DevArray<int32_t> pair_node, pair_cnt;
-    // reduction
-    DevArray<int32_t> hist, sorted_node, sorted_cnt;
-    DevArray<int64_t> part;
-    imin::ReduceBufs rb{};
-    // big-world path
+    // HBM world tier
     DevArray<int32_t> b_lid, b_nodes, b_parent, b_idom, b_aux, b_lvl, b_xv, b_xu;
     imin::BigSlots bs{};
     // selection
     DevArray<int64_t> sel_g;
     DevArray<int32_t> sel_u;
     int sel_parts = 0;
+    // per-workgroup work tallies
+    DevArray<unsigned long long> work;
+    int work_stride = 0;
     size_t tile_cap = 0;   // worlds per tile (buffer size)
     size_t tile = 0;       // worlds per tile in use
     int grid0 = 0, grid1 = 0;
@@ -194,7 +201,7 @@ struct Session {
 
     Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
 
-    imin_status_t init(uint64_t theta, bool need_gain_buffers) {
+    imin_status_t init(uint64_t theta, bool solve) {
         const size_t n = (size_t)g.n;
         IMIN_TRY(excl.alloc((n + 31) / 32));
         IMIN_TRY(gain.alloc(n));
@@ -204,21 +211,19 @@ struct Session {
         c0.expect_total = -1;
         IMIN_TRY(hipMemcpyAsync(ctl.p, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
 
-        tile_cap = std::min<size_t>(theta, env_size("IMIN_TILE_WORLDS", (size_t)1 << 22));
+        tile_cap = std::min<size_t>(theta, env_size("IMIN_TILE_WORLDS", (size_t)1 << 18));
         tile = tile_cap;
         IMIN_TRY(world_size.alloc(tile_cap));
+        IMIN_TRY(wloc.alloc(tile_cap));
+        // incremental rounds index change counts by world id
+        IMIN_TRY(wlen.alloc(solve ? std::max<size_t>(tile_cap, theta) : tile_cap));
         IMIN_TRY(list1.alloc(tile_cap));
         IMIN_TRY(list2.alloc(tile_cap));
         IMIN_TRY(list0.alloc(1));
-
-        // pair buffer: enough for the whole tile if worlds are small
-        const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
-        size_t want = tile_cap * std::min<size_t>(n, 512);
-        const size_t pcap = std::max<size_t>(std::min(want, budget), 1 << 16);
-        IMIN_TRY(pair_node.alloc(pcap));
-        IMIN_TRY(pair_cnt.alloc(pcap));
-        IMIN_TRY(sorted_node.alloc(pcap));
-        IMIN_TRY(sorted_cnt.alloc(pcap));
+        slot_cap0 = (size_t)imin::world_tier0_capacity();
+        big_cap = env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20);
+        IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
+        IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
 
         rb.nb = (int32_t)((n + ((size_t)1 << imin::kBucketShift) - 1) >> imin::kBucketShift);
         rb.g1 = 1024;
@@ -226,17 +231,16 @@ struct Session {
         IMIN_TRY(hist.alloc((size_t)rb.nb * rb.g1 + 1));
         IMIN_TRY(part.alloc((size_t)rb.slices * ((size_t)rb.nb << imin::kBucketShift)));
         rb.hist = hist.p;
-        rb.sorted_node = sorted_node.p;
-        rb.sorted_cnt = sorted_cnt.p;
         rb.part = part.p;
         // incremental rounds report few changes: fewer histogram chunks and
         // one workgroup per bucket adding straight into gain
         rb_delta = rb;
         rb_delta.g1 = 128;
         rb_delta.slices = 1;
-        (void)need_gain_buffers;
+        imin_status_t st = ensure_pairs(1 << 16);
+        if (st != IMIN_OK) return st;
 
-        // big-world slots: per slot 6 node arrays (+lvl) and 2 edge arrays
+        // HBM tier slots: per slot 6 node arrays (+lvl) and 2 edge arrays
         const int cus = cu_count();
         const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
         const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * xcap * 4;
@@ -271,6 +275,11 @@ struct Session {
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
+        if (timed.on) {
+            work_stride = std::max(std::max(grid0, grid1), bs.n_slots);
+            IMIN_TRY(work.alloc((size_t)9 * work_stride));
+            IMIN_TRY(hipMemsetAsync(work.p, 0, (size_t)9 * work_stride * sizeof(unsigned long long), s));
+        }
         return IMIN_OK;
     }
 
@@ -279,11 +288,18 @@ struct Session {
     void finish() {
         if (!timed.on) return;
         timed.flush();
+        std::vector<unsigned long long> h((size_t)9 * work_stride);
+        if (work.p && hipMemcpy(h.data(), work.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
+                          hipSuccess)
+            return;
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        for (int i = 0; i < 3; ++i) {
-            g_timing.work_worlds[i] += (int64_t)hctl.p->work_worlds[i];
-            g_timing.work_edges[i] += (int64_t)hctl.p->work_edges[i];
-            g_timing.work_bytes[i] += (int64_t)hctl.p->work_bytes[i];
+        for (int tier = 0; tier < 3; ++tier) {
+            int64_t f[3] = {0, 0, 0};
+            for (int field = 0; field < 3; ++field)
+                for (int b = 0; b < work_stride; ++b) f[field] += (int64_t)h[((size_t)tier * 3 + field) * work_stride + b];
+            g_timing.work_worlds[tier] += f[0];
+            g_timing.work_edges[tier] += f[1];
+            g_timing.work_bytes[tier] += f[2];
         }
     }
 
@@ -299,20 +315,61 @@ struct Session {
         return IMIN_OK;
     }
 
-    imin_status_t grow_pairs(unsigned long long needed) {
+    // dense pair buffer (and the reduction's sorted copy) of at least `needed`
+    imin_status_t ensure_pairs(unsigned long long needed) {
+        if (pair_node.p && pair_node.count >= needed) return IMIN_OK;
         const size_t want = (size_t)(needed + needed / 8 + 1024);
         IMIN_TRY(pair_node.alloc(want));
         IMIN_TRY(pair_cnt.alloc(want));
         IMIN_TRY(sorted_node.alloc(want));
         IMIN_TRY(sorted_cnt.alloc(want));
-        rb.sorted_node = sorted_node.p;
-        rb.sorted_cnt = sorted_cnt.p;
-        rb_delta.sorted_node = sorted_node.p;
-        rb_delta.sorted_cnt = sorted_cnt.p;
+        rb.sorted_node = rb_delta.sorted_node = sorted_node.p;
+        rb.sorted_cnt = rb_delta.sorted_cnt = sorted_cnt.p;
+        rb.sorted_cap = rb_delta.sorted_cap = sorted_node.count;
         return IMIN_OK;
     }
 
-    // node -> (store position, world) of every entry written in round 0
+    // Resident store for incremental rounds: per-world offsets and lengths;
+    // entries are allocated as round 0 produces them.
+    imin_status_t enable_store(uint64_t theta) {
+        store_budget = env_size("IMIN_STORE_CAP", (size_t)1 << 30);
+        if (store_off.alloc(theta) != hipSuccess || store_len.alloc(theta) != hipSuccess ||
+            list0.alloc(theta) != hipSuccess) {
+            store_off.release();
+            store_len.release();
+            (void)hipGetLastError();
+            return IMIN_OK;  // plain rounds give the same integers
+        }
+        incremental = true;
+        return IMIN_OK;
+    }
+
+    // room for `more` entries after the store's `used` ones; false when the
+    // budget or the device memory is exhausted
+    bool ensure_store(unsigned long long used, unsigned long long more) {
+        const unsigned long long need = used + more;
+        if (need > store_budget) return false;
+        if (store_node.p && store_node.count >= need) return true;
+        const size_t want = (size_t)std::min<unsigned long long>(store_budget, need + need / 4 + 1024);
+        DevArray<int32_t> nn, nc;
+        if (nn.alloc(want) != hipSuccess || nc.alloc(want) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        if (used) {
+            if (hipMemcpyAsync(nn.p, store_node.p, used * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(nc.p, store_cnt.p, used * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+                return false;
+        }
+        std::swap(store_node.p, nn.p);
+        std::swap(store_node.count, nn.count);
+        std::swap(store_cnt.p, nc.p);
+        std::swap(store_cnt.count, nc.count);
+        return hipStreamSynchronize(s) == hipSuccess;  // old arrays are freed on return
+    }
+
+    // node -> (store position, world) of every entry written in round 0;
+    // also the change buffers of incremental rounds
     imin_status_t build_index(uint64_t theta) {
         const unsigned long long entries = hctl.p->store_count;
         const size_t n = (size_t)g.n;
@@ -321,6 +378,10 @@ struct Session {
         IMIN_TRY(idx_cursor.alloc(n + 1));
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
+        IMIN_TRY(dl_node.alloc(entries));
+        IMIN_TRY(dl_cnt.alloc(entries));
+        imin_status_t st = ensure_pairs(entries);  // a round's changes never outnumber the entries
+        if (st != IMIN_OK) return st;
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_index_count(out, entries, idx_off.p, s));
@@ -330,32 +391,16 @@ struct Session {
         return IMIN_OK;
     }
 
-    // Evaluate worlds [w_begin, w_begin+count) under the current excl bitmap;
-    // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
-    // outputs are written at [0, count).
-    // Resident store for incremental rounds: per-world offsets and lengths
-    // for all theta worlds plus room for every world's list.
-    imin_status_t enable_store(uint64_t theta) {
-        const size_t cap = env_size("IMIN_STORE_CAP", (size_t)1 << 30);
-        if (cap < 1 || theta > (1ull << 32)) return IMIN_OK;
-        if (store_node.alloc(cap) != hipSuccess || store_cnt.alloc(cap) != hipSuccess ||
-            store_off.alloc(theta) != hipSuccess || store_len.alloc(theta) != hipSuccess ||
-            list0.alloc(theta) != hipSuccess) {
-            // not enough memory for the store: plain rounds give the same integers
-            store_node.release();
-            store_cnt.release();
-            store_off.release();
-            store_len.release();
-            (void)hipGetLastError();
-            return IMIN_OK;
-        }
-        incremental = true;
-        return IMIN_OK;
-    }
-
     imin::TileOut tile_out() const {
         imin::TileOut out{};
         out.mode = imin::kModePlain;
+        out.scr_node = scr_node.p;
+        out.scr_cnt = scr_cnt.p;
+        out.slot_cap0 = slot_cap0;
+        out.big_base = tile_cap * slot_cap0;
+        out.scr_cap = scr_node.count;
+        out.wloc = wloc.p;
+        out.wlen = wlen.p;
         out.pair_node = pair_node.p;
         out.pair_cnt = pair_cnt.p;
         out.pair_cap = pair_node.count;
@@ -364,6 +409,12 @@ struct Session {
         out.store_cap = store_node.count;
         out.store_off = store_off.p;
         out.store_len = store_len.p;
+        out.dl_node = dl_node.p;
+        out.dl_cnt = dl_cnt.p;
+        out.dl_cap = dl_node.count;
+        out.list_cap = (uint32_t)std::min<size_t>(list0.count, 0xFFFFFFFFu);
+        out.work = work.p;
+        out.work_stride = work_stride;
         return out;
     }
 
@@ -396,73 +447,78 @@ struct Session {
         imin_status_t st = launch_tiers(q, 0, 0, list0.p, out);
         if (st != IMIN_OK) return st;
         ev = timed.begin(s);
+        IMIN_TRY(imin::launch_compact(out, ctl.p, 0, 0, list0.p, s));
         IMIN_TRY(imin::launch_reduce_pairs(g, out, rb_delta, ctl.p, gain.p, s));
         timed.end(2, ev, s);
         IMIN_TRY(imin::launch_sum_sizes(world_size.p, (uint32_t)theta, ctl.p, s));
         return IMIN_OK;
     }
 
+    // Evaluate worlds [w_begin, w_begin+count) under the current excl bitmap;
+    // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
+    // outputs are written at [0, count).  With store_mode (round 0 of a
+    // solve) the per-world lists also become the resident store.
     imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
                            int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false) {
         uint64_t done = 0;
-        unsigned long long store_base = 0;
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
-            const bool use_store = store_mode && incremental;
             imin::TileOut out = tile_out();
-            out.mode = use_store ? imin::kModeStore : imin::kModePlain;
             out.world_size = ws_out ? ws_out + done : world_size.p;
             out.world_sum = wsum_out ? wsum_out + done : nullptr;
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
             imin_status_t st = launch_tiers(q, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, out);
             if (st != IMIN_OK) return st;
+            IMIN_TRY(imin::launch_sum_lengths(out, ctl.p, (uint32_t)nw, nullptr, s));
             st = read_ctl();
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
             // route later tiles straight to the tier most worlds end up in
             if (start_tier < 2 && hctl.p->list_n[2] * 2 > nw) start_tier = 2;
             else if (start_tier < 1 && hctl.p->list_n[1] * 2 > nw) start_tier = 1;
-            if (f & (imin::kFlagBigCapacity | imin::kFlagDomPasses)) {
+            if (f & (imin::kFlagBigCapacity | imin::kFlagDomPasses | imin::kFlagBounds | imin::kFlagReduceCapacity)) {
                 g_last_flags = f;
                 return IMIN_ERR_INTERNAL;
             }
-            if (f & imin::kFlagStoreOverflow) {
-                // the resident store is full: finish with plain rounds
-                st = clear_flag(imin::kFlagStoreOverflow);
-                if (st != IMIN_OK) return st;
-                incremental = false;
-                continue;  // redo this tile without the store
-            }
             if (f & imin::kFlagPairOverflow) {
+                // the scratch bump region was too small: grow it, redo the tile
                 st = clear_flag(imin::kFlagPairOverflow);
                 if (st != IMIN_OK) return st;
-                const unsigned long long need = hctl.p->pair_count;
-                const size_t budget = env_size("IMIN_PAIR_CAP", (size_t)1 << 28);
-                if (need <= budget) {
-                    st = grow_pairs(need);
-                    if (st != IMIN_OK) return st;
-                } else {
-                    // shrink the tile so that its pairs fit the budget
-                    if (pair_node.count < budget) {
-                        st = grow_pairs(budget);
-                        if (st != IMIN_OK) return st;
-                    }
-                    const double per_world = (double)need / (double)nw;
-                    uint64_t t2 = (uint64_t)((double)pair_node.count * 0.9 / std::max(per_world, 1.0));
-                    tile = std::max<uint64_t>(1, std::min<uint64_t>(t2, tile));
-                }
-                continue;  // redo this tile
+                big_cap = (size_t)hctl.p->big_count + hctl.p->big_count / 8 + 1024;
+                IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
+                IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
+                continue;
             }
+            // dense destination for the tile's entries
+            const unsigned long long total = hctl.p->tile_total;
+            const unsigned long long store_base = hctl.p->store_count;
+            bool use_store = store_mode && incremental;
+            if (use_store && !ensure_store(store_base, total)) {
+                incremental = false;  // the store does not fit: plain rounds from here on
+                use_store = false;
+            }
+            // the reduction's sorted copy needs room for every entry of the
+            // tile whichever buffer holds them
+            st = ensure_pairs(total);
+            if (st != IMIN_OK) return st;
+            out = [&] {
+                imin::TileOut o = tile_out();
+                o.world_size = out.world_size;
+                o.world_sum = out.world_sum;
+                o.world_edges = out.world_edges;
+                o.mode = use_store ? imin::kModeStore : imin::kModePlain;
+                return o;
+            }();
+            hipEvent_t ev = timed.begin(s);
+            IMIN_TRY(imin::launch_compact(out, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, s));
             imin::TileOut red = out;
             if (use_store) {
-                // this tile's pairs sit contiguously in the store
+                // this tile's entries sit contiguously in the store
                 red.pair_node = store_node.p + store_base;
                 red.pair_cnt = store_cnt.p + store_base;
-                red.pair_cap = store_node.count - store_base;
-                store_base = hctl.p->store_count;
+                red.pair_cap = total;
             }
-            hipEvent_t ev = timed.begin(s);
             IMIN_TRY(imin::launch_reduce_pairs(g, red, rb, ctl.p, gain.p, s));
             timed.end(2, ev, s);
             IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
@@ -607,11 +663,6 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             if (!indexed) {
                 st = ss.build_index((uint64_t)theta);
                 if (st != IMIN_OK) return st;
-                if (ss.pair_node.count < ss.hctl.p->store_count) {
-                    // a round's changes never outnumber the stored entries
-                    st = ss.grow_pairs(ss.hctl.p->store_count);
-                    if (st != IMIN_OK) return st;
-                }
                 indexed = true;
             }
             // incremental rounds need no host decision: enqueue a batch; once

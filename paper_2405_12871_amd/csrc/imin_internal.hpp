@@ -24,7 +24,9 @@ enum : uint32_t {
     kFlagBigCapacity = 1u << 9,    // big-world scratch too small
     kFlagSpreadMismatch = 1u << 10, // T_{r+1} != T_r - gain_r
     kFlagDomPasses = 1u << 11,      // dominator passes did not settle
-    kFlagStoreOverflow = 1u << 12   // resident per-world store too small
+    kFlagStoreOverflow = 1u << 12,  // resident per-world store too small
+    kFlagReduceCapacity = 1u << 13, // more entries than the reduction's buffers hold
+    kFlagBounds = 1u << 14          // a per-world range fell outside its buffer
 };
 
 // Graph as kept by a handle.  col/thr are padded with 4..7 trailing entries
@@ -55,12 +57,8 @@ struct RoundCtl {
     int32_t seed_chunks;     // entries of the level-0 slot-group table
     int32_t pad1;
     unsigned long long store_count;  // pairs held by the resident per-world store
-    // work done per world tier: worlds finished, CSR slots of their reached
-    // rows, and algorithmic HBM bytes (slot columns and thresholds, row
-    // offsets, level-0 table entries, count lists read and written)
-    unsigned long long work_worlds[3];
-    unsigned long long work_edges[3];
-    unsigned long long work_bytes[3];
+    unsigned long long big_count;    // entries bump-allocated by tier-1/2 worlds this tile
+    unsigned long long tile_total;   // entries the tile's worlds wrote (sum of lengths)
 };
 
 // How a world evaluation reports its counts.
@@ -86,10 +84,26 @@ struct BigSlots {
 };
 
 // Everything a tile of world evaluations writes.
+//
+// World evaluations first write their (node, count) entries to a scratch
+// space with no shared counter: a tier-0 world at its own fixed slot
+// (wi * slot_cap0), a larger world at a bump-allocated place after big_base
+// (few and large, so the shared counter is cheap).  A compaction kernel then
+// packs the entries densely, with one counter update per workgroup.  In
+// incremental rounds a world writes its count changes into dl_* at its own
+// stored-list positions, which it alone owns.
 struct TileOut {
     int mode;
-    int32_t* pair_node;  // [pair_cap]
-    int32_t* pair_cnt;   // [pair_cap]
+    int32_t* scr_node;
+    int32_t* scr_cnt;
+    unsigned long long slot_cap0;  // entries per tier-0 slot
+    unsigned long long big_base;   // first entry of the bump region
+    unsigned long long scr_cap;    // entries in the scratch space
+    int64_t* wloc;                 // [tile] scratch start of each world's entries
+    int32_t* wlen;                 // [tile] entries per world; [theta] changes per world (incremental)
+    // dense pairs for the reduction
+    int32_t* pair_node;
+    int32_t* pair_cnt;
     unsigned long long pair_cap;
     // resident per-world store (solve only), indexed by world id
     int32_t* store_node;
@@ -97,9 +111,15 @@ struct TileOut {
     unsigned long long store_cap;
     int64_t* store_off;  // [theta]
     int32_t* store_len;  // [theta]
+    int32_t* dl_node;    // [store entries] count changes, at the world's store positions
+    int32_t* dl_cnt;
+    unsigned long long dl_cap;
+    uint32_t list_cap;   // entries of the changed-world list
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
+    unsigned long long* work;  // [3 tiers][3 fields][work_stride] per-workgroup tallies
+    int work_stride;
 };
 
 struct QueryDev {
@@ -121,6 +141,7 @@ struct ReduceBufs {
     int32_t* hist;       // [nb * g1 + 1]
     int32_t* sorted_node;
     int32_t* sorted_cnt;
+    unsigned long long sorted_cap;  // entries of sorted_node / sorted_cnt
     int64_t* part;       // [slices][nb << kBucketShift]
 };
 
@@ -140,6 +161,10 @@ hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
+hipError_t launch_sum_lengths(const TileOut& out, RoundCtl* ctl, uint32_t count, const int32_t* list,
+                              hipStream_t s);
+hipError_t launch_compact(const TileOut& out, RoundCtl* ctl, uint32_t w_begin, uint32_t count, const int32_t* list,
+                          hipStream_t s);
 hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
@@ -151,6 +176,7 @@ hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
                             int4* table, hipStream_t s);
 int world_tier_blocks_per_cu(int tier);
+int world_tier0_capacity();  // non-seed nodes a tier-0 world may reach
 hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
                                RoundCtl* ctl, int64_t* gain, hipStream_t s);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);

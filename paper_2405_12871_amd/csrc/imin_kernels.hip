@@ -146,6 +146,8 @@ __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
         ctl->list_n[i] = 0;
     }
     ctl->pair_count = 0;
+    ctl->big_count = 0;
+    ctl->tile_total = 0;
 }
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_round<<<1, 1, 0, s>>>(ctl);
@@ -168,12 +170,17 @@ __device__ __forceinline__ void chunk_range(unsigned long long P, int g1, int c,
     b = P * (unsigned long long)(c + 1) / (unsigned long long)g1;
 }
 
-__global__ __launch_bounds__(kRedNT) void k_hist(const RoundCtl* ctl, const int32_t* pair_node,
+__global__ __launch_bounds__(kRedNT) void k_hist(RoundCtl* ctl, const int32_t* pair_node,
                                                  unsigned long long cap, ReduceBufs rb) {
     __shared__ int h[kMaxBuckets];
     if (ctl->stop) return;
     unsigned long long P = ctl->pair_count;
-    if (P > cap || (ctl->flags & kFlagPairOverflow)) P = 0;
+    if (P > cap || P > rb.sorted_cap || (ctl->flags & kFlagPairOverflow)) {
+        // never sort more entries than both buffers hold; flag it instead
+        if (P && blockIdx.x == 0 && threadIdx.x == 0 && !(ctl->flags & kFlagPairOverflow))
+            atomicOr(&ctl->flags, (uint32_t)kFlagReduceCapacity);
+        P = 0;
+    }
     for (int i = threadIdx.x; i < rb.nb; i += kRedNT) h[i] = 0;
     __syncthreads();
     unsigned long long a, b;
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(kRedNT) void k_scatter(const RoundCtl* ctl, const i
     __shared__ int cur[kMaxBuckets];
     if (ctl->stop) return;
     unsigned long long P = ctl->pair_count;
-    if (P > cap || (ctl->flags & kFlagPairOverflow)) P = 0;
+    if (P > cap || P > rb.sorted_cap || (ctl->flags & kFlagPairOverflow)) P = 0;
     for (int i = threadIdx.x; i < rb.nb; i += kRedNT) cur[i] = rb.hist[(size_t)i * rb.g1 + blockIdx.x];
     __syncthreads();
     unsigned long long a, b;
@@ -308,7 +315,7 @@ __global__ void k_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl) {
 
 hipError_t launch_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl, hipStream_t s) {
     unsigned blocks = (count + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    if (blocks > 64) blocks = 64;  // one counter update per block
     if (blocks == 0) return hipSuccess;
     k_sum_sizes<<<blocks, 256, 0, s>>>(ws, count, ctl);
     return hipGetLastError();

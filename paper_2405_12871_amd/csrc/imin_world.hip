@@ -24,7 +24,7 @@
 //   4. (node, c) pairs of the reached non-seeds go to the tile's pair buffer.
 //
 // Three tiers share this code: a one-wave workgroup with everything in LDS
-// (worlds of up to 384 non-seed nodes), a four-wave workgroup with a larger
+// (worlds of up to 256 non-seed nodes), a four-wave workgroup with a larger
 // LDS store (up to 2048), and a four-wave workgroup whose per-world arrays
 // live in HBM (any size).  A world that outgrows a tier is redone by the next
 // one; every tier gives the same integers.
@@ -44,7 +44,6 @@ struct WorldShared {
     int overflow; // store out of room: hand the world to the next tier
     int changed;
     int nonfwd;   // some extra edge does not go exactly one level down
-    int widx;
     unsigned long long pair_base;
     long long edges;  // CSR slots of reached rows
     int ndelta;       // count changes reported (incremental rounds)
@@ -65,6 +64,7 @@ struct WorldShared {
 template <int CAPNS, int HBITS, int XCAP, int LVCAP>
 struct LdsStore {
     static constexpr int kHash = 1 << HBITS;
+    static constexpr int kCapNonSeed = CAPNS;
     static constexpr int kMaxSeeds = 32767 - CAPNS;  // local ids fit int16
     int32_t keys[kHash];
     int16_t vals[kHash];
@@ -186,44 +186,79 @@ struct HbmStore {
     }
 };
 
-// One 4-aligned group of CSR slots [4*blk, 4*blk+4) of row ulid, restricted
-// to [e0, e1): draw the block's coins and claim or record every live edge.
-template <int NT, class Store>
-__device__ __forceinline__ void scan_slot_group(const GraphDev& g, const QueryDev& q, uint32_t w, uint32_t blk,
-                                                int ulid, int32_t unode, int e0, int e1, Store& st,
-                                                WorldShared<NT>& sh) {
-    const uint4 coin = philox_block(blk, w, q.key0, q.key1);
-    const int4 cv = *reinterpret_cast<const int4*>(g.col + 4 * (size_t)blk);
-    const uint4 tv = *reinterpret_cast<const uint4*>(g.thr + 4 * (size_t)blk);
-    const int ebase = (int)(4 * blk);
-    const int32_t vv[4] = {cv.x, cv.y, cv.z, cv.w};
-    const uint32_t tt[4] = {tv.x, tv.y, tv.z, tv.w};
-    const uint32_t cc[4] = {coin.x, coin.y, coin.z, coin.w};
+// A 4-aligned group of CSR slots [4*blk, 4*blk+4) of row ulid (node unode),
+// restricted to the row's slots [e0, e1).
+struct SlotGroup {
+    uint32_t blk;
+    int ulid;
+    int32_t unode;
+    int e0, e1;
+    bool valid;
+};
+
+// Draw the coins of U slot groups and claim or record every live edge.  The
+// work is split in phases so that the U groups' loads are in flight
+// together: columns and thresholds, then the Philox blocks, then the
+// exclusion bits of the live heads, then the claims.
+template <int NT, int U, class Store>
+__device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryDev& q, uint32_t w,
+                                                 const SlotGroup (&gr)[U], Store& st, WorldShared<NT>& sh) {
+    int4 cv[U];
+    uint4 tv[U];
 #pragma unroll
-    for (int qd = 0; qd < 4; ++qd) {
-        const int e = ebase + qd;
-        if (e < e0 || e >= e1) continue;
-        const uint32_t th = tt[qd];
-        if (!(th == kAlwaysLive || cc[qd] < th)) continue;
-        const int32_t v = vv[qd];
-        if (v == unode || bit_set(q.excl, v)) continue;
-        const int lid = st.claim(v, &sh.count);
-        if (lid >= 0) {
-            st.set_node(lid, v);
-            st.set_parent(lid, ulid);
-        } else if (lid == -1) {
-            const int x = atomicAdd(&sh.n_extra, 1);
-            if (x < st.cap_x()) {
-                st.xv[x] = v;
-                st.set_xu(x, ulid);
+    for (int u = 0; u < U; ++u) {
+        const size_t b = gr[u].valid ? (size_t)gr[u].blk : 0;
+        cv[u] = *reinterpret_cast<const int4*>(g.col + 4 * b);
+        tv[u] = *reinterpret_cast<const uint4*>(g.thr + 4 * b);
+    }
+    uint4 cn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) cn[u] = philox_block(gr[u].blk, w, q.key0, q.key1);
+    int32_t vv[U][4];
+    uint32_t ex[U][4];
+    bool lv[U][4];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t vs[4] = {cv[u].x, cv[u].y, cv[u].z, cv[u].w};
+        const uint32_t ts[4] = {tv[u].x, tv[u].y, tv[u].z, tv[u].w};
+        const uint32_t cs[4] = {cn[u].x, cn[u].y, cn[u].z, cn[u].w};
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+            const int e = (int)(4 * gr[u].blk) + qd;
+            const bool in = gr[u].valid && e >= gr[u].e0 && e < gr[u].e1;
+            const bool live = in && (ts[qd] == kAlwaysLive || cs[qd] < ts[qd]) && vs[qd] != gr[u].unode;
+            vv[u][qd] = vs[qd];
+            lv[u][qd] = live;
+            ex[u][qd] = live ? q.excl[(uint32_t)vs[qd] >> 5] : 0u;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+            if (!lv[u][qd]) continue;
+            const int32_t v = vv[u][qd];
+            if ((ex[u][qd] >> ((uint32_t)v & 31u)) & 1u) continue;  // seed or blocker
+            const int lid = st.claim(v, &sh.count);
+            if (lid >= 0) {
+                st.set_node(lid, v);
+                st.set_parent(lid, gr[u].ulid);
+            } else if (lid == -1) {
+                const int x = atomicAdd(&sh.n_extra, 1);
+                if (x < st.cap_x()) {
+                    st.xv[x] = v;
+                    st.set_xu(x, gr[u].ulid);
+                } else {
+                    sh.overflow = 1;
+                }
             } else {
                 sh.overflow = 1;
             }
-        } else {
-            sh.overflow = 1;
         }
     }
 }
+
+constexpr int kGroupsPerLane = 2;
 
 // Returns false when the store ran out of room.  On success writes the
 // world's pairs, size, id sum and scanned-slot count.
@@ -247,9 +282,19 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     __syncthreads();
 
     // ---- level 0: the seeds' slot groups from the per-query table
-    for (int j = t; j < q.n_seed_chunks; j += NT) {
-        const int4 d = q.seed_chunk[j];  // {blk, seed lid, e0, e1}
-        scan_slot_group<NT>(g, q, w, (uint32_t)d.x, d.y, -1, d.z, d.w, st, sh);
+    for (int j0 = t; j0 < q.n_seed_chunks; j0 += NT * kGroupsPerLane) {
+        SlotGroup gr[kGroupsPerLane];
+#pragma unroll
+        for (int u = 0; u < kGroupsPerLane; ++u) {
+            const int j = j0 + u * NT;
+            if (j < q.n_seed_chunks) {
+                const int4 d = q.seed_chunk[j];  // {blk, seed lid, e0, e1}
+                gr[u] = SlotGroup{(uint32_t)d.x, d.y, -1, d.z, d.w, true};
+            } else {
+                gr[u] = SlotGroup{0u, 0, -1, 0, 0, false};
+            }
+        }
+        scan_slot_groups<NT, kGroupsPerLane>(g, q, w, gr, st, sh);
     }
     __syncthreads();
     if (sh.overflow) return false;
@@ -281,15 +326,24 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
             sh.row_start[t] = start;
             __syncthreads();
             const int nrows = (f1 - base < NT) ? (f1 - base) : NT;
-            for (int j = t; j < total; j += NT) {
-                int lo = 0, hi = nrows - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (sh.row_start[mid] <= j) lo = mid; else hi = mid - 1;
+            for (int j0 = t; j0 < total; j0 += NT * kGroupsPerLane) {
+                SlotGroup gr[kGroupsPerLane];
+#pragma unroll
+                for (int u = 0; u < kGroupsPerLane; ++u) {
+                    const int j = j0 + u * NT;
+                    if (j < total) {
+                        int lo = 0, hi = nrows - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sh.row_start[mid] <= j) lo = mid; else hi = mid - 1;
+                        }
+                        gr[u] = SlotGroup{(uint32_t)(sh.row_e0[lo] >> 2) + (uint32_t)(j - sh.row_start[lo]),
+                                          sh.row_lid[lo], sh.row_node[lo], sh.row_e0[lo], sh.row_e1[lo], true};
+                    } else {
+                        gr[u] = SlotGroup{0u, 0, -1, 0, 0, false};
+                    }
                 }
-                const uint32_t blk = (uint32_t)(sh.row_e0[lo] >> 2) + (uint32_t)(j - sh.row_start[lo]);
-                scan_slot_group<NT>(g, q, w, blk, sh.row_lid[lo], sh.row_node[lo], sh.row_e0[lo], sh.row_e1[lo],
-                                    st, sh);
+                scan_slot_groups<NT, kGroupsPerLane>(g, q, w, gr, st, sh);
             }
             __syncthreads();
             if (sh.overflow) break;
@@ -388,9 +442,14 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
         // The stored list keeps the round-0 order; an entry whose count is 0
         // is a node no longer reached.  Blocking only removes nodes, so every
         // node reached now has a live entry: walking the live entries finds
-        // every count that changed, and each is updated in place.
+        // every count that changed; each is updated in place and the change
+        // written at the front of the world's own range of dl_*.
         const size_t so = (size_t)out.store_off[w];
-        const int list_len = out.store_len[w];
+        int list_len = out.store_len[w];
+        if (so + (size_t)list_len > out.store_cap || so + (size_t)list_len > out.dl_cap) {
+            if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            list_len = 0;  // uniform: every thread read the same values
+        }
         read_len = list_len;
         const int lane = t & 63;
         for (int base = 0; base < list_len; base += NT) {
@@ -409,45 +468,35 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
             }
             const unsigned long long mask = __ballot(d != 0);
             const int cnt = __popcll(mask);
-            unsigned long long wbase = 0;
-            if (lane == 0 && cnt) {
-                wbase = atomicAdd(&ctl->pair_count, (unsigned long long)cnt);
-                atomicAdd(&sh.ndelta, cnt);
-            }
+            int wbase = 0;
+            if (lane == 0 && cnt) wbase = atomicAdd(&sh.ndelta, cnt);
             wbase = __shfl(wbase, 0, 64);
             if (d != 0) {
-                const unsigned long long pos = wbase + __popcll(mask & ((1ull << lane) - 1ull));
-                if (pos < out.pair_cap) {
-                    out.pair_node[pos] = u;
-                    out.pair_cnt[pos] = d;
-                } else {
-                    atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
-                }
+                const size_t pos = so + (size_t)(wbase + __popcll(mask & ((1ull << lane) - 1ull)));
+                out.dl_node[pos] = u;
+                out.dl_cnt[pos] = d;
             }
         }
         __syncthreads();
+        if (t == 0) out.wlen[w] = sh.ndelta;
     } else {
-        const bool store = (out.mode == kModeStore);
         if (t == 0) {
-            sh.pair_base = atomicAdd(store ? &ctl->store_count : &ctl->pair_count, (unsigned long long)len);
-            if (store) atomicAdd(&ctl->pair_count, (unsigned long long)len);
+            sh.pair_base = (TIER == 0) ? (unsigned long long)wi * out.slot_cap0
+                                       : out.big_base + atomicAdd(&ctl->big_count, (unsigned long long)len);
         }
         __syncthreads();
-        const unsigned long long pb = sh.pair_base;
-        int32_t* dn = store ? out.store_node : out.pair_node;
-        int32_t* dc = store ? out.store_cnt : out.pair_cnt;
-        const unsigned long long cap = store ? out.store_cap : out.pair_cap;
-        if (pb + (unsigned long long)len <= cap) {
+        const unsigned long long off = sh.pair_base;
+        if (off + (unsigned long long)len <= out.scr_cap) {
             for (int i = t; i < len; i += NT) {
-                dn[pb + i] = st.node(ns + i);
-                dc[pb + i] = *st.aux_ptr(ns + i);
+                out.scr_node[off + i] = st.node(ns + i);
+                out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
             }
-            if (store && t == 0) {
-                out.store_off[w] = (int64_t)pb;
-                out.store_len[w] = len;
+            if (t == 0) {
+                out.wloc[wi] = (int64_t)off;
+                out.wlen[wi] = len;
             }
         } else if (t == 0) {
-            atomicOr(&ctl->flags, (uint32_t)(store ? kFlagStoreOverflow : kFlagPairOverflow));
+            atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);  // bump region full: the tile is redone
         }
     }
     long long s = 0;
@@ -462,7 +511,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
         if (out.mode == kModeDelta)
             bytes += 8ull * (unsigned long long)read_len + 12ull * (unsigned long long)sh.ndelta;
         else
-            bytes += 8ull * (unsigned long long)len;
+            bytes += 8ull * (unsigned long long)len + 12ull;
         // per-workgroup tallies, added to the device counters once at exit
         sh.acc_worlds += 1;
         sh.acc_edges += (unsigned long long)sh.edges;
@@ -475,12 +524,25 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
 // Tier 0 (one wave, small LDS store) and tier 1 (four waves, larger LDS
 // store).  With range_count > 0 the kernel takes worlds 0..range_count-1 of
 // the tile; otherwise it takes the list handed down by the previous tier.
-using Tier0Store = LdsStore<384, 10, 128, 30>;
+using Tier0Store = LdsStore<256, 9, 128, 30>;
 using Tier1Store = LdsStore<2048, 12, 1024, 254>;
 constexpr int kTier0NT = 64;
 constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
 
+// Per-workgroup work tallies, one slot per (tier, field, workgroup): no
+// shared counter is touched.
+__device__ __forceinline__ void add_work(const TileOut& out, int tier, unsigned long long worlds,
+                                         unsigned long long edges, unsigned long long bytes) {
+    if (!out.work || !worlds) return;
+    const size_t st = (size_t)out.work_stride;
+    unsigned long long* wk = out.work + (size_t)tier * 3 * st + blockIdx.x;
+    wk[0] += worlds;
+    wk[st] += edges;
+    wk[2 * st] += bytes;
+}
+
+// Worlds are dealt to workgroups by a fixed stride (no shared work counter).
 template <int NT, class Store, int TIER>
 __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
                                                   uint32_t range_count, const int32_t* in_list, int count_idx,
@@ -493,11 +555,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
     if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
     __syncthreads();
-    for (;;) {
-        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[TIER], 1u);
-        __syncthreads();
-        const uint32_t k = (uint32_t)sh.widx;
-        if (k >= n_items) break;
+    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<NT, TIER>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) {
@@ -507,11 +565,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         st.template reset<NT>(0);
         __syncthreads();
     }
-    if (t == 0 && sh.acc_worlds) {
-        atomicAdd(&ctl->work_worlds[TIER], sh.acc_worlds);
-        atomicAdd(&ctl->work_edges[TIER], sh.acc_edges);
-        atomicAdd(&ctl->work_bytes[TIER], sh.acc_bytes);
-    }
+    if (t == 0) add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
 }
 
 // Tier 2: per-world arrays in HBM, one slot per resident workgroup.
@@ -536,11 +590,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     if (ctl->stop) return;
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
     if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
-    for (;;) {
-        if (t == 0) sh.widx = (int)atomicAdd(&ctl->next[2], 1u);
-        __syncthreads();
-        const uint32_t k = (uint32_t)sh.widx;
-        if (k >= n_items) break;
+    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<kTier2NT, 2>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
@@ -548,12 +598,116 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
         st.reset<kTier2NT>(sh.count < g.n ? sh.count : g.n);
         __syncthreads();
     }
-    if (t == 0 && sh.acc_worlds) {
-        atomicAdd(&ctl->work_worlds[2], sh.acc_worlds);
-        atomicAdd(&ctl->work_edges[2], sh.acc_edges);
-        atomicAdd(&ctl->work_bytes[2], sh.acc_bytes);
+    if (t == 0) add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+}
+
+// ------------------------------------------------------------ compaction
+// Items are the tile's worlds [0, count) (entries at wloc/wlen in scratch) or,
+// in incremental rounds, the changed worlds of list[0 .. list_n[0]) (changes
+// at store_off[w] in dl_*, wlen[w] of them).  Each workgroup scans its
+// items' lengths, takes one range of the destination with one counter
+// update, and copies with one wave per item.
+constexpr int kCompactNT = 256;
+
+__global__ __launch_bounds__(kCompactNT) void k_sum_lengths(TileOut out, RoundCtl* ctl, uint32_t count,
+                                                            const int32_t* list) {
+    __shared__ long long tmp[kCompactNT / 64];
+    if (ctl->stop) return;
+    const uint32_t n_items = list ? ctl->list_n[0] : count;
+    long long s = 0;
+    for (uint32_t i = blockIdx.x * kCompactNT + threadIdx.x; i < n_items; i += gridDim.x * kCompactNT)
+        s += list ? out.wlen[list[i]] : out.wlen[i];
+    s = block_sum_ll<kCompactNT>(s, tmp);
+    if (threadIdx.x == 0 && s) atomicAdd(&ctl->tile_total, (unsigned long long)s);
+}
+
+__global__ __launch_bounds__(kCompactNT) void k_compact(TileOut out, RoundCtl* ctl, uint32_t w_begin, uint32_t count,
+                                                        const int32_t* list) {
+    __shared__ int tmp[kCompactNT / 64];
+    __shared__ unsigned long long base_sh;
+    __shared__ long long src_sh[kCompactNT];
+    __shared__ unsigned long long dst_sh[kCompactNT];
+    __shared__ int len_sh[kCompactNT];
+    if (ctl->stop) return;
+    const bool delta = (list != nullptr);
+    const bool store = (out.mode == kModeStore);
+    const uint32_t n_items = delta ? ctl->list_n[0] : count;
+    const int32_t* src_node = delta ? out.dl_node : out.scr_node;
+    const int32_t* src_cnt = delta ? out.dl_cnt : out.scr_cnt;
+    int32_t* dst_node = store ? out.store_node : out.pair_node;
+    int32_t* dst_cnt = store ? out.store_cnt : out.pair_cnt;
+    const unsigned long long cap = store ? out.store_cap : out.pair_cap;
+    unsigned long long* counter = store ? &ctl->store_count : &ctl->pair_count;
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    for (uint32_t b0 = blockIdx.x * kCompactNT; b0 < n_items; b0 += gridDim.x * kCompactNT) {
+        const uint32_t i = b0 + threadIdx.x;
+        int len = 0;
+        long long src = 0;
+        uint32_t w = 0;
+        if (i < n_items) {
+            if (delta) {
+                w = (uint32_t)list[i];
+                src = out.store_off[w];
+                len = out.wlen[w];
+            } else {
+                w = w_begin + i;
+                src = out.wloc[i];
+                len = out.wlen[i];
+            }
+            const unsigned long long src_cap = delta ? out.dl_cap : out.scr_cap;
+            if (len < 0 || src < 0 || (unsigned long long)src + (unsigned long long)len > src_cap) {
+                atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+                len = 0;
+            }
+        }
+        int tot;
+        const int ex = block_excl_scan<kCompactNT>(len, tmp, tot);
+        if (threadIdx.x == 0) {
+            base_sh = atomicAdd(counter, (unsigned long long)tot);
+            if (store) atomicAdd(&ctl->pair_count, (unsigned long long)tot);
+        }
+        __syncthreads();
+        const unsigned long long dst = base_sh + (unsigned long long)ex;
+        const bool fits = base_sh + (unsigned long long)tot <= cap;
+        if (i < n_items && store && fits) {
+            out.store_off[w] = (int64_t)dst;
+            out.store_len[w] = len;
+        }
+        src_sh[threadIdx.x] = src;
+        dst_sh[threadIdx.x] = dst;
+        len_sh[threadIdx.x] = (i < n_items) ? len : 0;
+        __syncthreads();
+        if (fits) {
+            for (int it = wid; it < kCompactNT; it += kCompactNT / 64) {
+                const int L = len_sh[it];
+                const long long sp = src_sh[it];
+                const unsigned long long dp = dst_sh[it];
+                for (int e = lane; e < L; e += 64) {
+                    dst_node[dp + e] = src_node[sp + e];
+                    dst_cnt[dp + e] = src_cnt[sp + e];
+                }
+            }
+        } else if (threadIdx.x == 0) {
+            atomicOr(&ctl->flags, (uint32_t)(store ? kFlagStoreOverflow : kFlagPairOverflow));
+        }
+        __syncthreads();
     }
 }
+
+hipError_t launch_sum_lengths(const TileOut& out, RoundCtl* ctl, uint32_t count, const int32_t* list,
+                              hipStream_t s) {
+    k_sum_lengths<<<128, kCompactNT, 0, s>>>(out, ctl, count, list);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const TileOut& out, RoundCtl* ctl, uint32_t w_begin, uint32_t count, const int32_t* list,
+                          hipStream_t s) {
+    k_compact<<<256, kCompactNT, 0, s>>>(out, ctl, w_begin, count, list);
+    return hipGetLastError();
+}
+
+int world_tier0_capacity() { return Tier0Store::kCapNonSeed; }
 
 int world_tier_blocks_per_cu(int tier) {
     size_t lds = 0;
@@ -623,7 +777,11 @@ __global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, co
         uint32_t base = 0;
         if (lane == 0 && cnt) base = atomicAdd(&ctl->list_n[0], (uint32_t)cnt);
         base = __shfl(base, 0, 64);
-        if (live) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = idx_world[k];
+        if (live) {
+            const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+            if (pos < out.list_cap) list[pos] = idx_world[k];
+            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+        }
     }
 }
 

@@ -100,6 +100,16 @@ def test_tiles_and_pair_overflow(B, oracle_mod, monkeypatch):
     _assert_same(got, want)
 
 
+def test_scratch_regrowth(B, oracle_mod, monkeypatch):
+    """A bump region far too small for the worlds that outgrow the fixed
+    slots is grown and the tile redone; the integers do not change."""
+    monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
+    monkeypatch.setenv("IMIN_START_TIER", "1")
+    g, seeds, _, _ = synth.workload("small")
+    got, want = _eval_both(B, oracle_mod, g, seeds, 0, 1500, 8)
+    _assert_same(got, want)
+
+
 @pytest.mark.parametrize("tier", ["0", "1", "2"])
 def test_every_start_tier_gives_the_same_integers(B, oracle_mod, monkeypatch, tier):
     """Worlds first tried on the LDS tiers or directly on the HBM tier."""
