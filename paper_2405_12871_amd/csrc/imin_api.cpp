@@ -450,7 +450,9 @@ struct Session {
         IMIN_TRY(imin::launch_compact(out, ctl.p, 0, 0, list0.p, s));
         IMIN_TRY(imin::launch_reduce_pairs(g, out, rb_delta, ctl.p, gain.p, s));
         timed.end(2, ev, s);
-        IMIN_TRY(imin::launch_sum_sizes(world_size.p, (uint32_t)theta, ctl.p, s));
+        // T is carried over from the last round and lowered by the changed
+        // worlds themselves: no pass over all theta sizes
+        (void)theta;
         return IMIN_OK;
     }
 
@@ -669,7 +671,6 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             // the selection stops, every later kernel returns at once
             const int32_t nb = (int32_t)std::min<size_t>(batch, (size_t)(k + 1 - r));
             for (int32_t i = 0; i < nb; ++i) {
-                IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
                 st = ss.evaluate_delta(q, (uint64_t)theta);
                 if (st != IMIN_OK) return st;
                 hipEvent_t ev = ss.timed.begin(s);

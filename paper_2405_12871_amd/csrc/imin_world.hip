@@ -47,7 +47,10 @@ struct WorldShared {
     unsigned long long pair_base;
     long long edges;  // CSR slots of reached rows
     int ndelta;       // count changes reported (incremental rounds)
+    int nlevels;      // BFS levels holding nodes
+    unsigned long long in_bytes;  // algorithmic bytes read by the BFS phase
     unsigned long long acc_worlds, acc_edges, acc_bytes;  // this workgroup's work so far
+    long long acc_dsize;  // reached nodes lost by this workgroup's worlds (incremental rounds)
     int row_lid[NT];
     int row_node[NT];
     int row_e0[NT];
@@ -133,6 +136,12 @@ struct LdsStore {
     __device__ int32_t* aux_ptr(int lid) { return &aux[lid - ns]; }
     __device__ int get_xu(int64_t x) const { return xu[x]; }
     __device__ void set_xu(int64_t x, int u) { xu[x] = (int16_t)u; }
+    __device__ int get_xv(int64_t x) const { return xv[x]; }
+    __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
+    // the extra edges' heads are node ids until resolved to local ids
+    __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
+    // local id now of the node of stored entry i (incremental rounds)
+    __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
     template <int NT>
     __device__ void reset(int /*count*/) { clear<NT>(); }
 };
@@ -180,6 +189,10 @@ struct HbmStore {
     __device__ int32_t* aux_ptr(int lid) { return &aux[lid]; }
     __device__ int get_xu(int64_t x) const { return xu_[x]; }
     __device__ void set_xu(int64_t x, int u) { xu_[x] = u; }
+    __device__ int get_xv(int64_t x) const { return xv[x]; }
+    __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
+    __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
+    __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
     template <int NT>
     __device__ void reset(int count) {
         for (int i = threadIdx.x; i < count; i += NT) lid_of[nodes[i]] = -1;
@@ -260,11 +273,10 @@ __device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryD
 
 constexpr int kGroupsPerLane = 2;
 
-// Returns false when the store ran out of room.  On success writes the
-// world's pairs, size, id sum and scanned-slot count.
-template <int NT, int TIER, class Store>
-__device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
-                               const TileOut& out, Store& st, WorldShared<NT>& sh) {
+// Phase 1 of a world evaluation by sampling: the BFS with coins.  Returns
+// false when the store ran out of room (uniform over the workgroup).
+template <int NT, class Store>
+__device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, Store& st, WorldShared<NT>& sh) {
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     if (!st.fits(ns)) return false;  // uniform
@@ -359,12 +371,28 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     }
     __syncthreads();
     if (sh.overflow) return false;
-    const int nlevels = nlev - 1;  // levels 0..nlevels-1 hold nodes
+    if (t == 0) {
+        sh.nlevels = nlev - 1;  // levels 0..nlevels-1 hold nodes
+        sh.in_bytes = 8ull * (unsigned long long)sh.edges + 8ull * (unsigned long long)(sh.count - ns) +
+                      16ull * (unsigned long long)q.n_seed_chunks;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Phase 2, shared by sampling and replay: immediate dominators, subtree
+// sizes and the outputs of the mode.
+template <int NT, int TIER, class Store>
+__device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi, const TileOut& out,
+                             Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    const int nlevels = sh.nlevels;
     const int R = sh.count;
     const int nx = sh.n_extra;
 
     // ---- dominators
-    for (int x = t; x < nx; x += NT) st.xv[x] = st.lookup(st.xv[x]);
+    for (int x = t; x < nx; x += NT) st.resolve_xv(x);
     for (int i = ns + t; i < R; i += NT) {
         const int p = st.get_parent(i);
         st.set_idom(i, p);
@@ -373,7 +401,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     if (t == 0) sh.nonfwd = 0;
     __syncthreads();
     for (int x = t; x < nx; x += NT) {
-        const int v = st.xv[x];
+        const int v = st.get_xv(x);
         const int u = st.get_xu(x);
         int lo = 0, hi = nlevels - 1;
         while (lo < hi) {
@@ -397,7 +425,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
             for (int L = 1; L < nlevels; ++L) {
                 const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
                 for (int x = t; x < nx; x += NT) {
-                    const int v = st.xv[x];
+                    const int v = st.get_xv(x);
                     if (v < v0 || v >= v1) continue;
                     int a = st.get_parent(v);
                     int b = st.get_xu(x);
@@ -408,7 +436,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
                 }
                 __syncthreads();
                 for (int x = t; x < nx; x += NT) {
-                    const int v = st.xv[x];
+                    const int v = st.get_xv(x);
                     if (v < v0 || v >= v1) continue;
                     const int nv = *st.aux_ptr(v);
                     if (nv != st.get_idom(v)) {
@@ -460,7 +488,7 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
                 const int c_old = out.store_cnt[so + i];
                 if (c_old > 0) {
                     u = out.store_node[so + i];
-                    const int lid = st.lookup(u);
+                    const int lid = st.delta_lid(i, u);
                     const int c_new = (lid >= ns) ? *st.aux_ptr(lid) : 0;
                     d = c_new - c_old;
                     if (d != 0) out.store_cnt[so + i] = c_new;
@@ -500,14 +528,16 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
         }
     }
     long long s = 0;
-    for (int i = ns + t; i < R; i += NT) s += st.node(i);
-    s = block_sum_ll<NT>(s, sh.sum_tmp);
+    if (out.world_sum) {  // uniform
+        for (int i = ns + t; i < R; i += NT) s += st.node(i);
+        s = block_sum_ll<NT>(s, sh.sum_tmp);
+    }
     if (t == 0) {
+        if (out.mode == kModeDelta) sh.acc_dsize += (long long)out.world_size[wi] - (long long)R;
         if (out.world_size) out.world_size[wi] = R;
         if (out.world_sum) out.world_sum[wi] = s + q.seed_sum;
         if (out.world_edges) out.world_edges[wi] = sh.edges;
-        unsigned long long bytes = 8ull * (unsigned long long)sh.edges + 8ull * (unsigned long long)(R - ns) +
-                                   16ull * (unsigned long long)q.n_seed_chunks;
+        unsigned long long bytes = sh.in_bytes;
         if (out.mode == kModeDelta)
             bytes += 8ull * (unsigned long long)read_len + 12ull * (unsigned long long)sh.ndelta;
         else
@@ -517,6 +547,14 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
         sh.acc_edges += (unsigned long long)sh.edges;
         sh.acc_bytes += bytes;
     }
+}
+
+// A world evaluated by sampling: false when the store ran out of room.
+template <int NT, int TIER, class Store>
+__device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
+                               const TileOut& out, Store& st, WorldShared<NT>& sh) {
+    if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
+    finish_world<NT, TIER>(q, ctl, w, wi, out, st, sh);
     return true;
 }
 
@@ -551,9 +589,13 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
     if (ctl->stop) return;
-    st.template clear<NT>();
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
-    if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+    if (blockIdx.x >= n_items) return;  // no world for this workgroup
+    st.template clear<NT>();
+    if (t == 0) {
+        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_dsize = 0;
+    }
     __syncthreads();
     for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
@@ -565,7 +607,11 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         st.template reset<NT>(0);
         __syncthreads();
     }
-    if (t == 0) add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+    if (t == 0) {
+        add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+        // incremental rounds keep T up to date: subtract the nodes lost
+        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+    }
 }
 
 // Tier 2: per-world arrays in HBM, one slot per resident workgroup.
@@ -589,7 +635,11 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     st.cap_x_ = bs.xcap;
     if (ctl->stop) return;
     const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
-    if (t == 0) sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+    if (blockIdx.x >= n_items) return;  // no world for this workgroup
+    if (t == 0) {
+        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_dsize = 0;
+    }
     for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<kTier2NT, 2>(g, q, ctl, w_begin + wi, wi, out, st, sh);
@@ -598,7 +648,10 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
         st.reset<kTier2NT>(sh.count < g.n ? sh.count : g.n);
         __syncthreads();
     }
-    if (t == 0) add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+    if (t == 0) {
+        add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+    }
 }
 
 // ------------------------------------------------------------ compaction
