@@ -150,6 +150,8 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
  *   5  search for the worlds a new blocker changes (incremental rounds)
+ *   6  replay of a changed world from its stored live edges (incremental
+ *      rounds; worlds too large for it go on to kernels 4 and 1)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */
@@ -159,12 +161,17 @@ imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_m
 
 /*
  * Work done while timing was enabled, per world tier (0 small LDS, 1 large
- * LDS, 2 HBM): worlds finished, CSR slots of their reached rows (the edges
- * whose coins were needed), and algorithmic HBM bytes = 8 per such slot
- * (column and threshold) + 8 per reached non-seed (row offsets) + 16 per
- * level-0 table entry + 8 per (node, count) entry written, plus, in
- * incremental rounds, 8 per stored entry read back and per change reported.
- * Host pointers; any may be NULL.
+ * LDS, 2 HBM, 3 replay): worlds finished, edges walked and algorithmic HBM
+ * bytes.  For tiers 0-2 the edges are the CSR slots of the reached rows (the
+ * edges whose coins were needed) and the bytes are 8 per such slot (column
+ * and threshold) + 8 per reached non-seed (row offsets) + 16 per level-0
+ * table entry + 8 per (node, count) entry written (12 with its BFS parent
+ * kept for replay, + 8 per extra live edge kept).  For the replay tier the
+ * edges are the stored live edges and the bytes are 12 per stored entry
+ * (node, count, parent) + 8 per stored extra edge.  Incremental rounds add,
+ * for every tier, 8 per stored entry read back and 12 per change reported
+ * (the change and the count updated in place).  Host pointers; any may be
+ * NULL.
  */
 imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes);
 

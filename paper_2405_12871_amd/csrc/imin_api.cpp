@@ -22,15 +22,16 @@ namespace {
 thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
-constexpr int kTimedKernels = 6;
+constexpr int kTimedKernels = 7;
+constexpr int kWorkTiers = 4;  // tiers 0-2 and replay
 struct Timing {
     std::atomic<bool> on{false};
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
     double ms[kTimedKernels] = {};
-    int64_t work_worlds[3] = {};
-    int64_t work_edges[3] = {};
-    int64_t work_bytes[3] = {};
+    int64_t work_worlds[kWorkTiers] = {};
+    int64_t work_edges[kWorkTiers] = {};
+    int64_t work_bytes[kWorkTiers] = {};
 };
 Timing g_timing;
 
@@ -176,6 +177,15 @@ struct Session {
     // resident per-world (node, count) lists for incremental rounds
     DevArray<int32_t> store_node, store_cnt, store_len, dl_node, dl_cnt;
     DevArray<int64_t> store_off;
+    // replay of changed worlds from their stored live edges: BFS parents
+    // beside the pairs, extra edges (local ids) in a store of their own
+    bool replay = false;
+    DevArray<int32_t> scr_par, xscr_v, xscr_u, xlen;
+    DevArray<int64_t> xloc;
+    size_t xslot_cap0 = 0, xbig_cap = 0;
+    DevArray<int32_t> store_par, xstore_v, xstore_u, xstore_len;
+    DevArray<int64_t> xstore_off;
+    int grid_r = 0;
     bool incremental = false;
     size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
@@ -217,8 +227,10 @@ struct Session {
         IMIN_TRY(wloc.alloc(tile_cap));
         // incremental rounds index change counts by world id
         IMIN_TRY(wlen.alloc(solve ? std::max<size_t>(tile_cap, theta) : tile_cap));
-        IMIN_TRY(list1.alloc(tile_cap));
-        IMIN_TRY(list2.alloc(tile_cap));
+        // incremental rounds hand down changed worlds of the whole theta
+        const size_t next_n = solve ? std::max<size_t>(tile_cap, theta) : tile_cap;
+        IMIN_TRY(list1.alloc(next_n));
+        IMIN_TRY(list2.alloc(next_n));
         IMIN_TRY(list0.alloc(1));
         slot_cap0 = (size_t)imin::world_tier0_capacity();
         big_cap = env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20);
@@ -274,11 +286,13 @@ struct Session {
         IMIN_TRY(sel_u.alloc(sel_parts));
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
+        grid_r = cus * imin::world_replay_blocks_per_cu();
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
-            work_stride = std::max(std::max(grid0, grid1), bs.n_slots);
-            IMIN_TRY(work.alloc((size_t)9 * work_stride));
-            IMIN_TRY(hipMemsetAsync(work.p, 0, (size_t)9 * work_stride * sizeof(unsigned long long), s));
+            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r), bs.n_slots);
+            const size_t wn = (size_t)3 * kWorkTiers * work_stride;
+            IMIN_TRY(work.alloc(wn));
+            IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));
         }
         return IMIN_OK;
     }
@@ -288,12 +302,12 @@ struct Session {
     void finish() {
         if (!timed.on) return;
         timed.flush();
-        std::vector<unsigned long long> h((size_t)9 * work_stride);
+        std::vector<unsigned long long> h((size_t)3 * kWorkTiers * work_stride);
         if (work.p && hipMemcpy(h.data(), work.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
                           hipSuccess)
             return;
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        for (int tier = 0; tier < 3; ++tier) {
+        for (int tier = 0; tier < kWorkTiers; ++tier) {
             int64_t f[3] = {0, 0, 0};
             for (int field = 0; field < 3; ++field)
                 for (int b = 0; b < work_stride; ++b) f[field] += (int64_t)h[((size_t)tier * 3 + field) * work_stride + b];
@@ -341,31 +355,74 @@ struct Session {
             return IMIN_OK;  // plain rounds give the same integers
         }
         incremental = true;
+        const char* rp = std::getenv("IMIN_REPLAY");
+        if (!(rp && rp[0] == '0')) {
+            xslot_cap0 = (size_t)imin::world_tier0_xcapacity();
+            xbig_cap = env_size("IMIN_XBIG_SCRATCH", (size_t)1 << 20);
+            const size_t xn = tile_cap * xslot_cap0 + xbig_cap;
+            replay = scr_par.alloc(scr_node.count) == hipSuccess && xscr_v.alloc(xn) == hipSuccess &&
+                     xscr_u.alloc(xn) == hipSuccess && xloc.alloc(tile_cap) == hipSuccess &&
+                     xlen.alloc(tile_cap) == hipSuccess && xstore_off.alloc(theta) == hipSuccess &&
+                     xstore_len.alloc(theta) == hipSuccess;
+            if (!replay) drop_replay();
+        }
         return IMIN_OK;
     }
 
-    // room for `more` entries after the store's `used` ones; false when the
-    // budget or the device memory is exhausted
-    bool ensure_store(unsigned long long used, unsigned long long more) {
-        const unsigned long long need = used + more;
-        if (need > store_budget) return false;
-        if (store_node.p && store_node.count >= need) return true;
-        const size_t want = (size_t)std::min<unsigned long long>(store_budget, need + need / 4 + 1024);
-        DevArray<int32_t> nn, nc;
-        if (nn.alloc(want) != hipSuccess || nc.alloc(want) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        if (used) {
-            if (hipMemcpyAsync(nn.p, store_node.p, used * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                hipMemcpyAsync(nc.p, store_cnt.p, used * sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    // replay off for the rest of the solve: its buffers are released
+    void drop_replay() {
+        replay = false;
+        scr_par.release();
+        xscr_v.release();
+        xscr_u.release();
+        xloc.release();
+        xlen.release();
+        store_par.release();
+        xstore_v.release();
+        xstore_u.release();
+        xstore_off.release();
+        xstore_len.release();
+        (void)hipGetLastError();
+    }
+
+    // grow the arrays of a store to hold `need` entries, keeping the first
+    // `used`; false when the budget or the device memory is exhausted
+    template <size_t N>
+    bool grow_store(DevArray<int32_t>* (&arrs)[N], unsigned long long used, unsigned long long need,
+                    unsigned long long budget) {
+        if (need > budget) return false;
+        if (arrs[0]->p && arrs[0]->count >= need) return true;
+        const size_t want = (size_t)std::min<unsigned long long>(budget, need + need / 4 + 1024);
+        DevArray<int32_t> fresh[N];
+        for (size_t i = 0; i < N; ++i) {
+            if (fresh[i].alloc(want) != hipSuccess) {
+                (void)hipGetLastError();
+                return false;
+            }
+            if (used && hipMemcpyAsync(fresh[i].p, arrs[i]->p, used * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                       s) != hipSuccess)
                 return false;
         }
-        std::swap(store_node.p, nn.p);
-        std::swap(store_node.count, nn.count);
-        std::swap(store_cnt.p, nc.p);
-        std::swap(store_cnt.count, nc.count);
+        for (size_t i = 0; i < N; ++i) {
+            std::swap(arrs[i]->p, fresh[i].p);
+            std::swap(arrs[i]->count, fresh[i].count);
+        }
         return hipStreamSynchronize(s) == hipSuccess;  // old arrays are freed on return
+    }
+
+    // room for `more` entries after the store's `used` ones
+    bool ensure_store(unsigned long long used, unsigned long long more) {
+        if (replay) {
+            DevArray<int32_t>* arrs[3] = {&store_node, &store_cnt, &store_par};
+            return grow_store(arrs, used, used + more, store_budget);
+        }
+        DevArray<int32_t>* arrs[2] = {&store_node, &store_cnt};
+        return grow_store(arrs, used, used + more, store_budget);
+    }
+
+    bool ensure_xstore(unsigned long long used, unsigned long long more) {
+        DevArray<int32_t>* arrs[2] = {&xstore_v, &xstore_u};
+        return grow_store(arrs, used, used + more, store_budget);
     }
 
     // node -> (store position, world) of every entry written in round 0;
@@ -413,17 +470,34 @@ struct Session {
         out.dl_cnt = dl_cnt.p;
         out.dl_cap = dl_node.count;
         out.list_cap = (uint32_t)std::min<size_t>(list0.count, 0xFFFFFFFFu);
+        out.next_cap = (uint32_t)std::min<size_t>(std::min(list1.count, list2.count), 0xFFFFFFFFu);
+        out.scr_par = scr_par.p;
+        out.store_par = store_par.p;
+        out.xscr_v = xscr_v.p;
+        out.xscr_u = xscr_u.p;
+        out.xslot_cap0 = xslot_cap0;
+        out.xbig_base = tile_cap * xslot_cap0;
+        out.xscr_cap = xscr_v.count;
+        out.xloc = xloc.p;
+        out.xlen = xlen.p;
+        out.xstore_v = xstore_v.p;
+        out.xstore_u = xstore_u.p;
+        out.xstore_cap = xstore_v.count;
+        out.xstore_off = xstore_off.p;
+        out.xstore_len = xstore_len.p;
         out.work = work.p;
         out.work_stride = work_stride;
         return out;
     }
 
+    // Tiers first_tier..2; the first reads first_list (count list_n[first_idx])
+    // or, without a list, worlds [wb, wb+range).
     imin_status_t launch_tiers(const imin::QueryDev& q, uint32_t wb, uint32_t range, const int32_t* first_list,
-                               const imin::TileOut& out) {
-        for (int tier = start_tier; tier < 3; ++tier) {
-            const bool first = (tier == start_tier);
+                               const imin::TileOut& out, int first_tier, int first_idx = 0) {
+        for (int tier = first_tier; tier < 3; ++tier) {
+            const bool first = (tier == first_tier);
             const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : list2.p);
-            const int count_idx = first ? 0 : tier;
+            const int count_idx = first ? first_idx : tier;
             int32_t* next_list = tier == 0 ? list1.p : list2.p;
             const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
             hipEvent_t ev = timed.begin(s);
@@ -444,10 +518,34 @@ struct Session {
         hipEvent_t ev = timed.begin(s);
         IMIN_TRY(imin::launch_affected(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, s));
         timed.end(5, ev, s);
-        imin_status_t st = launch_tiers(q, 0, 0, list0.p, out);
+        imin_status_t st;
+        if (replay) {
+            // replay every changed world; those too large go on to sampling
+            ev = timed.begin(s);
+            IMIN_TRY(imin::launch_world_replay(q, ctl.p, list0.p, list1.p, out, grid_r, s));
+            timed.end(6, ev, s);
+            st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1);
+        } else {
+            st = launch_tiers(q, 0, 0, list0.p, out, start_tier);
+        }
         if (st != IMIN_OK) return st;
         ev = timed.begin(s);
-        IMIN_TRY(imin::launch_compact(out, ctl.p, 0, 0, list0.p, s));
+        imin::CompactSpec cs{};
+        cs.src[0] = dl_node.p;
+        cs.src[1] = dl_cnt.p;
+        cs.dst[0] = pair_node.p;
+        cs.dst[1] = pair_cnt.p;
+        cs.nf = 2;
+        cs.src_cap = dl_node.count;
+        cs.dst_cap = pair_node.count;
+        cs.loc = store_off.p;
+        cs.len = wlen.p;
+        cs.by_world = 1;
+        cs.list = list0.p;
+        cs.count = out.list_cap;
+        cs.counter_id = 0;
+        cs.overflow_flag = imin::kFlagPairOverflow;
+        IMIN_TRY(imin::launch_compact(cs, ctl.p, s));
         IMIN_TRY(imin::launch_reduce_pairs(g, out, rb_delta, ctl.p, gain.p, s));
         timed.end(2, ev, s);
         // T is carried over from the last round and lowered by the changed
@@ -465,14 +563,17 @@ struct Session {
         uint64_t done = 0;
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
+            const bool keep = store_mode && incremental && replay;
             imin::TileOut out = tile_out();
             out.world_size = ws_out ? ws_out + done : world_size.p;
             out.world_sum = wsum_out ? wsum_out + done : nullptr;
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
+            out.keep_edges = keep ? 1 : 0;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            imin_status_t st = launch_tiers(q, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, out);
+            imin_status_t st = launch_tiers(q, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, out, start_tier);
             if (st != IMIN_OK) return st;
-            IMIN_TRY(imin::launch_sum_lengths(out, ctl.p, (uint32_t)nw, nullptr, s));
+            IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)nw, &ctl.p->tile_total, ctl.p, s));
+            if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)nw, &ctl.p->xtile_total, ctl.p, s));
             st = read_ctl();
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
@@ -484,12 +585,19 @@ struct Session {
                 return IMIN_ERR_INTERNAL;
             }
             if (f & imin::kFlagPairOverflow) {
-                // the scratch bump region was too small: grow it, redo the tile
+                // a scratch bump region was too small: grow it, redo the tile
                 st = clear_flag(imin::kFlagPairOverflow);
                 if (st != IMIN_OK) return st;
-                big_cap = (size_t)hctl.p->big_count + hctl.p->big_count / 8 + 1024;
+                const unsigned long long bc = hctl.p->big_count, xc = hctl.p->xbig_count;
+                big_cap = std::max<size_t>(big_cap, (size_t)(bc + bc / 8 + 1024));
                 IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
                 IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
+                if (keep) {
+                    xbig_cap = std::max<size_t>(xbig_cap, (size_t)(xc + xc / 8 + 1024));
+                    IMIN_TRY(scr_par.alloc(scr_node.count));
+                    IMIN_TRY(xscr_v.alloc(tile_cap * xslot_cap0 + xbig_cap));
+                    IMIN_TRY(xscr_u.alloc(tile_cap * xslot_cap0 + xbig_cap));
+                }
                 continue;
             }
             // dense destination for the tile's entries
@@ -499,22 +607,66 @@ struct Session {
             if (use_store && !ensure_store(store_base, total)) {
                 incremental = false;  // the store does not fit: plain rounds from here on
                 use_store = false;
+                drop_replay();
+            }
+            bool use_x = keep && use_store;
+            if (use_x && !ensure_xstore(hctl.p->xstore_count, hctl.p->xtile_total)) {
+                drop_replay();  // incremental rounds go on by sampling
+                use_x = false;
             }
             // the reduction's sorted copy needs room for every entry of the
             // tile whichever buffer holds them
             st = ensure_pairs(total);
             if (st != IMIN_OK) return st;
-            out = [&] {
-                imin::TileOut o = tile_out();
-                o.world_size = out.world_size;
-                o.world_sum = out.world_sum;
-                o.world_edges = out.world_edges;
-                o.mode = use_store ? imin::kModeStore : imin::kModePlain;
-                return o;
-            }();
             hipEvent_t ev = timed.begin(s);
-            IMIN_TRY(imin::launch_compact(out, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, s));
-            imin::TileOut red = out;
+            imin::CompactSpec cs{};
+            cs.src[0] = scr_node.p;
+            cs.src[1] = scr_cnt.p;
+            cs.src[2] = scr_par.p;
+            cs.nf = 2;
+            cs.src_cap = scr_node.count;
+            cs.loc = wloc.p;
+            cs.len = wlen.p;
+            cs.count = (uint32_t)nw;
+            cs.w_begin = (uint32_t)(w_begin + done);
+            if (use_store) {
+                cs.dst[0] = store_node.p;
+                cs.dst[1] = store_cnt.p;
+                cs.dst[2] = store_par.p;
+                if (use_x) cs.nf = 3;
+                cs.dst_cap = store_node.count;
+                cs.counter_id = 1;
+                cs.out_off = store_off.p;
+                cs.out_len = store_len.p;
+                cs.overflow_flag = imin::kFlagStoreOverflow;
+            } else {
+                cs.dst[0] = pair_node.p;
+                cs.dst[1] = pair_cnt.p;
+                cs.dst_cap = pair_node.count;
+                cs.counter_id = 0;
+                cs.overflow_flag = imin::kFlagPairOverflow;
+            }
+            IMIN_TRY(imin::launch_compact(cs, ctl.p, s));
+            if (use_x) {
+                imin::CompactSpec xs{};
+                xs.src[0] = xscr_v.p;
+                xs.src[1] = xscr_u.p;
+                xs.dst[0] = xstore_v.p;
+                xs.dst[1] = xstore_u.p;
+                xs.nf = 2;
+                xs.src_cap = xscr_v.count;
+                xs.dst_cap = xstore_v.count;
+                xs.loc = xloc.p;
+                xs.len = xlen.p;
+                xs.count = (uint32_t)nw;
+                xs.w_begin = (uint32_t)(w_begin + done);
+                xs.counter_id = 2;
+                xs.out_off = xstore_off.p;
+                xs.out_len = xstore_len.p;
+                xs.overflow_flag = imin::kFlagStoreOverflow;
+                IMIN_TRY(imin::launch_compact(xs, ctl.p, s));
+            }
+            imin::TileOut red = tile_out();
             if (use_store) {
                 // this tile's entries sit contiguously in the store
                 red.pair_node = store_node.p + store_base;
@@ -740,12 +892,12 @@ imin_status_t imin_timing_reset(void) {
         g_timing.launches[i] = 0;
         g_timing.ms[i] = 0.0;
     }
-    for (int i = 0; i < 3; ++i) g_timing.work_worlds[i] = g_timing.work_edges[i] = g_timing.work_bytes[i] = 0;
+    for (int i = 0; i < kWorkTiers; ++i) g_timing.work_worlds[i] = g_timing.work_edges[i] = g_timing.work_bytes[i] = 0;
     return IMIN_OK;
 }
 
 imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes) {
-    if (tier < 0 || tier > 2) return IMIN_ERR_INVALID;
+    if (tier < 0 || tier >= kWorkTiers) return IMIN_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g_timing.mu);
     if (worlds) *worlds = g_timing.work_worlds[tier];
     if (edges) *edges = g_timing.work_edges[tier];

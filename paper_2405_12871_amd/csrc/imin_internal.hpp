@@ -59,6 +59,9 @@ struct RoundCtl {
     unsigned long long store_count;  // pairs held by the resident per-world store
     unsigned long long big_count;    // entries bump-allocated by tier-1/2 worlds this tile
     unsigned long long tile_total;   // entries the tile's worlds wrote (sum of lengths)
+    unsigned long long xbig_count;   // extra edges bump-allocated this tile
+    unsigned long long xtile_total;  // extra edges the tile's worlds wrote
+    unsigned long long xstore_count; // extra edges held for replay
 };
 
 // How a world evaluation reports its counts.
@@ -115,11 +118,50 @@ struct TileOut {
     int32_t* dl_cnt;
     unsigned long long dl_cap;
     uint32_t list_cap;   // entries of the changed-world list
+    uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
     unsigned long long* work;  // [3 tiers][3 fields][work_stride] per-workgroup tallies
     int work_stride;
+    // Live edges kept for replay (solve only).  In round 0 each world also
+    // writes, aligned with its entries, the BFS parent of each node, and its
+    // extra live edges (v, u); all as local ids of that round-0 evaluation.
+    int keep_edges;
+    int32_t* scr_par;     // aligned with scr_node
+    int32_t* store_par;   // aligned with store_node
+    int32_t* xscr_v;      // extra-edge scratch: fixed tier-0 slots, then a bump region
+    int32_t* xscr_u;
+    unsigned long long xslot_cap0;
+    unsigned long long xbig_base;
+    unsigned long long xscr_cap;
+    int64_t* xloc;        // [tile]
+    int32_t* xlen;        // [tile]
+    int32_t* xstore_v;
+    int32_t* xstore_u;
+    unsigned long long xstore_cap;
+    int64_t* xstore_off;  // [theta]
+    int32_t* xstore_len;  // [theta]
+};
+
+// A compaction job: per-item ranges of up to three int32 fields are packed
+// densely into the destination, one counter update per workgroup.
+struct CompactSpec {
+    const int32_t* src[3];
+    int32_t* dst[3];
+    int nf;
+    unsigned long long src_cap;
+    unsigned long long dst_cap;
+    const int64_t* loc;       // source start per item (per world id when by_world)
+    const int32_t* len;       // entries per item (per world id when by_world)
+    int by_world;
+    const int32_t* list;      // items = list[0 .. ctl->list_n[0]) when set, else 0 .. count-1
+    uint32_t count;           // items, or the list's capacity when a list is set
+    uint32_t w_begin;
+    int counter_id;           // 0: pair_count, 1: store_count (+ pair_count), 2: xstore_count
+    int64_t* out_off;         // per world id: where its entries went (optional)
+    int32_t* out_len;
+    uint32_t overflow_flag;
 };
 
 struct QueryDev {
@@ -161,10 +203,12 @@ hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
-hipError_t launch_sum_lengths(const TileOut& out, RoundCtl* ctl, uint32_t count, const int32_t* list,
+hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s);
-hipError_t launch_compact(const TileOut& out, RoundCtl* ctl, uint32_t w_begin, uint32_t count, const int32_t* list,
-                          hipStream_t s);
+hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
+hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, const int32_t* in_list, int32_t* next_list,
+                               const TileOut& out, int grid, hipStream_t s);
+int world_replay_blocks_per_cu();
 hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
@@ -176,7 +220,8 @@ hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
                             int4* table, hipStream_t s);
 int world_tier_blocks_per_cu(int tier);
-int world_tier0_capacity();  // non-seed nodes a tier-0 world may reach
+int world_tier0_capacity();   // non-seed nodes a tier-0 world may reach
+int world_tier0_xcapacity();  // extra live edges a tier-0 world may record
 hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
                                RoundCtl* ctl, int64_t* gain, hipStream_t s);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);

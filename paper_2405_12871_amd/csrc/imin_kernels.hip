@@ -148,6 +148,8 @@ __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
     ctl->pair_count = 0;
     ctl->big_count = 0;
     ctl->tile_total = 0;
+    ctl->xbig_count = 0;
+    ctl->xtile_total = 0;
 }
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_round<<<1, 1, 0, s>>>(ctl);

@@ -45,6 +45,7 @@ struct WorldShared {
     int changed;
     int nonfwd;   // some extra edge does not go exactly one level down
     unsigned long long pair_base;
+    unsigned long long x_base;
     long long edges;  // CSR slots of reached rows
     int ndelta;       // count changes reported (incremental rounds)
     int nlevels;      // BFS levels holding nodes
@@ -68,6 +69,7 @@ template <int CAPNS, int HBITS, int XCAP, int LVCAP>
 struct LdsStore {
     static constexpr int kHash = 1 << HBITS;
     static constexpr int kCapNonSeed = CAPNS;
+    static constexpr int kCapX = XCAP;
     static constexpr int kMaxSeeds = 32767 - CAPNS;  // local ids fit int16
     int32_t keys[kHash];
     int16_t vals[kHash];
@@ -518,6 +520,7 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
             for (int i = t; i < len; i += NT) {
                 out.scr_node[off + i] = st.node(ns + i);
                 out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
+                if (out.keep_edges) out.scr_par[off + i] = st.get_parent(ns + i);
             }
             if (t == 0) {
                 out.wloc[wi] = (int64_t)off;
@@ -525,6 +528,27 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
             }
         } else if (t == 0) {
             atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);  // bump region full: the tile is redone
+        }
+        if (out.keep_edges) {
+            // the extra live edges, as local ids, for later replays
+            if (t == 0) {
+                sh.x_base = (TIER == 0) ? (unsigned long long)wi * out.xslot_cap0
+                                        : out.xbig_base + atomicAdd(&ctl->xbig_count, (unsigned long long)nx);
+            }
+            __syncthreads();
+            const unsigned long long xo = sh.x_base;
+            if (xo + (unsigned long long)nx <= out.xscr_cap) {
+                for (int x = t; x < nx; x += NT) {
+                    out.xscr_v[xo + x] = st.get_xv(x);
+                    out.xscr_u[xo + x] = st.get_xu(x);
+                }
+                if (t == 0) {
+                    out.xloc[wi] = (int64_t)xo;
+                    out.xlen[wi] = nx;
+                }
+            } else if (t == 0) {
+                atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);
+            }
         }
     }
     long long s = 0;
@@ -541,7 +565,8 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
         if (out.mode == kModeDelta)
             bytes += 8ull * (unsigned long long)read_len + 12ull * (unsigned long long)sh.ndelta;
         else
-            bytes += 8ull * (unsigned long long)len + 12ull;
+            bytes += (out.keep_edges ? 12ull : 8ull) * (unsigned long long)len + 12ull +
+                     (out.keep_edges ? 8ull * (unsigned long long)nx + 12ull : 0ull);
         // per-workgroup tallies, added to the device counters once at exit
         sh.acc_worlds += 1;
         sh.acc_edges += (unsigned long long)sh.edges;
@@ -589,7 +614,8 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
     if (ctl->stop) return;
-    const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
+    const uint32_t n_items = in_list ? min(ctl->list_n[count_idx], count_idx ? out.next_cap : out.list_cap)
+                                     : range_count;
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
     st.template clear<NT>();
     if (t == 0) {
@@ -602,7 +628,8 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         const bool ok = evaluate_world<NT, TIER>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) {
             const uint32_t pos = atomicAdd(&ctl->list_n[TIER + 1], 1u);
-            next_list[pos] = (int32_t)wi;
+            if (pos < out.next_cap) next_list[pos] = (int32_t)wi;
+            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         }
         st.template reset<NT>(0);
         __syncthreads();
@@ -634,7 +661,8 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     st.cap_lv_ = g.n + 1;
     st.cap_x_ = bs.xcap;
     if (ctl->stop) return;
-    const uint32_t n_items = in_list ? ctl->list_n[count_idx] : range_count;
+    const uint32_t n_items = in_list ? min(ctl->list_n[count_idx], count_idx ? out.next_cap : out.list_cap)
+                                     : range_count;
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
     if (t == 0) {
         sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
@@ -662,35 +690,26 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
 // update, and copies with one wave per item.
 constexpr int kCompactNT = 256;
 
-__global__ __launch_bounds__(kCompactNT) void k_sum_lengths(TileOut out, RoundCtl* ctl, uint32_t count,
-                                                            const int32_t* list) {
+__global__ __launch_bounds__(kCompactNT) void k_sum_lengths(const int32_t* len, uint32_t count,
+                                                            unsigned long long* total, RoundCtl* ctl) {
     __shared__ long long tmp[kCompactNT / 64];
     if (ctl->stop) return;
-    const uint32_t n_items = list ? ctl->list_n[0] : count;
     long long s = 0;
-    for (uint32_t i = blockIdx.x * kCompactNT + threadIdx.x; i < n_items; i += gridDim.x * kCompactNT)
-        s += list ? out.wlen[list[i]] : out.wlen[i];
+    for (uint32_t i = blockIdx.x * kCompactNT + threadIdx.x; i < count; i += gridDim.x * kCompactNT) s += len[i];
     s = block_sum_ll<kCompactNT>(s, tmp);
-    if (threadIdx.x == 0 && s) atomicAdd(&ctl->tile_total, (unsigned long long)s);
+    if (threadIdx.x == 0 && s) atomicAdd(total, (unsigned long long)s);
 }
 
-__global__ __launch_bounds__(kCompactNT) void k_compact(TileOut out, RoundCtl* ctl, uint32_t w_begin, uint32_t count,
-                                                        const int32_t* list) {
+__global__ __launch_bounds__(kCompactNT) void k_compact(CompactSpec sp, RoundCtl* ctl) {
     __shared__ int tmp[kCompactNT / 64];
     __shared__ unsigned long long base_sh;
     __shared__ long long src_sh[kCompactNT];
     __shared__ unsigned long long dst_sh[kCompactNT];
     __shared__ int len_sh[kCompactNT];
     if (ctl->stop) return;
-    const bool delta = (list != nullptr);
-    const bool store = (out.mode == kModeStore);
-    const uint32_t n_items = delta ? ctl->list_n[0] : count;
-    const int32_t* src_node = delta ? out.dl_node : out.scr_node;
-    const int32_t* src_cnt = delta ? out.dl_cnt : out.scr_cnt;
-    int32_t* dst_node = store ? out.store_node : out.pair_node;
-    int32_t* dst_cnt = store ? out.store_cnt : out.pair_cnt;
-    const unsigned long long cap = store ? out.store_cap : out.pair_cap;
-    unsigned long long* counter = store ? &ctl->store_count : &ctl->pair_count;
+    const uint32_t n_items = sp.list ? min(ctl->list_n[0], sp.count) : sp.count;
+    unsigned long long* counter =
+        sp.counter_id == 0 ? &ctl->pair_count : (sp.counter_id == 1 ? &ctl->store_count : &ctl->xstore_count);
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     for (uint32_t b0 = blockIdx.x * kCompactNT; b0 < n_items; b0 += gridDim.x * kCompactNT) {
@@ -699,17 +718,11 @@ __global__ __launch_bounds__(kCompactNT) void k_compact(TileOut out, RoundCtl* c
         long long src = 0;
         uint32_t w = 0;
         if (i < n_items) {
-            if (delta) {
-                w = (uint32_t)list[i];
-                src = out.store_off[w];
-                len = out.wlen[w];
-            } else {
-                w = w_begin + i;
-                src = out.wloc[i];
-                len = out.wlen[i];
-            }
-            const unsigned long long src_cap = delta ? out.dl_cap : out.scr_cap;
-            if (len < 0 || src < 0 || (unsigned long long)src + (unsigned long long)len > src_cap) {
+            w = sp.list ? (uint32_t)sp.list[i] : sp.w_begin + i;
+            const uint32_t key = sp.by_world ? w : i;
+            src = sp.loc[key];
+            len = sp.len[key];
+            if (len < 0 || src < 0 || (unsigned long long)src + (unsigned long long)len > sp.src_cap) {
                 atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
                 len = 0;
             }
@@ -718,14 +731,14 @@ __global__ __launch_bounds__(kCompactNT) void k_compact(TileOut out, RoundCtl* c
         const int ex = block_excl_scan<kCompactNT>(len, tmp, tot);
         if (threadIdx.x == 0) {
             base_sh = atomicAdd(counter, (unsigned long long)tot);
-            if (store) atomicAdd(&ctl->pair_count, (unsigned long long)tot);
+            if (sp.counter_id == 1) atomicAdd(&ctl->pair_count, (unsigned long long)tot);
         }
         __syncthreads();
         const unsigned long long dst = base_sh + (unsigned long long)ex;
-        const bool fits = base_sh + (unsigned long long)tot <= cap;
-        if (i < n_items && store && fits) {
-            out.store_off[w] = (int64_t)dst;
-            out.store_len[w] = len;
+        const bool fits = base_sh + (unsigned long long)tot <= sp.dst_cap;
+        if (i < n_items && sp.out_off && fits) {
+            sp.out_off[w] = (int64_t)dst;
+            sp.out_len[w] = len;
         }
         src_sh[threadIdx.x] = src;
         dst_sh[threadIdx.x] = dst;
@@ -734,33 +747,31 @@ __global__ __launch_bounds__(kCompactNT) void k_compact(TileOut out, RoundCtl* c
         if (fits) {
             for (int it = wid; it < kCompactNT; it += kCompactNT / 64) {
                 const int L = len_sh[it];
-                const long long sp = src_sh[it];
+                const long long sp0 = src_sh[it];
                 const unsigned long long dp = dst_sh[it];
-                for (int e = lane; e < L; e += 64) {
-                    dst_node[dp + e] = src_node[sp + e];
-                    dst_cnt[dp + e] = src_cnt[sp + e];
-                }
+                for (int f = 0; f < sp.nf; ++f)
+                    for (int e = lane; e < L; e += 64) sp.dst[f][dp + e] = sp.src[f][sp0 + e];
             }
         } else if (threadIdx.x == 0) {
-            atomicOr(&ctl->flags, (uint32_t)(store ? kFlagStoreOverflow : kFlagPairOverflow));
+            atomicOr(&ctl->flags, sp.overflow_flag);
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_sum_lengths(const TileOut& out, RoundCtl* ctl, uint32_t count, const int32_t* list,
+hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s) {
-    k_sum_lengths<<<128, kCompactNT, 0, s>>>(out, ctl, count, list);
+    k_sum_lengths<<<128, kCompactNT, 0, s>>>(len, count, total, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const TileOut& out, RoundCtl* ctl, uint32_t w_begin, uint32_t count, const int32_t* list,
-                          hipStream_t s) {
-    k_compact<<<256, kCompactNT, 0, s>>>(out, ctl, w_begin, count, list);
+hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s) {
+    k_compact<<<256, kCompactNT, 0, s>>>(spec, ctl);
     return hipGetLastError();
 }
 
 int world_tier0_capacity() { return Tier0Store::kCapNonSeed; }
+int world_tier0_xcapacity() { return Tier0Store::kCapX; }
 
 int world_tier_blocks_per_cu(int tier) {
     size_t lds = 0;
@@ -856,6 +867,164 @@ hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor
 hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
                            const int32_t* idx_world, int32_t* list, hipStream_t s) {
     k_affected<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_pos, idx_world, list);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- replay
+// A world re-evaluated without coins.  Reached sets only shrink as blockers
+// are added, so every live edge that can matter in a later round joins two
+// nodes reached in round 0, and round 0 kept all of them: the BFS tree edges
+// (each entry's parent) and the extra edges, as round-0 local ids.  The BFS
+// is redone over those edges with the blocked nodes (and the nodes already
+// lost, count 0) removed; dominators, counts and changes then follow exactly
+// as for a sampled world.  Old non-seed j = ns + i is stored entry i.
+template <int CAP, int XCAP, int ECAP, int LVCAP>
+struct ReplayStore {
+    int32_t nl[CAP];     // old entry -> new local id; -1 not reached yet, -2 removed, -3 being claimed
+    int16_t eu[ECAP];    // edge sources, round-0 local ids (seeds are 0..ns-1)
+    int16_t ev[ECAP];    // edge heads, old entry index
+    int16_t parent[CAP]; // by new local id - ns
+    int16_t idom[CAP];
+    int32_t aux[CAP];
+    int32_t xv[XCAP];    // extra edges of the new BFS: head (old entry until resolved), source new id
+    int16_t xu[XCAP];
+    int32_t lvl[LVCAP + 2];
+    int32_t ns;
+
+    __device__ static constexpr int cap_lv() { return LVCAP; }
+    __device__ static constexpr int cap_x() { return XCAP; }
+    __device__ int get_parent(int lid) const { return lid < ns ? -1 : (int)parent[lid - ns]; }
+    __device__ void set_parent(int lid, int p) { parent[lid - ns] = (int16_t)p; }
+    __device__ int get_idom(int lid) const { return lid < ns ? -1 : (int)idom[lid - ns]; }
+    __device__ void set_idom(int lid, int p) { idom[lid - ns] = (int16_t)p; }
+    __device__ int32_t* aux_ptr(int lid) { return &aux[lid - ns]; }
+    __device__ int get_xu(int64_t x) const { return xu[x]; }
+    __device__ void set_xu(int64_t x, int u) { xu[x] = (int16_t)u; }
+    __device__ int get_xv(int64_t x) const { return xv[x]; }
+    __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
+    __device__ void resolve_xv(int64_t x) { xv[x] = nl[xv[x]]; }
+    __device__ int delta_lid(int i, int32_t /*u*/) const { return nl[i]; }
+    __device__ int32_t node(int) const { return 0; }  // node ids are not needed in incremental rounds
+};
+
+using ReplayStoreT = ReplayStore<512, 128, 768, 62>;
+constexpr int kReplayNT = 64;
+
+template <int NT, class RS>
+__device__ bool bfs_replay(const QueryDev& q, uint32_t w, const TileOut& out, RS& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    const size_t so = (size_t)out.store_off[w];
+    const int L0 = out.store_len[w];
+    const size_t xo = (size_t)out.xstore_off[w];
+    const int X0 = out.xstore_len[w];
+    const int E = L0 + X0;
+    // room, and local ids that fit the 16-bit arrays (uniform checks)
+    if (L0 > 512 || E > 768 || ns + L0 > 32767) return false;
+    if (so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap) return false;
+    if (t == 0) {
+        st.ns = ns;
+        sh.count = ns;
+        sh.edges = E;
+        sh.ndelta = 0;
+        sh.n_extra = 0;
+        sh.overflow = 0;
+        st.lvl[0] = 0;
+        st.lvl[1] = ns;
+    }
+    for (int i = t; i < L0; i += NT) {
+        const bool gone = out.store_cnt[so + i] == 0 || bit_set(q.excl, out.store_node[so + i]);
+        st.nl[i] = gone ? -2 : -1;
+        st.eu[i] = (int16_t)out.store_par[so + i];
+        st.ev[i] = (int16_t)i;
+    }
+    for (int x = t; x < X0; x += NT) {
+        st.eu[L0 + x] = (int16_t)out.xstore_u[xo + x];
+        st.ev[L0 + x] = (int16_t)(out.xstore_v[xo + x] - ns);
+    }
+    __syncthreads();
+    int nlev = 1;
+    for (;;) {
+        const int f0 = st.lvl[nlev - 1];
+        const int f1 = st.lvl[nlev];
+        if (f0 == f1) break;
+        for (int e = t; e < E; e += NT) {
+            const int u = st.eu[e];
+            const int vi = st.ev[e];
+            if (u < 0 || u >= ns + L0 || vi < 0 || vi >= L0) continue;  // not a stored local id
+            const int nu = (u < ns) ? u : st.nl[u - ns];
+            if (nu < f0 || nu >= f1) continue;  // the source is not in this level
+            const int old = atomicCAS(&st.nl[vi], -1, -3);
+            if (old == -1) {
+                const int lid = atomicAdd(&sh.count, 1);
+                st.nl[vi] = lid;
+                st.set_parent(lid, nu);
+            } else if (old != -2) {
+                const int x = atomicAdd(&sh.n_extra, 1);
+                if (x < st.cap_x()) {
+                    st.xv[x] = vi;  // resolved to its new id in the dominator phase
+                    st.xu[x] = (int16_t)nu;
+                } else {
+                    sh.overflow = 1;
+                }
+            }
+        }
+        __syncthreads();
+        if (sh.overflow) return false;
+        if (nlev + 1 > st.cap_lv()) return false;  // same nlev in every thread: uniform
+        if (t == 0) st.lvl[nlev + 1] = sh.count;
+        __syncthreads();
+        ++nlev;
+    }
+    if (t == 0) {
+        sh.nlevels = nlev - 1;
+        sh.in_bytes = 12ull * (unsigned long long)L0 + 8ull * (unsigned long long)X0;
+    }
+    __syncthreads();
+    return true;
+}
+
+// Incremental rounds: every changed world is first replayed; a world that
+// does not fit the replay store goes on to the sampling tiers (list 1).
+__global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl* ctl, const int32_t* in_list,
+                                                             int32_t* next_list, TileOut out) {
+    __shared__ ReplayStoreT st;
+    __shared__ WorldShared<kReplayNT> sh;
+    const int t = threadIdx.x;
+    if (ctl->stop) return;
+    const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
+    if (blockIdx.x >= n_items) return;
+    if (t == 0) {
+        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_dsize = 0;
+    }
+    __syncthreads();
+    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+        const uint32_t w = (uint32_t)in_list[k];
+        if (bfs_replay<kReplayNT>(q, w, out, st, sh)) {
+            finish_world<kReplayNT, 0>(q, ctl, w, w, out, st, sh);
+        } else if (t == 0) {
+            const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
+            if (pos < out.next_cap) next_list[pos] = (int32_t)w;
+            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        add_work(out, 3, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+    }
+}
+
+int world_replay_blocks_per_cu() {
+    const size_t lds = sizeof(ReplayStoreT) + sizeof(WorldShared<kReplayNT>);
+    int b = (int)((160 * 1024) / lds);
+    return b < 1 ? 1 : b;
+}
+
+hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, const int32_t* in_list, int32_t* next_list,
+                               const TileOut& out, int grid, hipStream_t s) {
+    k_world_replay<<<grid, kReplayNT, 0, s>>>(q, ctl, in_list, next_list, out);
     return hipGetLastError();
 }
 

@@ -162,15 +162,26 @@ def test_solve_random_graphs(B, oracle_mod, case):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
-@pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7"])
+@pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7", "noreplay",
+                                     "xscratch", "tiles"])
 def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
-    """Incremental rounds (default), plain rounds, a resident store too small
-    to hold round 0 (falls back to plain rounds) and re-evaluation of changed
-    worlds on the larger tiers all give the oracle's selection."""
+    """Incremental rounds (default: changed worlds replayed from their stored
+    live edges), plain rounds, a resident store too small to hold round 0
+    (falls back to plain rounds), re-evaluation by sampling on every tier,
+    regrowth of the extra-edge scratch and several tiles all give the
+    oracle's selection."""
     if variant == "plain":
         monkeypatch.setenv("IMIN_INCREMENTAL", "0")
     elif variant == "store_overflow":
         monkeypatch.setenv("IMIN_STORE_CAP", "5000")
+    elif variant == "noreplay":
+        monkeypatch.setenv("IMIN_REPLAY", "0")
+    elif variant == "xscratch":
+        monkeypatch.setenv("IMIN_XBIG_SCRATCH", "16")
+        monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
+        monkeypatch.setenv("IMIN_START_TIER", "1")
+    elif variant == "tiles":
+        monkeypatch.setenv("IMIN_TILE_WORLDS", "97")
     elif variant.startswith("batch"):
         monkeypatch.setenv("IMIN_ROUND_BATCH", variant[5:])
     else:
@@ -180,6 +191,25 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
     _log(f"solve variant {variant}")
     res = B.solve(B.Graph.from_synth(g), seeds, 15, 700, 5)
     want = oracle_mod.Query(g, seeds).solve(15, 700, 5)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+@pytest.mark.parametrize("case", ["uniform", "multi", "binary"])
+def test_solve_replay_mixed_world_sizes(B, oracle_mod, case):
+    """Worlds from a few nodes to over a thousand: changed worlds are either
+    replayed or, when too large for the replay store, sampled again; parallel
+    edges and self-loops are kept in the multi case."""
+    n = 1200
+    if case == "multi":
+        g = synth.random_small_graph(n, 3600, seed=91, prob="uniform", allow_multi=True)
+    else:
+        g = synth.random_small_graph(n, 3000, seed=92, prob=case)
+    seeds = np.array([5, 17, 400, 999], np.int32)
+    _log(f"solve mixed world sizes {case}")
+    res = B.solve(B.Graph.from_synth(g), seeds, 12, 600, 31)
+    want = oracle_mod.Query(g, seeds).solve(12, 600, 31)
     np.testing.assert_array_equal(res.blockers, want["blockers"])
     np.testing.assert_array_equal(res.gains, want["gains"])
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
