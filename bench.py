@@ -186,8 +186,8 @@ def main():
         binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)
         torch.cuda.synchronize()
         log(f"warmup {i} done")
-    before = {kid: binding.timing_read(kid) for kid in range(7)}
-    work_before = [binding.timing_work(t) for t in range(4)]
+    before = {kid: binding.timing_read(kid) for kid in range(8)}
+    work_before = [binding.timing_work(t) for t in range(5)]
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -199,16 +199,17 @@ def main():
         log(f"step {i}: {lat[-1]:.1f} ms")
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
-    after = {kid: binding.timing_read(kid) for kid in range(7)}
-    work_after = [binding.timing_work(t) for t in range(4)]
+    after = {kid: binding.timing_read(kid) for kid in range(8)}
+    work_after = [binding.timing_work(t) for t in range(5)]
     n_sel = int(out[3].cpu()[0])
     rounds = min(n_sel + 1, k) if k > 0 else 1
     ms_per_step = total_s * 1e3 / args.steps
-    evals = sum(work_after[t][0] - work_before[t][0] for t in range(4)) / args.steps
+    evals = sum(work_after[t][0] - work_before[t][0] for t in range(5)) / args.steps
     value = evals / (ms_per_step / 1e3)
     kern = {name: (after[kid][1] - before[kid][1]) / args.steps
             for name, kid in (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("reduce", 2),
-                              ("select", 3), ("affected_search", 5), ("world_replay", 6))}
+                              ("select", 3), ("affected_search", 5), ("world_replay", 6),
+                              ("forest_update", 7))}
     # roofline of the dominant kernel over every launch in this process
     n0, ms0 = binding.timing_read(0)
     _, _, bytes0 = binding.timing_work(0)

@@ -152,6 +152,8 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  *   5  search for the worlds a new blocker changes (incremental rounds)
  *   6  replay of a changed world from its stored live edges (incremental
  *      rounds; worlds too large for it go on to kernels 4 and 1)
+ *   7  count update of a changed world whose reached live edges form a
+ *      forest (incremental rounds)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */
@@ -161,7 +163,8 @@ imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_m
 
 /*
  * Work done while timing was enabled, per world tier (0 small LDS, 1 large
- * LDS, 2 HBM, 3 replay): worlds finished, edges walked and algorithmic HBM
+ * LDS, 2 HBM, 3 replay, 4 forest update): worlds finished, edges walked (for
+ * tier 4: stored entries scanned) and algorithmic HBM
  * bytes.  For tiers 0-2 the edges are the CSR slots of the reached rows (the
  * edges whose coins were needed) and the bytes are 8 per such slot (column
  * and threshold) + 8 per reached non-seed (row offsets) + 16 per level-0

@@ -22,8 +22,8 @@ namespace {
 thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
-constexpr int kTimedKernels = 7;
-constexpr int kWorkTiers = 4;  // tiers 0-2 and replay
+constexpr int kTimedKernels = 8;
+constexpr int kWorkTiers = 5;  // tiers 0-2, replay, forest update
 struct Timing {
     std::atomic<bool> on{false};
     std::mutex mu;
@@ -173,18 +173,29 @@ struct Session {
     DevArray<int32_t> pair_node, pair_cnt, sorted_node, sorted_cnt;
     DevArray<int32_t> hist;
     DevArray<int64_t> part;
-    imin::ReduceBufs rb{}, rb_delta{};
+    imin::ReduceBufs rb{};
     // resident per-world (node, count) lists for incremental rounds
     DevArray<int32_t> store_node, store_cnt, store_len, dl_node, dl_cnt;
     DevArray<int64_t> store_off;
     // replay of changed worlds from their stored live edges: BFS parents
     // beside the pairs, extra edges (local ids) in a store of their own
     bool replay = false;
+    bool forest = true;  // forest worlds updated from their labels (with replay)
     DevArray<int32_t> scr_par, xscr_v, xscr_u, xlen;
     DevArray<int64_t> xloc;
     size_t xslot_cap0 = 0, xbig_cap = 0;
     DevArray<int32_t> store_par, xstore_v, xstore_u, xstore_len;
     DevArray<int64_t> xstore_off;
+    DevArray<imin::ReplayItem> items;   // changed worlds of an incremental round to re-evaluate
+    DevArray<imin::ReplayItem> titems;  // changed forest worlds
+    // dominator-tree labels and the forest flag per world (with replay)
+    DevArray<int32_t> scr_lab, store_lab;
+    DevArray<uint8_t> world_tree;
+    // nodes lost per (kernel, workgroup) in incremental rounds
+    DevArray<long long> dsz;
+    int32_t dsz_n = 0;
+    int32_t dsz_off[5] = {0, 0, 0, 0, 0};
+    int grid_t = 0;
     int grid_r = 0;
     bool incremental = false;
     size_t store_budget = 0;
@@ -199,6 +210,7 @@ struct Session {
     // selection
     DevArray<int64_t> sel_g;
     DevArray<int32_t> sel_u;
+    DevArray<long long> sel_d;
     int sel_parts = 0;
     // per-workgroup work tallies
     DevArray<unsigned long long> work;
@@ -244,11 +256,6 @@ struct Session {
         IMIN_TRY(part.alloc((size_t)rb.slices * ((size_t)rb.nb << imin::kBucketShift)));
         rb.hist = hist.p;
         rb.part = part.p;
-        // incremental rounds report few changes: fewer histogram chunks and
-        // one workgroup per bucket adding straight into gain
-        rb_delta = rb;
-        rb_delta.g1 = 128;
-        rb_delta.slices = 1;
         imin_status_t st = ensure_pairs(1 << 16);
         if (st != IMIN_OK) return st;
 
@@ -284,12 +291,25 @@ struct Session {
         sel_parts = (int)std::min<size_t>(1024, (n + 255) / 256);
         IMIN_TRY(sel_g.alloc(sel_parts));
         IMIN_TRY(sel_u.alloc(sel_parts));
+        IMIN_TRY(sel_d.alloc(sel_parts));
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
         grid_r = cus * imin::world_replay_blocks_per_cu();
+        grid_t = cus * 4;
+        {
+            const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_t};
+            int32_t at = 0;
+            for (int i = 0; i < 5; ++i) {
+                dsz_off[i] = at;
+                at += sizes[i];
+            }
+            dsz_n = at;
+            IMIN_TRY(dsz.alloc((size_t)dsz_n));
+            IMIN_TRY(hipMemsetAsync(dsz.p, 0, (size_t)dsz_n * sizeof(long long), s));
+        }
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
-            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r), bs.n_slots);
+            work_stride = std::max(std::max(std::max(grid0, grid1), std::max(grid_r, grid_t)), bs.n_slots);
             const size_t wn = (size_t)3 * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
             IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));
@@ -337,9 +357,9 @@ struct Session {
         IMIN_TRY(pair_cnt.alloc(want));
         IMIN_TRY(sorted_node.alloc(want));
         IMIN_TRY(sorted_cnt.alloc(want));
-        rb.sorted_node = rb_delta.sorted_node = sorted_node.p;
-        rb.sorted_cnt = rb_delta.sorted_cnt = sorted_cnt.p;
-        rb.sorted_cap = rb_delta.sorted_cap = sorted_node.count;
+        rb.sorted_node = sorted_node.p;
+        rb.sorted_cnt = sorted_cnt.p;
+        rb.sorted_cap = sorted_node.count;
         return IMIN_OK;
     }
 
@@ -355,15 +375,19 @@ struct Session {
             return IMIN_OK;  // plain rounds give the same integers
         }
         incremental = true;
+        const char* fp = std::getenv("IMIN_FOREST");
+        forest = !(fp && fp[0] == '0');
         const char* rp = std::getenv("IMIN_REPLAY");
         if (!(rp && rp[0] == '0')) {
             xslot_cap0 = (size_t)imin::world_tier0_xcapacity();
             xbig_cap = env_size("IMIN_XBIG_SCRATCH", (size_t)1 << 20);
             const size_t xn = tile_cap * xslot_cap0 + xbig_cap;
-            replay = scr_par.alloc(scr_node.count) == hipSuccess && xscr_v.alloc(xn) == hipSuccess &&
-                     xscr_u.alloc(xn) == hipSuccess && xloc.alloc(tile_cap) == hipSuccess &&
-                     xlen.alloc(tile_cap) == hipSuccess && xstore_off.alloc(theta) == hipSuccess &&
-                     xstore_len.alloc(theta) == hipSuccess;
+            replay = scr_par.alloc(scr_node.count) == hipSuccess && scr_lab.alloc(scr_node.count) == hipSuccess &&
+                     xscr_v.alloc(xn) == hipSuccess && xscr_u.alloc(xn) == hipSuccess &&
+                     xloc.alloc(tile_cap) == hipSuccess && xlen.alloc(tile_cap) == hipSuccess &&
+                     xstore_off.alloc(theta) == hipSuccess && xstore_len.alloc(theta) == hipSuccess &&
+                     world_tree.alloc(theta) == hipSuccess &&
+                     hipMemsetAsync(world_tree.p, 0, theta, s) == hipSuccess;
             if (!replay) drop_replay();
         }
         return IMIN_OK;
@@ -373,6 +397,9 @@ struct Session {
     void drop_replay() {
         replay = false;
         scr_par.release();
+        scr_lab.release();
+        store_lab.release();
+        world_tree.release();
         xscr_v.release();
         xscr_u.release();
         xloc.release();
@@ -413,7 +440,7 @@ struct Session {
     // room for `more` entries after the store's `used` ones
     bool ensure_store(unsigned long long used, unsigned long long more) {
         if (replay) {
-            DevArray<int32_t>* arrs[3] = {&store_node, &store_cnt, &store_par};
+            DevArray<int32_t>* arrs[4] = {&store_node, &store_cnt, &store_par, &store_lab};
             return grow_store(arrs, used, used + more, store_budget);
         }
         DevArray<int32_t>* arrs[2] = {&store_node, &store_cnt};
@@ -437,8 +464,8 @@ struct Session {
         IMIN_TRY(idx_world.alloc(entries));
         IMIN_TRY(dl_node.alloc(entries));
         IMIN_TRY(dl_cnt.alloc(entries));
-        imin_status_t st = ensure_pairs(entries);  // a round's changes never outnumber the entries
-        if (st != IMIN_OK) return st;
+        IMIN_TRY(items.alloc(theta));
+        IMIN_TRY(titems.alloc(theta));
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_index_count(out, entries, idx_off.p, s));
@@ -469,7 +496,15 @@ struct Session {
         out.dl_node = dl_node.p;
         out.dl_cnt = dl_cnt.p;
         out.dl_cap = dl_node.count;
-        out.list_cap = (uint32_t)std::min<size_t>(list0.count, 0xFFFFFFFFu);
+        out.list_cap = (uint32_t)std::min<size_t>(items.p ? std::min(list0.count, items.count) : list0.count,
+                                                  0xFFFFFFFFu);
+        out.items = items.p;
+        out.titems = titems.p;
+        out.scr_lab = (uint32_t*)scr_lab.p;
+        out.store_lab = (uint32_t*)store_lab.p;
+        out.world_tree = forest ? world_tree.p : nullptr;
+        out.dsz = dsz.p;
+        for (int i = 0; i < 5; ++i) out.dsz_off[i] = dsz_off[i];
         out.next_cap = (uint32_t)std::min<size_t>(std::min(list1.count, list2.count), 0xFFFFFFFFu);
         out.scr_par = scr_par.p;
         out.store_par = store_par.p;
@@ -520,9 +555,13 @@ struct Session {
         timed.end(5, ev, s);
         imin_status_t st;
         if (replay) {
-            // replay every changed world; those too large go on to sampling
+            // forest worlds: subtree removal from the labels
             ev = timed.begin(s);
-            IMIN_TRY(imin::launch_world_replay(q, ctl.p, list0.p, list1.p, out, grid_r, s));
+            IMIN_TRY(imin::launch_tree_update(ctl.p, out, grid_t, s));
+            timed.end(7, ev, s);
+            // replay every other changed world; those too large go on to sampling
+            ev = timed.begin(s);
+            IMIN_TRY(imin::launch_world_replay(q, ctl.p, list1.p, out, grid_r, s));
             timed.end(6, ev, s);
             st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1);
         } else {
@@ -530,23 +569,7 @@ struct Session {
         }
         if (st != IMIN_OK) return st;
         ev = timed.begin(s);
-        imin::CompactSpec cs{};
-        cs.src[0] = dl_node.p;
-        cs.src[1] = dl_cnt.p;
-        cs.dst[0] = pair_node.p;
-        cs.dst[1] = pair_cnt.p;
-        cs.nf = 2;
-        cs.src_cap = dl_node.count;
-        cs.dst_cap = pair_node.count;
-        cs.loc = store_off.p;
-        cs.len = wlen.p;
-        cs.by_world = 1;
-        cs.list = list0.p;
-        cs.count = out.list_cap;
-        cs.counter_id = 0;
-        cs.overflow_flag = imin::kFlagPairOverflow;
-        IMIN_TRY(imin::launch_compact(cs, ctl.p, s));
-        IMIN_TRY(imin::launch_reduce_pairs(g, out, rb_delta, ctl.p, gain.p, s));
+        IMIN_TRY(imin::launch_delta_reduce(g, out, ctl.p, gain.p, cu_count() * 4, s));
         timed.end(2, ev, s);
         // T is carried over from the last round and lowered by the changed
         // worlds themselves: no pass over all theta sizes
@@ -595,6 +618,7 @@ struct Session {
                 if (keep) {
                     xbig_cap = std::max<size_t>(xbig_cap, (size_t)(xc + xc / 8 + 1024));
                     IMIN_TRY(scr_par.alloc(scr_node.count));
+                    IMIN_TRY(scr_lab.alloc(scr_node.count));
                     IMIN_TRY(xscr_v.alloc(tile_cap * xslot_cap0 + xbig_cap));
                     IMIN_TRY(xscr_u.alloc(tile_cap * xslot_cap0 + xbig_cap));
                 }
@@ -623,6 +647,7 @@ struct Session {
             cs.src[0] = scr_node.p;
             cs.src[1] = scr_cnt.p;
             cs.src[2] = scr_par.p;
+            cs.src[3] = scr_lab.p;
             cs.nf = 2;
             cs.src_cap = scr_node.count;
             cs.loc = wloc.p;
@@ -633,7 +658,8 @@ struct Session {
                 cs.dst[0] = store_node.p;
                 cs.dst[1] = store_cnt.p;
                 cs.dst[2] = store_par.p;
-                if (use_x) cs.nf = 3;
+                cs.dst[3] = store_lab.p;
+                if (use_x) cs.nf = 4;
                 cs.dst_cap = store_node.count;
                 cs.counter_id = 1;
                 cs.out_off = store_off.p;
@@ -827,7 +853,8 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
                 if (st != IMIN_OK) return st;
                 hipEvent_t ev = ss.timed.begin(s);
                 IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p,
-                                             ss.sel_parts, k, blockers, gains, spread_totals, n_selected, s));
+                                             ss.sel_d.p, ss.dsz.p, ss.dsz_n, ss.sel_parts, k, blockers, gains,
+                                             spread_totals, n_selected, s));
                 ss.timed.end(3, ev, s);
             }
             r += nb;
@@ -837,7 +864,8 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, r == 0);
             if (st != IMIN_OK) return st;
             hipEvent_t ev = ss.timed.begin(s);
-            IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_parts,
+            IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_d.p,
+                                         ss.dsz.p, ss.dsz_n, ss.sel_parts,
                                          k, blockers, gains, spread_totals, n_selected, s));
             ss.timed.end(3, ev, s);
             ++r;

@@ -62,6 +62,8 @@ struct RoundCtl {
     unsigned long long xbig_count;   // extra edges bump-allocated this tile
     unsigned long long xtile_total;  // extra edges the tile's worlds wrote
     unsigned long long xstore_count; // extra edges held for replay
+    uint32_t tree_n;                 // changed worlds of the round whose reached part is a forest
+    uint32_t pad2;
 };
 
 // How a world evaluation reports its counts.
@@ -95,6 +97,28 @@ struct BigSlots {
 // packs the entries densely, with one counter update per workgroup.  In
 // incremental rounds a world writes its count changes into dl_* at its own
 // stored-list positions, which it alone owns.
+// A changed world of an incremental round with what its re-evaluation reads
+// first (gathered by the search for changed worlds).
+struct ReplayItem {
+    int64_t store_off;   // its (node, count, parent, label) entries
+    int64_t xstore_off;  // its extra live edges (replay only)
+    int32_t w;
+    int32_t store_len;
+    int32_t xstore_len;
+    int32_t world_size;  // reached nodes before this round
+    int32_t j;           // entry of the new blocker
+    int32_t cj;          // its count
+    uint32_t labj;       // its label
+    int32_t pad;
+};
+
+// Dominator-tree label of a stored entry: preorder index (high 16 bits) and
+// subtree size when labelled (low 16 bits); the subtree of an entry is the
+// entries whose preorder index lies in [index, index + size).
+__host__ __device__ constexpr uint32_t pack_label(int tin, int size) {
+    return ((uint32_t)tin << 16) | ((uint32_t)size & 0xFFFFu);
+}
+
 struct TileOut {
     int mode;
     int32_t* scr_node;
@@ -119,6 +143,8 @@ struct TileOut {
     unsigned long long dl_cap;
     uint32_t list_cap;   // entries of the changed-world list
     uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
+    ReplayItem* items;   // changed worlds to re-evaluate, with their store ranges (list_cap of them)
+    ReplayItem* titems;  // changed worlds whose reached part is a forest (list_cap of them)
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
@@ -142,13 +168,23 @@ struct TileOut {
     unsigned long long xstore_cap;
     int64_t* xstore_off;  // [theta]
     int32_t* xstore_len;  // [theta]
+    // Forest worlds: where the live edges among a world's reached nodes form
+    // a forest under the seeds, the dominator tree is that forest and adding
+    // a blocker only removes its subtree; the entries carry their labels.
+    uint32_t* scr_lab;    // aligned with scr_node
+    uint32_t* store_lab;  // aligned with store_node
+    uint8_t* world_tree;  // [theta] 1: the world's labels describe its dominator tree, which is a forest
+    // Incremental rounds: nodes each workgroup's worlds lost, one slot per
+    // (kernel, workgroup); summed and cleared by the selection.
+    long long* dsz;
+    int32_t dsz_off[5];   // slot ranges of tier 0, 1, 2, replay, forest update
 };
 
-// A compaction job: per-item ranges of up to three int32 fields are packed
+// A compaction job: per-item ranges of up to four 32-bit fields are packed
 // densely into the destination, one counter update per workgroup.
 struct CompactSpec {
-    const int32_t* src[3];
-    int32_t* dst[3];
+    const int32_t* src[4];
+    int32_t* dst[4];
     int nf;
     unsigned long long src_cap;
     unsigned long long dst_cap;
@@ -206,8 +242,13 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
 hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
-hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, const int32_t* in_list, int32_t* next_list,
-                               const TileOut& out, int grid, hipStream_t s);
+// gain += the count changes the changed worlds of items[0 .. list_n[0]) wrote
+hipError_t launch_delta_reduce(const GraphDev& g, const TileOut& out, RoundCtl* ctl, int64_t* gain, int grid,
+                               hipStream_t s);
+hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out, int grid,
+                               hipStream_t s);
+hipError_t launch_tree_update(RoundCtl* ctl, const TileOut& out, int grid, hipStream_t s);
+constexpr int kTreeNT = 256;  // four worlds at a time per workgroup
 int world_replay_blocks_per_cu();
 hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
@@ -225,10 +266,13 @@ int world_tier0_xcapacity();  // extra live edges a tier-0 world may record
 hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
                                RoundCtl* ctl, int64_t* gain, hipStream_t s);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
+// Argmax of gain over the candidates (ties to the smaller id), the stop rule
+// and the round's T; also sums and clears the dsz slots (nodes lost by the
+// round's changed worlds) into T.
 hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl, RoundCtl* ctl,
-                         int64_t* part_gain, int32_t* part_node, int parts, int32_t k,
-                         int32_t* blockers, int64_t* gains, int64_t* totals, int32_t* n_selected,
-                         hipStream_t s);
+                         int64_t* part_gain, int32_t* part_node, long long* part_dsz, long long* dsz,
+                         int32_t dsz_n, int parts, int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,
+                         int32_t* n_selected, hipStream_t s);
 
 
 } // namespace imin

@@ -44,6 +44,8 @@ struct WorldShared {
     int overflow; // store out of room: hand the world to the next tier
     int changed;
     int nonfwd;   // some extra edge does not go exactly one level down
+    unsigned long long xlevels;  // bit L: some extra edge ends in level L (bit 63: level 63 or deeper)
+    int root_cur;  // label placement of the dominator tree's roots
     unsigned long long pair_base;
     unsigned long long x_base;
     long long edges;  // CSR slots of reached rows
@@ -144,6 +146,12 @@ struct LdsStore {
     __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
     // local id now of the node of stored entry i (incremental rounds)
     __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
+    // dominator-tree labels, once the counts are known: the node table is
+    // no longer needed and holds the placement cursors and preorder indexes
+    static constexpr bool kLabels = true;
+    __device__ int32_t* cur_ptr(int lid) { return &keys[lid - ns]; }
+    __device__ void set_tin(int lid, int v) { vals[lid - ns] = (int16_t)v; }
+    __device__ int get_tin(int lid) const { return (int)(uint16_t)vals[lid - ns]; }
     template <int NT>
     __device__ void reset(int /*count*/) { clear<NT>(); }
 };
@@ -195,6 +203,10 @@ struct HbmStore {
     __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
     __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
     __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
+    static constexpr bool kLabels = false;  // worlds of this tier are never treated as forests
+    __device__ int32_t* cur_ptr(int) { return nullptr; }
+    __device__ void set_tin(int, int) {}
+    __device__ int get_tin(int) const { return 0; }
     template <int NT>
     __device__ void reset(int count) {
         for (int i = threadIdx.x; i < count; i += NT) lid_of[nodes[i]] = -1;
@@ -382,11 +394,11 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, Sto
     return true;
 }
 
-// Phase 2, shared by sampling and replay: immediate dominators, subtree
-// sizes and the outputs of the mode.
-template <int NT, int TIER, class Store>
-__device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi, const TileOut& out,
-                             Store& st, WorldShared<NT>& sh) {
+// Phase 2, shared by sampling and replay: immediate dominators under the
+// super-source and the dominator-subtree size (the count) of every reached
+// non-seed, left in aux.
+template <int NT, class Store>
+__device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldShared<NT>& sh) {
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     const int nlevels = sh.nlevels;
@@ -400,7 +412,10 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
         st.set_idom(i, p);
         *st.aux_ptr(i) = p;
     }
-    if (t == 0) sh.nonfwd = 0;
+    if (t == 0) {
+        sh.nonfwd = 0;
+        sh.xlevels = 0;
+    }
     __syncthreads();
     for (int x = t; x < nx; x += NT) {
         const int v = st.get_xv(x);
@@ -412,9 +427,33 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
         }
         const bool fwd = (lo >= 1) && (u >= st.lvl[lo - 1]) && (u < st.lvl[lo]);
         if (!fwd) sh.nonfwd = 1;
+        atomicOr(&sh.xlevels, lo < 63 ? (1ull << lo) : (1ull << 63));  // levels holding an extra edge's head
     }
     __syncthreads();
-    if (nx > 0) {
+    if (nx > 0 && !sh.nonfwd) {
+        // Every extra edge goes exactly one level down: the idom of a level-L
+        // node depends only on final idoms of shallower levels, so one sweep
+        // over the levels holding extra heads suffices, kept in aux.
+        const unsigned long long xl = sh.xlevels;
+        for (int L = 1; L < nlevels; ++L) {
+            if (L < 63 && !((xl >> L) & 1ull)) continue;  // uniform
+            const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
+            for (int x = t; x < nx; x += NT) {
+                const int v = st.get_xv(x);
+                if (v < v0 || v >= v1) continue;
+                int a = st.get_parent(v);
+                int b = st.get_xu(x);
+                while (a != b) {
+                    if (a > b) a = (a < ns) ? -1 : *st.aux_ptr(a);
+                    else b = (b < ns) ? -1 : *st.aux_ptr(b);
+                }
+                atomicMin(st.aux_ptr(v), a);
+            }
+            __syncthreads();
+        }
+        for (int i = ns + t; i < R; i += NT) st.set_idom(i, *st.aux_ptr(i));
+        __syncthreads();
+    } else if (nx > 0) {
         // Every sweep that changes something lowers some idom id, so the
         // sweeps end; the cap only guards a broken invariant.
         for (int pass = 0;; ++pass) {
@@ -448,7 +487,7 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
                 }
                 __syncthreads();
             }
-            const bool again = sh.nonfwd && sh.changed;
+            const bool again = sh.changed;
             __syncthreads();
             if (!again) break;
         }
@@ -464,8 +503,40 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
         }
         __syncthreads();
     }
+}
 
-    // ---- outputs
+// Dominator-tree labels: each non-seed gets a preorder index such that its
+// subtree is the index range [index, index + count).  Nodes are placed level
+// by level (an idom lies on every path, so on a shallower level): a node
+// takes the next range of its idom's cursor (or of the roots' cursor when
+// its idom is a seed or the super-source).  Sibling order is arbitrary.
+template <int NT, class Store>
+__device__ void world_labels(const QueryDev& q, Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    const int nlevels = sh.nlevels;
+    if (t == 0) sh.root_cur = 0;
+    __syncthreads();
+    for (int L = 1; L < nlevels; ++L) {
+        for (int v = st.lvl[L] + t; v < st.lvl[L + 1]; v += NT) {
+            const int p = st.get_idom(v);
+            const int size = *st.aux_ptr(v);
+            const int at = (p < ns) ? atomicAdd(&sh.root_cur, size) : atomicAdd(st.cur_ptr(p), size);
+            st.set_tin(v, at);
+            *st.cur_ptr(v) = at + 1;
+        }
+        __syncthreads();
+    }
+}
+
+// Phase 3 of a sampled world: the outputs of the mode.
+template <int NT, int TIER, class Store>
+__device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi, const TileOut& out,
+                              Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    const int R = sh.count;
+    const int nx = sh.n_extra;
     const int len = R - ns;
     int read_len = 0;  // stored entries read back (incremental rounds)
     if (out.mode == kModeDelta) {
@@ -508,7 +579,10 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
             }
         }
         __syncthreads();
-        if (t == 0) out.wlen[w] = sh.ndelta;
+        if (t == 0) {
+            out.wlen[w] = sh.ndelta;
+            if (out.world_tree) out.world_tree[w] = 0;  // no labels from this evaluation
+        }
     } else {
         if (t == 0) {
             sh.pair_base = (TIER == 0) ? (unsigned long long)wi * out.slot_cap0
@@ -520,7 +594,10 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
             for (int i = t; i < len; i += NT) {
                 out.scr_node[off + i] = st.node(ns + i);
                 out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
-                if (out.keep_edges) out.scr_par[off + i] = st.get_parent(ns + i);
+                if (out.keep_edges) {
+                    out.scr_par[off + i] = st.get_parent(ns + i);
+                    out.scr_lab[off + i] = Store::kLabels ? pack_label(st.get_tin(ns + i), *st.aux_ptr(ns + i)) : 0u;
+                }
             }
             if (t == 0) {
                 out.wloc[wi] = (int64_t)off;
@@ -530,6 +607,9 @@ __device__ void finish_world(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint3
             atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);  // bump region full: the tile is redone
         }
         if (out.keep_edges) {
+            // a world with no extra live edge is a forest: its labels serve
+            // the incremental rounds directly
+            if (t == 0 && out.world_tree) out.world_tree[w] = (Store::kLabels && nx == 0) ? 1 : 0;
             // the extra live edges, as local ids, for later replays
             if (t == 0) {
                 sh.x_base = (TIER == 0) ? (unsigned long long)wi * out.xslot_cap0
@@ -579,7 +659,11 @@ template <int NT, int TIER, class Store>
 __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
                                const TileOut& out, Store& st, WorldShared<NT>& sh) {
     if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
-    finish_world<NT, TIER>(q, ctl, w, wi, out, st, sh);
+    world_counts<NT>(q, ctl, st, sh);
+    if constexpr (Store::kLabels) {
+        if (out.keep_edges && out.mode != kModeDelta) world_labels<NT>(q, st, sh);  // uniform
+    }
+    world_outputs<NT, TIER>(q, ctl, w, wi, out, st, sh);
     return true;
 }
 
@@ -636,8 +720,8 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     }
     if (t == 0) {
         add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
-        // incremental rounds keep T up to date: subtract the nodes lost
-        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+        // incremental rounds keep T up to date: the nodes lost, per workgroup
+        if (sh.acc_dsize) out.dsz[out.dsz_off[TIER] + blockIdx.x] = sh.acc_dsize;
     }
 }
 
@@ -678,7 +762,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     }
     if (t == 0) {
         add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
-        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+        if (sh.acc_dsize) out.dsz[out.dsz_off[2] + blockIdx.x] = sh.acc_dsize;
     }
 }
 
@@ -825,7 +909,9 @@ __global__ void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32
     }
 }
 
-// worlds whose entry for the last selected blocker is live -> list_n[0]
+// Worlds whose entry for the last selected blocker is live, with their store
+// ranges and that entry: forest worlds -> titems[0 .. tree_n), the others ->
+// items / list[0 .. list_n[0]).
 __global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
                                                   const int32_t* idx_pos, const int32_t* idx_world,
                                                   int32_t* list) {
@@ -833,18 +919,47 @@ __global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, co
     const int32_t u = ctl->ustar;
     const int32_t a = idx_off[u], b = idx_off[u + 1];
     const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
     for (int i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
         const int k = i + lane;
-        const bool live = (k < b) && out.store_cnt[idx_pos[k]] > 0;
-        const unsigned long long mask = __ballot(live);
-        const int cnt = __popcll(mask);
-        uint32_t base = 0;
-        if (lane == 0 && cnt) base = atomicAdd(&ctl->list_n[0], (uint32_t)cnt);
-        base = __shfl(base, 0, 64);
+        int32_t pos = 0, c = 0, w = 0;
+        if (k < b) {
+            pos = idx_pos[k];
+            w = idx_world[k];
+            c = out.store_cnt[pos];
+        }
+        const bool live = c > 0;
+        const bool tree = live && out.world_tree && out.world_tree[w];
+        const unsigned long long mt = __ballot(tree);
+        const unsigned long long mr = __ballot(live && !tree);
+        uint32_t bt = 0, br = 0;
+        if (lane == 0 && mt) bt = atomicAdd(&ctl->tree_n, (uint32_t)__popcll(mt));
+        if (lane == 0 && mr) br = atomicAdd(&ctl->list_n[0], (uint32_t)__popcll(mr));
+        bt = __shfl(bt, 0, 64);
+        br = __shfl(br, 0, 64);
         if (live) {
-            const uint32_t pos = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-            if (pos < out.list_cap) list[pos] = idx_world[k];
-            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            const uint32_t at = tree ? bt + (uint32_t)__popcll(mt & below) : br + (uint32_t)__popcll(mr & below);
+            if (at < out.list_cap) {
+                ReplayItem it;
+                it.store_off = out.store_off[w];
+                it.store_len = out.store_len[w];
+                it.xstore_off = out.xstore_off ? out.xstore_off[w] : 0;
+                it.xstore_len = out.xstore_off ? out.xstore_len[w] : 0;
+                it.world_size = out.world_size[w];
+                it.w = w;
+                it.j = (int32_t)((int64_t)pos - it.store_off);
+                it.cj = c;
+                it.labj = out.store_lab ? out.store_lab[pos] : 0u;
+                it.pad = 0;
+                if (tree) {
+                    out.titems[at] = it;
+                } else {
+                    out.items[at] = it;
+                    list[at] = w;
+                }
+            } else {
+                atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            }
         }
     }
 }
@@ -878,19 +993,19 @@ hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx
 // is redone over those edges with the blocked nodes (and the nodes already
 // lost, count 0) removed; dominators, counts and changes then follow exactly
 // as for a sampled world.  Old non-seed j = ns + i is stored entry i.
-template <int CAP, int XCAP, int ECAP, int LVCAP>
+template <int CAP, int XCAP, int LVCAP>
 struct ReplayStore {
-    int32_t nl[CAP];     // old entry -> new local id; -1 not reached yet, -2 removed, -3 being claimed
-    int16_t eu[ECAP];    // edge sources, round-0 local ids (seeds are 0..ns-1)
-    int16_t ev[ECAP];    // edge heads, old entry index
-    int16_t parent[CAP]; // by new local id - ns
+    int32_t nl[CAP];      // old entry -> new local id; -1 not reached yet, -2 removed, -3 being claimed
+    int32_t cur[CAP];     // label placement cursors
+    int16_t parent[CAP];  // by new local id - ns; preorder index once the counts are known
     int16_t idom[CAP];
     int32_t aux[CAP];
-    int32_t xv[XCAP];    // extra edges of the new BFS: head (old entry until resolved), source new id
+    int32_t xv[XCAP];     // extra edges of the new BFS: head (old entry until resolved), source new id
     int16_t xu[XCAP];
     int32_t lvl[LVCAP + 2];
     int32_t ns;
 
+    static constexpr int kCap = CAP;
     __device__ static constexpr int cap_lv() { return LVCAP; }
     __device__ static constexpr int cap_x() { return XCAP; }
     __device__ int get_parent(int lid) const { return lid < ns ? -1 : (int)parent[lid - ns]; }
@@ -903,70 +1018,125 @@ struct ReplayStore {
     __device__ int get_xv(int64_t x) const { return xv[x]; }
     __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
     __device__ void resolve_xv(int64_t x) { xv[x] = nl[xv[x]]; }
-    __device__ int delta_lid(int i, int32_t /*u*/) const { return nl[i]; }
-    __device__ int32_t node(int) const { return 0; }  // node ids are not needed in incremental rounds
+    static constexpr bool kLabels = true;
+    __device__ int32_t* cur_ptr(int lid) { return &cur[lid - ns]; }
+    __device__ void set_tin(int lid, int v) { parent[lid - ns] = (int16_t)v; }
+    __device__ int get_tin(int lid) const { return (int)(uint16_t)parent[lid - ns]; }
 };
 
-using ReplayStoreT = ReplayStore<512, 128, 768, 62>;
+using ReplayStoreT = ReplayStore<512, 128, 62>;
 constexpr int kReplayNT = 64;
+constexpr int kReplaySlots = 12;  // stored edges per lane: at most 768 per world
+constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 
+// Claim old entry vi from source new id nu, or record the edge as extra.
 template <int NT, class RS>
-__device__ bool bfs_replay(const QueryDev& q, uint32_t w, const TileOut& out, RS& st, WorldShared<NT>& sh) {
+__device__ __forceinline__ void replay_claim(RS& st, WorldShared<NT>& sh, int vi, int nu) {
+    const int old = atomicCAS(&st.nl[vi], -1, -3);
+    if (old == -1) {
+        const int lid = atomicAdd(&sh.count, 1);
+        st.nl[vi] = lid;
+        st.set_parent(lid, nu);
+    } else if (old != -2) {
+        const int x = atomicAdd(&sh.n_extra, 1);
+        if (x < st.cap_x()) {
+            st.xv[x] = vi;  // resolved to its new id in the dominator phase
+            st.xu[x] = (int16_t)nu;
+        } else {
+            sh.overflow = 1;
+        }
+    }
+}
+
+// The stored edges stay in registers (kReplaySlots per lane); each level
+// looks up the new id of every pending edge's source and claims the heads
+// of the edges leaving the frontier.  Every edge is used once, when its
+// source's level is expanded.  The world's entries (count, node) stay in
+// registers too (lane t holds entries t, t+64, ...) for the outputs.  An
+// entry is removed when its count is 0 (lost in an earlier round, which
+// includes every earlier blocker) or it is this round's blocker.
+template <int NT, class RS>
+__device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
+                           WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots],
+                           int32_t (&en)[kReplayEntrySlots]) {
+    static_assert(NT == 64, "one wave per replayed world");
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
-    const size_t so = (size_t)out.store_off[w];
-    const int L0 = out.store_len[w];
-    const size_t xo = (size_t)out.xstore_off[w];
-    const int X0 = out.xstore_len[w];
+    const size_t so = (size_t)it.store_off;
+    const int L0 = it.store_len;
+    const size_t xo = (size_t)it.xstore_off;
+    const int X0 = it.xstore_len;
     const int E = L0 + X0;
-    // room, and local ids that fit the 16-bit arrays (uniform checks)
-    if (L0 > 512 || E > 768 || ns + L0 > 32767) return false;
-    if (so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap) return false;
+    // room, local ids that fit the 16-bit arrays, ranges inside the stores
+    // (uniform checks)
+    if (L0 < 0 || X0 < 0 || L0 > RS::kCap || E > NT * kReplaySlots || ns + L0 > 32767) return false;
+    if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || so + (size_t)L0 > out.dl_cap ||
+        xo + (size_t)X0 > out.xstore_cap)
+        return false;
     if (t == 0) {
         st.ns = ns;
         sh.count = ns;
         sh.edges = E;
-        sh.ndelta = 0;
         sh.n_extra = 0;
         sh.overflow = 0;
         st.lvl[0] = 0;
         st.lvl[1] = ns;
     }
-    for (int i = t; i < L0; i += NT) {
-        const bool gone = out.store_cnt[so + i] == 0 || bit_set(q.excl, out.store_node[so + i]);
-        st.nl[i] = gone ? -2 : -1;
-        st.eu[i] = (int16_t)out.store_par[so + i];
-        st.ev[i] = (int16_t)i;
+    // one batch of loads: entries, then edges (the tree edge of entry e is
+    // its round-0 parent; then the extras)
+#pragma unroll
+    for (int r = 0; r < kReplayEntrySlots; ++r) {
+        const int i = t + r * NT;
+        ec[r] = 0;
+        en[r] = -1;
+        if (i < L0) {
+            ec[r] = out.store_cnt[so + i];
+            en[r] = out.store_node[so + i];
+        }
     }
-    for (int x = t; x < X0; x += NT) {
-        st.eu[L0 + x] = (int16_t)out.xstore_u[xo + x];
-        st.ev[L0 + x] = (int16_t)(out.xstore_v[xo + x] - ns);
+    uint32_t ed[kReplaySlots];
+    uint32_t act = 0;
+#pragma unroll
+    for (int r = 0; r < kReplaySlots; ++r) {
+        const int e = t + r * NT;
+        int u = -1, vi = -1;
+        if (e < L0) {
+            u = out.store_par[so + e];
+            vi = e;
+        } else if (e < E) {
+            u = out.xstore_u[xo + (e - L0)];
+            vi = out.xstore_v[xo + (e - L0)] - ns;
+        }
+        const bool ok = u >= 0 && u < ns + L0 && vi >= 0 && vi < L0;
+        ed[r] = ok ? (((uint32_t)u << 16) | (uint32_t)vi) : 0u;
+        act |= ok ? (1u << r) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kReplayEntrySlots; ++r) {
+        const int i = t + r * NT;
+        if (i < L0) st.nl[i] = (ec[r] <= 0 || en[r] == ustar) ? -2 : -1;
     }
     __syncthreads();
-    int nlev = 1;
+    int nlev = 1;  // closed levels: lvl[0..nlev]
     for (;;) {
         const int f0 = st.lvl[nlev - 1];
         const int f1 = st.lvl[nlev];
         if (f0 == f1) break;
-        for (int e = t; e < E; e += NT) {
-            const int u = st.eu[e];
-            const int vi = st.ev[e];
-            if (u < 0 || u >= ns + L0 || vi < 0 || vi >= L0) continue;  // not a stored local id
-            const int nu = (u < ns) ? u : st.nl[u - ns];
-            if (nu < f0 || nu >= f1) continue;  // the source is not in this level
-            const int old = atomicCAS(&st.nl[vi], -1, -3);
-            if (old == -1) {
-                const int lid = atomicAdd(&sh.count, 1);
-                st.nl[vi] = lid;
-                st.set_parent(lid, nu);
-            } else if (old != -2) {
-                const int x = atomicAdd(&sh.n_extra, 1);
-                if (x < st.cap_x()) {
-                    st.xv[x] = vi;  // resolved to its new id in the dominator phase
-                    st.xu[x] = (int16_t)nu;
-                } else {
-                    sh.overflow = 1;
-                }
+        uint32_t hit = 0;
+#pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r) {
+            if ((act >> r) & 1u) {
+                const int u = (int)(ed[r] >> 16);
+                const int nu = (u < ns) ? u : st.nl[u - ns];
+                if (nu >= f0 && nu < f1) hit |= 1u << r;
+            }
+        }
+        act &= ~hit;
+#pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r) {
+            if ((hit >> r) & 1u) {
+                const int u = (int)(ed[r] >> 16);
+                replay_claim<NT>(st, sh, (int)(ed[r] & 0xFFFFu), (u < ns) ? u : st.nl[u - ns]);
             }
         }
         __syncthreads();
@@ -976,44 +1146,195 @@ __device__ bool bfs_replay(const QueryDev& q, uint32_t w, const TileOut& out, RS
         __syncthreads();
         ++nlev;
     }
-    if (t == 0) {
-        sh.nlevels = nlev - 1;
-        sh.in_bytes = 12ull * (unsigned long long)L0 + 8ull * (unsigned long long)X0;
-    }
+    if (t == 0) sh.nlevels = nlev - 1;
     __syncthreads();
     return true;
 }
 
+// Count changes of a replayed world: each entry's new count against the one
+// held in registers; changes go to the front of the world's own range of
+// dl_* (wave-wide ballots, no shared counter) and the counts are updated in
+// place.
+template <int NT, class RS>
+__device__ int replay_outputs(const ReplayItem& it, const TileOut& out, RS& st, WorldShared<NT>& sh,
+                              const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots]) {
+    const int t = threadIdx.x;
+    const int ns = st.ns;
+    const size_t so = (size_t)it.store_off;
+    const int L0 = it.store_len;
+    const unsigned long long below = (1ull << t) - 1ull;
+    int nd = 0;
+#pragma unroll
+    for (int r = 0; r < kReplayEntrySlots; ++r) {
+        const int i = t + r * NT;
+        int cn = 0, d = 0;
+        if (i < L0 && ec[r] > 0) {
+            const int lid = st.nl[i];
+            cn = (lid >= ns) ? st.aux[lid - ns] : 0;
+            d = cn - ec[r];
+            // the dominator tree may have changed shape: every reached
+            // entry takes its new label
+            if (cn > 0) out.store_lab[so + i] = pack_label(st.get_tin(lid), cn);
+        }
+        const unsigned long long mask = __ballot(d != 0);
+        if (d != 0) {
+            const size_t pos = so + (size_t)(nd + __popcll(mask & below));
+            out.dl_node[pos] = en[r];
+            out.dl_cnt[pos] = d;
+            out.store_cnt[so + i] = cn;
+        }
+        nd += __popcll(mask);
+    }
+    if (t == 0) {
+        out.wlen[it.w] = nd;
+        out.world_size[it.w] = sh.count;
+        if (out.world_tree) out.world_tree[it.w] = (sh.n_extra == 0) ? 1 : 0;
+    }
+    return nd;
+}
+
 // Incremental rounds: every changed world is first replayed; a world that
 // does not fit the replay store goes on to the sampling tiers (list 1).
-__global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl* ctl, const int32_t* in_list,
-                                                             int32_t* next_list, TileOut out) {
+// The next world's item is loaded while the current one is replayed.
+__global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl* ctl, int32_t* next_list,
+                                                             TileOut out) {
     __shared__ ReplayStoreT st;
     __shared__ WorldShared<kReplayNT> sh;
     const int t = threadIdx.x;
     if (ctl->stop) return;
     const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
     if (blockIdx.x >= n_items) return;
-    if (t == 0) {
-        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
-        sh.acc_dsize = 0;
-    }
-    __syncthreads();
+    const int32_t ustar = ctl->ustar;
+    unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
+    long long acc_d = 0;
+    ReplayItem cur = out.items[blockIdx.x];
     for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
-        const uint32_t w = (uint32_t)in_list[k];
-        if (bfs_replay<kReplayNT>(q, w, out, st, sh)) {
-            finish_world<kReplayNT, 0>(q, ctl, w, w, out, st, sh);
+        ReplayItem nxt = cur;
+        if (k + gridDim.x < n_items) nxt = out.items[k + gridDim.x];
+        int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
+        if (bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en)) {
+            world_counts<kReplayNT>(q, ctl, st, sh);
+            world_labels<kReplayNT>(q, st, sh);
+            const int nd = replay_outputs<kReplayNT>(cur, out, st, sh, ec, en);
+            acc_w += 1;
+            acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
+            acc_b += 32ull + 12ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
+                     12ull * (unsigned long long)nd + 8ull;
+            acc_d += (long long)cur.world_size - (long long)sh.count;
         } else if (t == 0) {
             const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
-            if (pos < out.next_cap) next_list[pos] = (int32_t)w;
+            if (pos < out.next_cap) next_list[pos] = cur.w;
             else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         }
         __syncthreads();
+        cur = nxt;
     }
     if (t == 0) {
-        add_work(out, 3, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
-        if (sh.acc_dsize) atomicAdd((unsigned long long*)&ctl->total, (unsigned long long)(-sh.acc_dsize));
+        add_work(out, 3, acc_w, acc_e, acc_b);
+        // T is lowered by the nodes the replayed worlds lost
+        if (acc_d) out.dsz[out.dsz_off[3] + blockIdx.x] = acc_d;
     }
+}
+
+// ------------------------------------------------------- forest worlds
+// In a world whose reached live edges form a forest under the seeds, the
+// dominator tree is that forest.  Blocking u removes exactly u's subtree
+// (its entries' counts become 0) and lowers the count of each of u's
+// ancestors by count(u); no other count changes.  Subtree and ancestors
+// are read off the labels: entry i lies in u's subtree when
+// tin(u) <= tin(i) < tin(u) + size(u), and is an ancestor of u when
+// tin(i) <= tin(u) < tin(i) + size(i).  One wave per world, one pass over
+// its entries; removing a subtree keeps the rest a forest with valid labels.
+constexpr int kTreeUnroll = 4;
+
+__global__ __launch_bounds__(kTreeNT) void k_tree_update(RoundCtl* ctl, TileOut out) {
+    __shared__ unsigned long long red[kTreeNT / 64][4];
+    if (ctl->stop) return;
+    const uint32_t n = min(ctl->tree_n, out.list_cap);
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
+    long long acc_d = 0;
+    for (uint32_t k = blockIdx.x * (kTreeNT / 64) + wid; k < n; k += gridDim.x * (kTreeNT / 64)) {
+        const ReplayItem it = out.titems[k];
+        const size_t so = (size_t)it.store_off;
+        const int L0 = it.store_len;
+        if (it.store_off < 0 || L0 < 0 || so + (size_t)L0 > out.store_cap || so + (size_t)L0 > out.dl_cap) {
+            if (lane == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            continue;  // uniform over the wave
+        }
+        const int tj = (int)(it.labj >> 16);
+        const int szj = (int)(it.labj & 0xFFFFu);
+        const int cj = it.cj;
+        int nd = 0;
+        for (int b0 = 0; b0 < L0; b0 += 64 * kTreeUnroll) {
+            int c[kTreeUnroll], v[kTreeUnroll];
+            uint32_t lab[kTreeUnroll];
+#pragma unroll
+            for (int r = 0; r < kTreeUnroll; ++r) {
+                const int i = b0 + r * 64 + lane;
+                c[r] = 0;
+                v[r] = 0;
+                lab[r] = 0;
+                if (i < L0) {
+                    c[r] = out.store_cnt[so + i];
+                    v[r] = out.store_node[so + i];
+                    lab[r] = out.store_lab[so + i];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kTreeUnroll; ++r) {
+                const int i = b0 + r * 64 + lane;
+                int d = 0, cn = 0;
+                if (c[r] > 0) {
+                    const int ti = (int)(lab[r] >> 16);
+                    const int si = (int)(lab[r] & 0xFFFFu);
+                    if (ti >= tj && ti < tj + szj) {
+                        d = -c[r];  // u's subtree, u included: no longer reached
+                    } else if (tj >= ti && tj < ti + si) {
+                        d = -cj;  // an ancestor of u
+                        cn = c[r] - cj;
+                    }
+                }
+                const unsigned long long mask = __ballot(d != 0);
+                if (d != 0) {
+                    const size_t pos = so + (size_t)(nd + __popcll(mask & below));
+                    out.dl_node[pos] = v[r];
+                    out.dl_cnt[pos] = d;
+                    out.store_cnt[so + i] = cn;
+                }
+                nd += __popcll(mask);
+            }
+        }
+        if (lane == 0) {
+            out.wlen[it.w] = nd;
+            out.world_size[it.w] = it.world_size - cj;
+        }
+        acc_w += 1;
+        acc_e += (unsigned long long)L0;
+        acc_b += sizeof(ReplayItem) + 12ull * (unsigned long long)L0 + 12ull * (unsigned long long)nd + 8ull;
+        acc_d += cj;
+    }
+    if (lane == 0) {
+        red[wid][0] = acc_w;
+        red[wid][1] = acc_e;
+        red[wid][2] = acc_b;
+        red[wid][3] = (unsigned long long)acc_d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long f[4] = {0, 0, 0, 0};
+        for (int x = 0; x < kTreeNT / 64; ++x)
+            for (int y = 0; y < 4; ++y) f[y] += red[x][y];
+        add_work(out, 4, f[0], f[1], f[2]);
+        if (f[3]) out.dsz[out.dsz_off[4] + blockIdx.x] = (long long)f[3];
+    }
+}
+
+hipError_t launch_tree_update(RoundCtl* ctl, const TileOut& out, int grid, hipStream_t s) {
+    k_tree_update<<<grid, kTreeNT, 0, s>>>(ctl, out);
+    return hipGetLastError();
 }
 
 int world_replay_blocks_per_cu() {
@@ -1022,9 +1343,9 @@ int world_replay_blocks_per_cu() {
     return b < 1 ? 1 : b;
 }
 
-hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, const int32_t* in_list, int32_t* next_list,
-                               const TileOut& out, int grid, hipStream_t s) {
-    k_world_replay<<<grid, kReplayNT, 0, s>>>(q, ctl, in_list, next_list, out);
+hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out, int grid,
+                               hipStream_t s) {
+    k_world_replay<<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out);
     return hipGetLastError();
 }
 

@@ -163,19 +163,22 @@ def test_solve_random_graphs(B, oracle_mod, case):
 
 
 @pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7", "noreplay",
-                                     "xscratch", "tiles"])
+                                     "noforest", "xscratch", "tiles"])
 def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
-    """Incremental rounds (default: changed worlds replayed from their stored
-    live edges), plain rounds, a resident store too small to hold round 0
-    (falls back to plain rounds), re-evaluation by sampling on every tier,
-    regrowth of the extra-edge scratch and several tiles all give the
-    oracle's selection."""
+    """Incremental rounds (default: forest worlds updated from their labels,
+    other changed worlds replayed from their stored live edges), replay
+    without the forest update, plain rounds, a resident store too small to
+    hold round 0 (falls back to plain rounds), re-evaluation by sampling on
+    every tier, regrowth of the extra-edge scratch and several tiles all give
+    the oracle's selection."""
     if variant == "plain":
         monkeypatch.setenv("IMIN_INCREMENTAL", "0")
     elif variant == "store_overflow":
         monkeypatch.setenv("IMIN_STORE_CAP", "5000")
     elif variant == "noreplay":
         monkeypatch.setenv("IMIN_REPLAY", "0")
+    elif variant == "noforest":
+        monkeypatch.setenv("IMIN_FOREST", "0")
     elif variant == "xscratch":
         monkeypatch.setenv("IMIN_XBIG_SCRATCH", "16")
         monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
