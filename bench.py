@@ -45,17 +45,16 @@ def percentile(xs, q):
     return xs[i]
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "large_world_tier0_traffic.md")
 KERNEL_SOURCES = ["imin_world.hip", "imin_device.hpp", "imin_internal.hpp"]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the tier-0 world kernel from the committed
-    FETCH_SIZE / WRITE_SIZE profile, or None when the kernel sources have
-    changed since the counters were taken."""
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a world kernel from its committed FETCH_SIZE /
+    WRITE_SIZE profile, or None when there is none or the kernel sources
+    have changed since the counters were taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", f"large_{kernel}_traffic.md")).read()
     except OSError:
         return None
     fields = {}
@@ -120,8 +119,8 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB copy first (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the estimator shards "
-              f"by world range, see the design notes; no multi-GPU run is part of this build)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the estimator would shard "
+              f"by world range, one range per GPU, and this benchmark drives a single device",
               file=sys.stderr)
         sys.exit(2)
 
@@ -177,17 +176,29 @@ def main():
         f"(tier0 {r0[0][1]:.3f}, tier1 {r0[4][1]:.3f}, tier2 {r0[1][1]:.3f}), reduce {r0[2][1]:.3f} ms, "
         f"wall {r0_wall * 1e3:.1f} ms, {r0_bytes / r0_world_ms / 1e6:.0f} GB/s algorithmic")
 
-    # timed solves
+    # solves: the warm-up solves time every kernel (per-kernel breakdown);
+    # the timed solves bracket only the dominant world kernel with events
     out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
            torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
            torch.zeros(k + 1, dtype=torch.int64, device=dev),
            torch.zeros(1, dtype=torch.int32, device=dev))
-    for i in range(args.warmup):
+    kernels = (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("changed_worlds", 6),
+               ("reduce", 2), ("select", 3), ("affected_search", 5))
+    kern = {}
+    for i in range(max(args.warmup, 1)):
+        binding.timing_reset()
         binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)
         torch.cuda.synchronize()
+        kern = {name: binding.timing_read(kid)[1] for name, kid in kernels}
         log(f"warmup {i} done")
-    before = {kid: binding.timing_read(kid) for kid in range(8)}
-    work_before = [binding.timing_work(t) for t in range(5)]
+    # the world kernel with the most time per solve
+    # kernel -> (timer id, work tiers it reports)
+    world_ids = {"world_tier0": (0, (0,)), "world_tier1": (4, (1,)), "world_tier2": (1, (2,)),
+                 "changed_worlds": (6, (3, 4))}
+    dom = max(world_ids, key=lambda nm: kern.get(nm, 0.0))
+    dom_kid, dom_tiers = world_ids[dom]
+    binding.timing_mask([dom_kid])
+    binding.timing_reset()
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -199,22 +210,18 @@ def main():
         log(f"step {i}: {lat[-1]:.1f} ms")
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
-    after = {kid: binding.timing_read(kid) for kid in range(8)}
-    work_after = [binding.timing_work(t) for t in range(5)]
+    work = [binding.timing_work(t) for t in range(5)]
+    n_dom, ms_dom = binding.timing_read(dom_kid)
+    binding.timing_enable(False)
+    binding.timing_mask(None)
     n_sel = int(out[3].cpu()[0])
     rounds = min(n_sel + 1, k) if k > 0 else 1
     ms_per_step = total_s * 1e3 / args.steps
-    evals = sum(work_after[t][0] - work_before[t][0] for t in range(5)) / args.steps
+    evals = sum(w[0] for w in work) / args.steps
     value = evals / (ms_per_step / 1e3)
-    kern = {name: (after[kid][1] - before[kid][1]) / args.steps
-            for name, kid in (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("reduce", 2),
-                              ("select", 3), ("affected_search", 5), ("world_replay", 6),
-                              ("forest_update", 7))}
-    # roofline of the dominant kernel over every launch in this process
-    n0, ms0 = binding.timing_read(0)
-    _, _, bytes0 = binding.timing_work(0)
-    binding.timing_enable(False)
-    achieved = bytes0 / (ms0 / 1e3) / 1e9
+    # roofline of the dominant world kernel over its launches in the timed solves
+    bytes_dom = sum(work[t][2] for t in dom_tiers)
+    achieved = bytes_dom / (ms_dom / 1e3) / 1e9 if ms_dom > 0 else 0.0
 
     spread = out[2].cpu().numpy()
     res = {
@@ -254,18 +261,21 @@ def main():
         "Rbar": float(R.mean()),
         "Ebar": float(E.mean()),
         "kernel_ms_per_step": kern,
+        "world_evaluations_by_kind_per_step": {
+            nm: work[t][0] / args.steps for nm, t in (("sampled_tier0", 0), ("sampled_tier1", 1), ("sampled_tier2", 2),
+                                                       ("replayed", 3), ("forest_updated", 4))},
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_world_lds tier 0 (one wave per world), all launches of this run",
+            "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic() if args.workload == "large" else None,
-            "traffic_unit": "bytes per launch (scaled FETCH_SIZE + WRITE_SIZE, committed profile)",
-            "launches": n0,
-            "avg_launch_ms": ms0 / max(n0, 1),
-            "algorithmic_bytes_per_launch": bytes0 / max(n0, 1),
+            "traffic": measured_traffic(dom) if args.workload == "large" else None,
+            "traffic_unit": "HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE, committed profile)",
+            "launches": n_dom,
+            "avg_launch_ms": ms_dom / max(n_dom, 1),
+            "algorithmic_bytes_per_launch": bytes_dom / max(n_dom, 1),
         },
     }
     if not args.no_cpu:

@@ -146,18 +146,24 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  * each launch's duration to a per-kernel tally (process-wide).  Kernel ids:
  *   0  world evaluation, small LDS tier (one wave per world)
  *   1  world evaluation, HBM tier (four waves per world, any size)
- *   2  gain reduction (bucket histogram, scan, scatter, accumulate, sum)
+ *   2  gain reduction of a from-scratch pass (bucket histogram, scan,
+ *      scatter, accumulate, sum); incremental rounds add their changes to
+ *      the gains inside kernels 1, 4, 6 and 7
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
  *   5  search for the worlds a new blocker changes (incremental rounds)
- *   6  replay of a changed world from its stored live edges (incremental
- *      rounds; worlds too large for it go on to kernels 4 and 1)
- *   7  count update of a changed world whose reached live edges form a
- *      forest (incremental rounds)
+ *   6  update of the changed worlds of an incremental round, one launch:
+ *      label-based count update of the worlds whose reached live edges
+ *      form a forest, and replay of the others from their stored live
+ *      edges (worlds too large for the replay go on to kernels 4 and 1)
+ *   7  (unused)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */
 imin_status_t imin_timing_enable(int on);
+/* Bit i set: kernel id i is bracketed with events while timing is enabled
+ * (default: all).  Work tallies are kept whatever the mask. */
+imin_status_t imin_timing_mask(uint32_t kernel_mask);
 imin_status_t imin_timing_reset(void);
 imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_ms);
 

@@ -65,6 +65,8 @@ def load():
     lib.imin_last_device_flags.restype = ctypes.c_uint32
     lib.imin_timing_enable.argtypes = [ctypes.c_int]
     lib.imin_timing_enable.restype = st
+    lib.imin_timing_mask.argtypes = [ctypes.c_uint32]
+    lib.imin_timing_mask.restype = st
     lib.imin_timing_reset.argtypes = []
     lib.imin_timing_reset.restype = st
     lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -227,6 +229,12 @@ def timing_enable(on: bool = True):
     _check(load().imin_timing_enable(1 if on else 0))
 
 
+def timing_mask(kernel_ids=None):
+    """Bracket only these kernel ids with events (None: all)."""
+    mask = 0xFFFFFFFF if kernel_ids is None else sum(1 << int(i) for i in kernel_ids)
+    _check(load().imin_timing_mask(mask))
+
+
 def timing_reset():
     _check(load().imin_timing_reset())
 
@@ -240,7 +248,8 @@ def timing_read(kernel_id: int):
 
 
 def timing_work(tier: int):
-    """(worlds, CSR slots scanned, algorithmic bytes) of one world tier since the last reset."""
+    """(worlds, edges walked, algorithmic bytes) of one world tier (0-2 sampled
+    tiers, 3 replay, 4 forest update) since the last reset."""
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().imin_timing_work(int(tier), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return int(a.value), int(b.value), int(c.value)

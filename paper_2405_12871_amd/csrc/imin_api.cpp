@@ -26,6 +26,7 @@ constexpr int kTimedKernels = 8;
 constexpr int kWorkTiers = 5;  // tiers 0-2, replay, forest update
 struct Timing {
     std::atomic<bool> on{false};
+    std::atomic<uint32_t> mask{0xFFFFFFFFu};  // kernels bracketed with events
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
     double ms[kTimedKernels] = {};
@@ -66,8 +67,9 @@ struct TimedLaunches {
     };
     std::vector<Rec> recs;
     bool on = g_timing.on.load();
-    hipEvent_t begin(hipStream_t s) {
-        if (!on) return nullptr;
+    uint32_t mask = g_timing.mask.load();
+    hipEvent_t begin(int id, hipStream_t s) {
+        if (!on || !((mask >> id) & 1u)) return nullptr;
         hipEvent_t e = event_acquire();
         if (e) (void)hipEventRecord(e, s);
         return e;
@@ -175,7 +177,7 @@ struct Session {
     DevArray<int64_t> part;
     imin::ReduceBufs rb{};
     // resident per-world (node, count) lists for incremental rounds
-    DevArray<int32_t> store_node, store_cnt, store_len, dl_node, dl_cnt;
+    DevArray<int32_t> store_node, store_cnt, store_len;
     DevArray<int64_t> store_off;
     // replay of changed worlds from their stored live edges: BFS parents
     // beside the pairs, extra edges (local ids) in a store of their own
@@ -219,6 +221,12 @@ struct Session {
     size_t tile = 0;       // worlds per tile in use
     int grid0 = 0, grid1 = 0;
     int start_tier = 0;    // first tier tried for every world of a tile
+    // Some world of the from-scratch pass needed the HBM tier.  Worlds only
+    // shrink as blockers are added and the large LDS tier holds any world
+    // that fitted it before, so without such a world incremental rounds
+    // never reach the HBM tier and do not launch it.
+    bool any_tier2 = false;
+    int last_tier() const { return any_tier2 ? 2 : 1; }
     TimedLaunches timed;
 
     Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
@@ -294,8 +302,9 @@ struct Session {
         IMIN_TRY(sel_d.alloc(sel_parts));
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
-        grid_r = cus * imin::world_replay_blocks_per_cu();
-        grid_t = cus * 4;
+        // changed-world update: replay and forest workgroups of one launch
+        grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
+        grid_t = cus * (int)env_size("IMIN_FOREST_WG_PER_CU", 4);
         {
             const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_t};
             int32_t at = 0;
@@ -453,7 +462,7 @@ struct Session {
     }
 
     // node -> (store position, world) of every entry written in round 0;
-    // also the change buffers of incremental rounds
+    // and the changed-world item lists of incremental rounds
     imin_status_t build_index(uint64_t theta) {
         const unsigned long long entries = hctl.p->store_count;
         const size_t n = (size_t)g.n;
@@ -462,8 +471,6 @@ struct Session {
         IMIN_TRY(idx_cursor.alloc(n + 1));
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
-        IMIN_TRY(dl_node.alloc(entries));
-        IMIN_TRY(dl_cnt.alloc(entries));
         IMIN_TRY(items.alloc(theta));
         IMIN_TRY(titems.alloc(theta));
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
@@ -493,9 +500,7 @@ struct Session {
         out.store_cap = store_node.count;
         out.store_off = store_off.p;
         out.store_len = store_len.p;
-        out.dl_node = dl_node.p;
-        out.dl_cnt = dl_cnt.p;
-        out.dl_cap = dl_node.count;
+        out.gain = gain.p;
         out.list_cap = (uint32_t)std::min<size_t>(items.p ? std::min(list0.count, items.count) : list0.count,
                                                   0xFFFFFFFFu);
         out.items = items.p;
@@ -525,17 +530,17 @@ struct Session {
         return out;
     }
 
-    // Tiers first_tier..2; the first reads first_list (count list_n[first_idx])
-    // or, without a list, worlds [wb, wb+range).
+    // Tiers first_tier..last_tier; the first reads first_list (count
+    // list_n[first_idx]) or, without a list, worlds [wb, wb+range).
     imin_status_t launch_tiers(const imin::QueryDev& q, uint32_t wb, uint32_t range, const int32_t* first_list,
-                               const imin::TileOut& out, int first_tier, int first_idx = 0) {
-        for (int tier = first_tier; tier < 3; ++tier) {
+                               const imin::TileOut& out, int first_tier, int first_idx = 0, int last_tier = 2) {
+        for (int tier = first_tier; tier <= last_tier; ++tier) {
             const bool first = (tier == first_tier);
             const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : list2.p);
             const int count_idx = first ? first_idx : tier;
             int32_t* next_list = tier == 0 ? list1.p : list2.p;
             const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
-            hipEvent_t ev = timed.begin(s);
+            hipEvent_t ev = timed.begin(timer_id, s);
             IMIN_TRY(imin::launch_world_tier(tier, g, q, ctl.p, wb, first_list ? 0u : range, in_list, count_idx,
                                              next_list, out, bs, tier == 0 ? grid0 : grid1, s));
             timed.end(timer_id, ev, s);
@@ -549,28 +554,22 @@ struct Session {
         imin::TileOut out = tile_out();
         out.mode = imin::kModeDelta;
         out.world_size = world_size.p;
-        IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-        hipEvent_t ev = timed.begin(s);
+        // the per-round counters were cleared by the last selection
+        hipEvent_t ev = timed.begin(5, s);
         IMIN_TRY(imin::launch_affected(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, s));
         timed.end(5, ev, s);
         imin_status_t st;
         if (replay) {
-            // forest worlds: subtree removal from the labels
-            ev = timed.begin(s);
-            IMIN_TRY(imin::launch_tree_update(ctl.p, out, grid_t, s));
-            timed.end(7, ev, s);
-            // replay every other changed world; those too large go on to sampling
-            ev = timed.begin(s);
-            IMIN_TRY(imin::launch_world_replay(q, ctl.p, list1.p, out, grid_r, s));
+            // forest worlds: subtree removal from the labels; every other
+            // changed world is replayed, those too large go on to sampling
+            ev = timed.begin(6, s);
+            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, grid_t, s));
             timed.end(6, ev, s);
-            st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1);
+            st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());
         } else {
-            st = launch_tiers(q, 0, 0, list0.p, out, start_tier);
+            st = launch_tiers(q, 0, 0, list0.p, out, start_tier, 0, last_tier());
         }
         if (st != IMIN_OK) return st;
-        ev = timed.begin(s);
-        IMIN_TRY(imin::launch_delta_reduce(g, out, ctl.p, gain.p, cu_count() * 4, s));
-        timed.end(2, ev, s);
         // T is carried over from the last round and lowered by the changed
         // worlds themselves: no pass over all theta sizes
         (void)theta;
@@ -600,6 +599,7 @@ struct Session {
             st = read_ctl();
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
+            if (hctl.p->list_n[2] > 0 || start_tier == 2) any_tier2 = true;
             // route later tiles straight to the tier most worlds end up in
             if (start_tier < 2 && hctl.p->list_n[2] * 2 > nw) start_tier = 2;
             else if (start_tier < 1 && hctl.p->list_n[1] * 2 > nw) start_tier = 1;
@@ -642,7 +642,7 @@ struct Session {
             // tile whichever buffer holds them
             st = ensure_pairs(total);
             if (st != IMIN_OK) return st;
-            hipEvent_t ev = timed.begin(s);
+            hipEvent_t ev = timed.begin(2, s);
             imin::CompactSpec cs{};
             cs.src[0] = scr_node.p;
             cs.src[1] = scr_cnt.p;
@@ -851,7 +851,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             for (int32_t i = 0; i < nb; ++i) {
                 st = ss.evaluate_delta(q, (uint64_t)theta);
                 if (st != IMIN_OK) return st;
-                hipEvent_t ev = ss.timed.begin(s);
+                hipEvent_t ev = ss.timed.begin(3, s);
                 IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p,
                                              ss.sel_d.p, ss.dsz.p, ss.dsz_n, ss.sel_parts, k, blockers, gains,
                                              spread_totals, n_selected, s));
@@ -863,7 +863,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
             st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, r == 0);
             if (st != IMIN_OK) return st;
-            hipEvent_t ev = ss.timed.begin(s);
+            hipEvent_t ev = ss.timed.begin(3, s);
             IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_d.p,
                                          ss.dsz.p, ss.dsz_n, ss.sel_parts,
                                          k, blockers, gains, spread_totals, n_selected, s));
@@ -911,6 +911,11 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
 
 imin_status_t imin_timing_enable(int on) {
     g_timing.on.store(on != 0);
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_mask(uint32_t kernel_mask) {
+    g_timing.mask.store(kernel_mask);
     return IMIN_OK;
 }
 

@@ -84,4 +84,49 @@ __device__ __forceinline__ long long block_sum_ll(long long x, long long* tmp) {
     }
 }
 
+// Per-workgroup sums keyed by node id in LDS: open addressing with linear
+// probing over 2^LOG slots (key -1 = empty).  A sum that finds no slot goes
+// straight to `spill[u]`.  Integer sums, so the order of additions does not
+// matter.
+template <int LOG>
+struct LdsSums {
+    static constexpr int kSlots = 1 << LOG;
+    static constexpr int kProbes = 32;
+    int32_t keys[kSlots];
+    unsigned long long vals[kSlots];
+
+    template <int NT>
+    __device__ void clear() {
+        for (int i = threadIdx.x; i < kSlots; i += NT) {
+            keys[i] = -1;
+            vals[i] = 0;
+        }
+    }
+    __device__ void add(int32_t u, long long d, int64_t* spill) {
+        const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - LOG);
+        for (int p = 0; p < kProbes; ++p) {
+            const uint32_t sl = (h + (uint32_t)p) & (kSlots - 1);
+            int32_t k = keys[sl];
+            if (k == -1) {
+                k = atomicCAS(&keys[sl], -1, u);
+                if (k == -1) k = u;
+            }
+            if (k == u) {
+                atomicAdd(&vals[sl], (unsigned long long)d);
+                return;
+            }
+        }
+        atomicAdd((unsigned long long*)&spill[u], (unsigned long long)d);
+    }
+    // add every nonzero sum to out[key]; after a workgroup barrier
+    template <int NT>
+    __device__ void flush(int64_t* out) {
+        for (int i = threadIdx.x; i < kSlots; i += NT) {
+            const int32_t k = keys[i];
+            const unsigned long long v = vals[i];
+            if (k >= 0 && v != 0) atomicAdd((unsigned long long*)&out[k], v);
+        }
+    }
+};
+
 }  // namespace imin

@@ -138,9 +138,7 @@ struct TileOut {
     unsigned long long store_cap;
     int64_t* store_off;  // [theta]
     int32_t* store_len;  // [theta]
-    int32_t* dl_node;    // [store entries] count changes, at the world's store positions
-    int32_t* dl_cnt;
-    unsigned long long dl_cap;
+    int64_t* gain;       // incremental rounds: count changes are added here
     uint32_t list_cap;   // entries of the changed-world list
     uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
     ReplayItem* items;   // changed worlds to re-evaluate, with their store ranges (list_cap of them)
@@ -242,14 +240,12 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
 hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
-// gain += the count changes the changed worlds of items[0 .. list_n[0]) wrote
-hipError_t launch_delta_reduce(const GraphDev& g, const TileOut& out, RoundCtl* ctl, int64_t* gain, int grid,
-                               hipStream_t s);
-hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out, int grid,
-                               hipStream_t s);
-hipError_t launch_tree_update(RoundCtl* ctl, const TileOut& out, int grid, hipStream_t s);
+// Changed worlds of an incremental round: replay_parts workgroups replay the
+// worlds of items (those too large go to next_list), forest_parts update the
+// forest worlds of titems.
+hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                                 int replay_parts, int forest_parts, hipStream_t s);
 constexpr int kTreeNT = 256;  // four worlds at a time per workgroup
-int world_replay_blocks_per_cu();
 hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
@@ -268,7 +264,7 @@ hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const Redu
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
 // Argmax of gain over the candidates (ties to the smaller id), the stop rule
 // and the round's T; also sums and clears the dsz slots (nodes lost by the
-// round's changed worlds) into T.
+// round's changed worlds) into T and clears the per-round counters.
 hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl, RoundCtl* ctl,
                          int64_t* part_gain, int32_t* part_node, long long* part_dsz, long long* dsz,
                          int32_t dsz_n, int parts, int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,

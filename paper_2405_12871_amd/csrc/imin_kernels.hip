@@ -306,120 +306,6 @@ hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const Redu
     return e;
 }
 
-// ------------------------------------------------ incremental-round gains
-// The changed worlds of a round (items[0 .. list_n[0]) and titems[0 .. tree_n))
-// report their count changes at their own store positions (dl_*, wlen[w] of
-// them).  Each workgroup takes chunks of
-// worlds, adds their changes into an LDS hash table and finally adds the
-// table's nonzero sums to gain with 64-bit atomics: integer sums, so the
-// order does not matter.  A node shared by many worlds costs one global
-// update per workgroup; a change that finds no free slot goes to gain
-// directly.
-constexpr int kDeltaNT = 256;
-constexpr int kDeltaChunk = 64;      // worlds per chunk
-constexpr int kDeltaSlotsLog = 11;
-constexpr int kDeltaSlots = 1 << kDeltaSlotsLog;
-constexpr int kDeltaProbes = 32;
-constexpr int kDeltaUnroll = 4;
-
-__device__ __forceinline__ void delta_insert(int32_t* keys, unsigned long long* vals, int32_t u, long long d,
-                                             int64_t* gain) {
-    const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - kDeltaSlotsLog);
-    for (int p = 0; p < kDeltaProbes; ++p) {
-        const uint32_t sl = (h + (uint32_t)p) & (kDeltaSlots - 1);
-        int32_t k = keys[sl];
-        if (k == -1) {
-            k = atomicCAS(&keys[sl], -1, u);
-            if (k == -1) k = u;
-        }
-        if (k == u) {
-            atomicAdd(&vals[sl], (unsigned long long)d);
-            return;
-        }
-    }
-    atomicAdd((unsigned long long*)&gain[u], (unsigned long long)d);
-}
-
-__global__ __launch_bounds__(kDeltaNT) void k_delta_reduce(TileOut out, RoundCtl* ctl, int32_t n, int64_t* gain) {
-    __shared__ int32_t keys[kDeltaSlots];
-    __shared__ unsigned long long vals[kDeltaSlots];
-    __shared__ int tmp[kDeltaNT / 64];
-    __shared__ int start_sh[kDeltaChunk];
-    __shared__ long long off_sh[kDeltaChunk];
-    const int t = threadIdx.x;
-    if (ctl->stop) return;
-    // the re-evaluated worlds, then the forest worlds
-    const uint32_t n_re = min(ctl->list_n[0], out.list_cap);
-    const uint32_t n_items = n_re + (out.titems ? min(ctl->tree_n, out.list_cap) : 0u);
-    if ((unsigned long long)blockIdx.x * kDeltaChunk >= n_items) return;
-    for (int i = t; i < kDeltaSlots; i += kDeltaNT) {
-        keys[i] = -1;
-        vals[i] = 0;
-    }
-    for (uint32_t b0 = blockIdx.x * kDeltaChunk; b0 < n_items; b0 += gridDim.x * kDeltaChunk) {
-        int len = 0;
-        long long so = 0;
-        if (t < kDeltaChunk && b0 + t < n_items) {
-            const uint32_t k = b0 + t;
-            const ReplayItem& it = (k < n_re) ? out.items[k] : out.titems[k - n_re];
-            so = it.store_off;
-            len = out.wlen[it.w];
-            if (len < 0 || so < 0 || (unsigned long long)so + (unsigned long long)len > out.dl_cap) {
-                atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
-                len = 0;
-            }
-        }
-        int tot;
-        const int ex = block_excl_scan<kDeltaNT>(len, tmp, tot);
-        if (t < kDeltaChunk) {
-            start_sh[t] = ex;
-            off_sh[t] = so;
-        }
-        __syncthreads();
-        for (int j0 = t; j0 < tot; j0 += kDeltaNT * kDeltaUnroll) {
-            int32_t u[kDeltaUnroll];
-            int d[kDeltaUnroll];
-#pragma unroll
-            for (int r = 0; r < kDeltaUnroll; ++r) {
-                const int j = j0 + r * kDeltaNT;
-                u[r] = -1;
-                d[r] = 0;
-                if (j < tot) {
-                    int lo = 0, hi = kDeltaChunk - 1;  // the last world whose range starts at or before j
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (start_sh[mid] <= j) lo = mid; else hi = mid - 1;
-                    }
-                    const size_t pos = (size_t)off_sh[lo] + (size_t)(j - start_sh[lo]);
-                    u[r] = out.dl_node[pos];
-                    d[r] = out.dl_cnt[pos];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kDeltaUnroll; ++r) {
-                if (u[r] < 0 && d[r] == 0) continue;  // no entry
-                if (u[r] < 0 || u[r] >= n) {
-                    atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
-                    continue;
-                }
-                delta_insert(keys, vals, u[r], d[r], gain);
-            }
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < kDeltaSlots; i += kDeltaNT) {
-        const int32_t k = keys[i];
-        const unsigned long long v = vals[i];
-        if (k >= 0 && v != 0) atomicAdd((unsigned long long*)&gain[k], v);
-    }
-}
-
-hipError_t launch_delta_reduce(const GraphDev& g, const TileOut& out, RoundCtl* ctl, int64_t* gain, int grid,
-                               hipStream_t s) {
-    k_delta_reduce<<<grid, kDeltaNT, 0, s>>>(out, ctl, g.n, gain);
-    return hipGetLastError();
-}
-
 __global__ void k_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl) {
     __shared__ long long tmp[4];
     if (ctl->stop) return;
@@ -508,13 +394,46 @@ __device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32
     return g1 > g2 || (g1 == g2 && u1 < u2);
 }
 
+// Two launches: every workgroup of the first reduces a slice of the
+// candidates (and of the dsz slots) to a part; one workgroup combines the
+// parts and applies the round's selection.  After a selection it also clears
+// the per-round counters for the next incremental round.  (A single launch
+// whose last workgroup combines the parts needs a counter that every
+// workgroup updates, and same-address atomics serialise.)
+__device__ __forceinline__ void select_block_best(int64_t& bg, int32_t& bu, long long& dl, int64_t* sg,
+                                                  int32_t* su, long long* sd) {
+    sg[threadIdx.x] = bg;
+    su[threadIdx.x] = bu;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            const int o = threadIdx.x + d;
+            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
+                sg[threadIdx.x] = sg[o];
+                su[threadIdx.x] = su[o];
+            }
+        }
+        __syncthreads();
+    }
+    dl = block_sum_ll<256>(dl, sd);
+    bg = sg[0];
+    bu = su[0];
+}
+
 __global__ __launch_bounds__(256) void k_select_partial(const RoundCtl* ctl, int32_t n, const int64_t* gain,
                                                         const uint32_t* excl, int64_t* pg, int32_t* pu,
                                                         long long* dsz, int32_t dsz_n, long long* pd) {
-    if (ctl->stop) return;
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
     __shared__ long long sd[4];
+    if (ctl->stop) return;
+    int64_t bg = 0;
+    int32_t bu = -1;
+    for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
+        if (bit_set(excl, u)) continue;
+        const int64_t gv = gain[u];
+        if (better(gv, u, bg, bu)) { bg = gv; bu = u; }
+    }
     // nodes lost by the changed worlds of the round: this part's slots
     long long dl = 0;
     if (dsz) {
@@ -526,38 +445,18 @@ __global__ __launch_bounds__(256) void k_select_partial(const RoundCtl* ctl, int
             dsz[i] = 0;
         }
     }
-    dl = block_sum_ll<256>(dl, sd);
-    int64_t bg = 0;
-    int32_t bu = -1;
-    for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
-        if (bit_set(excl, u)) continue;
-        const int64_t gv = gain[u];
-        if (better(gv, u, bg, bu)) { bg = gv; bu = u; }
-    }
-    sg[threadIdx.x] = bg;
-    su[threadIdx.x] = bu;
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if (threadIdx.x < d) {
-            const int o = threadIdx.x + d;
-            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
-                sg[threadIdx.x] = sg[o];
-                su[threadIdx.x] = su[o];
-            }
-        }
-        __syncthreads();
-    }
+    select_block_best(bg, bu, dl, sg, su, sd);
     if (threadIdx.x == 0) {
-        pg[blockIdx.x] = sg[0];
-        pu[blockIdx.x] = su[0];
+        pg[blockIdx.x] = bg;
+        pu[blockIdx.x] = bu;
         pd[blockIdx.x] = dl;
     }
 }
 
 __global__ __launch_bounds__(256) void k_select_final(int parts, const int64_t* pg, const int32_t* pu,
                                                       const long long* pd, uint32_t* excl, RoundCtl* ctl, int32_t k,
-                                                      int32_t* blockers, int64_t* gains,
-                                                      int64_t* totals, int32_t* n_selected) {
+                                                      int32_t* blockers, int64_t* gains, int64_t* totals,
+                                                      int32_t* n_selected) {
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
     __shared__ long long sd[4];
@@ -568,43 +467,35 @@ __global__ __launch_bounds__(256) void k_select_final(int parts, const int64_t* 
         if (better(pg[i], pu[i], bg, bu)) { bg = pg[i]; bu = pu[i]; }
         dl += pd[i];
     }
-    dl = block_sum_ll<256>(dl, sd);
-    sg[threadIdx.x] = bg;
-    su[threadIdx.x] = bu;
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if (threadIdx.x < d) {
-            const int o = threadIdx.x + d;
-            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
-                sg[threadIdx.x] = sg[o];
-                su[threadIdx.x] = su[o];
-            }
-        }
-        __syncthreads();
-    }
+    select_block_best(bg, bu, dl, sg, su, sd);
     if (threadIdx.x != 0 || ctl->stop) return;
     const int r = ctl->round;
     if (dl) ctl->total -= dl;
     const long long T = ctl->total;
     if (ctl->expect_total >= 0 && ctl->expect_total != T) atomicOr(&ctl->flags, (uint32_t)kFlagSpreadMismatch);
     totals[r] = T;
-    const int32_t u = su[0];
-    const int64_t gbest = sg[0];
-    if (r >= k || u < 0 || gbest <= 0) {
+    // counters of the next incremental round
+    for (int i = 0; i < 3; ++i) {
+        ctl->next[i] = 0;
+        ctl->list_n[i] = 0;
+    }
+    ctl->tree_n = 0;
+    ctl->pair_count = 0;
+    if (r >= k || bu < 0 || bg <= 0) {
         ctl->stop = 1;
         *n_selected = r;
         return;
     }
-    blockers[r] = u;
-    gains[r] = gbest;
-    excl[u >> 5] |= 1u << (u & 31);
-    ctl->ustar = u;
-    ctl->best_gain = gbest;
+    blockers[r] = bu;
+    gains[r] = bg;
+    excl[bu >> 5] |= 1u << (bu & 31);
+    ctl->ustar = bu;
+    ctl->best_gain = bg;
     ctl->round = r + 1;
-    ctl->expect_total = T - gbest;
+    ctl->expect_total = T - bg;
     if (r + 1 == k) {
         // T_k follows exactly from T_{k-1} - gain_{k-1}
-        totals[k] = T - gbest;
+        totals[k] = T - bg;
         ctl->stop = 1;
         *n_selected = k;
     }

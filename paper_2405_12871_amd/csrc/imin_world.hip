@@ -543,11 +543,11 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
         // The stored list keeps the round-0 order; an entry whose count is 0
         // is a node no longer reached.  Blocking only removes nodes, so every
         // node reached now has a live entry: walking the live entries finds
-        // every count that changed; each is updated in place and the change
-        // written at the front of the world's own range of dl_*.
+        // every count that changed; each is updated in place and its change
+        // added to gain.
         const size_t so = (size_t)out.store_off[w];
         int list_len = out.store_len[w];
-        if (so + (size_t)list_len > out.store_cap || so + (size_t)list_len > out.dl_cap) {
+        if (so + (size_t)list_len > out.store_cap) {
             if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
             list_len = 0;  // uniform: every thread read the same values
         }
@@ -568,21 +568,11 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
                 }
             }
             const unsigned long long mask = __ballot(d != 0);
-            const int cnt = __popcll(mask);
-            int wbase = 0;
-            if (lane == 0 && cnt) wbase = atomicAdd(&sh.ndelta, cnt);
-            wbase = __shfl(wbase, 0, 64);
-            if (d != 0) {
-                const size_t pos = so + (size_t)(wbase + __popcll(mask & ((1ull << lane) - 1ull)));
-                out.dl_node[pos] = u;
-                out.dl_cnt[pos] = d;
-            }
+            if (lane == 0 && mask) atomicAdd(&sh.ndelta, __popcll(mask));
+            if (d != 0 && u != ctl->ustar) atomicAdd((unsigned long long*)&out.gain[u], (unsigned long long)(long long)d);
         }
         __syncthreads();
-        if (t == 0) {
-            out.wlen[w] = sh.ndelta;
-            if (out.world_tree) out.world_tree[w] = 0;  // no labels from this evaluation
-        }
+        if (t == 0 && out.world_tree) out.world_tree[w] = 0;  // no labels from this evaluation
     } else {
         if (t == 0) {
             sh.pair_base = (TIER == 0) ? (unsigned long long)wi * out.slot_cap0
@@ -672,13 +662,24 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
 // store).  With range_count > 0 the kernel takes worlds 0..range_count-1 of
 // the tile; otherwise it takes the list handed down by the previous tier.
 using Tier0Store = LdsStore<256, 9, 128, 30>;
-using Tier1Store = LdsStore<2048, 12, 1024, 254>;
+// tier 1 keeps a level slot for every node it can hold: a world that fitted it
+// in a from-scratch pass fits it again after any blockers are added
+using Tier1Store = LdsStore<2048, 12, 1024, 2050>;
 constexpr int kTier0NT = 64;
 constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
 
 // Per-workgroup work tallies, one slot per (tier, field, workgroup): no
 // shared counter is touched.
+__device__ __forceinline__ void add_work_at(const TileOut& out, int tier, uint32_t slot, unsigned long long worlds,
+                                            unsigned long long edges, unsigned long long bytes) {
+    if (!out.work || !worlds) return;
+    const size_t st = (size_t)out.work_stride;
+    unsigned long long* wk = out.work + (size_t)tier * 3 * st + slot;
+    wk[0] += worlds;
+    wk[st] += edges;
+    wk[2 * st] += bytes;
+}
 __device__ __forceinline__ void add_work(const TileOut& out, int tier, unsigned long long worlds,
                                          unsigned long long edges, unsigned long long bytes) {
     if (!out.work || !worlds) return;
@@ -996,7 +997,7 @@ hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx
 template <int CAP, int XCAP, int LVCAP>
 struct ReplayStore {
     int32_t nl[CAP];      // old entry -> new local id; -1 not reached yet, -2 removed, -3 being claimed
-    int32_t cur[CAP];     // label placement cursors
+    int32_t cur[CAP];     // BFS: owner slot of each head claimed in a level; then label placement cursors
     int16_t parent[CAP];  // by new local id - ns; preorder index once the counts are known
     int16_t idom[CAP];
     int32_t aux[CAP];
@@ -1025,41 +1026,26 @@ struct ReplayStore {
 };
 
 using ReplayStoreT = ReplayStore<512, 128, 62>;
-constexpr int kReplayNT = 64;
-constexpr int kReplaySlots = 12;  // stored edges per lane: at most 768 per world
+constexpr int kReplayNT = 256;                     // four waves per replayed world
+constexpr int kReplaySlots = 768 / kReplayNT;      // stored edges per thread: at most 768 per world
 constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 
-// Claim old entry vi from source new id nu, or record the edge as extra.
-template <int NT, class RS>
-__device__ __forceinline__ void replay_claim(RS& st, WorldShared<NT>& sh, int vi, int nu) {
-    const int old = atomicCAS(&st.nl[vi], -1, -3);
-    if (old == -1) {
-        const int lid = atomicAdd(&sh.count, 1);
-        st.nl[vi] = lid;
-        st.set_parent(lid, nu);
-    } else if (old != -2) {
-        const int x = atomicAdd(&sh.n_extra, 1);
-        if (x < st.cap_x()) {
-            st.xv[x] = vi;  // resolved to its new id in the dominator phase
-            st.xu[x] = (int16_t)nu;
-        } else {
-            sh.overflow = 1;
-        }
-    }
-}
-
-// The stored edges stay in registers (kReplaySlots per lane); each level
+// The stored edges stay in registers (kReplaySlots per thread); each level
 // looks up the new id of every pending edge's source and claims the heads
 // of the edges leaving the frontier.  Every edge is used once, when its
 // source's level is expanded.  The world's entries (count, node) stay in
-// registers too (lane t holds entries t, t+64, ...) for the outputs.  An
+// registers too (thread t holds entries t, t+NT, ...) for the outputs.  An
 // entry is removed when its count is 0 (lost in an earlier round, which
 // includes every earlier blocker) or it is this round's blocker.
+//
+// Within a level, the edges into a head not reached before each write
+// their slot id into cur[head]; the edge whose id stays there claims it,
+// the other edges into reached heads become extra edges, and one
+// workgroup-wide scan hands out the new local ids and extra-edge slots.
 template <int NT, class RS>
 __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
                            WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots],
                            int32_t (&en)[kReplayEntrySlots]) {
-    static_assert(NT == 64, "one wave per replayed world");
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     const size_t so = (size_t)it.store_off;
@@ -1070,18 +1056,8 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
     // room, local ids that fit the 16-bit arrays, ranges inside the stores
     // (uniform checks)
     if (L0 < 0 || X0 < 0 || L0 > RS::kCap || E > NT * kReplaySlots || ns + L0 > 32767) return false;
-    if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || so + (size_t)L0 > out.dl_cap ||
-        xo + (size_t)X0 > out.xstore_cap)
+    if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap)
         return false;
-    if (t == 0) {
-        st.ns = ns;
-        sh.count = ns;
-        sh.edges = E;
-        sh.n_extra = 0;
-        sh.overflow = 0;
-        st.lvl[0] = 0;
-        st.lvl[1] = ns;
-    }
     // one batch of loads: entries, then edges (the tree edge of entry e is
     // its round-0 parent; then the extras)
 #pragma unroll
@@ -1108,7 +1084,7 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
             vi = out.xstore_v[xo + (e - L0)] - ns;
         }
         const bool ok = u >= 0 && u < ns + L0 && vi >= 0 && vi < L0;
-        ed[r] = ok ? (((uint32_t)u << 16) | (uint32_t)vi) : 0u;
+        ed[r] = ok ? (((uint32_t)u << 16) | (uint32_t)vi) : 0u;  // inactive slots read entry 0, harmlessly
         act |= ok ? (1u << r) : 0u;
     }
 #pragma unroll
@@ -1116,53 +1092,95 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
         const int i = t + r * NT;
         if (i < L0) st.nl[i] = (ec[r] <= 0 || en[r] == ustar) ? -2 : -1;
     }
+    if (t == 0) {
+        st.ns = ns;
+        st.lvl[0] = 0;
+        st.lvl[1] = ns;
+    }
     __syncthreads();
-    int nlev = 1;  // closed levels: lvl[0..nlev]
-    for (;;) {
-        const int f0 = st.lvl[nlev - 1];
-        const int f1 = st.lvl[nlev];
-        if (f0 == f1) break;
+    int count = ns, nx = 0;  // uniform
+    int f0 = 0, f1 = ns;     // the frontier: level nlev - 1
+    int nlev = 1;            // closed levels: lvl[0..nlev]
+    while (f0 != f1) {
+        int nu[kReplaySlots], hv[kReplaySlots], own[kReplaySlots];
         uint32_t hit = 0;
 #pragma unroll
         for (int r = 0; r < kReplaySlots; ++r) {
-            if ((act >> r) & 1u) {
-                const int u = (int)(ed[r] >> 16);
-                const int nu = (u < ns) ? u : st.nl[u - ns];
-                if (nu >= f0 && nu < f1) hit |= 1u << r;
-            }
+            const int u = (int)(ed[r] >> 16);
+            const int x = st.nl[(u >= ns) ? u - ns : 0];
+            nu[r] = (u < ns) ? u : x;
+            hv[r] = st.nl[ed[r] & 0xFFFFu];
         }
+#pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r)
+            hit |= (((act >> r) & 1u) && nu[r] >= f0 && nu[r] < f1) ? (1u << r) : 0u;
         act &= ~hit;
 #pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r)
+            if (((hit >> r) & 1u) && hv[r] == -1) st.cur[ed[r] & 0xFFFFu] = t * kReplaySlots + r;
+        __syncthreads();
+        uint32_t win = 0, ext = 0;
+#pragma unroll
         for (int r = 0; r < kReplaySlots; ++r) {
-            if ((hit >> r) & 1u) {
-                const int u = (int)(ed[r] >> 16);
-                replay_claim<NT>(st, sh, (int)(ed[r] & 0xFFFFu), (u < ns) ? u : st.nl[u - ns]);
+            own[r] = st.cur[ed[r] & 0xFFFFu];
+            const bool h = (hit >> r) & 1u;
+            const bool w = h && hv[r] == -1 && own[r] == t * kReplaySlots + r;
+            win |= w ? (1u << r) : 0u;
+            ext |= (h && hv[r] != -2 && !w) ? (1u << r) : 0u;
+        }
+        // local ids and extra-edge slots: one scan of (claims, extras)
+        int tot;
+        const int ex = block_excl_scan<NT>(__popc(win) | (__popc(ext) << 16), sh.scan_tmp, tot);
+        int lid = count + (ex & 0xFFFF);
+        int xs = nx + (ex >> 16);
+#pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r) {
+            const int vi = (int)(ed[r] & 0xFFFFu);
+            if ((win >> r) & 1u) {
+                st.nl[vi] = lid;
+                st.set_parent(lid, nu[r]);
+                ++lid;
+            }
+            if ((ext >> r) & 1u) {
+                if (xs < st.cap_x()) {
+                    st.xv[xs] = vi;  // resolved to its new id in the dominator phase
+                    st.xu[xs] = (int16_t)nu[r];
+                }
+                ++xs;
             }
         }
-        __syncthreads();
-        if (sh.overflow) return false;
-        if (nlev + 1 > st.cap_lv()) return false;  // same nlev in every thread: uniform
-        if (t == 0) st.lvl[nlev + 1] = sh.count;
-        __syncthreads();
+        count += tot & 0xFFFF;
+        nx += tot >> 16;
+        if (nx > st.cap_x()) return false;         // uniform
+        if (nlev + 1 > st.cap_lv()) return false;  // uniform
+        if (t == 0) st.lvl[nlev + 1] = count;
         ++nlev;
+        f0 = f1;
+        f1 = count;
+        __syncthreads();
     }
-    if (t == 0) sh.nlevels = nlev - 1;
+    if (t == 0) {
+        sh.count = count;
+        sh.n_extra = nx;
+        sh.edges = E;
+        sh.nlevels = nlev - 1;
+    }
     __syncthreads();
     return true;
 }
 
 // Count changes of a replayed world: each entry's new count against the one
-// held in registers; changes go to the front of the world's own range of
-// dl_* (wave-wide ballots, no shared counter) and the counts are updated in
+// held in registers; changes are added to gain and the counts updated in
 // place.
 template <int NT, class RS>
-__device__ int replay_outputs(const ReplayItem& it, const TileOut& out, RS& st, WorldShared<NT>& sh,
+__device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut& out, RS& st, WorldShared<NT>& sh,
                               const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots]) {
     const int t = threadIdx.x;
     const int ns = st.ns;
     const size_t so = (size_t)it.store_off;
     const int L0 = it.store_len;
-    const unsigned long long below = (1ull << t) - 1ull;
+    if (t == 0) sh.ndelta = 0;
+    __syncthreads();
     int nd = 0;
 #pragma unroll
     for (int r = 0; r < kReplayEntrySlots; ++r) {
@@ -1178,48 +1196,45 @@ __device__ int replay_outputs(const ReplayItem& it, const TileOut& out, RS& st, 
         }
         const unsigned long long mask = __ballot(d != 0);
         if (d != 0) {
-            const size_t pos = so + (size_t)(nd + __popcll(mask & below));
-            out.dl_node[pos] = en[r];
-            out.dl_cnt[pos] = d;
+            if (en[r] != ustar) atomicAdd((unsigned long long*)&out.gain[en[r]], (unsigned long long)(long long)d);
             out.store_cnt[so + i] = cn;
         }
         nd += __popcll(mask);
     }
+    if ((t & 63) == 0 && nd) atomicAdd(&sh.ndelta, nd);
+    __syncthreads();
     if (t == 0) {
-        out.wlen[it.w] = nd;
         out.world_size[it.w] = sh.count;
         if (out.world_tree) out.world_tree[it.w] = (sh.n_extra == 0) ? 1 : 0;
     }
-    return nd;
+    return sh.ndelta;
 }
 
-// Incremental rounds: every changed world is first replayed; a world that
-// does not fit the replay store goes on to the sampling tiers (list 1).
-// The next world's item is loaded while the current one is replayed.
-__global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl* ctl, int32_t* next_list,
-                                                             TileOut out) {
-    __shared__ ReplayStoreT st;
-    __shared__ WorldShared<kReplayNT> sh;
+// Changed worlds that are not forests are replayed; a world that does not
+// fit the replay store goes on to the sampling tiers (list 1).  Workgroup
+// `part` of `parts` takes items part, part + parts, ...; the next world's
+// item is loaded while the current one is replayed.
+__device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                              ReplayStoreT& st, WorldShared<kReplayNT>& sh, uint32_t part, uint32_t parts) {
     const int t = threadIdx.x;
-    if (ctl->stop) return;
     const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
-    if (blockIdx.x >= n_items) return;
+    if (part >= n_items) return;
     const int32_t ustar = ctl->ustar;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
-    ReplayItem cur = out.items[blockIdx.x];
-    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+    ReplayItem cur = out.items[part];
+    for (uint32_t k = part; k < n_items; k += parts) {
         ReplayItem nxt = cur;
-        if (k + gridDim.x < n_items) nxt = out.items[k + gridDim.x];
+        if (k + parts < n_items) nxt = out.items[k + parts];
         int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
         if (bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en)) {
             world_counts<kReplayNT>(q, ctl, st, sh);
             world_labels<kReplayNT>(q, st, sh);
-            const int nd = replay_outputs<kReplayNT>(cur, out, st, sh, ec, en);
+            const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
             acc_w += 1;
             acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
-            acc_b += 32ull + 12ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
-                     12ull * (unsigned long long)nd + 8ull;
+            acc_b += sizeof(ReplayItem) + 12ull * (unsigned long long)cur.store_len +
+                     8ull * (unsigned long long)cur.xstore_len + 12ull * (unsigned long long)nd + 8ull;
             acc_d += (long long)cur.world_size - (long long)sh.count;
         } else if (t == 0) {
             const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
@@ -1230,9 +1245,9 @@ __global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl
         cur = nxt;
     }
     if (t == 0) {
-        add_work(out, 3, acc_w, acc_e, acc_b);
+        add_work_at(out, 3, part, acc_w, acc_e, acc_b);
         // T is lowered by the nodes the replayed worlds lost
-        if (acc_d) out.dsz[out.dsz_off[3] + blockIdx.x] = acc_d;
+        if (acc_d) out.dsz[out.dsz_off[3] + part] = acc_d;
     }
 }
 
@@ -1245,22 +1260,33 @@ __global__ __launch_bounds__(kReplayNT) void k_world_replay(QueryDev q, RoundCtl
 // tin(u) <= tin(i) < tin(u) + size(u), and is an ancestor of u when
 // tin(i) <= tin(u) < tin(i) + size(i).  One wave per world, one pass over
 // its entries; removing a subtree keeps the rest a forest with valid labels.
+// The count changes of a workgroup's worlds are summed in LDS and added to
+// gain once per node per workgroup.
 constexpr int kTreeUnroll = 4;
+using TreeSums = LdsSums<11>;
 
-__global__ __launch_bounds__(kTreeNT) void k_tree_update(RoundCtl* ctl, TileOut out) {
-    __shared__ unsigned long long red[kTreeNT / 64][4];
-    if (ctl->stop) return;
+__device__ __forceinline__ bool ti_is_u(uint32_t lab, int tj) { return (int)(lab >> 16) == tj; }
+
+struct ForestShared {
+    TreeSums sums;
+    unsigned long long red[kTreeNT / 64][4];
+};
+
+__device__ void forest_worlds(RoundCtl* ctl, const TileOut& out, ForestShared& fs, uint32_t part, uint32_t parts) {
+    TreeSums& sums = fs.sums;
     const uint32_t n = min(ctl->tree_n, out.list_cap);
+    if ((unsigned long long)part * (kTreeNT / 64) >= n) return;  // no world for this workgroup
+    sums.clear<kTreeNT>();
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    const unsigned long long below = (1ull << lane) - 1ull;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
-    for (uint32_t k = blockIdx.x * (kTreeNT / 64) + wid; k < n; k += gridDim.x * (kTreeNT / 64)) {
+    for (uint32_t k = part * (kTreeNT / 64) + wid; k < n; k += parts * (kTreeNT / 64)) {
         const ReplayItem it = out.titems[k];
         const size_t so = (size_t)it.store_off;
         const int L0 = it.store_len;
-        if (it.store_off < 0 || L0 < 0 || so + (size_t)L0 > out.store_cap || so + (size_t)L0 > out.dl_cap) {
+        if (it.store_off < 0 || L0 < 0 || so + (size_t)L0 > out.store_cap) {
             if (lane == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
             continue;  // uniform over the wave
         }
@@ -1299,55 +1325,65 @@ __global__ __launch_bounds__(kTreeNT) void k_tree_update(RoundCtl* ctl, TileOut 
                 }
                 const unsigned long long mask = __ballot(d != 0);
                 if (d != 0) {
-                    const size_t pos = so + (size_t)(nd + __popcll(mask & below));
-                    out.dl_node[pos] = v[r];
-                    out.dl_cnt[pos] = d;
+                    // u itself is blocked from now on: its gain is never read again
+                    if (ti_is_u(lab[r], tj)) {} else sums.add(v[r], d, out.gain);
                     out.store_cnt[so + i] = cn;
                 }
                 nd += __popcll(mask);
             }
         }
-        if (lane == 0) {
-            out.wlen[it.w] = nd;
-            out.world_size[it.w] = it.world_size - cj;
-        }
+        if (lane == 0) out.world_size[it.w] = it.world_size - cj;
         acc_w += 1;
         acc_e += (unsigned long long)L0;
         acc_b += sizeof(ReplayItem) + 12ull * (unsigned long long)L0 + 12ull * (unsigned long long)nd + 8ull;
         acc_d += cj;
     }
     if (lane == 0) {
-        red[wid][0] = acc_w;
-        red[wid][1] = acc_e;
-        red[wid][2] = acc_b;
-        red[wid][3] = (unsigned long long)acc_d;
+        fs.red[wid][0] = acc_w;
+        fs.red[wid][1] = acc_e;
+        fs.red[wid][2] = acc_b;
+        fs.red[wid][3] = (unsigned long long)acc_d;
     }
     __syncthreads();
+    sums.flush<kTreeNT>(out.gain);
     if (threadIdx.x == 0) {
         unsigned long long f[4] = {0, 0, 0, 0};
         for (int x = 0; x < kTreeNT / 64; ++x)
-            for (int y = 0; y < 4; ++y) f[y] += red[x][y];
-        add_work(out, 4, f[0], f[1], f[2]);
-        if (f[3]) out.dsz[out.dsz_off[4] + blockIdx.x] = (long long)f[3];
+            for (int y = 0; y < 4; ++y) f[y] += fs.red[x][y];
+        add_work_at(out, 4, part, f[0], f[1], f[2]);
+        if (f[3]) out.dsz[out.dsz_off[4] + part] = (long long)f[3];
     }
 }
 
-hipError_t launch_tree_update(RoundCtl* ctl, const TileOut& out, int grid, hipStream_t s) {
-    k_tree_update<<<grid, kTreeNT, 0, s>>>(ctl, out);
+// ------------------------------------------------- changed-world update
+// One launch for the changed worlds of an incremental round: the first
+// replay_parts workgroups replay the other worlds while the rest update the
+// forest worlds, so the two run side by side.  LDS is shared between the
+// two roles.
+static_assert(kReplayNT == kTreeNT, "both roles use the same workgroup size");
+union ChangedShared {
+    struct {
+        ReplayStoreT st;
+        WorldShared<kReplayNT> sh;
+    } r;
+    ForestShared f;
+};
+
+__global__ __launch_bounds__(kReplayNT) void k_changed_worlds(QueryDev q, RoundCtl* ctl, int32_t* next_list,
+                                                               TileOut out, uint32_t replay_parts) {
+    __shared__ ChangedShared u;
+    if (ctl->stop) return;
+    if (blockIdx.x < replay_parts) replay_worlds(q, ctl, next_list, out, u.r.st, u.r.sh, blockIdx.x, replay_parts);
+    else forest_worlds(ctl, out, u.f, blockIdx.x - replay_parts, gridDim.x - replay_parts);
+}
+
+hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                                 int replay_parts, int forest_parts, hipStream_t s) {
+    k_changed_worlds<<<replay_parts + forest_parts, kReplayNT, 0, s>>>(q, ctl, next_list, out,
+                                                                       (uint32_t)replay_parts);
     return hipGetLastError();
 }
 
-int world_replay_blocks_per_cu() {
-    const size_t lds = sizeof(ReplayStoreT) + sizeof(WorldShared<kReplayNT>);
-    int b = (int)((160 * 1024) / lds);
-    return b < 1 ? 1 : b;
-}
-
-hipError_t launch_world_replay(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out, int grid,
-                               hipStream_t s) {
-    k_world_replay<<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out);
-    return hipGetLastError();
-}
 
 // ------------------------------------------------- level-0 slot table
 // For seed i with row [e0, e1): nb_i = number of 4-aligned slot groups.
