@@ -8,6 +8,7 @@
 #include <atomic>
 #include <mutex>
 #include <vector>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -68,10 +69,13 @@ struct TimedLaunches {
     std::vector<Rec> recs;
     bool on = g_timing.on.load();
     uint32_t mask = g_timing.mask.load();
+    void record(hipEvent_t e, hipStream_t s) {
+        if (hipEventRecord(e, s) != hipSuccess) (void)hipGetLastError();  // best effort: leave no error behind
+    }
     hipEvent_t begin(int id, hipStream_t s) {
         if (!on || !((mask >> id) & 1u)) return nullptr;
         hipEvent_t e = event_acquire();
-        if (e) (void)hipEventRecord(e, s);
+        if (e) record(e, s);
         return e;
     }
     void end(int id, hipEvent_t a, hipStream_t s) {
@@ -81,7 +85,7 @@ struct TimedLaunches {
             event_release(a);
             return;
         }
-        (void)hipEventRecord(e, s);
+        record(e, s);
         recs.push_back({id, a, e});
     }
     void flush() {
@@ -106,10 +110,20 @@ imin_status_t from_hip(hipError_t e) {
     return e == hipErrorOutOfMemory ? IMIN_ERR_NOMEM : IMIN_ERR_DEVICE;
 }
 
+// With IMIN_DEBUG set in the environment, a failing runtime call is named
+// on stderr.
+void report_hip(const char* what, hipError_t e) {
+    static const bool on = std::getenv("IMIN_DEBUG") != nullptr;
+    if (on) std::fprintf(stderr, "imin: %s failed: %s\n", what, hipGetErrorString(e));
+}
+
 #define IMIN_TRY(expr)                                  \
     do {                                                \
         const hipError_t imin_e_ = (expr);              \
-        if (imin_e_ != hipSuccess) return from_hip(imin_e_); \
+        if (imin_e_ != hipSuccess) {                    \
+            report_hip(#expr, imin_e_);                 \
+            return from_hip(imin_e_);                   \
+        }                                               \
     } while (0)
 
 // Device allocation owned by a scope.
@@ -230,6 +244,20 @@ struct Session {
     TimedLaunches timed;
 
     Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
+    Session(const Session&) = delete;
+    Session& operator=(const Session&) = delete;
+
+    // one incremental round: changed worlds, then the selection
+    imin_status_t delta_round(const imin::QueryDev& q, uint64_t theta, int32_t k, int32_t* blockers,
+                              int64_t* gains, int64_t* totals, int32_t* n_selected) {
+        imin_status_t st = evaluate_delta(q, theta);
+        if (st != IMIN_OK) return st;
+        hipEvent_t ev = timed.begin(3, s);
+        IMIN_TRY(imin::launch_select(g, gain.p, excl.p, ctl.p, sel_g.p, sel_u.p, sel_d.p, dsz.p, dsz_n, sel_parts, k,
+                                     blockers, gains, totals, n_selected, s));
+        timed.end(3, ev, s);
+        return IMIN_OK;
+    }
 
     imin_status_t init(uint64_t theta, bool solve) {
         const size_t n = (size_t)g.n;
@@ -849,13 +877,8 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             // the selection stops, every later kernel returns at once
             const int32_t nb = (int32_t)std::min<size_t>(batch, (size_t)(k + 1 - r));
             for (int32_t i = 0; i < nb; ++i) {
-                st = ss.evaluate_delta(q, (uint64_t)theta);
+                st = ss.delta_round(q, (uint64_t)theta, k, blockers, gains, spread_totals, n_selected);
                 if (st != IMIN_OK) return st;
-                hipEvent_t ev = ss.timed.begin(3, s);
-                IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p,
-                                             ss.sel_d.p, ss.dsz.p, ss.dsz_n, ss.sel_parts, k, blockers, gains,
-                                             spread_totals, n_selected, s));
-                ss.timed.end(3, ev, s);
             }
             r += nb;
         } else {

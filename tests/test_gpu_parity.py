@@ -169,8 +169,8 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
     other changed worlds replayed from their stored live edges), replay
     without the forest update, plain rounds, a resident store too small to
     hold round 0 (falls back to plain rounds), re-evaluation by sampling on
-    every tier, regrowth of the extra-edge scratch and several tiles all give
-    the oracle's selection."""
+    every tier, regrowth of the extra-edge scratch, several tiles and other
+    round batch sizes all give the oracle's selection."""
     if variant == "plain":
         monkeypatch.setenv("IMIN_INCREMENTAL", "0")
     elif variant == "store_overflow":
