@@ -257,6 +257,8 @@ def main():
         "round0_worlds_per_s": theta / r0_wall,
         "round0_world_kernel_ms": r0_world_ms,
         "round0_algorithmic_GBps": r0_bytes / r0_world_ms / 1e6,
+        "round0_tier0": {"launches": r0[0][0], "ms": r0[0][1], "algorithmic_bytes": r0_work[0][2],
+                         "worlds": r0_work[0][0]},
         "graph_ingest_ms": ingest_ms,
         "Rbar": float(R.mean()),
         "Ebar": float(E.mean()),
