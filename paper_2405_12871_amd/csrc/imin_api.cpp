@@ -187,7 +187,7 @@ struct Session {
     DevArray<int32_t> list0, list1, list2;  // changed worlds; worlds handed down to tier 1 / 2
     // dense pairs and the reduction's buffers
     DevArray<int32_t> pair_node, pair_cnt, sorted_node, sorted_cnt;
-    DevArray<int32_t> hist;
+    DevArray<long long> hist;
     DevArray<int64_t> part;
     imin::ReduceBufs rb{};
     // resident per-world (node, count) lists for incremental rounds

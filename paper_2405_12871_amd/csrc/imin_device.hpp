@@ -64,6 +64,32 @@ __device__ __forceinline__ int block_excl_scan(int x, int* tmp, int& total) {
     }
 }
 
+// 64-bit exclusive prefix sum over a workgroup of NT threads; `tmp` holds
+// NT/64 long longs of LDS.  All threads must call it.
+template <int NT>
+__device__ __forceinline__ long long block_excl_scan_ll(long long x, long long* tmp, long long& total) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    long long inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const long long y = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63) tmp[wid] = inc;
+    __syncthreads();
+    long long pre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const long long v = tmp[i];
+        pre += (i < wid) ? v : 0;
+        tot += v;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + inc - x;
+}
+
 // Sum over a workgroup of NT threads; `tmp` holds NT/64 values of LDS.
 template <int NT>
 __device__ __forceinline__ long long block_sum_ll(long long x, long long* tmp) {

@@ -214,7 +214,7 @@ struct ReduceBufs {
     int32_t nb;          // node buckets
     int32_t g1;          // chunks of the histogram pass
     int32_t slices;      // workgroups per bucket in the accumulate pass
-    int32_t* hist;       // [nb * g1 + 1]
+    long long* hist;     // [nb * g1 + 1] bucket positions (a tile may hold more than 2^31 pairs)
     int32_t* sorted_node;
     int32_t* sorted_cnt;
     unsigned long long sorted_cap;  // entries of sorted_node / sorted_cnt

@@ -194,26 +194,27 @@ __global__ __launch_bounds__(kRedNT) void k_hist(RoundCtl* ctl, const int32_t* p
     for (int i = threadIdx.x; i < rb.nb; i += kRedNT) rb.hist[(size_t)i * rb.g1 + blockIdx.x] = h[i];
 }
 
-// single-workgroup exclusive scan of hist[0 .. nb*g1) in place; hist[nb*g1] = total
+// single-workgroup exclusive scan of hist[0 .. nb*g1) in place; hist[nb*g1] =
+// total.  64-bit: a tile's pairs may exceed 2^31.
 __global__ __launch_bounds__(1024) void k_scan(const RoundCtl* ctl, ReduceBufs rb) {
-    __shared__ int tmp[16];
-    __shared__ int carry;
+    __shared__ long long tmp[16];
+    __shared__ long long carry;
     if (ctl->stop) return;
     const int total = rb.nb * rb.g1;
     if (threadIdx.x == 0) carry = 0;
     __syncthreads();
     for (int base = 0; base < total; base += 1024 * 4) {
-        int v[4];
-        int loc = 0;
+        long long v[4];
+        long long loc = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int i = base + threadIdx.x * 4 + k;
             v[k] = (i < total) ? rb.hist[i] : 0;
             loc += v[k];
         }
-        int tot;
-        const int ex = block_excl_scan<1024>(loc, tmp, tot);
-        int run = carry + ex;
+        long long tot;
+        const long long ex = block_excl_scan_ll<1024>(loc, tmp, tot);
+        long long run = carry + ex;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int i = base + threadIdx.x * 4 + k;
@@ -230,17 +231,18 @@ __global__ __launch_bounds__(1024) void k_scan(const RoundCtl* ctl, ReduceBufs r
 __global__ __launch_bounds__(kRedNT) void k_scatter(const RoundCtl* ctl, const int32_t* pair_node,
                                                     const int32_t* pair_cnt, unsigned long long cap,
                                                     ReduceBufs rb) {
-    __shared__ int cur[kMaxBuckets];
+    __shared__ unsigned long long cur[kMaxBuckets];
     if (ctl->stop) return;
     unsigned long long P = ctl->pair_count;
     if (P > cap || P > rb.sorted_cap || (ctl->flags & kFlagPairOverflow)) P = 0;
-    for (int i = threadIdx.x; i < rb.nb; i += kRedNT) cur[i] = rb.hist[(size_t)i * rb.g1 + blockIdx.x];
+    for (int i = threadIdx.x; i < rb.nb; i += kRedNT)
+        cur[i] = (unsigned long long)rb.hist[(size_t)i * rb.g1 + blockIdx.x];
     __syncthreads();
     unsigned long long a, b;
     chunk_range(P, rb.g1, blockIdx.x, a, b);
     for (unsigned long long i = a + threadIdx.x; i < b; i += kRedNT) {
         const int32_t v = pair_node[i];
-        const int pos = atomicAdd(&cur[v >> kBucketShift], 1);
+        const unsigned long long pos = atomicAdd(&cur[v >> kBucketShift], 1ull);
         rb.sorted_node[pos] = v;
         rb.sorted_cnt[pos] = pair_cnt[i];
     }

@@ -91,6 +91,24 @@ def test_world_range_shards_add_up(B):
     assert full[1] == sum(p[1] for p in parts)
 
 
+def test_tile_beyond_2pow31_pairs(B):
+    """The medium workload's from-scratch pass puts all 100,000 worlds in one
+    tile: 2.35e9 (node, count) pairs, more than a 32-bit position can address.
+    Its gains and total equal the sums over two half ranges (each below 2^31
+    pairs)."""
+    g, seeds, _, theta = synth.workload("medium")
+    G = B.Graph.from_synth(g)
+    _log("medium: one tile of all worlds")
+    full_gain, full_total, ws, _ = B.evaluate(G, seeds, 0, theta, 11, per_world=True)
+    assert int(ws.astype(np.int64).sum()) - theta * len(seeds) > 2 ** 31
+    _log("medium: two half ranges")
+    h = theta // 2
+    a = B.evaluate(G, seeds, 0, h, 11)
+    b = B.evaluate(G, seeds, h, theta - h, 11)
+    np.testing.assert_array_equal(full_gain, a[0] + b[0])
+    assert full_total == a[1] + b[1] == int(ws.astype(np.int64).sum())
+
+
 def test_tiles_and_pair_overflow(B, oracle_mod, monkeypatch):
     """Tiny tiles and a tiny pair buffer force the tile loop and its retry."""
     g, seeds, _, _ = synth.workload("small")
