@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "live-edge worlds/sec (sample+BFS+gain) at 1M-node graph; p50/p99 IMIN query latency"
 HBM_PEAK_GBS = 8000.0
+TIMED_EVERY = 8
 RNG_SEED = 2024
 
 
@@ -197,7 +198,10 @@ def main():
                  "changed_worlds": (6, (3, 4))}
     dom = max(world_ids, key=lambda nm: kern.get(nm, 0.0))
     dom_kid, dom_tiers = world_ids[dom]
+    # events take time on the stream: one launch in TIMED_EVERY of the dominant
+    # kernel is bracketed, spread evenly over every solve's rounds
     binding.timing_mask([dom_kid])
+    binding.timing_sample(TIMED_EVERY)
     binding.timing_reset()
     lat = []
     torch.cuda.synchronize()
@@ -212,16 +216,21 @@ def main():
     total_s = time.perf_counter() - t_start
     work = [binding.timing_work(t) for t in range(5)]
     n_dom, ms_dom = binding.timing_read(dom_kid)
+    all_dom = binding.timing_launches(dom_kid)
     binding.timing_enable(False)
     binding.timing_mask(None)
+    binding.timing_sample(1)
     n_sel = int(out[3].cpu()[0])
     rounds = min(n_sel + 1, k) if k > 0 else 1
     ms_per_step = total_s * 1e3 / args.steps
     evals = sum(w[0] for w in work) / args.steps
     value = evals / (ms_per_step / 1e3)
-    # roofline of the dominant world kernel over its launches in the timed solves
+    # roofline of the dominant world kernel over the timed solves: algorithmic
+    # bytes per launch (all its launches) over its average timed duration
     bytes_dom = sum(work[t][2] for t in dom_tiers)
-    achieved = bytes_dom / (ms_dom / 1e3) / 1e9 if ms_dom > 0 else 0.0
+    bytes_per_launch = bytes_dom / max(all_dom, 1)
+    avg_ms = ms_dom / max(n_dom, 1)
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9 if ms_dom > 0 else 0.0
 
     spread = out[2].cpu().numpy()
     res = {
@@ -268,16 +277,18 @@ def main():
                                                        ("replayed", 3), ("forest_updated", 4))},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves",
+            "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves "
+                      f"(one in {TIMED_EVERY} bracketed with HIP events)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": measured_traffic(dom) if args.workload == "large" else None,
             "traffic_unit": "HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE, committed profile)",
-            "launches": n_dom,
-            "avg_launch_ms": ms_dom / max(n_dom, 1),
-            "algorithmic_bytes_per_launch": bytes_dom / max(n_dom, 1),
+            "launches": all_dom,
+            "timed_launches": n_dom,
+            "avg_launch_ms": avg_ms,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
         },
     }
     if not args.no_cpu:

@@ -164,6 +164,12 @@ imin_status_t imin_timing_enable(int on);
 /* Bit i set: kernel id i is bracketed with events while timing is enabled
  * (default: all).  Work tallies are kept whatever the mask. */
 imin_status_t imin_timing_mask(uint32_t kernel_mask);
+/* Time one launch in `every` (>= 1, default 1) of each selected kernel: the
+ * events themselves take time on the stream.  IMIN_ERR_INVALID if every < 1. */
+imin_status_t imin_timing_sample(int every);
+/* Launches of a selected kernel while timing was enabled, timed or not, since
+ * the last reset (host pointer). */
+imin_status_t imin_timing_launches(int kernel_id, int64_t* all);
 imin_status_t imin_timing_reset(void);
 imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_ms);
 

@@ -67,6 +67,10 @@ def load():
     lib.imin_timing_enable.restype = st
     lib.imin_timing_mask.argtypes = [ctypes.c_uint32]
     lib.imin_timing_mask.restype = st
+    lib.imin_timing_sample.argtypes = [ctypes.c_int]
+    lib.imin_timing_sample.restype = st
+    lib.imin_timing_launches.argtypes = [ctypes.c_int, ctypes.POINTER(i64)]
+    lib.imin_timing_launches.restype = st
     lib.imin_timing_reset.argtypes = []
     lib.imin_timing_reset.restype = st
     lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -233,6 +237,18 @@ def timing_mask(kernel_ids=None):
     """Bracket only these kernel ids with events (None: all)."""
     mask = 0xFFFFFFFF if kernel_ids is None else sum(1 << int(i) for i in kernel_ids)
     _check(load().imin_timing_mask(mask))
+
+
+def timing_sample(every: int = 1):
+    """Time one launch in ``every`` of each selected kernel."""
+    _check(load().imin_timing_sample(int(every)))
+
+
+def timing_launches(kernel_id: int) -> int:
+    """Launches of a selected kernel since the last reset, timed or not."""
+    n = ctypes.c_int64()
+    _check(load().imin_timing_launches(int(kernel_id), ctypes.byref(n)))
+    return int(n.value)
 
 
 def timing_reset():

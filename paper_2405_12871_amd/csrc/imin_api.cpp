@@ -28,6 +28,8 @@ constexpr int kWorkTiers = 5;  // tiers 0-2, replay, forest update
 struct Timing {
     std::atomic<bool> on{false};
     std::atomic<uint32_t> mask{0xFFFFFFFFu};  // kernels bracketed with events
+    std::atomic<int> every{1};                // one launch in `every` of each selected kernel is timed
+    std::atomic<int64_t> seen[kTimedKernels] = {};  // launches of selected kernels, timed or not
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
     double ms[kTimedKernels] = {};
@@ -72,8 +74,11 @@ struct TimedLaunches {
     void record(hipEvent_t e, hipStream_t s) {
         if (hipEventRecord(e, s) != hipSuccess) (void)hipGetLastError();  // best effort: leave no error behind
     }
+    int every = g_timing.every.load();
     hipEvent_t begin(int id, hipStream_t s) {
         if (!on || !((mask >> id) & 1u)) return nullptr;
+        const int64_t nth = g_timing.seen[id].fetch_add(1);
+        if (every > 1 && nth % every != 0) return nullptr;
         hipEvent_t e = event_acquire();
         if (e) record(e, s);
         return e;
@@ -240,6 +245,7 @@ struct Session {
     // that fitted it before, so without such a world incremental rounds
     // never reach the HBM tier and do not launch it.
     bool any_tier2 = false;
+    bool replay_complete = false;  // every stored world fits the replay
     int last_tier() const { return any_tier2 ? 2 : 1; }
     TimedLaunches timed;
 
@@ -593,7 +599,10 @@ struct Session {
             ev = timed.begin(6, s);
             IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, grid_t, s));
             timed.end(6, ev, s);
-            st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());
+            // worlds the replay cannot hold are sampled again; when round 0
+            // stored none, no world ever falls back and the tiers are not launched
+            if (!replay_complete) st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());
+            else st = IMIN_OK;
         } else {
             st = launch_tiers(q, 0, 0, list0.p, out, start_tier, 0, last_tier());
         }
@@ -628,6 +637,7 @@ struct Session {
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
             if (hctl.p->list_n[2] > 0 || start_tier == 2) any_tier2 = true;
+            replay_complete = (hctl.p->replay_big == 0);
             // route later tiles straight to the tier most worlds end up in
             if (start_tier < 2 && hctl.p->list_n[2] * 2 > nw) start_tier = 2;
             else if (start_tier < 1 && hctl.p->list_n[1] * 2 > nw) start_tier = 1;
@@ -942,11 +952,24 @@ imin_status_t imin_timing_mask(uint32_t kernel_mask) {
     return IMIN_OK;
 }
 
+imin_status_t imin_timing_sample(int every) {
+    if (every < 1) return IMIN_ERR_INVALID;
+    g_timing.every.store(every);
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_launches(int kernel_id, int64_t* all) {
+    if (kernel_id < 0 || kernel_id >= kTimedKernels || !all) return IMIN_ERR_INVALID;
+    *all = g_timing.seen[kernel_id].load();
+    return IMIN_OK;
+}
+
 imin_status_t imin_timing_reset(void) {
     std::lock_guard<std::mutex> lk(g_timing.mu);
     for (int i = 0; i < kTimedKernels; ++i) {
         g_timing.launches[i] = 0;
         g_timing.ms[i] = 0.0;
+        g_timing.seen[i].store(0);
     }
     for (int i = 0; i < kWorkTiers; ++i) g_timing.work_worlds[i] = g_timing.work_edges[i] = g_timing.work_bytes[i] = 0;
     return IMIN_OK;

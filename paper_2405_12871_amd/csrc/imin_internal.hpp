@@ -63,7 +63,7 @@ struct RoundCtl {
     unsigned long long xtile_total;  // extra edges the tile's worlds wrote
     unsigned long long xstore_count; // extra edges held for replay
     uint32_t tree_n;                 // changed worlds of the round whose reached part is a forest
-    uint32_t pad2;
+    uint32_t replay_big;             // some world stored in round 0 exceeds the replay's limits
 };
 
 // How a world evaluation reports its counts.

@@ -37,6 +37,14 @@ namespace imin {
 
 constexpr int kMaxDomPasses = 4096;
 
+// Limits of the replay of a changed world (entries, stored extra edges, all
+// stored edges).  A world within them never fails its replay: the extra
+// edges of a replay never outnumber the stored ones, and the level array
+// has a slot per entry.
+constexpr int kReplayCap = 512;
+constexpr int kReplayXCap = 256;
+constexpr int kReplayEdgeCap = 768;
+
 template <int NT>
 struct WorldShared {
     int count;    // local ids handed out (= nodes reached so far)
@@ -600,6 +608,9 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
             // a world with no extra live edge is a forest: its labels serve
             // the incremental rounds directly
             if (t == 0 && out.world_tree) out.world_tree[w] = (Store::kLabels && nx == 0) ? 1 : 0;
+            // worlds beyond the replay's limits need the sampling tiers later
+            if (t == 0 && (len > kReplayCap || nx > kReplayXCap || len + nx > kReplayEdgeCap || ns + len > 32767))
+                atomicOr(&ctl->replay_big, 1u);
             // the extra live edges, as local ids, for later replays
             if (t == 0) {
                 sh.x_base = (TIER == 0) ? (unsigned long long)wi * out.xslot_cap0
@@ -1025,9 +1036,10 @@ struct ReplayStore {
     __device__ int get_tin(int lid) const { return (int)(uint16_t)parent[lid - ns]; }
 };
 
-using ReplayStoreT = ReplayStore<512, 128, 62>;
-constexpr int kReplayNT = 256;                     // four waves per replayed world
-constexpr int kReplaySlots = 768 / kReplayNT;      // stored edges per thread: at most 768 per world
+// levels: at most one per entry plus the seeds' and a closing empty one
+using ReplayStoreT = ReplayStore<kReplayCap, kReplayXCap, kReplayCap + 2>;
+constexpr int kReplayNT = 256;                          // four waves per replayed world
+constexpr int kReplaySlots = kReplayEdgeCap / kReplayNT;  // stored edges per thread
 constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 
 // The stored edges stay in registers (kReplaySlots per thread); each level
@@ -1055,7 +1067,8 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
     const int E = L0 + X0;
     // room, local ids that fit the 16-bit arrays, ranges inside the stores
     // (uniform checks)
-    if (L0 < 0 || X0 < 0 || L0 > RS::kCap || E > NT * kReplaySlots || ns + L0 > 32767) return false;
+    if (L0 < 0 || X0 < 0 || L0 > RS::kCap || X0 > RS::cap_x() || E > NT * kReplaySlots || ns + L0 > 32767)
+        return false;
     if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap)
         return false;
     // one batch of loads: entries, then edges (the tree edge of entry e is
@@ -1212,8 +1225,7 @@ __device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut
 
 // Changed worlds that are not forests are replayed; a world that does not
 // fit the replay store goes on to the sampling tiers (list 1).  Workgroup
-// `part` of `parts` takes items part, part + parts, ...; the next world's
-// item is loaded while the current one is replayed.
+// `part` of `parts` takes items part, part + parts, ...
 __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                               ReplayStoreT& st, WorldShared<kReplayNT>& sh, uint32_t part, uint32_t parts) {
     const int t = threadIdx.x;
@@ -1222,10 +1234,8 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
     const int32_t ustar = ctl->ustar;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
-    ReplayItem cur = out.items[part];
     for (uint32_t k = part; k < n_items; k += parts) {
-        ReplayItem nxt = cur;
-        if (k + parts < n_items) nxt = out.items[k + parts];
+        const ReplayItem cur = out.items[k];
         int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
         if (bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en)) {
             world_counts<kReplayNT>(q, ctl, st, sh);
@@ -1242,7 +1252,6 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
             else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         }
         __syncthreads();
-        cur = nxt;
     }
     if (t == 0) {
         add_work_at(out, 3, part, acc_w, acc_e, acc_b);
