@@ -274,7 +274,7 @@ def main():
         "kernel_ms_per_step": kern,
         "world_evaluations_by_kind_per_step": {
             nm: work[t][0] / args.steps for nm, t in (("sampled_tier0", 0), ("sampled_tier1", 1), ("sampled_tier2", 2),
-                                                       ("replayed", 3), ("forest_updated", 4))},
+                                                       ("replayed", 3), ("label_updated", 4))},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves "

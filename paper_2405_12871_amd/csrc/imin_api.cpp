@@ -352,7 +352,7 @@ struct Session {
         }
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
-            work_stride = std::max(std::max(std::max(grid0, grid1), std::max(grid_r, grid_t)), bs.n_slots);
+            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_t), bs.n_slots);
             const size_t wn = (size_t)3 * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
             IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));

@@ -109,7 +109,13 @@ struct ReplayItem {
     int32_t j;           // entry of the new blocker
     int32_t cj;          // its count
     uint32_t labj;       // its label
-    int32_t pad;
+    int32_t flags;       // the world's kWorld* flags
+};
+
+// Per-world state of the resident store.
+enum : uint8_t {
+    kWorldForest = 1,    // the reached live edges form a forest under the seeds
+    kWorldLabelled = 2,  // the stored labels describe the world's dominator tree
 };
 
 // Dominator-tree label of a stored entry: preorder index (high 16 bits) and
@@ -171,7 +177,7 @@ struct TileOut {
     // a blocker only removes its subtree; the entries carry their labels.
     uint32_t* scr_lab;    // aligned with scr_node
     uint32_t* store_lab;  // aligned with store_node
-    uint8_t* world_tree;  // [theta] 1: the world's labels describe its dominator tree, which is a forest
+    uint8_t* world_tree;  // [theta] kWorld* flags
     // Incremental rounds: nodes each workgroup's worlds lost, one slot per
     // (kernel, workgroup); summed and cleared by the selection.
     long long* dsz;

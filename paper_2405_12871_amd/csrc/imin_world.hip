@@ -607,7 +607,8 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
         if (out.keep_edges) {
             // a world with no extra live edge is a forest: its labels serve
             // the incremental rounds directly
-            if (t == 0 && out.world_tree) out.world_tree[w] = (Store::kLabels && nx == 0) ? 1 : 0;
+            if (t == 0 && out.world_tree)
+                out.world_tree[w] = Store::kLabels ? (uint8_t)(kWorldLabelled | (nx == 0 ? kWorldForest : 0)) : 0;
             // worlds beyond the replay's limits need the sampling tiers later
             if (t == 0 && (len > kReplayCap || nx > kReplayXCap || len + nx > kReplayEdgeCap || ns + len > 32767))
                 atomicOr(&ctl->replay_big, 1u);
@@ -941,7 +942,8 @@ __global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, co
             c = out.store_cnt[pos];
         }
         const bool live = c > 0;
-        const bool tree = live && out.world_tree && out.world_tree[w];
+        const uint8_t wflags = (live && out.world_tree) ? out.world_tree[w] : (uint8_t)0;
+        const bool tree = (wflags & kWorldForest) != 0;
         const unsigned long long mt = __ballot(tree);
         const unsigned long long mr = __ballot(live && !tree);
         uint32_t bt = 0, br = 0;
@@ -962,7 +964,7 @@ __global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, co
                 it.j = (int32_t)((int64_t)pos - it.store_off);
                 it.cj = c;
                 it.labj = out.store_lab ? out.store_lab[pos] : 0u;
-                it.pad = 0;
+                it.flags = wflags;
                 if (tree) {
                     out.titems[at] = it;
                 } else {
@@ -1042,6 +1044,40 @@ constexpr int kReplayNT = 256;                          // four waves per replay
 constexpr int kReplaySlots = kReplayEdgeCap / kReplayNT;  // stored edges per thread
 constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 
+// The forest rule on a world's entries held in registers: entries in u's
+// label range lose their whole count, u's ancestors lose count(u), and T
+// loses count(u).
+template <int NT>
+__device__ void replay_local_update(const ReplayItem& it, int32_t ustar, const TileOut& out,
+                                    const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots],
+                                    const uint32_t (&el)[kReplayEntrySlots]) {
+    const int t = threadIdx.x;
+    const size_t so = (size_t)it.store_off;
+    const int L0 = it.store_len;
+    const int tj = (int)(it.labj >> 16);
+    const int szj = (int)(it.labj & 0xFFFFu);
+    const int cj = it.cj;
+#pragma unroll
+    for (int r = 0; r < kReplayEntrySlots; ++r) {
+        const int i = t + r * NT;
+        if (i >= L0 || ec[r] <= 0) continue;
+        const int ti = (int)(el[r] >> 16);
+        const int si = (int)(el[r] & 0xFFFFu);
+        int d = 0, cn = 0;
+        if (ti >= tj && ti < tj + szj) {
+            d = -ec[r];
+        } else if (tj >= ti && tj < ti + si) {
+            d = -cj;
+            cn = ec[r] - cj;
+        }
+        if (d != 0) {
+            if (en[r] != ustar) atomicAdd((unsigned long long*)&out.gain[en[r]], (unsigned long long)(long long)d);
+            out.store_cnt[so + i] = cn;
+        }
+    }
+    if (t == 0) out.world_size[it.w] = it.world_size - cj;
+}
+
 // The stored edges stay in registers (kReplaySlots per thread); each level
 // looks up the new id of every pending edge's source and claims the heads
 // of the edges leaving the frontier.  Every edge is used once, when its
@@ -1054,10 +1090,17 @@ constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 // their slot id into cur[head]; the edge whose id stays there claims it,
 // the other edges into reached heads become extra edges, and one
 // workgroup-wide scan hands out the new local ids and extra-edge slots.
+//
+// Before the BFS, a world with valid labels is checked for a shortcut: if no
+// stored live edge leads from a reached node of u's dominator subtree to a
+// reached node outside it, no path to a node outside the subtree passes
+// through the subtree, so blocking u removes exactly the subtree and leaves
+// every other dominator (and label) as it was: the forest rule applies.
+// Returns 1 when the world was replayed, 2 when the shortcut applied, 0 when
+// the world exceeds the replay's limits.
 template <int NT, class RS>
-__device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
-                           WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots],
-                           int32_t (&en)[kReplayEntrySlots]) {
+__device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
+                          WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots], int32_t (&en)[kReplayEntrySlots]) {
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     const size_t so = (size_t)it.store_off;
@@ -1068,19 +1111,23 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
     // room, local ids that fit the 16-bit arrays, ranges inside the stores
     // (uniform checks)
     if (L0 < 0 || X0 < 0 || L0 > RS::kCap || X0 > RS::cap_x() || E > NT * kReplaySlots || ns + L0 > 32767)
-        return false;
+        return 0;
     if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap)
-        return false;
+        return 0;
+    const bool labelled = (it.flags & kWorldLabelled) != 0;
     // one batch of loads: entries, then edges (the tree edge of entry e is
     // its round-0 parent; then the extras)
+    uint32_t el[kReplayEntrySlots];
 #pragma unroll
     for (int r = 0; r < kReplayEntrySlots; ++r) {
         const int i = t + r * NT;
         ec[r] = 0;
         en[r] = -1;
+        el[r] = 0;
         if (i < L0) {
             ec[r] = out.store_cnt[so + i];
             en[r] = out.store_node[so + i];
+            if (labelled) el[r] = out.store_lab[so + i];
         }
     }
     uint32_t ed[kReplaySlots];
@@ -1099,6 +1146,31 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
         const bool ok = u >= 0 && u < ns + L0 && vi >= 0 && vi < L0;
         ed[r] = ok ? (((uint32_t)u << 16) | (uint32_t)vi) : 0u;  // inactive slots read entry 0, harmlessly
         act |= ok ? (1u << r) : 0u;
+    }
+    if (labelled) {
+        // reached entries' preorder indexes (-1: not reached) for the edge test
+        const int tj = (int)(it.labj >> 16);
+        const int szj = (int)(it.labj & 0xFFFFu);
+#pragma unroll
+        for (int r = 0; r < kReplayEntrySlots; ++r) {
+            const int i = t + r * NT;
+            if (i < L0) st.cur[i] = (ec[r] > 0) ? (int)(el[r] >> 16) : -1;
+        }
+        __syncthreads();
+        bool escape = false;
+#pragma unroll
+        for (int r = 0; r < kReplaySlots; ++r) {
+            const int u = (int)(ed[r] >> 16);
+            if (((act >> r) & 1u) && u >= ns) {
+                const int ts = st.cur[u - ns];
+                const int th = st.cur[ed[r] & 0xFFFFu];
+                escape |= ts >= tj && ts < tj + szj && th >= 0 && (th < tj || th >= tj + szj);
+            }
+        }
+        if (!__syncthreads_or(escape)) {
+            replay_local_update<NT>(it, ustar, out, ec, en, el);
+            return 2;
+        }
     }
 #pragma unroll
     for (int r = 0; r < kReplayEntrySlots; ++r) {
@@ -1164,8 +1236,8 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
         }
         count += tot & 0xFFFF;
         nx += tot >> 16;
-        if (nx > st.cap_x()) return false;         // uniform
-        if (nlev + 1 > st.cap_lv()) return false;  // uniform
+        if (nx > st.cap_x()) return 0;         // uniform (cannot happen within the limits)
+        if (nlev + 1 > st.cap_lv()) return 0;  // uniform (cannot happen within the limits)
         if (t == 0) st.lvl[nlev + 1] = count;
         ++nlev;
         f0 = f1;
@@ -1179,7 +1251,7 @@ __device__ bool bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& i
         sh.nlevels = nlev - 1;
     }
     __syncthreads();
-    return true;
+    return 1;
 }
 
 // Count changes of a replayed world: each entry's new count against the one
@@ -1218,7 +1290,7 @@ __device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut
     __syncthreads();
     if (t == 0) {
         out.world_size[it.w] = sh.count;
-        if (out.world_tree) out.world_tree[it.w] = (sh.n_extra == 0) ? 1 : 0;
+        if (out.world_tree) out.world_tree[it.w] = kWorldLabelled | ((sh.n_extra == 0) ? kWorldForest : 0);
     }
     return sh.ndelta;
 }
@@ -1232,12 +1304,20 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
     const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
     if (part >= n_items) return;
     const int32_t ustar = ctl->ustar;
-    unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
+    unsigned long long acc_w = 0, acc_e = 0, acc_b = 0, acc_lw = 0, acc_le = 0, acc_lb = 0;
     long long acc_d = 0;
     for (uint32_t k = part; k < n_items; k += parts) {
         const ReplayItem cur = out.items[k];
         int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
-        if (bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en)) {
+        const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en);
+        if (how == 2) {
+            // the shortcut: reported with the label-based updates
+            acc_lw += 1;
+            acc_le += (unsigned long long)(cur.store_len + cur.xstore_len);
+            acc_lb += sizeof(ReplayItem) + 16ull * (unsigned long long)cur.store_len +
+                      8ull * (unsigned long long)cur.xstore_len + 8ull;
+            acc_d += cur.cj;
+        } else if (how == 1) {
             world_counts<kReplayNT>(q, ctl, st, sh);
             world_labels<kReplayNT>(q, st, sh);
             const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
@@ -1255,6 +1335,7 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
     }
     if (t == 0) {
         add_work_at(out, 3, part, acc_w, acc_e, acc_b);
+        add_work_at(out, 4, out.work_stride - 1 - part, acc_lw, acc_le, acc_lb);
         // T is lowered by the nodes the replayed worlds lost
         if (acc_d) out.dsz[out.dsz_off[3] + part] = acc_d;
     }
