@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/imin.h.
 #include "imin.h"
 #include "imin_internal.hpp"
+#include "imin_select.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -253,14 +254,30 @@ struct Session {
     Session(const Session&) = delete;
     Session& operator=(const Session&) = delete;
 
-    // one incremental round: changed worlds, then the selection
-    imin_status_t delta_round(const imin::QueryDev& q, uint64_t theta, int32_t k, int32_t* blockers,
-                              int64_t* gains, int64_t* totals, int32_t* n_selected) {
-        imin_status_t st = evaluate_delta(q, theta);
+    imin::SelectOut select_out(int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,
+                               int32_t* n_selected) const {
+        imin::SelectOut so{};
+        so.parts = sel_parts;
+        so.pg = sel_g.p;
+        so.pu = sel_u.p;
+        so.pd = sel_d.p;
+        so.excl = excl.p;
+        so.k = k;
+        so.blockers = blockers;
+        so.gains = gains;
+        so.totals = totals;
+        so.n_selected = n_selected;
+        return so;
+    }
+
+    // one incremental round: the last selection committed and the changed
+    // worlds found, the changed worlds updated, then this round's partial
+    // selection (committed by the next round, or by a final combining launch)
+    imin_status_t delta_round(const imin::QueryDev& q, uint64_t theta, const imin::SelectOut& so) {
+        imin_status_t st = evaluate_delta(q, theta, so);
         if (st != IMIN_OK) return st;
         hipEvent_t ev = timed.begin(3, s);
-        IMIN_TRY(imin::launch_select(g, gain.p, excl.p, ctl.p, sel_g.p, sel_u.p, sel_d.p, dsz.p, dsz_n, sel_parts, k,
-                                     blockers, gains, totals, n_selected, s));
+        IMIN_TRY(imin::launch_select(g, gain.p, ctl.p, so, dsz.p, dsz_n, false, s));
         timed.end(3, ev, s);
         return IMIN_OK;
     }
@@ -584,13 +601,13 @@ struct Session {
 
     // One incremental round: worlds holding the last blocker are re-evaluated
     // and report their count changes; gain is updated in place.
-    imin_status_t evaluate_delta(const imin::QueryDev& q, uint64_t theta) {
+    imin_status_t evaluate_delta(const imin::QueryDev& q, uint64_t theta, const imin::SelectOut& so) {
         imin::TileOut out = tile_out();
         out.mode = imin::kModeDelta;
         out.world_size = world_size.p;
         // the per-round counters were cleared by the last selection
         hipEvent_t ev = timed.begin(5, s);
-        IMIN_TRY(imin::launch_affected(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, s));
+        IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, so, s));
         timed.end(5, ev, s);
         imin_status_t st;
         if (replay) {
@@ -875,6 +892,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
         if (st != IMIN_OK) return st;
     }
     const size_t batch = env_size("IMIN_ROUND_BATCH", 32);
+    const imin::SelectOut so = ss.select_out(k, blockers, gains, spread_totals, n_selected);
     bool indexed = false;
     for (int32_t r = 0; r <= k;) {
         if (r > 0 && ss.incremental) {
@@ -887,7 +905,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             // the selection stops, every later kernel returns at once
             const int32_t nb = (int32_t)std::min<size_t>(batch, (size_t)(k + 1 - r));
             for (int32_t i = 0; i < nb; ++i) {
-                st = ss.delta_round(q, (uint64_t)theta, k, blockers, gains, spread_totals, n_selected);
+                st = ss.delta_round(q, (uint64_t)theta, so);
                 if (st != IMIN_OK) return st;
             }
             r += nb;
@@ -896,10 +914,11 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
             IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
             st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, r == 0);
             if (st != IMIN_OK) return st;
+            // when incremental rounds follow, the first of them commits this
+            // selection; otherwise a combining launch does
+            const bool combine = !ss.incremental || k == 0;
             hipEvent_t ev = ss.timed.begin(3, s);
-            IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.excl.p, ss.ctl.p, ss.sel_g.p, ss.sel_u.p, ss.sel_d.p,
-                                         ss.dsz.p, ss.dsz_n, ss.sel_parts,
-                                         k, blockers, gains, spread_totals, n_selected, s));
+            IMIN_TRY(imin::launch_select(g->g, ss.gain.p, ss.ctl.p, so, ss.dsz.p, ss.dsz_n, combine, s));
             ss.timed.end(3, ev, s);
             ++r;
         }

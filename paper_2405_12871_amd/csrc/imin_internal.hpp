@@ -45,6 +45,7 @@ struct RoundCtl {
     uint32_t flags;
     int32_t stop;
     int32_t round;
+    int32_t round_snap;      // the round as the last partial selection saw it
     int32_t ustar;
     uint32_t next[3];        // work counters of the three world tiers
     uint32_t list_n[3];      // worlds handed down to tier 1 and tier 2
@@ -255,8 +256,9 @@ constexpr int kTreeNT = 256;  // four worlds at a time per workgroup
 hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
-hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
-                           const int32_t* idx_world, int32_t* list, hipStream_t s);
+struct SelectOut;
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
+                                  const int32_t* idx_world, int32_t* list, const SelectOut& so, hipStream_t s);
 hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
@@ -269,12 +271,12 @@ hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const Redu
                                RoundCtl* ctl, int64_t* gain, hipStream_t s);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
 // Argmax of gain over the candidates (ties to the smaller id), the stop rule
-// and the round's T; also sums and clears the dsz slots (nodes lost by the
-// round's changed worlds) into T and clears the per-round counters.
-hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl, RoundCtl* ctl,
-                         int64_t* part_gain, int32_t* part_node, long long* part_dsz, long long* dsz,
-                         int32_t dsz_n, int parts, int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,
-                         int32_t* n_selected, hipStream_t s);
+// and the round's T; the partial launch also sums and clears the dsz slots
+// (nodes lost by the round's changed worlds) and clears the next round's
+// counters.  With `combine` a second launch commits the selection; else the
+// next incremental round's search does.
+hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, const SelectOut& so, long long* dsz,
+                         int32_t dsz_n, bool combine, hipStream_t s);
 
 
 } // namespace imin

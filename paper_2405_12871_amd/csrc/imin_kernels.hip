@@ -8,6 +8,7 @@
 // are added in a fixed order.
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
+#include "imin_select.hpp"
 
 namespace imin {
 
@@ -390,39 +391,13 @@ hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStr
 
 // ----------------------------------------------------------- selection
 // argmax over candidates (not seeds, not blocked) of (gain desc, id asc).
-__device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32_t u2) {
-    if (u2 < 0) return u1 >= 0;
-    if (u1 < 0) return false;
-    return g1 > g2 || (g1 == g2 && u1 < u2);
-}
-
 // Two launches: every workgroup of the first reduces a slice of the
-// candidates (and of the dsz slots) to a part; one workgroup combines the
-// parts and applies the round's selection.  After a selection it also clears
-// the per-round counters for the next incremental round.  (A single launch
+// candidates (and of the dsz slots) to a part; then one workgroup, or in an
+// incremental round the search for the next round's changed worlds,
+// combines the parts and applies the round's selection.  (A single launch
 // whose last workgroup combines the parts needs a counter that every
 // workgroup updates, and same-address atomics serialise.)
-__device__ __forceinline__ void select_block_best(int64_t& bg, int32_t& bu, long long& dl, int64_t* sg,
-                                                  int32_t* su, long long* sd) {
-    sg[threadIdx.x] = bg;
-    su[threadIdx.x] = bu;
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if (threadIdx.x < d) {
-            const int o = threadIdx.x + d;
-            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
-                sg[threadIdx.x] = sg[o];
-                su[threadIdx.x] = su[o];
-            }
-        }
-        __syncthreads();
-    }
-    dl = block_sum_ll<256>(dl, sd);
-    bg = sg[0];
-    bu = su[0];
-}
-
-__global__ __launch_bounds__(256) void k_select_partial(const RoundCtl* ctl, int32_t n, const int64_t* gain,
+__global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n, const int64_t* gain,
                                                         const uint32_t* excl, int64_t* pg, int32_t* pu,
                                                         long long* dsz, int32_t dsz_n, long long* pd) {
     __shared__ int64_t sg[256];
@@ -452,66 +427,37 @@ __global__ __launch_bounds__(256) void k_select_partial(const RoundCtl* ctl, int
         pg[blockIdx.x] = bg;
         pu[blockIdx.x] = bu;
         pd[blockIdx.x] = dl;
+        if (blockIdx.x == 0) {
+            // for the combining launch: the round, and the next round's counters cleared
+            ctl->round_snap = ctl->round;
+            for (int i = 0; i < 3; ++i) {
+                ctl->next[i] = 0;
+                ctl->list_n[i] = 0;
+            }
+            ctl->tree_n = 0;
+            ctl->pair_count = 0;
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_select_final(int parts, const int64_t* pg, const int32_t* pu,
-                                                      const long long* pd, uint32_t* excl, RoundCtl* ctl, int32_t k,
-                                                      int32_t* blockers, int64_t* gains, int64_t* totals,
-                                                      int32_t* n_selected) {
+__global__ __launch_bounds__(256) void k_select_final(SelectOut so, RoundCtl* ctl) {
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
     __shared__ long long sd[4];
-    int64_t bg = 0;
-    int32_t bu = -1;
-    long long dl = 0;
-    for (int i = threadIdx.x; i < parts; i += 256) {
-        if (better(pg[i], pu[i], bg, bu)) { bg = pg[i]; bu = pu[i]; }
-        dl += pd[i];
-    }
-    select_block_best(bg, bu, dl, sg, su, sd);
+    int64_t bg;
+    int32_t bu;
+    long long dl;
+    select_combine(so, bg, bu, dl, sg, su, sd);
     if (threadIdx.x != 0 || ctl->stop) return;
-    const int r = ctl->round;
-    if (dl) ctl->total -= dl;
-    const long long T = ctl->total;
-    if (ctl->expect_total >= 0 && ctl->expect_total != T) atomicOr(&ctl->flags, (uint32_t)kFlagSpreadMismatch);
-    totals[r] = T;
-    // counters of the next incremental round
-    for (int i = 0; i < 3; ++i) {
-        ctl->next[i] = 0;
-        ctl->list_n[i] = 0;
-    }
-    ctl->tree_n = 0;
-    ctl->pair_count = 0;
-    if (r >= k || bu < 0 || bg <= 0) {
-        ctl->stop = 1;
-        *n_selected = r;
-        return;
-    }
-    blockers[r] = bu;
-    gains[r] = bg;
-    excl[bu >> 5] |= 1u << (bu & 31);
-    ctl->ustar = bu;
-    ctl->best_gain = bg;
-    ctl->round = r + 1;
-    ctl->expect_total = T - bg;
-    if (r + 1 == k) {
-        // T_k follows exactly from T_{k-1} - gain_{k-1}
-        totals[k] = T - bg;
-        ctl->stop = 1;
-        *n_selected = k;
-    }
+    select_commit(ctl, so, ctl->round, bg, bu, dl);
 }
 
-hipError_t launch_select(const GraphDev& g, const int64_t* gain, uint32_t* excl, RoundCtl* ctl,
-                         int64_t* part_gain, int32_t* part_node, long long* part_dsz, long long* dsz,
-                         int32_t dsz_n, int parts, int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,
-                         int32_t* n_selected, hipStream_t s) {
-    k_select_partial<<<parts, 256, 0, s>>>(ctl, g.n, gain, excl, part_gain, part_node, dsz, dsz_n, part_dsz);
+hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, const SelectOut& so, long long* dsz,
+                         int32_t dsz_n, bool combine, hipStream_t s) {
+    k_select_partial<<<so.parts, 256, 0, s>>>(ctl, g.n, gain, so.excl, so.pg, so.pu, dsz, dsz_n, so.pd);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    k_select_final<<<1, 256, 0, s>>>(parts, part_gain, part_node, part_dsz, excl, ctl, k, blockers, gains, totals,
-                                     n_selected);
+    if (e != hipSuccess || !combine) return e;
+    k_select_final<<<1, 256, 0, s>>>(so, ctl);
     return hipGetLastError();
 }
 

@@ -1,0 +1,103 @@
+// Greedy selection (§2.2, the greedy framework): argmax of the gains over the
+// candidates V \ (S ∪ B), ties to the smaller node id, and the round's
+// bookkeeping.  Shared by the selection kernels and by the search for the
+// changed worlds, which finishes the selection of the round before it.
+#pragma once
+
+#include "imin_device.hpp"
+#include "imin_internal.hpp"
+
+namespace imin {
+
+__device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32_t u2) {
+    if (u2 < 0) return u1 >= 0;
+    if (u1 < 0) return false;
+    return g1 > g2 || (g1 == g2 && u1 < u2);
+}
+
+// Workgroup-wide best (gain, node) and sum of the lost-node counts (256 threads).
+__device__ __forceinline__ void select_block_best(int64_t& bg, int32_t& bu, long long& dl, int64_t* sg,
+                                                  int32_t* su, long long* sd) {
+    sg[threadIdx.x] = bg;
+    su[threadIdx.x] = bu;
+    __syncthreads();
+    for (int d = 128; d >= 1; d >>= 1) {
+        if (threadIdx.x < d) {
+            const int o = threadIdx.x + d;
+            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
+                sg[threadIdx.x] = sg[o];
+                su[threadIdx.x] = su[o];
+            }
+        }
+        __syncthreads();
+    }
+    dl = block_sum_ll<256>(dl, sd);
+    bg = sg[0];
+    bu = su[0];
+}
+
+// Where a selection's parts are and where its results go.
+struct SelectOut {
+    int32_t parts;
+    int64_t* pg;           // per part: best gain
+    int32_t* pu;           //           its node
+    long long* pd;         //           nodes lost by the round's changed worlds
+    uint32_t* excl;        // bitmap of seeds and blockers
+    int32_t k;
+    int32_t* blockers;
+    int64_t* gains;
+    int64_t* totals;
+    int32_t* n_selected;
+};
+
+// Combine the parts in one workgroup (every workgroup gets the same result).
+__device__ __forceinline__ void select_combine(const SelectOut& so, int64_t& bg, int32_t& bu, long long& dl,
+                                               int64_t* sg, int32_t* su, long long* sd) {
+    bg = 0;
+    bu = -1;
+    dl = 0;
+    for (int i = threadIdx.x; i < so.parts; i += 256) {
+        if (better(so.pg[i], so.pu[i], bg, bu)) {
+            bg = so.pg[i];
+            bu = so.pu[i];
+        }
+        dl += so.pd[i];
+    }
+    select_block_best(bg, bu, dl, sg, su, sd);
+}
+
+// The selection stops at round r when the budget is spent or no candidate
+// with a positive gain is left.
+__device__ __forceinline__ bool select_stops(int r, int32_t k, int32_t bu, int64_t bg) {
+    return r >= k || bu < 0 || bg <= 0;
+}
+
+// Round r's bookkeeping (one thread): T_r, the check T_r = T_{r-1} - gain,
+// the blocker, and the stop rule.
+__device__ __forceinline__ void select_commit(RoundCtl* ctl, const SelectOut& so, int r, int64_t bg, int32_t bu,
+                                              long long dl) {
+    if (dl) ctl->total -= dl;
+    const long long T = ctl->total;
+    if (ctl->expect_total >= 0 && ctl->expect_total != T) atomicOr(&ctl->flags, (uint32_t)kFlagSpreadMismatch);
+    so.totals[r] = T;
+    if (select_stops(r, so.k, bu, bg)) {
+        ctl->stop = 1;
+        *so.n_selected = r;
+        return;
+    }
+    so.blockers[r] = bu;
+    so.gains[r] = bg;
+    so.excl[bu >> 5] |= 1u << (bu & 31);
+    ctl->ustar = bu;
+    ctl->best_gain = bg;
+    ctl->round = r + 1;
+    ctl->expect_total = T - bg;
+    if (r + 1 == so.k) {
+        // T_k follows exactly from T_{k-1} - gain_{k-1}
+        so.totals[so.k] = T - bg;
+        ctl->stop = 1;
+        *so.n_selected = so.k;
+    }
+}
+
+}  // namespace imin

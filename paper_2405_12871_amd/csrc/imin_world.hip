@@ -30,6 +30,7 @@
 // one; every tier gives the same integers.
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
+#include "imin_select.hpp"
 
 #include <algorithm>
 
@@ -922,14 +923,26 @@ __global__ void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32
     }
 }
 
-// Worlds whose entry for the last selected blocker is live, with their store
-// ranges and that entry: forest worlds -> titems[0 .. tree_n), the others ->
-// items / list[0 .. list_n[0]).
-__global__ __launch_bounds__(256) void k_affected(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
-                                                  const int32_t* idx_pos, const int32_t* idx_world,
-                                                  int32_t* list) {
+// An incremental round starts here.  Every workgroup combines the parts of
+// the last selection (the same result everywhere); workgroup 0 commits it.
+// Then the worlds whose entry for the new blocker u is live are listed, with
+// their store ranges and that entry: forest worlds -> titems[0 .. tree_n),
+// the others -> items / list[0 .. list_n[0]).
+__global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
+                                                         const int32_t* idx_pos, const int32_t* idx_world,
+                                                         int32_t* list, SelectOut so) {
+    __shared__ int64_t sg[256];
+    __shared__ int32_t su[256];
+    __shared__ long long sd[4];
     if (ctl->stop) return;
-    const int32_t u = ctl->ustar;
+    int64_t bg;
+    int32_t bu;
+    long long dl;
+    select_combine(so, bg, bu, dl, sg, su, sd);
+    const int r = ctl->round_snap;  // written by the partial launch; workgroup 0 updates ctl->round
+    if (blockIdx.x == 0 && threadIdx.x == 0) select_commit(ctl, so, r, bg, bu, dl);
+    if (select_stops(r, so.k, bu, bg) || r + 1 == so.k) return;  // no further round
+    const int32_t u = bu;
     const int32_t a = idx_off[u], b = idx_off[u + 1];
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
@@ -993,9 +1006,9 @@ hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor
     return hipGetLastError();
 }
 
-hipError_t launch_affected(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
-                           const int32_t* idx_world, int32_t* list, hipStream_t s) {
-    k_affected<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_pos, idx_world, list);
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
+                                  const int32_t* idx_world, int32_t* list, const SelectOut& so, hipStream_t s) {
+    k_affected_select<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_pos, idx_world, list, so);
     return hipGetLastError();
 }
 
