@@ -526,7 +526,7 @@ struct Session {
         IMIN_TRY(titems.alloc(theta));
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
-        IMIN_TRY(imin::launch_index_count(out, entries, idx_off.p, s));
+        IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, s));
         IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
         IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_pos.p, idx_world.p, s));

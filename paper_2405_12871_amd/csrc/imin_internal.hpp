@@ -253,7 +253,7 @@ hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s)
 hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                  int replay_parts, int forest_parts, hipStream_t s);
 constexpr int kTreeNT = 256;  // four worlds at a time per workgroup
-hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s);
+hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
 struct SelectOut;

@@ -901,22 +901,124 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
 // still live (count > 0): every other world keeps its reached set and its
 // dominator tree.
 
-// count entries per node
-__global__ void k_index_count(const int32_t* store_node, unsigned long long n_entries, int32_t* cnt) {
-    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n_entries; p += (size_t)gridDim.x * blockDim.x)
-        atomicAdd(&cnt[store_node[p]], 1);
-}
+// Hub nodes hold entries in most worlds, so counting and placing with one
+// global atomic per entry would serialise on their counters.  Each
+// workgroup takes a run of worlds, counts its entries per node in an LDS
+// table and touches a node's global counter once; placing, it reserves one
+// block of positions per node and hands them out in LDS.  A node that finds
+// no table slot (all of its probe slots taken) uses the global counter for
+// each of its entries.
+constexpr int kIdxNT = 256;
+constexpr int kIdxSlotsLog = 12;
+constexpr int kIdxSlots = 1 << kIdxSlotsLog;
+constexpr int kIdxProbes = 32;
+constexpr uint32_t kIdxWorldsPerWG = 32;
 
-// one wave per world: place (position, world) of each entry at its node's cursor
-__global__ void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32_t* idx_pos, int32_t* idx_world) {
+struct IdxTable {
+    int32_t keys[kIdxSlots];
+    int32_t cnt[kIdxSlots];
+    int32_t base[kIdxSlots];
+
+    __device__ void clear() {
+        for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
+            keys[i] = -1;
+            cnt[i] = 0;
+        }
+    }
+    // slot of node u, claimed if new; -1 when none is free
+    __device__ int slot(int32_t u) {
+        const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - kIdxSlotsLog);
+        for (int p = 0; p < kIdxProbes; ++p) {
+            const int sl = (int)((h + (uint32_t)p) & (kIdxSlots - 1));
+            int32_t k = keys[sl];
+            if (k == -1) {
+                k = atomicCAS(&keys[sl], -1, u);
+                if (k == -1) return sl;
+            }
+            if (k == u) return sl;
+        }
+        return -1;
+    }
+    // slot of node u if present (no claim)
+    __device__ int find(int32_t u) const {
+        const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - kIdxSlotsLog);
+        for (int p = 0; p < kIdxProbes; ++p) {
+            const int sl = (int)((h + (uint32_t)p) & (kIdxSlots - 1));
+            const int32_t k = keys[sl];
+            if (k == u) return sl;
+            if (k == -1) return -1;
+        }
+        return -1;
+    }
+};
+
+// the workgroup's entries, counted per node in LDS (overflow straight to spill)
+__device__ void index_count_lds(const TileOut& out, uint32_t w0, uint32_t w1, IdxTable& tb, int32_t* spill) {
     const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * (uint32_t)blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * (uint32_t)blockDim.x) >> 6;
-    for (uint32_t w = wave; w < theta; w += nwaves) {
+    for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
         const size_t so = (size_t)out.store_off[w];
         const int len = out.store_len[w];
         for (int i = lane; i < len; i += 64) {
-            const int pos = atomicAdd(&cursor[out.store_node[so + i]], 1);
+            const int32_t u = out.store_node[so + i];
+            const int sl = tb.slot(u);
+            if (sl >= 0) atomicAdd(&tb.cnt[sl], 1);
+            else atomicAdd(&spill[u], 1);
+        }
+    }
+}
+
+// count entries per node
+__global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t theta, int32_t* cnt) {
+    __shared__ IdxTable tb;
+    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
+    if (w0 >= theta) return;
+    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
+    tb.clear();
+    __syncthreads();
+    index_count_lds(out, w0, w1, tb, cnt);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT)
+        if (tb.keys[i] >= 0) atomicAdd(&cnt[tb.keys[i]], tb.cnt[i]);
+}
+
+// place (position, world) of each entry in its node's range
+__global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
+                                                       int32_t* idx_world) {
+    __shared__ IdxTable tb;
+    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
+    if (w0 >= theta) return;
+    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
+    tb.clear();
+    __syncthreads();
+    // local counts only: entries of nodes without a slot take global positions below
+    {
+        const int lane = threadIdx.x & 63;
+        for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
+            const size_t so = (size_t)out.store_off[w];
+            const int len = out.store_len[w];
+            for (int i = lane; i < len; i += 64) {
+                const int sl = tb.slot(out.store_node[so + i]);
+                if (sl >= 0) atomicAdd(&tb.cnt[sl], 1);
+            }
+        }
+    }
+    __syncthreads();
+    // one block of positions per node, handed out locally
+    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
+        if (tb.keys[i] >= 0) {
+            tb.base[i] = atomicAdd(&cursor[tb.keys[i]], tb.cnt[i]);
+            tb.cnt[i] = 0;
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
+        const size_t so = (size_t)out.store_off[w];
+        const int len = out.store_len[w];
+        for (int i = lane; i < len; i += 64) {
+            const int32_t u = out.store_node[so + i];
+            const int sl = tb.find(u);
+            const int pos = (sl >= 0) ? tb.base[sl] + atomicAdd(&tb.cnt[sl], 1) : atomicAdd(&cursor[u], 1);
             idx_pos[pos] = (int32_t)(so + i);
             idx_world[pos] = (int32_t)w;
         }
@@ -991,18 +1093,18 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     }
 }
 
-hipError_t launch_index_count(const TileOut& out, unsigned long long n_entries, int32_t* cnt, hipStream_t s) {
-    unsigned blocks = (unsigned)std::min<unsigned long long>((n_entries + 255) / 256, 8192ull);
+hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s) {
+    const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
     if (blocks == 0) return hipSuccess;
-    k_index_count<<<blocks, 256, 0, s>>>(out.store_node, n_entries, cnt);
+    k_index_count<<<blocks, kIdxNT, 0, s>>>(out, theta, cnt);
     return hipGetLastError();
 }
 
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s) {
-    unsigned blocks = (theta + 3) / 4;
-    if (blocks > 8192) blocks = 8192;
-    k_index_fill<<<blocks, 256, 0, s>>>(out, theta, cursor, idx_pos, idx_world);
+    const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
+    if (blocks == 0) return hipSuccess;
+    k_index_fill<<<blocks, kIdxNT, 0, s>>>(out, theta, cursor, idx_pos, idx_world);
     return hipGetLastError();
 }
 
