@@ -102,8 +102,9 @@ imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m);
  *   n_selected     int32[1], device, out: number of blockers chosen (<= k;
  *                  fewer when every remaining candidate protects nothing)
  *
- * Entries past n_selected are left untouched.  The call allocates its own
- * scratch device memory and frees it before returning.  Errors:
+ * Entries past n_selected are left untouched.  The call takes its scratch
+ * device memory from the library's block cache (see imin_cache_release) and
+ * hands it back before returning.  Errors:
  * IMIN_ERR_INVALID, IMIN_ERR_DATA (bad seeds), IMIN_ERR_NOMEM,
  * IMIN_ERR_DEVICE, IMIN_ERR_INTERNAL.
  */
@@ -141,6 +142,20 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
                             int64_t* world_edges);
 
 /*
+ * Scratch device memory of imin_solve and imin_evaluate comes from a block
+ * cache, per device: a block released at the end of a call stays allocated
+ * for the next call (a request reuses a cached block of at most twice its
+ * size), because freeing and allocating gigabytes costs milliseconds per
+ * call.  The cache holds at most IMIN_CACHE_BYTES bytes (environment,
+ * default 64 GiB; the largest blocks are freed first beyond it), and an
+ * allocation that fails frees the device's cached blocks and tries again.
+ * imin_cache_release frees every cached block on every device.  Blocks in
+ * use by calls still running are not cached and are not touched.  Never
+ * fails.
+ */
+imin_status_t imin_cache_release(void);
+
+/*
  * Kernel timing, for measurement.  While enabled, the library brackets its
  * own kernel launches with HIP events on the stream they run on and adds
  * each launch's duration to a per-kernel tally (process-wide).  Kernel ids:
@@ -148,7 +163,7 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  *   1  world evaluation, HBM tier (four waves per world, any size)
  *   2  gain reduction of a from-scratch pass (bucket histogram, scan,
  *      scatter, accumulate, sum); incremental rounds add their changes to
- *      the gains inside kernels 1, 4, 6 and 7
+ *      the gains inside kernels 1, 4 and 6
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
  *   5  search for the worlds a new blocker changes (incremental rounds)

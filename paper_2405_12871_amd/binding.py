@@ -71,6 +71,8 @@ def load():
     lib.imin_timing_sample.restype = st
     lib.imin_timing_launches.argtypes = [ctypes.c_int, ctypes.POINTER(i64)]
     lib.imin_timing_launches.restype = st
+    lib.imin_cache_release.argtypes = []
+    lib.imin_cache_release.restype = st
     lib.imin_timing_reset.argtypes = []
     lib.imin_timing_reset.restype = st
     lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
@@ -227,6 +229,11 @@ def evaluate(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blo
     if edges:
         res.append(wedge.cpu().numpy())
     return tuple(res)
+
+
+def cache_release():
+    """Free the device blocks the library keeps cached between calls."""
+    _check(load().imin_cache_release())
 
 
 def timing_enable(on: bool = True):

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <vector>
 #include <cstdio>
@@ -132,31 +133,167 @@ void report_hip(const char* what, hipError_t e) {
         }                                               \
     } while (0)
 
-// Device allocation owned by a scope.
+size_t env_size(const char* name, size_t dflt) {
+    const char* v = std::getenv(name);
+    if (!v || !*v) return dflt;
+    char* end = nullptr;
+    const unsigned long long x = std::strtoull(v, &end, 10);
+    return (end && *end == '\0' && x > 0) ? (size_t)x : dflt;
+}
+
+// Device blocks kept between calls, per device.  Freeing gigabytes costs
+// milliseconds per call (and the next call of the same query allocates the
+// same sizes again), so released blocks stay cached up to a limit
+// (IMIN_CACHE_BYTES, default 64 GiB; imin_cache_release frees them).  A block
+// is handed out again for a request of at least half its size.  Blocks that a
+// call releases while its stream may still use them wait in the call's
+// ReleaseScope until the stream has drained.
+struct BlockCache {
+    std::mutex mu;
+    std::map<int, std::multimap<size_t, void*>> free_blocks;
+    size_t cached = 0;
+    size_t limit = env_size("IMIN_CACHE_BYTES", (size_t)64 << 30);
+
+    void* get(int dev, size_t bytes, size_t& got) {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto& m = free_blocks[dev];
+            auto it = m.lower_bound(bytes);
+            if (it != m.end() && it->first / 2 <= bytes) {
+                got = it->first;
+                void* p = it->second;
+                m.erase(it);
+                cached -= got;
+                return p;
+            }
+        }
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            release_device(dev);  // cached blocks may be what is missing
+            if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        }
+        got = bytes;
+        return p;
+    }
+    void put(int dev, void* p, size_t bytes) {
+        std::lock_guard<std::mutex> lk(mu);
+        auto& m = free_blocks[dev];
+        m.emplace(bytes, p);
+        cached += bytes;
+        while (cached > limit && !m.empty()) {  // the largest blocks go first
+            auto it = std::prev(m.end());
+            (void)hipFree(it->second);
+            cached -= it->first;
+            m.erase(it);
+        }
+    }
+    void release_device(int dev) {
+        std::lock_guard<std::mutex> lk(mu);
+        free_locked(dev);
+    }
+    void release_all() {
+        std::lock_guard<std::mutex> lk(mu);
+        for (auto& dm : free_blocks) free_locked(dm.first);
+    }
+    // frees every cached block of one device with that device current
+    void free_locked(int dev) {
+        auto& m = free_blocks[dev];
+        if (m.empty()) return;
+        int cur = dev;
+        (void)hipGetDevice(&cur);
+        if (cur != dev) (void)hipSetDevice(dev);
+        for (auto& kv : m) {
+            (void)hipFree(kv.second);
+            cached -= kv.first;
+        }
+        m.clear();
+        if (cur != dev) (void)hipSetDevice(cur);
+    }
+};
+BlockCache g_cache;
+
+struct CachedBlock {
+    int dev;
+    void* p;
+    size_t bytes;
+};
+thread_local std::vector<CachedBlock>* t_deferred = nullptr;
+
+// Blocks released during one call on one stream; they enter the cache once
+// the owner has synchronised that stream (the scope's end).
+struct ReleaseScope {
+    std::vector<CachedBlock> blocks;
+    std::vector<CachedBlock>* prev;
+    ReleaseScope() : prev(t_deferred) { t_deferred = &blocks; }
+    ReleaseScope(const ReleaseScope&) = delete;
+    ReleaseScope& operator=(const ReleaseScope&) = delete;
+    ~ReleaseScope() {
+        t_deferred = prev;
+        for (auto& b : blocks) g_cache.put(b.dev, b.p, b.bytes);
+    }
+};
+
+// Device allocation owned by a scope; its block returns to the cache.
 template <class T>
 struct DevArray {
     T* p = nullptr;
     size_t count = 0;
+    size_t bytes = 0;  // the block's size
+    int dev = 0;
     DevArray() = default;
     DevArray(const DevArray&) = delete;
     DevArray& operator=(const DevArray&) = delete;
     ~DevArray() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (t_deferred)
+                t_deferred->push_back({dev, p, bytes});
+            else
+                g_cache.put(dev, p, bytes);
+        }
         p = nullptr;
         count = 0;
+        bytes = 0;
     }
     hipError_t alloc(size_t c) {
         release();
+        if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
+        void* q = g_cache.get(dev, std::max<size_t>(c, 1) * sizeof(T), bytes);
+        if (!q) return hipErrorOutOfMemory;
+        p = static_cast<T*>(q);
         count = c;
-        return hipMalloc((void**)&p, std::max<size_t>(c, 1) * sizeof(T));
+        return hipSuccess;
+    }
+    void swap(DevArray& o) {
+        std::swap(p, o.p);
+        std::swap(count, o.count);
+        std::swap(bytes, o.bytes);
+        std::swap(dev, o.dev);
     }
 };
 
+// Pinned host copies of the round counters, reused across calls.
+std::mutex g_pinned_mu;
+std::vector<imin::RoundCtl*> g_pinned;
+
 struct HostCtl {
     imin::RoundCtl* p = nullptr;
+    hipError_t get() {
+        {
+            std::lock_guard<std::mutex> lk(g_pinned_mu);
+            if (!g_pinned.empty()) {
+                p = g_pinned.back();
+                g_pinned.pop_back();
+                return hipSuccess;
+            }
+        }
+        return hipHostMalloc((void**)&p, sizeof(imin::RoundCtl), hipHostMallocDefault);
+    }
     ~HostCtl() {
-        if (p) (void)hipHostFree(p);
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        g_pinned.push_back(p);
     }
 };
 
@@ -168,18 +305,11 @@ int cu_count() {
     return cus;
 }
 
-size_t env_size(const char* name, size_t dflt) {
-    const char* v = std::getenv(name);
-    if (!v || !*v) return dflt;
-    char* end = nullptr;
-    const unsigned long long x = std::strtoull(v, &end, 10);
-    return (end && *end == '\0' && x > 0) ? (size_t)x : dflt;
-}
-
 // Everything one query needs on the device besides the graph.
 struct Session {
     const imin::GraphDev& g;
     hipStream_t s;
+    ReleaseScope scope;  // destroyed after every array below, and after the destructor's synchronisation
     DevArray<uint32_t> excl;
     DevArray<int64_t> gain;
     DevArray<imin::RoundCtl> ctl;
@@ -251,6 +381,11 @@ struct Session {
     TimedLaunches timed;
 
     Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
+    // an early return may leave work queued: drain it before any block can
+    // be handed to another call
+    ~Session() {
+        if (hipStreamSynchronize(s) != hipSuccess) (void)hipGetLastError();
+    }
     Session(const Session&) = delete;
     Session& operator=(const Session&) = delete;
 
@@ -287,7 +422,7 @@ struct Session {
         IMIN_TRY(excl.alloc((n + 31) / 32));
         IMIN_TRY(gain.alloc(n));
         IMIN_TRY(ctl.alloc(1));
-        IMIN_TRY(hipHostMalloc((void**)&hctl.p, sizeof(imin::RoundCtl), hipHostMallocDefault));
+        IMIN_TRY(hctl.get());
         imin::RoundCtl c0{};
         c0.expect_total = -1;
         IMIN_TRY(hipMemcpyAsync(ctl.p, &c0, sizeof(c0), hipMemcpyHostToDevice, s));
@@ -490,10 +625,7 @@ struct Session {
                                        s) != hipSuccess)
                 return false;
         }
-        for (size_t i = 0; i < N; ++i) {
-            std::swap(arrs[i]->p, fresh[i].p);
-            std::swap(arrs[i]->count, fresh[i].count);
-        }
+        for (size_t i = 0; i < N; ++i) arrs[i]->swap(fresh[i]);
         return hipStreamSynchronize(s) == hipSuccess;  // old arrays are freed on return
     }
 
@@ -958,6 +1090,11 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     st = ss.read_ctl();
     if (st != IMIN_OK) return st;
     ss.finish();
+    return IMIN_OK;
+}
+
+imin_status_t imin_cache_release(void) {
+    g_cache.release_all();
     return IMIN_OK;
 }
 

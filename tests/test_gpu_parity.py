@@ -246,6 +246,29 @@ def test_solve_small_workload(B, oracle_mod):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+def test_block_cache_reuse(B, oracle_mod):
+    """Scratch blocks handed back to the cache and reused by later calls
+    (holding a previous call's contents), then freed and allocated afresh,
+    give the same selections every time."""
+    g1 = synth.random_small_graph(1500, 4500, seed=17, prob="wc")
+    g2 = synth.random_small_graph(300, 900, seed=18, prob="uniform")
+    s1 = np.array([3, 700], np.int32)
+    s2 = np.array([9], np.int32)
+    want1 = oracle_mod.Query(g1, s1).solve(8, 500, 5)
+    want2 = oracle_mod.Query(g2, s2).solve(5, 200, 6)
+    G1, G2 = B.Graph.from_synth(g1), B.Graph.from_synth(g2)
+    for step, (G, s, k, th, rs, want) in enumerate([(G1, s1, 8, 500, 5, want1), (G2, s2, 5, 200, 6, want2),
+                                                    (G1, s1, 8, 500, 5, want1), (None, None, 0, 0, 0, None),
+                                                    (G1, s1, 8, 500, 5, want1)]):
+        _log(f"block cache step {step}")
+        if G is None:
+            B.cache_release()
+            continue
+        res = B.solve(G, s, k, th, rs)
+        np.testing.assert_array_equal(res.blockers, want["blockers"])
+        np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 def test_example1_and_submodularity_graph(B):
     """The paper's worked example and the submodularity-ratio construction."""
     g = synth.from_edges(7, [0, 0, 1, 2, 3, 3, 5], [1, 2, 3, 3, 5, 6, 6], [1.0] * 7)
