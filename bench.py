@@ -195,7 +195,7 @@ def main():
     # the world kernel with the most time per solve
     # kernel -> (timer id, work tiers it reports)
     world_ids = {"world_tier0": (0, (0,)), "world_tier1": (4, (1,)), "world_tier2": (1, (2,)),
-                 "changed_worlds": (6, (3, 4))}
+                 "changed_worlds": (6, (3, 4, 5))}
     dom = max(world_ids, key=lambda nm: kern.get(nm, 0.0))
     dom_kid, dom_tiers = world_ids[dom]
     # events take time on the stream: one launch in TIMED_EVERY of the dominant
@@ -214,7 +214,7 @@ def main():
         log(f"step {i}: {lat[-1]:.1f} ms")
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
-    work = [binding.timing_work(t) for t in range(5)]
+    work = [binding.timing_work(t) for t in range(6)]
     n_dom, ms_dom = binding.timing_read(dom_kid)
     all_dom = binding.timing_launches(dom_kid)
     binding.timing_enable(False)
@@ -274,7 +274,8 @@ def main():
         "kernel_ms_per_step": kern,
         "world_evaluations_by_kind_per_step": {
             nm: work[t][0] / args.steps for nm, t in (("sampled_tier0", 0), ("sampled_tier1", 1), ("sampled_tier2", 2),
-                                                       ("replayed", 3), ("label_updated", 4))},
+                                                       ("replayed", 3), ("label_updated", 4),
+                                                       ("label_updated_by_replay_workgroups", 5))},
         "roofline": {
             "bound": "hbm",
             "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves "

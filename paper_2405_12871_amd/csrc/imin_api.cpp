@@ -26,7 +26,7 @@ thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
 constexpr int kTimedKernels = 8;
-constexpr int kWorkTiers = 5;  // tiers 0-2, replay, forest update
+constexpr int kWorkTiers = 6;  // tiers 0-2, replay, label rule (one world per wave), label rule (replay workgroups)
 struct Timing {
     std::atomic<bool> on{false};
     std::atomic<uint32_t> mask{0xFFFFFFFFu};  // kernels bracketed with events
@@ -332,22 +332,22 @@ struct Session {
     // replay of changed worlds from their stored live edges: BFS parents
     // beside the pairs, extra edges (local ids) in a store of their own
     bool replay = false;
-    bool forest = true;  // forest worlds updated from their labels (with replay)
+    bool label_rule = true;  // changed worlds updated from their labels where the rule holds (with replay)
     DevArray<int32_t> scr_par, xscr_v, xscr_u, xlen;
     DevArray<int64_t> xloc;
     size_t xslot_cap0 = 0, xbig_cap = 0;
     DevArray<int32_t> store_par, xstore_v, xstore_u, xstore_len;
     DevArray<int64_t> xstore_off;
     DevArray<imin::ReplayItem> items;   // changed worlds of an incremental round to re-evaluate
-    DevArray<imin::ReplayItem> titems;  // changed forest worlds
-    // dominator-tree labels and the forest flag per world (with replay)
+    DevArray<imin::ReplayItem> rule_items;  // changed worlds that take the label rule
+    // dominator-tree labels and the labelled flag per world (with replay)
     DevArray<int32_t> scr_lab, store_lab;
-    DevArray<uint8_t> world_tree;
+    DevArray<uint8_t> world_flags;
     // nodes lost per (kernel, workgroup) in incremental rounds
     DevArray<long long> dsz;
     int32_t dsz_n = 0;
     int32_t dsz_off[5] = {0, 0, 0, 0, 0};
-    int grid_t = 0;
+    int grid_l = 0;
     int grid_r = 0;
     bool incremental = false;
     size_t store_budget = 0;
@@ -488,11 +488,11 @@ struct Session {
         IMIN_TRY(sel_d.alloc(sel_parts));
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
-        // changed-world update: replay and forest workgroups of one launch
+        // changed-world update: replay and label-rule workgroups of one launch
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
-        grid_t = cus * (int)env_size("IMIN_FOREST_WG_PER_CU", 4);
+        grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 4);
         {
-            const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_t};
+            const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_l};
             int32_t at = 0;
             for (int i = 0; i < 5; ++i) {
                 dsz_off[i] = at;
@@ -504,7 +504,7 @@ struct Session {
         }
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
-            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_t), bs.n_slots);
+            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_l), bs.n_slots);
             const size_t wn = (size_t)3 * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
             IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));
@@ -570,8 +570,8 @@ struct Session {
             return IMIN_OK;  // plain rounds give the same integers
         }
         incremental = true;
-        const char* fp = std::getenv("IMIN_FOREST");
-        forest = !(fp && fp[0] == '0');
+        const char* fp = std::getenv("IMIN_LABEL_RULE");
+        label_rule = !(fp && fp[0] == '0');
         const char* rp = std::getenv("IMIN_REPLAY");
         if (!(rp && rp[0] == '0')) {
             xslot_cap0 = (size_t)imin::world_tier0_xcapacity();
@@ -581,8 +581,8 @@ struct Session {
                      xscr_v.alloc(xn) == hipSuccess && xscr_u.alloc(xn) == hipSuccess &&
                      xloc.alloc(tile_cap) == hipSuccess && xlen.alloc(tile_cap) == hipSuccess &&
                      xstore_off.alloc(theta) == hipSuccess && xstore_len.alloc(theta) == hipSuccess &&
-                     world_tree.alloc(theta) == hipSuccess &&
-                     hipMemsetAsync(world_tree.p, 0, theta, s) == hipSuccess;
+                     world_flags.alloc(theta) == hipSuccess &&
+                     hipMemsetAsync(world_flags.p, 0, theta, s) == hipSuccess;
             if (!replay) drop_replay();
         }
         return IMIN_OK;
@@ -594,7 +594,7 @@ struct Session {
         scr_par.release();
         scr_lab.release();
         store_lab.release();
-        world_tree.release();
+        world_flags.release();
         xscr_v.release();
         xscr_u.release();
         xloc.release();
@@ -655,7 +655,7 @@ struct Session {
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
         IMIN_TRY(items.alloc(theta));
-        IMIN_TRY(titems.alloc(theta));
+        IMIN_TRY(rule_items.alloc(theta));
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, s));
@@ -687,10 +687,10 @@ struct Session {
         out.list_cap = (uint32_t)std::min<size_t>(items.p ? std::min(list0.count, items.count) : list0.count,
                                                   0xFFFFFFFFu);
         out.items = items.p;
-        out.titems = titems.p;
+        out.rule_items = rule_items.p;
         out.scr_lab = (uint32_t*)scr_lab.p;
         out.store_lab = (uint32_t*)store_lab.p;
-        out.world_tree = forest ? world_tree.p : nullptr;
+        out.world_flags = label_rule ? world_flags.p : nullptr;
         out.dsz = dsz.p;
         for (int i = 0; i < 5; ++i) out.dsz_off[i] = dsz_off[i];
         out.next_cap = (uint32_t)std::min<size_t>(std::min(list1.count, list2.count), 0xFFFFFFFFu);
@@ -743,10 +743,11 @@ struct Session {
         timed.end(5, ev, s);
         imin_status_t st;
         if (replay) {
-            // forest worlds: subtree removal from the labels; every other
-            // changed world is replayed, those too large go on to sampling
+            // worlds where no live edge leaves the blocker's subtree: subtree
+            // removal from the labels; every other changed world is
+            // replayed, those too large go on to sampling
             ev = timed.begin(6, s);
-            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, grid_t, s));
+            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, grid_l, s));
             timed.end(6, ev, s);
             // worlds the replay cannot hold are sampled again; when round 0
             // stored none, no world ever falls back and the tiers are not launched

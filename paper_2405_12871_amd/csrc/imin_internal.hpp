@@ -63,7 +63,7 @@ struct RoundCtl {
     unsigned long long xbig_count;   // extra edges bump-allocated this tile
     unsigned long long xtile_total;  // extra edges the tile's worlds wrote
     unsigned long long xstore_count; // extra edges held for replay
-    uint32_t tree_n;                 // changed worlds of the round whose reached part is a forest
+    uint32_t rule_n;                 // changed worlds of the round that take the label rule
     uint32_t replay_big;             // some world stored in round 0 exceeds the replay's limits
 };
 
@@ -115,16 +115,22 @@ struct ReplayItem {
 
 // Per-world state of the resident store.
 enum : uint8_t {
-    kWorldForest = 1,    // the reached live edges form a forest under the seeds
     kWorldLabelled = 2,  // the stored labels describe the world's dominator tree
 };
 
-// Dominator-tree label of a stored entry: preorder index (high 16 bits) and
-// subtree size when labelled (low 16 bits); the subtree of an entry is the
-// entries whose preorder index lies in [index, index + size).
-__host__ __device__ constexpr uint32_t pack_label(int tin, int size) {
-    return ((uint32_t)tin << 16) | ((uint32_t)size & 0xFFFFu);
+// Dominator-tree label of a stored entry: preorder index (bits 16-31), the
+// length of its subtree's index range (bits 0-14; the subtree of an entry is
+// the entries whose preorder index lies in [index, index + length)), and an
+// exit bit (15): set when some live edge between reached nodes leads from
+// the subtree to a node outside it.  Labelled worlds hold at most 2048
+// non-seeds, so both fields fit.
+constexpr uint32_t kLabelExit = 0x8000u;
+__host__ __device__ constexpr uint32_t pack_label(int tin, int size, bool exits) {
+    return ((uint32_t)tin << 16) | (exits ? kLabelExit : 0u) | ((uint32_t)size & 0x7FFFu);
 }
+__host__ __device__ constexpr int label_tin(uint32_t lab) { return (int)(lab >> 16); }
+__host__ __device__ constexpr int label_size(uint32_t lab) { return (int)(lab & 0x7FFFu); }
+__host__ __device__ constexpr bool label_exits(uint32_t lab) { return (lab & kLabelExit) != 0; }
 
 struct TileOut {
     int mode;
@@ -149,7 +155,7 @@ struct TileOut {
     uint32_t list_cap;   // entries of the changed-world list
     uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
     ReplayItem* items;   // changed worlds to re-evaluate, with their store ranges (list_cap of them)
-    ReplayItem* titems;  // changed worlds whose reached part is a forest (list_cap of them)
+    ReplayItem* rule_items;  // changed worlds that take the label rule (list_cap of them)
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
@@ -173,16 +179,16 @@ struct TileOut {
     unsigned long long xstore_cap;
     int64_t* xstore_off;  // [theta]
     int32_t* xstore_len;  // [theta]
-    // Forest worlds: where the live edges among a world's reached nodes form
-    // a forest under the seeds, the dominator tree is that forest and adding
-    // a blocker only removes its subtree; the entries carry their labels.
-    uint32_t* scr_lab;    // aligned with scr_node
-    uint32_t* store_lab;  // aligned with store_node
-    uint8_t* world_tree;  // [theta] kWorld* flags
+    // Label rule: when no live edge leads out of the new blocker's dominator
+    // subtree, blocking it removes exactly that subtree and leaves the rest
+    // of the dominator tree as it was; the entries carry their labels.
+    uint32_t* scr_lab;     // aligned with scr_node
+    uint32_t* store_lab;   // aligned with store_node
+    uint8_t* world_flags;  // [theta] kWorld* flags
     // Incremental rounds: nodes each workgroup's worlds lost, one slot per
     // (kernel, workgroup); summed and cleared by the selection.
     long long* dsz;
-    int32_t dsz_off[5];   // slot ranges of tier 0, 1, 2, replay, forest update
+    int32_t dsz_off[5];   // slot ranges of tier 0, 1, 2, replay, label rule
 };
 
 // A compaction job: per-item ranges of up to four 32-bit fields are packed
@@ -248,11 +254,11 @@ hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long 
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
 // Changed worlds of an incremental round: replay_parts workgroups replay the
-// worlds of items (those too large go to next_list), forest_parts update the
-// forest worlds of titems.
+// worlds of items (those too large go to next_list), rule_parts apply the
+// label rule to the worlds of rule_items.
 hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                 int replay_parts, int forest_parts, hipStream_t s);
-constexpr int kTreeNT = 256;  // four worlds at a time per workgroup
+                                 int replay_parts, int rule_parts, hipStream_t s);
+constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
 hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);

@@ -151,7 +151,7 @@ __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
     ctl->tile_total = 0;
     ctl->xbig_count = 0;
     ctl->xtile_total = 0;
-    ctl->tree_n = 0;
+    ctl->rule_n = 0;
 }
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_round<<<1, 1, 0, s>>>(ctl);
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
                 ctl->next[i] = 0;
                 ctl->list_n[i] = 0;
             }
-            ctl->tree_n = 0;
+            ctl->rule_n = 0;
             ctl->pair_count = 0;
         }
     }

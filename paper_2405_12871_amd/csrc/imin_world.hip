@@ -161,6 +161,11 @@ struct LdsStore {
     __device__ int32_t* cur_ptr(int lid) { return &keys[lid - ns]; }
     __device__ void set_tin(int lid, int v) { vals[lid - ns] = (int16_t)v; }
     __device__ int get_tin(int lid) const { return (int)(uint16_t)vals[lid - ns]; }
+    // once the labels are placed the cursors are free: the exit ranges of
+    // the labels live there and in the rest of the table
+    static_assert(kHash >= 2 * CAPNS, "room for the exit ranges");
+    __device__ int32_t* lo_ptr(int lid) { return &keys[lid - ns]; }
+    __device__ int32_t* hi_ptr(int lid) { return &keys[CAPNS + lid - ns]; }
     template <int NT>
     __device__ void reset(int /*count*/) { clear<NT>(); }
 };
@@ -212,7 +217,7 @@ struct HbmStore {
     __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
     __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
     __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
-    static constexpr bool kLabels = false;  // worlds of this tier are never treated as forests
+    static constexpr bool kLabels = false;  // worlds of this tier carry no labels
     __device__ int32_t* cur_ptr(int) { return nullptr; }
     __device__ void set_tin(int, int) {}
     __device__ int get_tin(int) const { return 0; }
@@ -538,6 +543,70 @@ __device__ void world_labels(const QueryDev& q, Store& st, WorldShared<NT>& sh) 
     }
 }
 
+// Exit bits of the labels.  For each non-seed v, [lo(v), hi(v)] spans the
+// preorder indexes of the heads of the live edges that leave v's subtree's
+// nodes; some edge leads out of the subtree when that span is not inside
+// [tin(v), tin(v) + count(v)).  An edge whose head dominates its source is
+// left out: a simple path reaches its source through its head already, so
+// it never carries a path out of any subtree it leaves.  Each edge widens
+// its source's span; spans are then merged into each idom, deepest level
+// first (an idom lies on a shallower level).
+template <int NT, class Store>
+__device__ void exits_init(int ns, int R, Store& st) {
+    for (int i = ns + (int)threadIdx.x; i < R; i += NT) {
+        *st.lo_ptr(i) = 0x7FFFFFFF;
+        *st.hi_ptr(i) = -1;
+    }
+}
+
+// live edge a -> b between reached nodes (local ids)
+template <class Store>
+__device__ __forceinline__ void exits_edge(int ns, Store& st, int a, int b) {
+    if (a < ns || b < ns) return;  // seeds lie in no non-seed's subtree
+    const int ta = st.get_tin(a), tb = st.get_tin(b);
+    if (tb <= ta && ta < tb + *st.aux_ptr(b)) return;  // b dominates a
+    atomicMin(st.lo_ptr(a), tb);
+    atomicMax(st.hi_ptr(a), tb);
+}
+
+template <int NT, class Store>
+__device__ void exits_merge(int ns, Store& st, WorldShared<NT>& sh) {
+    for (int L = sh.nlevels - 1; L >= 1; --L) {
+        for (int i = st.lvl[L] + (int)threadIdx.x; i < st.lvl[L + 1]; i += NT) {
+            const int p = st.get_idom(i);
+            if (p >= ns) {
+                atomicMin(st.lo_ptr(p), *st.lo_ptr(i));
+                atomicMax(st.hi_ptr(p), *st.hi_ptr(i));
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// whether some live edge leads out of lid's subtree (after exits_merge)
+template <class Store>
+__device__ __forceinline__ bool exits_of(Store& st, int lid, int count) {
+    const int tv = st.get_tin(lid);
+    return *st.lo_ptr(lid) < tv || *st.hi_ptr(lid) >= tv + count;
+}
+
+// The exits of a sampled world: its edges are the BFS tree edges and the
+// extra edges.  A world without extra edges is a forest and has none (the
+// caller skips it).
+template <int NT, class Store>
+__device__ void world_exits(const QueryDev& q, Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    const int R = sh.count;
+    const int nx = sh.n_extra;
+    exits_init<NT>(ns, R, st);
+    __syncthreads();
+    for (int i = ns + t; i < R; i += NT) exits_edge(ns, st, st.get_parent(i), i);
+    for (int x = t; x < nx; x += NT) exits_edge(ns, st, st.get_xu(x), st.get_xv(x));
+    __syncthreads();
+    exits_merge<NT>(ns, st, sh);
+}
+
 // Phase 3 of a sampled world: the outputs of the mode.
 template <int NT, int TIER, class Store>
 __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi, const TileOut& out,
@@ -581,7 +650,7 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
             if (d != 0 && u != ctl->ustar) atomicAdd((unsigned long long*)&out.gain[u], (unsigned long long)(long long)d);
         }
         __syncthreads();
-        if (t == 0 && out.world_tree) out.world_tree[w] = 0;  // no labels from this evaluation
+        if (t == 0 && out.world_flags) out.world_flags[w] = 0;  // no labels from this evaluation
     } else {
         if (t == 0) {
             sh.pair_base = (TIER == 0) ? (unsigned long long)wi * out.slot_cap0
@@ -595,7 +664,12 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
                 out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
                 if (out.keep_edges) {
                     out.scr_par[off + i] = st.get_parent(ns + i);
-                    out.scr_lab[off + i] = Store::kLabels ? pack_label(st.get_tin(ns + i), *st.aux_ptr(ns + i)) : 0u;
+                    uint32_t lab = 0u;
+                    if constexpr (Store::kLabels) {
+                        const int c = *st.aux_ptr(ns + i);
+                        lab = pack_label(st.get_tin(ns + i), c, nx > 0 && exits_of(st, ns + i, c));
+                    }
+                    out.scr_lab[off + i] = lab;
                 }
             }
             if (t == 0) {
@@ -606,10 +680,8 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
             atomicOr(&ctl->flags, (uint32_t)kFlagPairOverflow);  // bump region full: the tile is redone
         }
         if (out.keep_edges) {
-            // a world with no extra live edge is a forest: its labels serve
-            // the incremental rounds directly
-            if (t == 0 && out.world_tree)
-                out.world_tree[w] = Store::kLabels ? (uint8_t)(kWorldLabelled | (nx == 0 ? kWorldForest : 0)) : 0;
+            // the labels serve the incremental rounds directly
+            if (t == 0 && out.world_flags) out.world_flags[w] = Store::kLabels ? (uint8_t)kWorldLabelled : 0;
             // worlds beyond the replay's limits need the sampling tiers later
             if (t == 0 && (len > kReplayCap || nx > kReplayXCap || len + nx > kReplayEdgeCap || ns + len > 32767))
                 atomicOr(&ctl->replay_big, 1u);
@@ -664,7 +736,10 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
     world_counts<NT>(q, ctl, st, sh);
     if constexpr (Store::kLabels) {
-        if (out.keep_edges && out.mode != kModeDelta) world_labels<NT>(q, st, sh);  // uniform
+        if (out.keep_edges && out.mode != kModeDelta) {  // uniform
+            world_labels<NT>(q, st, sh);
+            if (sh.n_extra > 0) world_exits<NT>(q, st, sh);
+        }
     }
     world_outputs<NT, TIER>(q, ctl, w, wi, out, st, sh);
     return true;
@@ -1028,8 +1103,9 @@ __global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t the
 // An incremental round starts here.  Every workgroup combines the parts of
 // the last selection (the same result everywhere); workgroup 0 commits it.
 // Then the worlds whose entry for the new blocker u is live are listed, with
-// their store ranges and that entry: forest worlds -> titems[0 .. tree_n),
-// the others -> items / list[0 .. list_n[0]).
+// their store ranges and that entry: labelled worlds where no live edge
+// leaves u's subtree (u's exit bit clear) take the label rule ->
+// rule_items[0 .. rule_n), the others -> items / list[0 .. list_n[0]).
 __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
                                                          const int32_t* idx_pos, const int32_t* idx_world,
                                                          int32_t* list, SelectOut so) {
@@ -1051,23 +1127,25 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     for (int i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
         const int k = i + lane;
         int32_t pos = 0, c = 0, w = 0;
+        uint32_t lab = 0;
         if (k < b) {
             pos = idx_pos[k];
             w = idx_world[k];
             c = out.store_cnt[pos];
+            if (out.store_lab) lab = out.store_lab[pos];
         }
         const bool live = c > 0;
-        const uint8_t wflags = (live && out.world_tree) ? out.world_tree[w] : (uint8_t)0;
-        const bool tree = (wflags & kWorldForest) != 0;
-        const unsigned long long mt = __ballot(tree);
-        const unsigned long long mr = __ballot(live && !tree);
+        const uint8_t wflags = (live && out.world_flags) ? out.world_flags[w] : (uint8_t)0;
+        const bool rule = (wflags & kWorldLabelled) != 0 && !label_exits(lab);
+        const unsigned long long mt = __ballot(rule);
+        const unsigned long long mr = __ballot(live && !rule);
         uint32_t bt = 0, br = 0;
-        if (lane == 0 && mt) bt = atomicAdd(&ctl->tree_n, (uint32_t)__popcll(mt));
+        if (lane == 0 && mt) bt = atomicAdd(&ctl->rule_n, (uint32_t)__popcll(mt));
         if (lane == 0 && mr) br = atomicAdd(&ctl->list_n[0], (uint32_t)__popcll(mr));
         bt = __shfl(bt, 0, 64);
         br = __shfl(br, 0, 64);
         if (live) {
-            const uint32_t at = tree ? bt + (uint32_t)__popcll(mt & below) : br + (uint32_t)__popcll(mr & below);
+            const uint32_t at = rule ? bt + (uint32_t)__popcll(mt & below) : br + (uint32_t)__popcll(mr & below);
             if (at < out.list_cap) {
                 ReplayItem it;
                 it.store_off = out.store_off[w];
@@ -1078,10 +1156,10 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
                 it.w = w;
                 it.j = (int32_t)((int64_t)pos - it.store_off);
                 it.cj = c;
-                it.labj = out.store_lab ? out.store_lab[pos] : 0u;
+                it.labj = lab;
                 it.flags = wflags;
-                if (tree) {
-                    out.titems[at] = it;
+                if (rule) {
+                    out.rule_items[at] = it;
                 } else {
                     out.items[at] = it;
                     list[at] = w;
@@ -1129,6 +1207,7 @@ struct ReplayStore {
     int16_t parent[CAP];  // by new local id - ns; preorder index once the counts are known
     int16_t idom[CAP];
     int32_t aux[CAP];
+    int32_t hi[CAP];      // upper ends of the exit spans (lower ends: cur, after the labels)
     int32_t xv[XCAP];     // extra edges of the new BFS: head (old entry until resolved), source new id
     int16_t xu[XCAP];
     int32_t lvl[LVCAP + 2];
@@ -1151,6 +1230,8 @@ struct ReplayStore {
     __device__ int32_t* cur_ptr(int lid) { return &cur[lid - ns]; }
     __device__ void set_tin(int lid, int v) { parent[lid - ns] = (int16_t)v; }
     __device__ int get_tin(int lid) const { return (int)(uint16_t)parent[lid - ns]; }
+    __device__ int32_t* lo_ptr(int lid) { return &cur[lid - ns]; }
+    __device__ int32_t* hi_ptr(int lid) { return &hi[lid - ns]; }
 };
 
 // levels: at most one per entry plus the seeds' and a closing empty one
@@ -1159,7 +1240,7 @@ constexpr int kReplayNT = 256;                          // four waves per replay
 constexpr int kReplaySlots = kReplayEdgeCap / kReplayNT;  // stored edges per thread
 constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 
-// The forest rule on a world's entries held in registers: entries in u's
+// The label rule on a world's entries held in registers: entries in u's
 // label range lose their whole count, u's ancestors lose count(u), and T
 // loses count(u).
 template <int NT>
@@ -1169,15 +1250,15 @@ __device__ void replay_local_update(const ReplayItem& it, int32_t ustar, const T
     const int t = threadIdx.x;
     const size_t so = (size_t)it.store_off;
     const int L0 = it.store_len;
-    const int tj = (int)(it.labj >> 16);
-    const int szj = (int)(it.labj & 0xFFFFu);
+    const int tj = label_tin(it.labj);
+    const int szj = label_size(it.labj);
     const int cj = it.cj;
 #pragma unroll
     for (int r = 0; r < kReplayEntrySlots; ++r) {
         const int i = t + r * NT;
         if (i >= L0 || ec[r] <= 0) continue;
-        const int ti = (int)(el[r] >> 16);
-        const int si = (int)(el[r] & 0xFFFFu);
+        const int ti = label_tin(el[r]);
+        const int si = label_size(el[r]);
         int d = 0, cn = 0;
         if (ti >= tj && ti < tj + szj) {
             d = -ec[r];
@@ -1208,14 +1289,19 @@ __device__ void replay_local_update(const ReplayItem& it, int32_t ustar, const T
 //
 // Before the BFS, a world with valid labels is checked for a shortcut: if no
 // stored live edge leads from a reached node of u's dominator subtree to a
-// reached node outside it, no path to a node outside the subtree passes
-// through the subtree, so blocking u removes exactly the subtree and leaves
-// every other dominator (and label) as it was: the forest rule applies.
-// Returns 1 when the world was replayed, 2 when the shortcut applied, 0 when
-// the world exceeds the replay's limits.
+// reached node outside it (edges into a dominator of their source aside),
+// no simple path to a node outside the subtree passes through the subtree,
+// so blocking u removes exactly the subtree and leaves every other dominator
+// (and label) as it was: the label rule applies.  (The exit bit of u's label
+// answers the same question for the edges as they were when the labels were
+// made; the test here also sees the edges lost since.)  The stored edges are
+// left in ed (source << 16 | head entry, old ids), act marking the valid
+// ones.  Returns 1 when the world was replayed, 2 when the shortcut
+// applied, 0 when the world exceeds the replay's limits.
 template <int NT, class RS>
 __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
-                          WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots], int32_t (&en)[kReplayEntrySlots]) {
+                          WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots], int32_t (&en)[kReplayEntrySlots],
+                          uint32_t (&ed)[kReplaySlots], uint32_t& act0) {
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     const size_t so = (size_t)it.store_off;
@@ -1245,7 +1331,6 @@ __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it
             if (labelled) el[r] = out.store_lab[so + i];
         }
     }
-    uint32_t ed[kReplaySlots];
     uint32_t act = 0;
 #pragma unroll
     for (int r = 0; r < kReplaySlots; ++r) {
@@ -1262,14 +1347,16 @@ __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it
         ed[r] = ok ? (((uint32_t)u << 16) | (uint32_t)vi) : 0u;  // inactive slots read entry 0, harmlessly
         act |= ok ? (1u << r) : 0u;
     }
+    act0 = act;
     if (labelled) {
-        // reached entries' preorder indexes (-1: not reached) for the edge test
-        const int tj = (int)(it.labj >> 16);
-        const int szj = (int)(it.labj & 0xFFFFu);
+        // reached entries' labels (-1: not reached) for the edge test; a
+        // label is below 2^27
+        const int tj = label_tin(it.labj);
+        const int szj = label_size(it.labj);
 #pragma unroll
         for (int r = 0; r < kReplayEntrySlots; ++r) {
             const int i = t + r * NT;
-            if (i < L0) st.cur[i] = (ec[r] > 0) ? (int)(el[r] >> 16) : -1;
+            if (i < L0) st.cur[i] = (ec[r] > 0) ? (int)el[r] : -1;
         }
         __syncthreads();
         bool escape = false;
@@ -1277,9 +1364,16 @@ __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it
         for (int r = 0; r < kReplaySlots; ++r) {
             const int u = (int)(ed[r] >> 16);
             if (((act >> r) & 1u) && u >= ns) {
-                const int ts = st.cur[u - ns];
-                const int th = st.cur[ed[r] & 0xFFFFu];
-                escape |= ts >= tj && ts < tj + szj && th >= 0 && (th < tj || th >= tj + szj);
+                const int ls = st.cur[u - ns];
+                const int lh = st.cur[ed[r] & 0xFFFFu];
+                if (ls >= 0 && lh >= 0) {
+                    const int ts = label_tin((uint32_t)ls);
+                    const int th = label_tin((uint32_t)lh);
+                    const bool src_in = ts >= tj && ts < tj + szj;
+                    const bool head_out = th < tj || th >= tj + szj;
+                    const bool head_dominates = th <= ts && ts < th + label_size((uint32_t)lh);
+                    escape |= src_in && head_out && !head_dominates;
+                }
             }
         }
         if (!__syncthreads_or(escape)) {
@@ -1369,6 +1463,25 @@ __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it
     return 1;
 }
 
+// The exits of a replayed world: its edges are the stored edges whose
+// endpoints are both reached again.
+template <int NT, class RS>
+__device__ void replay_exits(RS& st, WorldShared<NT>& sh, const uint32_t (&ed)[kReplaySlots], uint32_t act) {
+    const int ns = st.ns;
+    exits_init<NT>(ns, sh.count, st);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kReplaySlots; ++r) {
+        if (!((act >> r) & 1u)) continue;
+        const int u = (int)(ed[r] >> 16);
+        const int a = (u < ns) ? -1 : st.nl[u - ns];
+        const int b = st.nl[ed[r] & 0xFFFFu];
+        exits_edge(ns, st, a, b);  // skips unreached (negative) ends
+    }
+    __syncthreads();
+    exits_merge<NT>(ns, st, sh);
+}
+
 // Count changes of a replayed world: each entry's new count against the one
 // held in registers; changes are added to gain and the counts updated in
 // place.
@@ -1392,7 +1505,8 @@ __device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut
             d = cn - ec[r];
             // the dominator tree may have changed shape: every reached
             // entry takes its new label
-            if (cn > 0) out.store_lab[so + i] = pack_label(st.get_tin(lid), cn);
+            if (cn > 0)
+                out.store_lab[so + i] = pack_label(st.get_tin(lid), cn, sh.n_extra > 0 && exits_of(st, lid, cn));
         }
         const unsigned long long mask = __ballot(d != 0);
         if (d != 0) {
@@ -1405,7 +1519,7 @@ __device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut
     __syncthreads();
     if (t == 0) {
         out.world_size[it.w] = sh.count;
-        if (out.world_tree) out.world_tree[it.w] = kWorldLabelled | ((sh.n_extra == 0) ? kWorldForest : 0);
+        if (out.world_flags) out.world_flags[it.w] = kWorldLabelled;
     }
     return sh.ndelta;
 }
@@ -1424,7 +1538,8 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
     for (uint32_t k = part; k < n_items; k += parts) {
         const ReplayItem cur = out.items[k];
         int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
-        const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en);
+        uint32_t ed[kReplaySlots], act;
+        const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
         if (how == 2) {
             // the shortcut: reported with the label-based updates
             acc_lw += 1;
@@ -1435,6 +1550,7 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
         } else if (how == 1) {
             world_counts<kReplayNT>(q, ctl, st, sh);
             world_labels<kReplayNT>(q, st, sh);
+            if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
             const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
             acc_w += 1;
             acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
@@ -1450,60 +1566,63 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
     }
     if (t == 0) {
         add_work_at(out, 3, part, acc_w, acc_e, acc_b);
-        add_work_at(out, 4, out.work_stride - 1 - part, acc_lw, acc_le, acc_lb);
+        add_work_at(out, 5, part, acc_lw, acc_le, acc_lb);
         // T is lowered by the nodes the replayed worlds lost
         if (acc_d) out.dsz[out.dsz_off[3] + part] = acc_d;
     }
 }
 
-// ------------------------------------------------------- forest worlds
-// In a world whose reached live edges form a forest under the seeds, the
-// dominator tree is that forest.  Blocking u removes exactly u's subtree
-// (its entries' counts become 0) and lowers the count of each of u's
-// ancestors by count(u); no other count changes.  Subtree and ancestors
-// are read off the labels: entry i lies in u's subtree when
-// tin(u) <= tin(i) < tin(u) + size(u), and is an ancestor of u when
-// tin(i) <= tin(u) < tin(i) + size(i).  One wave per world, one pass over
-// its entries; removing a subtree keeps the rest a forest with valid labels.
+// ------------------------------------------------------- label rule
+// When no live edge leads out of u's dominator subtree (u's exit bit is
+// clear; always so where the reached live edges form a forest), no simple
+// path to a node outside the subtree passes through it: blocking u removes
+// exactly u's subtree (its entries' counts become 0) and lowers the count
+// of each of u's ancestors by count(u); no other count and no other
+// dominator changes.  Subtree and ancestors are read off the labels: entry
+// i lies in u's subtree when tin(u) <= tin(i) < tin(u) + size(u), and is an
+// ancestor of u when tin(i) <= tin(u) < tin(i) + size(i).  One wave per
+// world, one pass over its entries.  The rest of the tree keeps valid
+// labels; exit bits can only have become stale in the safe direction (an
+// edge lost with the subtree may have been some ancestor's only exit).
 // The count changes of a workgroup's worlds are summed in LDS and added to
 // gain once per node per workgroup.
-constexpr int kTreeUnroll = 4;
-using TreeSums = LdsSums<11>;
+constexpr int kRuleUnroll = 4;
+using RuleSums = LdsSums<11>;
 
-__device__ __forceinline__ bool ti_is_u(uint32_t lab, int tj) { return (int)(lab >> 16) == tj; }
+__device__ __forceinline__ bool ti_is_u(uint32_t lab, int tj) { return label_tin(lab) == tj; }
 
-struct ForestShared {
-    TreeSums sums;
-    unsigned long long red[kTreeNT / 64][4];
+struct RuleShared {
+    RuleSums sums;
+    unsigned long long red[kRuleNT / 64][4];
 };
 
-__device__ void forest_worlds(RoundCtl* ctl, const TileOut& out, ForestShared& fs, uint32_t part, uint32_t parts) {
-    TreeSums& sums = fs.sums;
-    const uint32_t n = min(ctl->tree_n, out.list_cap);
-    if ((unsigned long long)part * (kTreeNT / 64) >= n) return;  // no world for this workgroup
-    sums.clear<kTreeNT>();
+__device__ void rule_worlds(RoundCtl* ctl, const TileOut& out, RuleShared& fs, uint32_t part, uint32_t parts) {
+    RuleSums& sums = fs.sums;
+    const uint32_t n = min(ctl->rule_n, out.list_cap);
+    if ((unsigned long long)part * (kRuleNT / 64) >= n) return;  // no world for this workgroup
+    sums.clear<kRuleNT>();
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
-    for (uint32_t k = part * (kTreeNT / 64) + wid; k < n; k += parts * (kTreeNT / 64)) {
-        const ReplayItem it = out.titems[k];
+    for (uint32_t k = part * (kRuleNT / 64) + wid; k < n; k += parts * (kRuleNT / 64)) {
+        const ReplayItem it = out.rule_items[k];
         const size_t so = (size_t)it.store_off;
         const int L0 = it.store_len;
         if (it.store_off < 0 || L0 < 0 || so + (size_t)L0 > out.store_cap) {
             if (lane == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
             continue;  // uniform over the wave
         }
-        const int tj = (int)(it.labj >> 16);
-        const int szj = (int)(it.labj & 0xFFFFu);
+        const int tj = label_tin(it.labj);
+        const int szj = label_size(it.labj);
         const int cj = it.cj;
         int nd = 0;
-        for (int b0 = 0; b0 < L0; b0 += 64 * kTreeUnroll) {
-            int c[kTreeUnroll], v[kTreeUnroll];
-            uint32_t lab[kTreeUnroll];
+        for (int b0 = 0; b0 < L0; b0 += 64 * kRuleUnroll) {
+            int c[kRuleUnroll], v[kRuleUnroll];
+            uint32_t lab[kRuleUnroll];
 #pragma unroll
-            for (int r = 0; r < kTreeUnroll; ++r) {
+            for (int r = 0; r < kRuleUnroll; ++r) {
                 const int i = b0 + r * 64 + lane;
                 c[r] = 0;
                 v[r] = 0;
@@ -1515,12 +1634,12 @@ __device__ void forest_worlds(RoundCtl* ctl, const TileOut& out, ForestShared& f
                 }
             }
 #pragma unroll
-            for (int r = 0; r < kTreeUnroll; ++r) {
+            for (int r = 0; r < kRuleUnroll; ++r) {
                 const int i = b0 + r * 64 + lane;
                 int d = 0, cn = 0;
                 if (c[r] > 0) {
-                    const int ti = (int)(lab[r] >> 16);
-                    const int si = (int)(lab[r] & 0xFFFFu);
+                    const int ti = label_tin(lab[r]);
+                    const int si = label_size(lab[r]);
                     if (ti >= tj && ti < tj + szj) {
                         d = -c[r];  // u's subtree, u included: no longer reached
                     } else if (tj >= ti && tj < ti + si) {
@@ -1550,10 +1669,10 @@ __device__ void forest_worlds(RoundCtl* ctl, const TileOut& out, ForestShared& f
         fs.red[wid][3] = (unsigned long long)acc_d;
     }
     __syncthreads();
-    sums.flush<kTreeNT>(out.gain);
+    sums.flush<kRuleNT>(out.gain);
     if (threadIdx.x == 0) {
         unsigned long long f[4] = {0, 0, 0, 0};
-        for (int x = 0; x < kTreeNT / 64; ++x)
+        for (int x = 0; x < kRuleNT / 64; ++x)
             for (int y = 0; y < 4; ++y) f[y] += fs.red[x][y];
         add_work_at(out, 4, part, f[0], f[1], f[2]);
         if (f[3]) out.dsz[out.dsz_off[4] + part] = (long long)f[3];
@@ -1562,16 +1681,16 @@ __device__ void forest_worlds(RoundCtl* ctl, const TileOut& out, ForestShared& f
 
 // ------------------------------------------------- changed-world update
 // One launch for the changed worlds of an incremental round: the first
-// replay_parts workgroups replay the other worlds while the rest update the
-// forest worlds, so the two run side by side.  LDS is shared between the
+// replay_parts workgroups replay the worlds of items while the rest apply
+// the label rule to the worlds of rule_items, so the two run side by side.  LDS is shared between the
 // two roles.
-static_assert(kReplayNT == kTreeNT, "both roles use the same workgroup size");
+static_assert(kReplayNT == kRuleNT, "both roles use the same workgroup size");
 union ChangedShared {
     struct {
         ReplayStoreT st;
         WorldShared<kReplayNT> sh;
     } r;
-    ForestShared f;
+    RuleShared f;
 };
 
 __global__ __launch_bounds__(kReplayNT) void k_changed_worlds(QueryDev q, RoundCtl* ctl, int32_t* next_list,
@@ -1579,7 +1698,7 @@ __global__ __launch_bounds__(kReplayNT) void k_changed_worlds(QueryDev q, RoundC
     __shared__ ChangedShared u;
     if (ctl->stop) return;
     if (blockIdx.x < replay_parts) replay_worlds(q, ctl, next_list, out, u.r.st, u.r.sh, blockIdx.x, replay_parts);
-    else forest_worlds(ctl, out, u.f, blockIdx.x - replay_parts, gridDim.x - replay_parts);
+    else rule_worlds(ctl, out, u.f, blockIdx.x - replay_parts, gridDim.x - replay_parts);
 }
 
 hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,

@@ -181,11 +181,12 @@ def test_solve_random_graphs(B, oracle_mod, case):
 
 
 @pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7", "noreplay",
-                                     "noforest", "xscratch", "tiles"])
+                                     "nolabelrule", "xscratch", "tiles"])
 def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
-    """Incremental rounds (default: forest worlds updated from their labels,
-    other changed worlds replayed from their stored live edges), replay
-    without the forest update, plain rounds, a resident store too small to
+    """Incremental rounds (default: worlds where no live edge leaves the new
+    blocker's dominator subtree updated from their labels, other changed
+    worlds replayed from their stored live edges), replay without the label
+    rule, plain rounds, a resident store too small to
     hold round 0 (falls back to plain rounds), re-evaluation by sampling on
     every tier, regrowth of the extra-edge scratch, several tiles and other
     round batch sizes all give the oracle's selection."""
@@ -195,8 +196,8 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
         monkeypatch.setenv("IMIN_STORE_CAP", "5000")
     elif variant == "noreplay":
         monkeypatch.setenv("IMIN_REPLAY", "0")
-    elif variant == "noforest":
-        monkeypatch.setenv("IMIN_FOREST", "0")
+    elif variant == "nolabelrule":
+        monkeypatch.setenv("IMIN_LABEL_RULE", "0")
     elif variant == "xscratch":
         monkeypatch.setenv("IMIN_XBIG_SCRATCH", "16")
         monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
