@@ -168,9 +168,10 @@ imin_status_t imin_cache_release(void);
  *   4  world evaluation, large LDS tier (four waves per world)
  *   5  search for the worlds a new blocker changes (incremental rounds)
  *   6  update of the changed worlds of an incremental round, one launch:
- *      label-based count update of the worlds whose reached live edges
- *      form a forest, and replay of the others from their stored live
- *      edges (worlds too large for the replay go on to kernels 4 and 1)
+ *      count update from the dominator-tree labels of the worlds where no
+ *      live edge leaves the blocker's dominator subtree, and replay of the
+ *      others from their stored live edges (worlds too large for the
+ *      replay go on to kernels 4 and 1)
  *   7  (unused)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.

@@ -339,7 +339,6 @@ struct Session {
     DevArray<int32_t> store_par, xstore_v, xstore_u, xstore_len;
     DevArray<int64_t> xstore_off;
     DevArray<imin::ReplayItem> items;   // changed worlds of an incremental round to re-evaluate
-    DevArray<imin::ReplayItem> rule_items;  // changed worlds that take the label rule
     // dominator-tree labels and the labelled flag per world (with replay)
     DevArray<int32_t> scr_lab, store_lab;
     DevArray<uint8_t> world_flags;
@@ -348,6 +347,7 @@ struct Session {
     int32_t dsz_n = 0;
     int32_t dsz_off[5] = {0, 0, 0, 0, 0};
     int grid_l = 0;
+    int rule_lanes = 16;  // lanes per world in the label rule
     int grid_r = 0;
     bool incremental = false;
     size_t store_budget = 0;
@@ -482,7 +482,9 @@ struct Session {
         bs.xv = b_xv.p;
         bs.xu = b_xu.p;
 
-        sel_parts = (int)std::min<size_t>(1024, (n + 255) / 256);
+        // parts of the selection: few enough that combining them is cheap
+        // for every workgroup of the search that reads them
+        sel_parts = (int)std::min<size_t>(env_size("IMIN_SELECT_PARTS", 512), (n + 255) / 256);
         IMIN_TRY(sel_g.alloc(sel_parts));
         IMIN_TRY(sel_u.alloc(sel_parts));
         IMIN_TRY(sel_d.alloc(sel_parts));
@@ -491,6 +493,7 @@ struct Session {
         // changed-world update: replay and label-rule workgroups of one launch
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
         grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 4);
+        rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
         {
             const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_l};
             int32_t at = 0;
@@ -655,7 +658,6 @@ struct Session {
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
         IMIN_TRY(items.alloc(theta));
-        IMIN_TRY(rule_items.alloc(theta));
         IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, s));
@@ -687,7 +689,6 @@ struct Session {
         out.list_cap = (uint32_t)std::min<size_t>(items.p ? std::min(list0.count, items.count) : list0.count,
                                                   0xFFFFFFFFu);
         out.items = items.p;
-        out.rule_items = rule_items.p;
         out.scr_lab = (uint32_t*)scr_lab.p;
         out.store_lab = (uint32_t*)store_lab.p;
         out.world_flags = label_rule ? world_flags.p : nullptr;
@@ -738,6 +739,7 @@ struct Session {
         out.mode = imin::kModeDelta;
         out.world_size = world_size.p;
         // the per-round counters were cleared by the last selection
+        // the search for the changed worlds the label rule cannot take
         hipEvent_t ev = timed.begin(5, s);
         IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, so, s));
         timed.end(5, ev, s);
@@ -747,7 +749,8 @@ struct Session {
             // removal from the labels; every other changed world is
             // replayed, those too large go on to sampling
             ev = timed.begin(6, s);
-            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, grid_l, s));
+            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, out.world_flags ? grid_l : 0,
+                                                 rule_lanes, idx_off.p, idx_pos.p, idx_world.p, s));
             timed.end(6, ev, s);
             // worlds the replay cannot hold are sampled again; when round 0
             // stored none, no world ever falls back and the tiers are not launched
@@ -1024,7 +1027,11 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
         st = ss.enable_store((uint64_t)theta);
         if (st != IMIN_OK) return st;
     }
-    const size_t batch = env_size("IMIN_ROUND_BATCH", 32);
+    // rounds enqueued between two reads of the round counters: doubling from
+    // IMIN_ROUND_BATCH up to 4x that, so that a long solve waits on the host
+    // a few times only and one that stops early wastes few empty launches
+    const size_t batch0 = env_size("IMIN_ROUND_BATCH", 32);
+    size_t batch = batch0;
     const imin::SelectOut so = ss.select_out(k, blockers, gains, spread_totals, n_selected);
     bool indexed = false;
     for (int32_t r = 0; r <= k;) {
@@ -1042,6 +1049,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
                 if (st != IMIN_OK) return st;
             }
             r += nb;
+            batch = std::min(batch * 2, batch0 * 4);
         } else {
             IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
             IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));

@@ -63,7 +63,7 @@ struct RoundCtl {
     unsigned long long xbig_count;   // extra edges bump-allocated this tile
     unsigned long long xtile_total;  // extra edges the tile's worlds wrote
     unsigned long long xstore_count; // extra edges held for replay
-    uint32_t rule_n;                 // changed worlds of the round that take the label rule
+    uint32_t pad2;
     uint32_t replay_big;             // some world stored in round 0 exceeds the replay's limits
 };
 
@@ -155,7 +155,6 @@ struct TileOut {
     uint32_t list_cap;   // entries of the changed-world list
     uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
     ReplayItem* items;   // changed worlds to re-evaluate, with their store ranges (list_cap of them)
-    ReplayItem* rule_items;  // changed worlds that take the label rule (list_cap of them)
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
@@ -254,10 +253,12 @@ hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long 
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
 // Changed worlds of an incremental round: replay_parts workgroups replay the
-// worlds of items (those too large go to next_list), rule_parts apply the
-// label rule to the worlds of rule_items.
+// worlds of items (those too large go to next_list); rule_parts workgroups
+// apply the label rule to the worlds it holds for, found through the index
+// (a world per `lanes` lanes: 16, 32 or 64).
 hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                 int replay_parts, int rule_parts, hipStream_t s);
+                                 int replay_parts, int rule_parts, int lanes, const int32_t* idx_off,
+                                 const int32_t* idx_pos, const int32_t* idx_world, hipStream_t s);
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
 hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,

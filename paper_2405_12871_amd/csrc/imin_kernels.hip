@@ -151,7 +151,6 @@ __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
     ctl->tile_total = 0;
     ctl->xbig_count = 0;
     ctl->xtile_total = 0;
-    ctl->rule_n = 0;
 }
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_round<<<1, 1, 0, s>>>(ctl);
@@ -406,7 +405,27 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
     if (ctl->stop) return;
     int64_t bg = 0;
     int32_t bu = -1;
-    for (int32_t u = blockIdx.x * 256 + threadIdx.x; u < n; u += gridDim.x * 256) {
+    // four candidates per thread in flight at a time
+    const int32_t stride = (int32_t)gridDim.x * 256;
+    int32_t u = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
+    for (; (int64_t)u + 3 * (int64_t)stride < n; u += 4 * stride) {
+        int64_t gv[4];
+        uint32_t ex[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            gv[j] = gain[u + j * stride];
+            ex[j] = excl[(uint32_t)(u + j * stride) >> 5];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t v = u + j * stride;
+            if (!((ex[j] >> ((uint32_t)v & 31u)) & 1u) && better(gv[j], v, bg, bu)) {
+                bg = gv[j];
+                bu = v;
+            }
+        }
+    }
+    for (; u < n; u += stride) {
         if (bit_set(excl, u)) continue;
         const int64_t gv = gain[u];
         if (better(gv, u, bg, bu)) { bg = gv; bu = u; }
@@ -434,7 +453,6 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
                 ctl->next[i] = 0;
                 ctl->list_n[i] = 0;
             }
-            ctl->rule_n = 0;
             ctl->pair_count = 0;
         }
     }

@@ -1103,9 +1103,16 @@ __global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t the
 // An incremental round starts here.  Every workgroup combines the parts of
 // the last selection (the same result everywhere); workgroup 0 commits it.
 // Then the worlds whose entry for the new blocker u is live are listed, with
-// their store ranges and that entry: labelled worlds where no live edge
-// leaves u's subtree (u's exit bit clear) take the label rule ->
-// rule_items[0 .. rule_n), the others -> items / list[0 .. list_n[0]).
+// their store ranges and that entry -> items / list[0 .. list_n[0]), except
+// those the label rule takes (labelled worlds where u's exit bit is clear:
+// no live edge leaves u's dominator subtree), which the changed-world
+// launch finds in the index itself.
+// Whether the label rule updates a world for the new blocker: the world is
+// labelled and the blocker's exit bit is clear.
+__device__ __forceinline__ bool label_rule_holds(uint8_t wflags, uint32_t lab) {
+    return (wflags & kWorldLabelled) != 0 && !label_exits(lab);
+}
+
 __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
                                                          const int32_t* idx_pos, const int32_t* idx_world,
                                                          int32_t* list, SelectOut so) {
@@ -1128,24 +1135,21 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
         const int k = i + lane;
         int32_t pos = 0, c = 0, w = 0;
         uint32_t lab = 0;
+        uint8_t wflags = 0;
         if (k < b) {
             pos = idx_pos[k];
             w = idx_world[k];
             c = out.store_cnt[pos];
             if (out.store_lab) lab = out.store_lab[pos];
+            if (out.world_flags) wflags = out.world_flags[w];
         }
-        const bool live = c > 0;
-        const uint8_t wflags = (live && out.world_flags) ? out.world_flags[w] : (uint8_t)0;
-        const bool rule = (wflags & kWorldLabelled) != 0 && !label_exits(lab);
-        const unsigned long long mt = __ballot(rule);
-        const unsigned long long mr = __ballot(live && !rule);
-        uint32_t bt = 0, br = 0;
-        if (lane == 0 && mt) bt = atomicAdd(&ctl->rule_n, (uint32_t)__popcll(mt));
+        const bool live = c > 0 && !label_rule_holds(wflags, lab);
+        const unsigned long long mr = __ballot(live);
+        uint32_t br = 0;
         if (lane == 0 && mr) br = atomicAdd(&ctl->list_n[0], (uint32_t)__popcll(mr));
-        bt = __shfl(bt, 0, 64);
         br = __shfl(br, 0, 64);
         if (live) {
-            const uint32_t at = rule ? bt + (uint32_t)__popcll(mt & below) : br + (uint32_t)__popcll(mr & below);
+            const uint32_t at = br + (uint32_t)__popcll(mr & below);
             if (at < out.list_cap) {
                 ReplayItem it;
                 it.store_off = out.store_off[w];
@@ -1158,12 +1162,8 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
                 it.cj = c;
                 it.labj = lab;
                 it.flags = wflags;
-                if (rule) {
-                    out.rule_items[at] = it;
-                } else {
-                    out.items[at] = it;
-                    list[at] = w;
-                }
+                out.items[at] = it;
+                list[at] = w;
             } else {
                 atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
             }
@@ -1244,7 +1244,7 @@ constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
 // label range lose their whole count, u's ancestors lose count(u), and T
 // loses count(u).
 template <int NT>
-__device__ void replay_local_update(const ReplayItem& it, int32_t ustar, const TileOut& out,
+__device__ __forceinline__ void replay_local_update(const ReplayItem& it, int32_t ustar, const TileOut& out,
                                     const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots],
                                     const uint32_t (&el)[kReplayEntrySlots]) {
     const int t = threadIdx.x;
@@ -1299,7 +1299,7 @@ __device__ void replay_local_update(const ReplayItem& it, int32_t ustar, const T
 // ones.  Returns 1 when the world was replayed, 2 when the shortcut
 // applied, 0 when the world exceeds the replay's limits.
 template <int NT, class RS>
-__device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
+__device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
                           WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots], int32_t (&en)[kReplayEntrySlots],
                           uint32_t (&ed)[kReplaySlots], uint32_t& act0) {
     const int t = threadIdx.x;
@@ -1466,7 +1466,7 @@ __device__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it
 // The exits of a replayed world: its edges are the stored edges whose
 // endpoints are both reached again.
 template <int NT, class RS>
-__device__ void replay_exits(RS& st, WorldShared<NT>& sh, const uint32_t (&ed)[kReplaySlots], uint32_t act) {
+__device__ __forceinline__ void replay_exits(RS& st, WorldShared<NT>& sh, const uint32_t (&ed)[kReplaySlots], uint32_t act) {
     const int ns = st.ns;
     exits_init<NT>(ns, sh.count, st);
     __syncthreads();
@@ -1486,7 +1486,7 @@ __device__ void replay_exits(RS& st, WorldShared<NT>& sh, const uint32_t (&ed)[k
 // held in registers; changes are added to gain and the counts updated in
 // place.
 template <int NT, class RS>
-__device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut& out, RS& st, WorldShared<NT>& sh,
+__device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut& out, RS& st, WorldShared<NT>& sh,
                               const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots]) {
     const int t = threadIdx.x;
     const int ns = st.ns;
@@ -1527,7 +1527,7 @@ __device__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut
 // Changed worlds that are not forests are replayed; a world that does not
 // fit the replay store goes on to the sampling tiers (list 1).  Workgroup
 // `part` of `parts` takes items part, part + parts, ...
-__device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+__device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                               ReplayStoreT& st, WorldShared<kReplayNT>& sh, uint32_t part, uint32_t parts) {
     const int t = threadIdx.x;
     const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
@@ -1580,109 +1580,176 @@ __device__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_li
 // of each of u's ancestors by count(u); no other count and no other
 // dominator changes.  Subtree and ancestors are read off the labels: entry
 // i lies in u's subtree when tin(u) <= tin(i) < tin(u) + size(u), and is an
-// ancestor of u when tin(i) <= tin(u) < tin(i) + size(i).  One wave per
-// world, one pass over its entries.  The rest of the tree keeps valid
-// labels; exit bits can only have become stale in the safe direction (an
-// edge lost with the subtree may have been some ancestor's only exit).
-// The count changes of a workgroup's worlds are summed in LDS and added to
+// ancestor of u when tin(i) <= tin(u) < tin(i) + size(i).  The rest of the
+// tree keeps valid labels; exit bits can only have become stale in the safe
+// direction (an edge lost with the subtree may have been some ancestor's
+// only exit).
+//
+// The label-rule workgroups of the changed-world launch walk the index
+// entries of u themselves (the search listed only the other worlds): each
+// group of LANES lanes takes entries a + group, a + group + groups, ...;
+// a live entry of a labelled world with a clear exit bit is updated by the
+// group in one pass over the world's entries.  The loads of the next entry
+// (index, then its count, label and world) are issued before the current
+// world's pass; smaller groups keep more worlds in flight per wave.  The
+// count changes of a workgroup's worlds are summed in LDS and added to
 // gain once per node per workgroup.
-constexpr int kRuleUnroll = 4;
+constexpr int kRuleUnroll = 8;
 using RuleSums = LdsSums<11>;
-
-__device__ __forceinline__ bool ti_is_u(uint32_t lab, int tj) { return label_tin(lab) == tj; }
 
 struct RuleShared {
     RuleSums sums;
-    unsigned long long red[kRuleNT / 64][4];
+    unsigned long long red[4];
 };
 
-__device__ void rule_worlds(RoundCtl* ctl, const TileOut& out, RuleShared& fs, uint32_t part, uint32_t parts) {
+// What is read of one index entry before deciding.
+struct RuleMeta {
+    int32_t pos, w, c;
+    uint32_t lab;
+    uint8_t flags;
+    int64_t off;
+    int32_t len, wsize;
+};
+
+__device__ __forceinline__ void rule_meta(const TileOut& out, RuleMeta& m) {
+    m.c = out.store_cnt[m.pos];
+    m.lab = out.store_lab[m.pos];
+    m.flags = out.world_flags[m.w];
+    m.off = out.store_off[m.w];
+    m.len = out.store_len[m.w];
+    m.wsize = out.world_size[m.w];
+}
+
+template <int LANES>
+__device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const int32_t* idx_off, const int32_t* idx_pos,
+                            const int32_t* idx_world, RuleShared& fs, uint32_t part, uint32_t parts) {
+    static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
+    constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
+    const int32_t ustar = ctl->ustar;
+    const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
+    if ((long long)a + (long long)part * kGroups >= (long long)b) return;  // no entry for this workgroup
     RuleSums& sums = fs.sums;
-    const uint32_t n = min(ctl->rule_n, out.list_cap);
-    if ((unsigned long long)part * (kRuleNT / 64) >= n) return;  // no world for this workgroup
     sums.clear<kRuleNT>();
+    if (threadIdx.x < 4) fs.red[threadIdx.x] = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
+    const int gl = lane % LANES;  // lane within the world's group
+    const unsigned long long gmask = (LANES == 64) ? ~0ull : (((1ull << LANES) - 1ull) << (lane - gl));
+    const int stride = (int)parts * kGroups;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
-    for (uint32_t k = part * (kRuleNT / 64) + wid; k < n; k += parts * (kRuleNT / 64)) {
-        const ReplayItem it = out.rule_items[k];
-        const size_t so = (size_t)it.store_off;
-        const int L0 = it.store_len;
-        if (it.store_off < 0 || L0 < 0 || so + (size_t)L0 > out.store_cap) {
-            if (lane == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
-            continue;  // uniform over the wave
+
+    // uniform over the group: entry k0 now, k1 next, k2 after that
+    int k0 = a + (int)part * kGroups + (int)threadIdx.x / LANES;
+    RuleMeta m0{};
+    if (k0 < b) {
+        m0.pos = idx_pos[k0];
+        m0.w = idx_world[k0];
+        rule_meta(out, m0);
+    }
+    int k1 = k0 + stride;
+    int32_t p1 = 0, w1 = 0;
+    if (k1 < b) {
+        p1 = idx_pos[k1];
+        w1 = idx_world[k1];
+    }
+    while (k0 < b) {
+        // next entry's decision data, and the index of the one after
+        RuleMeta m1{};
+        const int k2 = k1 + stride;
+        int32_t p2 = 0, w2 = 0;
+        if (k1 < b) {
+            m1.pos = p1;
+            m1.w = w1;
+            rule_meta(out, m1);
         }
-        const int tj = label_tin(it.labj);
-        const int szj = label_size(it.labj);
-        const int cj = it.cj;
-        int nd = 0;
-        for (int b0 = 0; b0 < L0; b0 += 64 * kRuleUnroll) {
-            int c[kRuleUnroll], v[kRuleUnroll];
-            uint32_t lab[kRuleUnroll];
+        if (k2 < b) {
+            p2 = idx_pos[k2];
+            w2 = idx_world[k2];
+        }
+        const size_t so0 = (size_t)m0.off;
+        const int L0 = m0.len;
+        if (m0.c <= 0 || !label_rule_holds(m0.flags, m0.lab)) {
+            // lost already, or listed for the replay
+        } else if (m0.off < 0 || L0 < 0 || so0 + (size_t)L0 > out.store_cap) {
+            if (gl == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+        } else {
+            const int tj = label_tin(m0.lab);
+            const int szj = label_size(m0.lab);
+            const int cj = m0.c;
+            int nd = 0;
+            for (int b0 = 0; b0 < L0; b0 += LANES * kRuleUnroll) {
+                int c[kRuleUnroll], v[kRuleUnroll];
+                uint32_t lab[kRuleUnroll];
 #pragma unroll
-            for (int r = 0; r < kRuleUnroll; ++r) {
-                const int i = b0 + r * 64 + lane;
-                c[r] = 0;
-                v[r] = 0;
-                lab[r] = 0;
-                if (i < L0) {
-                    c[r] = out.store_cnt[so + i];
-                    v[r] = out.store_node[so + i];
-                    lab[r] = out.store_lab[so + i];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < kRuleUnroll; ++r) {
-                const int i = b0 + r * 64 + lane;
-                int d = 0, cn = 0;
-                if (c[r] > 0) {
-                    const int ti = label_tin(lab[r]);
-                    const int si = label_size(lab[r]);
-                    if (ti >= tj && ti < tj + szj) {
-                        d = -c[r];  // u's subtree, u included: no longer reached
-                    } else if (tj >= ti && tj < ti + si) {
-                        d = -cj;  // an ancestor of u
-                        cn = c[r] - cj;
+                for (int q = 0; q < kRuleUnroll; ++q) {
+                    const int i = b0 + q * LANES + gl;
+                    c[q] = 0;
+                    v[q] = 0;
+                    lab[q] = 0;
+                    if (i < L0) {
+                        c[q] = out.store_cnt[so0 + i];
+                        v[q] = out.store_node[so0 + i];
+                        lab[q] = out.store_lab[so0 + i];
                     }
                 }
-                const unsigned long long mask = __ballot(d != 0);
-                if (d != 0) {
-                    // u itself is blocked from now on: its gain is never read again
-                    if (ti_is_u(lab[r], tj)) {} else sums.add(v[r], d, out.gain);
-                    out.store_cnt[so + i] = cn;
+#pragma unroll
+                for (int q = 0; q < kRuleUnroll; ++q) {
+                    const int i = b0 + q * LANES + gl;
+                    int d = 0, cn = 0;
+                    if (c[q] > 0) {
+                        const int ti = label_tin(lab[q]);
+                        const int si = label_size(lab[q]);
+                        if (ti >= tj && ti < tj + szj) {
+                            d = -c[q];  // u's subtree, u included: no longer reached
+                        } else if (tj >= ti && tj < ti + si) {
+                            d = -cj;  // an ancestor of u
+                            cn = c[q] - cj;
+                        }
+                    }
+                    const unsigned long long mask = __ballot(d != 0) & gmask;
+                    if (d != 0) {
+                        // u itself is blocked from now on: its gain is never read again
+                        if (label_tin(lab[q]) != tj) sums.add(v[q], d, out.gain);
+                        out.store_cnt[so0 + i] = cn;
+                    }
+                    nd += __popcll(mask);
                 }
-                nd += __popcll(mask);
+            }
+            if (gl == 0) {
+                out.world_size[m0.w] = m0.wsize - cj;
+                acc_w += 1;
+                acc_e += (unsigned long long)L0;
+                // index entry, count and label of u, the world's range, size
+                // and flags; the entries; the changes; the new size
+                acc_b += 33ull + 12ull * (unsigned long long)L0 + 12ull * (unsigned long long)nd + 4ull;
+                acc_d += cj;
             }
         }
-        if (lane == 0) out.world_size[it.w] = it.world_size - cj;
-        acc_w += 1;
-        acc_e += (unsigned long long)L0;
-        acc_b += sizeof(ReplayItem) + 12ull * (unsigned long long)L0 + 12ull * (unsigned long long)nd + 8ull;
-        acc_d += cj;
+        k0 = k1;
+        m0 = m1;
+        k1 = k2;
+        p1 = p2;
+        w1 = w2;
     }
-    if (lane == 0) {
-        fs.red[wid][0] = acc_w;
-        fs.red[wid][1] = acc_e;
-        fs.red[wid][2] = acc_b;
-        fs.red[wid][3] = (unsigned long long)acc_d;
+    if (gl == 0 && acc_w) {
+        atomicAdd(&fs.red[0], acc_w);
+        atomicAdd(&fs.red[1], acc_e);
+        atomicAdd(&fs.red[2], acc_b);
+        atomicAdd(&fs.red[3], (unsigned long long)acc_d);
     }
     __syncthreads();
     sums.flush<kRuleNT>(out.gain);
     if (threadIdx.x == 0) {
-        unsigned long long f[4] = {0, 0, 0, 0};
-        for (int x = 0; x < kRuleNT / 64; ++x)
-            for (int y = 0; y < 4; ++y) f[y] += fs.red[x][y];
-        add_work_at(out, 4, part, f[0], f[1], f[2]);
-        if (f[3]) out.dsz[out.dsz_off[4] + part] = (long long)f[3];
+        add_work_at(out, 4, part, fs.red[0], fs.red[1], fs.red[2]);
+        if (fs.red[3]) out.dsz[out.dsz_off[4] + part] = (long long)fs.red[3];
     }
 }
 
 // ------------------------------------------------- changed-world update
 // One launch for the changed worlds of an incremental round: the first
 // replay_parts workgroups replay the worlds of items while the rest apply
-// the label rule to the worlds of rule_items, so the two run side by side.  LDS is shared between the
+// the label rule, so the two run side by side.  LDS is shared between the
 // two roles.
 static_assert(kReplayNT == kRuleNT, "both roles use the same workgroup size");
 union ChangedShared {
@@ -1693,18 +1760,34 @@ union ChangedShared {
     RuleShared f;
 };
 
+template <int LANES>
 __global__ __launch_bounds__(kReplayNT) void k_changed_worlds(QueryDev q, RoundCtl* ctl, int32_t* next_list,
-                                                               TileOut out, uint32_t replay_parts) {
+                                                               TileOut out, uint32_t replay_parts,
+                                                               const int32_t* idx_off, const int32_t* idx_pos,
+                                                               const int32_t* idx_world) {
     __shared__ ChangedShared u;
     if (ctl->stop) return;
-    if (blockIdx.x < replay_parts) replay_worlds(q, ctl, next_list, out, u.r.st, u.r.sh, blockIdx.x, replay_parts);
-    else rule_worlds(ctl, out, u.f, blockIdx.x - replay_parts, gridDim.x - replay_parts);
+    if (blockIdx.x < replay_parts)
+        replay_worlds(q, ctl, next_list, out, u.r.st, u.r.sh, blockIdx.x, replay_parts);
+    else
+        rule_worlds<LANES>(ctl, out, idx_off, idx_pos, idx_world, u.f, blockIdx.x - replay_parts,
+                           gridDim.x - replay_parts);
 }
 
 hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                 int replay_parts, int forest_parts, hipStream_t s) {
-    k_changed_worlds<<<replay_parts + forest_parts, kReplayNT, 0, s>>>(q, ctl, next_list, out,
-                                                                       (uint32_t)replay_parts);
+                                 int replay_parts, int rule_parts, int lanes, const int32_t* idx_off,
+                                 const int32_t* idx_pos, const int32_t* idx_world, hipStream_t s) {
+    const unsigned grid = (unsigned)(replay_parts + rule_parts);
+    if (grid == 0) return hipSuccess;
+    if (lanes == 16)
+        k_changed_worlds<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
+                                                         idx_pos, idx_world);
+    else if (lanes == 32)
+        k_changed_worlds<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
+                                                         idx_pos, idx_world);
+    else
+        k_changed_worlds<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
+                                                         idx_pos, idx_world);
     return hipGetLastError();
 }
 

@@ -181,15 +181,16 @@ def test_solve_random_graphs(B, oracle_mod, case):
 
 
 @pytest.mark.parametrize("variant", ["plain", "store_overflow", "tier1", "tier2", "batch1", "batch7", "noreplay",
-                                     "nolabelrule", "xscratch", "tiles"])
+                                     "nolabelrule", "xscratch", "tiles", "lanes32", "lanes64"])
 def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
     """Incremental rounds (default: worlds where no live edge leaves the new
     blocker's dominator subtree updated from their labels, other changed
     worlds replayed from their stored live edges), replay without the label
     rule, plain rounds, a resident store too small to
     hold round 0 (falls back to plain rounds), re-evaluation by sampling on
-    every tier, regrowth of the extra-edge scratch, several tiles and other
-    round batch sizes all give the oracle's selection."""
+    every tier, regrowth of the extra-edge scratch, several tiles, other
+    round batch sizes and other lane counts per world in the label rule all
+    give the oracle's selection."""
     if variant == "plain":
         monkeypatch.setenv("IMIN_INCREMENTAL", "0")
     elif variant == "store_overflow":
@@ -198,6 +199,8 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
         monkeypatch.setenv("IMIN_REPLAY", "0")
     elif variant == "nolabelrule":
         monkeypatch.setenv("IMIN_LABEL_RULE", "0")
+    elif variant.startswith("lanes"):
+        monkeypatch.setenv("IMIN_RULE_LANES", variant[5:])
     elif variant == "xscratch":
         monkeypatch.setenv("IMIN_XBIG_SCRATCH", "16")
         monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
