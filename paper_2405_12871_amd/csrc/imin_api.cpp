@@ -347,6 +347,9 @@ struct Session {
     int32_t dsz_n = 0;
     int32_t dsz_off[5] = {0, 0, 0, 0, 0};
     int grid_l = 0;
+    bool adopted = false;                  // the round-0 scratch serves as the store
+    unsigned long long adopted_entries = 0;
+    bool index_counted = false;            // idx_off holds the entries per node
     int rule_lanes = 16;  // lanes per world in the label rule
     int grid_r = 0;
     bool incremental = false;
@@ -647,20 +650,33 @@ struct Session {
         return grow_store(arrs, used, used + more, store_budget);
     }
 
+    // entries per node of the resident store (the index's counts), and
+    // with gain_out the from-scratch gains of round 0 in the same pass
+    imin_status_t count_index(uint64_t theta, int64_t* gain_out) {
+        const size_t n = (size_t)g.n;
+        IMIN_TRY(idx_off.alloc(n + 1));
+        IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
+        imin::TileOut out = tile_out();
+        IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, gain_out, s));
+        index_counted = true;
+        return IMIN_OK;
+    }
+
     // node -> (store position, world) of every entry written in round 0;
     // and the changed-world item lists of incremental rounds
     imin_status_t build_index(uint64_t theta) {
-        const unsigned long long entries = hctl.p->store_count;
+        const unsigned long long entries = adopted ? adopted_entries : hctl.p->store_count;
         const size_t n = (size_t)g.n;
-        IMIN_TRY(idx_off.alloc(n + 1));
+        if (!index_counted) {
+            const imin_status_t st = count_index(theta, nullptr);
+            if (st != IMIN_OK) return st;
+        }
         IMIN_TRY(idx_bsum.alloc((n + 4095) / 4096 + 1));
         IMIN_TRY(idx_cursor.alloc(n + 1));
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
         IMIN_TRY(items.alloc(theta));
-        IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
         imin::TileOut out = tile_out();
-        IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, s));
         IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
         IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_pos.p, idx_world.p, s));
@@ -815,8 +831,36 @@ struct Session {
                 }
                 continue;
             }
-            // dense destination for the tile's entries
             const unsigned long long total = hctl.p->tile_total;
+            if (store_mode && incremental && done == 0 && nw == count && total < (1ull << 31) &&
+                scr_node.count < (1ull << 31)) {
+                // One tile holds every world: its scratch becomes the store
+                // where it lies (fixed tier-0 slots and the bump region,
+                // located by wloc / wlen), with no copy.  The gains follow
+                // from the store in the pass that counts the index.
+                store_node.swap(scr_node);
+                store_cnt.swap(scr_cnt);
+                store_off.swap(wloc);
+                store_len.swap(wlen);
+                if (keep) {
+                    store_par.swap(scr_par);
+                    store_lab.swap(scr_lab);
+                    xstore_v.swap(xscr_v);
+                    xstore_u.swap(xscr_u);
+                    xstore_off.swap(xloc);
+                    xstore_len.swap(xlen);
+                }
+                adopted = true;
+                adopted_entries = total;
+                hipEvent_t ev = timed.begin(2, s);
+                const imin_status_t st2 = count_index((uint64_t)count, gain.p);
+                if (st2 != IMIN_OK) return st2;
+                timed.end(2, ev, s);
+                IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
+                done += nw;
+                continue;
+            }
+            // dense destination for the tile's entries
             const unsigned long long store_base = hctl.p->store_count;
             bool use_store = store_mode && incremental;
             if (use_store && !ensure_store(store_base, total)) {

@@ -260,7 +260,9 @@ hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next
                                  int replay_parts, int rule_parts, int lanes, const int32_t* idx_off,
                                  const int32_t* idx_pos, const int32_t* idx_world, hipStream_t s);
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
-hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s);
+// entries per node of the resident store; with gain non-null also the
+// from-scratch gains (gain[u] += every count of u)
+hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
 struct SelectOut;

@@ -1027,33 +1027,48 @@ struct IdxTable {
     }
 };
 
-// the workgroup's entries, counted per node in LDS (overflow straight to spill)
-__device__ void index_count_lds(const TileOut& out, uint32_t w0, uint32_t w1, IdxTable& tb, int32_t* spill) {
+// count entries per node; with GAIN also gain[u] += the entries' counts
+// (the from-scratch gains of round 0, Section 2.2: the sum over worlds of
+// the nodes each candidate protects).  A node appears at most once per
+// world with a count below 2^24 (the node count), so the sums over a
+// workgroup's 32 worlds stay below 2^29: the base array, unused while
+// counting, holds them.
+template <bool GAIN>
+__global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t theta, int32_t* cnt, int64_t* gain) {
+    __shared__ IdxTable tb;
+    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
+    if (w0 >= theta) return;
+    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
+    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
+        tb.keys[i] = -1;
+        tb.cnt[i] = 0;
+        tb.base[i] = 0;
+    }
+    __syncthreads();
     const int lane = threadIdx.x & 63;
     for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
         const size_t so = (size_t)out.store_off[w];
         const int len = out.store_len[w];
         for (int i = lane; i < len; i += 64) {
             const int32_t u = out.store_node[so + i];
+            const int32_t c = GAIN ? out.store_cnt[so + i] : 0;
             const int sl = tb.slot(u);
-            if (sl >= 0) atomicAdd(&tb.cnt[sl], 1);
-            else atomicAdd(&spill[u], 1);
+            if (sl >= 0) {
+                atomicAdd(&tb.cnt[sl], 1);
+                if (GAIN) atomicAdd(&tb.base[sl], c);
+            } else {
+                atomicAdd(&cnt[u], 1);
+                if (GAIN) atomicAdd((unsigned long long*)&gain[u], (unsigned long long)(long long)c);
+            }
         }
     }
-}
-
-// count entries per node
-__global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t theta, int32_t* cnt) {
-    __shared__ IdxTable tb;
-    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
-    if (w0 >= theta) return;
-    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
-    tb.clear();
     __syncthreads();
-    index_count_lds(out, w0, w1, tb, cnt);
-    __syncthreads();
-    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT)
-        if (tb.keys[i] >= 0) atomicAdd(&cnt[tb.keys[i]], tb.cnt[i]);
+    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
+        const int32_t u = tb.keys[i];
+        if (u < 0) continue;
+        atomicAdd(&cnt[u], tb.cnt[i]);
+        if (GAIN) atomicAdd((unsigned long long*)&gain[u], (unsigned long long)(long long)tb.base[i]);
+    }
 }
 
 // place (position, world) of each entry in its node's range
@@ -1171,10 +1186,13 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     }
 }
 
-hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, hipStream_t s) {
+hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s) {
     const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
     if (blocks == 0) return hipSuccess;
-    k_index_count<<<blocks, kIdxNT, 0, s>>>(out, theta, cnt);
+    if (gain)
+        k_index_count<true><<<blocks, kIdxNT, 0, s>>>(out, theta, cnt, gain);
+    else
+        k_index_count<false><<<blocks, kIdxNT, 0, s>>>(out, theta, cnt, nullptr);
     return hipGetLastError();
 }
 
