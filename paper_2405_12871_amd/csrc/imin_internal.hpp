@@ -47,7 +47,7 @@ struct RoundCtl {
     int32_t round;
     int32_t round_snap;      // the round as the last partial selection saw it
     int32_t ustar;
-    uint32_t next[3];        // work counters of the three world tiers
+    uint32_t next[3];        // work counters of the LDS world tiers (chunks handed out)
     uint32_t list_n[3];      // worlds handed down to tier 1 and tier 2
     unsigned long long pair_count;
     long long total;         // sum of |R_w| over the worlds evaluated this round

@@ -63,6 +63,7 @@ struct WorldShared {
     unsigned long long in_bytes;  // algorithmic bytes read by the BFS phase
     unsigned long long acc_worlds, acc_edges, acc_bytes;  // this workgroup's work so far
     long long acc_dsize;  // reached nodes lost by this workgroup's worlds (incremental rounds)
+    uint32_t sched;       // first world of the chunk just taken
     int row_lid[NT];
     int row_node[NT];
     int row_e0[NT];
@@ -754,6 +755,7 @@ using Tier0Store = LdsStore<256, 9, 128, 30>;
 // in a from-scratch pass fits it again after any blockers are added
 using Tier1Store = LdsStore<2048, 12, 1024, 2050>;
 constexpr int kTier0NT = 64;
+constexpr uint32_t kSchedChunk = 8;  // worlds per update of a tier's work counter
 constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
 
@@ -796,7 +798,15 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         sh.acc_dsize = 0;
     }
     __syncthreads();
-    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+    // World costs vary widely, so after its first world (its block id) a
+    // workgroup takes chunks of worlds from a counter: the workgroups finish
+    // together, and the counter sees one update per chunk.  Chunks hold up to
+    // kSchedChunk worlds, fewer when the worlds left after the first ones
+    // would not give every workgroup several chunks.
+    const uint32_t rest = n_items > gridDim.x ? n_items - gridDim.x : 0u;
+    const uint32_t chunk = max(1u, min(kSchedChunk, rest / (gridDim.x * 4u)));
+    uint32_t k = blockIdx.x, kend = blockIdx.x + 1;
+    while (k < n_items) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<NT, TIER>(g, q, ctl, w_begin + wi, wi, out, st, sh);
         if (!ok && t == 0) {
@@ -805,6 +815,12 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
             else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         }
         st.template reset<NT>(0);
+        if (++k == kend) {
+            if (t == 0) sh.sched = gridDim.x + atomicAdd(&ctl->next[TIER], chunk);
+            __syncthreads();
+            k = sh.sched;
+            kend = k + chunk;
+        }
         __syncthreads();
     }
     if (t == 0) {
