@@ -166,12 +166,13 @@ imin_status_t imin_cache_release(void);
  *      the gains inside kernels 1, 4 and 6
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
- *   5  search for the worlds a new blocker changes (incremental rounds)
- *   6  update of the changed worlds of an incremental round, one launch:
- *      count update from the dominator-tree labels of the worlds where no
- *      live edge leaves the blocker's dominator subtree, and replay of the
- *      others from their stored live edges (worlds too large for the
- *      replay go on to kernels 4 and 1)
+ *   5  search for the worlds a new blocker changes (incremental rounds
+ *      without replay, whose changed worlds are sampled again)
+ *   6  an incremental round with replay, one launch: the last selection is
+ *      committed, the worlds where no live edge leaves the new blocker's
+ *      dominator subtree are updated from their dominator-tree labels, and
+ *      the other changed worlds are replayed from their stored live edges
+ *      (worlds too large for the replay go on to kernels 4 and 1)
  *   7  (unused)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.

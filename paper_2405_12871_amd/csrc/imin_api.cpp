@@ -338,7 +338,6 @@ struct Session {
     size_t xslot_cap0 = 0, xbig_cap = 0;
     DevArray<int32_t> store_par, xstore_v, xstore_u, xstore_len;
     DevArray<int64_t> xstore_off;
-    DevArray<imin::ReplayItem> items;   // changed worlds of an incremental round to re-evaluate
     // dominator-tree labels and the labelled flag per world (with replay)
     DevArray<int32_t> scr_lab, store_lab;
     DevArray<uint8_t> world_flags;
@@ -493,9 +492,9 @@ struct Session {
         IMIN_TRY(sel_d.alloc(sel_parts));
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
-        // changed-world update: replay and label-rule workgroups of one launch
+        // changed-world update: label-rule and replay workgroups of one launch
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
-        grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 4);
+        grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 2);
         rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
         {
             const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_l};
@@ -675,7 +674,6 @@ struct Session {
         IMIN_TRY(idx_cursor.alloc(n + 1));
         IMIN_TRY(idx_pos.alloc(entries));
         IMIN_TRY(idx_world.alloc(entries));
-        IMIN_TRY(items.alloc(theta));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
         IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -702,9 +700,7 @@ struct Session {
         out.store_off = store_off.p;
         out.store_len = store_len.p;
         out.gain = gain.p;
-        out.list_cap = (uint32_t)std::min<size_t>(items.p ? std::min(list0.count, items.count) : list0.count,
-                                                  0xFFFFFFFFu);
-        out.items = items.p;
+        out.list_cap = (uint32_t)std::min<size_t>(list0.count, 0xFFFFFFFFu);
         out.scr_lab = (uint32_t*)scr_lab.p;
         out.store_lab = (uint32_t*)store_lab.p;
         out.world_flags = label_rule ? world_flags.p : nullptr;
@@ -755,24 +751,25 @@ struct Session {
         out.mode = imin::kModeDelta;
         out.world_size = world_size.p;
         // the per-round counters were cleared by the last selection
-        // the search for the changed worlds the label rule cannot take
-        hipEvent_t ev = timed.begin(5, s);
-        IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, so, s));
-        timed.end(5, ev, s);
         imin_status_t st;
         if (replay) {
-            // worlds where no live edge leaves the blocker's subtree: subtree
-            // removal from the labels; every other changed world is
-            // replayed, those too large go on to sampling
-            ev = timed.begin(6, s);
-            IMIN_TRY(imin::launch_changed_worlds(q, ctl.p, list1.p, out, grid_r, out.world_flags ? grid_l : 0,
-                                                 rule_lanes, idx_off.p, idx_pos.p, idx_world.p, s));
+            // one launch: the last selection is committed; worlds where no
+            // live edge leaves the blocker's subtree lose it from their
+            // labels; every other changed world is replayed, those too
+            // large go on to sampling
+            hipEvent_t ev = timed.begin(6, s);
+            IMIN_TRY(imin::launch_round_update(q, ctl.p, list1.p, out, out.world_flags ? grid_l : 0, grid_r,
+                                               rule_lanes, idx_off.p, idx_pos.p, idx_world.p, so, s));
             timed.end(6, ev, s);
             // worlds the replay cannot hold are sampled again; when round 0
             // stored none, no world ever falls back and the tiers are not launched
             if (!replay_complete) st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());
             else st = IMIN_OK;
         } else {
+            // the search for the changed worlds, then their sampling
+            hipEvent_t ev = timed.begin(5, s);
+            IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, so, s));
+            timed.end(5, ev, s);
             st = launch_tiers(q, 0, 0, list0.p, out, start_tier, 0, last_tier());
         }
         if (st != IMIN_OK) return st;

@@ -154,7 +154,6 @@ struct TileOut {
     int64_t* gain;       // incremental rounds: count changes are added here
     uint32_t list_cap;   // entries of the changed-world list
     uint32_t next_cap;   // entries of each list handed down to tier 1 / 2
-    ReplayItem* items;   // changed worlds to re-evaluate, with their store ranges (list_cap of them)
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
@@ -252,20 +251,22 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
 hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
-// Changed worlds of an incremental round: replay_parts workgroups replay the
-// worlds of items (those too large go to next_list); rule_parts workgroups
-// apply the label rule to the worlds it holds for, found through the index
-// (a world per `lanes` lanes: 16, 32 or 64).
-hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                 int replay_parts, int rule_parts, int lanes, const int32_t* idx_off,
-                                 const int32_t* idx_pos, const int32_t* idx_world, hipStream_t s);
+// An incremental round with replay, one launch: the last selection is
+// combined and committed, then rule_parts workgroups apply the label rule to
+// the worlds it holds for (a world per `lanes` lanes: 16, 32 or 64) and
+// replay_parts (>= 1) workgroups replay the other changed worlds (those too
+// large go to next_list); both find the worlds through the index.
+struct SelectOut;
+hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                               int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
+                               const int32_t* idx_pos, const int32_t* idx_world, const SelectOut& so,
+                               hipStream_t s);
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
 // entries per node of the resident store; with gain non-null also the
 // from-scratch gains (gain[u] += every count of u)
 hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s);
 hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
                              int32_t* idx_world, hipStream_t s);
-struct SelectOut;
 hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
                                   const int32_t* idx_world, int32_t* list, const SelectOut& so, hipStream_t s);
 hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s);

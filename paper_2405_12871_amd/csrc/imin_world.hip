@@ -1131,19 +1131,17 @@ __global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t the
     }
 }
 
-// An incremental round starts here.  Every workgroup combines the parts of
-// the last selection (the same result everywhere); workgroup 0 commits it.
-// Then the worlds whose entry for the new blocker u is live are listed, with
-// their store ranges and that entry -> items / list[0 .. list_n[0]), except
-// those the label rule takes (labelled worlds where u's exit bit is clear:
-// no live edge leaves u's dominator subtree), which the changed-world
-// launch finds in the index itself.
 // Whether the label rule updates a world for the new blocker: the world is
 // labelled and the blocker's exit bit is clear.
 __device__ __forceinline__ bool label_rule_holds(uint8_t wflags, uint32_t lab) {
     return (wflags & kWorldLabelled) != 0 && !label_exits(lab);
 }
 
+// An incremental round without replay starts here (with replay,
+// k_round_update takes this role).  Every workgroup combines the parts of
+// the last selection (the same result everywhere); workgroup 0 commits it.
+// Then the worlds whose entry for the new blocker u is live are listed in
+// list[0 .. list_n[0]) for the sampling tiers.
 __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
                                                          const int32_t* idx_pos, const int32_t* idx_world,
                                                          int32_t* list, SelectOut so) {
@@ -1164,40 +1162,20 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     const unsigned long long below = (1ull << lane) - 1ull;
     for (int i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
         const int k = i + lane;
-        int32_t pos = 0, c = 0, w = 0;
-        uint32_t lab = 0;
-        uint8_t wflags = 0;
+        int32_t w = 0, c = 0;
         if (k < b) {
-            pos = idx_pos[k];
             w = idx_world[k];
-            c = out.store_cnt[pos];
-            if (out.store_lab) lab = out.store_lab[pos];
-            if (out.world_flags) wflags = out.world_flags[w];
+            c = out.store_cnt[idx_pos[k]];
         }
-        const bool live = c > 0 && !label_rule_holds(wflags, lab);
+        const bool live = c > 0;
         const unsigned long long mr = __ballot(live);
         uint32_t br = 0;
         if (lane == 0 && mr) br = atomicAdd(&ctl->list_n[0], (uint32_t)__popcll(mr));
         br = __shfl(br, 0, 64);
         if (live) {
             const uint32_t at = br + (uint32_t)__popcll(mr & below);
-            if (at < out.list_cap) {
-                ReplayItem it;
-                it.store_off = out.store_off[w];
-                it.store_len = out.store_len[w];
-                it.xstore_off = out.xstore_off ? out.xstore_off[w] : 0;
-                it.xstore_len = out.xstore_off ? out.xstore_len[w] : 0;
-                it.world_size = out.world_size[w];
-                it.w = w;
-                it.j = (int32_t)((int64_t)pos - it.store_off);
-                it.cj = c;
-                it.labj = lab;
-                it.flags = wflags;
-                out.items[at] = it;
-                list[at] = w;
-            } else {
-                atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
-            }
+            if (at < out.list_cap) list[at] = w;
+            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         }
     }
 }
@@ -1558,45 +1536,92 @@ __device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t usta
     return sh.ndelta;
 }
 
-// Changed worlds that are not forests are replayed; a world that does not
-// fit the replay store goes on to the sampling tiers (list 1).  Workgroup
-// `part` of `parts` takes items part, part + parts, ...
+// Changed worlds the label rule cannot take are replayed; a world that does
+// not fit the replay store goes on to the sampling tiers (list 1).  The
+// replay workgroups find those worlds in the index themselves: workgroup
+// `part` of `parts` takes slices of kReplaySlice index entries of u (slice
+// part, part + parts, ...), lists in LDS the live entries the rule cannot
+// take and replays them one by one.  Small slices spread the replays of a
+// round over many workgroups.
+constexpr int kReplaySlice = 32;
+
+struct ReplayShared {
+    ReplayStoreT st;
+    WorldShared<kReplayNT> sh;
+    int4 lst[kReplaySlice];  // (store position, world, count, label) of u's entry
+    uint32_t lst_n;
+};
+
 __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                              ReplayStoreT& st, WorldShared<kReplayNT>& sh, uint32_t part, uint32_t parts) {
+                                              const int32_t* idx_off, const int32_t* idx_pos, const int32_t* idx_world,
+                                              int32_t ustar, ReplayShared& rs, uint32_t part, uint32_t parts) {
+    static_assert(kReplaySlice <= kReplayNT, "one thread per entry of a slice");
     const int t = threadIdx.x;
-    const uint32_t n_items = min(ctl->list_n[0], out.list_cap);
-    if (part >= n_items) return;
-    const int32_t ustar = ctl->ustar;
+    const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
+    if ((long long)a + (long long)part * kReplaySlice >= (long long)b) return;  // no slice for this workgroup
+    ReplayStoreT& st = rs.st;
+    WorldShared<kReplayNT>& sh = rs.sh;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0, acc_lw = 0, acc_le = 0, acc_lb = 0;
     long long acc_d = 0;
-    for (uint32_t k = part; k < n_items; k += parts) {
-        const ReplayItem cur = out.items[k];
-        int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
-        uint32_t ed[kReplaySlots], act;
-        const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
-        if (how == 2) {
-            // the shortcut: reported with the label-based updates
-            acc_lw += 1;
-            acc_le += (unsigned long long)(cur.store_len + cur.xstore_len);
-            acc_lb += sizeof(ReplayItem) + 16ull * (unsigned long long)cur.store_len +
-                      8ull * (unsigned long long)cur.xstore_len + 8ull;
-            acc_d += cur.cj;
-        } else if (how == 1) {
-            world_counts<kReplayNT>(q, ctl, st, sh);
-            world_labels<kReplayNT>(q, st, sh);
-            if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
-            const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
-            acc_w += 1;
-            acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
-            acc_b += sizeof(ReplayItem) + 12ull * (unsigned long long)cur.store_len +
-                     8ull * (unsigned long long)cur.xstore_len + 12ull * (unsigned long long)nd + 8ull;
-            acc_d += (long long)cur.world_size - (long long)sh.count;
-        } else if (t == 0) {
-            const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
-            if (pos < out.next_cap) next_list[pos] = cur.w;
-            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+    for (long long base = (long long)a + (long long)part * kReplaySlice; base < (long long)b;
+         base += (long long)parts * kReplaySlice) {
+        if (t == 0) rs.lst_n = 0;
+        __syncthreads();
+        if (t < kReplaySlice && base + t < (long long)b) {
+            const int32_t pos = idx_pos[base + t];
+            const int32_t w = idx_world[base + t];
+            const int32_t c = out.store_cnt[pos];
+            const uint32_t lab = out.store_lab ? out.store_lab[pos] : 0u;
+            const uint8_t fl = out.world_flags ? out.world_flags[w] : (uint8_t)0;
+            if (c > 0 && !label_rule_holds(fl, lab)) {
+                const uint32_t at = atomicAdd(&rs.lst_n, 1u);
+                rs.lst[at] = make_int4(pos, w, c, (int)lab);
+            }
         }
         __syncthreads();
+        const uint32_t nl = rs.lst_n;
+        for (uint32_t li = 0; li < nl; ++li) {
+            const int4 e = rs.lst[li];
+            ReplayItem cur;
+            cur.w = e.y;
+            cur.store_off = out.store_off[e.y];
+            cur.store_len = out.store_len[e.y];
+            cur.xstore_off = out.xstore_off[e.y];
+            cur.xstore_len = out.xstore_len[e.y];
+            cur.world_size = out.world_size[e.y];
+            cur.j = (int32_t)((int64_t)e.x - cur.store_off);
+            cur.cj = e.z;
+            cur.labj = (uint32_t)e.w;
+            cur.flags = out.world_flags ? out.world_flags[e.y] : 0;
+            int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
+            uint32_t ed[kReplaySlots], act;
+            const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
+            if (how == 2) {
+                // the shortcut: reported with the label-based updates
+                acc_lw += 1;
+                acc_le += (unsigned long long)(cur.store_len + cur.xstore_len);
+                acc_lb += 37ull + 16ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
+                          8ull;
+                acc_d += cur.cj;
+            } else if (how == 1) {
+                world_counts<kReplayNT>(q, ctl, st, sh);
+                world_labels<kReplayNT>(q, st, sh);
+                if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
+                const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
+                acc_w += 1;
+                acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
+                // index entry, count, label, the world's ranges, size and
+                // flags; entries and edges; the changes; the new size
+                acc_b += 37ull + 12ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
+                         12ull * (unsigned long long)nd + 8ull;
+                acc_d += (long long)cur.world_size - (long long)sh.count;
+            } else if (t == 0) {
+                const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
+                if (pos < out.next_cap) next_list[pos] = cur.w;
+                else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            }
+            __syncthreads();
+        }
     }
     if (t == 0) {
         add_work_at(out, 3, part, acc_w, acc_e, acc_b);
@@ -1625,15 +1650,31 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
 // a live entry of a labelled world with a clear exit bit is updated by the
 // group in one pass over the world's entries.  The loads of the next entry
 // (index, then its count, label and world) are issued before the current
-// world's pass; smaller groups keep more worlds in flight per wave.  The
-// count changes of a workgroup's worlds are summed in LDS and added to
-// gain once per node per workgroup.
+// world's pass; smaller groups keep more worlds in flight per wave.  Each
+// entry's change depends only on its own count and label and on u's, so a
+// world longer than two passes of a group is split: the group takes the
+// first pass and queues the rest, which the workgroup's groups share once
+// every group is done with its entries.  The count changes of a
+// workgroup's worlds are summed in LDS and added to gain once per node per
+// workgroup.
 constexpr int kRuleUnroll = 8;
 using RuleSums = LdsSums<11>;
+
+constexpr int kRuleBigCap = 64;  // queued remainders of large worlds per workgroup
+
+// A large world's entries past its first span, left to the whole workgroup.
+struct RuleBig {
+    int64_t off;
+    int32_t len;
+    uint32_t lab;
+    int32_t cj;
+};
 
 struct RuleShared {
     RuleSums sums;
     unsigned long long red[4];
+    RuleBig big[kRuleBigCap];
+    uint32_t big_n;
 };
 
 // What is read of one index entry before deciding.
@@ -1654,27 +1695,79 @@ __device__ __forceinline__ void rule_meta(const TileOut& out, RuleMeta& m) {
     m.wsize = out.world_size[m.w];
 }
 
+// The rule on entries [i0, i1) of a world (group of LANES lanes): returns
+// the number of entries changed.
 template <int LANES>
-__device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const int32_t* idx_off, const int32_t* idx_pos,
-                            const int32_t* idx_world, RuleShared& fs, uint32_t part, uint32_t parts) {
+__device__ __forceinline__ int rule_span(const TileOut& out, RuleSums& sums, size_t so0, int i0, int i1, uint32_t labj,
+                                         int cj, int gl, unsigned long long gmask) {
+    const int tj = label_tin(labj);
+    const int szj = label_size(labj);
+    int nd = 0;
+    for (int b0 = i0; b0 < i1; b0 += LANES * kRuleUnroll) {
+        int c[kRuleUnroll], v[kRuleUnroll];
+        uint32_t lab[kRuleUnroll];
+#pragma unroll
+        for (int q = 0; q < kRuleUnroll; ++q) {
+            const int i = b0 + q * LANES + gl;
+            c[q] = 0;
+            v[q] = 0;
+            lab[q] = 0;
+            if (i < i1) {
+                c[q] = out.store_cnt[so0 + i];
+                v[q] = out.store_node[so0 + i];
+                lab[q] = out.store_lab[so0 + i];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kRuleUnroll; ++q) {
+            const int i = b0 + q * LANES + gl;
+            int d = 0, cn = 0;
+            if (c[q] > 0) {
+                const int ti = label_tin(lab[q]);
+                const int si = label_size(lab[q]);
+                if (ti >= tj && ti < tj + szj) {
+                    d = -c[q];  // u's subtree, u included: no longer reached
+                } else if (tj >= ti && tj < ti + si) {
+                    d = -cj;  // an ancestor of u
+                    cn = c[q] - cj;
+                }
+            }
+            const unsigned long long mask = __ballot(d != 0) & gmask;
+            if (d != 0) {
+                // u itself is blocked from now on: its gain is never read again
+                if (label_tin(lab[q]) != tj) sums.add(v[q], d, out.gain);
+                out.store_cnt[so0 + i] = cn;
+            }
+            nd += __popcll(mask);
+        }
+    }
+    return nd;
+}
+
+template <int LANES>
+__device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const int32_t* idx_off,
+                                            const int32_t* idx_pos, const int32_t* idx_world, int32_t ustar,
+                                            RuleShared& fs, uint32_t part, uint32_t parts) {
     static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
     constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
-    const int32_t ustar = ctl->ustar;
+    constexpr int kSpan = LANES * kRuleUnroll;  // entries a group takes in one pass
     const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
     if ((long long)a + (long long)part * kGroups >= (long long)b) return;  // no entry for this workgroup
     RuleSums& sums = fs.sums;
     sums.clear<kRuleNT>();
     if (threadIdx.x < 4) fs.red[threadIdx.x] = 0;
+    if (threadIdx.x == 0) fs.big_n = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane % LANES;  // lane within the world's group
+    const int group = (int)threadIdx.x / LANES;
     const unsigned long long gmask = (LANES == 64) ? ~0ull : (((1ull << LANES) - 1ull) << (lane - gl));
     const int stride = (int)parts * kGroups;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
 
     // uniform over the group: entry k0 now, k1 next, k2 after that
-    int k0 = a + (int)part * kGroups + (int)threadIdx.x / LANES;
+    int k0 = a + (int)part * kGroups + group;
     RuleMeta m0{};
     if (k0 < b) {
         m0.pos = idx_pos[k0];
@@ -1708,56 +1801,27 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
         } else if (m0.off < 0 || L0 < 0 || so0 + (size_t)L0 > out.store_cap) {
             if (gl == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         } else {
-            const int tj = label_tin(m0.lab);
-            const int szj = label_size(m0.lab);
-            const int cj = m0.c;
-            int nd = 0;
-            for (int b0 = 0; b0 < L0; b0 += LANES * kRuleUnroll) {
-                int c[kRuleUnroll], v[kRuleUnroll];
-                uint32_t lab[kRuleUnroll];
-#pragma unroll
-                for (int q = 0; q < kRuleUnroll; ++q) {
-                    const int i = b0 + q * LANES + gl;
-                    c[q] = 0;
-                    v[q] = 0;
-                    lab[q] = 0;
-                    if (i < L0) {
-                        c[q] = out.store_cnt[so0 + i];
-                        v[q] = out.store_node[so0 + i];
-                        lab[q] = out.store_lab[so0 + i];
-                    }
-                }
-#pragma unroll
-                for (int q = 0; q < kRuleUnroll; ++q) {
-                    const int i = b0 + q * LANES + gl;
-                    int d = 0, cn = 0;
-                    if (c[q] > 0) {
-                        const int ti = label_tin(lab[q]);
-                        const int si = label_size(lab[q]);
-                        if (ti >= tj && ti < tj + szj) {
-                            d = -c[q];  // u's subtree, u included: no longer reached
-                        } else if (tj >= ti && tj < ti + si) {
-                            d = -cj;  // an ancestor of u
-                            cn = c[q] - cj;
-                        }
-                    }
-                    const unsigned long long mask = __ballot(d != 0) & gmask;
-                    if (d != 0) {
-                        // u itself is blocked from now on: its gain is never read again
-                        if (label_tin(lab[q]) != tj) sums.add(v[q], d, out.gain);
-                        out.store_cnt[so0 + i] = cn;
-                    }
-                    nd += __popcll(mask);
+            // a world longer than two spans: the group takes the first span
+            // and leaves the rest to the whole workgroup
+            int L = L0;
+            if (L0 > 2 * kSpan) {
+                uint32_t at = 0;
+                if (gl == 0) at = atomicAdd(&fs.big_n, 1u);
+                at = __shfl(at, 0, LANES);
+                if (at < (uint32_t)kRuleBigCap) {
+                    if (gl == 0) fs.big[at] = RuleBig{m0.off, L0, m0.lab, m0.c};
+                    L = kSpan;
                 }
             }
+            const int nd = rule_span<LANES>(out, sums, so0, 0, L, m0.lab, m0.c, gl, gmask);
             if (gl == 0) {
-                out.world_size[m0.w] = m0.wsize - cj;
+                out.world_size[m0.w] = m0.wsize - m0.c;
                 acc_w += 1;
                 acc_e += (unsigned long long)L0;
                 // index entry, count and label of u, the world's range, size
                 // and flags; the entries; the changes; the new size
                 acc_b += 33ull + 12ull * (unsigned long long)L0 + 12ull * (unsigned long long)nd + 4ull;
-                acc_d += cj;
+                acc_d += m0.c;
             }
         }
         k0 = k1;
@@ -1766,7 +1830,17 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
         p1 = p2;
         w1 = w2;
     }
-    if (gl == 0 && acc_w) {
+    __syncthreads();
+    // the queued remainders, a span per group at a time
+    const uint32_t nbig = min(fs.big_n, (uint32_t)kRuleBigCap);
+    for (uint32_t qi = 0; qi < nbig; ++qi) {
+        const RuleBig bw = fs.big[qi];
+        int nd = 0;
+        for (int i0 = kSpan * (1 + group); i0 < bw.len; i0 += kSpan * kGroups)
+            nd += rule_span<LANES>(out, sums, (size_t)bw.off, i0, min(i0 + kSpan, bw.len), bw.lab, bw.cj, gl, gmask);
+        if (gl == 0) acc_b += 12ull * (unsigned long long)nd;
+    }
+    if (gl == 0 && (acc_w || acc_b)) {
         atomicAdd(&fs.red[0], acc_w);
         atomicAdd(&fs.red[1], acc_e);
         atomicAdd(&fs.red[2], acc_b);
@@ -1781,47 +1855,57 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
 }
 
 // ------------------------------------------------- changed-world update
-// One launch for the changed worlds of an incremental round: the first
-// replay_parts workgroups replay the worlds of items while the rest apply
-// the label rule, so the two run side by side.  LDS is shared between the
-// two roles.
+// One launch per incremental round: every workgroup combines the parts of
+// the last selection (the same result everywhere) and workgroup 0 commits
+// it; then the first rule_parts workgroups apply the label rule while the
+// rest replay the other changed worlds, side by side.  LDS is shared
+// between the roles.
 static_assert(kReplayNT == kRuleNT, "both roles use the same workgroup size");
-union ChangedShared {
+union UpdateShared {
     struct {
-        ReplayStoreT st;
-        WorldShared<kReplayNT> sh;
-    } r;
+        int64_t sg[kReplayNT];
+        int32_t su[kReplayNT];
+        long long sd[kReplayNT / 64];
+    } sel;
+    ReplayShared r;
     RuleShared f;
 };
 
 template <int LANES>
-__global__ __launch_bounds__(kReplayNT) void k_changed_worlds(QueryDev q, RoundCtl* ctl, int32_t* next_list,
-                                                               TileOut out, uint32_t replay_parts,
-                                                               const int32_t* idx_off, const int32_t* idx_pos,
-                                                               const int32_t* idx_world) {
-    __shared__ ChangedShared u;
+__global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, RoundCtl* ctl, int32_t* next_list, TileOut out,
+                                                             uint32_t rule_parts, const int32_t* idx_off,
+                                                             const int32_t* idx_pos, const int32_t* idx_world,
+                                                             SelectOut so) {
+    __shared__ UpdateShared u;
     if (ctl->stop) return;
-    if (blockIdx.x < replay_parts)
-        replay_worlds(q, ctl, next_list, out, u.r.st, u.r.sh, blockIdx.x, replay_parts);
+    int64_t bg;
+    int32_t bu;
+    long long dl;
+    select_combine(so, bg, bu, dl, u.sel.sg, u.sel.su, u.sel.sd);
+    const int r = ctl->round_snap;  // written by the partial launch; workgroup 0 updates ctl->round
+    if (blockIdx.x == 0 && threadIdx.x == 0) select_commit(ctl, so, r, bg, bu, dl);
+    if (select_stops(r, so.k, bu, bg) || r + 1 == so.k) return;  // no further round (uniform)
+    __syncthreads();  // the selection's LDS is reused below
+    if (blockIdx.x < rule_parts)
+        rule_worlds<LANES>(ctl, out, idx_off, idx_pos, idx_world, bu, u.f, blockIdx.x, rule_parts);
     else
-        rule_worlds<LANES>(ctl, out, idx_off, idx_pos, idx_world, u.f, blockIdx.x - replay_parts,
-                           gridDim.x - replay_parts);
+        replay_worlds(q, ctl, next_list, out, idx_off, idx_pos, idx_world, bu, u.r, blockIdx.x - rule_parts,
+                      gridDim.x - rule_parts);
 }
 
-hipError_t launch_changed_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                 int replay_parts, int rule_parts, int lanes, const int32_t* idx_off,
-                                 const int32_t* idx_pos, const int32_t* idx_world, hipStream_t s) {
+hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                               int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
+                               const int32_t* idx_pos, const int32_t* idx_world, const SelectOut& so,
+                               hipStream_t s) {
     const unsigned grid = (unsigned)(replay_parts + rule_parts);
-    if (grid == 0) return hipSuccess;
+    if (grid == 0 || replay_parts < 1) return hipErrorInvalidValue;
+    const uint32_t rp = (uint32_t)rule_parts;
     if (lanes == 16)
-        k_changed_worlds<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
-                                                         idx_pos, idx_world);
+        k_round_update<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
     else if (lanes == 32)
-        k_changed_worlds<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
-                                                         idx_pos, idx_world);
+        k_round_update<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
     else
-        k_changed_worlds<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, (uint32_t)replay_parts, idx_off,
-                                                         idx_pos, idx_world);
+        k_round_update<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
     return hipGetLastError();
 }
 
