@@ -46,7 +46,7 @@ def percentile(xs, q):
     return xs[i]
 
 
-KERNEL_SOURCES = ["imin_world.hip", "imin_device.hpp", "imin_internal.hpp"]
+KERNEL_SOURCES = ["imin_world.hip", "imin_device.hpp", "imin_internal.hpp", "imin_select.hpp"]
 
 
 def measured_traffic(kernel: str):
@@ -183,8 +183,8 @@ def main():
            torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
            torch.zeros(k + 1, dtype=torch.int64, device=dev),
            torch.zeros(1, dtype=torch.int32, device=dev))
-    kernels = (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("changed_worlds", 6),
-               ("reduce", 2), ("select", 3), ("affected_search", 5))
+    kernels = (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("round_update", 6),
+               ("reduce", 2), ("select", 3), ("search_without_replay", 5))
     kern = {}
     for i in range(max(args.warmup, 1)):
         binding.timing_reset()
@@ -195,7 +195,7 @@ def main():
     # the world kernel with the most time per solve
     # kernel -> (timer id, work tiers it reports)
     world_ids = {"world_tier0": (0, (0,)), "world_tier1": (4, (1,)), "world_tier2": (1, (2,)),
-                 "changed_worlds": (6, (3, 4, 5))}
+                 "round_update": (6, (3, 4, 5))}
     dom = max(world_ids, key=lambda nm: kern.get(nm, 0.0))
     dom_kid, dom_tiers = world_ids[dom]
     # events take time on the stream: one launch in TIMED_EVERY of the dominant
