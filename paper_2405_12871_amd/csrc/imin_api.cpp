@@ -354,7 +354,8 @@ struct Session {
     bool incremental = false;
     size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
-    DevArray<int32_t> idx_off, idx_bsum, idx_cursor, idx_pos, idx_world;
+    DevArray<int32_t> idx_off, idx_bsum, idx_cursor;
+    DevArray<int2> idx_ent;  // (store position, world) of each entry, grouped by node
     // level-0 slot groups of the seeds
     DevArray<int32_t> seed_cnt;
     DevArray<int4> seed_table;
@@ -672,12 +673,11 @@ struct Session {
         }
         IMIN_TRY(idx_bsum.alloc((n + 4095) / 4096 + 1));
         IMIN_TRY(idx_cursor.alloc(n + 1));
-        IMIN_TRY(idx_pos.alloc(entries));
-        IMIN_TRY(idx_world.alloc(entries));
+        IMIN_TRY(idx_ent.alloc(entries));
         imin::TileOut out = tile_out();
         IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
         IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_pos.p, idx_world.p, s));
+        IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_ent.p, s));
         return IMIN_OK;
     }
 
@@ -759,7 +759,7 @@ struct Session {
             // large go on to sampling
             hipEvent_t ev = timed.begin(6, s);
             IMIN_TRY(imin::launch_round_update(q, ctl.p, list1.p, out, out.world_flags ? grid_l : 0, grid_r,
-                                               rule_lanes, idx_off.p, idx_pos.p, idx_world.p, so, s));
+                                               rule_lanes, idx_off.p, idx_ent.p, so, s));
             timed.end(6, ev, s);
             // worlds the replay cannot hold are sampled again; when round 0
             // stored none, no world ever falls back and the tiers are not launched
@@ -768,7 +768,7 @@ struct Session {
         } else {
             // the search for the changed worlds, then their sampling
             hipEvent_t ev = timed.begin(5, s);
-            IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_pos.p, idx_world.p, list0.p, so, s));
+            IMIN_TRY(imin::launch_affected_select(out, ctl.p, idx_off.p, idx_ent.p, list0.p, so, s));
             timed.end(5, ev, s);
             st = launch_tiers(q, 0, 0, list0.p, out, start_tier, 0, last_tier());
         }

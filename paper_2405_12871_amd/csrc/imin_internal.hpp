@@ -259,16 +259,14 @@ hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s)
 struct SelectOut;
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
-                               const int32_t* idx_pos, const int32_t* idx_world, const SelectOut& so,
+                               const int2* idx_ent, const SelectOut& so,
                                hipStream_t s);
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
 // entries per node of the resident store; with gain non-null also the
 // from-scratch gains (gain[u] += every count of u)
 hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s);
-hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
-                             int32_t* idx_world, hipStream_t s);
-hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
-                                  const int32_t* idx_world, int32_t* list, const SelectOut& so, hipStream_t s);
+hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int2* idx_ent, hipStream_t s);
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int2* idx_ent, int32_t* list, const SelectOut& so, hipStream_t s);
 hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);

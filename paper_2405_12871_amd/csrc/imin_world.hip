@@ -1088,8 +1088,7 @@ __global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t th
 }
 
 // place (position, world) of each entry in its node's range
-__global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
-                                                       int32_t* idx_world) {
+__global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int2* idx_ent) {
     __shared__ IdxTable tb;
     const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
     if (w0 >= theta) return;
@@ -1125,8 +1124,7 @@ __global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t the
             const int32_t u = out.store_node[so + i];
             const int sl = tb.find(u);
             const int pos = (sl >= 0) ? tb.base[sl] + atomicAdd(&tb.cnt[sl], 1) : atomicAdd(&cursor[u], 1);
-            idx_pos[pos] = (int32_t)(so + i);
-            idx_world[pos] = (int32_t)w;
+            idx_ent[pos] = make_int2((int32_t)(so + i), (int32_t)w);
         }
     }
 }
@@ -1143,7 +1141,7 @@ __device__ __forceinline__ bool label_rule_holds(uint8_t wflags, uint32_t lab) {
 // Then the worlds whose entry for the new blocker u is live are listed in
 // list[0 .. list_n[0]) for the sampling tiers.
 __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
-                                                         const int32_t* idx_pos, const int32_t* idx_world,
+                                                         const int2* idx_ent,
                                                          int32_t* list, SelectOut so) {
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
@@ -1164,8 +1162,9 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
         const int k = i + lane;
         int32_t w = 0, c = 0;
         if (k < b) {
-            w = idx_world[k];
-            c = out.store_cnt[idx_pos[k]];
+            const int2 e = idx_ent[k];
+            w = e.y;
+            c = out.store_cnt[e.x];
         }
         const bool live = c > 0;
         const unsigned long long mr = __ballot(live);
@@ -1190,17 +1189,15 @@ hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, 
     return hipGetLastError();
 }
 
-hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int32_t* idx_pos,
-                             int32_t* idx_world, hipStream_t s) {
+hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int2* idx_ent, hipStream_t s) {
     const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
     if (blocks == 0) return hipSuccess;
-    k_index_fill<<<blocks, kIdxNT, 0, s>>>(out, theta, cursor, idx_pos, idx_world);
+    k_index_fill<<<blocks, kIdxNT, 0, s>>>(out, theta, cursor, idx_ent);
     return hipGetLastError();
 }
 
-hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int32_t* idx_pos,
-                                  const int32_t* idx_world, int32_t* list, const SelectOut& so, hipStream_t s) {
-    k_affected_select<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_pos, idx_world, list, so);
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int2* idx_ent, int32_t* list, const SelectOut& so, hipStream_t s) {
+    k_affected_select<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_ent, list, so);
     return hipGetLastError();
 }
 
@@ -1553,7 +1550,7 @@ struct ReplayShared {
 };
 
 __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                              const int32_t* idx_off, const int32_t* idx_pos, const int32_t* idx_world,
+                                              const int32_t* idx_off, const int2* idx_ent,
                                               int32_t ustar, ReplayShared& rs, uint32_t part, uint32_t parts) {
     static_assert(kReplaySlice <= kReplayNT, "one thread per entry of a slice");
     const int t = threadIdx.x;
@@ -1568,8 +1565,9 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
         if (t == 0) rs.lst_n = 0;
         __syncthreads();
         if (t < kReplaySlice && base + t < (long long)b) {
-            const int32_t pos = idx_pos[base + t];
-            const int32_t w = idx_world[base + t];
+            const int2 ie = idx_ent[base + t];
+            const int32_t pos = ie.x;
+            const int32_t w = ie.y;
             const int32_t c = out.store_cnt[pos];
             const uint32_t lab = out.store_lab ? out.store_lab[pos] : 0u;
             const uint8_t fl = out.world_flags ? out.world_flags[w] : (uint8_t)0;
@@ -1746,7 +1744,7 @@ __device__ __forceinline__ int rule_span(const TileOut& out, RuleSums& sums, siz
 
 template <int LANES>
 __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const int32_t* idx_off,
-                                            const int32_t* idx_pos, const int32_t* idx_world, int32_t ustar,
+                                            const int2* idx_ent, int32_t ustar,
                                             RuleShared& fs, uint32_t part, uint32_t parts) {
     static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
     constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
@@ -1770,15 +1768,17 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
     int k0 = a + (int)part * kGroups + group;
     RuleMeta m0{};
     if (k0 < b) {
-        m0.pos = idx_pos[k0];
-        m0.w = idx_world[k0];
+        const int2 e = idx_ent[k0];
+        m0.pos = e.x;
+        m0.w = e.y;
         rule_meta(out, m0);
     }
     int k1 = k0 + stride;
     int32_t p1 = 0, w1 = 0;
     if (k1 < b) {
-        p1 = idx_pos[k1];
-        w1 = idx_world[k1];
+        const int2 e = idx_ent[k1];
+        p1 = e.x;
+        w1 = e.y;
     }
     while (k0 < b) {
         // next entry's decision data, and the index of the one after
@@ -1791,8 +1791,9 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
             rule_meta(out, m1);
         }
         if (k2 < b) {
-            p2 = idx_pos[k2];
-            w2 = idx_world[k2];
+            const int2 e = idx_ent[k2];
+            p2 = e.x;
+            w2 = e.y;
         }
         const size_t so0 = (size_t)m0.off;
         const int L0 = m0.len;
@@ -1874,7 +1875,7 @@ union UpdateShared {
 template <int LANES>
 __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, RoundCtl* ctl, int32_t* next_list, TileOut out,
                                                              uint32_t rule_parts, const int32_t* idx_off,
-                                                             const int32_t* idx_pos, const int32_t* idx_world,
+                                                             const int2* idx_ent,
                                                              SelectOut so) {
     __shared__ UpdateShared u;
     if (ctl->stop) return;
@@ -1887,25 +1888,25 @@ __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, Round
     if (select_stops(r, so.k, bu, bg) || r + 1 == so.k) return;  // no further round (uniform)
     __syncthreads();  // the selection's LDS is reused below
     if (blockIdx.x < rule_parts)
-        rule_worlds<LANES>(ctl, out, idx_off, idx_pos, idx_world, bu, u.f, blockIdx.x, rule_parts);
+        rule_worlds<LANES>(ctl, out, idx_off, idx_ent, bu, u.f, blockIdx.x, rule_parts);
     else
-        replay_worlds(q, ctl, next_list, out, idx_off, idx_pos, idx_world, bu, u.r, blockIdx.x - rule_parts,
+        replay_worlds(q, ctl, next_list, out, idx_off, idx_ent, bu, u.r, blockIdx.x - rule_parts,
                       gridDim.x - rule_parts);
 }
 
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
-                               const int32_t* idx_pos, const int32_t* idx_world, const SelectOut& so,
+                               const int2* idx_ent, const SelectOut& so,
                                hipStream_t s) {
     const unsigned grid = (unsigned)(replay_parts + rule_parts);
     if (grid == 0 || replay_parts < 1) return hipErrorInvalidValue;
     const uint32_t rp = (uint32_t)rule_parts;
     if (lanes == 16)
-        k_round_update<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
+        k_round_update<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
     else if (lanes == 32)
-        k_round_update<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
+        k_round_update<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
     else
-        k_round_update<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_pos, idx_world, so);
+        k_round_update<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
     return hipGetLastError();
 }
 
