@@ -15,25 +15,41 @@ __device__ __forceinline__ bool better(int64_t g1, int32_t u1, int64_t g2, int32
     return g1 > g2 || (g1 == g2 && u1 < u2);
 }
 
-// Workgroup-wide best (gain, node) and sum of the lost-node counts (256 threads).
+// Workgroup-wide best (gain, node) and sum of the lost-node counts (256
+// threads; every thread gets the result): each wave reduces with lane
+// exchanges, then the four waves' results meet in LDS (sg, su, sd: four
+// entries each).
 __device__ __forceinline__ void select_block_best(int64_t& bg, int32_t& bu, long long& dl, int64_t* sg,
                                                   int32_t* su, long long* sd) {
-    sg[threadIdx.x] = bg;
-    su[threadIdx.x] = bu;
-    __syncthreads();
-    for (int d = 128; d >= 1; d >>= 1) {
-        if (threadIdx.x < d) {
-            const int o = threadIdx.x + d;
-            if (better(sg[o], su[o], sg[threadIdx.x], su[threadIdx.x])) {
-                sg[threadIdx.x] = sg[o];
-                su[threadIdx.x] = su[o];
-            }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        const int64_t og = __shfl_xor(bg, d, 64);
+        const int32_t ou = __shfl_xor(bu, d, 64);
+        dl += __shfl_xor(dl, d, 64);
+        if (better(og, ou, bg, bu)) {
+            bg = og;
+            bu = ou;
         }
-        __syncthreads();
     }
-    dl = block_sum_ll<256>(dl, sd);
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sg[wid] = bg;
+        su[wid] = bu;
+        sd[wid] = dl;
+    }
+    __syncthreads();
     bg = sg[0];
     bu = su[0];
+    dl = sd[0];
+#pragma unroll
+    for (int x = 1; x < 4; ++x) {
+        if (better(sg[x], su[x], bg, bu)) {
+            bg = sg[x];
+            bu = su[x];
+        }
+        dl += sd[x];
+    }
+    __syncthreads();  // the arrays may be reused
 }
 
 // Where a selection's parts are and where its results go.
