@@ -567,7 +567,8 @@ struct Session {
     // Resident store for incremental rounds: per-world offsets and lengths;
     // entries are allocated as round 0 produces them.
     imin_status_t enable_store(uint64_t theta) {
-        store_budget = env_size("IMIN_STORE_CAP", (size_t)1 << 30);
+        // the index keeps store positions as int32
+        store_budget = std::min<size_t>(env_size("IMIN_STORE_CAP", (size_t)1 << 30), (size_t)0x7FFFFFFF);
         if (store_off.alloc(theta) != hipSuccess || store_len.alloc(theta) != hipSuccess ||
             list0.alloc(theta) != hipSuccess) {
             store_off.release();
