@@ -1648,31 +1648,15 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
 // a live entry of a labelled world with a clear exit bit is updated by the
 // group in one pass over the world's entries.  The loads of the next entry
 // (index, then its count, label and world) are issued before the current
-// world's pass; smaller groups keep more worlds in flight per wave.  Each
-// entry's change depends only on its own count and label and on u's, so a
-// world longer than two passes of a group is split: the group takes the
-// first pass and queues the rest, which the workgroup's groups share once
-// every group is done with its entries.  The count changes of a
-// workgroup's worlds are summed in LDS and added to gain once per node per
-// workgroup.
+// world's pass; smaller groups keep more worlds in flight per wave.  The
+// count changes of a workgroup's worlds are summed in LDS and added to gain
+// once per node per workgroup.
 constexpr int kRuleUnroll = 8;
 using RuleSums = LdsSums<11>;
-
-constexpr int kRuleBigCap = 64;  // queued remainders of large worlds per workgroup
-
-// A large world's entries past its first span, left to the whole workgroup.
-struct RuleBig {
-    int64_t off;
-    int32_t len;
-    uint32_t lab;
-    int32_t cj;
-};
 
 struct RuleShared {
     RuleSums sums;
     unsigned long long red[4];
-    RuleBig big[kRuleBigCap];
-    uint32_t big_n;
 };
 
 // What is read of one index entry before deciding.
@@ -1748,13 +1732,11 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
                                             RuleShared& fs, uint32_t part, uint32_t parts) {
     static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
     constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
-    constexpr int kSpan = LANES * kRuleUnroll;  // entries a group takes in one pass
     const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
     if ((long long)a + (long long)part * kGroups >= (long long)b) return;  // no entry for this workgroup
     RuleSums& sums = fs.sums;
     sums.clear<kRuleNT>();
     if (threadIdx.x < 4) fs.red[threadIdx.x] = 0;
-    if (threadIdx.x == 0) fs.big_n = 0;
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int gl = lane % LANES;  // lane within the world's group
@@ -1802,19 +1784,7 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
         } else if (m0.off < 0 || L0 < 0 || so0 + (size_t)L0 > out.store_cap) {
             if (gl == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         } else {
-            // a world longer than two spans: the group takes the first span
-            // and leaves the rest to the whole workgroup
-            int L = L0;
-            if (L0 > 2 * kSpan) {
-                uint32_t at = 0;
-                if (gl == 0) at = atomicAdd(&fs.big_n, 1u);
-                at = __shfl(at, 0, LANES);
-                if (at < (uint32_t)kRuleBigCap) {
-                    if (gl == 0) fs.big[at] = RuleBig{m0.off, L0, m0.lab, m0.c};
-                    L = kSpan;
-                }
-            }
-            const int nd = rule_span<LANES>(out, sums, so0, 0, L, m0.lab, m0.c, gl, gmask);
+            const int nd = rule_span<LANES>(out, sums, so0, 0, L0, m0.lab, m0.c, gl, gmask);
             if (gl == 0) {
                 out.world_size[m0.w] = m0.wsize - m0.c;
                 acc_w += 1;
@@ -1831,17 +1801,7 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
         p1 = p2;
         w1 = w2;
     }
-    __syncthreads();
-    // the queued remainders, a span per group at a time
-    const uint32_t nbig = min(fs.big_n, (uint32_t)kRuleBigCap);
-    for (uint32_t qi = 0; qi < nbig; ++qi) {
-        const RuleBig bw = fs.big[qi];
-        int nd = 0;
-        for (int i0 = kSpan * (1 + group); i0 < bw.len; i0 += kSpan * kGroups)
-            nd += rule_span<LANES>(out, sums, (size_t)bw.off, i0, min(i0 + kSpan, bw.len), bw.lab, bw.cj, gl, gmask);
-        if (gl == 0) acc_b += 12ull * (unsigned long long)nd;
-    }
-    if (gl == 0 && (acc_w || acc_b)) {
+    if (gl == 0 && acc_w) {
         atomicAdd(&fs.red[0], acc_w);
         atomicAdd(&fs.red[1], acc_e);
         atomicAdd(&fs.red[2], acc_b);
