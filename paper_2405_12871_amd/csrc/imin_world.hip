@@ -1003,7 +1003,7 @@ constexpr int kIdxNT = 256;
 constexpr int kIdxSlotsLog = 12;
 constexpr int kIdxSlots = 1 << kIdxSlotsLog;
 constexpr int kIdxProbes = 32;
-constexpr uint32_t kIdxWorldsPerWG = 32;
+constexpr uint32_t kIdxWorldsPerWG = 64;
 
 struct IdxTable {
     int32_t keys[kIdxSlots];
@@ -1047,7 +1047,7 @@ struct IdxTable {
 // (the from-scratch gains of round 0, Section 2.2: the sum over worlds of
 // the nodes each candidate protects).  A node appears at most once per
 // world with a count below 2^24 (the node count), so the sums over a
-// workgroup's 32 worlds stay below 2^29: the base array, unused while
+// workgroup's 64 worlds stay below 2^30: the base array, unused while
 // counting, holds them.
 template <bool GAIN>
 __global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t theta, int32_t* cnt, int64_t* gain) {
