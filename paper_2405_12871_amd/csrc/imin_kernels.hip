@@ -402,7 +402,8 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
     __shared__ int64_t sg[256];
     __shared__ int32_t su[256];
     __shared__ long long sd[4];
-    if (ctl->stop) return;
+    // the stop flag is read with the first gains rather than before them
+    const int32_t stop = ctl->stop;
     int64_t bg = 0;
     int32_t bu = -1;
     // four candidates per thread in flight at a time
@@ -438,10 +439,11 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
         const int s1 = min(s0 + per, dsz_n);
         for (int i = s0 + (int)threadIdx.x; i < s1; i += 256) {
             dl += dsz[i];
-            dsz[i] = 0;
+            if (!stop) dsz[i] = 0;
         }
     }
     select_block_best(bg, bu, dl, sg, su, sd);
+    if (stop) return;  // uniform
     if (threadIdx.x == 0) {
         pg[blockIdx.x] = bg;
         pu[blockIdx.x] = bu;

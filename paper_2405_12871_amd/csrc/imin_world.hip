@@ -1538,8 +1538,7 @@ __device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t usta
 // replay workgroups find those worlds in the index themselves: workgroup
 // `part` of `parts` takes slices of kReplaySlice index entries of u (slice
 // part, part + parts, ...), lists in LDS the live entries the rule cannot
-// take and replays them one by one.  Small slices spread the replays of a
-// round over many workgroups.
+// take and replays them one by one.
 constexpr int kReplaySlice = 32;
 
 struct ReplayShared {
@@ -1549,17 +1548,65 @@ struct ReplayShared {
     uint32_t lst_n;
 };
 
+struct ReplayAcc {
+    unsigned long long w = 0, e = 0, b = 0, lw = 0, le = 0, lb = 0;
+    long long d = 0;
+};
+
+// Replay one listed world (every thread of the workgroup, uniform).
+__device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
+                                           int32_t ustar, const int4 e, ReplayShared& rs, ReplayAcc& acc) {
+    ReplayStoreT& st = rs.st;
+    WorldShared<kReplayNT>& sh = rs.sh;
+    const int t = threadIdx.x;
+    ReplayItem cur;
+    cur.w = e.y;
+    cur.store_off = out.store_off[e.y];
+    cur.store_len = out.store_len[e.y];
+    cur.xstore_off = out.xstore_off[e.y];
+    cur.xstore_len = out.xstore_len[e.y];
+    cur.world_size = out.world_size[e.y];
+    cur.j = (int32_t)((int64_t)e.x - cur.store_off);
+    cur.cj = e.z;
+    cur.labj = (uint32_t)e.w;
+    cur.flags = out.world_flags ? out.world_flags[e.y] : 0;
+    int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
+    uint32_t ed[kReplaySlots], act;
+    const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
+    if (how == 2) {
+        // the shortcut: reported with the label-based updates
+        acc.lw += 1;
+        acc.le += (unsigned long long)(cur.store_len + cur.xstore_len);
+        acc.lb += 37ull + 16ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len + 8ull;
+        acc.d += cur.cj;
+    } else if (how == 1) {
+        world_counts<kReplayNT>(q, ctl, st, sh);
+        world_labels<kReplayNT>(q, st, sh);
+        if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
+        const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
+        acc.w += 1;
+        acc.e += (unsigned long long)(cur.store_len + cur.xstore_len);
+        // index entry, count, label, the world's ranges, size and flags;
+        // entries and edges; the changes; the new size
+        acc.b += 37ull + 12ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
+                 12ull * (unsigned long long)nd + 8ull;
+        acc.d += (long long)cur.world_size - (long long)sh.count;
+    } else if (t == 0) {
+        const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
+        if (pos < out.next_cap) next_list[pos] = cur.w;
+        else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                              const int32_t* idx_off, const int2* idx_ent,
-                                              int32_t ustar, ReplayShared& rs, uint32_t part, uint32_t parts) {
+                                              const int32_t* idx_off, const int2* idx_ent, int32_t ustar,
+                                              ReplayShared& rs, uint32_t part, uint32_t parts) {
     static_assert(kReplaySlice <= kReplayNT, "one thread per entry of a slice");
     const int t = threadIdx.x;
     const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
     if ((long long)a + (long long)part * kReplaySlice >= (long long)b) return;  // no slice for this workgroup
-    ReplayStoreT& st = rs.st;
-    WorldShared<kReplayNT>& sh = rs.sh;
-    unsigned long long acc_w = 0, acc_e = 0, acc_b = 0, acc_lw = 0, acc_le = 0, acc_lb = 0;
-    long long acc_d = 0;
+    ReplayAcc acc;
     for (long long base = (long long)a + (long long)part * kReplaySlice; base < (long long)b;
          base += (long long)parts * kReplaySlice) {
         if (t == 0) rs.lst_n = 0;
@@ -1578,54 +1625,13 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
         }
         __syncthreads();
         const uint32_t nl = rs.lst_n;
-        for (uint32_t li = 0; li < nl; ++li) {
-            const int4 e = rs.lst[li];
-            ReplayItem cur;
-            cur.w = e.y;
-            cur.store_off = out.store_off[e.y];
-            cur.store_len = out.store_len[e.y];
-            cur.xstore_off = out.xstore_off[e.y];
-            cur.xstore_len = out.xstore_len[e.y];
-            cur.world_size = out.world_size[e.y];
-            cur.j = (int32_t)((int64_t)e.x - cur.store_off);
-            cur.cj = e.z;
-            cur.labj = (uint32_t)e.w;
-            cur.flags = out.world_flags ? out.world_flags[e.y] : 0;
-            int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
-            uint32_t ed[kReplaySlots], act;
-            const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
-            if (how == 2) {
-                // the shortcut: reported with the label-based updates
-                acc_lw += 1;
-                acc_le += (unsigned long long)(cur.store_len + cur.xstore_len);
-                acc_lb += 37ull + 16ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
-                          8ull;
-                acc_d += cur.cj;
-            } else if (how == 1) {
-                world_counts<kReplayNT>(q, ctl, st, sh);
-                world_labels<kReplayNT>(q, st, sh);
-                if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
-                const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
-                acc_w += 1;
-                acc_e += (unsigned long long)(cur.store_len + cur.xstore_len);
-                // index entry, count, label, the world's ranges, size and
-                // flags; entries and edges; the changes; the new size
-                acc_b += 37ull + 12ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len +
-                         12ull * (unsigned long long)nd + 8ull;
-                acc_d += (long long)cur.world_size - (long long)sh.count;
-            } else if (t == 0) {
-                const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
-                if (pos < out.next_cap) next_list[pos] = cur.w;
-                else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
-            }
-            __syncthreads();
-        }
+        for (uint32_t li = 0; li < nl; ++li) replay_one(q, ctl, next_list, out, ustar, rs.lst[li], rs, acc);
     }
     if (t == 0) {
-        add_work_at(out, 3, part, acc_w, acc_e, acc_b);
-        add_work_at(out, 5, part, acc_lw, acc_le, acc_lb);
+        add_work_at(out, 3, part, acc.w, acc.e, acc.b);
+        add_work_at(out, 5, part, acc.lw, acc.le, acc.lb);
         // T is lowered by the nodes the replayed worlds lost
-        if (acc_d) out.dsz[out.dsz_off[3] + part] = acc_d;
+        if (acc.d) out.dsz[out.dsz_off[3] + part] = acc.d;
     }
 }
 
@@ -1733,11 +1739,11 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
     static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
     constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
     const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
-    if ((long long)a + (long long)part * kGroups >= (long long)b) return;  // no entry for this workgroup
     RuleSums& sums = fs.sums;
-    sums.clear<kRuleNT>();
+    sums.clear<kRuleNT>();  // while u's index range is on its way
     if (threadIdx.x < 4) fs.red[threadIdx.x] = 0;
     __syncthreads();
+    if ((long long)a + (long long)part * kGroups >= (long long)b) return;  // no entry for this workgroup (uniform)
     const int lane = threadIdx.x & 63;
     const int gl = lane % LANES;  // lane within the world's group
     const int group = (int)threadIdx.x / LANES;
@@ -1838,12 +1844,15 @@ __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, Round
                                                              const int2* idx_ent,
                                                              SelectOut so) {
     __shared__ UpdateShared u;
-    if (ctl->stop) return;
+    // the stop flag, the round and the selection's parts are read together
+    // (the parts are always valid memory): one round trip, not three
+    const int32_t stop = ctl->stop;
+    const int r = ctl->round_snap;  // written by the partial launch; workgroup 0 updates ctl->round
     int64_t bg;
     int32_t bu;
     long long dl;
     select_combine(so, bg, bu, dl, u.sel.sg, u.sel.su, u.sel.sd);
-    const int r = ctl->round_snap;  // written by the partial launch; workgroup 0 updates ctl->round
+    if (stop) return;  // uniform
     if (blockIdx.x == 0 && threadIdx.x == 0) select_commit(ctl, so, r, bg, bu, dl);
     if (select_stops(r, so.k, bu, bg) || r + 1 == so.k) return;  // no further round (uniform)
     __syncthreads();  // the selection's LDS is reused below
