@@ -1544,7 +1544,7 @@ constexpr int kReplaySlice = 32;
 struct ReplayShared {
     ReplayStoreT st;
     WorldShared<kReplayNT> sh;
-    int4 lst[kReplaySlice];  // (store position, world, count, label) of u's entry
+    ReplayItem lst[kReplaySlice];  // the listed worlds
     uint32_t lst_n;
 };
 
@@ -1555,21 +1555,10 @@ struct ReplayAcc {
 
 // Replay one listed world (every thread of the workgroup, uniform).
 __device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                           int32_t ustar, const int4 e, ReplayShared& rs, ReplayAcc& acc) {
+                                           int32_t ustar, const ReplayItem& cur, ReplayShared& rs, ReplayAcc& acc) {
     ReplayStoreT& st = rs.st;
     WorldShared<kReplayNT>& sh = rs.sh;
     const int t = threadIdx.x;
-    ReplayItem cur;
-    cur.w = e.y;
-    cur.store_off = out.store_off[e.y];
-    cur.store_len = out.store_len[e.y];
-    cur.xstore_off = out.xstore_off[e.y];
-    cur.xstore_len = out.xstore_len[e.y];
-    cur.world_size = out.world_size[e.y];
-    cur.j = (int32_t)((int64_t)e.x - cur.store_off);
-    cur.cj = e.z;
-    cur.labj = (uint32_t)e.w;
-    cur.flags = out.world_flags ? out.world_flags[e.y] : 0;
     int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
     uint32_t ed[kReplaySlots], act;
     const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
@@ -1615,17 +1604,30 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
             const int2 ie = idx_ent[base + t];
             const int32_t pos = ie.x;
             const int32_t w = ie.y;
-            const int32_t c = out.store_cnt[pos];
-            const uint32_t lab = out.store_lab ? out.store_lab[pos] : 0u;
-            const uint8_t fl = out.world_flags ? out.world_flags[w] : (uint8_t)0;
-            if (c > 0 && !label_rule_holds(fl, lab)) {
+            // the world's record is read with u's entry, whether or not it
+            // is listed: one round trip
+            ReplayItem it;
+            it.w = w;
+            it.cj = out.store_cnt[pos];
+            it.labj = out.store_lab ? out.store_lab[pos] : 0u;
+            it.flags = out.world_flags ? out.world_flags[w] : (uint8_t)0;
+            it.store_off = out.store_off[w];
+            it.store_len = out.store_len[w];
+            it.xstore_off = out.xstore_off[w];
+            it.xstore_len = out.xstore_len[w];
+            it.world_size = out.world_size[w];
+            it.j = (int32_t)((int64_t)pos - it.store_off);
+            if (it.cj > 0 && !label_rule_holds((uint8_t)it.flags, it.labj)) {
                 const uint32_t at = atomicAdd(&rs.lst_n, 1u);
-                rs.lst[at] = make_int4(pos, w, c, (int)lab);
+                rs.lst[at] = it;
             }
         }
         __syncthreads();
         const uint32_t nl = rs.lst_n;
-        for (uint32_t li = 0; li < nl; ++li) replay_one(q, ctl, next_list, out, ustar, rs.lst[li], rs, acc);
+        for (uint32_t li = 0; li < nl; ++li) {
+            const ReplayItem cur = rs.lst[li];
+            replay_one(q, ctl, next_list, out, ustar, cur, rs, acc);
+        }
     }
     if (t == 0) {
         add_work_at(out, 3, part, acc.w, acc.e, acc.b);
