@@ -158,7 +158,10 @@ imin_status_t imin_cache_release(void);
 /*
  * Kernel timing, for measurement.  While enabled, the library brackets its
  * own kernel launches with HIP events on the stream they run on and adds
- * each launch's duration to a per-kernel tally (process-wide).  Kernel ids:
+ * each launch's duration to a per-kernel tally (process-wide).  The world
+ * kernels (ids 0, 1, 4, 6) take the events into their own launch
+ * (hipExtLaunchKernel), so that the interval is the kernel's alone; the
+ * others are bracketed by separate event records.  Kernel ids:
  *   0  world evaluation, small LDS tier (one wave per world)
  *   1  world evaluation, HBM tier (four waves per world, any size)
  *   2  gain reduction of a from-scratch pass (bucket histogram, scan,

@@ -85,6 +85,24 @@ struct TimedLaunches {
         if (e) record(e, s);
         return e;
     }
+    // Events for a launch that records them itself, around exactly its
+    // kernel (null when this launch is not timed); then taken() after it.
+    imin::LaunchEvents take(int id) {
+        imin::LaunchEvents ev;
+        if (!on || !((mask >> id) & 1u)) return ev;
+        const int64_t nth = g_timing.seen[id].fetch_add(1);
+        if (every > 1 && nth % every != 0) return ev;
+        ev.start = event_acquire();
+        ev.stop = ev.start ? event_acquire() : nullptr;
+        if (!ev.stop) {
+            event_release(ev.start);
+            ev.start = nullptr;
+        }
+        return ev;
+    }
+    void taken(int id, const imin::LaunchEvents& ev) {
+        if (ev.start) recs.push_back({id, ev.start, ev.stop});
+    }
     void end(int id, hipEvent_t a, hipStream_t s) {
         if (!on || !a) return;
         hipEvent_t e = event_acquire();
@@ -737,10 +755,12 @@ struct Session {
             const int count_idx = first ? first_idx : tier;
             int32_t* next_list = tier == 0 ? list1.p : list2.p;
             const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
-            hipEvent_t ev = timed.begin(timer_id, s);
-            IMIN_TRY(imin::launch_world_tier(tier, g, q, ctl.p, wb, first_list ? 0u : range, in_list, count_idx,
-                                             next_list, out, bs, tier == 0 ? grid0 : grid1, s));
-            timed.end(timer_id, ev, s);
+            const imin::LaunchEvents ev = timed.take(timer_id);
+            const hipError_t e = imin::launch_world_tier(tier, g, q, ctl.p, wb, first_list ? 0u : range, in_list,
+                                                         count_idx, next_list, out, bs, tier == 0 ? grid0 : grid1, s,
+                                                         ev);
+            timed.taken(timer_id, ev);
+            IMIN_TRY(e);
         }
         return IMIN_OK;
     }
@@ -758,10 +778,11 @@ struct Session {
             // live edge leaves the blocker's subtree lose it from their
             // labels; every other changed world is replayed, those too
             // large go on to sampling
-            hipEvent_t ev = timed.begin(6, s);
-            IMIN_TRY(imin::launch_round_update(q, ctl.p, list1.p, out, out.world_flags ? grid_l : 0, grid_r,
-                                               rule_lanes, idx_off.p, idx_ent.p, so, s));
-            timed.end(6, ev, s);
+            const imin::LaunchEvents ev = timed.take(6);
+            const hipError_t e = imin::launch_round_update(q, ctl.p, list1.p, out, out.world_flags ? grid_l : 0,
+                                                           grid_r, rule_lanes, idx_off.p, idx_ent.p, so, s, ev);
+            timed.taken(6, ev);
+            IMIN_TRY(e);
             // worlds the replay cannot hold are sampled again; when round 0
             // stored none, no world ever falls back and the tiers are not launched
             if (!replay_complete) st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());

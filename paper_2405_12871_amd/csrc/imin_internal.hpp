@@ -245,9 +245,18 @@ hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n
                               RoundCtl* ctl, hipStream_t s);
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s);
 hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s);
+// Events a launch records itself, around exactly its kernel (both null: an
+// ordinary launch).  Used to time a kernel without separate event packets
+// on the stream, whose own dispatch would be counted too.
+struct LaunchEvents {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
-                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s);
+                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s,
+                             const LaunchEvents& ev = LaunchEvents());
 hipError_t launch_sum_lengths(const int32_t* len, uint32_t count, unsigned long long* total, RoundCtl* ctl,
                               hipStream_t s);
 hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s);
@@ -259,8 +268,8 @@ hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s)
 struct SelectOut;
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
-                               const int2* idx_ent, const SelectOut& so,
-                               hipStream_t s);
+                               const int2* idx_ent, const SelectOut& so, hipStream_t s,
+                               const LaunchEvents& ev = LaunchEvents());
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
 // entries per node of the resident store; with gain non-null also the
 // from-scratch gains (gain[u] += every count of u)

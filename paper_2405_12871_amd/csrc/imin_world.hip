@@ -28,6 +28,8 @@
 // LDS store (up to 2048), and a four-wave workgroup whose per-world arrays
 // live in HBM (any size).  A world that outgrows a tier is redone by the next
 // one; every tier gives the same integers.
+#include <hip/hip_ext.h>
+
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
 #include "imin_select.hpp"
@@ -971,19 +973,29 @@ int world_tier_blocks_per_cu(int tier) {
     return b < 1 ? 1 : b;
 }
 
+// Launch kernel k on grid x block threads, with the kernel's own start and
+// stop timestamps in ev when given.
+template <class... P, class... A>
+hipError_t launch_k(void (*k)(P...), unsigned grid, unsigned block, hipStream_t s, const LaunchEvents& ev, A... a) {
+    if (ev.start)
+        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, ev.start, ev.stop, 0, a...);
+    else
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), 0, s, a...);
+    return hipGetLastError();
+}
+
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
-                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s) {
-    if (tier == 0) {
-        k_world_lds<kTier0NT, Tier0Store, 0><<<grid, kTier0NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
-                                                                       count_idx, next_list, out);
-    } else if (tier == 1) {
-        k_world_lds<kTier1NT, Tier1Store, 1><<<grid, kTier1NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list,
-                                                                       count_idx, next_list, out);
-    } else {
-        k_world_hbm<<<bs.n_slots, kTier2NT, 0, s>>>(g, q, ctl, w_begin, range_count, in_list, count_idx, out, bs);
-    }
-    return hipGetLastError();
+                             const TileOut& out, const BigSlots& bs, int grid, hipStream_t s,
+                             const LaunchEvents& ev) {
+    if (tier == 0)
+        return launch_k(k_world_lds<kTier0NT, Tier0Store, 0>, (unsigned)grid, kTier0NT, s, ev, g, q, ctl, w_begin,
+                        range_count, in_list, count_idx, next_list, out);
+    if (tier == 1)
+        return launch_k(k_world_lds<kTier1NT, Tier1Store, 1>, (unsigned)grid, kTier1NT, s, ev, g, q, ctl, w_begin,
+                        range_count, in_list, count_idx, next_list, out);
+    return launch_k(k_world_hbm, (unsigned)bs.n_slots, kTier2NT, s, ev, g, q, ctl, w_begin, range_count, in_list,
+                    count_idx, out, bs);
 }
 
 // ----------------------------------------------- incremental-round index
@@ -1867,18 +1879,15 @@ __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, Round
 
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
-                               const int2* idx_ent, const SelectOut& so,
-                               hipStream_t s) {
+                               const int2* idx_ent, const SelectOut& so, hipStream_t s, const LaunchEvents& ev) {
     const unsigned grid = (unsigned)(replay_parts + rule_parts);
     if (grid == 0 || replay_parts < 1) return hipErrorInvalidValue;
     const uint32_t rp = (uint32_t)rule_parts;
     if (lanes == 16)
-        k_round_update<16><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
-    else if (lanes == 32)
-        k_round_update<32><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
-    else
-        k_round_update<64><<<grid, kReplayNT, 0, s>>>(q, ctl, next_list, out, rp, idx_off, idx_ent, so);
-    return hipGetLastError();
+        return launch_k(k_round_update<16>, grid, kReplayNT, s, ev, q, ctl, next_list, out, rp, idx_off, idx_ent, so);
+    if (lanes == 32)
+        return launch_k(k_round_update<32>, grid, kReplayNT, s, ev, q, ctl, next_list, out, rp, idx_off, idx_ent, so);
+    return launch_k(k_round_update<64>, grid, kReplayNT, s, ev, q, ctl, next_list, out, rp, idx_off, idx_ent, so);
 }
 
 
