@@ -757,7 +757,7 @@ using Tier0Store = LdsStore<256, 9, 128, 30>;
 // in a from-scratch pass fits it again after any blockers are added
 using Tier1Store = LdsStore<2048, 12, 1024, 2050>;
 constexpr int kTier0NT = 64;
-constexpr uint32_t kSchedChunk = 8;  // worlds per update of a tier's work counter
+constexpr uint32_t kSchedChunk = 4;  // worlds per update of a tier's work counter
 constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
 

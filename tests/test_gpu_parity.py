@@ -273,6 +273,34 @@ def test_block_cache_reuse(B, oracle_mod):
         np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+@pytest.mark.parametrize("prob", [1.0, 0.6])
+@pytest.mark.parametrize("case", ["back_edge", "escape", "both"])
+def test_label_rule_exit_cases(B, oracle_mod, case, prob):
+    """Worlds built so that a blocker's dominator subtree has an edge back to
+    one of its dominators (the label rule still holds), an edge out to a
+    node it does not dominate (it must not: that node's dominator changes),
+    or both; every round matches the oracle."""
+    if case == "back_edge":
+        src, dst = [0, 1, 2, 3, 1, 4, 5], [1, 2, 3, 1, 4, 5, 4]
+        n = 6
+    elif case == "escape":
+        src, dst = [0, 0, 1, 3, 2, 4, 1, 5], [1, 2, 3, 4, 4, 6, 5, 6]
+        n = 7
+    else:
+        src = [0, 0, 1, 2, 3, 3, 4, 5, 5, 6, 7, 2, 8]
+        dst = [1, 2, 3, 4, 1, 5, 5, 6, 7, 4, 8, 8, 3]
+        n = 9
+    g = synth.from_edges(n, src, dst, [prob] * len(src))
+    seeds = np.array([0], np.int32)
+    _log(f"label rule exits {case} p={prob}")
+    res = B.solve(B.Graph.from_synth(g), seeds, n - 1, 300, 13)
+    want = oracle_mod.Query(g, seeds).solve(n - 1, 300, 13)
+    assert res.n_selected == want["n_selected"]
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 def test_example1_and_submodularity_graph(B):
     """The paper's worked example and the submodularity-ratio construction."""
     g = synth.from_edges(7, [0, 0, 1, 2, 3, 3, 5], [1, 2, 3, 3, 5, 6, 6], [1.0] * 7)
