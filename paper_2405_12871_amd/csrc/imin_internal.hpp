@@ -63,7 +63,6 @@ struct RoundCtl {
     unsigned long long xbig_count;   // extra edges bump-allocated this tile
     unsigned long long xtile_total;  // extra edges the tile's worlds wrote
     unsigned long long xstore_count; // extra edges held for replay
-    uint32_t pad2;
     uint32_t replay_big;             // some world stored in round 0 exceeds the replay's limits
 };
 
@@ -94,12 +93,13 @@ struct BigSlots {
 // World evaluations first write their (node, count) entries to a scratch
 // space with no shared counter: a tier-0 world at its own fixed slot
 // (wi * slot_cap0), a larger world at a bump-allocated place after big_base
-// (few and large, so the shared counter is cheap).  A compaction kernel then
-// packs the entries densely, with one counter update per workgroup.  In
-// incremental rounds a world writes its count changes into dl_* at its own
+// (few and large, so the shared counter is cheap).  With one tile for all
+// worlds that scratch is kept as the resident store; otherwise a compaction
+// kernel packs the entries densely, with one counter update per workgroup.
+// In incremental rounds a world's counts are updated in place, at its own
 // stored-list positions, which it alone owns.
-// A changed world of an incremental round with what its re-evaluation reads
-// first (gathered by the search for changed worlds).
+// A changed world of an incremental round with what its replay reads first
+// (gathered by the replay workgroup that lists it).
 struct ReplayItem {
     int64_t store_off;   // its (node, count, parent, label) entries
     int64_t xstore_off;  // its extra live edges (replay only)
@@ -197,12 +197,10 @@ struct CompactSpec {
     int nf;
     unsigned long long src_cap;
     unsigned long long dst_cap;
-    const int64_t* loc;       // source start per item (per world id when by_world)
-    const int32_t* len;       // entries per item (per world id when by_world)
-    int by_world;
-    const int32_t* list;      // items = list[0 .. ctl->list_n[0]) when set, else 0 .. count-1
-    uint32_t count;           // items, or the list's capacity when a list is set
-    uint32_t w_begin;
+    const int64_t* loc;       // source start per item
+    const int32_t* len;       // entries per item
+    uint32_t count;           // items: the tile's worlds 0 .. count-1
+    uint32_t w_begin;         // world id of item 0
     int counter_id;           // 0: pair_count, 1: store_count (+ pair_count), 2: xstore_count
     int64_t* out_off;         // per world id: where its entries went (optional)
     int32_t* out_len;

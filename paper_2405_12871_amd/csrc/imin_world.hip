@@ -874,11 +874,9 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
 }
 
 // ------------------------------------------------------------ compaction
-// Items are the tile's worlds [0, count) (entries at wloc/wlen in scratch) or,
-// in incremental rounds, the changed worlds of list[0 .. list_n[0]) (changes
-// at store_off[w] in dl_*, wlen[w] of them).  Each workgroup scans its
-// items' lengths, takes one range of the destination with one counter
-// update, and copies with one wave per item.
+// Items are the tile's worlds [0, count) (entries at wloc/wlen in scratch).
+// Each workgroup scans its items' lengths, takes one range of the
+// destination with one counter update, and copies with one wave per item.
 constexpr int kCompactNT = 256;
 
 __global__ __launch_bounds__(kCompactNT) void k_sum_lengths(const int32_t* len, uint32_t count,
@@ -898,7 +896,7 @@ __global__ __launch_bounds__(kCompactNT) void k_compact(CompactSpec sp, RoundCtl
     __shared__ unsigned long long dst_sh[kCompactNT];
     __shared__ int len_sh[kCompactNT];
     if (ctl->stop) return;
-    const uint32_t n_items = sp.list ? min(ctl->list_n[0], sp.count) : sp.count;
+    const uint32_t n_items = sp.count;
     unsigned long long* counter =
         sp.counter_id == 0 ? &ctl->pair_count : (sp.counter_id == 1 ? &ctl->store_count : &ctl->xstore_count);
     const int lane = threadIdx.x & 63;
@@ -909,10 +907,9 @@ __global__ __launch_bounds__(kCompactNT) void k_compact(CompactSpec sp, RoundCtl
         long long src = 0;
         uint32_t w = 0;
         if (i < n_items) {
-            w = sp.list ? (uint32_t)sp.list[i] : sp.w_begin + i;
-            const uint32_t key = sp.by_world ? w : i;
-            src = sp.loc[key];
-            len = sp.len[key];
+            w = sp.w_begin + i;
+            src = sp.loc[i];
+            len = sp.len[i];
             if (len < 0 || src < 0 || (unsigned long long)src + (unsigned long long)len > sp.src_cap) {
                 atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
                 len = 0;
