@@ -366,13 +366,14 @@ struct Session {
     int grid_l = 0;
     bool adopted = false;                  // the round-0 scratch serves as the store
     unsigned long long adopted_entries = 0;
-    bool index_counted = false;            // idx_off holds the entries per node
+    bool indexed = false;                  // idx_off / idx_ent hold the index
     int rule_lanes = 16;  // lanes per world in the label rule
     int grid_r = 0;
     bool incremental = false;
     size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
-    DevArray<int32_t> idx_off, idx_bsum, idx_cursor;
+    DevArray<int32_t> idx_off, idx_bcnt, idx_bbase, idx_bcur, idx_border;
+    DevArray<int4> idx_rec;  // the index build's entries grouped by bucket
     DevArray<int2> idx_ent;  // (store position, world) of each entry, grouped by node
     // level-0 slot groups of the seeds
     DevArray<int32_t> seed_cnt;
@@ -669,34 +670,40 @@ struct Session {
         return grow_store(arrs, used, used + more, store_budget);
     }
 
-    // entries per node of the resident store (the index's counts), and
-    // with gain_out the from-scratch gains of round 0 in the same pass
-    imin_status_t count_index(uint64_t theta, int64_t* gain_out) {
-        const size_t n = (size_t)g.n;
-        IMIN_TRY(idx_off.alloc(n + 1));
-        IMIN_TRY(imin::launch_fill_i32(idx_off.p, 0, n + 1, s));
-        imin::TileOut out = tile_out();
-        IMIN_TRY(imin::launch_index_count(out, (uint32_t)theta, idx_off.p, gain_out, s));
-        index_counted = true;
-        return IMIN_OK;
-    }
-
-    // node -> (store position, world) of every entry written in round 0;
-    // and the changed-world item lists of incremental rounds
-    imin_status_t build_index(uint64_t theta) {
+    // node -> (store position, world) of every entry written in round 0,
+    // for the incremental rounds; with gain_out also the from-scratch gains
+    // of round 0, from the same pass over the store.  Nodes are grouped in
+    // buckets of 2^IMIN_INDEX_BUCKET_LOG ids (default 10), widened until
+    // there are at most 8192 buckets.
+    imin_status_t build_index(uint64_t theta, int64_t* gain_out) {
+        if (indexed) return IMIN_OK;
         const unsigned long long entries = adopted ? adopted_entries : hctl.p->store_count;
-        const size_t n = (size_t)g.n;
-        if (!index_counted) {
-            const imin_status_t st = count_index(theta, nullptr);
-            if (st != IMIN_OK) return st;
-        }
-        IMIN_TRY(idx_bsum.alloc((n + 4095) / 4096 + 1));
-        IMIN_TRY(idx_cursor.alloc(n + 1));
+        if (entries > 0xFFFFFFFFull) return IMIN_ERR_INTERNAL;
+        const unsigned long long n = (unsigned long long)g.n;
+        int shift = (int)std::min<size_t>(std::max<size_t>(env_size("IMIN_INDEX_BUCKET_LOG", 10), 1), 30);
+        while (((n + (1ull << shift) - 1) >> shift) > 8192ull) ++shift;
+        const int nb = (int)((n + (1ull << shift) - 1) >> shift);
+        IMIN_TRY(idx_off.alloc(n + 1));
         IMIN_TRY(idx_ent.alloc(entries));
-        imin::TileOut out = tile_out();
-        IMIN_TRY(imin::launch_exclusive_scan(idx_off.p, (int)n, idx_bsum.p, s));
-        IMIN_TRY(hipMemcpyAsync(idx_cursor.p, idx_off.p, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-        IMIN_TRY(imin::launch_index_fill(out, (uint32_t)theta, idx_cursor.p, idx_ent.p, s));
+        IMIN_TRY(idx_bcnt.alloc((size_t)nb));
+        IMIN_TRY(idx_bbase.alloc((size_t)nb + 1));
+        IMIN_TRY(idx_bcur.alloc((size_t)nb));
+        IMIN_TRY(idx_border.alloc((size_t)nb));
+        IMIN_TRY(idx_rec.alloc(entries));
+        imin::IndexBufs ib{};
+        ib.shift = shift;
+        ib.nb = nb;
+        ib.bcnt = idx_bcnt.p;
+        ib.bbase = idx_bbase.p;
+        ib.bcur = idx_bcur.p;
+        ib.border = idx_border.p;
+        ib.rec = idx_rec.p;
+        ib.rec_cap = (uint32_t)entries;
+        ib.idx_off = idx_off.p;
+        ib.idx_ent = idx_ent.p;
+        ib.ent_cap = (uint32_t)entries;
+        IMIN_TRY(imin::launch_index_build(tile_out(), (uint32_t)theta, g.n, ib, gain_out, ctl.p, s));
+        indexed = true;
         return IMIN_OK;
     }
 
@@ -872,7 +879,7 @@ struct Session {
                 adopted = true;
                 adopted_entries = total;
                 hipEvent_t ev = timed.begin(2, s);
-                const imin_status_t st2 = count_index((uint64_t)count, gain.p);
+                const imin_status_t st2 = build_index((uint64_t)count, gain.p);
                 if (st2 != IMIN_OK) return st2;
                 timed.end(2, ev, s);
                 IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
@@ -1096,14 +1103,10 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
     const size_t batch0 = env_size("IMIN_ROUND_BATCH", 32);
     size_t batch = batch0;
     const imin::SelectOut so = ss.select_out(k, blockers, gains, spread_totals, n_selected);
-    bool indexed = false;
     for (int32_t r = 0; r <= k;) {
         if (r > 0 && ss.incremental) {
-            if (!indexed) {
-                st = ss.build_index((uint64_t)theta);
-                if (st != IMIN_OK) return st;
-                indexed = true;
-            }
+            st = ss.build_index((uint64_t)theta, nullptr);  // built once
+            if (st != IMIN_OK) return st;
             // incremental rounds need no host decision: enqueue a batch; once
             // the selection stops, every later kernel returns at once
             const int32_t nb = (int32_t)std::min<size_t>(batch, (size_t)(k + 1 - r));

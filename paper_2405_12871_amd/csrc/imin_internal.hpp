@@ -269,12 +269,26 @@ hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_l
                                const int2* idx_ent, const SelectOut& so, hipStream_t s,
                                const LaunchEvents& ev = LaunchEvents());
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
-// entries per node of the resident store; with gain non-null also the
-// from-scratch gains (gain[u] += every count of u)
-hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s);
-hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int2* idx_ent, hipStream_t s);
+// Buffers of the index build: nodes fall in nb buckets of 2^shift ids
+// (nb <= 8192, nb << shift >= n); rec and idx_ent hold every stored entry.
+struct IndexBufs {
+    int shift;
+    int nb;
+    int32_t* bcnt;   // [nb] entries per bucket
+    int32_t* bbase;  // [nb + 1] first entry of each bucket
+    int32_t* bcur;   // [nb] partition cursors
+    int32_t* border; // [nb] buckets by decreasing size class
+    int4* rec;       // [rec_cap] (position, world, node, count) grouped by bucket
+    uint32_t rec_cap;
+    int32_t* idx_off;  // [n + 1] first index entry of each node
+    int2* idx_ent;     // [ent_cap] (store position, world) grouped by node
+    uint32_t ent_cap;
+};
+// node -> (store position, world) of every entry of the resident store;
+// with gain non-null also the from-scratch gains (gain[u] += every count of u)
+hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, const IndexBufs& ib, int64_t* gain,
+                              RoundCtl* ctl, hipStream_t s);
 hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int2* idx_ent, int32_t* list, const SelectOut& so, hipStream_t s);
-hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,

@@ -327,67 +327,6 @@ hipError_t launch_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl, hi
 }
 
 // ------------------------------------------------ generic exclusive scan
-// data[0..count) -> exclusive prefix sums in place, data[count] = total.
-// Three passes: 4096-element blocks, a single-workgroup scan of the block
-// sums, and the carry-in add.  count <= 4096 * 4096.
-__global__ __launch_bounds__(1024) void k_xscan_blocks(int32_t* data, int count, int32_t* bsum) {
-    __shared__ int tmp[16];
-    const int base = blockIdx.x * 4096;
-    int v[4], loc = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = base + threadIdx.x * 4 + k;
-        v[k] = (i < count) ? data[i] : 0;
-        loc += v[k];
-    }
-    int tot;
-    int run = block_excl_scan<1024>(loc, tmp, tot);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int i = base + threadIdx.x * 4 + k;
-        if (i < count) data[i] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(1024) void k_xscan_sums(int32_t* bsum, int nblocks, int32_t* data, int count) {
-    __shared__ int tmp[16];
-    __shared__ int carry;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < nblocks; base += 1024) {
-        const int i = base + threadIdx.x;
-        const int v = (i < nblocks) ? bsum[i] : 0;
-        int tot;
-        const int ex = block_excl_scan<1024>(v, tmp, tot);
-        if (i < nblocks) bsum[i] = carry + ex;
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) data[count] = carry;
-}
-
-__global__ void k_xscan_add(int32_t* data, int count, const int32_t* bsum) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) data[i] += bsum[i / 4096];
-}
-
-hipError_t launch_exclusive_scan(int32_t* data, int count, int32_t* bsum, hipStream_t s) {
-    const int nblocks = (count + 4095) / 4096;
-    if (nblocks > 0) {
-        k_xscan_blocks<<<nblocks, 1024, 0, s>>>(data, count, bsum);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    k_xscan_sums<<<1, 1024, 0, s>>>(bsum, nblocks, data, count);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nblocks == 0) return e;
-    k_xscan_add<<<(count + 255) / 256, 256, 0, s>>>(data, count, bsum);
-    return hipGetLastError();
-}
-
 // ----------------------------------------------------------- selection
 // argmax over candidates (not seeds, not blocked) of (gain desc, id asc).
 // Two launches: every workgroup of the first reduces a slice of the

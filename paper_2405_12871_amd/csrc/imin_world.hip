@@ -1001,142 +1001,338 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
 // still live (count > 0): every other world keeps its reached set and its
 // dominator tree.
 
-// Hub nodes hold entries in most worlds, so counting and placing with one
-// global atomic per entry would serialise on their counters.  Each
-// workgroup takes a run of worlds, counts its entries per node in an LDS
-// table and touches a node's global counter once; placing, it reserves one
-// block of positions per node and hands them out in LDS.  A node that finds
-// no table slot (all of its probe slots taken) uses the global counter for
-// each of its entries.
-constexpr int kIdxNT = 256;
-constexpr int kIdxSlotsLog = 12;
-constexpr int kIdxSlots = 1 << kIdxSlotsLog;
-constexpr int kIdxProbes = 32;
-constexpr uint32_t kIdxWorldsPerWG = 64;
+// Building the index regroups world-major entries by node.  Nodes are cut
+// into buckets of 2^shift consecutive ids.  A histogram pass counts the
+// entries of each bucket, one workgroup turns the counts into bucket bases,
+// and a partition pass copies every entry, as a record (position, world,
+// node, count), into its bucket's range of a record array: each workgroup
+// reserves its share of a bucket with one counter update.  Then one
+// workgroup owns each bucket: it counts its nodes' entries (and sums their
+// counts into the gains) in LDS, scans the counts into the nodes' offsets,
+// and places the entries inside the bucket's range of the index, which is
+// the same range as in the record array.  A node's counters live in the
+// LDS of the one workgroup that owns it, so no per-node global counter is
+// ever updated and every index write lands in that workgroup's own range.
+constexpr int kIdxNT = 512;
+constexpr int kIdxMaxBuckets = 8192;
+constexpr uint32_t kIdxWorldsPerWG = 256;
+constexpr int kOwnNT = 1024;
+constexpr int kOwnSlots = 2048;  // nodes counted per pass over a bucket
 
-struct IdxTable {
-    int32_t keys[kIdxSlots];
-    int32_t cnt[kIdxSlots];
-    int32_t base[kIdxSlots];
-
-    __device__ void clear() {
-        for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
-            keys[i] = -1;
-            cnt[i] = 0;
-        }
+// The first 256 entries of a world (four per lane) from position so.
+template <bool CNT>
+__device__ __forceinline__ void load_world_head(const TileOut& out, long long so, int len, int lane, int32_t (&u)[4],
+                                                int32_t (&c)[4]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = lane + 64 * j;
+        u[j] = i < len ? out.store_node[so + i] : 0;
+        c[j] = (CNT && i < len) ? out.store_cnt[so + i] : 0;
     }
-    // slot of node u, claimed if new; -1 when none is free
-    __device__ int slot(int32_t u) {
-        const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - kIdxSlotsLog);
-        for (int p = 0; p < kIdxProbes; ++p) {
-            const int sl = (int)((h + (uint32_t)p) & (kIdxSlots - 1));
-            int32_t k = keys[sl];
-            if (k == -1) {
-                k = atomicCAS(&keys[sl], -1, u);
-                if (k == -1) return sl;
+}
+
+// Calls f(node, count, position, world) for every stored entry of the
+// worlds w0 + wave, w0 + wave + waves, ... below w1 taken by this wave.
+// The next world's first 256 entries, and the range of the world after
+// that, are loaded before f runs on the current world: a wave then waits
+// for memory about once per world, and stores made by f (which the same
+// in-order counter tracks) are not waited for by the next world's loads.
+template <int NT, bool CNT, typename F>
+__device__ __forceinline__ void for_stored_entries(const TileOut& out, uint32_t w0, uint32_t w1, F&& f) {
+    constexpr uint32_t kStep = NT / 64;
+    const int lane = threadIdx.x & 63;
+    uint32_t w = w0 + (threadIdx.x >> 6);
+    if (w >= w1) return;
+    long long so = out.store_off[w];
+    int len = out.store_len[w];
+    int32_t u[4], c[4];
+    load_world_head<CNT>(out, so, len, lane, u, c);
+    long long so_n = 0;
+    int len_n = 0;
+    if (w + kStep < w1) {
+        so_n = out.store_off[w + kStep];
+        len_n = out.store_len[w + kStep];
+    }
+    while (true) {
+        const uint32_t wn = w + kStep;
+        int32_t un[4], cn[4];
+        load_world_head<CNT>(out, so_n, len_n, lane, un, cn);
+        long long so_nn = 0;
+        int len_nn = 0;
+        if (wn + kStep < w1) {
+            so_nn = out.store_off[wn + kStep];
+            len_nn = out.store_len[wn + kStep];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = lane + 64 * j;
+            if (i < len) f(u[j], c[j], so + i, w);
+        }
+        for (int i0 = 256; i0 < len; i0 += 256) {  // worlds of more than 256 entries
+            int32_t ut[4], ct[4];
+            load_world_head<CNT>(out, so + i0, len - i0, lane, ut, ct);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = i0 + lane + 64 * j;
+                if (i < len) f(ut[j], ct[j], so + i, w);
             }
-            if (k == u) return sl;
         }
-        return -1;
-    }
-    // slot of node u if present (no claim)
-    __device__ int find(int32_t u) const {
-        const uint32_t h = ((uint32_t)u * 0x9E3779B1u) >> (32 - kIdxSlotsLog);
-        for (int p = 0; p < kIdxProbes; ++p) {
-            const int sl = (int)((h + (uint32_t)p) & (kIdxSlots - 1));
-            const int32_t k = keys[sl];
-            if (k == u) return sl;
-            if (k == -1) return -1;
+        if (wn >= w1) break;
+        w = wn;
+        so = so_n;
+        len = len_n;
+        so_n = so_nn;
+        len_n = len_nn;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            u[j] = un[j];
+            c[j] = cn[j];
         }
-        return -1;
     }
-};
+}
 
-// count entries per node; with GAIN also gain[u] += the entries' counts
-// (the from-scratch gains of round 0, Section 2.2: the sum over worlds of
-// the nodes each candidate protects).  A node appears at most once per
-// world with a count below 2^24 (the node count), so the sums over a
-// workgroup's 64 worlds stay below 2^30: the base array, unused while
-// counting, holds them.
+// entries per bucket
+__global__ __launch_bounds__(kIdxNT) void k_index_bucket_count(TileOut out, uint32_t theta, int shift, int nb,
+                                                              int32_t* bcnt, RoundCtl* ctl) {
+    __shared__ int32_t h[kIdxMaxBuckets];
+    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
+    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
+    for (int i = threadIdx.x; i < nb; i += kIdxNT) h[i] = 0;
+    __syncthreads();
+    bool bad = false;
+    for_stored_entries<kIdxNT, false>(out, w0, w1, [&](int32_t u, int32_t, long long, uint32_t) {
+        const uint32_t bk = (uint32_t)u >> shift;
+        if (bk < (uint32_t)nb) atomicAdd(&h[bk], 1);
+        else bad = true;
+    });
+    if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kIdxNT)
+        if (h[i]) atomicAdd(&bcnt[i], h[i]);
+}
+
+__device__ __forceinline__ int bucket_size_class(int v) { return v > 0 ? 32 - __clz(v) : 0; }
+
+// bucket bases: bbase[b] = entries of the buckets before b, bbase[nb] = all;
+// the partition's cursors start at the bases.  border lists the buckets by
+// decreasing size class (floor(log2(entries)) + 1), the order in which the
+// owning workgroups start.
+__global__ __launch_bounds__(1024) void k_index_bucket_scan(const int32_t* bcnt, int nb, int32_t* bbase,
+                                                           int32_t* bcur, int32_t* border) {
+    __shared__ int tmp[16];
+    __shared__ int cls[33];
+    if (threadIdx.x < 33) cls[threadIdx.x] = 0;
+    __syncthreads();
+    int run = 0;
+    for (int c0 = 0; c0 < nb; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const int v = i < nb ? bcnt[i] : 0;
+        int tot;
+        const int ex = block_excl_scan<1024>(v, tmp, tot);
+        if (i < nb) {
+            bbase[i] = run + ex;
+            bcur[i] = run + ex;
+            atomicAdd(&cls[bucket_size_class(v)], 1);
+        }
+        run += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bbase[nb] = run;
+        int start = 0;
+        for (int k = 32; k >= 0; --k) {
+            const int c = cls[k];
+            cls[k] = start;
+            start += c;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += 1024) border[atomicAdd(&cls[bucket_size_class(bcnt[i])], 1)] = i;
+}
+
+// records of the workgroup's worlds into their buckets' ranges
+__global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_t theta, int shift, int nb,
+                                                           int32_t* bcur, int4* rec, uint32_t rec_cap,
+                                                           RoundCtl* ctl) {
+    __shared__ int32_t h[kIdxMaxBuckets];
+    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
+    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
+    for (int i = threadIdx.x; i < nb; i += kIdxNT) h[i] = 0;
+    __syncthreads();
+    for_stored_entries<kIdxNT, false>(out, w0, w1, [&](int32_t u, int32_t, long long, uint32_t) {
+        const uint32_t bk = (uint32_t)u >> shift;
+        if (bk < (uint32_t)nb) atomicAdd(&h[bk], 1);
+    });
+    __syncthreads();
+    // the workgroup's share of each bucket
+    for (int i = threadIdx.x; i < nb; i += kIdxNT)
+        if (h[i]) h[i] = atomicAdd(&bcur[i], h[i]);
+    __syncthreads();
+    bool bad = false;
+    for_stored_entries<kIdxNT, true>(out, w0, w1, [&](int32_t u, int32_t c, long long pos, uint32_t w) {
+        const uint32_t bk = (uint32_t)u >> shift;
+        if (bk >= (uint32_t)nb) return;
+        const uint32_t r = (uint32_t)atomicAdd(&h[bk], 1);
+        if (r < rec_cap) rec[r] = make_int4((int32_t)pos, (int32_t)w, u, c);
+        else bad = true;
+    });
+    if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+}
+
+// The slot most lanes of a wave hold among those of lanes 0, 8, ..., 56
+// (held by at least two lanes), or -1; the same value on every lane.
+__device__ __forceinline__ int own_hot_slot(uint32_t d, bool ok) {
+    const int key = ok ? (int)d : -1;
+    int best = -1, best_n = 1;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int cand = __shfl(key, s * 8, 64);
+        const int m = __popcll(__ballot(cand >= 0 && key == cand));
+        if (m > best_n) {
+            best_n = m;
+            best = cand;
+        }
+    }
+    return best;
+}
+
+// One workgroup per bucket, largest buckets first: the nodes' entry counts
+// (and with GAIN the sums of the entries' counts: the from-scratch gains of
+// round 0, Section 2.2, added to gain[u]) in LDS, their offsets idx_off[u]
+// by a scan from the bucket's base, and each entry (position, world) at its
+// node's offset plus a rank handed out in LDS.  Buckets wider than the LDS
+// table take several passes over their records, one per slice of kOwnSlots
+// nodes.  A hub can hold a third of its bucket's entries, and lanes updating
+// one LDS counter are served one after another: each wave picks its most
+// common node (its hot slot) from its first records, keeps that node's
+// count and sum in registers while counting, and takes that node's ranks
+// with one counter update per instruction while placing.
 template <bool GAIN>
-__global__ __launch_bounds__(kIdxNT) void k_index_count(TileOut out, uint32_t theta, int32_t* cnt, int64_t* gain) {
-    __shared__ IdxTable tb;
-    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
-    if (w0 >= theta) return;
-    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
-    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
-        tb.keys[i] = -1;
-        tb.cnt[i] = 0;
-        tb.base[i] = 0;
+__global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t rec_cap, const int32_t* bbase,
+                                                     const int32_t* border, int nb, int shift, int32_t n,
+                                                     int32_t* idx_off, int2* idx_ent, uint32_t ent_cap,
+                                                     int64_t* gain, RoundCtl* ctl) {
+    __shared__ int32_t cnt[kOwnSlots];
+    __shared__ unsigned long long gs[GAIN ? kOwnSlots : 1];
+    __shared__ int tmp[kOwnNT / 64];
+    const int b = border[blockIdx.x];
+    if (b < 0 || b >= nb) {  // the order is a permutation of the buckets
+        if (threadIdx.x == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+        return;
     }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
-        const size_t so = (size_t)out.store_off[w];
-        const int len = out.store_len[w];
-        for (int i = lane; i < len; i += 64) {
-            const int32_t u = out.store_node[so + i];
-            const int32_t c = GAIN ? out.store_cnt[so + i] : 0;
-            const int sl = tb.slot(u);
-            if (sl >= 0) {
-                atomicAdd(&tb.cnt[sl], 1);
-                if (GAIN) atomicAdd(&tb.base[sl], c);
-            } else {
-                atomicAdd(&cnt[u], 1);
-                if (GAIN) atomicAdd((unsigned long long*)&gain[u], (unsigned long long)(long long)c);
+    // records [r0, r1) (within rec_cap even if the partition overflowed)
+    const uint32_t r0 = min((uint32_t)bbase[b], rec_cap), r1 = min((uint32_t)bbase[b + 1], rec_cap);
+    const int32_t lo = (int32_t)((long long)b << shift);
+    const int32_t hi = (int32_t)min((long long)n, (long long)lo + (1ll << shift));
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    int32_t run = (int32_t)r0;
+    bool bad = false;
+    for (int32_t sub = lo; sub < hi; sub += kOwnSlots) {
+        const int ns = min(kOwnSlots, hi - sub);
+        for (int i = t; i < kOwnSlots; i += kOwnNT) {
+            cnt[i] = 0;
+            if (GAIN) gs[i] = 0;
+        }
+        __syncthreads();
+        int hot = -1;
+        int hot_n = 0;
+        unsigned long long hot_s = 0;
+        for (uint32_t q = r0; q < r1; q += 4 * kOwnNT) {
+            int4 e[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t r = q + t + j * kOwnNT;
+                e[j] = r < r1 ? rec[r] : make_int4(0, 0, -1, 0);
+            }
+            if (q == r0) hot = own_hot_slot((uint32_t)(e[0].z - sub), r0 + t < r1 && (uint32_t)(e[0].z - sub) < (uint32_t)ns);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t d = (uint32_t)(e[j].z - sub);
+                if (q + t + j * kOwnNT < r1 && d < (uint32_t)ns) {
+                    if ((int)d == hot) {
+                        ++hot_n;
+                        if (GAIN) hot_s += (uint32_t)e[j].w;
+                    } else {
+                        atomicAdd(&cnt[d], 1);
+                        if (GAIN) atomicAdd(&gs[d], (unsigned long long)(uint32_t)e[j].w);
+                    }
+                }
             }
         }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
-        const int32_t u = tb.keys[i];
-        if (u < 0) continue;
-        atomicAdd(&cnt[u], tb.cnt[i]);
-        if (GAIN) atomicAdd((unsigned long long*)&gain[u], (unsigned long long)(long long)tb.base[i]);
-    }
-}
-
-// place (position, world) of each entry in its node's range
-__global__ __launch_bounds__(kIdxNT) void k_index_fill(TileOut out, uint32_t theta, int32_t* cursor, int2* idx_ent) {
-    __shared__ IdxTable tb;
-    const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
-    if (w0 >= theta) return;
-    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
-    tb.clear();
-    __syncthreads();
-    // local counts only: entries of nodes without a slot take global positions below
-    {
-        const int lane = threadIdx.x & 63;
-        for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
-            const size_t so = (size_t)out.store_off[w];
-            const int len = out.store_len[w];
-            for (int i = lane; i < len; i += 64) {
-                const int sl = tb.slot(out.store_node[so + i]);
-                if (sl >= 0) atomicAdd(&tb.cnt[sl], 1);
+        if (hot >= 0) {  // the same on every lane of the wave
+#pragma unroll
+            for (int k = 32; k >= 1; k >>= 1) {
+                hot_n += __shfl_xor(hot_n, k, 64);
+                if (GAIN) hot_s += __shfl_xor(hot_s, k, 64);
+            }
+            if (lane == 0 && hot_n) {
+                atomicAdd(&cnt[hot], hot_n);
+                if (GAIN) atomicAdd(&gs[hot], hot_s);
             }
         }
-    }
-    __syncthreads();
-    // one block of positions per node, handed out locally
-    for (int i = threadIdx.x; i < kIdxSlots; i += kIdxNT) {
-        if (tb.keys[i] >= 0) {
-            tb.base[i] = atomicAdd(&cursor[tb.keys[i]], tb.cnt[i]);
-            tb.cnt[i] = 0;
+        __syncthreads();
+        // two consecutive slots per thread
+        const int a0 = cnt[2 * t], a1 = cnt[2 * t + 1];
+        int tot;
+        const int32_t o0 = run + block_excl_scan<kOwnNT>(a0 + a1, tmp, tot);
+        const int32_t o1 = o0 + a0;
+        cnt[2 * t] = o0;
+        cnt[2 * t + 1] = o1;
+        if (2 * t < ns) {
+            idx_off[sub + 2 * t] = o0;
+            if (GAIN) gain[sub + 2 * t] += (int64_t)gs[2 * t];
         }
-    }
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (uint32_t w = w0 + (threadIdx.x >> 6); w < w1; w += kIdxNT / 64) {
-        const size_t so = (size_t)out.store_off[w];
-        const int len = out.store_len[w];
-        for (int i = lane; i < len; i += 64) {
-            const int32_t u = out.store_node[so + i];
-            const int sl = tb.find(u);
-            const int pos = (sl >= 0) ? tb.base[sl] + atomicAdd(&tb.cnt[sl], 1) : atomicAdd(&cursor[u], 1);
-            idx_ent[pos] = make_int2((int32_t)(so + i), (int32_t)w);
+        if (2 * t + 1 < ns) {
+            idx_off[sub + 2 * t + 1] = o1;
+            if (GAIN) gain[sub + 2 * t + 1] += (int64_t)gs[2 * t + 1];
         }
+        run += tot;
+        __syncthreads();
+        // the next records are loaded before this batch's stores, which
+        // the loads would otherwise wait for (one in-order counter)
+        int4 e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t r = r0 + t + j * kOwnNT;
+            e[j] = r < r1 ? rec[r] : make_int4(0, 0, -1, 0);
+        }
+        for (uint32_t q = r0; q < r1; q += 4 * kOwnNT) {
+            int4 en[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t r = q + 4 * kOwnNT + t + j * kOwnNT;
+                en[j] = r < r1 ? rec[r] : make_int4(0, 0, -1, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t d = (uint32_t)(e[j].z - sub);
+                const bool ok = q + t + j * kOwnNT < r1 && d < (uint32_t)ns;
+                const bool is_hot = ok && (int)d == hot;
+                const unsigned long long m = __ballot(is_hot);
+                uint32_t p = 0;
+                if (m) {
+                    const int leader = __ffsll((long long)m) - 1;
+                    uint32_t base = 0;
+                    if (lane == leader) base = (uint32_t)atomicAdd(&cnt[hot], __popcll(m));
+                    base = __shfl(base, leader, 64);
+                    p = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                }
+                if (ok && !is_hot) p = (uint32_t)atomicAdd(&cnt[d], 1);
+                if (ok) {
+                    if (p < ent_cap) idx_ent[p] = make_int2(e[j].x, e[j].y);
+                    else bad = true;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) e[j] = en[j];
+        }
+        __syncthreads();
     }
+    if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+    if (b == nb - 1 && t == 0) idx_off[n] = run;
 }
+static_assert(kOwnSlots == 2 * kOwnNT, "the offset scan takes two slots per thread");
 
 // Whether the label rule updates a world for the new blocker: the world is
 // labelled and the blocker's exit bit is clear.
@@ -1188,20 +1384,28 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     }
 }
 
-hipError_t launch_index_count(const TileOut& out, uint32_t theta, int32_t* cnt, int64_t* gain, hipStream_t s) {
-    const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
-    if (blocks == 0) return hipSuccess;
+hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, const IndexBufs& ib, int64_t* gain,
+                              RoundCtl* ctl, hipStream_t s) {
+    if (ib.nb < 1 || ib.nb > kIdxMaxBuckets || ((long long)ib.nb << ib.shift) < (long long)n) return hipErrorInvalidValue;
+    const unsigned groups = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
+    hipError_t e = launch_fill_i32(ib.bcnt, 0, (size_t)ib.nb, s);
+    if (e != hipSuccess) return e;
+    if (groups > 0) {
+        k_index_bucket_count<<<groups, kIdxNT, 0, s>>>(out, theta, ib.shift, ib.nb, ib.bcnt, ctl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    k_index_bucket_scan<<<1, 1024, 0, s>>>(ib.bcnt, ib.nb, ib.bbase, ib.bcur, ib.border);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (groups > 0) {
+        k_index_partition<<<groups, kIdxNT, 0, s>>>(out, theta, ib.shift, ib.nb, ib.bcur, ib.rec, ib.rec_cap, ctl);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     if (gain)
-        k_index_count<true><<<blocks, kIdxNT, 0, s>>>(out, theta, cnt, gain);
+        k_index_own<true><<<(unsigned)ib.nb, kOwnNT, 0, s>>>(ib.rec, ib.rec_cap, ib.bbase, ib.border, ib.nb, ib.shift, n, ib.idx_off,
+                                                              ib.idx_ent, ib.ent_cap, gain, ctl);
     else
-        k_index_count<false><<<blocks, kIdxNT, 0, s>>>(out, theta, cnt, nullptr);
-    return hipGetLastError();
-}
-
-hipError_t launch_index_fill(const TileOut& out, uint32_t theta, int32_t* cursor, int2* idx_ent, hipStream_t s) {
-    const unsigned blocks = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
-    if (blocks == 0) return hipSuccess;
-    k_index_fill<<<blocks, kIdxNT, 0, s>>>(out, theta, cursor, idx_ent);
+        k_index_own<false><<<(unsigned)ib.nb, kOwnNT, 0, s>>>(ib.rec, ib.rec_cap, ib.bbase, ib.border, ib.nb, ib.shift, n, ib.idx_off,
+                                                               ib.idx_ent, ib.ent_cap, nullptr, ctl);
     return hipGetLastError();
 }
 

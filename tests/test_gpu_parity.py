@@ -221,6 +221,26 @@ def test_solve_round_variants(B, oracle_mod, monkeypatch, variant):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+@pytest.mark.parametrize("tiles", [False, True])
+@pytest.mark.parametrize("bucket_log", ["1", "13"])
+def test_index_bucket_widths(B, oracle_mod, monkeypatch, bucket_log, tiles):
+    """The node index (and, with one tile, the round-0 gains computed with
+    it) built with buckets of 2 node ids (2500 buckets) or of 8192 ids (one
+    bucket counted in three slices of at most 2048 nodes), from one tile of
+    worlds or from several, gives the oracle's selection."""
+    monkeypatch.setenv("IMIN_INDEX_BUCKET_LOG", bucket_log)
+    if tiles:
+        monkeypatch.setenv("IMIN_TILE_WORLDS", "211")
+    g = synth.random_small_graph(5000, 20000, seed=123, prob="wc")
+    seeds = np.array([7, 1234, 4999], np.int32)
+    _log(f"solve with index buckets of 2^{bucket_log} ids, tiles={tiles}")
+    res = B.solve(B.Graph.from_synth(g), seeds, 10, 600, 9)
+    want = oracle_mod.Query(g, seeds).solve(10, 600, 9)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 @pytest.mark.parametrize("case", ["uniform", "multi", "binary"])
 def test_solve_replay_mixed_world_sizes(B, oracle_mod, case):
     """Worlds from a few nodes to over a thousand: changed worlds are either
