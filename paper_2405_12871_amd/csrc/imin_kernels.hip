@@ -343,43 +343,43 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
     __shared__ long long sd[4];
     // the stop flag is read with the first gains rather than before them
     const int32_t stop = ctl->stop;
+    // nodes lost by the changed worlds of the round: this part's slots,
+    // loaded with the gains
+    long long dl = 0;
+    if (dsz) {
+        const int per = (dsz_n + (int)gridDim.x - 1) / (int)gridDim.x;
+        const int s0 = (int)blockIdx.x * per;
+        const int s1 = min(s0 + per, dsz_n);
+        for (int i = s0 + (int)threadIdx.x; i < s1; i += 256) dl += dsz[i];
+    }
     int64_t bg = 0;
     int32_t bu = -1;
-    // four candidates per thread in flight at a time
-    const int32_t stride = (int32_t)gridDim.x * 256;
-    int32_t u = (int32_t)blockIdx.x * 256 + (int32_t)threadIdx.x;
-    for (; (int64_t)u + 3 * (int64_t)stride < n; u += 4 * stride) {
-        int64_t gv[4];
-        uint32_t ex[4];
+    // eight candidates per thread in flight at a time (all of a 2^20-node
+    // graph's in one pass with 512 parts)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t u0 = (int64_t)blockIdx.x * 256 + threadIdx.x; u0 < n; u0 += 8 * stride) {
+        int64_t gv[8];
+        uint32_t ex[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            gv[j] = gain[u + j * stride];
-            ex[j] = excl[(uint32_t)(u + j * stride) >> 5];
+        for (int j = 0; j < 8; ++j) {
+            const int64_t v = u0 + j * stride;
+            gv[j] = v < n ? gain[v] : 0;
+            ex[j] = v < n ? excl[(uint32_t)v >> 5] : ~0u;
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int32_t v = u + j * stride;
+        for (int j = 0; j < 8; ++j) {
+            const int32_t v = (int32_t)(u0 + j * stride);
             if (!((ex[j] >> ((uint32_t)v & 31u)) & 1u) && better(gv[j], v, bg, bu)) {
                 bg = gv[j];
                 bu = v;
             }
         }
     }
-    for (; u < n; u += stride) {
-        if (bit_set(excl, u)) continue;
-        const int64_t gv = gain[u];
-        if (better(gv, u, bg, bu)) { bg = gv; bu = u; }
-    }
-    // nodes lost by the changed worlds of the round: this part's slots
-    long long dl = 0;
-    if (dsz) {
+    if (dsz && !stop) {
         const int per = (dsz_n + (int)gridDim.x - 1) / (int)gridDim.x;
         const int s0 = (int)blockIdx.x * per;
         const int s1 = min(s0 + per, dsz_n);
-        for (int i = s0 + (int)threadIdx.x; i < s1; i += 256) {
-            dl += dsz[i];
-            if (!stop) dsz[i] = 0;
-        }
+        for (int i = s0 + (int)threadIdx.x; i < s1; i += 256) dsz[i] = 0;
     }
     select_block_best(bg, bu, dl, sg, su, sd);
     if (stop) return;  // uniform

@@ -72,12 +72,30 @@ __device__ __forceinline__ void select_combine(const SelectOut& so, int64_t& bg,
     bg = 0;
     bu = -1;
     dl = 0;
-    for (int i = threadIdx.x; i < so.parts; i += 256) {
-        if (better(so.pg[i], so.pu[i], bg, bu)) {
-            bg = so.pg[i];
-            bu = so.pu[i];
+    // two parts per thread loaded before either is compared (512 parts in
+    // one pass)
+    for (int i0 = threadIdx.x; i0 < so.parts; i0 += 512) {
+        const int i1 = i0 + 256;
+        const int64_t g0 = so.pg[i0];
+        const int32_t u0 = so.pu[i0];
+        const long long d0 = so.pd[i0];
+        int64_t g1 = 0;
+        int32_t u1 = -1;
+        long long d1 = 0;
+        if (i1 < so.parts) {
+            g1 = so.pg[i1];
+            u1 = so.pu[i1];
+            d1 = so.pd[i1];
         }
-        dl += so.pd[i];
+        if (better(g0, u0, bg, bu)) {
+            bg = g0;
+            bu = u0;
+        }
+        if (better(g1, u1, bg, bu)) {
+            bg = g1;
+            bu = u1;
+        }
+        dl += d0 + d1;
     }
     select_block_best(bg, bu, dl, sg, su, sd);
 }
