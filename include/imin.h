@@ -195,9 +195,9 @@ imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_m
 
 /*
  * Work done while timing was enabled, per world tier (0 small LDS, 1 large
- * LDS, 2 HBM, 3 replay, 4 label-based update by the workgroups that take one
- * world per wave, 5 label-based update of worlds handed to the replay that
- * reduce to it): worlds finished, edges walked (for tiers 4 and 5: stored
+ * LDS, 2 HBM, 3 replay, 4 label-based update by the label-rule workgroups,
+ * which take a world per 16, 32 or 64 lanes, 5 label-based update of worlds
+ * handed to the replay that reduce to it): worlds finished, edges walked (for tiers 4 and 5: stored
  * entries scanned) and algorithmic HBM
  * bytes.  For tiers 0-2 the edges are the CSR slots of the reached rows (the
  * edges whose coins were needed) and the bytes are 8 per such slot (column

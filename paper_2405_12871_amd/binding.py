@@ -272,8 +272,8 @@ def timing_read(kernel_id: int):
 
 def timing_work(tier: int):
     """(worlds, edges walked, algorithmic bytes) of one world tier (0-2 sampled
-    tiers, 3 replay, 4 label rule by the one-world-per-wave workgroups, 5 label
-    rule by the replay workgroups) since the last reset."""
+    tiers, 3 replay, 4 label rule by the label-rule workgroups, 5 label rule by
+    the replay workgroups) since the last reset."""
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().imin_timing_work(int(tier), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return int(a.value), int(b.value), int(c.value)

@@ -26,7 +26,7 @@ thread_local uint32_t g_last_flags = 0;
 
 // ---- optional per-kernel timing with HIP events
 constexpr int kTimedKernels = 8;
-constexpr int kWorkTiers = 6;  // tiers 0-2, replay, label rule (one world per wave), label rule (replay workgroups)
+constexpr int kWorkTiers = 6;  // tiers 0-2, replay, label rule (rule workgroups), label rule (replay workgroups)
 struct Timing {
     std::atomic<bool> on{false};
     std::atomic<uint32_t> mask{0xFFFFFFFFu};  // kernels bracketed with events

@@ -1150,32 +1150,104 @@ __global__ __launch_bounds__(1024) void k_index_bucket_scan(const int32_t* bcnt,
     for (int i = threadIdx.x; i < nb; i += 1024) border[atomicAdd(&cls[bucket_size_class(bcnt[i])], 1)] = i;
 }
 
-// records of the workgroup's worlds into their buckets' ranges
+// records of the workgroup's worlds into their buckets' ranges.  The
+// workgroup's entries, numbered flat over its worlds, go in batches of
+// kPartStage: each batch is counted per bucket in LDS, its share of every
+// bucket reserved with one counter update, the records staged in LDS
+// bucket by bucket, and each bucket's run written out to consecutive
+// addresses (scattered 16-byte stores would cost one transaction each).
+constexpr int kPartStage = 4096;
+static_assert(kIdxWorldsPerWG <= (uint32_t)kIdxNT, "one world range per thread");
+static_assert(kPartStage % kIdxNT == 0, "whole records per thread");
+
+size_t index_partition_lds(int nb) {
+    return (size_t)kPartStage * sizeof(int4) + kIdxWorldsPerWG * sizeof(long long) +
+           (kIdxWorldsPerWG + 1) * sizeof(int32_t) + 2 * (size_t)nb * sizeof(int32_t);
+}
+
 __global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_t theta, int shift, int nb,
                                                            int32_t* bcur, int4* rec, uint32_t rec_cap,
                                                            RoundCtl* ctl) {
-    __shared__ int32_t h[kIdxMaxBuckets];
+    extern __shared__ int4 part_lds[];
+    int4* stage = part_lds;                                                      // [kPartStage]
+    long long* woff = reinterpret_cast<long long*>(stage + kPartStage);          // [worlds]
+    int32_t* wpre = reinterpret_cast<int32_t*>(woff + kIdxWorldsPerWG);         // [worlds + 1]
+    int32_t* bnum = wpre + kIdxWorldsPerWG + 1;                                  // [nb] count, then base
+    int32_t* bdel = bnum + nb;                                                   // [nb] global - local
+    __shared__ int tmp[kIdxNT / 64];
+    constexpr int kPer = kPartStage / kIdxNT;
+    const int t = threadIdx.x;
     const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
-    const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
-    for (int i = threadIdx.x; i < nb; i += kIdxNT) h[i] = 0;
-    __syncthreads();
-    for_stored_entries<kIdxNT, false>(out, w0, w1, [&](int32_t u, int32_t, long long, uint32_t) {
-        const uint32_t bk = (uint32_t)u >> shift;
-        if (bk < (uint32_t)nb) atomicAdd(&h[bk], 1);
-    });
-    __syncthreads();
-    // the workgroup's share of each bucket
-    for (int i = threadIdx.x; i < nb; i += kIdxNT)
-        if (h[i]) h[i] = atomicAdd(&bcur[i], h[i]);
+    const int nw = (int)(min(theta, w0 + kIdxWorldsPerWG) - w0);
+    int len = 0;
+    if (t < nw) {
+        woff[t] = out.store_off[w0 + t];
+        len = max(out.store_len[w0 + t], 0);
+    }
+    int total;
+    const int ex = block_excl_scan<kIdxNT>(len, tmp, total);
+    if (t <= nw) wpre[t] = ex;  // wpre[nw] = total
     __syncthreads();
     bool bad = false;
-    for_stored_entries<kIdxNT, true>(out, w0, w1, [&](int32_t u, int32_t c, long long pos, uint32_t w) {
-        const uint32_t bk = (uint32_t)u >> shift;
-        if (bk >= (uint32_t)nb) return;
-        const uint32_t r = (uint32_t)atomicAdd(&h[bk], 1);
-        if (r < rec_cap) rec[r] = make_int4((int32_t)pos, (int32_t)w, u, c);
-        else bad = true;
-    });
+    for (int k0 = 0; k0 < total; k0 += kPartStage) {
+        const int k1 = min(total, k0 + kPartStage);
+        for (int i = t; i < nb; i += kIdxNT) bnum[i] = 0;
+        __syncthreads();
+        int32_t ru[kPer], rc[kPer], rp[kPer], rw[kPer], rr[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            const int k = k0 + t + j * kIdxNT;
+            ru[j] = -1;
+            rc[j] = rp[j] = rw[j] = rr[j] = 0;
+            if (k < k1) {
+                // the world holding flat entry k: wpre[lo] <= k < wpre[lo + 1]
+                int lo = 0, hi = nw;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (wpre[mid] <= k) lo = mid;
+                    else hi = mid;
+                }
+                const long long pos = woff[lo] + (k - wpre[lo]);
+                rp[j] = (int32_t)pos;
+                rw[j] = (int32_t)(w0 + (uint32_t)lo);
+                ru[j] = out.store_node[pos];
+                rc[j] = out.store_cnt[pos];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (ru[j] < 0) continue;
+            const uint32_t bk = (uint32_t)ru[j] >> shift;
+            if (bk < (uint32_t)nb) rr[j] = atomicAdd(&bnum[bk], 1);
+            else ru[j] = -1;
+        }
+        __syncthreads();
+        // local bases, and the batch's share of each bucket
+        const int per = (nb + kIdxNT - 1) / kIdxNT;
+        const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+        int sum = 0;
+        for (int bk = b0; bk < b1; ++bk) sum += bnum[bk];
+        int staged;
+        int base = block_excl_scan<kIdxNT>(sum, tmp, staged);
+        for (int bk = b0; bk < b1; ++bk) {
+            const int c = bnum[bk];
+            bnum[bk] = base;
+            if (c) bdel[bk] = atomicAdd(&bcur[bk], c) - base;
+            base += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (ru[j] >= 0) stage[bnum[(uint32_t)ru[j] >> shift] + rr[j]] = make_int4(rp[j], rw[j], ru[j], rc[j]);
+        __syncthreads();
+        for (int i = t; i < staged; i += kIdxNT) {
+            const int4 r = stage[i];
+            const uint32_t g = (uint32_t)(bdel[(uint32_t)r.z >> shift] + i);
+            if (g < rec_cap) rec[g] = r;
+            else bad = true;
+        }
+        __syncthreads();
+    }
     if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
 }
 
@@ -1397,7 +1469,11 @@ hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, con
     k_index_bucket_scan<<<1, 1024, 0, s>>>(ib.bcnt, ib.nb, ib.bbase, ib.bcur, ib.border);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (groups > 0) {
-        k_index_partition<<<groups, kIdxNT, 0, s>>>(out, theta, ib.shift, ib.nb, ib.bcur, ib.rec, ib.rec_cap, ctl);
+        const size_t lds = index_partition_lds(ib.nb);
+        if ((e = hipFuncSetAttribute((const void*)k_index_partition, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds)) != hipSuccess)
+            return e;
+        k_index_partition<<<groups, kIdxNT, lds, s>>>(out, theta, ib.shift, ib.nb, ib.bcur, ib.rec, ib.rec_cap, ctl);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (gain)
