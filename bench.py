@@ -16,6 +16,12 @@ The line also carries the from-scratch round-0 rate, the solve latency
 percentiles, the roofline of the world-evaluation kernel (HIP events on the
 library's stream, over every launch of the run) and the CPU oracle's rate on
 a bounded sample.
+
+With ``--many N`` it measures instead a batch of N mixed queries on the same
+graph (|S| uniform in 10..500, k uniform in 10..200, theta 10^4 or 10^5, each
+with its own coin key): solved one after another on one stream, then side by
+side on ``--streams`` streams (``imin_solve_many``), with the results of the
+two runs checked to be identical; one JSON line with both rates.
 """
 from __future__ import annotations
 
@@ -109,6 +115,47 @@ def cpu_baseline(g, seeds, k, theta, budget_s):
             "seconds": dt}, res["blockers"]
 
 
+def run_many(args, binding, G, n):
+    """Batch throughput: the same mixed queries sequentially and side by side."""
+    import numpy as np
+    import torch
+
+    rs = np.random.default_rng(0xB0)
+    queries = []
+    for _ in range(args.many):
+        seeds = rs.choice(n, size=int(rs.integers(10, 501)), replace=False).astype(np.int32)
+        queries.append((seeds, int(rs.integers(10, 201)), int(rs.choice([10_000, 100_000])),
+                        int(rs.integers(0, 1 << 62))))
+    log(f"{len(queries)} queries; warm-up")
+    binding.solve_many(G, queries[:min(len(queries), 2 * args.streams)], n_streams=args.streams)
+    torch.cuda.synchronize()
+    runs = {}
+    for label, streams in (("sequential", 1), ("side_by_side", args.streams)):
+        t0 = time.perf_counter()
+        res = binding.solve_many(G, queries, n_streams=streams)
+        torch.cuda.synchronize()
+        runs[label] = (time.perf_counter() - t0, res)
+        log(f"{label}: {runs[label][0] * 1e3:.1f} ms on {streams} stream(s)")
+    (t_seq, seq), (t_par, par) = runs["sequential"], runs["side_by_side"]
+    same = all(np.array_equal(a.blockers, b.blockers) and np.array_equal(a.gains, b.gains) and
+               np.array_equal(a.spread_totals, b.spread_totals) for a, b in zip(seq, par))
+    print(json.dumps({
+        "metric": "greedy IMIN queries/s, mixed batch on one graph",
+        "value": len(queries) / t_par,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "dtype": "u32+int64",
+        "config": {"workload": f"{args.workload} graph, {len(queries)} queries: |S|~U{{10..500}}, "
+                               f"k~U{{10..200}}, theta in {{1e4, 1e5}}", "streams": args.streams},
+        "sequential_queries_per_s": len(queries) / t_seq,
+        "speedup_over_sequential": t_seq / t_par,
+        "identical_to_sequential": bool(same),
+        "blockers_selected": int(sum(r.n_selected for r in par)),
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +165,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB copy first (counter scaling)")
+    ap.add_argument("--many", type=int, default=0, help="measure a batch of this many mixed queries instead")
+    ap.add_argument("--streams", type=int, default=4, help="streams for --many")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the estimator would shard "
@@ -148,6 +197,10 @@ def main():
     torch.cuda.synchronize()
     ingest_ms = (time.perf_counter() - t0) * 1e3
     log(f"graph ingest {ingest_ms:.2f} ms")
+
+    if args.many > 0:
+        run_many(args, binding, G, g.n)
+        return
 
     if args.copy_probe:
         # a plain copy of known size, for scaling HBM byte counters

@@ -113,6 +113,47 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
                          int64_t* gains, int64_t* spread_totals, int32_t* n_selected);
 
 /*
+ * One query of imin_solve_many: the arguments of imin_solve (device arrays,
+ * the same meaning and sizes) and, written by the call, the query's own
+ * status and device flags (imin_last_device_flags of its solve).
+ */
+typedef struct imin_query {
+    const int32_t* seeds;
+    int32_t n_seeds;
+    int32_t k;
+    int64_t theta;
+    uint64_t rng_seed;
+    int32_t* blockers;
+    int64_t* gains;
+    int64_t* spread_totals;
+    int32_t* n_selected;
+    int32_t status;         /* out: an imin_status_t */
+    uint32_t device_flags;  /* out */
+} imin_query_t;
+
+/*
+ * imin_solve_many -- several independent greedy selections on one graph
+ * (each as imin_solve), run side by side: one host thread per stream (at
+ * most n_queries), each taking the next unstarted query and solving it on
+ * its own stream.  An incremental round of one query is a chain of short
+ * dependent launches that leaves most of the GPU idle, so queries on
+ * different streams overlap.  Every query's worlds are keyed by its own
+ * rng_seed, so each result is identical to the query's imin_solve alone.
+ *
+ *   queries    host array of n_queries entries (n_queries >= 0); each
+ *              entry's status and device_flags are written
+ *   streams    host array of n_streams hipStream_t (as void*), n_streams >= 1;
+ *              the streams must be distinct, on the graph's device
+ *
+ * The device arrays of a query must be ready on the host's side of every
+ * stream (e.g. the device synchronised after they were written).  Returns
+ * IMIN_OK when every query succeeded, else the status of the first failing
+ * query (by index); IMIN_ERR_INVALID for bad arguments (no query is run).
+ */
+imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_queries, void* const* streams,
+                              int32_t n_streams);
+
+/*
  * imin_evaluate -- one pass of the estimator (Section 2.2: sample worlds,
  * build each world's dominator tree under the super-source, measure every
  * subtree) over the worlds [w_begin, w_begin + w_count) with a given blocked

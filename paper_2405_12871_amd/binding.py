@@ -24,6 +24,14 @@ STATUS_NAMES = {0: "IMIN_OK", 1: "IMIN_ERR_INVALID", 2: "IMIN_ERR_DATA", 3: "IMI
 _lib = None
 
 
+class Query(ctypes.Structure):
+    """One entry of imin_solve_many (imin_query_t)."""
+    _fields_ = [("seeds", ctypes.c_void_p), ("n_seeds", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("theta", ctypes.c_int64), ("rng_seed", ctypes.c_uint64), ("blockers", ctypes.c_void_p),
+                ("gains", ctypes.c_void_p), ("spread_totals", ctypes.c_void_p), ("n_selected", ctypes.c_void_p),
+                ("status", ctypes.c_int32), ("device_flags", ctypes.c_uint32)]
+
+
 class IminError(RuntimeError):
     def __init__(self, status: int, message: str, flags: int = 0):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message} (device flags 0x{flags:x})")
@@ -57,6 +65,8 @@ def load():
     lib.imin_graph_info.restype = st
     lib.imin_solve.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P]
     lib.imin_solve.restype = st
+    lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32]
+    lib.imin_solve_many.restype = st
     lib.imin_evaluate.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P, P, P, P, P]
     lib.imin_evaluate.restype = st
     lib.imin_status_string.argtypes = [st]
@@ -197,6 +207,50 @@ def solve(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> SolveResult
     r = int(ns.cpu()[0])
     return SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
                        spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=int(theta))
+
+
+def solve_many(graph: Graph, queries, n_streams: int = 4, raise_on_error: bool = True):
+    """Several selections on one graph side by side (imin_solve_many).
+
+    ``queries`` is a sequence of (seeds, k, theta, rng_seed).  Returns one
+    SolveResult per query, each equal to solve() of that query alone.  A
+    failing query raises IminError (naming the query) or, with
+    ``raise_on_error=False``, takes an IminError in its place in the list.
+    """
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    n = len(queries)
+    arr = (Query * max(n, 1))()
+    keep = []
+    for i, (seeds, k, theta, rng_seed) in enumerate(queries):
+        s = _dev(seeds, torch.int32, dev)
+        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
+               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
+               torch.zeros(k + 1, dtype=torch.int64, device=dev),
+               torch.zeros(1, dtype=torch.int32, device=dev))
+        keep.append((s, out, int(theta)))
+        arr[i] = Query(s.data_ptr(), int(s.numel()), int(k), int(theta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF,
+                       out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), 0, 0)
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, min(int(n_streams), n)))]
+    handles = (ctypes.c_void_p * len(streams))(*[st.cuda_stream for st in streams])
+    torch.cuda.synchronize(dev)  # inputs and zeroed outputs are ready for every stream
+    with torch.cuda.device(dev):
+        lib.imin_solve_many(graph.handle, arr, n, handles, len(streams))
+    results = []
+    for i, (s, (b, g, t, ns), theta) in enumerate(keep):
+        status = int(arr[i].status)
+        if status != IMIN_OK:
+            err = IminError(status, f"query {i}: " + lib.imin_status_string(status).decode(),
+                            int(arr[i].device_flags))
+            if raise_on_error:
+                raise err
+            results.append(err)
+            continue
+        r = int(ns.cpu()[0])
+        results.append(SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
+                                   spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=theta))
+    return results
 
 
 def evaluate(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blocked=(),

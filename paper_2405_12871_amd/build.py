@@ -27,7 +27,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     """Compile every source and link the shared library; returns its path."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+    cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared", "-pthread",
            "-Wall", "-I", INCLUDE, "-I", CSRC, *DEVICE_FLAGS]
     cmd += [os.path.join(CSRC, s) for s in SOURCES]
     cmd += ["-o", tmp]

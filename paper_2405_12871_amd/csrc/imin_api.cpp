@@ -9,6 +9,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 #include <cstdio>
 #include <cstdlib>
@@ -1165,6 +1166,57 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     st = ss.read_ctl();
     if (st != IMIN_OK) return st;
     ss.finish();
+    return IMIN_OK;
+}
+
+imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_queries, void* const* streams,
+                              int32_t n_streams) {
+    if (!g || n_queries < 0 || (n_queries > 0 && !queries) || n_streams < 1 || !streams) return IMIN_ERR_INVALID;
+    for (int32_t i = 0; i < n_streams; ++i)
+        for (int32_t j = 0; j < i; ++j)
+            if (streams[i] == streams[j]) return IMIN_ERR_INVALID;
+    for (int32_t q = 0; q < n_queries; ++q) {
+        queries[q].status = (int32_t)IMIN_ERR_INTERNAL;  // until the query has run
+        queries[q].device_flags = 0;
+    }
+    std::atomic<int32_t> next{0};
+    auto work = [&](int32_t i) {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if (prev != g->device) (void)hipSetDevice(g->device);
+        for (;;) {
+            const int32_t q = next.fetch_add(1);
+            if (q >= n_queries) break;
+            imin_query_t& Q = queries[q];
+            Q.status = (int32_t)imin_solve(g, Q.seeds, Q.n_seeds, Q.k, Q.theta, Q.rng_seed, streams[i], Q.blockers,
+                                           Q.gains, Q.spread_totals, Q.n_selected);
+            Q.device_flags = g_last_flags;
+        }
+        if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
+    };
+    const int32_t workers = std::min(n_streams, n_queries);
+    if (workers <= 1) {
+        work(0);
+    } else {
+        // a thread that cannot be started leaves its stream unused; the
+        // calling thread then takes stream 0's part of the queue itself
+        std::vector<std::thread> pool;
+        pool.reserve((size_t)workers);
+        for (int32_t i = 1; i < workers; ++i) {
+            try {
+                pool.emplace_back(work, i);
+            } catch (...) {
+                break;
+            }
+        }
+        work(0);
+        for (std::thread& th : pool) th.join();
+    }
+    for (int32_t q = 0; q < n_queries; ++q)
+        if (queries[q].status != (int32_t)IMIN_OK) {
+            g_last_flags = queries[q].device_flags;
+            return (imin_status_t)queries[q].status;
+        }
     return IMIN_OK;
 }
 

@@ -1083,8 +1083,7 @@ __device__ __forceinline__ void for_stored_entries(const TileOut& out, uint32_t 
         len = len_n;
         so_n = so_nn;
         len_n = len_nn;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 4; ++j) {  // register moves (unrolled by the compiler)
             u[j] = un[j];
             c[j] = cn[j];
         }

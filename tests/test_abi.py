@@ -49,4 +49,14 @@ def test_host_argument_checks(lib):
     assert lib.imin_solve(None, dummy, 1, 1, 10, 0, None, dummy, dummy, dummy, dummy) == 1
     assert lib.imin_evaluate(None, dummy, 1, None, 0, 0, 10, 0, None, dummy, dummy, None, None, None) == 1
     assert lib.imin_graph_info(None, None, None) == 1
+    # imin_solve_many: NULL graph, no stream, a stream named twice, bad counts
+    q = (binding.Query * 1)()
+    s1 = (ctypes.c_void_p * 2)(0x10, 0x20)
+    s2 = (ctypes.c_void_p * 2)(0x10, 0x10)
+    assert lib.imin_solve_many(None, q, 1, s1, 2) == 1
+    assert lib.imin_solve_many(dummy, q, 1, s1, 0) == 1
+    assert lib.imin_solve_many(dummy, q, 1, None, 1) == 1
+    assert lib.imin_solve_many(dummy, q, 1, s2, 2) == 1
+    assert lib.imin_solve_many(dummy, q, -1, s1, 2) == 1
+    assert lib.imin_solve_many(dummy, None, 1, s1, 2) == 1
     assert lib.imin_graph_destroy(None) == 0

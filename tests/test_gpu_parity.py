@@ -270,6 +270,46 @@ def test_solve_small_workload(B, oracle_mod):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+@pytest.mark.parametrize("n_streams", [1, 3])
+def test_solve_many_equals_each_query_alone(B, oracle_mod, n_streams):
+    """Queries with different seed sets, budgets, world counts and coin keys
+    solved side by side on several streams give each query's own oracle
+    selection."""
+    g = synth.random_small_graph(2000, 8000, seed=55, prob="wc")
+    G = B.Graph.from_synth(g)
+    rs = np.random.default_rng(7)
+    queries = []
+    for _ in range(5):
+        seeds = rs.choice(2000, size=int(rs.integers(1, 20)), replace=False).astype(np.int32)
+        queries.append((seeds, int(rs.integers(1, 12)), int(rs.choice([300, 700, 1500])), int(rs.integers(0, 1 << 40))))
+    _log(f"solve_many, {len(queries)} queries on {n_streams} streams")
+    res = B.solve_many(G, queries, n_streams=n_streams)
+    for (seeds, k, theta, rng), r in zip(queries, res):
+        want = oracle_mod.Query(g, seeds).solve(k, theta, rng)
+        np.testing.assert_array_equal(r.blockers, want["blockers"])
+        np.testing.assert_array_equal(r.gains, want["gains"])
+        np.testing.assert_array_equal(r.spread_totals, want["spread_totals"])
+
+
+def test_solve_many_reports_each_query(B, oracle_mod):
+    """A query with a repeated seed fails with a data error of its own; the
+    others are solved."""
+    g = synth.random_small_graph(300, 1500, seed=77, prob="wc")
+    G = B.Graph.from_synth(g)
+    good = (np.array([3, 30, 111], np.int32), 6, 400, 5)
+    bad = (np.array([3, 3], np.int32), 6, 400, 5)
+    _log("solve_many with a failing query")
+    res = B.solve_many(G, [good, bad, good], n_streams=2, raise_on_error=False)
+    assert isinstance(res[1], B.IminError) and res[1].status == 2 and "query 1" in str(res[1])
+    want = oracle_mod.Query(g, good[0]).solve(6, 400, 5)
+    for r in (res[0], res[2]):
+        np.testing.assert_array_equal(r.blockers, want["blockers"])
+        np.testing.assert_array_equal(r.spread_totals, want["spread_totals"])
+    with pytest.raises(B.IminError) as ei:
+        B.solve_many(G, [good, bad], n_streams=2)
+    assert ei.value.status == 2
+
+
 def test_block_cache_reuse(B, oracle_mod):
     """Scratch blocks handed back to the cache and reused by later calls
     (holding a previous call's contents), then freed and allocated afresh,
