@@ -135,7 +135,7 @@ typedef struct imin_query {
  * imin_solve_many -- several independent greedy selections on one graph
  * (each as imin_solve), run side by side: one host thread per stream (at
  * most n_queries), each taking the next unstarted query and solving it on
- * its own stream.  An incremental round of one query is a chain of short
+ * its own stream.  Queries start in decreasing order of theta * (k + 1).  An incremental round of one query is a chain of short
  * dependent launches that leaves most of the GPU idle, so queries on
  * different streams overlap.  Every query's worlds are keyed by its own
  * rng_seed, so each result is identical to the query's imin_solve alone.

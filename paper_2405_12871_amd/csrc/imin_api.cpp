@@ -1179,15 +1179,24 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
         queries[q].status = (int32_t)IMIN_ERR_INTERNAL;  // until the query has run
         queries[q].device_flags = 0;
     }
+    // largest first (theta * (k + 1) bounds a query's work), so that a long
+    // query does not start last and stretch the batch
+    std::vector<int32_t> order((size_t)n_queries);
+    for (int32_t q = 0; q < n_queries; ++q) order[(size_t)q] = q;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        const double wa = (double)queries[a].theta * ((double)queries[a].k + 1.0);
+        const double wb = (double)queries[b].theta * ((double)queries[b].k + 1.0);
+        return wa > wb;
+    });
     std::atomic<int32_t> next{0};
     auto work = [&](int32_t i) {
         int prev = -1;
         (void)hipGetDevice(&prev);
         if (prev != g->device) (void)hipSetDevice(g->device);
         for (;;) {
-            const int32_t q = next.fetch_add(1);
-            if (q >= n_queries) break;
-            imin_query_t& Q = queries[q];
+            const int32_t j = next.fetch_add(1);
+            if (j >= n_queries) break;
+            imin_query_t& Q = queries[order[(size_t)j]];
             Q.status = (int32_t)imin_solve(g, Q.seeds, Q.n_seeds, Q.k, Q.theta, Q.rng_seed, streams[i], Q.blockers,
                                            Q.gains, Q.spread_totals, Q.n_selected);
             Q.device_flags = g_last_flags;
