@@ -22,6 +22,12 @@ graph (|S| uniform in 10..500, k uniform in 10..200, theta 10^4 or 10^5, each
 with its own coin key): solved one after another on one stream, then side by
 side on ``--streams`` streams (``imin_solve_many``), with the results of the
 two runs checked to be identical; one JSON line with both rates.
+
+With ``--serve N`` it replays N queries arriving at ``--rate`` per second
+(exponential gaps; |S| uniform in 10..1000, k uniform in 10..500, theta
+5*10^4) against a server on ``--streams`` streams (``imin_server_*``), and
+reports the latency percentiles from arrival to result next to those of a
+single queue served one query at a time (each query's time measured alone).
 """
 from __future__ import annotations
 
@@ -156,6 +162,88 @@ def run_many(args, binding, G, n):
     }))
 
 
+def run_serve(args, binding, G, n):
+    """Latency under arrivals: the server against one-at-a-time service."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    rs = np.random.default_rng(0x5E)
+    queries = []
+    for _ in range(args.serve):
+        seeds = rs.choice(n, size=int(rs.integers(10, 1001)), replace=False).astype(np.int32)
+        queries.append((seeds, int(rs.integers(10, 501)), 50_000, int(rs.integers(0, 1 << 62))))
+    arrivals = np.cumsum(rs.exponential(1.0 / args.rate, size=len(queries)))
+    # each query alone: its service time and its result
+    log(f"{len(queries)} queries at {args.rate}/s; solving each alone")
+    binding.solve_many(G, queries[:2], n_streams=1)
+    alone, service = [], []
+    for q in queries:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alone.append(binding.solve_many(G, [q], n_streams=1)[0])
+        service.append(time.perf_counter() - t0)
+    # one queue, one query at a time
+    free, seq_lat = 0.0, []
+    for a, sv in zip(arrivals, service):
+        free = max(free, a) + sv
+        seq_lat.append(free - a)
+    # the server, queries submitted at their arrival times
+    log(f"serving on {args.streams} streams")
+    srv = binding.Server(G, n_streams=args.streams)
+    finish, results = {}, {}
+    tickets = {}
+    lock = threading.Lock()
+    submitted = threading.Semaphore(0)  # next() only while a query is outstanding
+
+    def collect():
+        for _ in range(len(queries)):
+            submitted.acquire()
+            t, r = srv.next()
+            now = time.perf_counter()
+            with lock:
+                i = tickets.pop(t)
+            finish[i] = now
+            results[i] = r
+
+    waiter = threading.Thread(target=collect)
+    start = time.perf_counter()
+    for i, (q, a) in enumerate(zip(queries, arrivals)):
+        delay = start + a - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        with lock:
+            tickets[srv.submit(*q)] = i
+        submitted.release()
+        if i == 0:
+            waiter.start()
+    waiter.join()
+    srv.close()
+    lat = [finish[i] - (start + arrivals[i]) for i in range(len(queries))]
+    same = all(not isinstance(results[i], Exception) and
+               np.array_equal(results[i].blockers, alone[i].blockers) and
+               np.array_equal(results[i].spread_totals, alone[i].spread_totals) for i in range(len(queries)))
+    span = max(finish.values()) - start
+    print(json.dumps({
+        "metric": "greedy IMIN query latency under Poisson arrivals, p50/p99",
+        "value": percentile(lat, 50) * 1e3,
+        "unit": "ms (p50)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "data": "synthetic",
+        "dtype": "u32+int64",
+        "config": {"workload": f"{args.workload} graph, {len(queries)} queries at {args.rate}/s: "
+                               f"|S|~U{{10..1000}}, k~U{{10..500}}, theta=5e4", "streams": args.streams},
+        "p50_ms": percentile(lat, 50) * 1e3,
+        "p99_ms": percentile(lat, 99) * 1e3,
+        "throughput_queries_per_s": len(queries) / span,
+        "one_at_a_time": {"p50_ms": percentile(seq_lat, 50) * 1e3, "p99_ms": percentile(seq_lat, 99) * 1e3,
+                          "mean_service_ms": float(np.mean(service)) * 1e3},
+        "identical_to_alone": bool(same),
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,7 +254,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB copy first (counter scaling)")
     ap.add_argument("--many", type=int, default=0, help="measure a batch of this many mixed queries instead")
-    ap.add_argument("--streams", type=int, default=4, help="streams for --many")
+    ap.add_argument("--streams", type=int, default=4, help="streams for --many and --serve")
+    ap.add_argument("--serve", type=int, default=0, help="measure latency of this many arriving queries instead")
+    ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the estimator would shard "
@@ -200,6 +290,9 @@ def main():
 
     if args.many > 0:
         run_many(args, binding, G, g.n)
+        return
+    if args.serve > 0:
+        run_serve(args, binding, G, g.n)
         return
 
     if args.copy_probe:

@@ -154,6 +154,37 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
                               int32_t n_streams);
 
 /*
+ * A serving loop: a pool of worker threads, one per stream, that solve the
+ * queries submitted to it (each as imin_solve) as they arrive, at most one
+ * per stream at a time; the others wait in arrival order.
+ *
+ * imin_server_create   streams: host array of n_streams distinct
+ *                      hipStream_t (as void*) on the graph's device,
+ *                      n_streams >= 1; the graph must outlive the server.
+ * imin_server_submit   queues one query and returns at once.  The query
+ *                      entry and its device arrays must stay valid, and its
+ *                      inputs ready on every stream, until imin_server_next
+ *                      has returned it.  IMIN_ERR_INVALID after
+ *                      imin_server_destroy has begun.
+ * imin_server_next     blocks until a submitted query has finished and
+ *                      returns it in *done (its status and device_flags
+ *                      written); every query is returned once, in the order
+ *                      they finish.  IMIN_ERR_INVALID when no submitted
+ *                      query is outstanding.
+ * imin_server_destroy  lets the workers finish every queued query, joins
+ *                      them and frees the server (queries not yet returned
+ *                      by imin_server_next are finished but not returned).
+ *
+ * One thread may submit while another waits in imin_server_next;
+ * imin_server_destroy must not overlap any other call on the same server.
+ */
+typedef struct imin_server* imin_server_t;
+imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, imin_server_t* out);
+imin_status_t imin_server_submit(imin_server_t s, imin_query_t* query);
+imin_status_t imin_server_next(imin_server_t s, imin_query_t** done);
+imin_status_t imin_server_destroy(imin_server_t s);
+
+/*
  * imin_evaluate -- one pass of the estimator (Section 2.2: sample worlds,
  * build each world's dominator tree under the super-source, measure every
  * subtree) over the worlds [w_begin, w_begin + w_count) with a given blocked

@@ -67,6 +67,14 @@ def load():
     lib.imin_solve.restype = st
     lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32]
     lib.imin_solve_many.restype = st
+    lib.imin_server_create.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P)]
+    lib.imin_server_create.restype = st
+    lib.imin_server_submit.argtypes = [P, ctypes.POINTER(Query)]
+    lib.imin_server_submit.restype = st
+    lib.imin_server_next.argtypes = [P, ctypes.POINTER(ctypes.POINTER(Query))]
+    lib.imin_server_next.restype = st
+    lib.imin_server_destroy.argtypes = [P]
+    lib.imin_server_destroy.restype = st
     lib.imin_evaluate.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P, P, P, P, P]
     lib.imin_evaluate.restype = st
     lib.imin_status_string.argtypes = [st]
@@ -251,6 +259,77 @@ def solve_many(graph: Graph, queries, n_streams: int = 4, raise_on_error: bool =
         results.append(SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
                                    spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=theta))
     return results
+
+
+def _query_result(lib, q: Query, out, theta: int, label: str):
+    """SolveResult of a finished query, or the IminError it ended with."""
+    status = int(q.status)
+    if status != IMIN_OK:
+        return IminError(status, f"{label}: " + lib.imin_status_string(status).decode(), int(q.device_flags))
+    b, g, t, ns = out
+    r = int(ns.cpu()[0])
+    return SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
+                       spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=int(theta))
+
+
+class Server:
+    """Queries solved as they arrive by a pool of worker threads, one per
+    stream (imin_server_create / submit / next / destroy)."""
+
+    def __init__(self, graph: Graph, n_streams: int = 4):
+        torch = _torch()
+        lib = load()
+        self.graph = graph
+        self._streams = [torch.cuda.Stream(device=graph.device) for _ in range(max(1, int(n_streams)))]
+        handles = (ctypes.c_void_p * len(self._streams))(*[st.cuda_stream for st in self._streams])
+        h = ctypes.c_void_p()
+        with torch.cuda.device(graph.device):
+            _check(lib.imin_server_create(graph.handle, handles, len(self._streams), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}  # ticket -> (query entry, its tensors, theta)
+
+    def submit(self, seeds, k: int, theta: int, rng_seed: int) -> int:
+        """Queue one query; returns its ticket at once."""
+        torch = _torch()
+        lib = load()
+        dev = self.graph.device
+        s = _dev(seeds, torch.int32, dev)
+        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
+               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
+               torch.zeros(k + 1, dtype=torch.int64, device=dev),
+               torch.zeros(1, dtype=torch.int32, device=dev))
+        q = Query(s.data_ptr(), int(s.numel()), int(k), int(theta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF,
+                  out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), 0, 0)
+        torch.cuda.current_stream(dev).synchronize()  # inputs and zeroed outputs ready on every stream
+        ticket = ctypes.addressof(q)
+        self._pending[ticket] = (q, (s, out), int(theta))
+        status = lib.imin_server_submit(self._h, ctypes.byref(q))
+        if status != IMIN_OK:
+            del self._pending[ticket]
+            _check(status)
+        return ticket
+
+    def next(self):
+        """(ticket, SolveResult or IminError) of the next query to finish;
+        blocks until one has."""
+        lib = load()
+        p = ctypes.POINTER(Query)()
+        _check(lib.imin_server_next(self._h, ctypes.byref(p)))
+        ticket = ctypes.addressof(p.contents)
+        q, (s, out), theta = self._pending.pop(ticket)
+        return ticket, _query_result(lib, q, out, theta, f"query {ticket:#x}")
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load().imin_server_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def evaluate(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blocked=(),

@@ -7,6 +7,8 @@
 
 #include <algorithm>
 #include <atomic>
+#include <condition_variable>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <thread>
@@ -1226,6 +1228,104 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
             g_last_flags = queries[q].device_flags;
             return (imin_status_t)queries[q].status;
         }
+    return IMIN_OK;
+}
+
+struct imin_server {
+    imin_graph_t g = nullptr;
+    std::vector<void*> streams;
+    std::vector<std::thread> workers;
+    std::mutex mu;
+    std::condition_variable queued_cv;  // a query was queued, or the server stops
+    std::condition_variable done_cv;    // a query finished
+    std::deque<imin_query_t*> queue;    // submitted, not started
+    std::deque<imin_query_t*> done;     // finished, not yet returned
+    int64_t outstanding = 0;            // submitted, not yet returned
+    bool stopping = false;
+
+    void work(int32_t i) {
+        (void)hipSetDevice(g->device);
+        for (;;) {
+            imin_query_t* q = nullptr;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                queued_cv.wait(lk, [&] { return stopping || !queue.empty(); });
+                if (queue.empty()) return;  // stopping, and nothing left to run
+                q = queue.front();
+                queue.pop_front();
+            }
+            q->status = (int32_t)imin_solve(g, q->seeds, q->n_seeds, q->k, q->theta, q->rng_seed, streams[(size_t)i],
+                                            q->blockers, q->gains, q->spread_totals, q->n_selected);
+            q->device_flags = g_last_flags;
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                done.push_back(q);
+            }
+            done_cv.notify_all();
+        }
+    }
+};
+
+imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, imin_server_t* out) {
+    if (!g || !streams || n_streams < 1 || !out) return IMIN_ERR_INVALID;
+    for (int32_t i = 0; i < n_streams; ++i)
+        for (int32_t j = 0; j < i; ++j)
+            if (streams[i] == streams[j]) return IMIN_ERR_INVALID;
+    *out = nullptr;
+    imin_server* sv = new (std::nothrow) imin_server();
+    if (!sv) return IMIN_ERR_NOMEM;
+    sv->g = g;
+    sv->streams.assign(streams, streams + n_streams);
+    try {
+        for (int32_t i = 0; i < n_streams; ++i) sv->workers.emplace_back([sv, i] { sv->work(i); });
+    } catch (...) {
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->stopping = true;
+        }
+        sv->queued_cv.notify_all();
+        for (std::thread& th : sv->workers) th.join();
+        delete sv;
+        return IMIN_ERR_NOMEM;
+    }
+    *out = sv;
+    return IMIN_OK;
+}
+
+imin_status_t imin_server_submit(imin_server_t s, imin_query_t* query) {
+    if (!s || !query) return IMIN_ERR_INVALID;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stopping) return IMIN_ERR_INVALID;
+        query->status = (int32_t)IMIN_ERR_INTERNAL;  // until it has run
+        query->device_flags = 0;
+        s->queue.push_back(query);
+        ++s->outstanding;
+    }
+    s->queued_cv.notify_one();
+    return IMIN_OK;
+}
+
+imin_status_t imin_server_next(imin_server_t s, imin_query_t** done) {
+    if (!s || !done) return IMIN_ERR_INVALID;
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->outstanding == 0) return IMIN_ERR_INVALID;
+    s->done_cv.wait(lk, [&] { return !s->done.empty(); });
+    *done = s->done.front();
+    s->done.pop_front();
+    --s->outstanding;
+    return IMIN_OK;
+}
+
+imin_status_t imin_server_destroy(imin_server_t s) {
+    if (!s) return IMIN_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->queued_cv.notify_all();
+    for (std::thread& th : s->workers) th.join();
+    delete s;
     return IMIN_OK;
 }
 

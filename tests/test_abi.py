@@ -59,4 +59,15 @@ def test_host_argument_checks(lib):
     assert lib.imin_solve_many(dummy, q, 1, s2, 2) == 1
     assert lib.imin_solve_many(dummy, q, -1, s1, 2) == 1
     assert lib.imin_solve_many(dummy, None, 1, s1, 2) == 1
+    # server: NULL graph / streams / output, no stream, a stream named twice;
+    # NULL server handles
+    hs = ctypes.c_void_p()
+    assert lib.imin_server_create(None, s1, 2, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, None, 2, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s1, 0, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s2, 2, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s1, 2, None) == 1
+    assert lib.imin_server_submit(None, q) == 1
+    assert lib.imin_server_next(None, ctypes.byref(ctypes.POINTER(binding.Query)())) == 1
+    assert lib.imin_server_destroy(None) == 0
     assert lib.imin_graph_destroy(None) == 0

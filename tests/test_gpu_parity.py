@@ -310,6 +310,45 @@ def test_solve_many_reports_each_query(B, oracle_mod):
     assert ei.value.status == 2
 
 
+def test_server_solves_queries_as_they_arrive(B, oracle_mod):
+    """Queries submitted to a server on three streams, some while others
+    run, each come back once with the oracle's selection; a failing query
+    returns its own error; next() with nothing outstanding is refused."""
+    g = synth.random_small_graph(2000, 8000, seed=56, prob="wc")
+    G = B.Graph.from_synth(g)
+    rs = np.random.default_rng(11)
+    queries = []
+    for _ in range(6):
+        seeds = rs.choice(2000, size=int(rs.integers(1, 15)), replace=False).astype(np.int32)
+        queries.append((seeds, int(rs.integers(1, 10)), int(rs.choice([300, 900])), int(rs.integers(0, 1 << 40))))
+    _log("server: 6 queries on 3 streams")
+    srv = B.Server(G, n_streams=3)
+    try:
+        tickets = {srv.submit(*q): i for i, q in enumerate(queries[:3])}
+        got = {}
+        t, r = srv.next()
+        got[tickets.pop(t)] = r
+        tickets.update({srv.submit(*q): i for i, q in enumerate(queries[3:], start=3)})
+        bad = srv.submit(np.array([5, 5], np.int32), 3, 300, 1)
+        while tickets or bad is not None:
+            t, r = srv.next()
+            if t == bad:
+                assert isinstance(r, B.IminError) and r.status == 2
+                bad = None
+            else:
+                got[tickets.pop(t)] = r
+        with pytest.raises(B.IminError):
+            srv.next()
+    finally:
+        srv.close()
+    assert sorted(got) == list(range(6))
+    for i, (seeds, k, theta, rng) in enumerate(queries):
+        want = oracle_mod.Query(g, seeds).solve(k, theta, rng)
+        np.testing.assert_array_equal(got[i].blockers, want["blockers"])
+        np.testing.assert_array_equal(got[i].gains, want["gains"])
+        np.testing.assert_array_equal(got[i].spread_totals, want["spread_totals"])
+
+
 def test_block_cache_reuse(B, oracle_mod):
     """Scratch blocks handed back to the cache and reused by later calls
     (holding a previous call's contents), then freed and allocated afresh,
