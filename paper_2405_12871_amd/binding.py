@@ -10,6 +10,7 @@ import ctypes
 import dataclasses
 import os
 import re
+import threading
 
 import numpy as np
 
@@ -286,10 +287,14 @@ class Server:
         with torch.cuda.device(graph.device):
             _check(lib.imin_server_create(graph.handle, handles, len(self._streams), ctypes.byref(h)))
         self._h = h
-        self._pending = {}  # ticket -> (query entry, its tensors, theta)
+        # address of a query entry -> (ticket, entry, its tensors, theta); an
+        # address is unique among outstanding queries, tickets for ever
+        self._pending = {}
+        self._tickets = 0
+        self._lock = threading.Lock()
 
     def submit(self, seeds, k: int, theta: int, rng_seed: int) -> int:
-        """Queue one query; returns its ticket at once."""
+        """Queue one query; returns its ticket (a serial number) at once."""
         torch = _torch()
         lib = load()
         dev = self.graph.device
@@ -301,11 +306,15 @@ class Server:
         q = Query(s.data_ptr(), int(s.numel()), int(k), int(theta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF,
                   out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), 0, 0)
         torch.cuda.current_stream(dev).synchronize()  # inputs and zeroed outputs ready on every stream
-        ticket = ctypes.addressof(q)
-        self._pending[ticket] = (q, (s, out), int(theta))
+        addr = ctypes.addressof(q)
+        with self._lock:
+            ticket = self._tickets
+            self._tickets += 1
+            self._pending[addr] = (ticket, q, (s, out), int(theta))
         status = lib.imin_server_submit(self._h, ctypes.byref(q))
         if status != IMIN_OK:
-            del self._pending[ticket]
+            with self._lock:
+                del self._pending[addr]
             _check(status)
         return ticket
 
@@ -315,9 +324,9 @@ class Server:
         lib = load()
         p = ctypes.POINTER(Query)()
         _check(lib.imin_server_next(self._h, ctypes.byref(p)))
-        ticket = ctypes.addressof(p.contents)
-        q, (s, out), theta = self._pending.pop(ticket)
-        return ticket, _query_result(lib, q, out, theta, f"query {ticket:#x}")
+        with self._lock:
+            ticket, q, (s, out), theta = self._pending.pop(ctypes.addressof(p.contents))
+        return ticket, _query_result(lib, q, out, theta, f"query {ticket}")
 
     def close(self):
         if getattr(self, "_h", None) is not None:
