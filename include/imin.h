@@ -231,14 +231,16 @@ imin_status_t imin_cache_release(void);
  * Kernel timing, for measurement.  While enabled, the library brackets its
  * own kernel launches with HIP events on the stream they run on and adds
  * each launch's duration to a per-kernel tally (process-wide).  The world
- * kernels (ids 0, 1, 4, 6) take the events into their own launch
+ * kernels (ids 0, 1, 4, 6, 7) take the events into their own launch
  * (hipExtLaunchKernel), so that the interval is the kernel's alone; the
  * others are bracketed by separate event records.  Kernel ids:
  *   0  world evaluation, small LDS tier (one wave per world)
  *   1  world evaluation, HBM tier (four waves per world, any size)
  *   2  gain reduction of a from-scratch pass (bucket histogram, scan,
- *      scatter, accumulate, sum); incremental rounds add their changes to
- *      the gains inside kernels 1, 4 and 6
+ *      scatter, accumulate, sum), or in a solve whose round-0 worlds stay
+ *      where they were written, the build of the node index that yields the
+ *      gains; incremental rounds add their changes to the gains inside
+ *      kernels 1, 4, 6 and 7
  *   3  greedy selection
  *   4  world evaluation, large LDS tier (four waves per world)
  *   5  search for the worlds a new blocker changes (incremental rounds
@@ -247,8 +249,10 @@ imin_status_t imin_cache_release(void);
  *      committed, the worlds where no live edge leaves the new blocker's
  *      dominator subtree are updated from their dominator-tree labels, and
  *      the other changed worlds are replayed from their stored live edges
- *      (worlds too large for the replay go on to kernels 4 and 1)
- *   7  (unused)
+ *      (worlds too large for the replay go on to kernel 7)
+ *   7  the wide replay of an incremental round: worlds too large for kernel
+ *      6's replay, one 1024-thread workgroup each, with four times its
+ *      capacities (worlds too large for it go on to kernels 4 and 1)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */

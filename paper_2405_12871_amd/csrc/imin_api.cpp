@@ -341,7 +341,7 @@ struct Session {
     DevArray<int32_t> wlen;
     DevArray<int32_t> scr_node, scr_cnt;  // per-world scratch (fixed tier-0 slots + bump region)
     size_t slot_cap0 = 0, big_cap = 0;
-    DevArray<int32_t> list0, list1, list2;  // changed worlds; worlds handed down to tier 1 / 2
+    DevArray<int32_t> list0, list1, list2, list3;  // changed worlds; worlds handed on (RoundCtl::list_n)
     // dense pairs and the reduction's buffers
     DevArray<int32_t> pair_node, pair_cnt, sorted_node, sorted_cnt;
     DevArray<long long> hist;
@@ -365,13 +365,14 @@ struct Session {
     // nodes lost per (kernel, workgroup) in incremental rounds
     DevArray<long long> dsz;
     int32_t dsz_n = 0;
-    int32_t dsz_off[5] = {0, 0, 0, 0, 0};
+    int32_t dsz_off[6] = {0, 0, 0, 0, 0, 0};
     int grid_l = 0;
     bool adopted = false;                  // the round-0 scratch serves as the store
     unsigned long long adopted_entries = 0;
     bool indexed = false;                  // idx_off / idx_ent hold the index
     int rule_lanes = 16;  // lanes per world in the label rule
     int grid_r = 0;
+    int grid_w = 0;  // wide-replay workgroups
     bool incremental = false;
     size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
@@ -462,6 +463,7 @@ struct Session {
         const size_t next_n = solve ? std::max<size_t>(tile_cap, theta) : tile_cap;
         IMIN_TRY(list1.alloc(next_n));
         IMIN_TRY(list2.alloc(next_n));
+        IMIN_TRY(list3.alloc(next_n));
         IMIN_TRY(list0.alloc(1));
         slot_cap0 = (size_t)imin::world_tier0_capacity();
         big_cap = env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20);
@@ -519,10 +521,11 @@ struct Session {
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
         grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 2);
         rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
+        grid_w = cus;  // wide replay: one 1024-thread workgroup per CU
         {
-            const int sizes[5] = {grid0, grid1, bs.n_slots, grid_r, grid_l};
+            const int sizes[6] = {grid0, grid1, bs.n_slots, grid_r, grid_l, grid_w};
             int32_t at = 0;
-            for (int i = 0; i < 5; ++i) {
+            for (int i = 0; i < 6; ++i) {
                 dsz_off[i] = at;
                 at += sizes[i];
             }
@@ -734,8 +737,9 @@ struct Session {
         out.store_lab = (uint32_t*)store_lab.p;
         out.world_flags = label_rule ? world_flags.p : nullptr;
         out.dsz = dsz.p;
-        for (int i = 0; i < 5; ++i) out.dsz_off[i] = dsz_off[i];
-        out.next_cap = (uint32_t)std::min<size_t>(std::min(list1.count, list2.count), 0xFFFFFFFFu);
+        for (int i = 0; i < 6; ++i) out.dsz_off[i] = dsz_off[i];
+        out.next_cap =
+            (uint32_t)std::min<size_t>(std::min(std::min(list1.count, list2.count), list3.count), 0xFFFFFFFFu);
         out.scr_par = scr_par.p;
         out.store_par = store_par.p;
         out.xscr_v = xscr_v.p;
@@ -793,10 +797,18 @@ struct Session {
                                                            grid_r, rule_lanes, idx_off.p, idx_ent.p, so, s, ev);
             timed.taken(6, ev);
             IMIN_TRY(e);
-            // worlds the replay cannot hold are sampled again; when round 0
-            // stored none, no world ever falls back and the tiers are not launched
-            if (!replay_complete) st = launch_tiers(q, 0, 0, list1.p, out, std::max(start_tier, 1), 1, last_tier());
-            else st = IMIN_OK;
+            // worlds the replay workgroups cannot hold are replayed by the
+            // wide replay, and those too large for it sampled again; when
+            // round 0 stored no such world, neither is launched
+            if (!replay_complete) {
+                const imin::LaunchEvents evw = timed.take(7);
+                const hipError_t ew = imin::launch_replay_wide(q, ctl.p, out, list1.p, list3.p, grid_w, s, evw);
+                timed.taken(7, evw);
+                IMIN_TRY(ew);
+                st = launch_tiers(q, 0, 0, list3.p, out, std::max(start_tier, 1), 3, last_tier());
+            } else {
+                st = IMIN_OK;
+            }
         } else {
             // the search for the changed worlds, then their sampling
             hipEvent_t ev = timed.begin(5, s);

@@ -48,7 +48,10 @@ struct RoundCtl {
     int32_t round_snap;      // the round as the last partial selection saw it
     int32_t ustar;
     uint32_t next[3];        // work counters of the LDS world tiers (chunks handed out)
-    uint32_t list_n[3];      // worlds handed down to tier 1 and tier 2
+    // worlds listed for a later kernel: [0] changed worlds (rounds without
+    // replay), [1] from tier 0 or the replay workgroups, [2] from tier 1,
+    // [3] from the wide replay
+    uint32_t list_n[4];
     unsigned long long pair_count;
     long long total;         // sum of |R_w| over the worlds evaluated this round
     long long expect_total;  // T_r - gain_r from the previous selection (-1: none)
@@ -186,7 +189,7 @@ struct TileOut {
     // Incremental rounds: nodes each workgroup's worlds lost, one slot per
     // (kernel, workgroup); summed and cleared by the selection.
     long long* dsz;
-    int32_t dsz_off[5];   // slot ranges of tier 0, 1, 2, replay, label rule
+    int32_t dsz_off[6];   // slot ranges of tier 0, 1, 2, replay, label rule, wide replay
 };
 
 // A compaction job: per-item ranges of up to four 32-bit fields are packed
@@ -264,6 +267,12 @@ hipError_t launch_compact(const CompactSpec& spec, RoundCtl* ctl, hipStream_t s)
 // replay_parts (>= 1) workgroups replay the other changed worlds (those too
 // large go to next_list); both find the worlds through the index.
 struct SelectOut;
+// The wide replay of an incremental round: worlds of in_list (count
+// list_n[1]) too large for the round-update launch's replay; those beyond
+// its limits are appended to over_list (count list_n[3]).  grid workgroups
+// of 1024 threads.
+hipError_t launch_replay_wide(const QueryDev& q, RoundCtl* ctl, const TileOut& out, const int32_t* in_list,
+                              int32_t* over_list, int grid, hipStream_t s, const LaunchEvents& ev = LaunchEvents());
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
                                int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
                                const int2* idx_ent, const SelectOut& so, hipStream_t s,

@@ -1534,16 +1534,32 @@ struct ReplayStore {
 // levels: at most one per entry plus the seeds' and a closing empty one
 using ReplayStoreT = ReplayStore<kReplayCap, kReplayXCap, kReplayCap + 2>;
 constexpr int kReplayNT = 256;                          // four waves per replayed world
-constexpr int kReplaySlots = kReplayEdgeCap / kReplayNT;  // stored edges per thread
-constexpr int kReplayEntrySlots = ReplayStoreT::kCap / kReplayNT;
+
+// A replay configuration: workgroup size and store, with the world's
+// entries and stored edges held in registers (kEntrySlots and kSlots per
+// thread).
+template <int NT_, int CAP, int XCAP, int EDGECAP>
+struct ReplayCfg {
+    static constexpr int NT = NT_;
+    using Store = ReplayStore<CAP, XCAP, CAP + 2>;
+    static constexpr int kEntrySlots = CAP / NT_;
+    static constexpr int kSlots = EDGECAP / NT_;
+    static_assert(CAP % NT_ == 0 && EDGECAP % NT_ == 0, "whole slots per thread");
+    static_assert(kSlots <= 32, "the valid edge slots fit one 32-bit mask");
+};
+// the replay workgroups of the round-update launch
+using ReplaySmall = ReplayCfg<kReplayNT, kReplayCap, kReplayXCap, kReplayEdgeCap>;
+constexpr int kReplaySlots = ReplaySmall::kSlots;  // stored edges per thread
+constexpr int kReplayEntrySlots = ReplaySmall::kEntrySlots;
 
 // The label rule on a world's entries held in registers: entries in u's
 // label range lose their whole count, u's ancestors lose count(u), and T
 // loses count(u).
-template <int NT>
+template <class C>
 __device__ __forceinline__ void replay_local_update(const ReplayItem& it, int32_t ustar, const TileOut& out,
-                                    const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots],
-                                    const uint32_t (&el)[kReplayEntrySlots]) {
+                                    const int32_t (&ec)[C::kEntrySlots], const int32_t (&en)[C::kEntrySlots],
+                                    const uint32_t (&el)[C::kEntrySlots]) {
+    constexpr int NT = C::NT;
     const int t = threadIdx.x;
     const size_t so = (size_t)it.store_off;
     const int L0 = it.store_len;
@@ -1551,7 +1567,7 @@ __device__ __forceinline__ void replay_local_update(const ReplayItem& it, int32_
     const int szj = label_size(it.labj);
     const int cj = it.cj;
 #pragma unroll
-    for (int r = 0; r < kReplayEntrySlots; ++r) {
+    for (int r = 0; r < C::kEntrySlots; ++r) {
         const int i = t + r * NT;
         if (i >= L0 || ec[r] <= 0) continue;
         const int ti = label_tin(el[r]);
@@ -1595,10 +1611,12 @@ __device__ __forceinline__ void replay_local_update(const ReplayItem& it, int32_
 // left in ed (source << 16 | head entry, old ids), act marking the valid
 // ones.  Returns 1 when the world was replayed, 2 when the shortcut
 // applied, 0 when the world exceeds the replay's limits.
-template <int NT, class RS>
-__device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out, RS& st,
-                          WorldShared<NT>& sh, int32_t (&ec)[kReplayEntrySlots], int32_t (&en)[kReplayEntrySlots],
-                          uint32_t (&ed)[kReplaySlots], uint32_t& act0) {
+template <class C>
+__device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, const ReplayItem& it, const TileOut& out,
+                          typename C::Store& st, WorldShared<C::NT>& sh, int32_t (&ec)[C::kEntrySlots],
+                          int32_t (&en)[C::kEntrySlots], uint32_t (&ed)[C::kSlots], uint32_t& act0) {
+    constexpr int NT = C::NT;
+    using RS = typename C::Store;
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     const size_t so = (size_t)it.store_off;
@@ -1608,16 +1626,16 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
     const int E = L0 + X0;
     // room, local ids that fit the 16-bit arrays, ranges inside the stores
     // (uniform checks)
-    if (L0 < 0 || X0 < 0 || L0 > RS::kCap || X0 > RS::cap_x() || E > NT * kReplaySlots || ns + L0 > 32767)
+    if (L0 < 0 || X0 < 0 || L0 > RS::kCap || X0 > RS::cap_x() || E > NT * C::kSlots || ns + L0 > 32767)
         return 0;
     if (it.store_off < 0 || it.xstore_off < 0 || so + (size_t)L0 > out.store_cap || xo + (size_t)X0 > out.xstore_cap)
         return 0;
     const bool labelled = (it.flags & kWorldLabelled) != 0;
     // one batch of loads: entries, then edges (the tree edge of entry e is
     // its round-0 parent; then the extras)
-    uint32_t el[kReplayEntrySlots];
+    uint32_t el[C::kEntrySlots];
 #pragma unroll
-    for (int r = 0; r < kReplayEntrySlots; ++r) {
+    for (int r = 0; r < C::kEntrySlots; ++r) {
         const int i = t + r * NT;
         ec[r] = 0;
         en[r] = -1;
@@ -1630,7 +1648,7 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
     }
     uint32_t act = 0;
 #pragma unroll
-    for (int r = 0; r < kReplaySlots; ++r) {
+    for (int r = 0; r < C::kSlots; ++r) {
         const int e = t + r * NT;
         int u = -1, vi = -1;
         if (e < L0) {
@@ -1651,14 +1669,14 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
         const int tj = label_tin(it.labj);
         const int szj = label_size(it.labj);
 #pragma unroll
-        for (int r = 0; r < kReplayEntrySlots; ++r) {
+        for (int r = 0; r < C::kEntrySlots; ++r) {
             const int i = t + r * NT;
             if (i < L0) st.cur[i] = (ec[r] > 0) ? (int)el[r] : -1;
         }
         __syncthreads();
         bool escape = false;
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r) {
+        for (int r = 0; r < C::kSlots; ++r) {
             const int u = (int)(ed[r] >> 16);
             if (((act >> r) & 1u) && u >= ns) {
                 const int ls = st.cur[u - ns];
@@ -1674,12 +1692,12 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
             }
         }
         if (!__syncthreads_or(escape)) {
-            replay_local_update<NT>(it, ustar, out, ec, en, el);
+            replay_local_update<C>(it, ustar, out, ec, en, el);
             return 2;
         }
     }
 #pragma unroll
-    for (int r = 0; r < kReplayEntrySlots; ++r) {
+    for (int r = 0; r < C::kEntrySlots; ++r) {
         const int i = t + r * NT;
         if (i < L0) st.nl[i] = (ec[r] <= 0 || en[r] == ustar) ? -2 : -1;
     }
@@ -1693,29 +1711,29 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
     int f0 = 0, f1 = ns;     // the frontier: level nlev - 1
     int nlev = 1;            // closed levels: lvl[0..nlev]
     while (f0 != f1) {
-        int nu[kReplaySlots], hv[kReplaySlots], own[kReplaySlots];
+        int nu[C::kSlots], hv[C::kSlots], own[C::kSlots];
         uint32_t hit = 0;
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r) {
+        for (int r = 0; r < C::kSlots; ++r) {
             const int u = (int)(ed[r] >> 16);
             const int x = st.nl[(u >= ns) ? u - ns : 0];
             nu[r] = (u < ns) ? u : x;
             hv[r] = st.nl[ed[r] & 0xFFFFu];
         }
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r)
+        for (int r = 0; r < C::kSlots; ++r)
             hit |= (((act >> r) & 1u) && nu[r] >= f0 && nu[r] < f1) ? (1u << r) : 0u;
         act &= ~hit;
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r)
-            if (((hit >> r) & 1u) && hv[r] == -1) st.cur[ed[r] & 0xFFFFu] = t * kReplaySlots + r;
+        for (int r = 0; r < C::kSlots; ++r)
+            if (((hit >> r) & 1u) && hv[r] == -1) st.cur[ed[r] & 0xFFFFu] = t * C::kSlots + r;
         __syncthreads();
         uint32_t win = 0, ext = 0;
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r) {
+        for (int r = 0; r < C::kSlots; ++r) {
             own[r] = st.cur[ed[r] & 0xFFFFu];
             const bool h = (hit >> r) & 1u;
-            const bool w = h && hv[r] == -1 && own[r] == t * kReplaySlots + r;
+            const bool w = h && hv[r] == -1 && own[r] == t * C::kSlots + r;
             win |= w ? (1u << r) : 0u;
             ext |= (h && hv[r] != -2 && !w) ? (1u << r) : 0u;
         }
@@ -1725,7 +1743,7 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
         int lid = count + (ex & 0xFFFF);
         int xs = nx + (ex >> 16);
 #pragma unroll
-        for (int r = 0; r < kReplaySlots; ++r) {
+        for (int r = 0; r < C::kSlots; ++r) {
             const int vi = (int)(ed[r] & 0xFFFFu);
             if ((win >> r) & 1u) {
                 st.nl[vi] = lid;
@@ -1762,13 +1780,15 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
 
 // The exits of a replayed world: its edges are the stored edges whose
 // endpoints are both reached again.
-template <int NT, class RS>
-__device__ __forceinline__ void replay_exits(RS& st, WorldShared<NT>& sh, const uint32_t (&ed)[kReplaySlots], uint32_t act) {
+template <class C>
+__device__ __forceinline__ void replay_exits(typename C::Store& st, WorldShared<C::NT>& sh,
+                                             const uint32_t (&ed)[C::kSlots], uint32_t act) {
+    constexpr int NT = C::NT;
     const int ns = st.ns;
     exits_init<NT>(ns, sh.count, st);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kReplaySlots; ++r) {
+    for (int r = 0; r < C::kSlots; ++r) {
         if (!((act >> r) & 1u)) continue;
         const int u = (int)(ed[r] >> 16);
         const int a = (u < ns) ? -1 : st.nl[u - ns];
@@ -1782,9 +1802,11 @@ __device__ __forceinline__ void replay_exits(RS& st, WorldShared<NT>& sh, const 
 // Count changes of a replayed world: each entry's new count against the one
 // held in registers; changes are added to gain and the counts updated in
 // place.
-template <int NT, class RS>
-__device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut& out, RS& st, WorldShared<NT>& sh,
-                              const int32_t (&ec)[kReplayEntrySlots], const int32_t (&en)[kReplayEntrySlots]) {
+template <class C>
+__device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t ustar, const TileOut& out,
+                              typename C::Store& st, WorldShared<C::NT>& sh,
+                              const int32_t (&ec)[C::kEntrySlots], const int32_t (&en)[C::kEntrySlots]) {
+    constexpr int NT = C::NT;
     const int t = threadIdx.x;
     const int ns = st.ns;
     const size_t so = (size_t)it.store_off;
@@ -1793,7 +1815,7 @@ __device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t usta
     __syncthreads();
     int nd = 0;
 #pragma unroll
-    for (int r = 0; r < kReplayEntrySlots; ++r) {
+    for (int r = 0; r < C::kEntrySlots; ++r) {
         const int i = t + r * NT;
         int cn = 0, d = 0;
         if (i < L0 && ec[r] > 0) {
@@ -1829,27 +1851,33 @@ __device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t usta
 // take and replays them one by one.
 constexpr int kReplaySlice = 32;
 
-struct ReplayShared {
-    ReplayStoreT st;
-    WorldShared<kReplayNT> sh;
+template <class C>
+struct ReplaySharedT {
+    typename C::Store st;
+    WorldShared<C::NT> sh;
     ReplayItem lst[kReplaySlice];  // the listed worlds
     uint32_t lst_n;
 };
+using ReplayShared = ReplaySharedT<ReplaySmall>;
 
 struct ReplayAcc {
     unsigned long long w = 0, e = 0, b = 0, lw = 0, le = 0, lb = 0;
     long long d = 0;
 };
 
-// Replay one listed world (every thread of the workgroup, uniform).
-__device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                           int32_t ustar, const ReplayItem& cur, ReplayShared& rs, ReplayAcc& acc) {
-    ReplayStoreT& st = rs.st;
-    WorldShared<kReplayNT>& sh = rs.sh;
+// Replay one listed world (every thread of the workgroup, uniform); a world
+// beyond the configuration's limits is appended to over_list (counter
+// list_n[over_idx]).
+template <class C>
+__device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int over_idx, int32_t* over_list,
+                                           const TileOut& out, int32_t ustar, const ReplayItem& cur,
+                                           ReplaySharedT<C>& rs, ReplayAcc& acc) {
+    typename C::Store& st = rs.st;
+    WorldShared<C::NT>& sh = rs.sh;
     const int t = threadIdx.x;
-    int32_t ec[kReplayEntrySlots], en[kReplayEntrySlots];
-    uint32_t ed[kReplaySlots], act;
-    const int how = bfs_replay<kReplayNT>(q, ustar, cur, out, st, sh, ec, en, ed, act);
+    int32_t ec[C::kEntrySlots], en[C::kEntrySlots];
+    uint32_t ed[C::kSlots], act;
+    const int how = bfs_replay<C>(q, ustar, cur, out, st, sh, ec, en, ed, act);
     if (how == 2) {
         // the shortcut: reported with the label-based updates
         acc.lw += 1;
@@ -1857,10 +1885,10 @@ __device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int
         acc.lb += 37ull + 16ull * (unsigned long long)cur.store_len + 8ull * (unsigned long long)cur.xstore_len + 8ull;
         acc.d += cur.cj;
     } else if (how == 1) {
-        world_counts<kReplayNT>(q, ctl, st, sh);
-        world_labels<kReplayNT>(q, st, sh);
-        if (sh.n_extra > 0) replay_exits<kReplayNT>(st, sh, ed, act);  // uniform
-        const int nd = replay_outputs<kReplayNT>(cur, ustar, out, st, sh, ec, en);
+        world_counts<C::NT>(q, ctl, st, sh);
+        world_labels<C::NT>(q, st, sh);
+        if (sh.n_extra > 0) replay_exits<C>(st, sh, ed, act);  // uniform
+        const int nd = replay_outputs<C>(cur, ustar, out, st, sh, ec, en);
         acc.w += 1;
         acc.e += (unsigned long long)(cur.store_len + cur.xstore_len);
         // index entry, count, label, the world's ranges, size and flags;
@@ -1869,8 +1897,8 @@ __device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int
                  12ull * (unsigned long long)nd + 8ull;
         acc.d += (long long)cur.world_size - (long long)sh.count;
     } else if (t == 0) {
-        const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
-        if (pos < out.next_cap) next_list[pos] = cur.w;
+        const uint32_t pos = atomicAdd(&ctl->list_n[over_idx], 1u);
+        if (pos < out.next_cap) over_list[pos] = cur.w;
         else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
     }
     __syncthreads();
@@ -1914,7 +1942,7 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
         const uint32_t nl = rs.lst_n;
         for (uint32_t li = 0; li < nl; ++li) {
             const ReplayItem cur = rs.lst[li];
-            replay_one(q, ctl, next_list, out, ustar, cur, rs, acc);
+            replay_one<ReplaySmall>(q, ctl, 1, next_list, out, ustar, cur, rs, acc);
         }
     }
     if (t == 0) {
@@ -1923,6 +1951,66 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
         // T is lowered by the nodes the replayed worlds lost
         if (acc.d) out.dsz[out.dsz_off[3] + part] = acc.d;
     }
+}
+
+// Changed worlds too large for the replay workgroups of the round-update
+// launch (list 1, world ids) are replayed by one workgroup of 1024 threads
+// each, with four times the capacities; a world beyond those goes on to
+// the sampling tiers (list 3).  The new blocker's entry in each world is
+// found by scanning the world's entries.
+using ReplayWide = ReplayCfg<1024, 4 * kReplayCap, 4 * kReplayXCap, 4 * kReplayEdgeCap>;
+
+__global__ __launch_bounds__(ReplayWide::NT) void k_replay_wide(QueryDev q, RoundCtl* ctl, TileOut out,
+                                                             const int32_t* in_list, int32_t* over_list) {
+    __shared__ ReplaySharedT<ReplayWide> rs;
+    __shared__ int32_t jpos;
+    const int t = threadIdx.x;
+    if (ctl->stop) return;
+    const uint32_t n_items = min(ctl->list_n[1], out.next_cap);
+    if (blockIdx.x >= n_items) return;  // no world for this workgroup
+    const int32_t ustar = ctl->ustar;   // committed by the round-update launch
+    ReplayAcc acc;
+    for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
+        ReplayItem it;
+        it.w = in_list[k];
+        it.store_off = out.store_off[it.w];
+        it.store_len = out.store_len[it.w];
+        it.xstore_off = out.xstore_off[it.w];
+        it.xstore_len = out.xstore_len[it.w];
+        it.world_size = out.world_size[it.w];
+        it.flags = out.world_flags ? out.world_flags[it.w] : (uint8_t)0;
+        if (it.store_off < 0 || it.store_len < 0 || (size_t)it.store_off + (size_t)it.store_len > out.store_cap) {
+            if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            continue;  // uniform
+        }
+        if (t == 0) jpos = -1;
+        __syncthreads();
+        for (int i = t; i < it.store_len; i += ReplayWide::NT)
+            if (out.store_node[it.store_off + i] == ustar) jpos = i;  // a node has one entry per world
+        __syncthreads();
+        it.j = jpos;
+        __syncthreads();  // jpos is written again for the next world
+        if (it.j < 0) {
+            if (t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);  // listed without an entry for u
+            continue;  // uniform
+        }
+        it.cj = out.store_cnt[it.store_off + it.j];
+        it.labj = out.store_lab ? out.store_lab[it.store_off + it.j] : 0u;
+        if (it.cj <= 0) continue;  // uniform: listed only while u's entry is live
+        replay_one<ReplayWide>(q, ctl, 3, over_list, out, ustar, it, rs, acc);
+    }
+    if (t == 0) {
+        add_work_at(out, 3, blockIdx.x, acc.w, acc.e, acc.b);
+        add_work_at(out, 5, blockIdx.x, acc.lw, acc.le, acc.lb);
+        // T is lowered by the nodes the replayed worlds lost
+        if (acc.d) out.dsz[out.dsz_off[5] + blockIdx.x] = acc.d;
+    }
+}
+
+hipError_t launch_replay_wide(const QueryDev& q, RoundCtl* ctl, const TileOut& out, const int32_t* in_list,
+                              int32_t* over_list, int grid, hipStream_t s, const LaunchEvents& ev) {
+    if (grid < 1) return hipErrorInvalidValue;
+    return launch_k(k_replay_wide, (unsigned)grid, (unsigned)ReplayWide::NT, s, ev, q, ctl, out, in_list, over_list);
 }
 
 // ------------------------------------------------------- label rule

@@ -260,6 +260,29 @@ def test_solve_replay_mixed_world_sizes(B, oracle_mod, case):
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
 
 
+def test_solve_worlds_beyond_the_replays(B, oracle_mod):
+    """Worlds of 3 to about 2,400 reached nodes: changed worlds are replayed
+    by the round-update workgroups (up to 512 entries) or by the wide replay
+    (up to 2,048), and sampled again beyond that; the selection is the
+    oracle's."""
+    g = synth.random_small_graph(5000, 13000, seed=93, prob="uniform")
+    seeds = np.random.default_rng(1).choice(5000, size=6, replace=False).astype(np.int32)
+    G = B.Graph.from_synth(g)
+    _log("solve with worlds beyond both replays")
+    B.timing_reset()
+    B.timing_enable(True)
+    try:
+        res = B.solve(G, seeds, 8, 240, 3)
+        wide_launches = B.timing_launches(7)
+    finally:
+        B.timing_enable(False)
+    assert wide_launches > 0
+    want = oracle_mod.Query(g, seeds).solve(8, 240, 3)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 def test_solve_small_workload(B, oracle_mod):
     g, seeds, k, theta = synth.workload("small")
     _log("solve small workload")
