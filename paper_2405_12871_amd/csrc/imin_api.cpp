@@ -21,6 +21,12 @@
 struct imin_graph {
     imin::GraphDev g;
     int device;
+    // bump-region entries per world (1/1024 units) that earlier calls on this
+    // graph needed, for worlds beyond tier 0's slots and for their extra
+    // edges: later calls size their scratch from them and need not redo a
+    // tile whose worlds overflowed it
+    std::atomic<uint64_t> big_per_world{0};
+    std::atomic<uint64_t> xbig_per_world{0};
 };
 
 namespace {
@@ -406,7 +412,30 @@ struct Session {
     int last_tier() const { return any_tier2 ? 2 : 1; }
     TimedLaunches timed;
 
-    Session(const imin::GraphDev& gd, hipStream_t st) : g(gd), s(st) {}
+    Session(const imin::GraphDev& gd, hipStream_t st, imin_graph* h = nullptr) : g(gd), s(st), gh(h) {}
+    imin_graph* gh;  // per-graph scratch hints (may be null)
+
+    // the scratch a tile of `worlds` worlds is expected to need, from the
+    // graph's hint (entries per world in 1/1024 units), with an eighth more
+    size_t hinted(const std::atomic<uint64_t>* hint, size_t worlds, size_t dflt) const {
+        if (!hint) return dflt;
+        const unsigned long long per = hint->load(std::memory_order_relaxed);
+        const unsigned long long need = (per * (unsigned long long)worlds) >> 10;
+        return std::max<size_t>(dflt, (size_t)(need + need / 8 + 1024));
+    }
+
+    // a tile of nw worlds that asked for bc bump-region and xc extra-edge
+    // entries raises the graph's hints
+    void record_scratch(unsigned long long bc, unsigned long long xc, uint64_t nw) {
+        if (!gh || nw == 0) return;
+        auto raise = [](std::atomic<uint64_t>& a, uint64_t v) {
+            uint64_t cur = a.load(std::memory_order_relaxed);
+            while (v > cur && !a.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
+            }
+        };
+        raise(gh->big_per_world, (uint64_t)((bc << 10) / nw));
+        raise(gh->xbig_per_world, (uint64_t)((xc << 10) / nw));
+    }
     // an early return may leave work queued: drain it before any block can
     // be handed to another call
     ~Session() {
@@ -466,7 +495,7 @@ struct Session {
         IMIN_TRY(list3.alloc(next_n));
         IMIN_TRY(list0.alloc(1));
         slot_cap0 = (size_t)imin::world_tier0_capacity();
-        big_cap = env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20);
+        big_cap = hinted(gh ? &gh->big_per_world : nullptr, tile_cap, env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20));
         IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
         IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
 
@@ -607,7 +636,8 @@ struct Session {
         const char* rp = std::getenv("IMIN_REPLAY");
         if (!(rp && rp[0] == '0')) {
             xslot_cap0 = (size_t)imin::world_tier0_xcapacity();
-            xbig_cap = env_size("IMIN_XBIG_SCRATCH", (size_t)1 << 20);
+            xbig_cap = hinted(gh ? &gh->xbig_per_world : nullptr, tile_cap,
+                              env_size("IMIN_XBIG_SCRATCH", (size_t)1 << 20));
             const size_t xn = tile_cap * xslot_cap0 + xbig_cap;
             replay = scr_par.alloc(scr_node.count) == hipSuccess && scr_lab.alloc(scr_node.count) == hipSuccess &&
                      xscr_v.alloc(xn) == hipSuccess && xscr_u.alloc(xn) == hipSuccess &&
@@ -855,6 +885,7 @@ struct Session {
                 g_last_flags = f;
                 return IMIN_ERR_INTERNAL;
             }
+            record_scratch(hctl.p->big_count, hctl.p->xbig_count, nw);
             if (f & imin::kFlagPairOverflow) {
                 // a scratch bump region was too small: grow it, redo the tile
                 st = clear_flag(imin::kFlagPairOverflow);
@@ -1098,7 +1129,7 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
     if (n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
     if (theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    Session ss(g->g, s);
+    Session ss(g->g, s, g);
     imin_status_t st = ss.init((uint64_t)theta, true);
     if (st != IMIN_OK) return st;
     imin::QueryDev q{};
@@ -1165,7 +1196,7 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     if (n_seeds < 1 || n_seeds > g->g.n || n_blocked < 0 || (n_blocked > 0 && !blocked)) return IMIN_ERR_INVALID;
     if (w_begin < 0 || w_count < 1 || w_begin + w_count > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
-    Session ss(g->g, s);
+    Session ss(g->g, s, g);
     imin_status_t st = ss.init((uint64_t)w_count, false);
     if (st != IMIN_OK) return st;
     imin::QueryDev q{};

@@ -1549,8 +1549,6 @@ struct ReplayCfg {
 };
 // the replay workgroups of the round-update launch
 using ReplaySmall = ReplayCfg<kReplayNT, kReplayCap, kReplayXCap, kReplayEdgeCap>;
-constexpr int kReplaySlots = ReplaySmall::kSlots;  // stored edges per thread
-constexpr int kReplayEntrySlots = ReplaySmall::kEntrySlots;
 
 // The label rule on a world's entries held in registers: entries in u's
 // label range lose their whole count, u's ancestors lose count(u), and T
@@ -1587,7 +1585,7 @@ __device__ __forceinline__ void replay_local_update(const ReplayItem& it, int32_
     if (t == 0) out.world_size[it.w] = it.world_size - cj;
 }
 
-// The stored edges stay in registers (kReplaySlots per thread); each level
+// The stored edges stay in registers (C::kSlots per thread); each level
 // looks up the new id of every pending edge's source and claims the heads
 // of the edges leaving the frontier.  Every edge is used once, when its
 // source's level is expanded.  The world's entries (count, node) stay in
