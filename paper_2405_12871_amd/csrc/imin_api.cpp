@@ -416,12 +416,15 @@ struct Session {
     imin_graph* gh;  // per-graph scratch hints (may be null)
 
     // the scratch a tile of `worlds` worlds is expected to need, from the
-    // graph's hint (entries per world in 1/1024 units), with an eighth more
+    // graph's hint (entries per world in 1/1024 units), with an eighth more;
+    // at most 2^28 entries (a tile needing more grows its scratch and is
+    // redone, as without a hint)
     size_t hinted(const std::atomic<uint64_t>* hint, size_t worlds, size_t dflt) const {
         if (!hint) return dflt;
         const unsigned long long per = hint->load(std::memory_order_relaxed);
         const unsigned long long need = (per * (unsigned long long)worlds) >> 10;
-        return std::max<size_t>(dflt, (size_t)(need + need / 8 + 1024));
+        const unsigned long long want = std::min<unsigned long long>(need + need / 8 + 1024, 1ull << 28);
+        return std::max<size_t>(dflt, (size_t)want);
     }
 
     // a tile of nw worlds that asked for bc bump-region and xc extra-edge
