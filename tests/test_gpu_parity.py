@@ -128,6 +128,24 @@ def test_scratch_regrowth(B, oracle_mod, monkeypatch):
     _assert_same(got, want)
 
 
+def test_scratch_hint_from_earlier_calls(B, oracle_mod, monkeypatch):
+    """The first solve on a graph grows a far too small bump region and
+    redoes its tile; the second sizes it from what the first needed.  Both
+    give the oracle's selection."""
+    monkeypatch.setenv("IMIN_BIG_SCRATCH", "64")
+    monkeypatch.setenv("IMIN_START_TIER", "1")
+    g = synth.random_small_graph(1200, 3000, seed=92, prob="uniform")
+    seeds = np.array([5, 17, 400, 999], np.int32)
+    G = B.Graph.from_synth(g)
+    want = oracle_mod.Query(g, seeds).solve(6, 500, 31)
+    for call in range(2):
+        _log(f"solve {call} on one graph with a tiny initial bump region")
+        res = B.solve(G, seeds, 6, 500, 31)
+        np.testing.assert_array_equal(res.blockers, want["blockers"])
+        np.testing.assert_array_equal(res.gains, want["gains"])
+        np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
 @pytest.mark.parametrize("tier", ["0", "1", "2"])
 def test_every_start_tier_gives_the_same_integers(B, oracle_mod, monkeypatch, tier):
     """Worlds first tried on the LDS tiers or directly on the HBM tier."""
