@@ -109,11 +109,12 @@ def test_tile_beyond_2pow31_pairs(B):
     assert full_total == a[1] + b[1] == int(ws.astype(np.int64).sum())
 
 
-def test_tiles_and_pair_overflow(B, oracle_mod, monkeypatch):
-    """Tiny tiles and a tiny pair buffer force the tile loop and its retry."""
+def test_tiles(B, oracle_mod, monkeypatch):
+    """Tiny tiles force the tile loop (a ragged last tile included); the
+    retry of a tile whose scratch overflows is covered by the regrowth
+    tests below."""
     g, seeds, _, _ = synth.workload("small")
     monkeypatch.setenv("IMIN_TILE_WORLDS", "97")
-    monkeypatch.setenv("IMIN_PAIR_CAP", "3000")
     got, want = _eval_both(B, oracle_mod, g, seeds, 10, 1001, 2)
     _assert_same(got, want)
 
