@@ -391,6 +391,58 @@ def test_server_solves_queries_as_they_arrive(B, oracle_mod):
         np.testing.assert_array_equal(got[i].spread_totals, want["spread_totals"])
 
 
+def test_server_with_concurrent_submitters(B):
+    """Two threads submit while a third collects: every query comes back
+    once, each equal to the same query solved alone."""
+    import threading
+
+    g = synth.random_small_graph(1500, 6000, seed=57, prob="wc")
+    G = B.Graph.from_synth(g)
+    rs = np.random.default_rng(13)
+    queries = []
+    for _ in range(16):
+        seeds = rs.choice(1500, size=int(rs.integers(1, 12)), replace=False).astype(np.int32)
+        queries.append((seeds, int(rs.integers(1, 8)), int(rs.choice([200, 500])), int(rs.integers(0, 1 << 40))))
+    alone = [B.solve(G, *q) for q in queries]
+    _log("server: 16 queries from two submitting threads")
+    srv = B.Server(G, n_streams=4)
+    owner, lock, sem, got, errors = {}, threading.Lock(), threading.Semaphore(0), {}, []
+
+    def submit(part):
+        try:
+            for i in range(part, len(queries), 2):
+                with lock:
+                    owner[srv.submit(*queries[i])] = i
+                sem.release()
+        except Exception as e:  # reported below
+            errors.append(e)
+            sem.release()
+
+    def collect():
+        for _ in range(len(queries)):
+            sem.acquire()
+            if errors:
+                return
+            t, r = srv.next()
+            with lock:
+                got[owner.pop(t)] = r
+
+    threads = [threading.Thread(target=submit, args=(0,)), threading.Thread(target=submit, args=(1,)),
+               threading.Thread(target=collect)]
+    try:
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join(timeout=60)
+    finally:
+        srv.close()
+    assert not errors
+    assert sorted(got) == list(range(len(queries)))
+    for i, r in got.items():
+        np.testing.assert_array_equal(r.blockers, alone[i].blockers)
+        np.testing.assert_array_equal(r.spread_totals, alone[i].spread_totals)
+
+
 def test_block_cache_reuse(B, oracle_mod):
     """Scratch blocks handed back to the cache and reused by later calls
     (holding a previous call's contents), then freed and allocated afresh,
