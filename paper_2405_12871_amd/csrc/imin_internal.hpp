@@ -239,7 +239,6 @@ constexpr int kBucketShift = 13;  // 8192 nodes per bucket (int64 LDS accumulato
 hipError_t launch_graph_ingest(const GraphDev& g, const int64_t* row_ptr, const int32_t* col_in,
                                const float* p, RoundCtl* ctl, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t count, hipStream_t s);
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t count, hipStream_t s);
 hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n_seeds,
                               const int32_t* blocked, int32_t n_blocked, uint32_t* excl,

@@ -72,7 +72,6 @@ static hipError_t fill(T* p, T v, size_t count, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
 hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
 
 // ------------------------------------------------------- query set-up

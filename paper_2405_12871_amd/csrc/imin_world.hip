@@ -1842,8 +1842,9 @@ __device__ __forceinline__ int replay_outputs(const ReplayItem& it, int32_t usta
 }
 
 // Changed worlds the label rule cannot take are replayed; a world that does
-// not fit the replay store goes on to the sampling tiers (list 1).  The
-// replay workgroups find those worlds in the index themselves: workgroup
+// not fit the replay store goes on (list 1) to the wide replay, and from
+// there to the sampling tiers.  The replay workgroups find those worlds in
+// the index themselves: workgroup
 // `part` of `parts` takes slices of kReplaySlice index entries of u (slice
 // part, part + parts, ...), lists in LDS the live entries the rule cannot
 // take and replays them one by one.
