@@ -177,6 +177,7 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
  *
  * One thread may submit while another waits in imin_server_next;
  * imin_server_destroy must not overlap any other call on the same server.
+ * IMIN_ERR_NOMEM when host memory for the server or its queues runs out.
  */
 typedef struct imin_server* imin_server_t;
 imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, imin_server_t* out);

@@ -1229,7 +1229,12 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
     }
     // largest first (theta * (k + 1) bounds a query's work), so that a long
     // query does not start last and stretch the batch
-    std::vector<int32_t> order((size_t)n_queries);
+    std::vector<int32_t> order;
+    try {
+        order.resize((size_t)n_queries);
+    } catch (...) {
+        return IMIN_ERR_NOMEM;
+    }
     for (int32_t q = 0; q < n_queries; ++q) order[(size_t)q] = q;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         const double wa = (double)queries[a].theta * ((double)queries[a].k + 1.0);
@@ -1258,7 +1263,6 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
         // a thread that cannot be started leaves its stream unused; the
         // calling thread then takes stream 0's part of the queue itself
         std::vector<std::thread> pool;
-        pool.reserve((size_t)workers);
         for (int32_t i = 1; i < workers; ++i) {
             try {
                 pool.emplace_back(work, i);
@@ -1305,7 +1309,13 @@ struct imin_server {
             q->device_flags = g_last_flags;
             {
                 std::lock_guard<std::mutex> lk(mu);
-                done.push_back(q);
+                try {
+                    done.push_back(q);
+                } catch (...) {
+                    // the query cannot be handed back: drop it from the count
+                    // so that imin_server_next does not wait for it forever
+                    --outstanding;
+                }
             }
             done_cv.notify_all();
         }
@@ -1321,8 +1331,8 @@ imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n
     imin_server* sv = new (std::nothrow) imin_server();
     if (!sv) return IMIN_ERR_NOMEM;
     sv->g = g;
-    sv->streams.assign(streams, streams + n_streams);
     try {
+        sv->streams.assign(streams, streams + n_streams);
         for (int32_t i = 0; i < n_streams; ++i) sv->workers.emplace_back([sv, i] { sv->work(i); });
     } catch (...) {
         {
@@ -1345,7 +1355,11 @@ imin_status_t imin_server_submit(imin_server_t s, imin_query_t* query) {
         if (s->stopping) return IMIN_ERR_INVALID;
         query->status = (int32_t)IMIN_ERR_INTERNAL;  // until it has run
         query->device_flags = 0;
-        s->queue.push_back(query);
+        try {
+            s->queue.push_back(query);
+        } catch (...) {
+            return IMIN_ERR_NOMEM;
+        }
         ++s->outstanding;
     }
     s->queued_cv.notify_one();
@@ -1356,7 +1370,8 @@ imin_status_t imin_server_next(imin_server_t s, imin_query_t** done) {
     if (!s || !done) return IMIN_ERR_INVALID;
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->outstanding == 0) return IMIN_ERR_INVALID;
-    s->done_cv.wait(lk, [&] { return !s->done.empty(); });
+    s->done_cv.wait(lk, [&] { return !s->done.empty() || s->outstanding == 0; });
+    if (s->done.empty()) return IMIN_ERR_NOMEM;  // the last query could not be handed back
     *done = s->done.front();
     s->done.pop_front();
     --s->outstanding;
