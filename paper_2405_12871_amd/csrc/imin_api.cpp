@@ -1124,9 +1124,9 @@ static imin_status_t setup_query(Session& ss, const int32_t* seeds, int32_t n_se
     return IMIN_OK;
 }
 
-imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
-                         uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
-                         int64_t* spread_totals, int32_t* n_selected) {
+static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                                uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
+                                int64_t* spread_totals, int32_t* n_selected) {
     g_last_flags = 0;
     if (!g || !seeds || !blockers || !gains || !spread_totals || !n_selected) return IMIN_ERR_INVALID;
     if (n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
@@ -1190,10 +1190,10 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
     return IMIN_OK;
 }
 
-imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
-                            int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed, void* stream,
-                            int64_t* gain, int64_t* total, int32_t* world_size, int64_t* world_sum,
-                            int64_t* world_edges) {
+static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                                   int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed,
+                                   void* stream, int64_t* gain, int64_t* total, int32_t* world_size,
+                                   int64_t* world_sum, int64_t* world_edges) {
     g_last_flags = 0;
     if (!g || !seeds || !gain || !total) return IMIN_ERR_INVALID;
     if (n_seeds < 1 || n_seeds > g->g.n || n_blocked < 0 || (n_blocked > 0 && !blocked)) return IMIN_ERR_INVALID;
@@ -1215,6 +1215,36 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     if (st != IMIN_OK) return st;
     ss.finish();
     return IMIN_OK;
+}
+
+// No C++ exception crosses the boundary: host allocations that fail inside a
+// call end it with IMIN_ERR_NOMEM (its session drains its stream while
+// unwinding).
+imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                         uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
+                         int64_t* spread_totals, int32_t* n_selected) {
+    try {
+        return solve_impl(g, seeds, n_seeds, k, theta, rng_seed, stream, blockers, gains, spread_totals,
+                          n_selected);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                            int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed, void* stream,
+                            int64_t* gain, int64_t* total, int32_t* world_size, int64_t* world_sum,
+                            int64_t* world_edges) {
+    try {
+        return evaluate_impl(g, seeds, n_seeds, blocked, n_blocked, w_begin, w_count, rng_seed, stream, gain, total,
+                             world_size, world_sum, world_edges);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
 }
 
 imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_queries, void* const* streams,
