@@ -391,6 +391,19 @@ def test_server_solves_queries_as_they_arrive(B, oracle_mod):
         np.testing.assert_array_equal(got[i].spread_totals, want["spread_totals"])
 
 
+def test_batch_and_server_without_queries(B):
+    """An empty batch returns no results; a server closed before any
+    query was submitted stops its workers and returns; next() on it with
+    nothing outstanding is refused."""
+    g = synth.random_small_graph(200, 800, seed=58, prob="wc")
+    G = B.Graph.from_synth(g)
+    assert B.solve_many(G, [], n_streams=3) == []
+    srv = B.Server(G, n_streams=2)
+    with pytest.raises(B.IminError):
+        srv.next()
+    srv.close()
+
+
 def test_server_with_concurrent_submitters(B):
     """Two threads submit while a third collects: every query comes back
     once, each equal to the same query solved alone."""
