@@ -3,19 +3,19 @@
 
 Workload (default ``large``): directed Chung-Lu power-law graph with 1,000,000
 nodes and 10,000,000 edges (degree exponent 2.1), trivalency probabilities
-{0.1, 0.01, 0.001}, |S| = 200 uniform seeds, k = 500 blockers, theta = 200,000
-worlds.  One step is one full greedy solve (``imin_solve``): seed set-up,
-k rounds of world sampling + BFS + dominator counts + gain reduction +
-selection.  Inputs (graph handle, seeds, output buffers) are resident in HBM
-before the timed region.
+{0.1, 0.01, 0.001}, |S| = 200 uniform seeds, theta = 200,000 worlds (k = 500
+for the greedy solves).  Inputs (graph handle, seeds, output buffers) are
+resident in HBM before the timed region.
 
-Printed: one JSON line.  ``value`` is live-edge world evaluations actually
-performed per second over whole solves (round 0 evaluates theta worlds from
-scratch; each later round re-evaluates the worlds the new blocker changes).
-The line also carries the from-scratch round-0 rate, the solve latency
-percentiles, the roofline of the world-evaluation kernel (HIP events on the
-library's stream, over every launch of the run) and the CPU oracle's rate on
-a bounded sample.
+One step is one from-scratch pass of the estimator over all theta worlds
+(``imin_evaluate``): sample every live-edge world, BFS from the seeds,
+dominators and subtree sizes, and the per-node gain reduction.  ``value`` is
+theta divided by the pass time (worlds/s).  The ``roofline`` object is that of
+the tier-0 world kernel (the pass's dominant kernel), timed with HIP events
+recorded by its own launch; the Philox and copy probes give the measured ALU
+and HBM ceilings.  After the timed passes, full greedy solves (k rounds, with
+incremental rounds) give the query latency percentiles; the CPU oracle's
+from-scratch rate on the same query is the ``cpu_baseline``.
 
 With ``--many N`` it measures instead a batch of N mixed queries on the same
 graph (|S| uniform in 10..500, k uniform in 10..200, theta 10^4 or 10^5, each
@@ -87,38 +87,32 @@ def measured_traffic(kernel: str):
         return None
 
 
-def cpu_baseline(g, seeds, k, theta, budget_s):
-    """The oracle as it stands, on a bounded sample of the same query: its own
-    greedy solve (every round re-evaluates all theta worlds) cut to the first
-    rounds, sized to about ``budget_s`` seconds of CPU work."""
+def cpu_baseline(g, seeds, theta, budget_s, gpu_gain):
+    """The oracle as it stands, on a bounded sample of the same workload: its
+    from-scratch pass (dominator mode, no blockers) over the first worlds of
+    the same query, sized to about ``budget_s`` seconds of CPU work (all theta
+    worlds when that fits).  When the sample is the whole workload its gains
+    are compared with the GPU's."""
+    import numpy as np
+
     from oracle import oracle
     q = oracle.Query(g, seeds)
     threads = oracle.default_threads()
-    # one round-0 pass to size the sample
     nw = max(64, min(theta, 2000))
     t0 = time.perf_counter()
     q.eval(RNG_SEED, 0, nw, threads=threads)
     per_world = (time.perf_counter() - t0) / nw
-    per_round = per_world * theta
-    if per_round * 2 > budget_s:
-        # even one full round is too long: a round-0 pass over a prefix of the worlds
-        nw2 = int(max(nw, min(theta, budget_s / max(per_world, 1e-9))))
-        t0 = time.perf_counter()
-        q.eval(RNG_SEED, 0, nw2, threads=threads)
-        dt = time.perf_counter() - t0
-        return {"value": nw2 / dt, "unit": "worlds/s", "cores": threads, "kind": "oracle",
-                "sample": f"round-0 pass (no blockers) over worlds [0, {nw2}) of the same query; "
-                          f"{dt:.1f} s on {threads} threads", "seconds": dt}, None
-    k_cpu = int(max(1, min(k, budget_s / per_round - 1)))
+    nw2 = int(min(theta, max(nw, budget_s / max(per_world, 1e-12))))
     t0 = time.perf_counter()
-    res = q.solve(k_cpu, theta, RNG_SEED, threads=threads)
+    gain, total = q.eval(RNG_SEED, 0, nw2, threads=threads)
     dt = time.perf_counter() - t0
-    # plain rounds: every round evaluates theta worlds, plus a final reachability pass
-    evals = theta * (res["n_selected"] + 1)
-    return {"value": evals / dt, "unit": "worlds/s", "cores": threads, "kind": "oracle",
-            "sample": f"greedy solve of the same query cut to k={k_cpu} of {k} rounds (theta={theta} worlds "
-                      f"per round, dominator mode, {res['n_selected'] + 1} passes); {dt:.1f} s on {threads} threads",
-            "seconds": dt}, res["blockers"]
+    out = {"value": nw2 / dt, "unit": "worlds/s", "cores": threads, "kind": "oracle",
+           "sample": f"from-scratch pass (dominator mode, no blockers) over worlds [0, {nw2}) of the same "
+                     f"query ({'all' if nw2 == theta else 'a prefix'} of theta={theta}); {dt:.1f} s on "
+                     f"{threads} threads", "seconds": dt}
+    if nw2 == theta:
+        out["oracle_gains_equal_gpu"] = bool(np.array_equal(gain, gpu_gain))
+    return out
 
 
 def run_many(args, binding, G, n):
@@ -244,15 +238,35 @@ def run_serve(args, binding, G, n):
     }))
 
 
+def probe_ceilings(binding, dev, theta, ebar, cus):
+    """Measured ceilings: Philox coins/s with the world kernels' coin layout
+    (theta worlds of about Ebar/4 slot groups), and device copy GB/s (1 GiB)."""
+    import torch
+    groups = max(1, int(round(ebar / 4)))
+    grid = cus * 8
+    binding.probe_philox(theta, groups, RNG_SEED, grid, dev)  # warm
+    ms = min(binding.probe_philox(theta, groups, RNG_SEED, grid, dev) for _ in range(3))
+    coins = 4.0 * theta * groups / (ms / 1e3)
+    src = torch.ones(1 << 28, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    binding.probe_copy(dst, src, cus * 16)
+    cms = min(binding.probe_copy(dst, src, cus * 16) for _ in range(3))
+    nbytes = src.numel() * 4
+    del src, dst
+    torch.cuda.synchronize()
+    return {"philox_coins_per_s": coins, "philox_probe_ms": ms, "philox_blocks": theta * groups,
+            "copy_GBps": 2.0 * nbytes / (cms / 1e3) / 1e9, "copy_bytes": nbytes, "copy_probe_ms": cms}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="large", choices=["small", "medium", "large"])
+    ap.add_argument("--solves", type=int, default=5, help="full greedy solves for the latency figures (0: none)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true", help="run a 256 MiB copy first (counter scaling)")
     ap.add_argument("--many", type=int, default=0, help="measure a batch of this many mixed queries instead")
     ap.add_argument("--streams", type=int, default=4, help="streams for --many and --serve")
     ap.add_argument("--serve", type=int, default=0, help="measure latency of this many arriving queries instead")
@@ -271,6 +285,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    cus = torch.cuda.get_device_properties(dev).multi_processor_count
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     g, seeds, k, theta = synth.workload(args.workload)
@@ -295,90 +310,63 @@ def main():
         run_serve(args, binding, G, g.n)
         return
 
-    if args.copy_probe:
-        # a plain copy of known size, for scaling HBM byte counters
-        a = torch.empty(64 << 20, dtype=torch.int32, device=dev).fill_(1)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    # every library kernel launch of this process is timed with HIP events
-    binding.timing_enable(True)
-    binding.timing_reset()
-
-    # from-scratch round-0 pass: exact R and E per world
-    t0 = time.perf_counter()
-    gain0, T0, wsize, wsum, wedges = binding.evaluate(G, seeds_dev, 0, theta, RNG_SEED, per_world=True,
-                                                      edges=True)
-    r0_wall = time.perf_counter() - t0
-    r0 = {kid: binding.timing_read(kid) for kid in (0, 1, 2, 4)}
-    r0_work = [binding.timing_work(t) for t in range(3)]
+    # per-world sizes of the workload (an untimed pass): R and E per world
+    _, T0, wsize, _, wedges = binding.evaluate(G, seeds_dev, 0, theta, RNG_SEED, per_world=True, edges=True)
     R = wsize.astype(np.int64)
     E = wedges.astype(np.int64)
     ns = len(seeds)
-    r0_world_ms = r0[0][1] + r0[4][1] + r0[1][1]
-    r0_bytes = sum(w[2] for w in r0_work)
-    log(f"round 0: T0={T0} Rbar={R.mean():.1f} Ebar={E.mean():.1f} world kernels {r0_world_ms:.3f} ms "
-        f"(tier0 {r0[0][1]:.3f}, tier1 {r0[4][1]:.3f}, tier2 {r0[1][1]:.3f}), reduce {r0[2][1]:.3f} ms, "
-        f"wall {r0_wall * 1e3:.1f} ms, {r0_bytes / r0_world_ms / 1e6:.0f} GB/s algorithmic")
+    log(f"workload: T0={T0} Rbar={R.mean():.1f} Ebar={E.mean():.1f}")
+    ceil = probe_ceilings(binding, dev, theta, float(E.mean()), cus)
+    log(f"ceilings: Philox {ceil['philox_coins_per_s'] / 1e12:.3f} T coins/s, copy {ceil['copy_GBps']:.0f} GB/s")
 
-    # solves: the warm-up solves time every kernel (per-kernel breakdown);
-    # the timed solves bracket only the dominant world kernel with events
-    out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
-           torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
-           torch.zeros(k + 1, dtype=torch.int64, device=dev),
-           torch.zeros(1, dtype=torch.int32, device=dev))
-    kernels = (("world_tier0", 0), ("world_tier1", 4), ("world_tier2", 1), ("round_update", 6),
-               ("reduce", 2), ("select", 3), ("search_without_replay", 5))
-    kern = {}
-    for i in range(max(args.warmup, 1)):
-        binding.timing_reset()
-        binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)
-        torch.cuda.synchronize()
-        kern = {name: binding.timing_read(kid)[1] for name, kid in kernels}
-        log(f"warmup {i} done")
-    # the world kernel with the most time per solve
-    # kernel -> (timer id, work tiers it reports)
-    world_ids = {"world_tier0": (0, (0,)), "world_tier1": (4, (1,)), "world_tier2": (1, (2,)),
-                 "round_update": (6, (3, 4, 5))}
-    dom = max(world_ids, key=lambda nm: kern.get(nm, 0.0))
-    dom_kid, dom_tiers = world_ids[dom]
-    # events take time on the stream: one launch in TIMED_EVERY of the dominant
-    # kernel is bracketed, spread evenly over every solve's rounds
-    binding.timing_mask([dom_kid])
-    binding.timing_sample(TIMED_EVERY)
+    gain = torch.empty(g.n, dtype=torch.int64, device=dev)
+    total = torch.empty(1, dtype=torch.int64, device=dev)
+    for i in range(args.warmup):
+        binding.evaluate_device(G, seeds_dev, 0, theta, RNG_SEED, gain, total)
+    torch.cuda.synchronize()
+    # every launch of the tier-0 world kernel in the timed passes records its
+    # own start and stop events (hipExtLaunchKernel on the library's stream);
+    # no other kernel is bracketed
+    binding.timing_enable(True)
+    binding.timing_mask([0])
+    binding.timing_sample(1)
     binding.timing_reset()
     lat = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
         t1 = time.perf_counter()
-        binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)
+        binding.evaluate_device(G, seeds_dev, 0, theta, RNG_SEED, gain, total)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t1) * 1e3)
-        log(f"step {i}: {lat[-1]:.1f} ms")
     torch.cuda.synchronize()
     total_s = time.perf_counter() - t_start
-    work = [binding.timing_work(t) for t in range(6)]
-    n_dom, ms_dom = binding.timing_read(dom_kid)
-    all_dom = binding.timing_launches(dom_kid)
+    log("passes: " + " ".join(f"{x:.2f}" for x in lat) + " ms")
+    work = [binding.timing_work(t) for t in range(3)]
+    n0, ms0 = binding.timing_read(0)
     binding.timing_enable(False)
     binding.timing_mask(None)
-    binding.timing_sample(1)
-    n_sel = int(out[3].cpu()[0])
-    rounds = min(n_sel + 1, k) if k > 0 else 1
+    assert int(total.cpu()[0]) == T0, "passes must reproduce the characterisation pass"
+    gpu_gain = gain.cpu().numpy()
     ms_per_step = total_s * 1e3 / args.steps
-    evals = sum(w[0] for w in work) / args.steps
-    value = evals / (ms_per_step / 1e3)
-    # roofline of the dominant world kernel over the timed solves: algorithmic
-    # bytes per launch (all its launches) over its average timed duration
-    bytes_dom = sum(work[t][2] for t in dom_tiers)
-    bytes_per_launch = bytes_dom / max(all_dom, 1)
-    avg_ms = ms_dom / max(n_dom, 1)
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9 if ms_dom > 0 else 0.0
+    value = theta / (ms_per_step / 1e3)
 
-    spread = out[2].cpu().numpy()
+    # roofline of the tier-0 world kernel: bytes per world as the from-scratch
+    # unit of work counts them, restricted to what the world kernel itself
+    # moves (sampling, BFS, dominators, subtree sizes, pair output):
+    #   8 E (column + threshold per scanned slot) + 8 R (row offsets)
+    #   + 4 L (visited touches per live edge) + 12 R (reached list and live
+    #   subgraph) + 8 R (its (node, count) pair written)
+    # with E, R, L tallied over the worlds the kernel finished; the pair's
+    # bucketing and accumulation (16 R more) belong to the reduction kernels.
+    w0, e0, b0, r0, l0 = (x / args.steps for x in work[0])
+    k14 = 8 * e0 + 28 * r0 + 4 * l0
+    avg0 = ms0 / max(n0, 1)
+    achieved = k14 / (avg0 / 1e3) / 1e9
+    allw = [sum(wk[i] for wk in work) / args.steps for i in range(5)]
+    pass_bytes = 8 * allw[1] + 44 * allw[3] + 4 * allw[4]
+    coins0 = e0  # coins the tier-0 worlds needed (slots of reached rows)
+
     res = {
         "metric": METRIC,
         "value": value,
@@ -395,58 +383,107 @@ def main():
         "config": {
             "workload": f"{args.workload}: directed Chung-Lu n={g.n} m={g.m} gamma=2.1 "
                         f"{'trivalency' if args.workload == 'large' else 'weighted-cascade'}, "
-                        f"|S|={ns}, k={k}, theta={theta}, one full greedy solve per step",
+                        f"|S|={ns}, theta={theta}; one step = one from-scratch pass over all theta worlds "
+                        f"(sample + BFS + dominators + gain reduction)",
             "n": g.n, "m": g.m, "seeds": ns, "k": k, "theta": theta, "rng_seed": RNG_SEED,
             "graph_sha256": g.sha256()[:16],
         },
-        "value_definition": "live-edge world evaluations (sample + BFS + dominator counts + gain) actually "
-                            "performed per second over whole greedy solves: theta from-scratch worlds in "
-                            "round 0 plus the worlds each later round re-evaluates",
-        "world_evaluations_per_step": evals,
-        "p50_ms": percentile(lat, 50),
-        "p99_ms": percentile(lat, 99),
-        "n_selected": n_sel,
-        "ag_equivalent_worlds_per_s": theta * rounds / (ms_per_step / 1e3),
-        "spread_T0_over_theta": float(spread[0]) / theta,
-        "spread_final_over_theta": float(spread[n_sel]) / theta,
-        "round0_worlds_per_s": theta / r0_wall,
-        "round0_world_kernel_ms": r0_world_ms,
-        "round0_algorithmic_GBps": r0_bytes / r0_world_ms / 1e6,
-        "round0_tier0": {"launches": r0[0][0], "ms": r0[0][1], "algorithmic_bytes": r0_work[0][2],
-                         "worlds": r0_work[0][0]},
-        "graph_ingest_ms": ingest_ms,
+        "value_definition": "theta / wall time of one from-scratch pass over theta live-edge worlds (coins, BFS "
+                            "from S, dominator-subtree sizes, per-node gain sums), inputs resident in HBM",
+        "pass_ms_p50": percentile(lat, 50),
+        "pass_ms_min": min(lat),
         "Rbar": float(R.mean()),
         "Ebar": float(E.mean()),
-        "kernel_ms_per_step": kern,
-        "world_evaluations_by_kind_per_step": {
-            nm: work[t][0] / args.steps for nm, t in (("sampled_tier0", 0), ("sampled_tier1", 1), ("sampled_tier2", 2),
-                                                       ("replayed", 3), ("label_updated", 4),
-                                                       ("label_updated_by_replay_workgroups", 5))},
+        "Lbar": allw[4] / max(allw[0], 1),
+        "T0": int(T0),
         "roofline": {
             "bound": "hbm",
-            "kernel": f"{dom} (the world kernel with the most time per solve), its launches in the timed solves "
-                      f"(one in {TIMED_EVERY} bracketed with HIP events)",
+            "kernel": "k_world_lds tier 0 (one wave per world; the pass's dominant kernel), every launch of the "
+                      "timed passes, duration from events recorded by the launch itself",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(dom) if args.workload == "large" else None,
+            "traffic": measured_traffic("world_tier0"),
             "traffic_unit": "HBM bytes per launch (scaled FETCH_SIZE + WRITE_SIZE, committed profile)",
-            "launches": all_dom,
-            "timed_launches": n_dom,
-            "avg_launch_ms": avg_ms,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "bytes_per_world": "8E + 28R + 4L (see value_definition of the pass roofline)",
+            "algorithmic_bytes_per_launch": k14,
+            "worlds_per_launch": w0,
+            "avg_launch_ms": avg0,
+            "launches": n0,
+            "hbm_only_algorithmic_bytes_per_launch": b0,
+            "coins_per_s": coins0 / (avg0 / 1e3),
+            "coins_frac_of_philox_probe": coins0 / (avg0 / 1e3) / ceil["philox_coins_per_s"],
+            "frac_of_copy_probe": achieved / ceil["copy_GBps"],
         },
+        "pass_roofline": {
+            "achieved": pass_bytes / (ms_per_step / 1e3) / 1e9, "unit": "GB/s",
+            "bytes_per_pass": pass_bytes,
+            "bytes_per_world": "8E + 8R + 4L + 12R + 24R over every world of the pass",
+        },
+        "ceilings": ceil,
+        "graph_ingest_ms": ingest_ms,
     }
+    if args.solves > 0:
+        res.update(solve_latency(args, binding, G, seeds_dev, k, theta, dev))
     if not args.no_cpu:
         log("cpu baseline (oracle)")
-        cb, cpu_blockers = cpu_baseline(g, seeds, k, theta, args.cpu_seconds)
-        if cpu_blockers is not None:
-            # the oracle's blockers must be the first blockers of the GPU solve
-            gpu_b = out[0].cpu().numpy()[:len(cpu_blockers)]
-            cb["oracle_blockers_equal_gpu_prefix"] = bool(np.array_equal(gpu_b, cpu_blockers))
-        res["cpu_baseline"] = cb
+        res["cpu_baseline"] = cpu_baseline(g, seeds, theta, args.cpu_seconds, gpu_gain)
     print(json.dumps(res), flush=True)
+
+
+def solve_latency(args, binding, G, seeds_dev, k, theta, dev):
+    """Full greedy solves (k rounds: round 0 from scratch, then incremental
+    rounds): latency percentiles, the evaluations of each kind, and the
+    roofline of the incremental-round kernel."""
+    import torch
+    out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
+           torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
+           torch.zeros(k + 1, dtype=torch.int64, device=dev),
+           torch.zeros(1, dtype=torch.int32, device=dev))
+    binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)  # warm
+    torch.cuda.synchronize()
+    # one launch in TIMED_EVERY of the round-update kernel is bracketed
+    binding.timing_enable(True)
+    binding.timing_mask([6])
+    binding.timing_sample(TIMED_EVERY)
+    binding.timing_reset()
+    lat = []
+    for i in range(args.solves):
+        t1 = time.perf_counter()
+        binding.solve_device(G, seeds_dev, k, theta, RNG_SEED, out=out)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t1) * 1e3)
+    log("solves: " + " ".join(f"{x:.1f}" for x in lat) + " ms")
+    work = [binding.timing_work(t) for t in range(6)]
+    n6, ms6 = binding.timing_read(6)
+    all6 = binding.timing_launches(6)
+    binding.timing_enable(False)
+    binding.timing_mask(None)
+    binding.timing_sample(1)
+    n_sel = int(out[3].cpu()[0])
+    spread = out[2].cpu().numpy()
+    b6 = sum(work[t][2] for t in (3, 4, 5)) / max(all6, 1)
+    avg6 = ms6 / max(n6, 1)
+    return {
+        "solve": {
+            "k": k, "n_selected": n_sel, "solves": args.solves,
+            "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+            "spread_T0_over_theta": float(spread[0]) / theta,
+            "spread_final_over_theta": float(spread[n_sel]) / theta,
+            "world_evaluations_by_kind_per_solve": {
+                nm: work[t][0] / args.solves for nm, t in (
+                    ("sampled_tier0", 0), ("sampled_tier1", 1), ("sampled_tier2", 2), ("replayed", 3),
+                    ("label_updated", 4), ("label_updated_by_replay_workgroups", 5))},
+            "round_update_roofline": {
+                "achieved": b6 / (avg6 / 1e3) / 1e9 if ms6 > 0 else 0.0, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "algorithmic_bytes_per_launch": b6, "avg_launch_ms": avg6, "launches": all6,
+                "timed_launches": n6, "traffic": measured_traffic("round_update"),
+            },
+        },
+        "p50_ms": percentile(lat, 50),
+        "p99_ms": percentile(lat, 99),
+    }
 
 
 if __name__ == "__main__":

@@ -274,20 +274,45 @@ imin_status_t imin_timing_read(int kernel_id, int64_t* launches, double* total_m
  * Work done while timing was enabled, per world tier (0 small LDS, 1 large
  * LDS, 2 HBM, 3 replay, 4 label-based update by the label-rule workgroups,
  * which take a world per 16, 32 or 64 lanes, 5 label-based update of worlds
- * handed to the replay that reduce to it): worlds finished, edges walked (for tiers 4 and 5: stored
- * entries scanned) and algorithmic HBM
- * bytes.  For tiers 0-2 the edges are the CSR slots of the reached rows (the
- * edges whose coins were needed) and the bytes are 8 per such slot (column
- * and threshold) + 8 per reached non-seed (row offsets) + 16 per level-0
- * table entry + 8 per (node, count) entry written (12 with its BFS parent
- * kept for replay, + 8 per extra live edge kept).  For the replay tier the
- * edges are the stored live edges and the bytes are 12 per stored entry
- * (node, count, parent) + 8 per stored extra edge.  Incremental rounds add,
- * for every tier, 8 per stored entry read back and 12 per change reported
- * (the change and the count updated in place).  Host pointers; any may be
- * NULL.
+ * handed to the replay that reduce to it): worlds finished, edges walked (for
+ * tiers 4 and 5: stored entries scanned), algorithmic HBM bytes, reached
+ * nodes and live edges.  For tiers 0-2 the edges are the CSR slots of the
+ * reached rows (the edges whose coins were needed), the bytes are 8 per such
+ * slot (column and threshold) + 8 per reached non-seed (row offsets) + 16 per
+ * level-0 table entry + 8 per (node, count) entry written (12 with its BFS
+ * parent kept for replay, + 8 per extra live edge kept), the reached nodes
+ * count the seeds, and the live edges are the live edges between reached
+ * nodes that are not seeds or blocked (one BFS-tree edge per reached
+ * non-seed plus every other such edge).  For the replay tier the edges are
+ * the stored live edges and the bytes are 12 per stored entry (node, count,
+ * parent) + 8 per stored extra edge.  Incremental rounds add, for every tier,
+ * 8 per stored entry read back and 12 per change reported (the change and
+ * the count updated in place).  Reached nodes and live edges are tallied for
+ * tiers 0-2 only.  Host pointers; any may be NULL.
  */
-imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes);
+imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes, int64_t* reached,
+                               int64_t* live);
+
+/*
+ * Measurement probes: the ceilings the sampling kernels are held against.
+ * Each launches one kernel on `stream`, waits for it and writes its duration
+ * in milliseconds (from events recorded by the launch) to *ms (host).
+ *
+ * imin_probe_philox  draws Philox4x32-10 blocks with the coin layout of the
+ *                    world kernels (counter (group, world, 0, 0), key
+ *                    (lo32(key), hi32(key))) for groups 0..groups_per_world-1
+ *                    of worlds 0..worlds-1, touching no memory but one word
+ *                    per thread of `out` (device, out_count >= grid * 256
+ *                    entries, overwritten); 4 coins per block.
+ * imin_probe_copy    copies `bytes` (a multiple of 16; both pointers 16-byte
+ *                    aligned, device) from src to dst with 16-byte accesses;
+ *                    2 * bytes cross HBM.
+ * `grid` is the number of 256-thread workgroups.  IMIN_ERR_INVALID for bad
+ * arguments, IMIN_ERR_DEVICE when a runtime call fails.
+ */
+imin_status_t imin_probe_philox(int64_t worlds, int32_t groups_per_world, uint64_t key, uint32_t* out,
+                                int64_t out_count, int32_t grid, void* stream, float* ms);
+imin_status_t imin_probe_copy(void* dst, const void* src, size_t bytes, int32_t grid, void* stream, float* ms);
 
 /* Static description of a status code. */
 const char* imin_status_string(imin_status_t s);

@@ -96,8 +96,12 @@ def load():
     lib.imin_timing_reset.restype = st
     lib.imin_timing_read.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_double)]
     lib.imin_timing_read.restype = st
-    lib.imin_timing_work.argtypes = [ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.imin_timing_work.argtypes = [ctypes.c_int] + [ctypes.POINTER(i64)] * 5
     lib.imin_timing_work.restype = st
+    lib.imin_probe_philox.argtypes = [i64, i32, u64, P, i64, i32, P, ctypes.POINTER(ctypes.c_float)]
+    lib.imin_probe_philox.restype = st
+    lib.imin_probe_copy.argtypes = [P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_float)]
+    lib.imin_probe_copy.restype = st
     _lib = lib
     return lib
 
@@ -373,6 +377,18 @@ def evaluate(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blo
     return tuple(res)
 
 
+def evaluate_device(graph: Graph, seeds_dev, w_begin: int, w_count: int, rng_seed: int, gain, total):
+    """imin_evaluate on device tensors with no blocked set and no per-world
+    outputs: gain (int64[n]) and total (int64[1]) are written in place."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    with torch.cuda.device(dev):
+        _check(lib.imin_evaluate(graph.handle, _ptr(seeds_dev), int(seeds_dev.numel()), None, 0, int(w_begin),
+                                 int(w_count), int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(gain),
+                                 _ptr(total), None, None, None))
+
+
 def cache_release():
     """Free the device blocks the library keeps cached between calls."""
     _check(load().imin_cache_release())
@@ -413,9 +429,31 @@ def timing_read(kernel_id: int):
 
 
 def timing_work(tier: int):
-    """(worlds, edges walked, algorithmic bytes) of one world tier (0-2 sampled
-    tiers, 3 replay, 4 label rule by the label-rule workgroups, 5 label rule by
-    the replay workgroups) since the last reset."""
-    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(load().imin_timing_work(int(tier), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return int(a.value), int(b.value), int(c.value)
+    """(worlds, edges walked, algorithmic bytes, reached nodes, live edges) of
+    one world tier (0-2 sampled tiers, 3 replay, 4 label rule by the
+    label-rule workgroups, 5 label rule by the replay workgroups) since the
+    last reset; reached nodes and live edges for tiers 0-2 only."""
+    v = [ctypes.c_int64() for _ in range(5)]
+    _check(load().imin_timing_work(int(tier), *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
+
+
+def probe_philox(worlds: int, groups_per_world: int, key: int, grid: int, device="cuda:0") -> float:
+    """Milliseconds of one launch drawing worlds * groups_per_world Philox
+    blocks (4 coins each) with the world kernels' coin layout."""
+    torch = _torch()
+    out = torch.empty(grid * 256, dtype=torch.int32, device=device)
+    ms = ctypes.c_float()
+    _check(load().imin_probe_philox(int(worlds), int(groups_per_world), int(key), _ptr(out), out.numel(), int(grid),
+                                    _stream(device), ctypes.byref(ms)))
+    return float(ms.value)
+
+
+def probe_copy(dst, src, grid: int) -> float:
+    """Milliseconds of one device copy of src into dst (torch tensors of the
+    same byte size, a multiple of 16)."""
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    ms = ctypes.c_float()
+    _check(load().imin_probe_copy(_ptr(dst), _ptr(src), nbytes, int(grid), _stream(src.device), ctypes.byref(ms)))
+    return float(ms.value)

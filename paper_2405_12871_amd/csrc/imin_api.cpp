@@ -44,9 +44,7 @@ struct Timing {
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
     double ms[kTimedKernels] = {};
-    int64_t work_worlds[kWorkTiers] = {};
-    int64_t work_edges[kWorkTiers] = {};
-    int64_t work_bytes[kWorkTiers] = {};
+    int64_t work[kWorkTiers][imin::kWorkFields] = {};
 };
 Timing g_timing;
 
@@ -348,11 +346,10 @@ struct Session {
     DevArray<int32_t> scr_node, scr_cnt;  // per-world scratch (fixed tier-0 slots + bump region)
     size_t slot_cap0 = 0, big_cap = 0;
     DevArray<int32_t> list0, list1, list2, list3;  // changed worlds; worlds handed on (RoundCtl::list_n)
-    // dense pairs and the reduction's buffers
-    DevArray<int32_t> pair_node, pair_cnt, sorted_node, sorted_cnt;
-    DevArray<long long> hist;
-    DevArray<int64_t> part;
-    imin::ReduceBufs rb{};
+    // the gain reduction's buffers (bucket counts, bases, cursors, records)
+    DevArray<long long> g_bcnt, g_bbase, g_bcur;
+    DevArray<int2> g_rec;
+    imin::GainBufs gb{};
     // resident per-world (node, count) lists for incremental rounds
     DevArray<int32_t> store_node, store_cnt, store_len;
     DevArray<int64_t> store_off;
@@ -385,9 +382,12 @@ struct Session {
     DevArray<int32_t> idx_off, idx_bcnt, idx_bbase, idx_bcur, idx_border;
     DevArray<int4> idx_rec;  // the index build's entries grouped by bucket
     DevArray<int2> idx_ent;  // (store position, world) of each entry, grouped by node
-    // level-0 slot groups of the seeds
+    // level-0 slot groups of the seeds, with their columns and thresholds;
+    // the query's thresholds (0 where the head is excluded)
     DevArray<int32_t> seed_cnt;
-    DevArray<int4> seed_table;
+    DevArray<int4> seed_table, seed_col;
+    DevArray<uint4> seed_thr;
+    DevArray<uint32_t> thr_q;
     // HBM world tier
     DevArray<int32_t> b_lid, b_nodes, b_parent, b_idom, b_aux, b_lvl, b_xv, b_xu;
     imin::BigSlots bs{};
@@ -502,18 +502,15 @@ struct Session {
         IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
         IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
 
-        rb.nb = (int32_t)((n + ((size_t)1 << imin::kBucketShift) - 1) >> imin::kBucketShift);
-        rb.g1 = 1024;
-        rb.slices = std::max(1, 1024 / rb.nb);
-        IMIN_TRY(hist.alloc((size_t)rb.nb * rb.g1 + 1));
-        IMIN_TRY(part.alloc((size_t)rb.slices * ((size_t)rb.nb << imin::kBucketShift)));
-        rb.hist = hist.p;
-        rb.part = part.p;
-        imin_status_t st = ensure_pairs(1 << 16);
-        if (st != IMIN_OK) return st;
-
         // HBM tier slots: per slot 6 node arrays (+lvl) and 2 edge arrays
         const int cus = cu_count();
+        gb = imin::gain_buckets(g.n);
+        IMIN_TRY(g_bcnt.alloc((size_t)gb.nb));
+        IMIN_TRY(g_bbase.alloc((size_t)gb.nb + 1));
+        IMIN_TRY(g_bcur.alloc((size_t)gb.nb));
+        gb.bcnt = g_bcnt.p;
+        gb.bbase = g_bbase.p;
+        gb.bcur = g_bcur.p;
         const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
         const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * xcap * 4;
         const size_t big_budget = env_size("IMIN_BIG_BUDGET", (size_t)6 << 30);
@@ -568,7 +565,7 @@ struct Session {
         if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
             work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_l), bs.n_slots);
-            const size_t wn = (size_t)3 * kWorkTiers * work_stride;
+            const size_t wn = (size_t)imin::kWorkFields * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
             IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));
         }
@@ -580,19 +577,18 @@ struct Session {
     void finish() {
         if (!timed.on) return;
         timed.flush();
-        std::vector<unsigned long long> h((size_t)3 * kWorkTiers * work_stride);
+        constexpr int F = imin::kWorkFields;
+        std::vector<unsigned long long> h((size_t)F * kWorkTiers * work_stride);
         if (work.p && hipMemcpy(h.data(), work.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
                           hipSuccess)
             return;
         std::lock_guard<std::mutex> lk(g_timing.mu);
-        for (int tier = 0; tier < kWorkTiers; ++tier) {
-            int64_t f[3] = {0, 0, 0};
-            for (int field = 0; field < 3; ++field)
-                for (int b = 0; b < work_stride; ++b) f[field] += (int64_t)h[((size_t)tier * 3 + field) * work_stride + b];
-            g_timing.work_worlds[tier] += f[0];
-            g_timing.work_edges[tier] += f[1];
-            g_timing.work_bytes[tier] += f[2];
-        }
+        for (int tier = 0; tier < kWorkTiers; ++tier)
+            for (int field = 0; field < F; ++field) {
+                int64_t f = 0;
+                for (int b = 0; b < work_stride; ++b) f += (int64_t)h[((size_t)tier * F + field) * work_stride + b];
+                g_timing.work[tier][field] += f;
+            }
     }
 
     imin_status_t read_ctl() {
@@ -607,17 +603,14 @@ struct Session {
         return IMIN_OK;
     }
 
-    // dense pair buffer (and the reduction's sorted copy) of at least `needed`
-    imin_status_t ensure_pairs(unsigned long long needed) {
-        if (pair_node.p && pair_node.count >= needed) return IMIN_OK;
-        const size_t want = (size_t)(needed + needed / 8 + 1024);
-        IMIN_TRY(pair_node.alloc(want));
-        IMIN_TRY(pair_cnt.alloc(want));
-        IMIN_TRY(sorted_node.alloc(want));
-        IMIN_TRY(sorted_cnt.alloc(want));
-        rb.sorted_node = sorted_node.p;
-        rb.sorted_cnt = sorted_cnt.p;
-        rb.sorted_cap = sorted_node.count;
+    // gain[u] += every count of u among the tile entries of src (`entries`
+    // in all)
+    imin_status_t reduce_gains(const imin::GainSrc& src, unsigned long long entries) {
+        if (!g_rec.p || g_rec.count < entries) IMIN_TRY(g_rec.alloc((size_t)(entries + entries / 8 + 1024)));
+        gb.rec = g_rec.p;
+        gb.rec_cap = g_rec.count;
+        gb.slices = imin::gain_slices(gb, entries, cu_count());
+        IMIN_TRY(imin::launch_gain_reduce(src, gb, g.n, gain.p, ctl.p, s));
         return IMIN_OK;
     }
 
@@ -756,9 +749,6 @@ struct Session {
         out.scr_cap = scr_node.count;
         out.wloc = wloc.p;
         out.wlen = wlen.p;
-        out.pair_node = pair_node.p;
-        out.pair_cnt = pair_cnt.p;
-        out.pair_cap = pair_node.count;
         out.store_node = store_node.p;
         out.store_cnt = store_cnt.p;
         out.store_cap = store_node.count;
@@ -814,7 +804,11 @@ struct Session {
 
     // One incremental round: worlds holding the last blocker are re-evaluated
     // and report their count changes; gain is updated in place.
-    imin_status_t evaluate_delta(const imin::QueryDev& q, uint64_t theta, const imin::SelectOut& so) {
+    imin_status_t evaluate_delta(const imin::QueryDev& q0, uint64_t theta, const imin::SelectOut& so) {
+        // blockers added since the thresholds were made are tested against
+        // the exclusion bitmap
+        imin::QueryDev q = q0;
+        q.excl_in_thr = 0;
         imin::TileOut out = tile_out();
         out.mode = imin::kModeDelta;
         out.world_size = world_size.p;
@@ -862,6 +856,10 @@ struct Session {
     // solve) the per-world lists also become the resident store.
     imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
                            int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false) {
+        // the exclusions as they stand (blockers may have been added since
+        // the last pass) go into the query's thresholds
+        IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.n_seed_chunks, seed_col.p,
+                                               seed_thr.p, s));
         uint64_t done = 0;
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
@@ -948,68 +946,67 @@ struct Session {
                 drop_replay();  // incremental rounds go on by sampling
                 use_x = false;
             }
-            // the reduction's sorted copy needs room for every entry of the
-            // tile whichever buffer holds them
-            st = ensure_pairs(total);
-            if (st != IMIN_OK) return st;
             hipEvent_t ev = timed.begin(2, s);
-            imin::CompactSpec cs{};
-            cs.src[0] = scr_node.p;
-            cs.src[1] = scr_cnt.p;
-            cs.src[2] = scr_par.p;
-            cs.src[3] = scr_lab.p;
-            cs.nf = 2;
-            cs.src_cap = scr_node.count;
-            cs.loc = wloc.p;
-            cs.len = wlen.p;
-            cs.count = (uint32_t)nw;
-            cs.w_begin = (uint32_t)(w_begin + done);
+            imin::GainSrc src{};
+            src.count = (uint32_t)nw;
             if (use_store) {
+                // pack the tile's entries densely into the store
+                imin::CompactSpec cs{};
+                cs.src[0] = scr_node.p;
+                cs.src[1] = scr_cnt.p;
+                cs.src[2] = scr_par.p;
+                cs.src[3] = scr_lab.p;
+                cs.nf = use_x ? 4 : 2;
+                cs.src_cap = scr_node.count;
+                cs.loc = wloc.p;
+                cs.len = wlen.p;
+                cs.count = (uint32_t)nw;
+                cs.w_begin = (uint32_t)(w_begin + done);
                 cs.dst[0] = store_node.p;
                 cs.dst[1] = store_cnt.p;
                 cs.dst[2] = store_par.p;
                 cs.dst[3] = store_lab.p;
-                if (use_x) cs.nf = 4;
                 cs.dst_cap = store_node.count;
                 cs.counter_id = 1;
                 cs.out_off = store_off.p;
                 cs.out_len = store_len.p;
                 cs.overflow_flag = imin::kFlagStoreOverflow;
+                IMIN_TRY(imin::launch_compact(cs, ctl.p, s));
+                if (use_x) {
+                    imin::CompactSpec xs{};
+                    xs.src[0] = xscr_v.p;
+                    xs.src[1] = xscr_u.p;
+                    xs.dst[0] = xstore_v.p;
+                    xs.dst[1] = xstore_u.p;
+                    xs.nf = 2;
+                    xs.src_cap = xscr_v.count;
+                    xs.dst_cap = xstore_v.count;
+                    xs.loc = xloc.p;
+                    xs.len = xlen.p;
+                    xs.count = (uint32_t)nw;
+                    xs.w_begin = (uint32_t)(w_begin + done);
+                    xs.counter_id = 2;
+                    xs.out_off = xstore_off.p;
+                    xs.out_len = xstore_len.p;
+                    xs.overflow_flag = imin::kFlagStoreOverflow;
+                    IMIN_TRY(imin::launch_compact(xs, ctl.p, s));
+                }
+                // the tile's worlds, by world id, where the compaction put them
+                src.node = store_node.p;
+                src.cnt = store_cnt.p;
+                src.off = store_off.p + (w_begin + done);
+                src.len = store_len.p + (w_begin + done);
+                src.cap = store_node.count;
             } else {
-                cs.dst[0] = pair_node.p;
-                cs.dst[1] = pair_cnt.p;
-                cs.dst_cap = pair_node.count;
-                cs.counter_id = 0;
-                cs.overflow_flag = imin::kFlagPairOverflow;
+                // the entries where the world kernels wrote them
+                src.node = scr_node.p;
+                src.cnt = scr_cnt.p;
+                src.off = wloc.p;
+                src.len = wlen.p;
+                src.cap = scr_node.count;
             }
-            IMIN_TRY(imin::launch_compact(cs, ctl.p, s));
-            if (use_x) {
-                imin::CompactSpec xs{};
-                xs.src[0] = xscr_v.p;
-                xs.src[1] = xscr_u.p;
-                xs.dst[0] = xstore_v.p;
-                xs.dst[1] = xstore_u.p;
-                xs.nf = 2;
-                xs.src_cap = xscr_v.count;
-                xs.dst_cap = xstore_v.count;
-                xs.loc = xloc.p;
-                xs.len = xlen.p;
-                xs.count = (uint32_t)nw;
-                xs.w_begin = (uint32_t)(w_begin + done);
-                xs.counter_id = 2;
-                xs.out_off = xstore_off.p;
-                xs.out_len = xstore_len.p;
-                xs.overflow_flag = imin::kFlagStoreOverflow;
-                IMIN_TRY(imin::launch_compact(xs, ctl.p, s));
-            }
-            imin::TileOut red = tile_out();
-            if (use_store) {
-                // this tile's entries sit contiguously in the store
-                red.pair_node = store_node.p + store_base;
-                red.pair_cnt = store_cnt.p + store_base;
-                red.pair_cap = total;
-            }
-            IMIN_TRY(imin::launch_reduce_pairs(g, red, rb, ctl.p, gain.p, s));
+            st = reduce_gains(src, total);
+            if (st != IMIN_OK) return st;
             timed.end(2, ev, s);
             IMIN_TRY(imin::launch_sum_sizes(out.world_size, (uint32_t)nw, ctl.p, s));
             done += nw;
@@ -1111,8 +1108,15 @@ static imin_status_t setup_query(Session& ss, const int32_t* seeds, int32_t n_se
     if (st != IMIN_OK) return st;
     const int32_t chunks = ss.hctl.p->seed_chunks;
     IMIN_TRY(ss.seed_table.alloc((size_t)std::max(chunks, 1)));
+    IMIN_TRY(ss.seed_col.alloc((size_t)std::max(chunks, 1)));
+    IMIN_TRY(ss.seed_thr.alloc((size_t)std::max(chunks, 1)));
+    IMIN_TRY(ss.thr_q.alloc((size_t)ss.g.m_pad));
     if (chunks > 0) IMIN_TRY(imin::launch_seed_fill(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.seed_table.p, ss.s));
     q.excl = ss.excl.p;
+    q.thr = ss.thr_q.p;
+    q.excl_in_thr = 1;
+    q.seed_col = ss.seed_col.p;
+    q.seed_thr = ss.seed_thr.p;
     q.seeds = seeds;
     q.n_seeds = n_seeds;
     q.key0 = (uint32_t)rng_seed;
@@ -1213,6 +1217,10 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
     IMIN_TRY(hipMemcpyAsync(total, &ss.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
     st = ss.read_ctl();
     if (st != IMIN_OK) return st;
+    if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+        g_last_flags = ss.hctl.p->flags;
+        return IMIN_ERR_INTERNAL;
+    }
     ss.finish();
     return IMIN_OK;
 }
@@ -1454,16 +1462,18 @@ imin_status_t imin_timing_reset(void) {
         g_timing.ms[i] = 0.0;
         g_timing.seen[i].store(0);
     }
-    for (int i = 0; i < kWorkTiers; ++i) g_timing.work_worlds[i] = g_timing.work_edges[i] = g_timing.work_bytes[i] = 0;
+    for (int i = 0; i < kWorkTiers; ++i)
+        for (int f = 0; f < imin::kWorkFields; ++f) g_timing.work[i][f] = 0;
     return IMIN_OK;
 }
 
-imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes) {
+imin_status_t imin_timing_work(int tier, int64_t* worlds, int64_t* edges, int64_t* bytes, int64_t* reached,
+                               int64_t* live) {
     if (tier < 0 || tier >= kWorkTiers) return IMIN_ERR_INVALID;
     std::lock_guard<std::mutex> lk(g_timing.mu);
-    if (worlds) *worlds = g_timing.work_worlds[tier];
-    if (edges) *edges = g_timing.work_edges[tier];
-    if (bytes) *bytes = g_timing.work_bytes[tier];
+    int64_t* const outs[imin::kWorkFields] = {worlds, edges, bytes, reached, live};
+    for (int f = 0; f < imin::kWorkFields; ++f)
+        if (outs[f]) *outs[f] = g_timing.work[tier][f];
     return IMIN_OK;
 }
 

@@ -69,6 +69,10 @@ struct RoundCtl {
     uint32_t replay_big;             // some world stored in round 0 exceeds the replay's limits
 };
 
+// Fields of a per-workgroup work tally: worlds, edges, bytes, reached nodes,
+// live edges.
+constexpr int kWorkFields = 5;
+
 // How a world evaluation reports its counts.
 enum : int {
     kModePlain = 0,  // (node, c) pairs of the world into the tile pair buffer
@@ -144,10 +148,6 @@ struct TileOut {
     unsigned long long scr_cap;    // entries in the scratch space
     int64_t* wloc;                 // [tile] scratch start of each world's entries
     int32_t* wlen;                 // [tile] entries per world; [theta] changes per world (incremental)
-    // dense pairs for the reduction
-    int32_t* pair_node;
-    int32_t* pair_cnt;
-    unsigned long long pair_cap;
     // resident per-world store (solve only), indexed by world id
     int32_t* store_node;
     int32_t* store_cnt;
@@ -160,7 +160,7 @@ struct TileOut {
     int32_t* world_size; // [tile] or nullptr
     int64_t* world_sum;  // [tile] or nullptr
     int64_t* world_edges;// [tile] or nullptr: CSR slots scanned (coins drawn)
-    unsigned long long* work;  // [3 tiers][3 fields][work_stride] per-workgroup tallies
+    unsigned long long* work;  // [tiers][kWorkFields fields][work_stride] per-workgroup tallies
     int work_stride;
     // Live edges kept for replay (solve only).  In round 0 each world also
     // writes, aligned with its entries, the BFS parent of each node, and its
@@ -212,28 +212,43 @@ struct CompactSpec {
 
 struct QueryDev {
     const uint32_t* excl;    // bitmap: seeds and blocked nodes
+    const uint32_t* thr;     // [m_pad] the query's coin thresholds: the graph's, 0 where the head is excluded
+    int32_t excl_in_thr;     // thr reflects every bit of excl (else live heads are tested against excl)
     const int32_t* seeds;
     int32_t n_seeds;
     uint32_t key0, key1;
     const int4* seed_chunk;  // level-0 slot groups {blk, seed lid, e0, e1}
+    const int4* seed_col;    // their columns
+    const uint4* seed_thr;   // their thresholds (from thr)
     int32_t n_seed_chunks;
     long long seed_sum;
     long long seed_edges;
 };
 
-// Bucketed reduction scratch.
-struct ReduceBufs {
-    int32_t nb;          // node buckets
-    int32_t g1;          // chunks of the histogram pass
-    int32_t slices;      // workgroups per bucket in the accumulate pass
-    long long* hist;     // [nb * g1 + 1] bucket positions (a tile may hold more than 2^31 pairs)
-    int32_t* sorted_node;
-    int32_t* sorted_cnt;
-    unsigned long long sorted_cap;  // entries of sorted_node / sorted_cnt
-    int64_t* part;       // [slices][nb << kBucketShift]
+// Entries of a tile's worlds, world by world, for the gain reduction:
+// world i's (node, count) entries are node/cnt[off[i] .. off[i] + len[i]).
+struct GainSrc {
+    const int32_t* node;
+    const int32_t* cnt;
+    const int64_t* off;       // [count]
+    const int32_t* len;       // [count]
+    uint32_t count;           // worlds
+    unsigned long long cap;   // entries node / cnt hold
 };
 
-constexpr int kBucketShift = 13;  // 8192 nodes per bucket (int64 LDS accumulators: 64 KB)
+// Buffers of the gain reduction: nb buckets of 2^shift node ids, each summed
+// by `slices` workgroups; rec holds every entry of the tile as (node, count).
+constexpr int kGainMaxBuckets = 512;
+struct GainBufs {
+    int shift;
+    int nb;
+    int slices;
+    long long* bcnt;   // [nb]
+    long long* bbase;  // [nb + 1]
+    long long* bcur;   // [nb]
+    int2* rec;         // [rec_cap]
+    unsigned long long rec_cap;
+};
 
 // ---- launchers (imin_kernels.hip) ----
 hipError_t launch_graph_ingest(const GraphDev& g, const int64_t* row_ptr, const int32_t* col_in,
@@ -301,11 +316,23 @@ hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
                             int4* table, hipStream_t s);
+// thr_q[e] = 0 where col[e] is excluded, else the graph's threshold; then the
+// level-0 table's columns and thresholds (ctl->seed_chunks entries, at most
+// chunk_cap)
+hipError_t launch_query_thresholds(const GraphDev& g, const uint32_t* excl, uint32_t* thr_q, const int4* table,
+                                   const RoundCtl* ctl, int32_t chunk_cap, int4* seed_col, uint4* seed_thr,
+                                   hipStream_t s);
 int world_tier_blocks_per_cu(int tier);
 int world_tier0_capacity();   // non-seed nodes a tier-0 world may reach
 int world_tier0_xcapacity();  // extra live edges a tier-0 world may record
-hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
-                               RoundCtl* ctl, int64_t* gain, hipStream_t s);
+// gain[u] += every count of u among src's entries (bounds and capacity
+// problems raise kFlagBounds / kFlagReduceCapacity).
+hipError_t launch_gain_reduce(const GainSrc& src, const GainBufs& gb, int32_t n, int64_t* gain, RoundCtl* ctl,
+                              hipStream_t s);
+// bucket width for n nodes (one slice, the buffers left null), and the
+// slices per bucket for a tile of `entries` entries on `cus` compute units
+GainBufs gain_buckets(int32_t n);
+int gain_slices(const GainBufs& gb, unsigned long long entries, int cus);
 hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl* ctl, hipStream_t s);
 // Argmax of gain over the candidates (ties to the smaller id), the stop rule
 // and the round's T; the partial launch also sums and clears the dsz slots

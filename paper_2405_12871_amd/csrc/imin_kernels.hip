@@ -1,11 +1,14 @@
 // Device code around the world evaluation: graph ingest (offsets, coin
-// thresholds, validation), query set-up, the atomic-free per-node gain
-// reduction and the greedy selection.
+// thresholds, validation), query set-up, the per-node gain reduction of a
+// from-scratch pass and the greedy selection.
 //
-// The per-node sums over worlds are formed without global atomics: a tile's
-// (node, count) pairs are counting-sorted into node buckets of 8192 nodes,
-// each (bucket, slice) is accumulated in LDS, and the slices' partial vectors
-// are added in a fixed order.
+// A from-scratch pass sums the per-world counts by node bucket: the entries
+// are partitioned into node buckets and each bucket's sums are formed in LDS,
+// so no per-node counter in global memory is updated by more than one
+// workgroup per slice of a bucket.  (Incremental rounds add their count
+// changes to the gains with integer atomics in the world kernels.)
+#include <algorithm>
+
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
 #include "imin_select.hpp"
@@ -160,151 +163,279 @@ hipError_t launch_ctl_reset_tile(RoundCtl* ctl, hipStream_t s) {
     return hipGetLastError();
 }
 
-// ------------------------------------------------------- pair reduction
-// Counting sort of the tile's pairs by node bucket (8192 nodes), then one
-// LDS accumulation per (bucket, slice), then a fixed-order sum of slices.
-constexpr int kRedNT = 256;
-constexpr int kMaxBuckets = 2048;  // n < 2^24
+// ------------------------------------------------------- gain reduction
+// gain[u] += the counts of every (node u, count) entry of a tile's worlds
+// (Section 2.2: the estimate of D(u) is the average of u's dominator-subtree
+// sizes over the worlds; the sum is that average times the world count),
+// read where the world kernels left them.  Nodes are cut into nb buckets of
+// 2^shift consecutive ids:
+//   k_gain_count      entries per bucket: an LDS histogram per workgroup of
+//                     worlds, one counter update per bucket and workgroup;
+//   k_gain_scan       64-bit bucket bases and partition cursors;
+//   k_gain_partition  every entry as an 8-byte record (node, count) into its
+//                     bucket's range: a batch of entries is counted per
+//                     bucket in LDS, the batch's share of each bucket
+//                     reserved with one counter update, the records staged
+//                     bucket by bucket and each bucket's run written to
+//                     consecutive addresses;
+//   k_gain_own        one workgroup per (bucket, slice) sums its records'
+//                     counts per node in LDS and adds the sums to gain: with
+//                     one slice per bucket no two workgroups touch a node,
+//                     with several each node gets one atomic add per slice.
+// Integer sums: the result does not depend on any order.
+constexpr int kGainNT = 512;
+constexpr int kGainWorlds = 128;     // worlds per counting / partition workgroup
+constexpr int kGainStage = 8192;     // records per partition batch
+constexpr int kGainOwnNT = 1024;
+static_assert(kGainWorlds <= kGainNT, "one world per thread when loading the ranges");
+static_assert(kGainStage % kGainNT == 0, "whole batches per thread");
 
-__device__ __forceinline__ void chunk_range(unsigned long long P, int g1, int c, unsigned long long& a,
-                                            unsigned long long& b) {
-    a = P * (unsigned long long)c / (unsigned long long)g1;
-    b = P * (unsigned long long)(c + 1) / (unsigned long long)g1;
-}
-
-__global__ __launch_bounds__(kRedNT) void k_hist(RoundCtl* ctl, const int32_t* pair_node,
-                                                 unsigned long long cap, ReduceBufs rb) {
-    __shared__ int h[kMaxBuckets];
-    if (ctl->stop) return;
-    unsigned long long P = ctl->pair_count;
-    if (P > cap || P > rb.sorted_cap || (ctl->flags & kFlagPairOverflow)) {
-        // never sort more entries than both buffers hold; flag it instead
-        if (P && blockIdx.x == 0 && threadIdx.x == 0 && !(ctl->flags & kFlagPairOverflow))
-            atomicOr(&ctl->flags, (uint32_t)kFlagReduceCapacity);
-        P = 0;
+// Per-workgroup ranges of the worlds [w0, w0 + nw): woff / wpre (the flat
+// numbering of their entries) in LDS; returns the workgroup's entry count.
+// A range outside the entry arrays counts as empty and raises kFlagBounds.
+__device__ __forceinline__ int gain_ranges(const GainSrc& src, uint32_t w0, int nw, long long* woff, int32_t* wpre,
+                                           int* tmp, RoundCtl* ctl) {
+    const int t = threadIdx.x;
+    int len = 0;
+    if (t < nw) {
+        const long long o = src.off[w0 + t];
+        len = src.len[w0 + t];
+        if (o < 0 || len < 0 || (unsigned long long)o + (unsigned long long)len > src.cap) {
+            atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            len = 0;
+        }
+        woff[t] = o;
     }
-    for (int i = threadIdx.x; i < rb.nb; i += kRedNT) h[i] = 0;
+    int total;
+    const int ex = block_excl_scan<kGainNT>(len, tmp, total);
+    if (t <= nw) wpre[t] = ex;  // wpre[nw] = total
     __syncthreads();
-    unsigned long long a, b;
-    chunk_range(P, rb.g1, blockIdx.x, a, b);
-    for (unsigned long long i = a + threadIdx.x; i < b; i += kRedNT)
-        atomicAdd(&h[pair_node[i] >> kBucketShift], 1);
-    __syncthreads();
-    for (int i = threadIdx.x; i < rb.nb; i += kRedNT) rb.hist[(size_t)i * rb.g1 + blockIdx.x] = h[i];
+    return total;
 }
 
-// single-workgroup exclusive scan of hist[0 .. nb*g1) in place; hist[nb*g1] =
-// total.  64-bit: a tile's pairs may exceed 2^31.
-__global__ __launch_bounds__(1024) void k_scan(const RoundCtl* ctl, ReduceBufs rb) {
+// the world of flat entry k: wpre[lo] <= k < wpre[lo + 1]
+__device__ __forceinline__ int gain_world_of(const int32_t* wpre, int nw, int k) {
+    int lo = 0, hi = nw;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (wpre[mid] <= k) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kGainNT) void k_gain_count(GainSrc src, GainBufs gb, RoundCtl* ctl) {
+    __shared__ int32_t h[kGainMaxBuckets];
+    __shared__ long long woff[kGainWorlds];
+    __shared__ int32_t wpre[kGainWorlds + 1];
+    __shared__ int tmp[kGainNT / 64];
+    if (ctl->stop) return;
+    const uint32_t w0 = blockIdx.x * (uint32_t)kGainWorlds;
+    const int nw = (int)min((uint32_t)kGainWorlds, src.count - w0);
+    for (int i = threadIdx.x; i < gb.nb; i += kGainNT) h[i] = 0;
+    const int total = gain_ranges(src, w0, nw, woff, wpre, tmp, ctl);
+    bool bad = false;
+    for (int k0 = 0; k0 < total; k0 += 4 * kGainNT) {
+        int32_t u[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int k = k0 + threadIdx.x + j * kGainNT;
+            u[j] = -1;
+            if (k < total) {
+                const int lo = gain_world_of(wpre, nw, k);
+                u[j] = src.node[woff[lo] + (k - wpre[lo])];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (u[j] < 0) continue;
+            const uint32_t bk = (uint32_t)u[j] >> gb.shift;
+            if (bk < (uint32_t)gb.nb) atomicAdd(&h[bk], 1);
+            else bad = true;
+        }
+    }
+    if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+    __syncthreads();
+    for (int i = threadIdx.x; i < gb.nb; i += kGainNT)
+        if (h[i]) atomicAdd((unsigned long long*)&gb.bcnt[i], (unsigned long long)h[i]);
+}
+
+__global__ __launch_bounds__(1024) void k_gain_scan(GainBufs gb, RoundCtl* ctl) {
     __shared__ long long tmp[16];
-    __shared__ long long carry;
     if (ctl->stop) return;
-    const int total = rb.nb * rb.g1;
-    if (threadIdx.x == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < total; base += 1024 * 4) {
-        long long v[4];
-        long long loc = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = base + threadIdx.x * 4 + k;
-            v[k] = (i < total) ? rb.hist[i] : 0;
-            loc += v[k];
-        }
+    long long run = 0;
+    for (int c0 = 0; c0 < gb.nb; c0 += 1024) {
+        const int i = c0 + threadIdx.x;
+        const long long v = i < gb.nb ? gb.bcnt[i] : 0;
         long long tot;
-        const long long ex = block_excl_scan_ll<1024>(loc, tmp, tot);
-        long long run = carry + ex;
+        const long long ex = block_excl_scan_ll<1024>(v, tmp, tot);
+        if (i < gb.nb) {
+            gb.bbase[i] = run + ex;
+            gb.bcur[i] = run + ex;
+        }
+        run += tot;
+    }
+    if (threadIdx.x == 0) {
+        gb.bbase[gb.nb] = run;
+        if ((unsigned long long)run > gb.rec_cap) atomicOr(&ctl->flags, (uint32_t)kFlagReduceCapacity);
+    }
+}
+
+size_t gain_partition_lds(int nb) {
+    return (size_t)kGainStage * sizeof(int2) + (size_t)nb * (sizeof(int32_t) + sizeof(long long));
+}
+
+__global__ __launch_bounds__(kGainNT) void k_gain_partition(GainSrc src, GainBufs gb, RoundCtl* ctl) {
+    extern __shared__ int2 gpart_lds[];
+    int2* stage = gpart_lds;                                                        // [kGainStage]
+    long long* bdel = reinterpret_cast<long long*>(stage + kGainStage);             // [nb] global - local
+    int32_t* bnum = reinterpret_cast<int32_t*>(bdel + gb.nb);                       // [nb] count, then base
+    __shared__ long long woff[kGainWorlds];
+    __shared__ int32_t wpre[kGainWorlds + 1];
+    __shared__ int tmp[kGainNT / 64];
+    constexpr int kPer = kGainStage / kGainNT;
+    if (ctl->stop) return;
+    const int t = threadIdx.x;
+    const uint32_t w0 = blockIdx.x * (uint32_t)kGainWorlds;
+    const int nw = (int)min((uint32_t)kGainWorlds, src.count - w0);
+    const int total = gain_ranges(src, w0, nw, woff, wpre, tmp, ctl);
+    const int nb = gb.nb;
+    bool bad = false;
+    for (int k0 = 0; k0 < total; k0 += kGainStage) {
+        const int k1 = min(total, k0 + kGainStage);
+        for (int i = t; i < nb; i += kGainNT) bnum[i] = 0;
+        __syncthreads();
+        int32_t ru[kPer], rc[kPer], rr[kPer];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int i = base + threadIdx.x * 4 + k;
-            if (i < total) rb.hist[i] = run;
-            run += v[k];
+        for (int j = 0; j < kPer; ++j) {
+            const int k = k0 + t + j * kGainNT;
+            ru[j] = -1;
+            rc[j] = rr[j] = 0;
+            if (k < k1) {
+                const int lo = gain_world_of(wpre, nw, k);
+                const long long pos = woff[lo] + (k - wpre[lo]);
+                ru[j] = src.node[pos];
+                rc[j] = src.cnt[pos];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (ru[j] < 0) continue;
+            const uint32_t bk = (uint32_t)ru[j] >> gb.shift;
+            if (bk < (uint32_t)nb) rr[j] = atomicAdd(&bnum[bk], 1);
+            else ru[j] = -1;
         }
         __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
+        // local bases, and the batch's share of each bucket
+        const int per = (nb + kGainNT - 1) / kGainNT;
+        const int b0 = min(nb, t * per), b1 = min(nb, b0 + per);
+        int sum = 0;
+        for (int bk = b0; bk < b1; ++bk) sum += bnum[bk];
+        int staged;
+        int base = block_excl_scan<kGainNT>(sum, tmp, staged);
+        for (int bk = b0; bk < b1; ++bk) {
+            const int c = bnum[bk];
+            bnum[bk] = base;
+            if (c)
+                bdel[bk] = (long long)atomicAdd((unsigned long long*)&gb.bcur[bk], (unsigned long long)c) -
+                           (long long)base;
+            base += c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            if (ru[j] >= 0) stage[bnum[(uint32_t)ru[j] >> gb.shift] + rr[j]] = make_int2(ru[j], rc[j]);
+        __syncthreads();
+        for (int i = t; i < staged; i += kGainNT) {
+            const int2 r = stage[i];
+            const unsigned long long g = (unsigned long long)(bdel[(uint32_t)r.x >> gb.shift] + i);
+            if (g < gb.rec_cap) gb.rec[g] = r;
+            else bad = true;
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) rb.hist[total] = carry;
+    if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
 }
 
-__global__ __launch_bounds__(kRedNT) void k_scatter(const RoundCtl* ctl, const int32_t* pair_node,
-                                                    const int32_t* pair_cnt, unsigned long long cap,
-                                                    ReduceBufs rb) {
-    __shared__ unsigned long long cur[kMaxBuckets];
+__global__ __launch_bounds__(kGainOwnNT) void k_gain_own(GainBufs gb, int32_t n, int64_t* gain, RoundCtl* ctl) {
+    extern __shared__ unsigned long long gacc[];  // [1 << shift]
     if (ctl->stop) return;
-    unsigned long long P = ctl->pair_count;
-    if (P > cap || P > rb.sorted_cap || (ctl->flags & kFlagPairOverflow)) P = 0;
-    for (int i = threadIdx.x; i < rb.nb; i += kRedNT)
-        cur[i] = (unsigned long long)rb.hist[(size_t)i * rb.g1 + blockIdx.x];
+    const int b = blockIdx.x / gb.slices;
+    const int sl = blockIdx.x % gb.slices;
+    const int width = 1 << gb.shift;
+    for (int i = threadIdx.x; i < width; i += kGainOwnNT) gacc[i] = 0ull;
     __syncthreads();
-    unsigned long long a, b;
-    chunk_range(P, rb.g1, blockIdx.x, a, b);
-    for (unsigned long long i = a + threadIdx.x; i < b; i += kRedNT) {
-        const int32_t v = pair_node[i];
-        const unsigned long long pos = atomicAdd(&cur[v >> kBucketShift], 1ull);
-        rb.sorted_node[pos] = v;
-        rb.sorted_cnt[pos] = pair_cnt[i];
-    }
-}
-
-// One workgroup per (bucket, slice): LDS accumulation of the slice's pairs.
-// With one slice the workgroup owns its bucket's nodes and adds the sums
-// straight into gain; otherwise it writes a partial vector for k_sum_slices.
-__global__ __launch_bounds__(kRedNT) void k_accum(const RoundCtl* ctl, int32_t n, ReduceBufs rb, int64_t* gain) {
-    __shared__ unsigned long long acc[1 << kBucketShift];
-    if (ctl->stop) return;
-    const int bucket = blockIdx.x / rb.slices;
-    const int slice = blockIdx.x % rb.slices;
-    const long long bs = rb.hist[(size_t)bucket * rb.g1];
-    const long long be = (bucket + 1 < rb.nb) ? rb.hist[(size_t)(bucket + 1) * rb.g1] : rb.hist[(size_t)rb.nb * rb.g1];
-    const long long len = be - bs;
-    if (rb.slices == 1 && len == 0) return;  // nothing to add to this bucket
-    for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) acc[i] = 0ull;
-    __syncthreads();
-    const long long a = bs + len * slice / rb.slices;
-    const long long b = bs + len * (slice + 1) / rb.slices;
-    const int32_t node0 = bucket << kBucketShift;
-    for (long long i = a + threadIdx.x; i < b; i += kRedNT)
-        atomicAdd(&acc[rb.sorted_node[i] - node0], (unsigned long long)(long long)rb.sorted_cnt[i]);
-    __syncthreads();
-    if (rb.slices == 1) {
-        for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) {
-            const long long v = (long long)acc[i];
-            if (v != 0 && node0 + i < n) gain[node0 + i] += v;
+    const unsigned long long cap = gb.rec_cap;
+    const unsigned long long bs = min((unsigned long long)gb.bbase[b], cap);
+    const unsigned long long be = min((unsigned long long)gb.bbase[b + 1], cap);
+    const unsigned long long len = be - bs;
+    const unsigned long long r0 = bs + len * (unsigned long long)sl / (unsigned long long)gb.slices;
+    const unsigned long long r1 = bs + len * (unsigned long long)(sl + 1) / (unsigned long long)gb.slices;
+    const int32_t node0 = b << gb.shift;
+    for (unsigned long long q = r0; q < r1; q += 4ull * kGainOwnNT) {
+        int2 e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const unsigned long long r = q + threadIdx.x + (unsigned long long)j * kGainOwnNT;
+            e[j] = r < r1 ? gb.rec[r] : make_int2(-1, 0);
         }
-        return;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t d = (uint32_t)(e[j].x - node0);
+            if (d < (uint32_t)width) atomicAdd(&gacc[d], (unsigned long long)(uint32_t)e[j].y);
+        }
     }
-    int64_t* out = rb.part + (size_t)slice * ((size_t)rb.nb << kBucketShift) + ((size_t)bucket << kBucketShift);
-    for (int i = threadIdx.x; i < (1 << kBucketShift); i += kRedNT) out[i] = (int64_t)acc[i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < width; i += kGainOwnNT) {
+        const unsigned long long v = gacc[i];
+        const int32_t u = node0 + i;
+        if (v == 0ull || u >= n) continue;
+        if (gb.slices == 1) gain[u] += (int64_t)v;
+        else atomicAdd((unsigned long long*)&gain[u], v);
+    }
 }
 
-__global__ void k_sum_slices(const RoundCtl* ctl, int32_t n, ReduceBufs rb, int64_t* gain) {
-    if (ctl->stop) return;
-    const size_t stride_s = (size_t)rb.nb << kBucketShift;
-    for (size_t u = blockIdx.x * (size_t)blockDim.x + threadIdx.x; u < (size_t)n;
-         u += (size_t)gridDim.x * blockDim.x) {
-        int64_t s = gain[u];
-        for (int k = 0; k < rb.slices; ++k) s += rb.part[k * stride_s + u];
-        gain[u] = s;
-    }
+GainBufs gain_buckets(int32_t n) {
+    GainBufs gb{};
+    int shift = 5;
+    while (shift < 15 && (((long long)n + (1ll << shift) - 1) >> shift) > kGainMaxBuckets) ++shift;
+    gb.shift = shift;
+    gb.nb = (int)(((long long)n + (1ll << shift) - 1) >> shift);
+    gb.slices = 1;
+    return gb;
 }
 
-hipError_t launch_reduce_pairs(const GraphDev& g, const TileOut& out, const ReduceBufs& rb,
-                               RoundCtl* ctl, int64_t* gain, hipStream_t s) {
-    k_hist<<<rb.g1, kRedNT, 0, s>>>(ctl, out.pair_node, out.pair_cap, rb);
-    hipError_t e = hipGetLastError();
+int gain_slices(const GainBufs& gb, unsigned long long entries, int cus) {
+    // enough (bucket, slice) workgroups to cover the chip; more when the
+    // buckets are long
+    const long long want = (long long)cus * (entries > (64ull << 20) ? 4 : 1);
+    return (int)std::max(1ll, std::min(64ll, (want + gb.nb - 1) / gb.nb));
+}
+
+hipError_t launch_gain_reduce(const GainSrc& src, const GainBufs& gb, int32_t n, int64_t* gain, RoundCtl* ctl,
+                              hipStream_t s) {
+    if (gb.nb < 1 || gb.nb > kGainMaxBuckets || ((long long)gb.nb << gb.shift) < (long long)n || gb.slices < 1)
+        return hipErrorInvalidValue;
+    if (src.count == 0) return hipSuccess;
+    hipError_t e = hipMemsetAsync(gb.bcnt, 0, (size_t)gb.nb * sizeof(long long), s);
     if (e != hipSuccess) return e;
-    k_scan<<<1, 1024, 0, s>>>(ctl, rb);
+    const unsigned groups = (src.count + kGainWorlds - 1) / kGainWorlds;
+    k_gain_count<<<groups, kGainNT, 0, s>>>(src, gb, ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_scatter<<<rb.g1, kRedNT, 0, s>>>(ctl, out.pair_node, out.pair_cnt, out.pair_cap, rb);
+    k_gain_scan<<<1, 1024, 0, s>>>(gb, ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    k_accum<<<rb.nb * rb.slices, kRedNT, 0, s>>>(ctl, g.n, rb, gain);
+    const size_t lds = gain_partition_lds(gb.nb);
+    if ((e = hipFuncSetAttribute((const void*)k_gain_partition, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+        return e;
+    k_gain_partition<<<groups, kGainNT, lds, s>>>(src, gb, ctl);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (rb.slices > 1) {
-        k_sum_slices<<<1024, 256, 0, s>>>(ctl, g.n, rb, gain);
-        e = hipGetLastError();
-    }
-    return e;
+    const size_t olds = sizeof(unsigned long long) << gb.shift;
+    if ((e = hipFuncSetAttribute((const void*)k_gain_own, hipFuncAttributeMaxDynamicSharedMemorySize, (int)olds)) !=
+        hipSuccess)
+        return e;
+    k_gain_own<<<(unsigned)(gb.nb * gb.slices), kGainOwnNT, olds, s>>>(gb, n, gain, ctl);
+    return hipGetLastError();
 }
 
 __global__ void k_sum_sizes(const int32_t* ws, uint32_t count, RoundCtl* ctl) {

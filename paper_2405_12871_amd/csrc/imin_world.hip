@@ -64,6 +64,7 @@ struct WorldShared {
     int nlevels;      // BFS levels holding nodes
     unsigned long long in_bytes;  // algorithmic bytes read by the BFS phase
     unsigned long long acc_worlds, acc_edges, acc_bytes;  // this workgroup's work so far
+    unsigned long long acc_reached, acc_live;  // reached nodes (seeds included) and recorded live edges
     long long acc_dsize;  // reached nodes lost by this workgroup's worlds (incremental rounds)
     uint32_t sched;       // first world of the chunk just taken
     int row_lid[NT];
@@ -240,21 +241,17 @@ struct SlotGroup {
     bool valid;
 };
 
-// Draw the coins of U slot groups and claim or record every live edge.  The
-// work is split in phases so that the U groups' loads are in flight
-// together: columns and thresholds, then the Philox blocks, then the
-// exclusion bits of the live heads, then the claims.
+// Draw the coins of U slot groups whose columns (cv) and thresholds (tv) are
+// loaded, and claim or record every live edge.  Exclusions (seeds, blocked
+// nodes) are already in the per-query thresholds when q.excl_in_thr is set
+// (an excluded head's slots have threshold 0, never live); otherwise the
+// exclusion bits of the live heads are loaded and tested.  Phases keep the U
+// groups' work side by side: the Philox blocks, then the exclusion bits,
+// then the claims.
 template <int NT, int U, class Store>
-__device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryDev& q, uint32_t w,
-                                                 const SlotGroup (&gr)[U], Store& st, WorldShared<NT>& sh) {
-    int4 cv[U];
-    uint4 tv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const size_t b = gr[u].valid ? (size_t)gr[u].blk : 0;
-        cv[u] = *reinterpret_cast<const int4*>(g.col + 4 * b);
-        tv[u] = *reinterpret_cast<const uint4*>(g.thr + 4 * b);
-    }
+__device__ __forceinline__ void claim_slot_groups(const QueryDev& q, uint32_t w, const SlotGroup (&gr)[U],
+                                                  const int4 (&cv)[U], const uint4 (&tv)[U], Store& st,
+                                                  WorldShared<NT>& sh) {
     uint4 cn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) cn[u] = philox_block(gr[u].blk, w, q.key0, q.key1);
@@ -273,7 +270,7 @@ __device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryD
             const bool live = in && (ts[qd] == kAlwaysLive || cs[qd] < ts[qd]) && vs[qd] != gr[u].unode;
             vv[u][qd] = vs[qd];
             lv[u][qd] = live;
-            ex[u][qd] = live ? q.excl[(uint32_t)vs[qd] >> 5] : 0u;
+            ex[u][qd] = (live && !q.excl_in_thr) ? q.excl[(uint32_t)vs[qd] >> 5] : 0u;
         }
     }
 #pragma unroll
@@ -302,6 +299,23 @@ __device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryD
     }
 }
 
+
+// Slot groups of reached rows: columns from the graph, thresholds from the
+// query's own copy.
+template <int NT, int U, class Store>
+__device__ __forceinline__ void scan_slot_groups(const GraphDev& g, const QueryDev& q, uint32_t w,
+                                                 const SlotGroup (&gr)[U], Store& st, WorldShared<NT>& sh) {
+    int4 cv[U];
+    uint4 tv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const size_t b = gr[u].valid ? (size_t)gr[u].blk : 0;
+        cv[u] = *reinterpret_cast<const int4*>(g.col + 4 * b);
+        tv[u] = *reinterpret_cast<const uint4*>(q.thr + 4 * b);
+    }
+    claim_slot_groups<NT, U>(q, w, gr, cv, tv, st, sh);
+}
+
 constexpr int kGroupsPerLane = 2;
 
 // Phase 1 of a world evaluation by sampling: the BFS with coins.  Returns
@@ -324,20 +338,27 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, Sto
     }
     __syncthreads();
 
-    // ---- level 0: the seeds' slot groups from the per-query table
+    // ---- level 0: the seeds' slot groups from the per-query table, which
+    // carries each group's columns and thresholds (one round trip)
     for (int j0 = t; j0 < q.n_seed_chunks; j0 += NT * kGroupsPerLane) {
         SlotGroup gr[kGroupsPerLane];
+        int4 cv[kGroupsPerLane];
+        uint4 tv[kGroupsPerLane];
 #pragma unroll
         for (int u = 0; u < kGroupsPerLane; ++u) {
             const int j = j0 + u * NT;
             if (j < q.n_seed_chunks) {
                 const int4 d = q.seed_chunk[j];  // {blk, seed lid, e0, e1}
+                cv[u] = q.seed_col[j];
+                tv[u] = q.seed_thr[j];
                 gr[u] = SlotGroup{(uint32_t)d.x, d.y, -1, d.z, d.w, true};
             } else {
+                cv[u] = make_int4(0, 0, 0, 0);
+                tv[u] = make_uint4(0u, 0u, 0u, 0u);
                 gr[u] = SlotGroup{0u, 0, -1, 0, 0, false};
             }
         }
-        scan_slot_groups<NT, kGroupsPerLane>(g, q, w, gr, st, sh);
+        claim_slot_groups<NT, kGroupsPerLane>(q, w, gr, cv, tv, st, sh);
     }
     __syncthreads();
     if (sh.overflow) return false;
@@ -729,6 +750,10 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
         sh.acc_worlds += 1;
         sh.acc_edges += (unsigned long long)sh.edges;
         sh.acc_bytes += bytes;
+        // live edges between non-excluded nodes: one BFS-tree edge per
+        // reached non-seed plus the extra edges
+        sh.acc_reached += (unsigned long long)R;
+        sh.acc_live += (unsigned long long)(R - ns + nx);
     }
 }
 
@@ -762,24 +787,24 @@ constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
 
 // Per-workgroup work tallies, one slot per (tier, field, workgroup): no
-// shared counter is touched.
+// shared counter is touched.  Fields: worlds, edges, bytes, reached nodes,
+// live edges (the last two only for sampled worlds).
 __device__ __forceinline__ void add_work_at(const TileOut& out, int tier, uint32_t slot, unsigned long long worlds,
-                                            unsigned long long edges, unsigned long long bytes) {
+                                            unsigned long long edges, unsigned long long bytes,
+                                            unsigned long long reached = 0, unsigned long long live = 0) {
     if (!out.work || !worlds) return;
     const size_t st = (size_t)out.work_stride;
-    unsigned long long* wk = out.work + (size_t)tier * 3 * st + slot;
+    unsigned long long* wk = out.work + (size_t)tier * kWorkFields * st + slot;
     wk[0] += worlds;
     wk[st] += edges;
     wk[2 * st] += bytes;
+    wk[3 * st] += reached;
+    wk[4 * st] += live;
 }
 __device__ __forceinline__ void add_work(const TileOut& out, int tier, unsigned long long worlds,
-                                         unsigned long long edges, unsigned long long bytes) {
-    if (!out.work || !worlds) return;
-    const size_t st = (size_t)out.work_stride;
-    unsigned long long* wk = out.work + (size_t)tier * 3 * st + blockIdx.x;
-    wk[0] += worlds;
-    wk[st] += edges;
-    wk[2 * st] += bytes;
+                                         unsigned long long edges, unsigned long long bytes,
+                                         unsigned long long reached, unsigned long long live) {
+    add_work_at(out, tier, blockIdx.x, worlds, edges, bytes, reached, live);
 }
 
 // Worlds are dealt to workgroups by a fixed stride (no shared work counter).
@@ -797,6 +822,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
     st.template clear<NT>();
     if (t == 0) {
         sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_reached = sh.acc_live = 0;
         sh.acc_dsize = 0;
     }
     __syncthreads();
@@ -826,7 +852,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
         __syncthreads();
     }
     if (t == 0) {
-        add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+        add_work(out, TIER, sh.acc_worlds, sh.acc_edges, sh.acc_bytes, sh.acc_reached, sh.acc_live);
         // incremental rounds keep T up to date: the nodes lost, per workgroup
         if (sh.acc_dsize) out.dsz[out.dsz_off[TIER] + blockIdx.x] = sh.acc_dsize;
     }
@@ -857,6 +883,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
     if (t == 0) {
         sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_reached = sh.acc_live = 0;
         sh.acc_dsize = 0;
     }
     for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
@@ -868,7 +895,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
         __syncthreads();
     }
     if (t == 0) {
-        add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes);
+        add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes, sh.acc_reached, sh.acc_live);
         if (sh.acc_dsize) out.dsz[out.dsz_off[2] + blockIdx.x] = sh.acc_dsize;
     }
 }
@@ -2300,6 +2327,43 @@ __global__ void k_seed_fill(GraphDev g, const int32_t* seeds, int32_t ns, const 
         const int b0 = e0 >> 2, b1 = (e1 - 1) >> 2;
         for (int b = b0; b <= b1; ++b) table[start[i] + (b - b0)] = make_int4(b, i, e0, e1);
     }
+}
+
+// The per-query thresholds: the graph's, with every slot whose head is a
+// seed or a blocked node set to 0 (never live), and the level-0 table's
+// copies of its slot groups' columns and thresholds.
+__global__ void k_query_thr(GraphDev g, const uint32_t* excl, uint32_t* thr_q) {
+    const size_t groups = (size_t)g.m_pad / 4;
+    for (size_t b = blockIdx.x * (size_t)blockDim.x + threadIdx.x; b < groups; b += (size_t)gridDim.x * blockDim.x) {
+        const int4 c = *reinterpret_cast<const int4*>(g.col + 4 * b);
+        uint4 th = *reinterpret_cast<const uint4*>(g.thr + 4 * b);
+        const size_t e = 4 * b;
+        if (e + 0 < (size_t)g.m && bit_set(excl, c.x)) th.x = 0u;
+        if (e + 1 < (size_t)g.m && bit_set(excl, c.y)) th.y = 0u;
+        if (e + 2 < (size_t)g.m && bit_set(excl, c.z)) th.z = 0u;
+        if (e + 3 < (size_t)g.m && bit_set(excl, c.w)) th.w = 0u;
+        *reinterpret_cast<uint4*>(thr_q + 4 * b) = th;
+    }
+}
+
+__global__ void k_seed_slots(GraphDev g, const uint32_t* thr_q, const int4* table, const RoundCtl* ctl,
+                             int32_t cap, int4* scol, uint4* sthr) {
+    const int32_t nc = min(ctl->seed_chunks, cap);
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
+        const size_t b = (size_t)table[j].x;
+        scol[j] = *reinterpret_cast<const int4*>(g.col + 4 * b);
+        sthr[j] = *reinterpret_cast<const uint4*>(thr_q + 4 * b);
+    }
+}
+
+hipError_t launch_query_thresholds(const GraphDev& g, const uint32_t* excl, uint32_t* thr_q, const int4* table,
+                                   const RoundCtl* ctl, int32_t chunk_cap, int4* seed_col, uint4* seed_thr,
+                                   hipStream_t s) {
+    k_query_thr<<<2048, 256, 0, s>>>(g, excl, thr_q);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || chunk_cap < 1) return e;
+    k_seed_slots<<<(chunk_cap + 255) / 256, 256, 0, s>>>(g, thr_q, table, ctl, chunk_cap, seed_col, seed_thr);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,

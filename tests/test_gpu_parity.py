@@ -557,9 +557,57 @@ def test_edge_cases(B):
     torch.cuda.synchronize()
 
 
-def test_large_workload_first_rounds(B, oracle_mod):
-    """Full-size 1M-node workload: the first rounds equal the oracle's; all
-    rounds satisfy the exact invariants."""
+def _argmax_candidates(gain, seeds, blocked):
+    """argmax of the oracle's gains over V minus (S + B), ties to the smaller id."""
+    key = gain.astype(np.int64).copy()
+    key[np.asarray(seeds, dtype=np.int64)] = -1
+    if len(blocked):
+        key[np.asarray(blocked, dtype=np.int64)] = -1
+    u = int(np.argmax(key))  # first maximum: the smallest id
+    return u, int(gain[u])
+
+
+def _check_rounds_against_oracle(oracle_mod, g, seeds, theta, rng_seed, res, rounds):
+    """At each round r: the oracle's from-scratch pass under B_r (the GPU's
+    first r blockers) gives T_r, and, while r < n_selected, an argmax and a
+    gain that must be the GPU's blockers[r] and gains[r]."""
+    q = oracle_mod.Query(g, seeds)
+    for r in rounds:
+        if r > res.n_selected:
+            continue
+        blocked = res.blockers[:r].tolist()
+        _log(f"  oracle pass under the first {r} blockers")
+        gain, total = q.eval(rng_seed, 0, theta, blocked=blocked)
+        assert total == int(res.spread_totals[r]), (r, total, int(res.spread_totals[r]))
+        if r < res.n_selected:
+            u, gu = _argmax_candidates(gain, seeds, blocked)
+            assert u == int(res.blockers[r]), (r, u, int(res.blockers[r]))
+            assert gu == int(res.gains[r]), (r, gu, int(res.gains[r]))
+
+
+def test_coin_threshold_boundary(B, oracle_mod):
+    """A coin equal to the edge's threshold leaves the edge dead (the edge is
+    kept with probability exactly p when p * 2^32 is an integer); one step of
+    256 above it makes it live.  The coins and thresholds come from the
+    oracle; the GPU draws its own."""
+    from conftest import boundary_coins, dyadic_p
+    seeds = np.array([0], np.int32)
+    for rng_seed in (7, 0x0123456789ABCDEF):
+        for w, c in boundary_coins(oracle_mod, rng_seed, 3):
+            for cc, live in ((c, False), (c + 256, True), (c - 256, False)):
+                g = synth.from_edges(2, [0], [1], [dyadic_p(cc)])
+                _log(f"coin boundary seed={rng_seed:#x} world={w} coin={c:#x} thr={cc:#x}")
+                G = B.Graph.from_synth(g)
+                _, total, ws, _ = B.evaluate(G, seeds, w, 1, rng_seed, per_world=True)
+                assert int(ws[0]) == (2 if live else 1) and total == int(ws[0]), (rng_seed, w, c, cc)
+                G.destroy()
+
+
+def test_large_workload_rounds(B, oracle_mod):
+    """Full-size 1M-node workload (k = 500, theta = 2e5): the first rounds
+    equal the oracle's greedy; at rounds spread over the whole solve the
+    oracle's from-scratch pass under the GPU's blockers so far gives the same
+    T_r, argmax and gain; every round satisfies the exact invariants."""
     g, seeds, k, theta = synth.workload("large")
     _log("solve large workload (full k, theta)")
     G = B.Graph.from_synth(g)
@@ -576,3 +624,34 @@ def test_large_workload_first_rounds(B, oracle_mod):
     np.testing.assert_array_equal(res.blockers[:kpar], want["blockers"])
     np.testing.assert_array_equal(res.gains[:kpar], want["gains"])
     np.testing.assert_array_equal(T[:kpar + 1], want["spread_totals"])
+    _check_rounds_against_oracle(oracle_mod, g, seeds, theta, 2024, res, (2, 10, 50, 100, 250, 499, 500))
+
+
+def test_medium_workload_every_round_reduced_theta(B, oracle_mod):
+    """The medium workload's graph and seeds (worlds of about 24K nodes) with
+    k = 100 at theta = 300: every round of the GPU's solve equals the
+    oracle's greedy."""
+    g, seeds, k, _ = synth.workload("medium")
+    theta = 300
+    _log(f"solve medium graph k={k} theta={theta}")
+    res = B.solve(B.Graph.from_synth(g), seeds, k, theta, 31)
+    _log("oracle solve")
+    want = oracle_mod.Query(g, seeds).solve(k, theta, 31)
+    assert res.n_selected == want["n_selected"]
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+@pytest.mark.timeout(1200)
+def test_medium_workload_full_solve(B, oracle_mod):
+    """The full medium workload (k = 100, theta = 1e5): at rounds 0, 1, 99
+    and 100 the oracle's from-scratch pass under the GPU's blockers so far
+    gives the same T_r, argmax and gain."""
+    g, seeds, k, theta = synth.workload("medium")
+    _log("solve medium workload (full k, theta)")
+    res = B.solve(B.Graph.from_synth(g), seeds, k, theta, 2024)
+    T = res.spread_totals
+    np.testing.assert_array_equal(T[1:res.n_selected + 1], T[:res.n_selected] - res.gains[:res.n_selected])
+    rounds = [int(x) for x in os.environ.get("IMIN_TEST_MEDIUM_ROUNDS", "0,1,99,100").split(",")]
+    _check_rounds_against_oracle(oracle_mod, g, seeds, theta, 2024, res, rounds)

@@ -97,6 +97,23 @@ def test_live_frequency(oracle_mod):
     assert total == theta + gain[1:].sum()
 
 
+def test_coin_threshold_boundary(oracle_mod):
+    """An edge is live with probability exactly p when p * 2^32 is an integer
+    (Section 2.1: the edge is kept with probability p).  With the threshold
+    thr = p * 2^32, P(coin < thr) = thr / 2^32 = p, while "coin <= thr" would
+    keep it with probability p + 2^-32.  So a coin equal to its threshold must
+    leave the edge dead, and one step of 256 above it must make it live."""
+    from conftest import boundary_coins, dyadic_p
+    seeds = np.array([0], dtype=np.int32)
+    for rng_seed in (7, 0x0123456789ABCDEF):
+        for w, c in boundary_coins(oracle_mod, rng_seed, 3):
+            for cc, live in ((c, False), (c + 256, True), (c - 256, False)):
+                g = synth.from_edges(2, [0], [1], [dyadic_p(cc)])
+                assert int(oracle_mod.thresholds(g.p)[0]) == cc
+                _, reached = oracle_mod.Query(g, seeds).world(rng_seed, w)
+                assert len(reached) == (2 if live else 1), (rng_seed, w, c, cc)
+
+
 # --------------------------------------------------------- worked example (P1)
 def _example1():
     with open(os.path.join(GOLDEN, "example1_realization.json")) as f:
