@@ -26,8 +26,9 @@
  *   - array arguments are DEVICE pointers (HBM of the current HIP device)
  *     unless stated otherwise; scalars are passed by value;
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream);
- *   - calls are synchronous with respect to the host: they return after the
- *     results are in place (work is ordered on `stream`);
+ *   - calls are synchronous with respect to the host (they return after the
+ *     results are in place; work is ordered on `stream`), except imin_solve
+ *     given a workspace, which only enqueues, and imin_server_submit;
  *   - no C++ exception crosses this boundary; every call returns a status.
  */
 #ifndef IMIN_H
@@ -49,7 +50,8 @@ typedef enum {
                              range or repeated, a blocker that is a seed      */
     IMIN_ERR_DEVICE = 3,  /* a HIP runtime call failed                        */
     IMIN_ERR_NOMEM = 4,   /* device memory could not be allocated             */
-    IMIN_ERR_INTERNAL = 5 /* an internal consistency check failed             */
+    IMIN_ERR_INTERNAL = 5,/* an internal consistency check failed             */
+    IMIN_ERR_WORKSPACE = 6/* a caller's workspace is too small for the call   */
 } imin_status_t;
 
 typedef struct imin_graph* imin_graph_t;
@@ -84,14 +86,22 @@ imin_status_t imin_graph_destroy(imin_graph_t g);
 imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m);
 
 /*
- * imin_solve -- greedy blocker selection (Section 2.2: the greedy framework
- * driven by the dominator-tree estimator; problem statement of Section 2.1).
+ * imin_solve -- greedy blocker selection (Section 2.1, problem statement:
+ * given G, p, the seed set S and a budget k, find at most k blockers
+ * minimising the expected spread; Section 2.2: the greedy framework driven
+ * by the dominator-tree estimator; Section 3.1, Algorithm 1: its inputs are
+ * the graph, the seed set and the budget, its output the blocker set).
  *
  *   seeds          int32[n_seeds], device: the misinformation seed set S,
  *                  distinct ids in [0, n); 1 <= n_seeds <= n
  *   k              budget, 0 <= k <= n
- *   theta          worlds per round, 1 <= theta < 2^32
+ *   theta          worlds per round, 1 <= theta < 2^32 (the number of
+ *                  realizations the greedy evaluates, Section 6)
  *   rng_seed       key of the coin generator
+ *   workspace      device scratch owned by the caller, 256-byte aligned, of
+ *                  workspace_bytes bytes (see imin_solve_workspace_size); or
+ *                  NULL, see below
+ *   stream         the stream every kernel of the call is enqueued on
  *   blockers       int32[max(k,1)], device, out: u*_0 .. u*_{n_selected-1}
  *   gains          int64[max(k,1)], device, out: gains[r] = sum over worlds
  *                  of nodes protected by u*_r given u*_0..u*_{r-1} blocked
@@ -101,16 +111,51 @@ imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m);
  *                  blocking is T_{n_selected} / theta
  *   n_selected     int32[1], device, out: number of blockers chosen (<= k;
  *                  fewer when every remaining candidate protects nothing)
+ *   device_status  int32[1], device, out: 0 when the solve succeeded, else
+ *                  an imin_status_t code (may be NULL when workspace is NULL)
  *
- * Entries past n_selected are left untouched.  The call takes its scratch
- * device memory from the library's block cache (see imin_cache_release) and
- * hands it back before returning.  Errors:
- * IMIN_ERR_INVALID, IMIN_ERR_DATA (bad seeds), IMIN_ERR_NOMEM,
- * IMIN_ERR_DEVICE, IMIN_ERR_INTERNAL.
+ * With a workspace the call only enqueues: it allocates nothing, reads
+ * nothing back and does not wait (so it can be captured into a HIP graph).
+ * Every piece of scratch is carved from the workspace, which the call uses
+ * until the stream reaches the end of its work; the caller keeps it, the
+ * seeds and the outputs alive until then and must not share one workspace
+ * between solves that overlap.  Problems found on the host (bad arguments,
+ * a workspace smaller than the fixed part of the layout) return
+ * IMIN_ERR_INVALID / IMIN_ERR_WORKSPACE at once and enqueue nothing.
+ * Problems found on the device are written to device_status when the
+ * stream gets there, and every later kernel of the solve then does nothing
+ * (n_selected is set to 0): IMIN_ERR_DATA for bad seeds, IMIN_ERR_WORKSPACE
+ * when the worlds beyond the smallest world tier need more bump-region
+ * entries than the workspace holds (the graph then remembers how many were
+ * needed, so imin_solve_workspace_size returns enough next time),
+ * IMIN_ERR_INTERNAL when a consistency check fails.  The layout takes
+ * incremental rounds (a resident per-world store and a node index) when the
+ * stored entries can be indexed with 32-bit positions, else every round
+ * evaluates all theta worlds again; both give the same integers.
+ *
+ * With workspace == NULL the call takes its scratch from the library's
+ * block cache (see imin_cache_release), waits for its work and returns the
+ * solve's status (also written to device_status when that is not NULL).
+ * Entries past n_selected are left untouched.  Errors: IMIN_ERR_INVALID,
+ * IMIN_ERR_DATA (bad seeds), IMIN_ERR_NOMEM, IMIN_ERR_DEVICE,
+ * IMIN_ERR_INTERNAL.
  */
-imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
-                         int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
-                         int64_t* gains, int64_t* spread_totals, int32_t* n_selected);
+imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                         uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream,
+                         int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
+                         int32_t* device_status);
+
+/*
+ * imin_solve_workspace_size -- bytes of workspace an enqueued imin_solve on
+ * this graph with these sizes needs (host pointer `bytes`).  The fixed part
+ * depends on n, m, n_seeds and theta; the bump region for worlds beyond the
+ * smallest world tier is data-dependent and sized from what earlier calls on
+ * the graph needed per world (at least 2^20 entries), with an eighth more.
+ * A solve given more bytes uses them for that region.  Waits for the
+ * device (it reads the graph's device-side record of those needs).
+ * IMIN_ERR_INVALID for bad arguments.
+ */
+imin_status_t imin_solve_workspace_size(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes);
 
 /*
  * One query of imin_solve_many: the arguments of imin_solve (device arrays,

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "imin.h")
 
 IMIN_OK = 0
 STATUS_NAMES = {0: "IMIN_OK", 1: "IMIN_ERR_INVALID", 2: "IMIN_ERR_DATA", 3: "IMIN_ERR_DEVICE",
-                4: "IMIN_ERR_NOMEM", 5: "IMIN_ERR_INTERNAL"}
+                4: "IMIN_ERR_NOMEM", 5: "IMIN_ERR_INTERNAL", 6: "IMIN_ERR_WORKSPACE"}
 
 _lib = None
 
@@ -64,8 +64,10 @@ def load():
     lib.imin_graph_destroy.restype = st
     lib.imin_graph_info.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i64)]
     lib.imin_graph_info.restype = st
-    lib.imin_solve.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P]
+    lib.imin_solve.argtypes = [P, P, i32, i32, i64, u64, P, ctypes.c_size_t, P, P, P, P, P, P]
     lib.imin_solve.restype = st
+    lib.imin_solve_workspace_size.argtypes = [P, i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.imin_solve_workspace_size.restype = st
     lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32]
     lib.imin_solve_many.restype = st
     lib.imin_server_create.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P)]
@@ -194,22 +196,81 @@ class SolveResult:
         return float(self.spread_totals[0] - self.spread_totals[self.n_selected]) / float(self.theta)
 
 
+def _solve_outputs(k: int, dev):
+    torch = _torch()
+    return (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
+            torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
+            torch.zeros(k + 1, dtype=torch.int64, device=dev),
+            torch.zeros(1, dtype=torch.int32, device=dev))
+
+
 def solve_device(graph: Graph, seeds_dev, k: int, theta: int, rng_seed: int, out=None):
-    """imin_solve on device tensors; returns the device output tensors."""
+    """imin_solve on device tensors, scratch from the library's cache (the
+    call waits for its work); returns the device output tensors."""
     torch = _torch()
     lib = load()
     dev = graph.device
     if out is None:
-        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
-               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
-               torch.zeros(k + 1, dtype=torch.int64, device=dev),
-               torch.zeros(1, dtype=torch.int32, device=dev))
+        out = _solve_outputs(k, dev)
     b, g, t, ns = out
     with torch.cuda.device(dev):
         _check(lib.imin_solve(graph.handle, _ptr(seeds_dev), int(seeds_dev.numel()), int(k), int(theta),
-                              int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(b), _ptr(g), _ptr(t),
-                              _ptr(ns)))
+                              int(rng_seed) & 0xFFFFFFFFFFFFFFFF, None, 0, _stream(dev), _ptr(b), _ptr(g), _ptr(t),
+                              _ptr(ns), None))
     return out
+
+
+def workspace_size(graph: Graph, n_seeds: int, k: int, theta: int) -> int:
+    """Bytes of workspace an enqueued solve needs (imin_solve_workspace_size)."""
+    nbytes = ctypes.c_size_t()
+    _check(load().imin_solve_workspace_size(graph.handle, int(n_seeds), int(k), int(theta), ctypes.byref(nbytes)))
+    return int(nbytes.value)
+
+
+def solve_enqueue(graph: Graph, seeds_dev, k: int, theta: int, rng_seed: int, workspace, out=None, status=None,
+                  stream=None):
+    """imin_solve with a workspace (a uint8 device tensor): only enqueues on
+    ``stream`` (default: the current stream).  Returns (outputs, status
+    tensor); the status (0 = ok, else an imin_status_t) is valid once the
+    stream has reached the end of the solve."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    if out is None:
+        out = _solve_outputs(k, dev)
+    if status is None:
+        status = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    b, g, t, ns = out
+    st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_solve(graph.handle, _ptr(seeds_dev), int(seeds_dev.numel()), int(k), int(theta),
+                              int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _ptr(workspace), workspace.numel(), st, _ptr(b),
+                              _ptr(g), _ptr(t), _ptr(ns), _ptr(status)))
+    return out, status
+
+
+def result_of(out, theta: int) -> "SolveResult":
+    """The host copy of a solve's device outputs."""
+    b, g, t, ns = out
+    r = int(ns.cpu()[0])
+    return SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
+                       spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=int(theta))
+
+
+def solve_ws(graph: Graph, seeds, k: int, theta: int, rng_seed: int, workspace=None) -> "SolveResult":
+    """An enqueued solve in a workspace of imin_solve_workspace_size bytes
+    (allocated here unless given), waited for; raises on a non-zero device
+    status."""
+    torch = _torch()
+    s = _dev(seeds, torch.int32, graph.device)
+    if workspace is None:
+        workspace = torch.empty(workspace_size(graph, s.numel(), k, theta), dtype=torch.uint8, device=graph.device)
+    out, status = solve_enqueue(graph, s, k, theta, rng_seed, workspace)
+    torch.cuda.synchronize(graph.device)
+    code = int(status.cpu()[0])
+    if code != IMIN_OK:
+        raise IminError(code, load().imin_status_string(code).decode(), 0)
+    return result_of(out, theta)
 
 
 def solve(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> SolveResult:

@@ -27,7 +27,24 @@ struct imin_graph {
     // tile whose worlds overflowed it
     std::atomic<uint64_t> big_per_world{0};
     std::atomic<uint64_t> xbig_per_world{0};
+    // shares of a pass's worlds (1/1024 units) that earlier calls handed on
+    // to tier 1 and to tier 2: a call starts its worlds at the tier most of
+    // them end up in
+    std::atomic<uint64_t> tier1_share{0};
+    std::atomic<uint64_t> tier2_share{0};
+    std::atomic<bool> tier2_seen{false};  // some world of an earlier call needed the HBM tier
+    // the same four figures as raised on the device by enqueued solves
+    // (bump entries and extra edges per world, tier-1 and tier-2 shares)
+    unsigned long long* hints_dev = nullptr;
 };
+
+namespace {
+void raise_hint(std::atomic<uint64_t>& a, uint64_t v) {
+    uint64_t cur = a.load(std::memory_order_relaxed);
+    while (v > cur && !a.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
+    }
+}
+}  // namespace
 
 namespace {
 
@@ -259,19 +276,51 @@ struct ReleaseScope {
     }
 };
 
-// Device allocation owned by a scope; its block returns to the cache.
+// A caller's workspace, handed out in 256-byte-aligned pieces in the order
+// they are asked for; nothing is given back.  Without a base it only adds up
+// the sizes (the workspace size of a plan).
+struct Arena {
+    char* base = nullptr;
+    size_t size = 0;
+    size_t used = 0;
+    bool failed = false;
+    void* take(size_t bytes) {
+        const size_t at = (used + 255) & ~(size_t)255;
+        used = at + bytes;
+        if (!base) return reinterpret_cast<void*>((uintptr_t)256);  // sizing only: never dereferenced
+        if (used > size) {
+            failed = true;
+            return nullptr;
+        }
+        return base + at;
+    }
+};
+thread_local Arena* t_arena = nullptr;
+
+// While alive, DevArray allocations of this thread come from the arena.
+struct ArenaScope {
+    Arena* prev;
+    explicit ArenaScope(Arena* a) : prev(t_arena) { t_arena = a; }
+    ~ArenaScope() { t_arena = prev; }
+    ArenaScope(const ArenaScope&) = delete;
+    ArenaScope& operator=(const ArenaScope&) = delete;
+};
+
+// Device allocation owned by a scope; its block returns to the cache (or,
+// taken from a caller's workspace, is simply dropped).
 template <class T>
 struct DevArray {
     T* p = nullptr;
     size_t count = 0;
     size_t bytes = 0;  // the block's size
     int dev = 0;
+    bool borrowed = false;  // a piece of a caller's workspace
     DevArray() = default;
     DevArray(const DevArray&) = delete;
     DevArray& operator=(const DevArray&) = delete;
     ~DevArray() { release(); }
     void release() {
-        if (p) {
+        if (p && !borrowed) {
             if (t_deferred)
                 t_deferred->push_back({dev, p, bytes});
             else
@@ -280,9 +329,19 @@ struct DevArray {
         p = nullptr;
         count = 0;
         bytes = 0;
+        borrowed = false;
     }
     hipError_t alloc(size_t c) {
         release();
+        if (t_arena) {
+            void* q = t_arena->take(std::max<size_t>(c, 1) * sizeof(T));
+            if (!q) return hipErrorOutOfMemory;
+            p = static_cast<T*>(q);
+            count = c;
+            bytes = std::max<size_t>(c, 1) * sizeof(T);
+            borrowed = true;
+            return hipSuccess;
+        }
         if (hipGetDevice(&dev) != hipSuccess) return hipErrorInvalidDevice;
         void* q = g_cache.get(dev, std::max<size_t>(c, 1) * sizeof(T), bytes);
         if (!q) return hipErrorOutOfMemory;
@@ -295,6 +354,7 @@ struct DevArray {
         std::swap(count, o.count);
         std::swap(bytes, o.bytes);
         std::swap(dev, o.dev);
+        std::swap(borrowed, o.borrowed);
     }
 };
 
@@ -329,6 +389,15 @@ int cu_count() {
         return 256;
     return cus;
 }
+
+// How an enqueued solve lays out its workspace.
+struct WsPlan {
+    bool incremental = true;  // resident store and node index (else every round evaluates all worlds)
+    size_t big_cap = 0;       // bump-region entries for worlds beyond tier 0 (and as many extra edges)
+    size_t slots = 1;         // HBM-tier slots
+    int32_t chunk_cap = 1;    // level-0 table entries
+    int start_tier = 0;
+};
 
 // Everything one query needs on the device besides the graph.
 struct Session {
@@ -410,6 +479,9 @@ struct Session {
     bool any_tier2 = false;
     bool replay_complete = false;  // every stored world fits the replay
     int last_tier() const { return any_tier2 ? 2 : 1; }
+    // Enqueue-only: every array is a piece of the caller's workspace, and
+    // nothing is read back or waited for on the host.
+    bool ws = false;
     TimedLaunches timed;
 
     Session(const imin::GraphDev& gd, hipStream_t st, imin_graph* h = nullptr) : g(gd), s(st), gh(h) {}
@@ -431,21 +503,187 @@ struct Session {
     // entries raises the graph's hints
     void record_scratch(unsigned long long bc, unsigned long long xc, uint64_t nw) {
         if (!gh || nw == 0) return;
-        auto raise = [](std::atomic<uint64_t>& a, uint64_t v) {
-            uint64_t cur = a.load(std::memory_order_relaxed);
-            while (v > cur && !a.compare_exchange_weak(cur, v, std::memory_order_relaxed)) {
-            }
-        };
-        raise(gh->big_per_world, (uint64_t)((bc << 10) / nw));
-        raise(gh->xbig_per_world, (uint64_t)((xc << 10) / nw));
+        raise_hint(gh->big_per_world, (uint64_t)((bc << 10) / nw));
+        raise_hint(gh->xbig_per_world, (uint64_t)((xc << 10) / nw));
+    }
+    // the tier a call's worlds start at: the one most worlds of earlier calls
+    // on the graph ended up in (IMIN_START_TIER overrides)
+    int hinted_start_tier() const {
+        if (const char* t = std::getenv("IMIN_START_TIER")) return std::max(0, std::min(2, std::atoi(t)));
+        if (!gh) return 0;
+        if (gh->tier2_share.load(std::memory_order_relaxed) > 512) return 2;
+        if (gh->tier1_share.load(std::memory_order_relaxed) > 512) return 1;
+        return 0;
     }
     // an early return may leave work queued: drain it before any block can
     // be handed to another call
     ~Session() {
-        if (hipStreamSynchronize(s) != hipSuccess) (void)hipGetLastError();
+        if (!ws && hipStreamSynchronize(s) != hipSuccess) (void)hipGetLastError();
     }
     Session(const Session&) = delete;
     Session& operator=(const Session&) = delete;
+
+    // Every array of an enqueued solve, taken in a fixed order (so that
+    // carving from an arena without a base gives the bytes a plan needs).
+    imin_status_t carve(const WsPlan& p, uint64_t theta, int32_t n_seeds) {
+        ws = true;
+        timed.on = false;
+        const size_t n = (size_t)g.n;
+        tile_cap = tile = (size_t)theta;
+        IMIN_TRY(ctl.alloc(1));
+        IMIN_TRY(excl.alloc((n + 31) / 32));
+        IMIN_TRY(gain.alloc(n));
+        IMIN_TRY(world_size.alloc(theta));
+        IMIN_TRY(wloc.alloc(theta));
+        IMIN_TRY(wlen.alloc(theta));
+        IMIN_TRY(list0.alloc(theta));
+        IMIN_TRY(list1.alloc(theta));
+        IMIN_TRY(list2.alloc(theta));
+        IMIN_TRY(list3.alloc(theta));
+        IMIN_TRY(seed_cnt.alloc((size_t)n_seeds));
+        IMIN_TRY(seed_table.alloc((size_t)p.chunk_cap));
+        IMIN_TRY(seed_col.alloc((size_t)p.chunk_cap));
+        IMIN_TRY(seed_thr.alloc((size_t)p.chunk_cap));
+        IMIN_TRY(thr_q.alloc((size_t)g.m_pad));
+        slot_cap0 = (size_t)imin::world_tier0_capacity();
+        big_cap = p.big_cap;
+        const size_t scr = tile_cap * slot_cap0 + big_cap;
+        IMIN_TRY(scr_node.alloc(scr));
+        IMIN_TRY(scr_cnt.alloc(scr));
+        gb = imin::gain_buckets(g.n);
+        IMIN_TRY(g_bcnt.alloc((size_t)gb.nb));
+        IMIN_TRY(g_bbase.alloc((size_t)gb.nb + 1));
+        IMIN_TRY(g_bcur.alloc((size_t)gb.nb));
+        gb.bcnt = g_bcnt.p;
+        gb.bbase = g_bbase.p;
+        gb.bcur = g_bcur.p;
+        const int cus = cu_count();
+        IMIN_TRY(alloc_slots(p.slots));
+        IMIN_TRY(alloc_grids(cus));
+        start_tier = p.start_tier;
+        any_tier2 = true;         // whether a world needs the HBM tier is not known on the host
+        replay_complete = false;  // nor whether every stored world fits the replay
+        if (p.incremental) {
+            incremental = true;
+            replay = true;
+            const char* fp = std::getenv("IMIN_LABEL_RULE");
+            label_rule = !(fp && fp[0] == '0');
+            xslot_cap0 = (size_t)imin::world_tier0_xcapacity();
+            xbig_cap = big_cap;
+            IMIN_TRY(scr_par.alloc(scr));
+            IMIN_TRY(scr_lab.alloc(scr));
+            IMIN_TRY(xscr_v.alloc(tile_cap * xslot_cap0 + xbig_cap));
+            IMIN_TRY(xscr_u.alloc(tile_cap * xslot_cap0 + xbig_cap));
+            IMIN_TRY(xloc.alloc(theta));
+            IMIN_TRY(xlen.alloc(theta));
+            IMIN_TRY(world_flags.alloc((theta + 3) & ~(uint64_t)3));
+            IMIN_TRY(alloc_index(scr));  // every scratch entry can be indexed
+        } else {
+            IMIN_TRY(g_rec.alloc(scr));
+        }
+        return IMIN_OK;
+    }
+
+    // One from-scratch pass of an enqueued solve over all theta worlds (one
+    // tile) under the current exclusions; round 0 of an incremental solve
+    // keeps its scratch as the resident store and builds the node index,
+    // whose pass also yields the gains.
+    imin_status_t pass_ws(const imin::QueryDev& q, uint64_t theta, bool round0, unsigned long long* hints) {
+        const bool keep = round0 && incremental;
+        IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.seed_cap, seed_col.p,
+                                               seed_thr.p, s));
+        IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+        imin::TileOut out = tile_out();
+        out.world_size = world_size.p;
+        out.keep_edges = keep ? 1 : 0;
+        imin_status_t st = launch_tiers(q, 0, (uint32_t)theta, nullptr, out, start_tier);
+        if (st != IMIN_OK) return st;
+        IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)theta, &ctl.p->tile_total, ctl.p, s));
+        if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)theta, &ctl.p->xtile_total, ctl.p, s));
+        // a world that found no room (or bad data) stops the solve here
+        IMIN_TRY(imin::launch_guard(ctl.p, imin::kFlagFatalMask, s, round0 ? theta : 0, round0 ? hints : nullptr));
+        if (keep) {
+            store_node.swap(scr_node);
+            store_cnt.swap(scr_cnt);
+            store_off.swap(wloc);
+            store_len.swap(wlen);
+            store_par.swap(scr_par);
+            store_lab.swap(scr_lab);
+            xstore_v.swap(xscr_v);
+            xstore_u.swap(xscr_u);
+            xstore_off.swap(xloc);
+            xstore_len.swap(xlen);
+            adopted = true;
+            st = build_index(theta, gain.p);
+            if (st != IMIN_OK) return st;
+        } else {
+            imin::GainSrc src{};
+            src.count = (uint32_t)theta;
+            src.node = scr_node.p;
+            src.cnt = scr_cnt.p;
+            src.off = wloc.p;
+            src.len = wlen.p;
+            src.cap = scr_node.count;
+            st = reduce_gains(src, 0);
+            if (st != IMIN_OK) return st;
+        }
+        IMIN_TRY(imin::launch_sum_sizes(world_size.p, (uint32_t)theta, ctl.p, s));
+        return IMIN_OK;
+    }
+
+    // A whole solve, enqueued: set-up, round 0 and k rounds, then the status.
+    // Every kernel returns at once after the selection stops or a fatal flag
+    // is raised, so nothing is decided on the host.
+    imin_status_t run_ws(const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
+                         int32_t chunk_cap, const imin::SelectOut& so, int32_t* device_status,
+                         unsigned long long* hints) {
+        IMIN_TRY(imin::launch_ctl_init(ctl.p, s));
+        IMIN_TRY(imin::launch_fill_i64((int64_t*)dsz.p, 0, (size_t)dsz_n, s));
+        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, (size_t)bs.n_slots * (size_t)g.n, s));
+        if (world_flags.p) IMIN_TRY(imin::launch_fill_u8(world_flags.p, 0, world_flags.count, s));
+        IMIN_TRY(imin::launch_query_setup(g, seeds, n_seeds, nullptr, 0, excl.p, ctl.p, s));
+        IMIN_TRY(imin::launch_seed_count(g, seeds, n_seeds, seed_cnt.p, ctl.p, s));
+        IMIN_TRY(imin::launch_guard(ctl.p, imin::kFlagDataMask, s));
+        IMIN_TRY(imin::launch_seed_fill(g, seeds, n_seeds, seed_cnt.p, seed_table.p, chunk_cap, ctl.p, s));
+        const imin::QueryDev q = make_query(seeds, n_seeds, rng_seed, chunk_cap);
+        IMIN_TRY(imin::launch_ctl_reset_round(ctl.p, s));
+        IMIN_TRY(imin::launch_fill_i64_live(gain.p, 0, (size_t)g.n, ctl.p, s));
+        imin_status_t st = pass_ws(q, theta, true, hints);
+        if (st != IMIN_OK) return st;
+        IMIN_TRY(imin::launch_select(g, gain.p, ctl.p, so, dsz.p, dsz_n, !incremental || k == 0, s));
+        for (int32_t r = 1; r <= k; ++r) {
+            if (incremental) {
+                st = delta_round(q, theta, so);
+            } else {
+                IMIN_TRY(imin::launch_ctl_reset_round(ctl.p, s));
+                IMIN_TRY(imin::launch_fill_i64_live(gain.p, 0, (size_t)g.n, ctl.p, s));
+                st = pass_ws(q, theta, false, nullptr);
+                if (st == IMIN_OK) IMIN_TRY(imin::launch_select(g, gain.p, ctl.p, so, dsz.p, dsz_n, true, s));
+            }
+            if (st != IMIN_OK) return st;
+        }
+        IMIN_TRY(imin::launch_solve_status(ctl.p, device_status, so.n_selected, theta, hints, s));
+        return IMIN_OK;
+    }
+
+    // The query as the kernels take it (the level-0 table's length and the
+    // seeds' sums are read on the device).
+    imin::QueryDev make_query(const int32_t* seeds, int32_t n_seeds, uint64_t rng_seed, int32_t chunk_cap) const {
+        imin::QueryDev q{};
+        q.excl = excl.p;
+        q.thr = thr_q.p;
+        q.excl_in_thr = 1;
+        q.seeds = seeds;
+        q.n_seeds = n_seeds;
+        q.key0 = (uint32_t)rng_seed;
+        q.key1 = (uint32_t)(rng_seed >> 32);
+        q.seed_chunk = seed_table.p;
+        q.seed_col = seed_col.p;
+        q.seed_thr = seed_thr.p;
+        q.seed_cap = chunk_cap;
+        q.n_seed_chunks = chunk_cap;
+        return q;
+    }
 
     imin::SelectOut select_out(int32_t k, int32_t* blockers, int64_t* gains, int64_t* totals,
                                int32_t* n_selected) const {
@@ -475,6 +713,86 @@ struct Session {
         return IMIN_OK;
     }
 
+    // bytes of one HBM-tier slot: 6 node arrays (+ level offsets) and 2
+    // extra-edge arrays
+    size_t slot_bytes() const {
+        const size_t n = (size_t)g.n;
+        return (5 * n + (n + 3)) * 4 + 2 * (size_t)std::max<int64_t>(g.m, 1) * 4;
+    }
+
+    // most HBM-tier slots a call uses (one per resident workgroup)
+    static int max_slots(int cus) { return cus * 4; }
+
+    // the HBM-tier slots of a call that takes its scratch from the block
+    // cache: as many as IMIN_BIG_BUDGET (default 6 GiB) allows, at most
+    // max_slots; allocated when a tile first hands a world to that tier (or
+    // starts there), so that calls whose worlds all fit the LDS tiers hold
+    // none
+    bool slots_ready() const { return b_lid.p != nullptr; }
+    imin_status_t ensure_slots() {
+        if (slots_ready()) return IMIN_OK;
+        const size_t big_budget = env_size("IMIN_BIG_BUDGET", (size_t)6 << 30);
+        IMIN_TRY(alloc_slots(std::min<size_t>(std::max<size_t>(big_budget / slot_bytes(), 1),
+                                              (size_t)max_slots(cu_count()))));
+        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, (size_t)bs.n_slots * (size_t)g.n, s));
+        return IMIN_OK;
+    }
+
+    // HBM-tier slots (at most one per world of a tile and max_slots)
+    hipError_t alloc_slots(size_t slots) {
+        const size_t n = (size_t)g.n;
+        const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
+        slots = std::max<size_t>(std::min<size_t>(slots, tile_cap), 1);
+        bs.n_slots = (int32_t)slots;
+        bs.xcap = (int64_t)xcap;
+        hipError_t e;
+        if ((e = b_lid.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = b_nodes.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = b_parent.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = b_idom.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = b_aux.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = b_lvl.alloc(slots * (n + 3))) != hipSuccess) return e;
+        if ((e = b_xv.alloc(slots * xcap)) != hipSuccess) return e;
+        if ((e = b_xu.alloc(slots * xcap)) != hipSuccess) return e;
+        bs.lid_of = b_lid.p;
+        bs.nodes = b_nodes.p;
+        bs.parent = b_parent.p;
+        bs.idom = b_idom.p;
+        bs.aux = b_aux.p;
+        bs.lvl = b_lvl.p;
+        bs.xv = b_xv.p;
+        bs.xu = b_xu.p;
+        return hipSuccess;
+    }
+
+    // launch shapes of the world and round kernels, the selection's parts
+    // and the per-workgroup lost-node slots (not cleared here)
+    hipError_t alloc_grids(int cus) {
+        const size_t n = (size_t)g.n;
+        // parts of the selection: few enough that combining them is cheap
+        // for every workgroup of the search that reads them
+        sel_parts = (int)std::min<size_t>(env_size("IMIN_SELECT_PARTS", 512), (n + 255) / 256);
+        hipError_t e;
+        if ((e = sel_g.alloc(sel_parts)) != hipSuccess) return e;
+        if ((e = sel_u.alloc(sel_parts)) != hipSuccess) return e;
+        if ((e = sel_d.alloc(sel_parts)) != hipSuccess) return e;
+        grid0 = cus * imin::world_tier_blocks_per_cu(0);
+        grid1 = cus * imin::world_tier_blocks_per_cu(1);
+        // changed-world update: label-rule and replay workgroups of one launch
+        grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
+        grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 2);
+        rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
+        grid_w = cus;  // wide replay: one 1024-thread workgroup per CU
+        const int sizes[6] = {grid0, grid1, max_slots(cus), grid_r, grid_l, grid_w};
+        int32_t at = 0;
+        for (int i = 0; i < 6; ++i) {
+            dsz_off[i] = at;
+            at += sizes[i];
+        }
+        dsz_n = at;
+        return dsz.alloc((size_t)dsz_n);
+    }
+
     imin_status_t init(uint64_t theta, bool solve) {
         const size_t n = (size_t)g.n;
         IMIN_TRY(excl.alloc((n + 31) / 32));
@@ -502,7 +820,6 @@ struct Session {
         IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
         IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
 
-        // HBM tier slots: per slot 6 node arrays (+lvl) and 2 edge arrays
         const int cus = cu_count();
         gb = imin::gain_buckets(g.n);
         IMIN_TRY(g_bcnt.alloc((size_t)gb.nb));
@@ -511,60 +828,15 @@ struct Session {
         gb.bcnt = g_bcnt.p;
         gb.bbase = g_bbase.p;
         gb.bcur = g_bcur.p;
-        const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
-        const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * xcap * 4;
-        const size_t big_budget = env_size("IMIN_BIG_BUDGET", (size_t)6 << 30);
-        size_t slots = big_budget / slot_bytes;
-        slots = std::min<size_t>(slots, (size_t)cus * 4);
-        slots = std::min<size_t>(slots, tile_cap);
-        slots = std::max<size_t>(slots, 1);
-        bs.n_slots = (int32_t)slots;
-        bs.xcap = (int64_t)xcap;
-        IMIN_TRY(b_lid.alloc(slots * n));
-        IMIN_TRY(b_nodes.alloc(slots * n));
-        IMIN_TRY(b_parent.alloc(slots * n));
-        IMIN_TRY(b_idom.alloc(slots * n));
-        IMIN_TRY(b_aux.alloc(slots * n));
-        IMIN_TRY(b_lvl.alloc(slots * (n + 3)));
-        IMIN_TRY(b_xv.alloc(slots * xcap));
-        IMIN_TRY(b_xu.alloc(slots * xcap));
-        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, slots * n, s));
-        bs.lid_of = b_lid.p;
-        bs.nodes = b_nodes.p;
-        bs.parent = b_parent.p;
-        bs.idom = b_idom.p;
-        bs.aux = b_aux.p;
-        bs.lvl = b_lvl.p;
-        bs.xv = b_xv.p;
-        bs.xu = b_xu.p;
-
-        // parts of the selection: few enough that combining them is cheap
-        // for every workgroup of the search that reads them
-        sel_parts = (int)std::min<size_t>(env_size("IMIN_SELECT_PARTS", 512), (n + 255) / 256);
-        IMIN_TRY(sel_g.alloc(sel_parts));
-        IMIN_TRY(sel_u.alloc(sel_parts));
-        IMIN_TRY(sel_d.alloc(sel_parts));
-        grid0 = cus * imin::world_tier_blocks_per_cu(0);
-        grid1 = cus * imin::world_tier_blocks_per_cu(1);
-        // changed-world update: label-rule and replay workgroups of one launch
-        grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
-        grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 2);
-        rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
-        grid_w = cus;  // wide replay: one 1024-thread workgroup per CU
-        {
-            const int sizes[6] = {grid0, grid1, bs.n_slots, grid_r, grid_l, grid_w};
-            int32_t at = 0;
-            for (int i = 0; i < 6; ++i) {
-                dsz_off[i] = at;
-                at += sizes[i];
-            }
-            dsz_n = at;
-            IMIN_TRY(dsz.alloc((size_t)dsz_n));
-            IMIN_TRY(hipMemsetAsync(dsz.p, 0, (size_t)dsz_n * sizeof(long long), s));
+        IMIN_TRY(alloc_grids(cus));
+        IMIN_TRY(hipMemsetAsync(dsz.p, 0, (size_t)dsz_n * sizeof(long long), s));
+        start_tier = hinted_start_tier();
+        if (start_tier == 2 || (gh && gh->tier2_seen.load(std::memory_order_relaxed))) {
+            const imin_status_t st = ensure_slots();
+            if (st != IMIN_OK) return st;
         }
-        if (const char* t = std::getenv("IMIN_START_TIER")) start_tier = std::max(0, std::min(2, std::atoi(t)));
         if (timed.on) {
-            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_l), bs.n_slots);
+            work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_l), max_slots(cus));
             const size_t wn = (size_t)imin::kWorkFields * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
             IMIN_TRY(hipMemsetAsync(work.p, 0, wn * sizeof(unsigned long long), s));
@@ -606,7 +878,8 @@ struct Session {
     // gain[u] += every count of u among the tile entries of src (`entries`
     // in all)
     imin_status_t reduce_gains(const imin::GainSrc& src, unsigned long long entries) {
-        if (!g_rec.p || g_rec.count < entries) IMIN_TRY(g_rec.alloc((size_t)(entries + entries / 8 + 1024)));
+        if (ws) entries = g_rec.count;  // carved for the most a tile can write
+        else if (!g_rec.p || g_rec.count < entries) IMIN_TRY(g_rec.alloc((size_t)(entries + entries / 8 + 1024)));
         gb.rec = g_rec.p;
         gb.rec_cap = g_rec.count;
         gb.slices = imin::gain_slices(gb, entries, cu_count());
@@ -709,34 +982,46 @@ struct Session {
     // there are at most 8192 buckets.
     imin_status_t build_index(uint64_t theta, int64_t* gain_out) {
         if (indexed) return IMIN_OK;
-        const unsigned long long entries = adopted ? adopted_entries : hctl.p->store_count;
-        if (entries > 0xFFFFFFFFull) return IMIN_ERR_INTERNAL;
-        const unsigned long long n = (unsigned long long)g.n;
-        int shift = (int)std::min<size_t>(std::max<size_t>(env_size("IMIN_INDEX_BUCKET_LOG", 10), 1), 30);
-        while (((n + (1ull << shift) - 1) >> shift) > 8192ull) ++shift;
-        const int nb = (int)((n + (1ull << shift) - 1) >> shift);
-        IMIN_TRY(idx_off.alloc(n + 1));
-        IMIN_TRY(idx_ent.alloc(entries));
-        IMIN_TRY(idx_bcnt.alloc((size_t)nb));
-        IMIN_TRY(idx_bbase.alloc((size_t)nb + 1));
-        IMIN_TRY(idx_bcur.alloc((size_t)nb));
-        IMIN_TRY(idx_border.alloc((size_t)nb));
-        IMIN_TRY(idx_rec.alloc(entries));
+        if (!ws) {
+            const unsigned long long entries = adopted ? adopted_entries : hctl.p->store_count;
+            if (entries > 0x7FFFFFFFull) return IMIN_ERR_INTERNAL;  // positions are int32
+            IMIN_TRY(alloc_index((size_t)entries));
+        }
         imin::IndexBufs ib{};
-        ib.shift = shift;
-        ib.nb = nb;
+        ib.shift = idx_shift;
+        ib.nb = (int)idx_bcnt.count;
         ib.bcnt = idx_bcnt.p;
         ib.bbase = idx_bbase.p;
         ib.bcur = idx_bcur.p;
         ib.border = idx_border.p;
         ib.rec = idx_rec.p;
-        ib.rec_cap = (uint32_t)entries;
+        ib.rec_cap = (uint32_t)idx_rec.count;
         ib.idx_off = idx_off.p;
         ib.idx_ent = idx_ent.p;
-        ib.ent_cap = (uint32_t)entries;
+        ib.ent_cap = (uint32_t)idx_ent.count;
         IMIN_TRY(imin::launch_index_build(tile_out(), (uint32_t)theta, g.n, ib, gain_out, ctl.p, s));
         indexed = true;
         return IMIN_OK;
+    }
+
+    // arrays of the node index for `entries` stored entries (< 2^31).
+    // Nodes are grouped in buckets of 2^IMIN_INDEX_BUCKET_LOG ids (default
+    // 10), widened until there are at most 8192 buckets.
+    int idx_shift = 10;
+    hipError_t alloc_index(size_t entries) {
+        const unsigned long long n = (unsigned long long)g.n;
+        int shift = (int)std::min<size_t>(std::max<size_t>(env_size("IMIN_INDEX_BUCKET_LOG", 10), 1), 30);
+        while (((n + (1ull << shift) - 1) >> shift) > 8192ull) ++shift;
+        idx_shift = shift;
+        const size_t nb = (size_t)((n + (1ull << shift) - 1) >> shift);
+        hipError_t e;
+        if ((e = idx_off.alloc(n + 1)) != hipSuccess) return e;
+        if ((e = idx_ent.alloc(entries)) != hipSuccess) return e;
+        if ((e = idx_bcnt.alloc(nb)) != hipSuccess) return e;
+        if ((e = idx_bbase.alloc(nb + 1)) != hipSuccess) return e;
+        if ((e = idx_bcur.alloc(nb)) != hipSuccess) return e;
+        if ((e = idx_border.alloc(nb)) != hipSuccess) return e;
+        return idx_rec.alloc(entries);
     }
 
     imin::TileOut tile_out() const {
@@ -787,6 +1072,7 @@ struct Session {
     imin_status_t launch_tiers(const imin::QueryDev& q, uint32_t wb, uint32_t range, const int32_t* first_list,
                                const imin::TileOut& out, int first_tier, int first_idx = 0, int last_tier = 2) {
         for (int tier = first_tier; tier <= last_tier; ++tier) {
+            if (tier == 2 && !slots_ready()) return IMIN_ERR_INTERNAL;  // never launched without its slots
             const bool first = (tier == first_tier);
             const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : list2.p);
             const int count_idx = first ? first_idx : tier;
@@ -858,7 +1144,7 @@ struct Session {
                            int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false) {
         // the exclusions as they stand (blockers may have been added since
         // the last pass) go into the query's thresholds
-        IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.n_seed_chunks, seed_col.p,
+        IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.seed_cap, seed_col.p,
                                                seed_thr.p, s));
         uint64_t done = 0;
         while (done < count) {
@@ -870,7 +1156,21 @@ struct Session {
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
             out.keep_edges = keep ? 1 : 0;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            imin_status_t st = launch_tiers(q, (uint32_t)(w_begin + done), (uint32_t)nw, nullptr, out, start_tier);
+            const uint32_t wb = (uint32_t)(w_begin + done);
+            imin_status_t st;
+            if (start_tier == 2 && (st = ensure_slots()) != IMIN_OK) return st;
+            if (slots_ready()) {
+                st = launch_tiers(q, wb, (uint32_t)nw, nullptr, out, start_tier);
+            } else {
+                // the LDS tiers first; the HBM tier (and its slots) only for
+                // the worlds they hand on
+                st = launch_tiers(q, wb, (uint32_t)nw, nullptr, out, start_tier, 0, 1);
+                if (st == IMIN_OK) st = read_ctl();
+                if (st == IMIN_OK && hctl.p->list_n[2] > 0) {
+                    st = ensure_slots();
+                    if (st == IMIN_OK) st = launch_tiers(q, wb, 0, list2.p, out, 2, 2, 2);
+                }
+            }
             if (st != IMIN_OK) return st;
             IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)nw, &ctl.p->tile_total, ctl.p, s));
             if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)nw, &ctl.p->xtile_total, ctl.p, s));
@@ -878,6 +1178,11 @@ struct Session {
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
             if (hctl.p->list_n[2] > 0 || start_tier == 2) any_tier2 = true;
+            if (hctl.p->list_n[2] > 0 && gh) gh->tier2_seen.store(true, std::memory_order_relaxed);
+            if (gh && nw > 0) {
+                raise_hint(gh->tier1_share, ((uint64_t)hctl.p->list_n[1] << 10) / nw);
+                raise_hint(gh->tier2_share, ((uint64_t)hctl.p->list_n[2] << 10) / nw);
+            }
             replay_complete = (hctl.p->replay_big == 0);
             // route later tiles straight to the tier most worlds end up in
             if (start_tier < 2 && hctl.p->list_n[2] * 2 > nw) start_tier = 2;
@@ -1035,6 +1340,7 @@ const char* imin_status_string(imin_status_t s) {
         case IMIN_ERR_DEVICE: return "HIP runtime error";
         case IMIN_ERR_NOMEM: return "out of device memory";
         case IMIN_ERR_INTERNAL: return "internal consistency check failed";
+        case IMIN_ERR_WORKSPACE: return "workspace too small";
     }
     return "unknown status";
 }
@@ -1058,16 +1364,21 @@ imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, co
     hipError_t e = hipMalloc((void**)&h->g.off, ((size_t)n + 1) * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&h->g.col, (size_t)h->g.m_pad * sizeof(int32_t));
     if (e == hipSuccess) e = hipMalloc((void**)&h->g.thr, (size_t)h->g.m_pad * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&h->hints_dev, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemsetAsync(h->hints_dev, 0, 4 * sizeof(unsigned long long), s);
     imin::RoundCtl* ctl = nullptr;
     imin::RoundCtl* hc = nullptr;
     if (e == hipSuccess) e = hipMalloc((void**)&ctl, sizeof(imin::RoundCtl));
     if (e == hipSuccess) e = hipHostMalloc((void**)&hc, sizeof(imin::RoundCtl), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemsetAsync(ctl, 0, sizeof(imin::RoundCtl), s);
     if (e == hipSuccess) e = imin::launch_graph_ingest(h->g, row_ptr, col, p, ctl, s);
+    // the largest out-degree bounds the level-0 table of any seed set
+    if (e == hipSuccess) e = imin::launch_max_degree(h->g, &ctl->seed_chunks, s);
     if (e == hipSuccess) e = hipMemcpyAsync(hc, ctl, sizeof(imin::RoundCtl), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     imin_status_t st = from_hip(e);
     if (st == IMIN_OK) st = check_data_flags(hc->flags);
+    if (st == IMIN_OK) h->g.max_deg = hc->seed_chunks;
     if (ctl) (void)hipFree(ctl);
     if (hc) (void)hipHostFree(hc);
     if (st != IMIN_OK) {
@@ -1083,6 +1394,7 @@ imin_status_t imin_graph_destroy(imin_graph_t g) {
     if (g->g.off) (void)hipFree(g->g.off);
     if (g->g.col) (void)hipFree(g->g.col);
     if (g->g.thr) (void)hipFree(g->g.thr);
+    if (g->hints_dev) (void)hipFree(g->hints_dev);
     delete g;
     return IMIN_OK;
 }
@@ -1106,26 +1418,26 @@ static imin_status_t setup_query(Session& ss, const int32_t* seeds, int32_t n_se
     IMIN_TRY(imin::launch_seed_count(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.ctl.p, ss.s));
     st = ss.read_ctl();
     if (st != IMIN_OK) return st;
-    const int32_t chunks = ss.hctl.p->seed_chunks;
-    IMIN_TRY(ss.seed_table.alloc((size_t)std::max(chunks, 1)));
-    IMIN_TRY(ss.seed_col.alloc((size_t)std::max(chunks, 1)));
-    IMIN_TRY(ss.seed_thr.alloc((size_t)std::max(chunks, 1)));
+    const int32_t chunks = std::max(ss.hctl.p->seed_chunks, 1);
+    IMIN_TRY(ss.seed_table.alloc((size_t)chunks));
+    IMIN_TRY(ss.seed_col.alloc((size_t)chunks));
+    IMIN_TRY(ss.seed_thr.alloc((size_t)chunks));
     IMIN_TRY(ss.thr_q.alloc((size_t)ss.g.m_pad));
-    if (chunks > 0) IMIN_TRY(imin::launch_seed_fill(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.seed_table.p, ss.s));
-    q.excl = ss.excl.p;
-    q.thr = ss.thr_q.p;
-    q.excl_in_thr = 1;
-    q.seed_col = ss.seed_col.p;
-    q.seed_thr = ss.seed_thr.p;
-    q.seeds = seeds;
-    q.n_seeds = n_seeds;
-    q.key0 = (uint32_t)rng_seed;
-    q.key1 = (uint32_t)(rng_seed >> 32);
-    q.seed_chunk = ss.seed_table.p;
-    q.n_seed_chunks = chunks;
-    q.seed_sum = ss.hctl.p->seed_sum;
-    q.seed_edges = ss.hctl.p->seed_edges;
+    IMIN_TRY(imin::launch_seed_fill(ss.g, seeds, n_seeds, ss.seed_cnt.p, ss.seed_table.p, chunks, ss.ctl.p, ss.s));
+    q = ss.make_query(seeds, n_seeds, rng_seed, chunks);
     return IMIN_OK;
+}
+
+// a solve's status, also written to its device_status word when given
+static imin_status_t with_device_status(imin_status_t st, int32_t* device_status, void* stream) {
+    if (device_status) {
+        const hipStream_t s = (hipStream_t)stream;
+        if (imin::launch_fill_i32(device_status, (int32_t)st, 1, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipGetLastError();
+            if (st == IMIN_OK) st = IMIN_ERR_DEVICE;
+        }
+    }
+    return st;
 }
 
 static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
@@ -1194,6 +1506,129 @@ static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_
     return IMIN_OK;
 }
 
+// ---- enqueued solves: a caller's workspace, nothing read back
+
+// the largest level-0 table a seed set of n_seeds seeds can need
+static int32_t chunk_bound(const imin::GraphDev& g, int32_t n_seeds) {
+    const long long per = (long long)g.max_deg / 4 + 2;
+    const long long all = g.m_pad / 4 + n_seeds;
+    return (int32_t)std::max(1ll, std::min((long long)n_seeds * per, all));
+}
+
+// bytes a plan takes from a workspace
+static size_t plan_bytes(imin_graph_t g, const WsPlan& p, uint64_t theta, int32_t n_seeds) {
+    Arena sizing;
+    ArenaScope as(&sizing);
+    Session ss(g->g, nullptr, g);
+    (void)ss.carve(p, theta, n_seeds);
+    return sizing.used;
+}
+
+static void fixed_plan(imin_graph_t g, WsPlan& p, int32_t n_seeds, uint64_t theta) {
+    const size_t n = (size_t)g->g.n;
+    const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * (size_t)std::max<int64_t>(g->g.m, 1) * 4;
+    const int cus = cu_count();
+    // HBM-tier slots: up to 1 GiB of them, one per resident workgroup at most
+    p.slots = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(((size_t)1 << 30) / slot_bytes, (size_t)cus * 4),
+                                                    (size_t)theta));
+    p.chunk_cap = chunk_bound(g->g, n_seeds);
+    p.start_tier = 0;
+    if (const char* t = std::getenv("IMIN_START_TIER")) p.start_tier = std::max(0, std::min(2, std::atoi(t)));
+    else if (g->tier2_share.load(std::memory_order_relaxed) > 512) p.start_tier = 2;
+    else if (g->tier1_share.load(std::memory_order_relaxed) > 512) p.start_tier = 1;
+}
+
+// incremental rounds index every scratch entry with an int32 position
+static bool incremental_fits(uint64_t theta, size_t big_cap) {
+    const char* inc_env = std::getenv("IMIN_INCREMENTAL");
+    if (inc_env && inc_env[0] == '0') return false;
+    return theta * (uint64_t)imin::world_tier0_capacity() + big_cap < ((uint64_t)1 << 31);
+}
+
+// The layout for a workspace of `bytes`: incremental rounds when they fit,
+// else plain rounds; the bump region takes what the fixed arrays leave.
+static imin_status_t plan_for(imin_graph_t g, int32_t n_seeds, uint64_t theta, size_t bytes, WsPlan& out) {
+    WsPlan p;
+    fixed_plan(g, p, n_seeds, theta);
+    for (int inc = 1; inc >= 0; --inc) {
+        p.incremental = inc == 1;
+        if (p.incremental && !incremental_fits(theta, 0)) continue;
+        p.big_cap = 0;
+        const size_t base = plan_bytes(g, p, theta, n_seeds);
+        if (base > bytes) continue;
+        p.big_cap = (size_t)1 << 20;
+        const size_t per = (plan_bytes(g, p, theta, n_seeds) - base + ((size_t)1 << 20) - 1) >> 20;
+        size_t big = (bytes - base) / std::max<size_t>(per, 1);
+        if (p.incremental) big = std::min<size_t>(big, ((size_t)1 << 31) - 1 - theta * (size_t)imin::world_tier0_capacity());
+        p.big_cap = big;
+        while (p.big_cap > 0 && plan_bytes(g, p, theta, n_seeds) > bytes) p.big_cap -= std::min<size_t>(p.big_cap, 4096);
+        out = p;
+        return IMIN_OK;
+    }
+    return IMIN_ERR_WORKSPACE;
+}
+
+// the graph's device-side hints folded into its host-side ones
+static void fold_device_hints(imin_graph_t g) {
+    unsigned long long h[4] = {0, 0, 0, 0};
+    if (hipMemcpy(h, g->hints_dev, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    raise_hint(g->big_per_world, h[0]);
+    raise_hint(g->xbig_per_world, h[1]);
+    raise_hint(g->tier1_share, h[2]);
+    raise_hint(g->tier2_share, h[3]);
+    if (h[3] > 0) g->tier2_seen.store(true, std::memory_order_relaxed);
+}
+
+static imin_status_t workspace_size_impl(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes) {
+    if (!g || !bytes || n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n || theta < 1 ||
+        theta > (int64_t)0xFFFFFFFFll)
+        return IMIN_ERR_INVALID;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    if (prev != g->device) (void)hipSetDevice(g->device);
+    fold_device_hints(g);
+    WsPlan p;
+    fixed_plan(g, p, n_seeds, (uint64_t)theta);
+    // bump entries (and as many extra edges) for the worlds beyond tier 0, from
+    // what earlier calls on the graph needed, with an eighth more
+    const uint64_t per = std::max(g->big_per_world.load(), g->xbig_per_world.load());
+    const unsigned long long need = (per * (unsigned long long)theta) >> 10;
+    p.big_cap = std::max<size_t>((size_t)1 << 20, (size_t)(need + need / 8 + 1024));
+    p.incremental = incremental_fits((uint64_t)theta, p.big_cap);
+    *bytes = plan_bytes(g, p, (uint64_t)theta, n_seeds);
+    if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
+    return IMIN_OK;
+}
+
+static imin_status_t solve_ws_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                                   uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream,
+                                   int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
+                                   int32_t* device_status) {
+    g_last_flags = 0;
+    if (!g || !seeds || !blockers || !gains || !spread_totals || !n_selected || !device_status || !workspace)
+        return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
+    if (theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
+    if ((uintptr_t)workspace % 256 != 0) return IMIN_ERR_INVALID;
+    WsPlan plan;
+    imin_status_t st = plan_for(g, n_seeds, (uint64_t)theta, workspace_bytes, plan);
+    if (st != IMIN_OK) return st;
+    Arena arena;
+    arena.base = static_cast<char*>(workspace);
+    arena.size = workspace_bytes;
+    ArenaScope as(&arena);
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s, g);
+    st = ss.carve(plan, (uint64_t)theta, n_seeds);
+    if (arena.failed) return IMIN_ERR_WORKSPACE;
+    if (st != IMIN_OK) return st;
+    const imin::SelectOut so = ss.select_out(k, blockers, gains, spread_totals, n_selected);
+    return ss.run_ws(seeds, n_seeds, k, (uint64_t)theta, rng_seed, plan.chunk_cap, so, device_status, g->hints_dev);
+}
+
 static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
                                    int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed,
                                    void* stream, int64_t* gain, int64_t* total, int32_t* world_size,
@@ -1229,11 +1664,25 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
 // call end it with IMIN_ERR_NOMEM (its session drains its stream while
 // unwinding).
 imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
-                         uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
-                         int64_t* spread_totals, int32_t* n_selected) {
+                         uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream, int32_t* blockers,
+                         int64_t* gains, int64_t* spread_totals, int32_t* n_selected, int32_t* device_status) {
     try {
-        return solve_impl(g, seeds, n_seeds, k, theta, rng_seed, stream, blockers, gains, spread_totals,
-                          n_selected);
+        if (workspace)
+            return solve_ws_impl(g, seeds, n_seeds, k, theta, rng_seed, workspace, workspace_bytes, stream, blockers,
+                                 gains, spread_totals, n_selected, device_status);
+        const imin_status_t st = solve_impl(g, seeds, n_seeds, k, theta, rng_seed, stream, blockers, gains,
+                                            spread_totals, n_selected);
+        return st == IMIN_ERR_INVALID ? st : with_device_status(st, device_status, stream);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_solve_workspace_size(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes) {
+    try {
+        return workspace_size_impl(g, n_seeds, k, theta, bytes);
     } catch (const std::bad_alloc&) {
         return IMIN_ERR_NOMEM;
     } catch (...) {
@@ -1288,8 +1737,8 @@ imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_q
             const int32_t j = next.fetch_add(1);
             if (j >= n_queries) break;
             imin_query_t& Q = queries[order[(size_t)j]];
-            Q.status = (int32_t)imin_solve(g, Q.seeds, Q.n_seeds, Q.k, Q.theta, Q.rng_seed, streams[i], Q.blockers,
-                                           Q.gains, Q.spread_totals, Q.n_selected);
+            Q.status = (int32_t)imin_solve(g, Q.seeds, Q.n_seeds, Q.k, Q.theta, Q.rng_seed, nullptr, 0, streams[i],
+                                           Q.blockers, Q.gains, Q.spread_totals, Q.n_selected, nullptr);
             Q.device_flags = g_last_flags;
         }
         if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
@@ -1342,8 +1791,9 @@ struct imin_server {
                 q = queue.front();
                 queue.pop_front();
             }
-            q->status = (int32_t)imin_solve(g, q->seeds, q->n_seeds, q->k, q->theta, q->rng_seed, streams[(size_t)i],
-                                            q->blockers, q->gains, q->spread_totals, q->n_selected);
+            q->status = (int32_t)imin_solve(g, q->seeds, q->n_seeds, q->k, q->theta, q->rng_seed, nullptr, 0,
+                                            streams[(size_t)i], q->blockers, q->gains, q->spread_totals,
+                                            q->n_selected, nullptr);
             q->device_flags = g_last_flags;
             {
                 std::lock_guard<std::mutex> lk(mu);

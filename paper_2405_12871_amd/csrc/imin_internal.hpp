@@ -26,7 +26,12 @@ enum : uint32_t {
     kFlagDomPasses = 1u << 11,      // dominator passes did not settle
     kFlagStoreOverflow = 1u << 12,  // resident per-world store too small
     kFlagReduceCapacity = 1u << 13, // more entries than the reduction's buffers hold
-    kFlagBounds = 1u << 14          // a per-world range fell outside its buffer
+    kFlagBounds = 1u << 14,         // a per-world range fell outside its buffer
+    // a solve cannot go on once any of these is set
+    kFlagFatalMask = kFlagDataMask | kFlagPairOverflow | kFlagBigCapacity | kFlagSpreadMismatch | kFlagDomPasses |
+                     kFlagStoreOverflow | kFlagReduceCapacity | kFlagBounds,
+    // of those, the ones that mean a caller's workspace was too small
+    kFlagCapacityMask = kFlagPairOverflow | kFlagStoreOverflow | kFlagReduceCapacity
 };
 
 // Graph as kept by a handle.  col/thr are padded with 4..7 trailing entries
@@ -38,6 +43,7 @@ struct GraphDev {
     int32_t* off;  // [n+1]
     int32_t* col;  // [m_pad]
     uint32_t* thr; // [m_pad]
+    int32_t max_deg;  // largest out-degree
 };
 
 // Round and tile counters, one instance in device memory per call.
@@ -220,6 +226,7 @@ struct QueryDev {
     const int4* seed_chunk;  // level-0 slot groups {blk, seed lid, e0, e1}
     const int4* seed_col;    // their columns
     const uint4* seed_thr;   // their thresholds (from thr)
+    int32_t seed_cap;        // entries the table holds (kernels take the length from RoundCtl::seed_chunks)
     int32_t n_seed_chunks;
     long long seed_sum;
     long long seed_edges;
@@ -255,6 +262,8 @@ hipError_t launch_graph_ingest(const GraphDev& g, const int64_t* row_ptr, const 
                                const float* p, RoundCtl* ctl, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t count, hipStream_t s);
+hipError_t launch_fill_i64_live(int64_t* p, int64_t v, size_t count, const RoundCtl* ctl, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, size_t count, hipStream_t s);
 hipError_t launch_query_setup(const GraphDev& g, const int32_t* seeds, int32_t n_seeds,
                               const int32_t* blocked, int32_t n_blocked, uint32_t* excl,
                               RoundCtl* ctl, hipStream_t s);
@@ -315,7 +324,22 @@ hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
-                            int4* table, hipStream_t s);
+                            int4* table, int32_t cap, RoundCtl* ctl, hipStream_t s);
+// ctl = {0, expect_total = -1}, by a kernel (no host copy)
+hipError_t launch_ctl_init(RoundCtl* ctl, hipStream_t s);
+// stop every later kernel once a flag of `mask` is set; with hints, also
+// raise hints[2] / hints[3] to the shares of the tile's theta worlds handed
+// on to tier 1 / tier 2 (1/1024 units)
+hipError_t launch_guard(RoundCtl* ctl, uint32_t mask, hipStream_t s, uint64_t theta = 0,
+                        unsigned long long* hints = nullptr);
+// the end of an enqueued solve: device_status from the flags (0, or an
+// imin_status_t code), n_selected = 0 when the solve stopped on an error,
+// and the graph's per-world scratch hints raised by what round 0 asked for
+// (entries * 1024 / theta, for bump-region entries and extra edges)
+hipError_t launch_solve_status(RoundCtl* ctl, int32_t* device_status, int32_t* n_selected, uint64_t theta,
+                               unsigned long long* hints, hipStream_t s);
+// largest out-degree of the graph into *out (device)
+hipError_t launch_max_degree(const GraphDev& g, int32_t* out, hipStream_t s);
 // thr_q[e] = 0 where col[e] is excluded, else the graph's threshold; then the
 // level-0 table's columns and thresholds (ctl->seed_chunks entries, at most
 // chunk_cap)

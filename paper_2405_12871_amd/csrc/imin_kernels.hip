@@ -9,6 +9,7 @@
 // changes to the gains with integer atomics in the world kernels.)
 #include <algorithm>
 
+#include "imin.h"
 #include "imin_device.hpp"
 #include "imin_internal.hpp"
 #include "imin_select.hpp"
@@ -60,22 +61,28 @@ hipError_t launch_graph_ingest(const GraphDev& g, const int64_t* row_ptr, const 
     return hipGetLastError();
 }
 
+// p[0 .. count) = v; with ctl given, nothing once the solve has stopped
 template <class T>
-__global__ void k_fill(T* p, T v, size_t count) {
+__global__ void k_fill(T* p, T v, size_t count, const RoundCtl* ctl) {
+    if (ctl && ctl->stop) return;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += stride) p[i] = v;
 }
 
 template <class T>
-static hipError_t fill(T* p, T v, size_t count, hipStream_t s) {
+static hipError_t fill(T* p, T v, size_t count, hipStream_t s, const RoundCtl* ctl = nullptr) {
     if (count == 0) return hipSuccess;
     size_t blocks = (count + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    k_fill<T><<<(unsigned)blocks, 256, 0, s>>>(p, v, count);
+    k_fill<T><<<(unsigned)blocks, 256, 0, s>>>(p, v, count, ctl);
     return hipGetLastError();
 }
 hipError_t launch_fill_i32(int32_t* p, int32_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
 hipError_t launch_fill_i64(int64_t* p, int64_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
+hipError_t launch_fill_i64_live(int64_t* p, int64_t v, size_t c, const RoundCtl* ctl, hipStream_t s) {
+    return fill(p, v, c, s, ctl);
+}
+hipError_t launch_fill_u8(uint8_t* p, uint8_t v, size_t c, hipStream_t s) { return fill(p, v, c, s); }
 
 // ------------------------------------------------------- query set-up
 // excl must be zero on entry.  Seeds are checked for range and repeats (the
@@ -154,6 +161,63 @@ __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
     ctl->xbig_count = 0;
     ctl->xtile_total = 0;
 }
+__global__ void k_ctl_init(RoundCtl* ctl) {
+    RoundCtl c{};
+    c.expect_total = -1;
+    *ctl = c;
+}
+
+__global__ void k_guard(RoundCtl* ctl, uint32_t mask, uint64_t theta, unsigned long long* hints) {
+    if (ctl->flags & mask) ctl->stop = 1;
+    if (hints && theta) {  // shares of the worlds handed on to tier 1 and tier 2 (1/1024 units)
+        atomicMax(&hints[2], ((unsigned long long)ctl->list_n[1] << 10) / theta);
+        atomicMax(&hints[3], ((unsigned long long)ctl->list_n[2] << 10) / theta);
+    }
+}
+
+__global__ void k_solve_status(RoundCtl* ctl, int32_t* status, int32_t* n_selected, uint64_t theta,
+                               unsigned long long* hints) {
+    const uint32_t f = ctl->flags;
+    int32_t st = IMIN_OK;
+    if (f & kFlagDataMask) st = IMIN_ERR_DATA;
+    else if (f & kFlagCapacityMask) st = IMIN_ERR_WORKSPACE;
+    else if (f & kFlagFatalMask) st = IMIN_ERR_INTERNAL;
+    if (status) *status = st;
+    if (st != IMIN_OK && n_selected) *n_selected = 0;
+    if (hints && theta) {
+        atomicMax(&hints[0], (ctl->big_count << 10) / theta);
+        atomicMax(&hints[1], (ctl->xbig_count << 10) / theta);
+    }
+}
+
+__global__ void k_max_degree(GraphDev g, int32_t* out) {
+    int d = 0;
+    for (int u = blockIdx.x * blockDim.x + threadIdx.x; u < g.n; u += gridDim.x * blockDim.x)
+        d = max(d, g.off[u + 1] - g.off[u]);
+    if (d > 0) atomicMax(out, d);
+}
+
+hipError_t launch_ctl_init(RoundCtl* ctl, hipStream_t s) {
+    k_ctl_init<<<1, 1, 0, s>>>(ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_guard(RoundCtl* ctl, uint32_t mask, hipStream_t s, uint64_t theta, unsigned long long* hints) {
+    k_guard<<<1, 1, 0, s>>>(ctl, mask, theta, hints);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_status(RoundCtl* ctl, int32_t* device_status, int32_t* n_selected, uint64_t theta,
+                               unsigned long long* hints, hipStream_t s) {
+    k_solve_status<<<1, 1, 0, s>>>(ctl, device_status, n_selected, theta, hints);
+    return hipGetLastError();
+}
+
+hipError_t launch_max_degree(const GraphDev& g, int32_t* out, hipStream_t s) {
+    k_max_degree<<<256, 256, 0, s>>>(g, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_ctl_reset_round(RoundCtl* ctl, hipStream_t s) {
     k_ctl_reset_round<<<1, 1, 0, s>>>(ctl);
     return hipGetLastError();
@@ -417,7 +481,7 @@ hipError_t launch_gain_reduce(const GainSrc& src, const GainBufs& gb, int32_t n,
     if (gb.nb < 1 || gb.nb > kGainMaxBuckets || ((long long)gb.nb << gb.shift) < (long long)n || gb.slices < 1)
         return hipErrorInvalidValue;
     if (src.count == 0) return hipSuccess;
-    hipError_t e = hipMemsetAsync(gb.bcnt, 0, (size_t)gb.nb * sizeof(long long), s);
+    hipError_t e = fill<long long>(gb.bcnt, 0ll, (size_t)gb.nb, s);
     if (e != hipSuccess) return e;
     const unsigned groups = (src.count + kGainWorlds - 1) / kGainWorlds;
     k_gain_count<<<groups, kGainNT, 0, s>>>(src, gb, ctl);
@@ -518,6 +582,9 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
         pu[blockIdx.x] = bu;
         pd[blockIdx.x] = dl;
         if (blockIdx.x == 0) {
+            // a solve that met a fatal condition (bad data, scratch too
+            // small, a failed check) commits nothing more
+            if (ctl->flags & kFlagFatalMask) ctl->stop = 1;
             // for the combining launch: the round, and the next round's counters cleared
             ctl->round_snap = ctl->round;
             for (int i = 0; i < 3; ++i) ctl->next[i] = 0;

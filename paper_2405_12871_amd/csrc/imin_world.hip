@@ -773,6 +773,16 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
     return true;
 }
 
+// The query as a world kernel runs it: the level-0 table's length and the
+// seeds' id and edge sums come from the device counters that the set-up
+// kernels wrote (a caller that enqueues a whole solve never reads them).
+__device__ __forceinline__ QueryDev query_at_run(QueryDev q, const RoundCtl* ctl) {
+    q.n_seed_chunks = min(ctl->seed_chunks, q.seed_cap);
+    q.seed_sum = ctl->seed_sum;
+    q.seed_edges = ctl->seed_edges;
+    return q;
+}
+
 // ------------------------------------------------------------- kernels
 // Tier 0 (one wave, small LDS store) and tier 1 (four waves, larger LDS
 // store).  With range_count > 0 the kernel takes worlds 0..range_count-1 of
@@ -809,13 +819,14 @@ __device__ __forceinline__ void add_work(const TileOut& out, int tier, unsigned 
 
 // Worlds are dealt to workgroups by a fixed stride (no shared work counter).
 template <int NT, class Store, int TIER>
-__global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
+__global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q_in, RoundCtl* ctl, uint32_t w_begin,
                                                   uint32_t range_count, const int32_t* in_list, int count_idx,
                                                   int32_t* next_list, TileOut out) {
     __shared__ Store st;
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
     if (ctl->stop) return;
+    const QueryDev q = query_at_run(q_in, ctl);
     const uint32_t n_items = in_list ? min(ctl->list_n[count_idx], count_idx ? out.next_cap : out.list_cap)
                                      : range_count;
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
@@ -859,7 +870,7 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q, RoundC
 }
 
 // Tier 2: per-world arrays in HBM, one slot per resident workgroup.
-__global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, RoundCtl* ctl, uint32_t w_begin,
+__global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q_in, RoundCtl* ctl, uint32_t w_begin,
                                                         uint32_t range_count, const int32_t* in_list,
                                                         int count_idx, TileOut out, BigSlots bs) {
     __shared__ WorldShared<kTier2NT> sh;
@@ -878,6 +889,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q, 
     st.cap_lv_ = g.n + 1;
     st.cap_x_ = bs.xcap;
     if (ctl->stop) return;
+    const QueryDev q = query_at_run(q_in, ctl);
     const uint32_t n_items = in_list ? min(ctl->list_n[count_idx], count_idx ? out.next_cap : out.list_cap)
                                      : range_count;
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
@@ -2319,20 +2331,27 @@ __global__ __launch_bounds__(1024) void k_seed_scan(int32_t* cnt, int32_t ns, Ro
     if (threadIdx.x == 0) ctl->seed_chunks = carry;
 }
 
-__global__ void k_seed_fill(GraphDev g, const int32_t* seeds, int32_t ns, const int32_t* start, int4* table) {
+__global__ void k_seed_fill(GraphDev g, const int32_t* seeds, int32_t ns, const int32_t* start, int4* table,
+                            int32_t cap, RoundCtl* ctl) {
+    if (ctl->stop) return;  // bad seeds: nothing to read
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
         const int32_t v = seeds[i];
         const int e0 = g.off[v], e1 = g.off[v + 1];
         if (e1 <= e0) continue;
         const int b0 = e0 >> 2, b1 = (e1 - 1) >> 2;
-        for (int b = b0; b <= b1; ++b) table[start[i] + (b - b0)] = make_int4(b, i, e0, e1);
+        for (int b = b0; b <= b1; ++b) {
+            const int j = start[i] + (b - b0);
+            if (j < cap) table[j] = make_int4(b, i, e0, e1);
+            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+        }
     }
 }
 
 // The per-query thresholds: the graph's, with every slot whose head is a
 // seed or a blocked node set to 0 (never live), and the level-0 table's
 // copies of its slot groups' columns and thresholds.
-__global__ void k_query_thr(GraphDev g, const uint32_t* excl, uint32_t* thr_q) {
+__global__ void k_query_thr(GraphDev g, const uint32_t* excl, uint32_t* thr_q, const RoundCtl* ctl) {
+    if (ctl->stop) return;
     const size_t groups = (size_t)g.m_pad / 4;
     for (size_t b = blockIdx.x * (size_t)blockDim.x + threadIdx.x; b < groups; b += (size_t)gridDim.x * blockDim.x) {
         const int4 c = *reinterpret_cast<const int4*>(g.col + 4 * b);
@@ -2348,6 +2367,7 @@ __global__ void k_query_thr(GraphDev g, const uint32_t* excl, uint32_t* thr_q) {
 
 __global__ void k_seed_slots(GraphDev g, const uint32_t* thr_q, const int4* table, const RoundCtl* ctl,
                              int32_t cap, int4* scol, uint4* sthr) {
+    if (ctl->stop) return;  // bad seeds: the table is not filled
     const int32_t nc = min(ctl->seed_chunks, cap);
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < nc; j += gridDim.x * blockDim.x) {
         const size_t b = (size_t)table[j].x;
@@ -2359,7 +2379,7 @@ __global__ void k_seed_slots(GraphDev g, const uint32_t* thr_q, const int4* tabl
 hipError_t launch_query_thresholds(const GraphDev& g, const uint32_t* excl, uint32_t* thr_q, const int4* table,
                                    const RoundCtl* ctl, int32_t chunk_cap, int4* seed_col, uint4* seed_thr,
                                    hipStream_t s) {
-    k_query_thr<<<2048, 256, 0, s>>>(g, excl, thr_q);
+    k_query_thr<<<2048, 256, 0, s>>>(g, excl, thr_q, ctl);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || chunk_cap < 1) return e;
     k_seed_slots<<<(chunk_cap + 255) / 256, 256, 0, s>>>(g, thr_q, table, ctl, chunk_cap, seed_col, seed_thr);
@@ -2376,8 +2396,8 @@ hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns
 }
 
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
-                            int4* table, hipStream_t s) {
-    k_seed_fill<<<(ns + 255) / 256, 256, 0, s>>>(g, seeds, ns, start, table);
+                            int4* table, int32_t cap, RoundCtl* ctl, hipStream_t s) {
+    k_seed_fill<<<(ns + 255) / 256, 256, 0, s>>>(g, seeds, ns, start, table, cap, ctl);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ def lib():
 def test_header_declares_the_boundary():
     names = binding.header_functions()
     for required in ("imin_graph_create", "imin_graph_destroy", "imin_graph_info", "imin_solve",
-                     "imin_evaluate", "imin_status_string", "imin_last_device_flags"):
+                     "imin_solve_workspace_size", "imin_evaluate", "imin_status_string", "imin_last_device_flags"):
         assert required in names
 
 
@@ -29,7 +29,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for code in range(6):
+    for code in range(7):
         s = lib.imin_status_string(code)
         assert s and s.decode() != "unknown status"
     assert lib.imin_status_string(99).decode() == "unknown status"
@@ -46,7 +46,10 @@ def test_host_argument_checks(lib):
     assert lib.imin_graph_create(5, 0, None, None, None, None, ctypes.byref(h)) == 1
     assert lib.imin_graph_create(5, 0, dummy, None, None, None, None) == 1
     # NULL graph handles
-    assert lib.imin_solve(None, dummy, 1, 1, 10, 0, None, dummy, dummy, dummy, dummy) == 1
+    assert lib.imin_solve(None, dummy, 1, 1, 10, 0, None, 0, None, dummy, dummy, dummy, dummy, None) == 1
+    assert lib.imin_solve(None, dummy, 1, 1, 10, 0, dummy, 1 << 20, None, dummy, dummy, dummy, dummy, dummy) == 1
+    nbytes = ctypes.c_size_t()
+    assert lib.imin_solve_workspace_size(None, 1, 1, 10, ctypes.byref(nbytes)) == 1
     assert lib.imin_evaluate(None, dummy, 1, None, 0, 0, 10, 0, None, dummy, dummy, None, None, None) == 1
     assert lib.imin_graph_info(None, None, None) == 1
     # imin_solve_many: NULL graph, no stream, a stream named twice, bad counts
