@@ -158,6 +158,28 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
 imin_status_t imin_solve_workspace_size(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes);
 
 /*
+ * imin_solve_static -- for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): imin_solve with its workspace taken from a fixed array of
+ * 256 MiB that the library declares, one copy per device, held until the
+ * process ends.  Arguments and outputs are those of imin_solve (device_status
+ * required); the call only enqueues on `stream` and allocates nothing.  The
+ * graph's device must be current.
+ *
+ * Limit: the solve's layout must fit the 256 MiB array; a larger one returns
+ * IMIN_ERR_WORKSPACE at once, and worlds that need more bump-region entries
+ * than the array leaves report IMIN_ERR_WORKSPACE in device_status.  Every
+ * call on a device shares that device's array and leaves the last call's
+ * contents in it: calls that overlap on one GPU (any streams) race, so the
+ * caller must order them.  IMIN_ERR_INVALID for bad arguments or when the
+ * graph's device is not current; IMIN_ERR_DEVICE if the array's address
+ * cannot be looked up.
+ */
+imin_status_t imin_solve_static(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                                uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains,
+                                int64_t* spread_totals, int32_t* n_selected, int32_t* device_status);
+
+/*
  * One query of imin_solve_many: the arguments of imin_solve (device arrays,
  * the same meaning and sizes) and, written by the call, the query's own
  * status and device flags (imin_last_device_flags of its solve).

@@ -68,6 +68,8 @@ def load():
     lib.imin_solve.restype = st
     lib.imin_solve_workspace_size.argtypes = [P, i32, i32, i64, ctypes.POINTER(ctypes.c_size_t)]
     lib.imin_solve_workspace_size.restype = st
+    lib.imin_solve_static.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P, P]
+    lib.imin_solve_static.restype = st
     lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32]
     lib.imin_solve_many.restype = st
     lib.imin_server_create.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P)]
@@ -247,6 +249,27 @@ def solve_enqueue(graph: Graph, seeds_dev, k: int, theta: int, rng_seed: int, wo
                               int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _ptr(workspace), workspace.numel(), st, _ptr(b),
                               _ptr(g), _ptr(t), _ptr(ns), _ptr(status)))
     return out, status
+
+
+def solve_static(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> "SolveResult":
+    """imin_solve_static (the workspace is the library's fixed device array),
+    waited for; raises on a non-zero device status."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    out = _solve_outputs(k, dev)
+    status = torch.full((1,), -1, dtype=torch.int32, device=dev)
+    b, g, t, ns = out
+    with torch.cuda.device(dev):
+        _check(lib.imin_solve_static(graph.handle, _ptr(s), int(s.numel()), int(k), int(theta),
+                                     int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(b), _ptr(g), _ptr(t),
+                                     _ptr(ns), _ptr(status)))
+    torch.cuda.synchronize(dev)
+    code = int(status.cpu()[0])
+    if code != IMIN_OK:
+        raise IminError(code, lib.imin_status_string(code).decode(), 0)
+    return result_of(out, theta)
 
 
 def result_of(out, theta: int) -> "SolveResult":

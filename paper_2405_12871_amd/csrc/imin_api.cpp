@@ -1663,6 +1663,28 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
 // No C++ exception crosses the boundary: host allocations that fail inside a
 // call end it with IMIN_ERR_NOMEM (its session drains its stream while
 // unwinding).
+}  // extern "C"
+
+namespace imin {
+imin_status_t solve_enqueued(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                             uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream,
+                             int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
+                             int32_t* device_status) {
+    try {
+        return solve_ws_impl(g, seeds, n_seeds, k, theta, rng_seed, workspace, workspace_bytes, stream, blockers,
+                             gains, spread_totals, n_selected, device_status);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+int graph_device(imin_graph_t g) { return g ? g->device : -1; }
+}  // namespace imin
+
+extern "C" {
+
 imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
                          uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream, int32_t* blockers,
                          int64_t* gains, int64_t* spread_totals, int32_t* n_selected, int32_t* device_status) {

@@ -367,4 +367,15 @@ hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, 
                          int32_t dsz_n, bool combine, hipStream_t s);
 
 
+// An enqueued solve in a given workspace (imin_solve with a workspace),
+// and the device a graph handle lives on.
+}  // namespace imin
+#include "imin.h"
+namespace imin {
+imin_status_t solve_enqueued(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                             uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream,
+                             int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
+                             int32_t* device_status);
+int graph_device(imin_graph_t g);
+
 } // namespace imin
