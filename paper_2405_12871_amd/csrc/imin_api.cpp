@@ -394,7 +394,8 @@ int cu_count() {
 struct WsPlan {
     bool incremental = true;  // resident store and node index (else every round evaluates all worlds)
     size_t big_cap = 0;       // bump-region entries for worlds beyond tier 0 (and as many extra edges)
-    size_t slots = 1;         // HBM-tier slots
+    size_t slots = 1;         // tier-2 slots (bounded per-world arrays)
+    size_t slots3 = 1;        // tier-3 slots (any world), when some world can outgrow tier 2
     int32_t chunk_cap = 1;    // level-0 table entries
     int start_tier = 0;
 };
@@ -414,7 +415,7 @@ struct Session {
     DevArray<int32_t> wlen;
     DevArray<int32_t> scr_node, scr_cnt;  // per-world scratch (fixed tier-0 slots + bump region)
     size_t slot_cap0 = 0, big_cap = 0;
-    DevArray<int32_t> list0, list1, list2, list3;  // changed worlds; worlds handed on (RoundCtl::list_n)
+    DevArray<int32_t> list0, list1, list2, list3, list4;  // changed worlds; worlds handed on (RoundCtl::list_n)
     // the gain reduction's buffers (bucket counts, bases, cursors, records)
     DevArray<long long> g_bcnt, g_bbase, g_bcur;
     DevArray<int2> g_rec;
@@ -437,7 +438,7 @@ struct Session {
     // nodes lost per (kernel, workgroup) in incremental rounds
     DevArray<long long> dsz;
     int32_t dsz_n = 0;
-    int32_t dsz_off[6] = {0, 0, 0, 0, 0, 0};
+    int32_t dsz_off[7] = {0, 0, 0, 0, 0, 0, 0};
     int grid_l = 0;
     bool adopted = false;                  // the round-0 scratch serves as the store
     unsigned long long adopted_entries = 0;
@@ -458,7 +459,15 @@ struct Session {
     DevArray<uint4> seed_thr;
     DevArray<uint32_t> thr_q;
     // HBM world tier
-    DevArray<int32_t> b_lid, b_nodes, b_parent, b_idom, b_aux, b_lvl, b_xv, b_xu;
+    // HBM-tier slots: tier 2's hold worlds of up to 2^16 nodes and 2^16
+    // extra edges (many slots), tier 3's any world of the graph (a few)
+    struct Slots {
+        DevArray<int32_t> lid, nodes, parent, idom, aux, lvl, xv, xu;
+        DevArray<uint32_t> vis;
+        imin::BigSlots bs{};
+        bool ready() const { return lid.p != nullptr; }
+    };
+    Slots t2, t3;
     imin::BigSlots bs{};
     // selection
     DevArray<int64_t> sel_g;
@@ -477,8 +486,9 @@ struct Session {
     // that fitted it before, so without such a world incremental rounds
     // never reach the HBM tier and do not launch it.
     bool any_tier2 = false;
+    bool any_tier3 = false;  // likewise for the worlds tier 2's slots cannot hold
     bool replay_complete = false;  // every stored world fits the replay
-    int last_tier() const { return any_tier2 ? 2 : 1; }
+    int last_tier() const { return any_tier3 ? 3 : (any_tier2 ? 2 : 1); }
     // Enqueue-only: every array is a piece of the caller's workspace, and
     // nothing is read back or waited for on the host.
     bool ws = false;
@@ -495,7 +505,7 @@ struct Session {
         if (!hint) return dflt;
         const unsigned long long per = hint->load(std::memory_order_relaxed);
         const unsigned long long need = (per * (unsigned long long)worlds) >> 10;
-        const unsigned long long want = std::min<unsigned long long>(need + need / 8 + 1024, 1ull << 28);
+        const unsigned long long want = std::min<unsigned long long>(need + need / 8 + 1024, 1ull << 34);
         return std::max<size_t>(dflt, (size_t)want);
     }
 
@@ -540,6 +550,7 @@ struct Session {
         IMIN_TRY(list1.alloc(theta));
         IMIN_TRY(list2.alloc(theta));
         IMIN_TRY(list3.alloc(theta));
+        IMIN_TRY(list4.alloc(theta));
         IMIN_TRY(seed_cnt.alloc((size_t)n_seeds));
         IMIN_TRY(seed_table.alloc((size_t)p.chunk_cap));
         IMIN_TRY(seed_col.alloc((size_t)p.chunk_cap));
@@ -558,10 +569,12 @@ struct Session {
         gb.bbase = g_bbase.p;
         gb.bcur = g_bcur.p;
         const int cus = cu_count();
-        IMIN_TRY(alloc_slots(p.slots));
+        IMIN_TRY(alloc_slots(t2, p.slots, t2_lid_cap(), t2_xcap()));
+        if (tier3_possible()) IMIN_TRY(alloc_slots(t3, p.slots3, g.n, std::max<int64_t>(g.m, 1)));
         IMIN_TRY(alloc_grids(cus));
         start_tier = p.start_tier;
-        any_tier2 = true;         // whether a world needs the HBM tier is not known on the host
+        any_tier2 = true;         // whether a world needs the HBM tiers is not known on the host
+        any_tier3 = tier3_possible();
         replay_complete = false;  // nor whether every stored world fits the replay
         if (p.incremental) {
             incremental = true;
@@ -596,7 +609,7 @@ struct Session {
         imin::TileOut out = tile_out();
         out.world_size = world_size.p;
         out.keep_edges = keep ? 1 : 0;
-        imin_status_t st = launch_tiers(q, 0, (uint32_t)theta, nullptr, out, start_tier);
+        imin_status_t st = launch_tiers(q, 0, (uint32_t)theta, nullptr, out, start_tier, 0, 3);
         if (st != IMIN_OK) return st;
         IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)theta, &ctl.p->tile_total, ctl.p, s));
         if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)theta, &ctl.p->xtile_total, ctl.p, s));
@@ -639,7 +652,8 @@ struct Session {
                          unsigned long long* hints) {
         IMIN_TRY(imin::launch_ctl_init(ctl.p, s));
         IMIN_TRY(imin::launch_fill_i64((int64_t*)dsz.p, 0, (size_t)dsz_n, s));
-        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, (size_t)bs.n_slots * (size_t)g.n, s));
+        IMIN_TRY(imin::launch_fill_i32((int32_t*)t2.vis.p, 0, t2.vis.count, s));
+        if (t3.ready()) IMIN_TRY(imin::launch_fill_i32((int32_t*)t3.vis.p, 0, t3.vis.count, s));
         if (world_flags.p) IMIN_TRY(imin::launch_fill_u8(world_flags.p, 0, world_flags.count, s));
         IMIN_TRY(imin::launch_query_setup(g, seeds, n_seeds, nullptr, 0, excl.p, ctl.p, s));
         IMIN_TRY(imin::launch_seed_count(g, seeds, n_seeds, seed_cnt.p, ctl.p, s));
@@ -713,55 +727,77 @@ struct Session {
         return IMIN_OK;
     }
 
-    // bytes of one HBM-tier slot: 6 node arrays (+ level offsets) and 2
-    // extra-edge arrays
-    size_t slot_bytes() const {
-        const size_t n = (size_t)g.n;
-        return (5 * n + (n + 3)) * 4 + 2 * (size_t)std::max<int64_t>(g.m, 1) * 4;
-    }
-
-    // most HBM-tier slots a call uses (one per resident workgroup)
+    // most tier-2 slots a call uses (one per resident workgroup)
     static int max_slots(int cus) { return cus * 4; }
 
-    // the HBM-tier slots of a call that takes its scratch from the block
-    // cache: as many as IMIN_BIG_BUDGET (default 6 GiB) allows, at most
-    // max_slots; allocated when a tile first hands a world to that tier (or
-    // starts there), so that calls whose worlds all fit the LDS tiers hold
-    // none
-    bool slots_ready() const { return b_lid.p != nullptr; }
-    imin_status_t ensure_slots() {
-        if (slots_ready()) return IMIN_OK;
-        const size_t big_budget = env_size("IMIN_BIG_BUDGET", (size_t)6 << 30);
-        IMIN_TRY(alloc_slots(std::min<size_t>(std::max<size_t>(big_budget / slot_bytes(), 1),
-                                              (size_t)max_slots(cu_count()))));
-        IMIN_TRY(imin::launch_fill_i32(b_lid.p, -1, (size_t)bs.n_slots * (size_t)g.n, s));
+    static constexpr int32_t kT2Nodes = 1 << 16;  // nodes a world may reach in a tier-2 slot
+    static constexpr int64_t kT2Edges = 1 << 16;  // extra edges it may keep there
+    int32_t t2_lid_cap() const { return std::min<int32_t>(g.n, kT2Nodes); }
+    int64_t t2_xcap() const { return std::min<int64_t>(std::max<int64_t>(g.m, 1), kT2Edges); }
+    // whether some world of the graph could outgrow a tier-2 slot
+    bool tier3_possible() const { return g.n > t2_lid_cap() || std::max<int64_t>(g.m, 1) > t2_xcap(); }
+
+    // bytes of one HBM-tier slot: node -> local id, the visited bitset, four
+    // per-node arrays and the level offsets, and two extra-edge arrays
+    size_t slot_bytes(int32_t lid_cap, int64_t xcap) const {
+        const size_t n = (size_t)g.n;
+        return n * 4 + (n + 31) / 32 * 4 + 4 * (size_t)lid_cap * 4 + ((size_t)lid_cap + 3) * 4 + 2 * (size_t)xcap * 4;
+    }
+    size_t t2_slot_bytes() const { return slot_bytes(t2_lid_cap(), t2_xcap()); }
+    size_t t3_slot_bytes() const { return slot_bytes(g.n, std::max<int64_t>(g.m, 1)); }
+
+    // the slots of a call that takes its scratch from the block cache,
+    // allocated when a tile first hands a world to their tier (or starts
+    // there), so that calls whose worlds all fit the LDS tiers hold none:
+    // tier 2 as many as IMIN_BIG_BUDGET (default 8 GiB) allows, at most
+    // max_slots; tier 3 as many as IMIN_HUGE_BUDGET (default 2 GiB) allows,
+    // at most one per compute unit
+    imin_status_t ensure_t2() {
+        if (t2.ready()) return IMIN_OK;
+        const size_t budget = env_size("IMIN_BIG_BUDGET", (size_t)8 << 30);
+        IMIN_TRY(alloc_slots(t2, std::min<size_t>(std::max<size_t>(budget / t2_slot_bytes(), 1),
+                                                  (size_t)max_slots(cu_count())),
+                             t2_lid_cap(), t2_xcap()));
+        IMIN_TRY(imin::launch_fill_i32((int32_t*)t2.vis.p, 0, t2.vis.count, s));
+        return IMIN_OK;
+    }
+    imin_status_t ensure_t3() {
+        if (t3.ready()) return IMIN_OK;
+        const size_t budget = env_size("IMIN_HUGE_BUDGET", (size_t)2 << 30);
+        IMIN_TRY(alloc_slots(t3, std::min<size_t>(std::max<size_t>(budget / t3_slot_bytes(), 1), (size_t)cu_count()),
+                             g.n, std::max<int64_t>(g.m, 1)));
+        IMIN_TRY(imin::launch_fill_i32((int32_t*)t3.vis.p, 0, t3.vis.count, s));
         return IMIN_OK;
     }
 
-    // HBM-tier slots (at most one per world of a tile and max_slots)
-    hipError_t alloc_slots(size_t slots) {
+    // slots of one HBM tier (at most one per world of a tile)
+    hipError_t alloc_slots(Slots& S, size_t slots, int32_t lid_cap, int64_t xcap) {
         const size_t n = (size_t)g.n;
-        const size_t xcap = (size_t)std::max<int64_t>(g.m, 1);
+        const size_t lc = (size_t)lid_cap;
         slots = std::max<size_t>(std::min<size_t>(slots, tile_cap), 1);
-        bs.n_slots = (int32_t)slots;
-        bs.xcap = (int64_t)xcap;
+        S.bs.n_slots = (int32_t)slots;
+        S.bs.lid_cap = lid_cap;
+        S.bs.xcap = xcap;
+        S.bs.vis_words = (int32_t)((n + 31) / 32);
         hipError_t e;
-        if ((e = b_lid.alloc(slots * n)) != hipSuccess) return e;
-        if ((e = b_nodes.alloc(slots * n)) != hipSuccess) return e;
-        if ((e = b_parent.alloc(slots * n)) != hipSuccess) return e;
-        if ((e = b_idom.alloc(slots * n)) != hipSuccess) return e;
-        if ((e = b_aux.alloc(slots * n)) != hipSuccess) return e;
-        if ((e = b_lvl.alloc(slots * (n + 3))) != hipSuccess) return e;
-        if ((e = b_xv.alloc(slots * xcap)) != hipSuccess) return e;
-        if ((e = b_xu.alloc(slots * xcap)) != hipSuccess) return e;
-        bs.lid_of = b_lid.p;
-        bs.nodes = b_nodes.p;
-        bs.parent = b_parent.p;
-        bs.idom = b_idom.p;
-        bs.aux = b_aux.p;
-        bs.lvl = b_lvl.p;
-        bs.xv = b_xv.p;
-        bs.xu = b_xu.p;
+        if ((e = S.lid.alloc(slots * n)) != hipSuccess) return e;
+        if ((e = S.nodes.alloc(slots * lc)) != hipSuccess) return e;
+        if ((e = S.parent.alloc(slots * lc)) != hipSuccess) return e;
+        if ((e = S.idom.alloc(slots * lc)) != hipSuccess) return e;
+        if ((e = S.aux.alloc(slots * lc)) != hipSuccess) return e;
+        if ((e = S.lvl.alloc(slots * (lc + 3))) != hipSuccess) return e;
+        if ((e = S.xv.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
+        if ((e = S.xu.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
+        if ((e = S.vis.alloc(slots * (size_t)S.bs.vis_words)) != hipSuccess) return e;
+        S.bs.vis = S.vis.p;
+        S.bs.lid_of = S.lid.p;
+        S.bs.nodes = S.nodes.p;
+        S.bs.parent = S.parent.p;
+        S.bs.idom = S.idom.p;
+        S.bs.aux = S.aux.p;
+        S.bs.lvl = S.lvl.p;
+        S.bs.xv = S.xv.p;
+        S.bs.xu = S.xu.p;
         return hipSuccess;
     }
 
@@ -783,9 +819,9 @@ struct Session {
         grid_l = cus * (int)env_size("IMIN_RULE_WG_PER_CU", 2);
         rule_lanes = (int)env_size("IMIN_RULE_LANES", 16);
         grid_w = cus;  // wide replay: one 1024-thread workgroup per CU
-        const int sizes[6] = {grid0, grid1, max_slots(cus), grid_r, grid_l, grid_w};
+        const int sizes[7] = {grid0, grid1, max_slots(cus), grid_r, grid_l, grid_w, cus};
         int32_t at = 0;
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 7; ++i) {
             dsz_off[i] = at;
             at += sizes[i];
         }
@@ -814,6 +850,7 @@ struct Session {
         IMIN_TRY(list1.alloc(next_n));
         IMIN_TRY(list2.alloc(next_n));
         IMIN_TRY(list3.alloc(next_n));
+        IMIN_TRY(list4.alloc(next_n));
         IMIN_TRY(list0.alloc(1));
         slot_cap0 = (size_t)imin::world_tier0_capacity();
         big_cap = hinted(gh ? &gh->big_per_world : nullptr, tile_cap, env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20));
@@ -832,7 +869,7 @@ struct Session {
         IMIN_TRY(hipMemsetAsync(dsz.p, 0, (size_t)dsz_n * sizeof(long long), s));
         start_tier = hinted_start_tier();
         if (start_tier == 2 || (gh && gh->tier2_seen.load(std::memory_order_relaxed))) {
-            const imin_status_t st = ensure_slots();
+            const imin_status_t st = ensure_t2();
             if (st != IMIN_OK) return st;
         }
         if (timed.on) {
@@ -1045,9 +1082,10 @@ struct Session {
         out.store_lab = (uint32_t*)store_lab.p;
         out.world_flags = label_rule ? world_flags.p : nullptr;
         out.dsz = dsz.p;
-        for (int i = 0; i < 6; ++i) out.dsz_off[i] = dsz_off[i];
+        for (int i = 0; i < 7; ++i) out.dsz_off[i] = dsz_off[i];
         out.next_cap =
-            (uint32_t)std::min<size_t>(std::min(std::min(list1.count, list2.count), list3.count), 0xFFFFFFFFu);
+            (uint32_t)std::min<size_t>(std::min(std::min(std::min(list1.count, list2.count), list3.count), list4.count),
+                                       0xFFFFFFFFu);
         out.scr_par = scr_par.p;
         out.store_par = store_par.p;
         out.xscr_v = xscr_v.p;
@@ -1068,22 +1106,53 @@ struct Session {
     }
 
     // Tiers first_tier..last_tier; the first reads first_list (count
-    // list_n[first_idx]) or, without a list, worlds [wb, wb+range).
+    // list_n[first_idx]) or, without a list, worlds [wb, wb+range).  Tier t
+    // hands the worlds it cannot hold to tier t+1's list (list1, list2,
+    // list4); tiers 2 and 3 run only with their slots allocated.
     imin_status_t launch_tiers(const imin::QueryDev& q, uint32_t wb, uint32_t range, const int32_t* first_list,
                                const imin::TileOut& out, int first_tier, int first_idx = 0, int last_tier = 2) {
+        if (last_tier > 2 && !tier3_possible()) last_tier = 2;
         for (int tier = first_tier; tier <= last_tier; ++tier) {
-            if (tier == 2 && !slots_ready()) return IMIN_ERR_INTERNAL;  // never launched without its slots
+            if ((tier == 2 && !t2.ready()) || (tier == 3 && !t3.ready())) return IMIN_ERR_INTERNAL;
             const bool first = (tier == first_tier);
-            const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : list2.p);
-            const int count_idx = first ? first_idx : tier;
-            int32_t* next_list = tier == 0 ? list1.p : list2.p;
+            const int32_t* in_list = first ? first_list : (tier == 1 ? list1.p : (tier == 2 ? list2.p : list4.p));
+            const int count_idx = first ? first_idx : (tier == 3 ? 4 : tier);
+            int32_t* next_list = tier == 0 ? list1.p : (tier == 1 ? list2.p : list4.p);
             const int timer_id = tier == 0 ? 0 : (tier == 1 ? 4 : 1);
             const imin::LaunchEvents ev = timed.take(timer_id);
             const hipError_t e = imin::launch_world_tier(tier, g, q, ctl.p, wb, first_list ? 0u : range, in_list,
-                                                         count_idx, next_list, out, bs, tier == 0 ? grid0 : grid1, s,
-                                                         ev);
+                                                         count_idx, next_list, out, tier == 3 ? t3.bs : t2.bs,
+                                                         tier == 0 ? grid0 : grid1, s, ev);
             timed.taken(timer_id, ev);
             IMIN_TRY(e);
+        }
+        return IMIN_OK;
+    }
+
+    // All tiers of a tile in a call with the block cache: the HBM tiers'
+    // slots are allocated (and their launches made) only once some world of
+    // the tile has been handed to them.
+    imin_status_t launch_tiers_checked(const imin::QueryDev& q, uint32_t wb, uint32_t nw, const imin::TileOut& out) {
+        imin_status_t st;
+        if (start_tier >= 2 && (st = ensure_t2()) != IMIN_OK) return st;
+        const bool three = tier3_possible();
+        const int ready_last = !t2.ready() ? 1 : ((!three || t3.ready()) ? 3 : 2);
+        if ((st = launch_tiers(q, wb, nw, nullptr, out, start_tier, 0, ready_last)) != IMIN_OK) return st;
+        bool ran2 = ready_last >= 2;
+        if (!t2.ready()) {
+            if ((st = read_ctl()) != IMIN_OK) return st;
+            if (hctl.p->list_n[2] > 0) {
+                if ((st = ensure_t2()) != IMIN_OK) return st;
+                if ((st = launch_tiers(q, wb, 0, list2.p, out, 2, 2, 2)) != IMIN_OK) return st;
+                ran2 = true;
+            }
+        }
+        if (three && ran2 && !t3.ready()) {
+            if ((st = read_ctl()) != IMIN_OK) return st;
+            if (hctl.p->list_n[4] > 0) {
+                if ((st = ensure_t3()) != IMIN_OK) return st;
+                if ((st = launch_tiers(q, wb, 0, list4.p, out, 3, 4, 3)) != IMIN_OK) return st;
+            }
         }
         return IMIN_OK;
     }
@@ -1156,21 +1225,7 @@ struct Session {
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
             out.keep_edges = keep ? 1 : 0;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            const uint32_t wb = (uint32_t)(w_begin + done);
-            imin_status_t st;
-            if (start_tier == 2 && (st = ensure_slots()) != IMIN_OK) return st;
-            if (slots_ready()) {
-                st = launch_tiers(q, wb, (uint32_t)nw, nullptr, out, start_tier);
-            } else {
-                // the LDS tiers first; the HBM tier (and its slots) only for
-                // the worlds they hand on
-                st = launch_tiers(q, wb, (uint32_t)nw, nullptr, out, start_tier, 0, 1);
-                if (st == IMIN_OK) st = read_ctl();
-                if (st == IMIN_OK && hctl.p->list_n[2] > 0) {
-                    st = ensure_slots();
-                    if (st == IMIN_OK) st = launch_tiers(q, wb, 0, list2.p, out, 2, 2, 2);
-                }
-            }
+            imin_status_t st = launch_tiers_checked(q, (uint32_t)(w_begin + done), (uint32_t)nw, out);
             if (st != IMIN_OK) return st;
             IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)nw, &ctl.p->tile_total, ctl.p, s));
             if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)nw, &ctl.p->xtile_total, ctl.p, s));
@@ -1178,6 +1233,7 @@ struct Session {
             if (st != IMIN_OK) return st;
             const uint32_t f = hctl.p->flags;
             if (hctl.p->list_n[2] > 0 || start_tier == 2) any_tier2 = true;
+            if (hctl.p->list_n[4] > 0) any_tier3 = true;
             if (hctl.p->list_n[2] > 0 && gh) gh->tier2_seen.store(true, std::memory_order_relaxed);
             if (gh && nw > 0) {
                 raise_hint(gh->tier1_share, ((uint64_t)hctl.p->list_n[1] << 10) / nw);
@@ -1457,8 +1513,13 @@ static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_
     // worlds are resident: per-world sizes for all theta, and the per-world
     // count lists when they fit (incremental rounds)
     IMIN_TRY(ss.world_size.alloc((size_t)theta));
+    // the resident store when earlier calls on the graph suggest its entries
+    // can be indexed with 32-bit positions (else plain rounds from the start)
     const char* inc_env = std::getenv("IMIN_INCREMENTAL");
-    if (!(inc_env && inc_env[0] == '0')) {
+    const unsigned long long est =
+        ((g->big_per_world.load() * (unsigned long long)theta) >> 10) +
+        (unsigned long long)theta * (unsigned long long)imin::world_tier0_capacity();
+    if (!(inc_env && inc_env[0] == '0') && est < (1ull << 31)) {
         st = ss.enable_store((uint64_t)theta);
         if (st != IMIN_OK) return st;
     }
@@ -1526,11 +1587,18 @@ static size_t plan_bytes(imin_graph_t g, const WsPlan& p, uint64_t theta, int32_
 
 static void fixed_plan(imin_graph_t g, WsPlan& p, int32_t n_seeds, uint64_t theta) {
     const size_t n = (size_t)g->g.n;
-    const size_t slot_bytes = (5 * n + (n + 3)) * 4 + 2 * (size_t)std::max<int64_t>(g->g.m, 1) * 4;
+    const size_t m1 = (size_t)std::max<int64_t>(g->g.m, 1);
+    const size_t lc2 = std::min<size_t>(n, (size_t)1 << 16), xc2 = std::min<size_t>(m1, (size_t)1 << 16);
+    const size_t base = n * 4 + (n + 31) / 32 * 4;
+    const size_t bytes2 = base + 5 * lc2 * 4 + 12 + 2 * xc2 * 4;
+    const size_t bytes3 = base + 5 * n * 4 + 12 + 2 * m1 * 4;
     const int cus = cu_count();
-    // HBM-tier slots: up to 1 GiB of them, one per resident workgroup at most
-    p.slots = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(((size_t)1 << 30) / slot_bytes, (size_t)cus * 4),
-                                                    (size_t)theta));
+    // tier-2 slots: up to 4 GiB once some world of the graph has needed that
+    // tier, else up to 256 MiB; one per resident workgroup at most
+    const bool big = g->tier2_seen.load(std::memory_order_relaxed) || g->tier2_share.load() > 0;
+    const size_t budget = big ? ((size_t)4 << 30) : ((size_t)256 << 20);
+    p.slots = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(budget / bytes2, (size_t)cus * 4), (size_t)theta));
+    p.slots3 = std::max<size_t>(1, std::min<size_t>(((size_t)1 << 30) / bytes3, 8));
     p.chunk_cap = chunk_bound(g->g, n_seeds);
     p.start_tier = 0;
     if (const char* t = std::getenv("IMIN_START_TIER")) p.start_tier = std::max(0, std::min(2, std::atoi(t)));

@@ -56,8 +56,8 @@ struct RoundCtl {
     uint32_t next[3];        // work counters of the LDS world tiers (chunks handed out)
     // worlds listed for a later kernel: [0] changed worlds (rounds without
     // replay), [1] from tier 0 or the replay workgroups, [2] from tier 1,
-    // [3] from the wide replay
-    uint32_t list_n[4];
+    // [3] from the wide replay, [4] from tier 2 (for tier 3)
+    uint32_t list_n[5];
     unsigned long long pair_count;
     long long total;         // sum of |R_w| over the worlds evaluated this round
     long long expect_total;  // T_r - gain_r from the previous selection (-1: none)
@@ -90,13 +90,16 @@ enum : int {
 // Scratch of the workgroup-per-world path, one slot per resident workgroup.
 struct BigSlots {
     int32_t n_slots;
+    int32_t lid_cap;   // nodes a world may reach (nodes/parent/idom/aux entries; lvl has lid_cap + 3)
     int64_t xcap;      // extra-edge capacity per slot
-    int32_t* lid_of;   // [slots][n]   node -> local id, -1 = absent
-    int32_t* nodes;    // [slots][n]
-    int32_t* parent;   // [slots][n]
-    int32_t* idom;     // [slots][n]
-    int32_t* aux;      // [slots][n]
-    int32_t* lvl;      // [slots][n+3]
+    int32_t vis_words; // (n + 31) / 32
+    uint32_t* vis;     // [slots][vis_words] visited bitsets (zero between worlds; unused when they fit LDS)
+    int32_t* lid_of;   // [slots][n]   node -> local id, valid while its visited bit is set
+    int32_t* nodes;    // [slots][lid_cap]
+    int32_t* parent;   // [slots][lid_cap]
+    int32_t* idom;     // [slots][lid_cap]
+    int32_t* aux;      // [slots][lid_cap]
+    int32_t* lvl;      // [slots][lid_cap+3]
     int32_t* xv;       // [slots][xcap]
     int32_t* xu;       // [slots][xcap]
 };
@@ -195,7 +198,7 @@ struct TileOut {
     // Incremental rounds: nodes each workgroup's worlds lost, one slot per
     // (kernel, workgroup); summed and cleared by the selection.
     long long* dsz;
-    int32_t dsz_off[6];   // slot ranges of tier 0, 1, 2, replay, label rule, wide replay
+    int32_t dsz_off[7];   // slot ranges of tier 0, 1, 2, replay, label rule, wide replay, tier 3
 };
 
 // A compaction job: per-item ranges of up to four 32-bit fields are packed
@@ -277,6 +280,8 @@ struct LaunchEvents {
     hipEvent_t stop = nullptr;
 };
 
+// Tiers 0 and 1 (LDS), 2 (HBM slots with bounded per-world arrays) and 3
+// (HBM slots with arrays for any world); bs gives the slots of tier 2 or 3.
 hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin,
                              uint32_t range_count, const int32_t* in_list, int count_idx, int32_t* next_list,
                              const TileOut& out, const BigSlots& bs, int grid, hipStream_t s,

@@ -152,7 +152,7 @@ __global__ void k_ctl_reset_round(RoundCtl* ctl) {
 __global__ void k_ctl_reset_tile(RoundCtl* ctl) {
     if (ctl->stop) return;
     for (int i = 0; i < 3; ++i) ctl->next[i] = 0;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < 5; ++i) {
         ctl->list_n[i] = 0;
     }
     ctl->pair_count = 0;
@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256) void k_select_partial(RoundCtl* ctl, int32_t n
             // for the combining launch: the round, and the next round's counters cleared
             ctl->round_snap = ctl->round;
             for (int i = 0; i < 3; ++i) ctl->next[i] = 0;
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < 5; ++i) {
                 ctl->list_n[i] = 0;
             }
             ctl->pair_count = 0;

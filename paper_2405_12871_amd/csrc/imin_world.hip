@@ -172,12 +172,21 @@ struct LdsStore {
     __device__ int32_t* hi_ptr(int lid) { return &keys[CAPNS + lid - ns]; }
     template <int NT>
     __device__ void reset(int /*count*/) { clear<NT>(); }
+    template <int NT>
+    __device__ void stage(int) {}  // everything is in LDS already
 };
 
 // ------------------------------------------------------------ HBM store
 // Per-slot arrays sized for the whole graph, so a world never outgrows it.
+// A node is claimed in a visited bitset (in LDS when the graph's bitset
+// fits, else the slot's own words in HBM); its claimer writes lid_of[v],
+// which is read only while v's bit is set and so is never reset.  For the
+// dominator phase the extra edges are staged in LDS when they fit.
 struct HbmStore {
-    int32_t* lid_of;  // node -> local id, -1 = absent
+    uint32_t* vis;     // visited bitset, (n + 31) / 32 words
+    int32_t vis_words;
+    bool vis_lds;      // vis is in LDS (cleared whole after a world)
+    int32_t* lid_of;   // node -> local id, valid while the node's bit is set
     int32_t* nodes;
     int32_t* parent_;
     int32_t* idom_;
@@ -185,6 +194,11 @@ struct HbmStore {
     int32_t* lvl;
     int32_t* xv;
     int32_t* xu_;
+    int32_t* xv_s;     // LDS copies of the extra edges (xs_cap of them)
+    int32_t* xu_s;
+    int32_t xs_cap;
+    bool staged;       // the extra edges are read from and written to the LDS copies
+    int32_t lid_cap;   // nodes a world may reach in this slot
     int32_t cap_lv_;
     int64_t cap_x_;
 
@@ -195,6 +209,7 @@ struct HbmStore {
     __device__ void init_seeds(const QueryDev& q) {
         for (int i = threadIdx.x; i < q.n_seeds; i += NT) {
             const int32_t v = q.seeds[i];
+            atomicOr(&vis[(uint32_t)v >> 5], 1u << ((uint32_t)v & 31u));
             lid_of[v] = i;
             nodes[i] = v;
             parent_[i] = -1;
@@ -202,12 +217,16 @@ struct HbmStore {
         }
     }
     __device__ int claim(int32_t v, int* counter) {
-        if (atomicCAS(&lid_of[v], -1, -2) != -1) return -1;
+        const uint32_t bit = 1u << ((uint32_t)v & 31u);
+        if (atomicOr(&vis[(uint32_t)v >> 5], bit) & bit) return -1;
         const int lid = atomicAdd(counter, 1);
+        if (lid >= lid_cap) return -2;  // out of room: the world goes to the next tier
         lid_of[v] = lid;
         return lid;
     }
-    __device__ int lookup(int32_t v) const { return lid_of[v]; }
+    __device__ int lookup(int32_t v) const {
+        return ((vis[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u) ? lid_of[v] : -1;
+    }
     __device__ int32_t node(int lid) const { return nodes[lid]; }
     __device__ void set_node(int lid, int32_t v) { nodes[lid] = v; }
     __device__ int get_parent(int lid) const { return parent_[lid]; }
@@ -215,19 +234,41 @@ struct HbmStore {
     __device__ int get_idom(int lid) const { return idom_[lid]; }
     __device__ void set_idom(int lid, int p) { idom_[lid] = p; }
     __device__ int32_t* aux_ptr(int lid) { return &aux[lid]; }
-    __device__ int get_xu(int64_t x) const { return xu_[x]; }
-    __device__ void set_xu(int64_t x, int u) { xu_[x] = u; }
-    __device__ int get_xv(int64_t x) const { return xv[x]; }
-    __device__ void set_xv(int64_t x, int v) { xv[x] = v; }
-    __device__ void resolve_xv(int64_t x) { xv[x] = lookup(xv[x]); }
+    __device__ int get_xu(int64_t x) const { return staged ? xu_s[x] : xu_[x]; }
+    __device__ void set_xu(int64_t x, int u) { xu_[x] = u; }  // written while sampling (not staged)
+    __device__ int get_xv(int64_t x) const { return staged ? xv_s[x] : xv[x]; }
+    __device__ void set_xv(int64_t x, int v) {
+        if (staged) xv_s[x] = v;
+        else xv[x] = v;
+    }
+    __device__ void resolve_xv(int64_t x) { set_xv(x, lookup(get_xv(x))); }
     __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
+    // the extra edges into LDS when they fit (every thread takes the same
+    // decision); the caller synchronises before they are read
+    template <int NT>
+    __device__ void stage(int nx) {
+        staged = nx <= xs_cap;
+        if (!staged) return;
+        for (int x = threadIdx.x; x < nx; x += NT) {
+            xv_s[x] = xv[x];
+            xu_s[x] = xu_[x];
+        }
+    }
     static constexpr bool kLabels = false;  // worlds of this tier carry no labels
     __device__ int32_t* cur_ptr(int) { return nullptr; }
     __device__ void set_tin(int, int) {}
     __device__ int get_tin(int) const { return 0; }
+    // clear the bitset for the next world: whole when it is in LDS or the
+    // world ran out of room (claimed nodes past lid_cap are not listed),
+    // else the words of the world's reached nodes
     template <int NT>
-    __device__ void reset(int count) {
-        for (int i = threadIdx.x; i < count; i += NT) lid_of[nodes[i]] = -1;
+    __device__ void reset(int count, bool whole) {
+        if (vis_lds || whole) {
+            for (int i = threadIdx.x; i < vis_words; i += NT) vis[i] = 0u;
+        } else {
+            for (int i = threadIdx.x; i < count; i += NT) vis[(uint32_t)nodes[i] >> 5] = 0u;
+        }
+        staged = false;
     }
 };
 
@@ -444,6 +485,8 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
     const int nx = sh.n_extra;
 
     // ---- dominators
+    st.template stage<NT>(nx);
+    __syncthreads();
     for (int x = t; x < nx; x += NT) st.resolve_xv(x);
     for (int i = ns + t; i < R; i += NT) {
         const int p = st.get_parent(i);
@@ -501,7 +544,10 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
             }
             if (t == 0) sh.changed = 0;
             __syncthreads();
+            const unsigned long long xl = sh.xlevels;
             for (int L = 1; L < nlevels; ++L) {
+                // a level without extra heads keeps idom = BFS parent
+                if (L < 63 && !((xl >> L) & 1ull)) continue;  // uniform
                 const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
                 for (int x = t; x < nx; x += NT) {
                     const int v = st.get_xv(x);
@@ -869,46 +915,76 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q_in, Rou
     }
 }
 
-// Tier 2: per-world arrays in HBM, one slot per resident workgroup.
+// Tiers 2 and 3: per-world arrays in HBM, one slot per resident workgroup;
+// the visited bitset in LDS (VIS_LDS) or in the slot, and up to kStageX
+// extra edges staged in LDS, both in dynamic LDS.  Tier 2's slots hold
+// worlds of up to lid_cap nodes and xcap extra edges and hand larger ones
+// on to tier 3, whose few slots are sized for any world of the graph.
+constexpr int kStageX = 2048;
+constexpr int kVisLdsMaxWords = 4096;  // graphs of up to 2^17 nodes keep their bitset in LDS
+
+template <bool VIS_LDS, int TIER>
 __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q_in, RoundCtl* ctl, uint32_t w_begin,
                                                         uint32_t range_count, const int32_t* in_list,
-                                                        int count_idx, TileOut out, BigSlots bs) {
+                                                        int count_idx, int32_t* next_list, TileOut out,
+                                                        BigSlots bs) {
     __shared__ WorldShared<kTier2NT> sh;
+    extern __shared__ int32_t t2_lds[];  // [2 * kStageX] staged edges, then the bitset (VIS_LDS)
     const int t = threadIdx.x;
     const size_t slot = blockIdx.x;
     const size_t n = (size_t)g.n;
+    const size_t lc = (size_t)bs.lid_cap;
     HbmStore st;
+    st.vis_words = bs.vis_words;
+    st.vis_lds = VIS_LDS;
+    st.vis = VIS_LDS ? reinterpret_cast<uint32_t*>(t2_lds + 2 * kStageX) : bs.vis + slot * (size_t)bs.vis_words;
     st.lid_of = bs.lid_of + slot * n;
-    st.nodes = bs.nodes + slot * n;
-    st.parent_ = bs.parent + slot * n;
-    st.idom_ = bs.idom + slot * n;
-    st.aux = bs.aux + slot * n;
-    st.lvl = bs.lvl + slot * (n + 3);
+    st.nodes = bs.nodes + slot * lc;
+    st.parent_ = bs.parent + slot * lc;
+    st.idom_ = bs.idom + slot * lc;
+    st.aux = bs.aux + slot * lc;
+    st.lvl = bs.lvl + slot * (lc + 3);
     st.xv = bs.xv + slot * (size_t)bs.xcap;
     st.xu_ = bs.xu + slot * (size_t)bs.xcap;
-    st.cap_lv_ = g.n + 1;
+    st.xv_s = t2_lds;
+    st.xu_s = t2_lds + kStageX;
+    st.xs_cap = kStageX;
+    st.staged = false;
+    st.lid_cap = bs.lid_cap;
+    st.cap_lv_ = bs.lid_cap + 1;
     st.cap_x_ = bs.xcap;
     if (ctl->stop) return;
     const QueryDev q = query_at_run(q_in, ctl);
     const uint32_t n_items = in_list ? min(ctl->list_n[count_idx], count_idx ? out.next_cap : out.list_cap)
                                      : range_count;
     if (blockIdx.x >= n_items) return;  // no world for this workgroup
+    if (VIS_LDS)
+        for (int i = t; i < bs.vis_words; i += kTier2NT) st.vis[i] = 0u;
     if (t == 0) {
         sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
         sh.acc_reached = sh.acc_live = 0;
         sh.acc_dsize = 0;
     }
+    __syncthreads();
     for (uint32_t k = blockIdx.x; k < n_items; k += gridDim.x) {
         const uint32_t wi = in_list ? (uint32_t)in_list[k] : k;
         const bool ok = evaluate_world<kTier2NT, 2>(g, q, ctl, w_begin + wi, wi, out, st, sh);
-        if (!ok && t == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
+        if (!ok && t == 0) {
+            if (TIER == 2) {
+                const uint32_t pos = atomicAdd(&ctl->list_n[4], 1u);
+                if (pos < out.next_cap) next_list[pos] = (int32_t)wi;
+                else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            } else {
+                atomicOr(&ctl->flags, (uint32_t)kFlagBigCapacity);
+            }
+        }
         __syncthreads();
-        st.reset<kTier2NT>(sh.count < g.n ? sh.count : g.n);
+        st.reset<kTier2NT>(min(sh.count, bs.lid_cap), !ok);
         __syncthreads();
     }
     if (t == 0) {
         add_work(out, 2, sh.acc_worlds, sh.acc_edges, sh.acc_bytes, sh.acc_reached, sh.acc_live);
-        if (sh.acc_dsize) out.dsz[out.dsz_off[2] + blockIdx.x] = sh.acc_dsize;
+        if (sh.acc_dsize) out.dsz[out.dsz_off[TIER == 2 ? 2 : 6] + blockIdx.x] = sh.acc_dsize;
     }
 }
 
@@ -1009,6 +1085,18 @@ int world_tier_blocks_per_cu(int tier) {
     return b < 1 ? 1 : b;
 }
 
+// Launch kernel k on grid x block threads with `lds` bytes of dynamic LDS,
+// with the kernel's own start and stop timestamps in ev when given.
+template <class... P, class... A>
+hipError_t launch_k_lds(void (*k)(P...), unsigned grid, unsigned block, size_t lds, hipStream_t s,
+                        const LaunchEvents& ev, A... a) {
+    if (ev.start)
+        hipExtLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, ev.start, ev.stop, 0, a...);
+    else
+        hipLaunchKernelGGL(k, dim3(grid), dim3(block), lds, s, a...);
+    return hipGetLastError();
+}
+
 // Launch kernel k on grid x block threads, with the kernel's own start and
 // stop timestamps in ev when given.
 template <class... P, class... A>
@@ -1030,8 +1118,20 @@ hipError_t launch_world_tier(int tier, const GraphDev& g, const QueryDev& q, Rou
     if (tier == 1)
         return launch_k(k_world_lds<kTier1NT, Tier1Store, 1>, (unsigned)grid, kTier1NT, s, ev, g, q, ctl, w_begin,
                         range_count, in_list, count_idx, next_list, out);
-    return launch_k(k_world_hbm, (unsigned)bs.n_slots, kTier2NT, s, ev, g, q, ctl, w_begin, range_count, in_list,
-                    count_idx, out, bs);
+    const bool vis_lds = bs.vis_words <= kVisLdsMaxWords;
+    const size_t lds = (size_t)2 * kStageX * sizeof(int32_t) + (vis_lds ? (size_t)bs.vis_words * sizeof(uint32_t) : 0);
+    if (tier == 2) {
+        if (vis_lds)
+            return launch_k_lds(k_world_hbm<true, 2>, (unsigned)bs.n_slots, kTier2NT, lds, s, ev, g, q, ctl, w_begin,
+                                range_count, in_list, count_idx, next_list, out, bs);
+        return launch_k_lds(k_world_hbm<false, 2>, (unsigned)bs.n_slots, kTier2NT, lds, s, ev, g, q, ctl, w_begin,
+                            range_count, in_list, count_idx, next_list, out, bs);
+    }
+    if (vis_lds)
+        return launch_k_lds(k_world_hbm<true, 3>, (unsigned)bs.n_slots, kTier2NT, lds, s, ev, g, q, ctl, w_begin,
+                            range_count, in_list, count_idx, next_list, out, bs);
+    return launch_k_lds(k_world_hbm<false, 3>, (unsigned)bs.n_slots, kTier2NT, lds, s, ev, g, q, ctl, w_begin,
+                        range_count, in_list, count_idx, next_list, out, bs);
 }
 
 // ----------------------------------------------- incremental-round index
@@ -1568,6 +1668,8 @@ struct ReplayStore {
     __device__ int get_tin(int lid) const { return (int)(uint16_t)parent[lid - ns]; }
     __device__ int32_t* lo_ptr(int lid) { return &cur[lid - ns]; }
     __device__ int32_t* hi_ptr(int lid) { return &hi[lid - ns]; }
+    template <int NT>
+    __device__ void stage(int) {}  // everything is in LDS already
 };
 
 // levels: at most one per entry plus the seeds' and a closing empty one

@@ -159,15 +159,38 @@ def test_every_start_tier_gives_the_same_integers(B, oracle_mod, monkeypatch, ti
     _assert_same(got, want)
 
 
-@pytest.mark.parametrize("shape", ["path", "star", "grid", "star1000", "path100"])
+@pytest.mark.parametrize("shape", ["path", "star", "grid", "star1000", "path100", "star70k", "dense", "mixed70k"])
 def test_evaluate_deterministic_shapes(B, oracle_mod, shape):
     """p = 1 shapes that outgrow the LDS tiers: 1500- and 100-level paths,
-    3000- and 1000-leaf stars, a 50x50 grid (many equal-level predecessors)."""
+    3000- and 1000-leaf stars, a 50x50 grid (many equal-level predecessors).
+    Beyond the bounded HBM-tier slots (2^16 nodes, 2^16 extra edges): a
+    70,000-leaf star, a 1,200-node graph with 100,000 live edges, and a
+    graph whose worlds mix both sizes (seed 0 reaches a 70,000-leaf star
+    through an edge of p = 0.5)."""
+    if shape == "dense":
+        rng = np.random.default_rng(9)
+        n = 1200
+        pairs = np.unique(rng.integers(0, n, size=(130_000, 2)), axis=0)
+        pairs = pairs[pairs[:, 0] != pairs[:, 1]][:100_000]
+        g = synth.from_edges(n, pairs[:, 0], pairs[:, 1], np.ones(len(pairs), np.float32), name=shape)
+        got, want = _eval_both(B, oracle_mod, g, np.array([0], np.int32), 0, 3, 1)
+        _assert_same(got, want)
+        return
+    if shape == "mixed70k":
+        n = 70_002
+        src = np.concatenate([[0], np.ones(n - 2, int)])
+        dst = np.arange(1, n)
+        p = np.concatenate([[0.5], np.ones(n - 2)]).astype(np.float32)
+        g = synth.from_edges(n, src, dst, p, name=shape)
+        got, want = _eval_both(B, oracle_mod, g, np.array([0], np.int32), 0, 40, 5)
+        assert 0 < int((got[2] > 2).sum()) < 40  # both small and huge worlds
+        _assert_same(got, want)
+        return
     if shape in ("path", "path100"):
         n = 1500 if shape == "path" else 100
         src, dst = np.arange(n - 1), np.arange(1, n)
-    elif shape in ("star", "star1000"):
-        n = 3001 if shape == "star" else 1001
+    elif shape in ("star", "star1000", "star70k"):
+        n = {"star": 3001, "star1000": 1001, "star70k": 70_001}[shape]
         src, dst = np.zeros(n - 1, int), np.arange(1, n)
     else:
         s = 50
@@ -655,3 +678,24 @@ def test_medium_workload_full_solve(B, oracle_mod):
     np.testing.assert_array_equal(T[1:res.n_selected + 1], T[:res.n_selected] - res.gains[:res.n_selected])
     rounds = [int(x) for x in os.environ.get("IMIN_TEST_MEDIUM_ROUNDS", "0,1,99,100").split(",")]
     _check_rounds_against_oracle(oracle_mod, g, seeds, theta, 2024, res, rounds)
+
+
+def test_solve_worlds_beyond_the_hbm_tier_bounds(B, oracle_mod):
+    """Worlds of 70,000 nodes (beyond the bounded HBM-tier slots) beside
+    one-node worlds, in a full solve: with the block cache and with a
+    workspace, every round equals the oracle's."""
+    h = 35_000  # leaves per hub: a world reaching both hubs has 70,003 nodes
+    n = 3 + 2 * h
+    src = np.concatenate([[0, 0, 1], np.full(h, 1), np.full(h, 2)])
+    dst = np.concatenate([[1, 2, 2], np.arange(3, 3 + h), np.arange(3 + h, n)])
+    p = np.concatenate([[0.5, 0.5, 1.0], np.full(2 * h, 0.95)]).astype(np.float32)
+    g = synth.from_edges(n, src, dst, p, name="hub70k")
+    seeds = np.array([0], np.int32)
+    want = oracle_mod.Query(g, seeds).solve(4, 30, 6)
+    G = B.Graph.from_synth(g)
+    for label, res in (("cache", B.solve(G, seeds, 4, 30, 6)), ("workspace", B.solve_ws(G, seeds, 4, 30, 6))):
+        _log(f"hub70k solve ({label})")
+        assert res.n_selected == want["n_selected"]
+        np.testing.assert_array_equal(res.blockers, want["blockers"])
+        np.testing.assert_array_equal(res.gains, want["gains"])
+        np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
