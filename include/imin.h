@@ -180,11 +180,14 @@ imin_status_t imin_solve_static(imin_graph_t g, const int32_t* seeds, int32_t n_
                                 int64_t* spread_totals, int32_t* n_selected, int32_t* device_status);
 
 /*
- * One query of imin_solve_many: the arguments of imin_solve (device arrays,
- * the same meaning and sizes) and, written by the call, the query's own
- * status and device flags (imin_last_device_flags of its solve).
+ * One query of imin_solve_many and of the serving loop: its graph (NULL: the
+ * batch's or server's own graph; any graph on the same device), the
+ * arguments of imin_solve (device arrays, the same meaning and sizes) and,
+ * written by the call, the query's status (an imin_status_t, from the
+ * device_status of its solve) and device flags.
  */
 typedef struct imin_query {
+    imin_graph_t graph;
     const int32_t* seeds;
     int32_t n_seeds;
     int32_t k;
@@ -199,55 +202,64 @@ typedef struct imin_query {
 } imin_query_t;
 
 /*
- * imin_solve_many -- several independent greedy selections on one graph
- * (each as imin_solve), run side by side: one host thread per stream (at
- * most n_queries), each taking the next unstarted query and solving it on
- * its own stream.  Queries start in decreasing order of theta * (k + 1).  An incremental round of one query is a chain of short
- * dependent launches that leaves most of the GPU idle, so queries on
- * different streams overlap.  Every query's worlds are keyed by its own
- * rng_seed, so each result is identical to the query's imin_solve alone.
- *
- *   queries    host array of n_queries entries (n_queries >= 0); each
- *              entry's status and device_flags are written
- *   streams    host array of n_streams hipStream_t (as void*), n_streams >= 1;
- *              the streams must be distinct, on the graph's device
+ * Batches and serving (many queries of Section 2.1's problem on resident
+ * graphs).  Both run every query as an enqueued imin_solve whose workspace is
+ * a range of one pool of device memory, allocated once when the batch or
+ * server starts (hbm_budget bytes; 0 = half the device's free memory, at
+ * most 96 GiB).  A query is admitted when the workspace its layout needs
+ * (imin_solve_workspace_size) fits a free range of the pool: queries wait
+ * in arrival order, and while the first waiting one does not fit a few
+ * later ones that do may start.  Each admitted query goes to the stream
+ * with the fewest queries in flight, so queries overlap on the device; its
+ * workspace returns to the pool when its last kernel has run.  A query
+ * whose worlds need more scratch than its workspace held
+ * (IMIN_ERR_WORKSPACE found on the device) is admitted again with the size
+ * its graph now records.  A query larger than the whole pool fails with
+ * IMIN_ERR_WORKSPACE.  Every query's worlds are keyed by its own rng_seed,
+ * so each result is identical to the query solved alone.
  *
  * The device arrays of a query must be ready on the host's side of every
- * stream (e.g. the device synchronised after they were written).  Returns
- * IMIN_OK when every query succeeded, else the status of the first failing
- * query (by index); IMIN_ERR_INVALID for bad arguments (no query is run).
+ * stream (e.g. the device synchronised after they were written).  streams:
+ * host array of n_streams distinct hipStream_t (as void*) on the graphs'
+ * device, n_streams >= 1.
+ *
+ * imin_solve_many  solves queries[0 .. n_queries) (largest theta * (k + 1)
+ *                  first) and returns when all have finished: IMIN_OK when
+ *                  every query succeeded, else the status of the first
+ *                  failing one (by index); IMIN_ERR_INVALID for bad
+ *                  arguments (no query run), IMIN_ERR_NOMEM when the pool
+ *                  cannot be allocated.
  */
 imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_queries, void* const* streams,
-                              int32_t n_streams);
+                              int32_t n_streams, size_t hbm_budget);
 
 /*
- * A serving loop: a pool of worker threads, one per stream, that solve the
- * queries submitted to it (each as imin_solve) as they arrive, at most one
- * per stream at a time; the others wait in arrival order.
+ * A serving loop: one dispatcher thread admits submitted queries as the
+ * pool and the streams allow (see above) and hands back finished ones.
  *
- * imin_server_create   streams: host array of n_streams distinct
- *                      hipStream_t (as void*) on the graph's device,
- *                      n_streams >= 1; the graph must outlive the server.
+ * imin_server_create   g is the default graph of queries with graph NULL;
+ *                      the graphs must outlive the server.
  * imin_server_submit   queues one query and returns at once.  The query
  *                      entry and its device arrays must stay valid, and its
  *                      inputs ready on every stream, until imin_server_next
  *                      has returned it.  IMIN_ERR_INVALID after
  *                      imin_server_destroy has begun.
  * imin_server_next     blocks until a submitted query has finished and
- *                      returns it in *done (its status and device_flags
+ *                      returns it in *done (status and device_flags
  *                      written); every query is returned once, in the order
  *                      they finish.  IMIN_ERR_INVALID when no submitted
  *                      query is outstanding.
- * imin_server_destroy  lets the workers finish every queued query, joins
- *                      them and frees the server (queries not yet returned
- *                      by imin_server_next are finished but not returned).
+ * imin_server_destroy  lets every queued query finish, joins the dispatcher
+ *                      and frees the server and its pool (queries not yet
+ *                      returned by imin_server_next are finished but not
+ *                      returned).
  *
  * One thread may submit while another waits in imin_server_next;
  * imin_server_destroy must not overlap any other call on the same server.
- * IMIN_ERR_NOMEM when host memory for the server or its queues runs out.
  */
 typedef struct imin_server* imin_server_t;
-imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, imin_server_t* out);
+imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, size_t hbm_budget,
+                                 imin_server_t* out);
 imin_status_t imin_server_submit(imin_server_t s, imin_query_t* query);
 imin_status_t imin_server_next(imin_server_t s, imin_query_t** done);
 imin_status_t imin_server_destroy(imin_server_t s);

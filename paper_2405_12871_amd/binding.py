@@ -26,8 +26,9 @@ _lib = None
 
 
 class Query(ctypes.Structure):
-    """One entry of imin_solve_many (imin_query_t)."""
-    _fields_ = [("seeds", ctypes.c_void_p), ("n_seeds", ctypes.c_int32), ("k", ctypes.c_int32),
+    """One entry of imin_solve_many and of the server (imin_query_t)."""
+    _fields_ = [("graph", ctypes.c_void_p), ("seeds", ctypes.c_void_p), ("n_seeds", ctypes.c_int32),
+                ("k", ctypes.c_int32),
                 ("theta", ctypes.c_int64), ("rng_seed", ctypes.c_uint64), ("blockers", ctypes.c_void_p),
                 ("gains", ctypes.c_void_p), ("spread_totals", ctypes.c_void_p), ("n_selected", ctypes.c_void_p),
                 ("status", ctypes.c_int32), ("device_flags", ctypes.c_uint32)]
@@ -70,9 +71,9 @@ def load():
     lib.imin_solve_workspace_size.restype = st
     lib.imin_solve_static.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P, P]
     lib.imin_solve_static.restype = st
-    lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32]
+    lib.imin_solve_many.argtypes = [P, ctypes.POINTER(Query), i32, ctypes.POINTER(P), i32, ctypes.c_size_t]
     lib.imin_solve_many.restype = st
-    lib.imin_server_create.argtypes = [P, ctypes.POINTER(P), i32, ctypes.POINTER(P)]
+    lib.imin_server_create.argtypes = [P, ctypes.POINTER(P), i32, ctypes.c_size_t, ctypes.POINTER(P)]
     lib.imin_server_create.restype = st
     lib.imin_server_submit.argtypes = [P, ctypes.POINTER(Query)]
     lib.imin_server_submit.restype = st
@@ -306,13 +307,35 @@ def solve(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> SolveResult
                        spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=int(theta))
 
 
-def solve_many(graph: Graph, queries, n_streams: int = 4, raise_on_error: bool = True):
-    """Several selections on one graph side by side (imin_solve_many).
+def _query_entry(graph, default, seeds, k, theta, rng_seed):
+    """A Query entry with its device tensors (kept alive by the caller)."""
+    torch = _torch()
+    g = graph if graph is not None else default
+    s = _dev(seeds, torch.int32, g.device)
+    out = _solve_outputs(k, g.device)
+    q = Query(g.handle.value if graph is not None else None, s.data_ptr(), int(s.numel()), int(k), int(theta),
+              int(rng_seed) & 0xFFFFFFFFFFFFFFFF, out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+              out[3].data_ptr(), 0, 0)
+    return q, (s, out)
 
-    ``queries`` is a sequence of (seeds, k, theta, rng_seed).  Returns one
+
+def _split_query(item):
+    """(graph or None, seeds, k, theta, rng_seed) from a 4- or 5-tuple."""
+    if len(item) == 5:
+        return item
+    return (None,) + tuple(item)
+
+
+def solve_many(graph: Graph, queries, n_streams: int = 4, raise_on_error: bool = True, hbm_budget: int = 0):
+    """Many selections side by side (imin_solve_many).
+
+    ``queries`` is a sequence of (seeds, k, theta, rng_seed) on ``graph`` or
+    (graph, seeds, k, theta, rng_seed) on another resident graph.  Returns one
     SolveResult per query, each equal to solve() of that query alone.  A
     failing query raises IminError (naming the query) or, with
     ``raise_on_error=False``, takes an IminError in its place in the list.
+    ``hbm_budget`` is the byte size of the workspace pool (0: the library's
+    default).
     """
     torch = _torch()
     lib = load()
@@ -320,33 +343,21 @@ def solve_many(graph: Graph, queries, n_streams: int = 4, raise_on_error: bool =
     n = len(queries)
     arr = (Query * max(n, 1))()
     keep = []
-    for i, (seeds, k, theta, rng_seed) in enumerate(queries):
-        s = _dev(seeds, torch.int32, dev)
-        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
-               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
-               torch.zeros(k + 1, dtype=torch.int64, device=dev),
-               torch.zeros(1, dtype=torch.int32, device=dev))
-        keep.append((s, out, int(theta)))
-        arr[i] = Query(s.data_ptr(), int(s.numel()), int(k), int(theta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF,
-                       out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), 0, 0)
-    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, min(int(n_streams), n)))]
+    for i, item in enumerate(queries):
+        gq, seeds, k, theta, rng_seed = _split_query(item)
+        arr[i], tensors = _query_entry(gq, graph, seeds, k, theta, rng_seed)
+        keep.append((tensors, int(theta)))
+    streams = [torch.cuda.Stream(device=dev) for _ in range(max(1, min(int(n_streams), max(n, 1))))]
     handles = (ctypes.c_void_p * len(streams))(*[st.cuda_stream for st in streams])
     torch.cuda.synchronize(dev)  # inputs and zeroed outputs are ready for every stream
     with torch.cuda.device(dev):
-        lib.imin_solve_many(graph.handle, arr, n, handles, len(streams))
+        lib.imin_solve_many(graph.handle, arr, n, handles, len(streams), int(hbm_budget))
     results = []
-    for i, (s, (b, g, t, ns), theta) in enumerate(keep):
-        status = int(arr[i].status)
-        if status != IMIN_OK:
-            err = IminError(status, f"query {i}: " + lib.imin_status_string(status).decode(),
-                            int(arr[i].device_flags))
-            if raise_on_error:
-                raise err
-            results.append(err)
-            continue
-        r = int(ns.cpu()[0])
-        results.append(SolveResult(blockers=b.cpu().numpy()[:r].copy(), gains=g.cpu().numpy()[:r].copy(),
-                                   spread_totals=t.cpu().numpy()[:r + 1].copy(), n_selected=r, theta=theta))
+    for i, ((s, out), theta) in enumerate(keep):
+        r = _query_result(lib, arr[i], out, theta, f"query {i}")
+        if isinstance(r, IminError) and raise_on_error:
+            raise r
+        results.append(r)
     return results
 
 
@@ -362,10 +373,11 @@ def _query_result(lib, q: Query, out, theta: int, label: str):
 
 
 class Server:
-    """Queries solved as they arrive by a pool of worker threads, one per
-    stream (imin_server_create / submit / next / destroy)."""
+    """Queries solved as they arrive, admitted by workspace size into a pool
+    of device memory and run side by side on several streams
+    (imin_server_create / submit / next / destroy)."""
 
-    def __init__(self, graph: Graph, n_streams: int = 4):
+    def __init__(self, graph: Graph, n_streams: int = 4, hbm_budget: int = 0):
         torch = _torch()
         lib = load()
         self.graph = graph
@@ -373,7 +385,8 @@ class Server:
         handles = (ctypes.c_void_p * len(self._streams))(*[st.cuda_stream for st in self._streams])
         h = ctypes.c_void_p()
         with torch.cuda.device(graph.device):
-            _check(lib.imin_server_create(graph.handle, handles, len(self._streams), ctypes.byref(h)))
+            _check(lib.imin_server_create(graph.handle, handles, len(self._streams), int(hbm_budget),
+                                          ctypes.byref(h)))
         self._h = h
         # address of a query entry -> (ticket, entry, its tensors, theta); an
         # address is unique among outstanding queries, tickets for ever
@@ -381,24 +394,18 @@ class Server:
         self._tickets = 0
         self._lock = threading.Lock()
 
-    def submit(self, seeds, k: int, theta: int, rng_seed: int) -> int:
-        """Queue one query; returns its ticket (a serial number) at once."""
+    def submit(self, seeds, k: int, theta: int, rng_seed: int, graph: "Graph" = None) -> int:
+        """Queue one query (on ``graph``, default the server's); returns its
+        ticket (a serial number) at once."""
         torch = _torch()
         lib = load()
-        dev = self.graph.device
-        s = _dev(seeds, torch.int32, dev)
-        out = (torch.zeros(max(k, 1), dtype=torch.int32, device=dev),
-               torch.zeros(max(k, 1), dtype=torch.int64, device=dev),
-               torch.zeros(k + 1, dtype=torch.int64, device=dev),
-               torch.zeros(1, dtype=torch.int32, device=dev))
-        q = Query(s.data_ptr(), int(s.numel()), int(k), int(theta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF,
-                  out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), 0, 0)
-        torch.cuda.current_stream(dev).synchronize()  # inputs and zeroed outputs ready on every stream
+        q, tensors = _query_entry(graph, self.graph, seeds, k, theta, rng_seed)
+        torch.cuda.current_stream(self.graph.device).synchronize()  # inputs and zeroed outputs ready
         addr = ctypes.addressof(q)
         with self._lock:
             ticket = self._tickets
             self._tickets += 1
-            self._pending[addr] = (ticket, q, (s, out), int(theta))
+            self._pending[addr] = (ticket, q, tensors, int(theta))
         status = lib.imin_server_submit(self._h, ctypes.byref(q))
         if status != IMIN_OK:
             with self._lock:

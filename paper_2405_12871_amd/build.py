@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libimin.so")
-SOURCES = ["imin_world.hip", "imin_kernels.hip", "imin_probe.hip", "imin_static.hip", "imin_api.cpp"]
+SOURCES = ["imin_world.hip", "imin_kernels.hip", "imin_probe.hip", "imin_static.hip", "imin_api.cpp", "imin_serve.cpp"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of every device build.

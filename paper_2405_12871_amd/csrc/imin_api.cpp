@@ -1600,10 +1600,13 @@ static void fixed_plan(imin_graph_t g, WsPlan& p, int32_t n_seeds, uint64_t thet
     p.slots = std::max<size_t>(1, std::min<size_t>(std::min<size_t>(budget / bytes2, (size_t)cus * 4), (size_t)theta));
     p.slots3 = std::max<size_t>(1, std::min<size_t>(((size_t)1 << 30) / bytes3, 8));
     p.chunk_cap = chunk_bound(g->g, n_seeds);
+    // worlds start in tier 0 (whose fixed slots the layout has anyway), or
+    // in tier 2 when most worlds of earlier calls ended up there: both
+    // routes put the same worlds in the bump region, so the record of bump
+    // entries per world sizes it either way
     p.start_tier = 0;
     if (const char* t = std::getenv("IMIN_START_TIER")) p.start_tier = std::max(0, std::min(2, std::atoi(t)));
     else if (g->tier2_share.load(std::memory_order_relaxed) > 512) p.start_tier = 2;
-    else if (g->tier1_share.load(std::memory_order_relaxed) > 512) p.start_tier = 1;
 }
 
 // incremental rounds index every scratch entry with an int32 position
@@ -1638,8 +1641,20 @@ static imin_status_t plan_for(imin_graph_t g, int32_t n_seeds, uint64_t theta, s
 
 // the graph's device-side hints folded into its host-side ones
 static void fold_device_hints(imin_graph_t g) {
+    // a stream of this thread's own, so that the read waits for nothing else
+    thread_local hipStream_t hs = nullptr;
+    thread_local int hs_dev = -1;
+    if (!hs || hs_dev != g->device) {
+        if (hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess) {
+            (void)hipGetLastError();
+            hs = nullptr;
+            return;
+        }
+        hs_dev = g->device;
+    }
     unsigned long long h[4] = {0, 0, 0, 0};
-    if (hipMemcpy(h, g->hints_dev, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) {
+    if (hipMemcpyAsync(h, g->hints_dev, sizeof(h), hipMemcpyDeviceToHost, hs) != hipSuccess ||
+        hipStreamSynchronize(hs) != hipSuccess) {
         (void)hipGetLastError();
         return;
     }
@@ -1792,180 +1807,6 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     } catch (...) {
         return IMIN_ERR_INTERNAL;
     }
-}
-
-imin_status_t imin_solve_many(imin_graph_t g, imin_query_t* queries, int32_t n_queries, void* const* streams,
-                              int32_t n_streams) {
-    if (!g || n_queries < 0 || (n_queries > 0 && !queries) || n_streams < 1 || !streams) return IMIN_ERR_INVALID;
-    for (int32_t i = 0; i < n_streams; ++i)
-        for (int32_t j = 0; j < i; ++j)
-            if (streams[i] == streams[j]) return IMIN_ERR_INVALID;
-    for (int32_t q = 0; q < n_queries; ++q) {
-        queries[q].status = (int32_t)IMIN_ERR_INTERNAL;  // until the query has run
-        queries[q].device_flags = 0;
-    }
-    // largest first (theta * (k + 1) bounds a query's work), so that a long
-    // query does not start last and stretch the batch
-    std::vector<int32_t> order;
-    try {
-        order.resize((size_t)n_queries);
-    } catch (...) {
-        return IMIN_ERR_NOMEM;
-    }
-    for (int32_t q = 0; q < n_queries; ++q) order[(size_t)q] = q;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        const double wa = (double)queries[a].theta * ((double)queries[a].k + 1.0);
-        const double wb = (double)queries[b].theta * ((double)queries[b].k + 1.0);
-        return wa > wb;
-    });
-    std::atomic<int32_t> next{0};
-    auto work = [&](int32_t i) {
-        int prev = -1;
-        (void)hipGetDevice(&prev);
-        if (prev != g->device) (void)hipSetDevice(g->device);
-        for (;;) {
-            const int32_t j = next.fetch_add(1);
-            if (j >= n_queries) break;
-            imin_query_t& Q = queries[order[(size_t)j]];
-            Q.status = (int32_t)imin_solve(g, Q.seeds, Q.n_seeds, Q.k, Q.theta, Q.rng_seed, nullptr, 0, streams[i],
-                                           Q.blockers, Q.gains, Q.spread_totals, Q.n_selected, nullptr);
-            Q.device_flags = g_last_flags;
-        }
-        if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
-    };
-    const int32_t workers = std::min(n_streams, n_queries);
-    if (workers <= 1) {
-        work(0);
-    } else {
-        // a thread that cannot be started leaves its stream unused; the
-        // calling thread then takes stream 0's part of the queue itself
-        std::vector<std::thread> pool;
-        for (int32_t i = 1; i < workers; ++i) {
-            try {
-                pool.emplace_back(work, i);
-            } catch (...) {
-                break;
-            }
-        }
-        work(0);
-        for (std::thread& th : pool) th.join();
-    }
-    for (int32_t q = 0; q < n_queries; ++q)
-        if (queries[q].status != (int32_t)IMIN_OK) {
-            g_last_flags = queries[q].device_flags;
-            return (imin_status_t)queries[q].status;
-        }
-    return IMIN_OK;
-}
-
-struct imin_server {
-    imin_graph_t g = nullptr;
-    std::vector<void*> streams;
-    std::vector<std::thread> workers;
-    std::mutex mu;
-    std::condition_variable queued_cv;  // a query was queued, or the server stops
-    std::condition_variable done_cv;    // a query finished
-    std::deque<imin_query_t*> queue;    // submitted, not started
-    std::deque<imin_query_t*> done;     // finished, not yet returned
-    int64_t outstanding = 0;            // submitted, not yet returned
-    bool stopping = false;
-
-    void work(int32_t i) {
-        (void)hipSetDevice(g->device);
-        for (;;) {
-            imin_query_t* q = nullptr;
-            {
-                std::unique_lock<std::mutex> lk(mu);
-                queued_cv.wait(lk, [&] { return stopping || !queue.empty(); });
-                if (queue.empty()) return;  // stopping, and nothing left to run
-                q = queue.front();
-                queue.pop_front();
-            }
-            q->status = (int32_t)imin_solve(g, q->seeds, q->n_seeds, q->k, q->theta, q->rng_seed, nullptr, 0,
-                                            streams[(size_t)i], q->blockers, q->gains, q->spread_totals,
-                                            q->n_selected, nullptr);
-            q->device_flags = g_last_flags;
-            {
-                std::lock_guard<std::mutex> lk(mu);
-                try {
-                    done.push_back(q);
-                } catch (...) {
-                    // the query cannot be handed back: drop it from the count
-                    // so that imin_server_next does not wait for it forever
-                    --outstanding;
-                }
-            }
-            done_cv.notify_all();
-        }
-    }
-};
-
-imin_status_t imin_server_create(imin_graph_t g, void* const* streams, int32_t n_streams, imin_server_t* out) {
-    if (!g || !streams || n_streams < 1 || !out) return IMIN_ERR_INVALID;
-    for (int32_t i = 0; i < n_streams; ++i)
-        for (int32_t j = 0; j < i; ++j)
-            if (streams[i] == streams[j]) return IMIN_ERR_INVALID;
-    *out = nullptr;
-    imin_server* sv = new (std::nothrow) imin_server();
-    if (!sv) return IMIN_ERR_NOMEM;
-    sv->g = g;
-    try {
-        sv->streams.assign(streams, streams + n_streams);
-        for (int32_t i = 0; i < n_streams; ++i) sv->workers.emplace_back([sv, i] { sv->work(i); });
-    } catch (...) {
-        {
-            std::lock_guard<std::mutex> lk(sv->mu);
-            sv->stopping = true;
-        }
-        sv->queued_cv.notify_all();
-        for (std::thread& th : sv->workers) th.join();
-        delete sv;
-        return IMIN_ERR_NOMEM;
-    }
-    *out = sv;
-    return IMIN_OK;
-}
-
-imin_status_t imin_server_submit(imin_server_t s, imin_query_t* query) {
-    if (!s || !query) return IMIN_ERR_INVALID;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->stopping) return IMIN_ERR_INVALID;
-        query->status = (int32_t)IMIN_ERR_INTERNAL;  // until it has run
-        query->device_flags = 0;
-        try {
-            s->queue.push_back(query);
-        } catch (...) {
-            return IMIN_ERR_NOMEM;
-        }
-        ++s->outstanding;
-    }
-    s->queued_cv.notify_one();
-    return IMIN_OK;
-}
-
-imin_status_t imin_server_next(imin_server_t s, imin_query_t** done) {
-    if (!s || !done) return IMIN_ERR_INVALID;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->outstanding == 0) return IMIN_ERR_INVALID;
-    s->done_cv.wait(lk, [&] { return !s->done.empty() || s->outstanding == 0; });
-    if (s->done.empty()) return IMIN_ERR_NOMEM;  // the last query could not be handed back
-    *done = s->done.front();
-    s->done.pop_front();
-    --s->outstanding;
-    return IMIN_OK;
-}
-
-imin_status_t imin_server_destroy(imin_server_t s) {
-    if (!s) return IMIN_OK;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->stopping = true;
-    }
-    s->queued_cv.notify_all();
-    for (std::thread& th : s->workers) th.join();
-    delete s;
-    return IMIN_OK;
 }
 
 imin_status_t imin_cache_release(void) {

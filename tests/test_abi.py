@@ -56,20 +56,20 @@ def test_host_argument_checks(lib):
     q = (binding.Query * 1)()
     s1 = (ctypes.c_void_p * 2)(0x10, 0x20)
     s2 = (ctypes.c_void_p * 2)(0x10, 0x10)
-    assert lib.imin_solve_many(None, q, 1, s1, 2) == 1
-    assert lib.imin_solve_many(dummy, q, 1, s1, 0) == 1
-    assert lib.imin_solve_many(dummy, q, 1, None, 1) == 1
-    assert lib.imin_solve_many(dummy, q, 1, s2, 2) == 1
-    assert lib.imin_solve_many(dummy, q, -1, s1, 2) == 1
-    assert lib.imin_solve_many(dummy, None, 1, s1, 2) == 1
+    assert lib.imin_solve_many(None, q, 1, s1, 2, 0) == 1
+    assert lib.imin_solve_many(dummy, q, 1, s1, 0, 0) == 1
+    assert lib.imin_solve_many(dummy, q, 1, None, 1, 0) == 1
+    assert lib.imin_solve_many(dummy, q, 1, s2, 2, 0) == 1
+    assert lib.imin_solve_many(dummy, q, -1, s1, 2, 0) == 1
+    assert lib.imin_solve_many(dummy, None, 1, s1, 2, 0) == 1
     # server: NULL graph / streams / output, no stream, a stream named twice;
     # NULL server handles
     hs = ctypes.c_void_p()
-    assert lib.imin_server_create(None, s1, 2, ctypes.byref(hs)) == 1
-    assert lib.imin_server_create(dummy, None, 2, ctypes.byref(hs)) == 1
-    assert lib.imin_server_create(dummy, s1, 0, ctypes.byref(hs)) == 1
-    assert lib.imin_server_create(dummy, s2, 2, ctypes.byref(hs)) == 1
-    assert lib.imin_server_create(dummy, s1, 2, None) == 1
+    assert lib.imin_server_create(None, s1, 2, 0, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, None, 2, 0, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s1, 0, 0, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s2, 2, 0, ctypes.byref(hs)) == 1
+    assert lib.imin_server_create(dummy, s1, 2, 0, None) == 1
     assert lib.imin_server_submit(None, q) == 1
     assert lib.imin_server_next(None, ctypes.byref(ctypes.POINTER(binding.Query)())) == 1
     assert lib.imin_server_destroy(None) == 0
