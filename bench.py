@@ -115,84 +115,123 @@ def cpu_baseline(g, seeds, theta, budget_s, gpu_gain):
     return out
 
 
-def run_many(args, binding, G, n):
-    """Batch throughput: the same mixed queries sequentially and side by side."""
+def _same_result(a, b):
+    import numpy as np
+    return (not isinstance(a, Exception) and not isinstance(b, Exception) and a.n_selected == b.n_selected and
+            np.array_equal(a.blockers, b.blockers) and np.array_equal(a.gains, b.gains) and
+            np.array_equal(a.spread_totals, b.spread_totals))
+
+
+def _solve_alone(binding, Gs, queries, label):
+    """Each query solved alone, one after another (imin_solve with the block
+    cache): its service time and its result."""
+    import torch
+    service, alone = [], []
+    t_all = time.perf_counter()
+    for i, (gi, seeds, k, theta, rng) in enumerate(queries):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        alone.append(binding.solve(Gs[gi], seeds, k, theta, rng))
+        service.append(time.perf_counter() - t0)
+        log(f"{label} {i + 1}/{len(queries)}: graph {gi} |S|={len(seeds)} k={k} theta={theta} "
+            f"{service[-1] * 1e3:.1f} ms (elapsed {time.perf_counter() - t_all:.1f} s)")
+    return service, alone
+
+
+def run_many(args, binding, dev):
+    """Config B: a batch of mixed queries on the weighted-cascade twin of the
+    1M-node graph, solved one after another and then all submitted at once
+    to the serving runtime (pool admission, several streams)."""
     import numpy as np
     import torch
 
-    rs = np.random.default_rng(0xB0)
-    queries = []
-    for _ in range(args.many):
-        seeds = rs.choice(n, size=int(rs.integers(10, 501)), replace=False).astype(np.int32)
-        queries.append((seeds, int(rs.integers(10, 201)), int(rs.choice([10_000, 100_000])),
-                        int(rs.integers(0, 1 << 62))))
-    log(f"{len(queries)} queries; warm-up")
-    binding.solve_many(G, queries[:min(len(queries), 2 * args.streams)], n_streams=args.streams)
+    from paper_2405_12871_amd import synth
+    t0 = time.perf_counter()
+    g = synth.named_graph(args.graph)
+    log(f"graph {args.graph}: n={g.n} m={g.m} ({time.perf_counter() - t0:.1f} s)")
+    G = binding.Graph.from_synth(g, device=dev)
+    queries = synth.query_mix(args.many, [g.n], 0xB0, (10, 500), (10, 200), (10_000, 100_000))
+    # one query of each size class first, so that the graph's record sizes
+    # later workspaces (both runs start from it)
+    binding.solve(G, queries[0][1], queries[0][2], queries[0][3], queries[0][4])
+    service, alone = _solve_alone(binding, [G], queries, "alone")
+    t_seq = sum(service)
+    srv = binding.Server(G, n_streams=args.streams, hbm_budget=int(args.pool_gib * (1 << 30)))
+    got, done_at = {}, {}
     torch.cuda.synchronize()
-    runs = {}
-    for label, streams in (("sequential", 1), ("side_by_side", args.streams)):
-        t0 = time.perf_counter()
-        res = binding.solve_many(G, queries, n_streams=streams)
-        torch.cuda.synchronize()
-        runs[label] = (time.perf_counter() - t0, res)
-        log(f"{label}: {runs[label][0] * 1e3:.1f} ms on {streams} stream(s)")
-    (t_seq, seq), (t_par, par) = runs["sequential"], runs["side_by_side"]
-    same = all(np.array_equal(a.blockers, b.blockers) and np.array_equal(a.gains, b.gains) and
-               np.array_equal(a.spread_totals, b.spread_totals) for a, b in zip(seq, par))
+    start = time.perf_counter()
+    owner = {srv.submit(s, k, th, r): i for i, (_, s, k, th, r) in enumerate(queries)}
+    for j in range(len(queries)):
+        t, r = srv.next()
+        i = owner[t]
+        got[i], done_at[i] = r, time.perf_counter() - start
+        log(f"batch {j + 1}/{len(queries)}: query {i} done at {done_at[i]:.2f} s")
+    t_par = time.perf_counter() - start
+    srv.close()
+    same = all(_same_result(got[i], alone[i]) for i in range(len(queries)))
+    lat = [done_at[i] for i in range(len(queries))]
     print(json.dumps({
-        "metric": "greedy IMIN queries/s, mixed batch on one graph",
+        "metric": "IMIN queries/s, batch of mixed queries on one resident graph",
         "value": len(queries) / t_par,
         "unit": "queries/s",
         "n_gpus": 1,
         "higher_is_better": True,
         "data": "synthetic",
         "dtype": "u32+int64",
-        "config": {"workload": f"{args.workload} graph, {len(queries)} queries: |S|~U{{10..500}}, "
-                               f"k~U{{10..200}}, theta in {{1e4, 1e5}}", "streams": args.streams},
+        "config": {"workload": f"config B: {args.graph} weighted cascade (n={g.n}, m={g.m}), {len(queries)} queries: "
+                               f"|S|~U{{10..500}}, k~U{{10..200}}, theta in {{1e4, 1e5}}, all submitted at once",
+                   "streams": args.streams, "pool_GiB": args.pool_gib},
+        "batch_seconds": t_par,
+        "sequential_seconds": t_seq,
         "sequential_queries_per_s": len(queries) / t_seq,
         "speedup_over_sequential": t_seq / t_par,
-        "identical_to_sequential": bool(same),
-        "blockers_selected": int(sum(r.n_selected for r in par)),
-    }))
+        "batch_completion_p50_s": percentile(lat, 50),
+        "batch_completion_p99_s": percentile(lat, 99),
+        "service_ms_p50": percentile(service, 50) * 1e3,
+        "service_ms_p99": percentile(service, 99) * 1e3,
+        "identical_to_alone": bool(same),
+        "blockers_selected": int(sum(r.n_selected for r in alone)),
+    }), flush=True)
 
 
-def run_serve(args, binding, G, n):
-    """Latency under arrivals: the server against one-at-a-time service."""
+def run_serve(args, binding, dev):
+    """Config V: Poisson arrivals over three resident weighted-cascade graphs
+    against the serving runtime, next to one queue served one query at a
+    time (each query's service time measured alone)."""
     import threading
 
     import numpy as np
     import torch
 
-    rs = np.random.default_rng(0x5E)
-    queries = []
-    for _ in range(args.serve):
-        seeds = rs.choice(n, size=int(rs.integers(10, 1001)), replace=False).astype(np.int32)
-        queries.append((seeds, int(rs.integers(10, 501)), 50_000, int(rs.integers(0, 1 << 62))))
-    arrivals = np.cumsum(rs.exponential(1.0 / args.rate, size=len(queries)))
-    # each query alone: its service time and its result
-    log(f"{len(queries)} queries at {args.rate}/s; solving each alone")
-    binding.solve_many(G, queries[:2], n_streams=1)
-    alone, service = [], []
-    for q in queries:
-        torch.cuda.synchronize()
+    from paper_2405_12871_amd import synth
+    names = args.graphs.split(",")
+    gs = []
+    for nm in names:
         t0 = time.perf_counter()
-        alone.append(binding.solve_many(G, [q], n_streams=1)[0])
-        service.append(time.perf_counter() - t0)
-    # one queue, one query at a time
+        gs.append(synth.named_graph(nm))
+        log(f"graph {nm}: n={gs[-1].n} m={gs[-1].m} ({time.perf_counter() - t0:.1f} s)")
+    Gs = [binding.Graph.from_synth(g, device=dev) for g in gs]
+    queries = synth.query_mix(args.serve, [g.n for g in gs], 0x5E, (10, 1000), (10, 500), (50_000,),
+                              n_graphs=len(gs))
+    rs = np.random.default_rng(0x5E5E)
+    arrivals = np.cumsum(rs.exponential(1.0 / args.rate, size=len(queries)))
+    for gi, G in enumerate(Gs):  # a first query on each graph records its scratch needs
+        q = next(q for q in queries if q[0] == gi) if any(q[0] == gi for q in queries) else None
+        if q is not None:
+            binding.solve(G, q[1], q[2], q[3], q[4])
+    service, alone = _solve_alone(binding, Gs, queries, "alone")
     free, seq_lat = 0.0, []
     for a, sv in zip(arrivals, service):
         free = max(free, a) + sv
         seq_lat.append(free - a)
-    # the server, queries submitted at their arrival times
-    log(f"serving on {args.streams} streams")
-    srv = binding.Server(G, n_streams=args.streams)
-    finish, results = {}, {}
-    tickets = {}
+    log(f"serving at {args.rate}/s on {args.streams} streams")
+    srv = binding.Server(Gs[0], n_streams=args.streams, hbm_budget=int(args.pool_gib * (1 << 30)))
+    finish, results, tickets = {}, {}, {}
     lock = threading.Lock()
     submitted = threading.Semaphore(0)  # next() only while a query is outstanding
 
     def collect():
-        for _ in range(len(queries)):
+        for j in range(len(queries)):
             submitted.acquire()
             t, r = srv.next()
             now = time.perf_counter()
@@ -200,42 +239,43 @@ def run_serve(args, binding, G, n):
                 i = tickets.pop(t)
             finish[i] = now
             results[i] = r
+            log(f"served {j + 1}/{len(queries)}: query {i} latency {(now - start - arrivals[i]) * 1e3:.0f} ms")
 
     waiter = threading.Thread(target=collect)
     start = time.perf_counter()
-    for i, (q, a) in enumerate(zip(queries, arrivals)):
+    for i, ((gi, s, k, th, r), a) in enumerate(zip(queries, arrivals)):
         delay = start + a - time.perf_counter()
         if delay > 0:
             time.sleep(delay)
         with lock:
-            tickets[srv.submit(*q)] = i
+            tickets[srv.submit(s, k, th, r, graph=Gs[gi])] = i
         submitted.release()
         if i == 0:
             waiter.start()
     waiter.join()
     srv.close()
     lat = [finish[i] - (start + arrivals[i]) for i in range(len(queries))]
-    same = all(not isinstance(results[i], Exception) and
-               np.array_equal(results[i].blockers, alone[i].blockers) and
-               np.array_equal(results[i].spread_totals, alone[i].spread_totals) for i in range(len(queries)))
+    same = all(_same_result(results[i], alone[i]) for i in range(len(queries)))
     span = max(finish.values()) - start
     print(json.dumps({
-        "metric": "greedy IMIN query latency under Poisson arrivals, p50/p99",
+        "metric": "IMIN query latency under Poisson arrivals, p50/p99",
         "value": percentile(lat, 50) * 1e3,
         "unit": "ms (p50)",
         "n_gpus": 1,
         "higher_is_better": False,
         "data": "synthetic",
         "dtype": "u32+int64",
-        "config": {"workload": f"{args.workload} graph, {len(queries)} queries at {args.rate}/s: "
-                               f"|S|~U{{10..1000}}, k~U{{10..500}}, theta=5e4", "streams": args.streams},
+        "config": {"workload": f"config V: graphs {names} (weighted cascade), {len(queries)} queries at {args.rate}/s "
+                               f"(graph uniform, |S|~U{{10..1000}}, k~U{{10..500}}, theta=5e4)",
+                   "streams": args.streams, "pool_GiB": args.pool_gib},
         "p50_ms": percentile(lat, 50) * 1e3,
         "p99_ms": percentile(lat, 99) * 1e3,
         "throughput_queries_per_s": len(queries) / span,
         "one_at_a_time": {"p50_ms": percentile(seq_lat, 50) * 1e3, "p99_ms": percentile(seq_lat, 99) * 1e3,
-                          "mean_service_ms": float(np.mean(service)) * 1e3},
+                          "mean_service_ms": float(np.mean(service)) * 1e3,
+                          "throughput_queries_per_s": len(queries) / max(free, 1e-9)},
         "identical_to_alone": bool(same),
-    }))
+    }), flush=True)
 
 
 def probe_ceilings(binding, dev, theta, ebar, cus):
@@ -268,8 +308,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--many", type=int, default=0, help="measure a batch of this many mixed queries instead")
+    ap.add_argument("--graph", default="wc1m", help="graph of --many (a name of synth.GRAPHS)")
     ap.add_argument("--streams", type=int, default=4, help="streams for --many and --serve")
+    ap.add_argument("--pool-gib", type=float, default=0.0, help="workspace pool of --many/--serve (0: default)")
     ap.add_argument("--serve", type=int, default=0, help="measure latency of this many arriving queries instead")
+    ap.add_argument("--graphs", default="wc100k,wc1m,wc4m", help="graphs of --serve")
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -285,6 +328,12 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.many > 0:
+        run_many(args, binding, dev)
+        return
+    if args.serve > 0:
+        run_serve(args, binding, dev)
+        return
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
@@ -302,13 +351,6 @@ def main():
     torch.cuda.synchronize()
     ingest_ms = (time.perf_counter() - t0) * 1e3
     log(f"graph ingest {ingest_ms:.2f} ms")
-
-    if args.many > 0:
-        run_many(args, binding, G, g.n)
-        return
-    if args.serve > 0:
-        run_serve(args, binding, G, g.n)
-        return
 
     # per-world sizes of the workload (an untimed pass): R and E per world
     _, T0, wsize, _, wedges = binding.evaluate(G, seeds_dev, 0, theta, RNG_SEED, per_world=True, edges=True)

@@ -734,7 +734,14 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
                 out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
                 if (out.keep_edges) {
                     out.scr_par[off + i] = st.get_parent(ns + i);
-                    uint32_t lab = 0u;
+                    // A world without labels stores every entry with its exit
+                    // bit set, so the label rule never takes one of its
+                    // entries: the round-update launch's replay may label the
+                    // world while a rule workgroup still reads the entry of
+                    // the same blocker, whose label the replay leaves as it
+                    // was (the blocker is no longer reached); with the exit
+                    // bit set both roles agree that the rule does not hold.
+                    uint32_t lab = kLabelExit;
                     if constexpr (Store::kLabels) {
                         const int c = *st.aux_ptr(ns + i);
                         lab = pack_label(st.get_tin(ns + i), c, nx > 0 && exits_of(st, ns + i, c));

@@ -46,6 +46,9 @@ __all__ = [
     "random_small_graph",
     "WORKLOADS",
     "workload",
+    "GRAPHS",
+    "named_graph",
+    "query_mix",
 ]
 
 
@@ -258,3 +261,38 @@ def workload(name: str):
     else:
         seeds = seeds_top_out(g, count)
     return g, seeds, spec["k"], spec["theta"]
+
+
+# Weighted-cascade graphs that batches and serving run on: the medium
+# workload's graph, the weighted-cascade twin of the large workload's graph
+# (same generator seed), and a 4M-node graph.
+GRAPHS = {
+    "wc100k": dict(n=100_000, m=1_000_000, gen_seed=102),
+    "wc1m": dict(n=1_000_000, m=10_000_000, gen_seed=103),
+    "wc4m": dict(n=4_000_000, m=40_000_000, gen_seed=105),
+}
+
+
+@functools.lru_cache(maxsize=4)
+def named_graph(name: str) -> Graph:
+    """A weighted-cascade Chung-Lu graph of GRAPHS (cached per process)."""
+    spec = GRAPHS[name]
+    return chung_lu(spec["n"], spec["m"], prob="wc", gen_seed=spec["gen_seed"], name=name)
+
+
+def query_mix(count: int, n_nodes, seed: int, seeds_range, k_range, thetas, n_graphs: int = 1):
+    """``count`` queries drawn from numpy PCG64(seed): a graph index uniform
+    in [0, n_graphs), |S| uniform in seeds_range (inclusive) as distinct
+    uniform nodes of that graph (n_nodes[g] nodes), k uniform in k_range
+    (inclusive), theta uniform from ``thetas``, and a 62-bit coin key.
+    Returns [(graph index, seeds int32, k, theta, coin key)]."""
+    rs = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        gi = int(rs.integers(0, n_graphs))
+        ns = int(rs.integers(seeds_range[0], seeds_range[1] + 1))
+        seeds = rs.choice(int(n_nodes[gi]), size=ns, replace=False).astype(np.int32)
+        k = int(rs.integers(k_range[0], k_range[1] + 1))
+        theta = int(rs.choice(list(thetas)))
+        out.append((gi, seeds, k, theta, int(rs.integers(0, 1 << 62))))
+    return out

@@ -699,3 +699,27 @@ def test_solve_worlds_beyond_the_hbm_tier_bounds(B, oracle_mod):
         np.testing.assert_array_equal(res.blockers, want["blockers"])
         np.testing.assert_array_equal(res.gains, want["gains"])
         np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+def test_solve_with_worlds_labelled_by_replays(B, oracle_mod, monkeypatch):
+    """Every world starts in the HBM tier, which keeps no dominator-tree
+    labels, so the small ones get their labels from replays during the
+    rounds; a replay that labels a world must not let the label rule take
+    the same world in the same round.  Weighted-cascade 1M-node graph, 207
+    seeds, theta = 1e5, k = 37 (worlds of a few to thousands of nodes): the
+    solve equals the one whose worlds start in the LDS tiers, and the
+    oracle's from-scratch passes at rounds 0, 1 and 36."""
+    g = synth.named_graph("wc1m")
+    q = synth.query_mix(5, [g.n], 0xB0, (10, 500), (10, 200), (10_000, 100_000))
+    _, seeds, k, theta, rng = q[4]
+    G = B.Graph.from_synth(g)
+    _log("solve with worlds starting in the LDS tiers")
+    base = B.solve(G, seeds, k, theta, rng)
+    monkeypatch.setenv("IMIN_START_TIER", "2")
+    _log("solve with every world starting in the HBM tier")
+    res = B.solve(G, seeds, k, theta, rng)
+    assert res.n_selected == base.n_selected == k
+    np.testing.assert_array_equal(res.blockers, base.blockers)
+    np.testing.assert_array_equal(res.gains, base.gains)
+    np.testing.assert_array_equal(res.spread_totals, base.spread_totals)
+    _check_rounds_against_oracle(oracle_mod, g, seeds, theta, rng, res, (0, 1, 36))
