@@ -133,3 +133,21 @@ def expected_dominator_subtrees(n, src, dst, p, seeds, blocked=()):
             if v not in seeds_set:
                 acc[v] += pr * size[v]
     return acc
+
+
+def expected_lower_bound(n, src, dst, p, seeds, B):
+    """(D^L(B), E[f^2]) exactly, where f(phi) = |union over v in B of N_phi(v)|
+    and N_phi(v) is the set of nodes that stop being reached when v alone is
+    blocked (Section 3.2, the lower bounding function)."""
+    B = [int(b) for b in B]
+    m1 = Fraction(0)
+    m2 = Fraction(0)
+    for pr, edges, live in enumerate_worlds(n, src, dst, p):
+        base = _reach(n, edges, live, seeds, set())
+        lost = set()
+        for v in B:
+            if v in base:
+                lost |= base - _reach(n, edges, live, seeds, {v})
+        m1 += pr * len(lost)
+        m2 += pr * len(lost) * len(lost)
+    return m1, m2

@@ -570,3 +570,421 @@ int oracle_solve(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* co
     free(blk); free(is_seed); free(gain);
     return status;
 }
+
+/* ======================================================================== */
+/* Lower-bound coverage (Section 4.1) and Max-Coverage (Section 5.1).        */
+/*                                                                          */
+/*   CP set     C_w(s,v): the non-seed nodes that lie on every path from s   */
+/*              to v in world w (Definition 4.1).  Algorithm 2 builds them   */
+/*              from the dominator tree: walking R_w in depth-first preorder */
+/*              from s, a node whose immediate dominator is a seed (or s)   */
+/*              gets {v}; any other node gets its immediate dominator's set  */
+/*              plus itself.                                                */
+/*   CP seq.    the CP sets of every v in R_w \ S.                           */
+/*   Cov(B)     number of (world, v) pairs whose CP set meets B; Cov/theta  */
+/*              is unbiased for the lower bound D^L(B) (Lemma 4.2).          */
+/*   Max-Cov.   k greedy steps, each adding argmax over V \ S of the        */
+/*              marginal coverage (ties to the smaller id); stops when the  */
+/*              best marginal is 0.                                         */
+/*   Cov^u      for every greedy prefix B_i (0 <= i <= n_selected):          */
+/*              Cov(B_i) + the sum of the k largest marginal coverages given */
+/*              B_i; Algorithm 4 takes their minimum as its upper bound.    */
+/* Worlds are drawn exactly as for the greedy above, without blockers.      */
+/* ======================================================================== */
+
+/* CP sets of the current world once world_counts_dominator has run on it:  */
+/* entries (non-seed reached nodes) in depth-first preorder from s, each    */
+/* with its set.  node_out[i] is entry i's node, its set is                  */
+/* cp[cp_off[i] .. cp_off[i+1]).  Returns the entry count, or -1 when the   */
+/* set storage (cp_cap node slots) is too small.                             */
+static int32_t world_cp_sets(scratch_t* s, int32_t R, const uint8_t* is_seed,
+                             int32_t* node_out, int64_t* cp_off, int32_t* cp, int64_t cp_cap,
+                             int32_t* set_of /* [R+1]: entry index of each local id, -1 none */) {
+    int32_t N = R + 1;
+    /* depth-first preorder of the live subgraph from s (local id 0) */
+    int32_t* seen = s->po; /* postorder numbers are no longer needed */
+    for (int32_t v = 0; v < N; ++v) { seen[v] = 0; set_of[v] = -1; }
+    int32_t top = 0, ne = 0;
+    int64_t used = 0;
+    cp_off[0] = 0;
+    s->stack[top] = 0; s->it[top] = s->succ_off[0]; top = 1; seen[0] = 1;
+    for (;;) {
+        if (top == 0) break;
+        int32_t v = s->stack[top - 1];
+        if (s->it[top - 1] < s->succ_off[v + 1]) {
+            int32_t x = s->succ[s->it[top - 1]++];
+            if (seen[x]) continue;
+            seen[x] = 1;
+            s->stack[top] = x;
+            s->it[top] = s->succ_off[x];
+            ++top;
+            /* x is visited now (preorder): its immediate dominator was      */
+            /* visited earlier, since every path from s to x passes it       */
+            int32_t node = s->queue[x - 1];
+            if (is_seed[node]) continue;
+            int32_t d = s->idom[x];
+            int32_t dn = (d == 0) ? -1 : s->queue[d - 1];
+            if (d != 0 && !is_seed[dn]) {
+                int32_t pe = set_of[d];
+                if (pe < 0) return -1; /* cannot happen: d is a visited non-seed */
+                int64_t len = cp_off[pe + 1] - cp_off[pe];
+                if (used + len + 1 > cp_cap) return -1;
+                memcpy(cp + used, cp + cp_off[pe], (size_t)len * sizeof(int32_t));
+                used += len;
+            }
+            if (used + 1 > cp_cap) return -1;
+            cp[used++] = node;
+            set_of[x] = ne;
+            node_out[ne] = node;
+            cp_off[ne + 1] = used;
+            ++ne;
+        } else {
+            --top;
+        }
+    }
+    return ne;
+}
+
+/* Public: the CP sequence of world w (for fixtures and the tests).          */
+/* Returns the entry count, -1 on a bad query, -2 when cp_cap is too small. */
+int32_t oracle_cp_world(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                        const int32_t* seeds, int32_t n_seeds, uint64_t rng_seed, uint64_t w,
+                        int32_t* node_out, int64_t* cp_off, int32_t* cp, int64_t cp_cap) {
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    scratch_t s;
+    if (scratch_init(&s, n, NULL)) return -1;
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    int32_t* set_of = malloc(((size_t)n + 2) * sizeof(int32_t));
+    int32_t ret = -1;
+    if (is_seed && set_of) {
+        for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+        int32_t R = world_counts_dominator(&q, &s, w);
+        if (R >= 0 && !s.oom) {
+            ret = world_cp_sets(&s, R, is_seed, node_out, cp_off, cp, cp_cap, set_of);
+            if (ret < 0) ret = -2;
+        }
+    }
+    free(is_seed); free(set_of);
+    scratch_free(&s);
+    return ret;
+}
+
+/* The CP sequences of a world range, kept for the greedy: one flat list of */
+/* sets per thread, a covered flag per set.                                  */
+typedef struct {
+    const query_t* q;
+    const uint8_t* is_seed;
+    uint64_t w_begin, w_end;
+    int64_t n_sets;
+    int64_t* set_off;  /* [n_sets + 1] */
+    int32_t* cp;       /* set members */
+    uint8_t* covered;  /* [n_sets] */
+    int64_t* marg;     /* [n] this thread's marginal coverages */
+    const uint8_t* in_b; /* [n] blocker flags (coverage of a given set) */
+    int64_t count;     /* coverage counted by this thread */
+    int status;
+} cov_job_t;
+
+static int grow(void** p, int64_t* cap, int64_t need, size_t elem) {
+    if (need <= *cap) return 0;
+    int64_t c = *cap ? *cap : 1024;
+    while (c < need) c *= 2;
+    void* np = realloc(*p, (size_t)c * elem);
+    if (!np) return -1;
+    *p = np;
+    *cap = c;
+    return 0;
+}
+
+/* Build every CP set of the job's worlds (Algorithm 2 on each world). */
+static void* cov_build_job(void* arg) {
+    cov_job_t* j = (cov_job_t*)arg;
+    const query_t* q = j->q;
+    scratch_t s;
+    if (scratch_init(&s, q->n, NULL)) { j->status = -1; return NULL; }
+    int32_t* node_out = malloc(((size_t)q->n + 1) * sizeof(int32_t));
+    int64_t* off = malloc(((size_t)q->n + 2) * sizeof(int64_t));
+    int32_t* set_of = malloc(((size_t)q->n + 2) * sizeof(int32_t));
+    int64_t tmp_cap = 1 << 16;
+    int32_t* tmp = malloc((size_t)tmp_cap * sizeof(int32_t));
+    int64_t off_cap = 0, cp_cap = 0, cov_cap = 0;
+    j->n_sets = 0;
+    j->set_off = NULL; j->cp = NULL; j->covered = NULL;
+    if (!node_out || !off || !set_of || !tmp || grow((void**)&j->set_off, &off_cap, 1, sizeof(int64_t))) {
+        j->status = -1;
+        goto done;
+    }
+    j->set_off[0] = 0;
+    for (uint64_t w = j->w_begin; w < j->w_end; ++w) {
+        int32_t R = world_counts_dominator(q, &s, w);
+        if (R < 0 || s.oom) { j->status = -1; break; }
+        int32_t ne;
+        while ((ne = world_cp_sets(&s, R, j->is_seed, node_out, off, tmp, tmp_cap, set_of)) < 0) {
+            int32_t* nt = realloc(tmp, (size_t)tmp_cap * 2 * sizeof(int32_t));
+            if (!nt) { j->status = -1; goto done; }
+            tmp = nt;
+            tmp_cap *= 2;
+        }
+        int64_t base = j->set_off[j->n_sets];
+        if (grow((void**)&j->set_off, &off_cap, j->n_sets + ne + 1, sizeof(int64_t)) ||
+            grow((void**)&j->cp, &cp_cap, base + off[ne], sizeof(int32_t)) ||
+            grow((void**)&j->covered, &cov_cap, j->n_sets + ne, 1)) {
+            j->status = -1;
+            break;
+        }
+        memcpy(j->cp + base, tmp, (size_t)off[ne] * sizeof(int32_t));
+        for (int32_t i = 0; i < ne; ++i) {
+            j->set_off[j->n_sets + i + 1] = base + off[i + 1];
+            j->covered[j->n_sets + i] = 0;
+        }
+        j->n_sets += ne;
+    }
+done:
+    free(node_out); free(off); free(set_of); free(tmp);
+    scratch_free(&s);
+    return NULL;
+}
+
+/* Marginal coverage of every node given the covered flags: each uncovered  */
+/* set adds one to each of its members.                                      */
+static void* cov_marg_job(void* arg) {
+    cov_job_t* j = (cov_job_t*)arg;
+    memset(j->marg, 0, (size_t)j->q->n * sizeof(int64_t));
+    for (int64_t i = 0; i < j->n_sets; ++i) {
+        if (j->covered[i]) continue;
+        for (int64_t x = j->set_off[i]; x < j->set_off[i + 1]; ++x) j->marg[j->cp[x]] += 1;
+    }
+    return NULL;
+}
+
+/* Mark the sets that contain the flagged nodes; count the newly covered.  */
+static void* cov_mark_job(void* arg) {
+    cov_job_t* j = (cov_job_t*)arg;
+    j->count = 0;
+    for (int64_t i = 0; i < j->n_sets; ++i) {
+        if (j->covered[i]) continue;
+        for (int64_t x = j->set_off[i]; x < j->set_off[i + 1]; ++x) {
+            if (j->in_b[j->cp[x]]) {
+                j->covered[i] = 1;
+                j->count += 1;
+                break;
+            }
+        }
+    }
+    return NULL;
+}
+
+static void run_jobs(cov_job_t* jobs, int nthreads, void* (*fn)(void*)) {
+    pthread_t* th = calloc((size_t)nthreads, sizeof(pthread_t));
+    int started = 0;
+    if (th) {
+        for (int t = 1; t < nthreads; ++t) {
+            if (pthread_create(&th[t], NULL, fn, &jobs[t]) == 0) ++started;
+            else break;
+        }
+    }
+    fn(&jobs[0]);
+    for (int t = 1; t <= started; ++t) pthread_join(th[t], NULL);
+    for (int t = started + 1; t < nthreads; ++t) fn(&jobs[t]); /* threads that could not start */
+    free(th);
+}
+
+static int cmp_desc_i64(const void* a, const void* b) {
+    int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x < y) - (x > y);
+}
+
+static void cov_free_jobs(cov_job_t* jobs, int nthreads) {
+    for (int t = 0; t < nthreads; ++t) {
+        free(jobs[t].set_off); free(jobs[t].cp); free(jobs[t].covered); free(jobs[t].marg);
+    }
+    free(jobs);
+}
+
+static cov_job_t* cov_build(const query_t* q, const uint8_t* is_seed, uint64_t theta, int nthreads, int with_marg) {
+    cov_job_t* jobs = calloc((size_t)nthreads, sizeof(cov_job_t));
+    if (!jobs) return NULL;
+    int bad = 0;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t].q = q;
+        jobs[t].is_seed = is_seed;
+        jobs[t].w_begin = theta * (uint64_t)t / (uint64_t)nthreads;
+        jobs[t].w_end = theta * (uint64_t)(t + 1) / (uint64_t)nthreads;
+        if (with_marg && !(jobs[t].marg = malloc((size_t)q->n * sizeof(int64_t)))) bad = 1;
+    }
+    if (!bad) run_jobs(jobs, nthreads, cov_build_job);
+    for (int t = 0; t < nthreads; ++t) bad |= jobs[t].status;
+    if (bad) { cov_free_jobs(jobs, nthreads); return NULL; }
+    return jobs;
+}
+
+/* Public: Max-Coverage over the CP sequences of worlds [0, theta) (Section  */
+/* 5.1, procedure Max-Coverage of Algorithm 4), with the coverage of every   */
+/* prefix and its upper-bound term.  Outputs: blockers[k], gains[k] (the     */
+/* marginal coverage of each pick), cov[k+1] = Cov(B_0..B_{n_selected}),     */
+/* cov_upper[k+1] = Cov(B_i) + sum of the k largest marginals given B_i.     */
+int oracle_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                        const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
+                        int nthreads, int32_t* blockers, int64_t* gains, int64_t* cov, int64_t* cov_upper,
+                        int32_t* n_selected) {
+    if (k < 0 || theta < 1) return -1;
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > theta) nthreads = (int)theta;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    uint8_t* in_b = calloc((size_t)n, 1);  /* the pick whose sets are being covered */
+    uint8_t* chosen = calloc((size_t)n, 1); /* B_r */
+    int64_t* marg = malloc((size_t)n * sizeof(int64_t));
+    int64_t* sorted = malloc((size_t)n * sizeof(int64_t));
+    if (!is_seed || !in_b || !chosen || !marg || !sorted) {
+        free(is_seed); free(in_b); free(chosen); free(marg); free(sorted);
+        return -1;
+    }
+    for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+    cov_job_t* jobs = cov_build(&q, is_seed, theta, nthreads, 1);
+    if (!jobs) { free(is_seed); free(in_b); free(chosen); free(marg); free(sorted); return -1; }
+    for (int t = 0; t < nthreads; ++t) jobs[t].in_b = in_b;
+    int64_t covered = 0;
+    int32_t r = 0;
+    for (;;) {
+        /* marginal coverage of every candidate given B_r */
+        run_jobs(jobs, nthreads, cov_marg_job);
+        memset(marg, 0, (size_t)n * sizeof(int64_t));
+        for (int t = 0; t < nthreads; ++t)
+            for (int32_t v = 0; v < n; ++v) marg[v] += jobs[t].marg[v];
+        /* the k largest marginals over V \ S \ B_r (nodes with none add 0) */
+        int64_t nz = 0;
+        for (int32_t v = 0; v < n; ++v)
+            if (!is_seed[v] && !chosen[v] && marg[v] > 0) sorted[nz++] = marg[v];
+        qsort(sorted, (size_t)nz, sizeof(int64_t), cmp_desc_i64);
+        int64_t top = 0;
+        for (int64_t i = 0; i < nz && i < k; ++i) top += sorted[i];
+        cov[r] = covered;
+        cov_upper[r] = covered + top;
+        if (r == k) break;
+        int32_t best = -1;
+        for (int32_t v = 0; v < n; ++v) {
+            if (is_seed[v] || chosen[v]) continue;
+            if (best < 0 || marg[v] > marg[best]) best = v; /* ties keep the smaller id */
+        }
+        if (best < 0 || marg[best] == 0) break;
+        blockers[r] = best;
+        gains[r] = marg[best];
+        chosen[best] = 1;
+        /* cover the sets that contain the pick (sets covered before are     */
+        /* skipped, so only the new pick is flagged)                         */
+        memset(in_b, 0, (size_t)n);
+        in_b[best] = 1;
+        run_jobs(jobs, nthreads, cov_mark_job);
+        int64_t add = 0;
+        for (int t = 0; t < nthreads; ++t) add += jobs[t].count;
+        covered += add;
+        ++r;
+    }
+    *n_selected = r;
+    cov_free_jobs(jobs, nthreads);
+    free(is_seed); free(in_b); free(chosen); free(marg); free(sorted);
+    return 0;
+}
+
+/* Public: Cov(B) over the CP sequences of worlds [0, theta) (Section 4.1). */
+int oracle_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                    const int32_t* seeds, int32_t n_seeds, const int32_t* blockers, int32_t n_blockers,
+                    uint64_t theta, uint64_t rng_seed, int nthreads, int64_t* cov) {
+    if (theta < 1 || n_blockers < 0) return -1;
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > theta) nthreads = (int)theta;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    uint8_t* in_b = calloc((size_t)n, 1);
+    if (!is_seed || !in_b) { free(is_seed); free(in_b); return -1; }
+    for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+    int bad = 0;
+    for (int32_t i = 0; i < n_blockers; ++i) {
+        if (blockers[i] < 0 || blockers[i] >= n) bad = 1;
+        else in_b[blockers[i]] = 1;
+    }
+    cov_job_t* jobs = bad ? NULL : cov_build(&q, is_seed, theta, nthreads, 0);
+    if (!jobs) { free(is_seed); free(in_b); return -1; }
+    for (int t = 0; t < nthreads; ++t) jobs[t].in_b = in_b;
+    run_jobs(jobs, nthreads, cov_mark_job);
+    *cov = 0;
+    for (int t = 0; t < nthreads; ++t) *cov += jobs[t].count;
+    cov_free_jobs(jobs, nthreads);
+    free(is_seed); free(in_b);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-node reach counts over worlds [w0, w0+nw): counts[v] = number of      */
+/* worlds in which v is reached from S (no blockers).  counts[v]/nw          */
+/* estimates Pr[s -> v] (Section 5.1, the lower bound OPT^L).                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    const query_t* q;
+    uint64_t w_begin, w_end;
+    int64_t* counts;
+    int status;
+} reach_job_t;
+
+static void* reach_job(void* arg) {
+    reach_job_t* j = (reach_job_t*)arg;
+    scratch_t s;
+    if (scratch_init(&s, j->q->n, NULL)) { j->status = -1; return NULL; }
+    for (uint64_t w = j->w_begin; w < j->w_end; ++w) {
+        int32_t R = reach(j->q, &s, w);
+        for (int32_t i = 0; i < R; ++i) j->counts[s.queue[i]] += 1;
+    }
+    scratch_free(&s);
+    return NULL;
+}
+
+int oracle_reach_counts(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                        const int32_t* seeds, int32_t n_seeds, uint64_t rng_seed, uint64_t w0, uint64_t nw,
+                        int nthreads, int64_t* counts) {
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nw > 0 && (uint64_t)nthreads > nw) nthreads = (int)nw;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    reach_job_t* jobs = calloc((size_t)nthreads, sizeof(reach_job_t));
+    pthread_t* th = calloc((size_t)nthreads, sizeof(pthread_t));
+    int status = (jobs && th) ? 0 : -1;
+    for (int t = 0; t < nthreads && status == 0; ++t) {
+        jobs[t].q = &q;
+        jobs[t].w_begin = w0 + nw * (uint64_t)t / (uint64_t)nthreads;
+        jobs[t].w_end = w0 + nw * (uint64_t)(t + 1) / (uint64_t)nthreads;
+        if (!(jobs[t].counts = calloc((size_t)n, sizeof(int64_t)))) status = -1;
+    }
+    if (status == 0) {
+        for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, reach_job, &jobs[t]);
+        reach_job(&jobs[0]);
+        for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+        memset(counts, 0, (size_t)n * sizeof(int64_t));
+        for (int t = 0; t < nthreads; ++t) {
+            if (jobs[t].status) status = -1;
+            for (int32_t v = 0; v < n; ++v) counts[v] += jobs[t].counts[v];
+        }
+    }
+    if (jobs)
+        for (int t = 0; t < nthreads; ++t) free(jobs[t].counts);
+    free(jobs); free(th);
+    return status;
+}
+
+/* Public: |R_w| of every world in [w0, w0+nw), no blockers (the samples of */
+/* the stopping-rule estimate of E[I_G(s)] in Algorithm 4).                  */
+int oracle_world_sizes(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                       const int32_t* seeds, int32_t n_seeds, uint64_t rng_seed, uint64_t w0, uint64_t nw,
+                       int nthreads, int32_t* rsize) {
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* blk = calloc((size_t)n, 1);
+    if (!blk) return -1;
+    int64_t total = 0;
+    int st = run_eval(&q, blk, 0, 0, w0, nw, nthreads, NULL, &total, rsize, NULL);
+    free(blk);
+    return st;
+}

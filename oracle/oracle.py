@@ -55,6 +55,17 @@ def _load():
         lib.oracle_solve.argtypes = [i32, i64, P, P, P, P, i32, i32, u64, u64, ctypes.c_int,
                                      ctypes.c_int, P, P, P, P]
         lib.oracle_solve.restype = ctypes.c_int
+        lib.oracle_cp_world.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, P, P, P, i64]
+        lib.oracle_cp_world.restype = i32
+        lib.oracle_max_coverage.argtypes = [i32, i64, P, P, P, P, i32, i32, u64, u64, ctypes.c_int,
+                                            P, P, P, P, P]
+        lib.oracle_max_coverage.restype = ctypes.c_int
+        lib.oracle_coverage.argtypes = [i32, i64, P, P, P, P, i32, P, i32, u64, u64, ctypes.c_int, P]
+        lib.oracle_coverage.restype = ctypes.c_int
+        lib.oracle_reach_counts.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, u64, ctypes.c_int, P]
+        lib.oracle_reach_counts.restype = ctypes.c_int
+        lib.oracle_world_sizes.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, u64, ctypes.c_int, P]
+        lib.oracle_world_sizes.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -159,3 +170,77 @@ class Query:
         r = int(nsel[0])
         return dict(blockers=blockers[:r].copy(), gains=gains[:r].copy(),
                     spread_totals=totals[:r + 1].copy(), n_selected=r)
+
+    # ---------------------------------------------------------- coverage
+    def cp_world(self, rng_seed: int, w: int):
+        """The CP sequence of world w (Definition 4.1, Algorithm 2): a list of
+        (node, CP set) in depth-first preorder from the virtual source."""
+        lib = _load()
+        node = np.zeros(self.n, dtype=np.int32)
+        off = np.zeros(self.n + 1, dtype=np.int64)
+        cap = 1 << 16
+        while True:
+            cp = np.zeros(cap, dtype=np.int32)
+            ne = lib.oracle_cp_world(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                     _ptr(self.seeds), len(self.seeds), rng_seed, w, _ptr(node), _ptr(off),
+                                     _ptr(cp), cap)
+            if ne == -2:
+                cap *= 4
+                continue
+            if ne < 0:
+                raise ValueError("oracle_cp_world rejected the query")
+            return [(int(node[i]), [int(x) for x in cp[off[i]:off[i + 1]]]) for i in range(ne)]
+
+    def max_coverage(self, k: int, theta: int, rng_seed: int, threads: int | None = None):
+        """Max-Coverage over the CP sequences of worlds [0, theta): dict(blockers,
+        gains, cov, cov_upper, n_selected); cov and cov_upper have n_selected+1
+        entries (every prefix B_0 .. B_{n_selected})."""
+        lib = _load()
+        blockers = np.zeros(max(k, 1), dtype=np.int32)
+        gains = np.zeros(max(k, 1), dtype=np.int64)
+        cov = np.zeros(k + 1, dtype=np.int64)
+        cu = np.zeros(k + 1, dtype=np.int64)
+        nsel = np.zeros(1, dtype=np.int32)
+        st = lib.oracle_max_coverage(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                     _ptr(self.seeds), len(self.seeds), k, theta, rng_seed,
+                                     threads or default_threads(), _ptr(blockers), _ptr(gains), _ptr(cov),
+                                     _ptr(cu), _ptr(nsel))
+        if st != 0:
+            raise ValueError("oracle_max_coverage rejected the query")
+        r = int(nsel[0])
+        return dict(blockers=blockers[:r].copy(), gains=gains[:r].copy(), cov=cov[:r + 1].copy(),
+                    cov_upper=cu[:r + 1].copy(), n_selected=r)
+
+    def coverage(self, blockers, theta: int, rng_seed: int, threads: int | None = None) -> int:
+        """Cov(B) over the CP sequences of worlds [0, theta) (Section 4.1)."""
+        lib = _load()
+        b = np.ascontiguousarray(blockers, dtype=np.int32)
+        out = np.zeros(1, dtype=np.int64)
+        st = lib.oracle_coverage(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                 _ptr(self.seeds), len(self.seeds), _ptr(b), len(b), theta, rng_seed,
+                                 threads or default_threads(), _ptr(out))
+        if st != 0:
+            raise ValueError("oracle_coverage rejected the query")
+        return int(out[0])
+
+    def reach_counts(self, rng_seed: int, w0: int, nw: int, threads: int | None = None) -> np.ndarray:
+        """int64[n]: in how many worlds of [w0, w0+nw) each node is reached."""
+        lib = _load()
+        out = np.zeros(self.n, dtype=np.int64)
+        st = lib.oracle_reach_counts(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                     _ptr(self.seeds), len(self.seeds), rng_seed, w0, nw,
+                                     threads or default_threads(), _ptr(out))
+        if st != 0:
+            raise ValueError("oracle_reach_counts rejected the query")
+        return out
+
+    def world_sizes(self, rng_seed: int, w0: int, nw: int, threads: int | None = None) -> np.ndarray:
+        """int32[nw]: |R_w| of worlds [w0, w0+nw) with no blockers."""
+        lib = _load()
+        out = np.zeros(nw, dtype=np.int32)
+        st = lib.oracle_world_sizes(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                    _ptr(self.seeds), len(self.seeds), rng_seed, w0, nw,
+                                    threads or default_threads(), _ptr(out))
+        if st != 0:
+            raise ValueError("oracle_world_sizes rejected the query")
+        return out
