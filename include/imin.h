@@ -86,6 +86,14 @@ imin_status_t imin_graph_destroy(imin_graph_t g);
 imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m);
 
 /*
+ * Host copies of a handle's graph: row_ptr int64[n+1], col int32[m] and the
+ * coin thresholds thr uint32[m] the handle derived from p (Section 2.1, the
+ * live-edge process; 0xFFFFFFFF for p == 1, else floor(p * 2^32)).  All three
+ * are HOST pointers.  Synchronous.
+ */
+imin_status_t imin_graph_export(imin_graph_t g, int64_t* row_ptr, int32_t* col, uint32_t* thr);
+
+/*
  * imin_solve -- greedy blocker selection (Section 2.1, problem statement:
  * given G, p, the seed set S and a budget k, find at most k blockers
  * minimising the expected spread; Section 2.2: the greedy framework driven
@@ -292,6 +300,120 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
                             int64_t w_count, uint64_t rng_seed, void* stream, int64_t* gain,
                             int64_t* total, int32_t* world_size, int64_t* world_sum,
                             int64_t* world_edges);
+
+/*
+ * Lower-bound coverage (Section 3.2, the lower bounding function D^L;
+ * Section 4.1, CP sequences and coverage; Section 5.1, Max-Coverage).
+ *
+ * In a world w (drawn as above, with no blockers) the CP set C_w(s, v) of a
+ * reached non-seed v is the set of non-seed nodes on every path from the
+ * seeds to v, v included (Definition 4.1): v's chain of non-seed dominators.
+ * Cov(B) over worlds [0, theta) counts the pairs (w, v) whose CP set meets B;
+ * Cov(B) / theta estimates D^L(B) without bias (Lemma 4.2).
+ */
+
+/*
+ * imin_max_coverage -- the procedure Max-Coverage of Algorithm 4 on the CP
+ * sequences of worlds [0, theta): k greedy steps, each adding the node of
+ * V \ (S + B) with the largest marginal coverage Cov(B + v) - Cov(B), ties to
+ * the smaller id; it stops early when the best marginal is 0.
+ *
+ *   blockers   int32[k], out: picks in order (n_selected of them)
+ *   gains      int64[k], out: the marginal coverage of each pick
+ *   cov        int64[k+1], out: cov[i] = Cov(B_i) for the prefixes
+ *              B_0 .. B_{n_selected}; -1 beyond
+ *   cov_upper  int64[k+1], out: cov[i] + the sum of the k largest marginal
+ *              coverages given B_i (over V \ (S + B_i)); Algorithm 4 bounds
+ *              the optimum's coverage by their minimum
+ *   n_selected int32[1], out
+ *
+ * The worlds' dominator trees stay resident (16 bytes per reached non-seed
+ * per world, plus 8 for the node index): IMIN_ERR_NOMEM when they exceed the
+ * device or 2^31 - 1 entries.  Errors otherwise as for imin_solve.
+ */
+imin_status_t imin_max_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
+                                int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
+                                int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected);
+
+/*
+ * imin_coverage -- Cov(set) over the CP sequences of worlds [0, theta)
+ * (Section 4.1).  set: int32[n_set], device, non-seeds (repeats allowed; a
+ * seed or an id out of range is IMIN_ERR_DATA); covered: int64[1], out.
+ */
+imin_status_t imin_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set,
+                            int32_t n_set, int64_t theta, uint64_t rng_seed, void* stream,
+                            int64_t* covered);
+
+/*
+ * imin_reach_counts -- in how many of the worlds [w_begin, w_begin + w_count)
+ * each non-seed is reached from S (no blockers): counts[v] / w_count
+ * estimates Pr[s -> v] (Section 5.1, OPT^L).  counts: int64[n], out (0 for
+ * seeds); world_size: int32[w_count], out, optional: |R_w|.
+ */
+imin_status_t imin_reach_counts(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t w_begin,
+                                int64_t w_count, uint64_t rng_seed, void* stream, int64_t* counts,
+                                int32_t* world_size);
+
+/*
+ * imin_lsbm -- LSBM (Algorithm 4, Section 5.1): a blocker set B_L whose lower
+ * bound D^L(B_L) is within 1 - 1/e - eps of the best size-k set's with
+ * probability at least 1 - delta (Section 5.1, the theorem after Lemma 5.3).
+ *
+ *   1. ON = nodes a seed reaches by one edge that can be live (threshold > 0),
+ *      seeds left out; when |ON| <= k the answer is ON (ascending).
+ *   2. I_hat, E[I_G(s)] within relative error beta with probability
+ *      1 - delta/6, by the Stopping Rule Algorithm of Dagum, Karp, Luby and
+ *      Ross (SIAM J. Comput. 2000) on Z_w = |R_w| / b, b the nodes reachable
+ *      from S over edges with threshold > 0: worlds 0, 1, ... are drawn until
+ *      sum |R_w| >= b * Upsilon_1, with Upsilon = 4 (e - 2) ln(2 / (delta/6)) /
+ *      beta^2 and Upsilon_1 = 1 + (1 + beta) Upsilon; then
+ *      I_hat = b * Upsilon_1 / N for the N worlds drawn.
+ *   3. OPT^L = sum over the k nodes of ON with the largest reach counts in
+ *      those N worlds of count / N (1 / N when that sum is 0).
+ *   4. theta_max = 2 I_hat ((1 - 1/e) sqrt(ln(12/delta)) +
+ *      sqrt((1 - 1/e)(ln C(n - |S|, k) + ln(12/delta))))^2 /
+ *      ((1 - beta) eps^2 OPT^L), with ln C(N, k) = sum over j = 1..k of
+ *      ln((N - k + j) / j); theta_0 = theta_max (1 - beta) eps^2 OPT^L / I_hat;
+ *      i_max = max(1, ceil(log2(theta_max / theta_0)));
+ *      a_1 = a_2 = ln(3 i_max / delta).
+ *   5. For i = 1 .. i_max, with both pools of theta_i = ceil(theta_0) 2^(i-1)
+ *      worlds: B_L = Max-Coverage on pool 1; sigma^L from Cov(B_L) on pool 2
+ *      and sigma^U from min_i cov_upper on pool 1 (Lemma 5.3, as Algorithm 4
+ *      states them); return B_L when sigma^L / sigma^U >= 1 - 1/e - eps or
+ *      i = i_max.
+ *
+ * Pool 1's worlds are those of key rng_seed (the worlds of imin_solve);
+ * pool 2 uses key rng_seed ^ 0x9E3779B97F4A7C15 and the stopping rule
+ * rng_seed ^ 0xC2B2AE3D27D4EB4F.  Floating-point steps are evaluated in
+ * double, left to right as written above.
+ *
+ *   blockers    int32[k], device, out; n_selected int32[1], device, out
+ *   info        host, out, optional: every intermediate quantity
+ *   eps in (0, 1), beta in [0, 1), delta in (0, 1); k >= 1.
+ */
+typedef struct imin_lsbm_info {
+    int32_t returned_on;  /* 1: |ON| <= k, the answer is ON */
+    int32_t on_size;
+    int64_t reach_bound;  /* b */
+    int64_t sra_worlds;   /* N */
+    double i_hat;
+    double opt_l;
+    double theta_max;
+    double theta_0;
+    int32_t i_max;
+    int32_t iterations;   /* pool doublings + 1 */
+    int64_t theta;        /* worlds per pool in the last iteration */
+    int64_t cov1;         /* Cov(B_L) on pool 1 */
+    int64_t cov2;         /* Cov(B_L) on pool 2 */
+    int64_t cov_upper;    /* min_i cov_upper on pool 1 */
+    double sigma_l;
+    double sigma_u;
+    double a1;
+} imin_lsbm_info_t;
+
+imin_status_t imin_lsbm(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, double eps,
+                        double beta, double delta, uint64_t rng_seed, void* stream, int32_t* blockers,
+                        int32_t* n_selected, imin_lsbm_info_t* info);
 
 /*
  * Scratch device memory of imin_solve and imin_evaluate comes from a block

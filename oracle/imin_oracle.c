@@ -988,3 +988,40 @@ int oracle_world_sizes(int32_t n, int64_t m, const int64_t* row_ptr, const int32
     free(blk);
     return st;
 }
+
+/* Public: the marginal coverage of every node given B over the CP sequences */
+/* of worlds [0, theta): marg[v] = Cov(B + v) - Cov(B) for v not in B (0 for */
+/* seeds and for B), and *cov = Cov(B) (Section 4.1).                         */
+int oracle_cover_marginals(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                           const int32_t* seeds, int32_t n_seeds, const int32_t* blockers, int32_t n_blockers,
+                           uint64_t theta, uint64_t rng_seed, int nthreads, int64_t* marg, int64_t* cov) {
+    if (theta < 1 || n_blockers < 0) return -1;
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > theta) nthreads = (int)theta;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    uint8_t* in_b = calloc((size_t)n, 1);
+    if (!is_seed || !in_b) { free(is_seed); free(in_b); return -1; }
+    for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+    int bad = 0;
+    for (int32_t i = 0; i < n_blockers; ++i) {
+        if (blockers[i] < 0 || blockers[i] >= n) bad = 1;
+        else in_b[blockers[i]] = 1;
+    }
+    cov_job_t* jobs = bad ? NULL : cov_build(&q, is_seed, theta, nthreads, 1);
+    if (!jobs) { free(is_seed); free(in_b); return -1; }
+    for (int t = 0; t < nthreads; ++t) jobs[t].in_b = in_b;
+    run_jobs(jobs, nthreads, cov_mark_job);
+    *cov = 0;
+    for (int t = 0; t < nthreads; ++t) *cov += jobs[t].count;
+    run_jobs(jobs, nthreads, cov_marg_job);
+    memset(marg, 0, (size_t)n * sizeof(int64_t));
+    for (int t = 0; t < nthreads; ++t)
+        for (int32_t v = 0; v < n; ++v) marg[v] += jobs[t].marg[v];
+    for (int32_t v = 0; v < n; ++v)
+        if (in_b[v]) marg[v] = 0;
+    cov_free_jobs(jobs, nthreads);
+    free(is_seed); free(in_b);
+    return 0;
+}

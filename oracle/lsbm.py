@@ -5,14 +5,14 @@ tests and the CPU leg of the benchmark, never by the library.
 
 Every step follows Section 5.1 in the paper's order and notation:
 
-* ON, the out-neighbours of S (edges with p > 0, seeds left out); when
-  |ON| <= k the answer is ON itself.
+* ON, the out-neighbours of S (over edges the sampler can draw live, i.e.
+  with threshold above 0; seeds left out); when |ON| <= k the answer is ON.
 * I_hat, an estimate of E[I_G(s)] with (beta, delta/6) relative accuracy.  The
   paper delegates this to a generalised stopping rule it does not print; here
   it is the Stopping Rule Algorithm of Dagum, Karp, Luby and Ross ("An optimal
   algorithm for Monte Carlo estimation", SIAM J. Comput. 2000) applied to
-  Z = |R_w| / b, where b (the nodes reachable from S over edges with p > 0)
-  bounds every world's spread so that Z lies in [0, 1].
+  Z = |R_w| / b, where b (the nodes reachable from S over edges that can be
+  live) bounds every world's spread so that Z lies in [0, 1].
 * OPT^L, the sum of Pr[s -> v] over the k nodes of ON most likely to be
   reached, each probability estimated by its reach frequency over the N worlds
   the stopping rule drew.
@@ -47,27 +47,33 @@ def pool_keys(rng_seed: int):
     return s, s ^ POOL2_KEY_XOR, s ^ SRA_KEY_XOR
 
 
+def _can_be_live(g) -> np.ndarray:
+    """Edges the sampler can draw live: integer threshold above 0 (an edge
+    with 0 < p < 2^-32 has threshold 0 and is never live)."""
+    return oracle.thresholds(g.p) > 0
+
+
 def out_neighbours(g, seeds) -> np.ndarray:
-    """ON: nodes a seed reaches by one edge of positive probability, not
-    themselves seeds, ascending (Algorithm 4, first step)."""
+    """ON: nodes a seed reaches by one edge that can be live, not themselves
+    seeds, ascending (Algorithm 4, first step)."""
     seeds = np.asarray(seeds, dtype=np.int64)
-    p = np.asarray(g.p, dtype=np.float32)
+    live = _can_be_live(g)
     out = []
     for u in seeds:
         a, b = int(g.row_ptr[u]), int(g.row_ptr[u + 1])
         cols = np.asarray(g.col[a:b], dtype=np.int64)
-        out.append(cols[p[a:b] > 0])
+        out.append(cols[live[a:b]])
     on = np.unique(np.concatenate(out)) if out else np.zeros(0, np.int64)
     return np.setdiff1d(on, seeds).astype(np.int32)
 
 
 def reach_bound(g, seeds) -> int:
-    """b: nodes reachable from S (seeds included) over edges with p > 0, found
-    level by level."""
+    """b: nodes reachable from S (seeds included) over edges that can be live,
+    found level by level."""
     n = int(g.n)
     row_ptr = np.asarray(g.row_ptr, dtype=np.int64)
     col = np.asarray(g.col, dtype=np.int64)
-    pos = np.asarray(g.p, dtype=np.float32) > 0
+    pos = _can_be_live(g)
     seen = np.zeros(n, dtype=bool)
     frontier = np.unique(np.asarray(seeds, dtype=np.int64))
     seen[frontier] = True

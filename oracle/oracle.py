@@ -66,6 +66,8 @@ def _load():
         lib.oracle_reach_counts.restype = ctypes.c_int
         lib.oracle_world_sizes.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, u64, ctypes.c_int, P]
         lib.oracle_world_sizes.restype = ctypes.c_int
+        lib.oracle_cover_marginals.argtypes = [i32, i64, P, P, P, P, i32, P, i32, u64, u64, ctypes.c_int, P, P]
+        lib.oracle_cover_marginals.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -244,3 +246,17 @@ class Query:
         if st != 0:
             raise ValueError("oracle_world_sizes rejected the query")
         return out
+
+    def cover_marginals(self, blockers, theta: int, rng_seed: int, threads: int | None = None):
+        """(marg int64[n], Cov(B)): the marginal coverage of every node given B
+        (0 on B and the seeds) over the CP sequences of worlds [0, theta)."""
+        lib = _load()
+        b = np.ascontiguousarray(blockers, dtype=np.int32)
+        marg = np.zeros(self.n, dtype=np.int64)
+        cov = np.zeros(1, dtype=np.int64)
+        st = lib.oracle_cover_marginals(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                        _ptr(self.seeds), len(self.seeds), _ptr(b), len(b), theta, rng_seed,
+                                        threads or default_threads(), _ptr(marg), _ptr(cov))
+        if st != 0:
+            raise ValueError("oracle_cover_marginals rejected the query")
+        return marg, int(cov[0])

@@ -34,6 +34,20 @@ class Query(ctypes.Structure):
                 ("status", ctypes.c_int32), ("device_flags", ctypes.c_uint32)]
 
 
+class LsbmInfo(ctypes.Structure):
+    """imin_lsbm_info_t: every intermediate quantity of an LSBM call."""
+    _fields_ = [("returned_on", ctypes.c_int32), ("on_size", ctypes.c_int32),
+                ("reach_bound", ctypes.c_int64), ("sra_worlds", ctypes.c_int64),
+                ("i_hat", ctypes.c_double), ("opt_l", ctypes.c_double),
+                ("theta_max", ctypes.c_double), ("theta_0", ctypes.c_double),
+                ("i_max", ctypes.c_int32), ("iterations", ctypes.c_int32), ("theta", ctypes.c_int64),
+                ("cov1", ctypes.c_int64), ("cov2", ctypes.c_int64), ("cov_upper", ctypes.c_int64),
+                ("sigma_l", ctypes.c_double), ("sigma_u", ctypes.c_double), ("a1", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class IminError(RuntimeError):
     def __init__(self, status: int, message: str, flags: int = 0):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message} (device flags 0x{flags:x})")
@@ -107,6 +121,17 @@ def load():
     lib.imin_probe_philox.restype = st
     lib.imin_probe_copy.argtypes = [P, P, ctypes.c_size_t, i32, P, ctypes.POINTER(ctypes.c_float)]
     lib.imin_probe_copy.restype = st
+    lib.imin_graph_export.argtypes = [P, P, P, P]
+    lib.imin_graph_export.restype = st
+    lib.imin_max_coverage.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P, P]
+    lib.imin_max_coverage.restype = st
+    lib.imin_coverage.argtypes = [P, P, i32, P, i32, i64, u64, P, P]
+    lib.imin_coverage.restype = st
+    lib.imin_reach_counts.argtypes = [P, P, i32, i64, i64, u64, P, P, P]
+    lib.imin_reach_counts.restype = st
+    lib.imin_lsbm.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, u64, P, P, P,
+                              ctypes.POINTER(LsbmInfo)]
+    lib.imin_lsbm.restype = st
     _lib = lib
     return lib
 
@@ -548,3 +573,89 @@ def probe_copy(dst, src, grid: int) -> float:
     ms = ctypes.c_float()
     _check(load().imin_probe_copy(_ptr(dst), _ptr(src), nbytes, int(grid), _stream(src.device), ctypes.byref(ms)))
     return float(ms.value)
+
+
+# ------------------------------------------------------ lower-bound coverage
+def graph_export(graph: Graph):
+    """(row_ptr int64[n+1], col int32[m], thr uint32[m]) of the handle (imin_graph_export)."""
+    lib = load()
+    row_ptr = np.zeros(graph.n + 1, dtype=np.int64)
+    col = np.zeros(max(graph.m, 1), dtype=np.int32)
+    thr = np.zeros(max(graph.m, 1), dtype=np.uint32)
+    _check(lib.imin_graph_export(graph.handle, row_ptr.ctypes.data_as(ctypes.c_void_p),
+                                 col.ctypes.data_as(ctypes.c_void_p), thr.ctypes.data_as(ctypes.c_void_p)))
+    return row_ptr, col[:graph.m], thr[:graph.m]
+
+
+def max_coverage(graph: Graph, seeds, k: int, theta: int, rng_seed: int) -> dict:
+    """Max-Coverage over the CP sequences of worlds [0, theta) (imin_max_coverage):
+    dict(blockers, gains, cov, cov_upper, n_selected), cov and cov_upper over
+    the prefixes B_0 .. B_{n_selected}."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    gains = torch.zeros(max(k, 1), dtype=torch.int64, device=dev)
+    cov = torch.zeros(k + 1, dtype=torch.int64, device=dev)
+    cu = torch.zeros(k + 1, dtype=torch.int64, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_max_coverage(graph.handle, _ptr(s), int(s.numel()), int(k), int(theta),
+                                     int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(blockers), _ptr(gains),
+                                     _ptr(cov), _ptr(cu), _ptr(nsel)))
+    r = int(nsel.cpu()[0])
+    return dict(blockers=blockers.cpu().numpy()[:r], gains=gains.cpu().numpy()[:r],
+                cov=cov.cpu().numpy()[:r + 1], cov_upper=cu.cpu().numpy()[:r + 1], n_selected=r)
+
+
+def coverage(graph: Graph, seeds, blockers, theta: int, rng_seed: int) -> int:
+    """Cov(blockers) over the CP sequences of worlds [0, theta) (imin_coverage)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    b = np.asarray(blockers, dtype=np.int32)
+    bd = _dev(b, torch.int32, dev) if b.size else None
+    out = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_coverage(graph.handle, _ptr(s), int(s.numel()), _ptr(bd), int(b.size), int(theta),
+                                 int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(out)))
+    return int(out.cpu()[0])
+
+
+def reach_counts(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, per_world: bool = False):
+    """Per-node reach counts over worlds [w_begin, w_begin + w_count)
+    (imin_reach_counts); with per_world also |R_w| per world."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    counts = torch.zeros(graph.n, dtype=torch.int64, device=dev)
+    ws = torch.zeros(w_count, dtype=torch.int32, device=dev) if per_world else None
+    with torch.cuda.device(dev):
+        _check(lib.imin_reach_counts(graph.handle, _ptr(s), int(s.numel()), int(w_begin), int(w_count),
+                                     int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(counts), _ptr(ws)))
+    if per_world:
+        return counts.cpu().numpy(), ws.cpu().numpy()
+    return counts.cpu().numpy()
+
+
+def lsbm(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, delta: float | None = None,
+         rng_seed: int = 0) -> dict:
+    """LSBM, Algorithm 4 (imin_lsbm): dict(blockers, n_selected, info)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    if delta is None:
+        delta = 1.0 / graph.n
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = LsbmInfo()
+    with torch.cuda.device(dev):
+        _check(lib.imin_lsbm(graph.handle, _ptr(s), int(s.numel()), int(k), float(eps), float(beta), float(delta),
+                             int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(blockers), _ptr(nsel),
+                             ctypes.byref(info)))
+    r = int(nsel.cpu()[0])
+    return dict(blockers=blockers.cpu().numpy()[:r], n_selected=r, info=info.as_dict())

@@ -462,7 +462,7 @@ struct Session {
     // HBM-tier slots: tier 2's hold worlds of up to 2^16 nodes and 2^16
     // extra edges (many slots), tier 3's any world of the graph (a few)
     struct Slots {
-        DevArray<int32_t> lid, nodes, parent, idom, aux, lvl, xv, xu;
+        DevArray<int32_t> lid, nodes, parent, idom, aux, tin, lvl, xv, xu;
         DevArray<uint32_t> vis;
         imin::BigSlots bs{};
         bool ready() const { return lid.p != nullptr; }
@@ -493,6 +493,12 @@ struct Session {
     // nothing is read back or waited for on the host.
     bool ws = false;
     TimedLaunches timed;
+    // lower-bound coverage: the worlds' dominator trees as the store
+    // (kCoverStore), or the coverage of the marked set cover_mark counted
+    // per world (kCoverCount); unit_counts: every entry counts 1 (reach counts)
+    int cover = imin::kCoverNone;
+    const uint32_t* cover_mark = nullptr;
+    int unit_counts = 0;
 
     Session(const imin::GraphDev& gd, hipStream_t st, imin_graph* h = nullptr) : g(gd), s(st), gh(h) {}
     imin_graph* gh;  // per-graph scratch hints (may be null)
@@ -738,10 +744,13 @@ struct Session {
     bool tier3_possible() const { return g.n > t2_lid_cap() || std::max<int64_t>(g.m, 1) > t2_xcap(); }
 
     // bytes of one HBM-tier slot: node -> local id, the visited bitset, four
-    // per-node arrays and the level offsets, and two extra-edge arrays
+    // per-node arrays (five with the coverage store's preorder indexes) and
+    // the level offsets, and two extra-edge arrays
     size_t slot_bytes(int32_t lid_cap, int64_t xcap) const {
         const size_t n = (size_t)g.n;
-        return n * 4 + (n + 31) / 32 * 4 + 4 * (size_t)lid_cap * 4 + ((size_t)lid_cap + 3) * 4 + 2 * (size_t)xcap * 4;
+        const size_t per_node = cover == imin::kCoverStore ? 5 : 4;
+        return n * 4 + (n + 31) / 32 * 4 + per_node * (size_t)lid_cap * 4 + ((size_t)lid_cap + 3) * 4 +
+               2 * (size_t)xcap * 4;
     }
     size_t t2_slot_bytes() const { return slot_bytes(t2_lid_cap(), t2_xcap()); }
     size_t t3_slot_bytes() const { return slot_bytes(g.n, std::max<int64_t>(g.m, 1)); }
@@ -785,6 +794,7 @@ struct Session {
         if ((e = S.parent.alloc(slots * lc)) != hipSuccess) return e;
         if ((e = S.idom.alloc(slots * lc)) != hipSuccess) return e;
         if ((e = S.aux.alloc(slots * lc)) != hipSuccess) return e;
+        if (cover == imin::kCoverStore && (e = S.tin.alloc(slots * lc)) != hipSuccess) return e;
         if ((e = S.lvl.alloc(slots * (lc + 3))) != hipSuccess) return e;
         if ((e = S.xv.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
         if ((e = S.xu.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
@@ -795,6 +805,7 @@ struct Session {
         S.bs.parent = S.parent.p;
         S.bs.idom = S.idom.p;
         S.bs.aux = S.aux.p;
+        S.bs.tin = S.tin.p;
         S.bs.lvl = S.lvl.p;
         S.bs.xv = S.xv.p;
         S.bs.xu = S.xu.p;
@@ -999,7 +1010,7 @@ struct Session {
 
     // room for `more` entries after the store's `used` ones
     bool ensure_store(unsigned long long used, unsigned long long more) {
-        if (replay) {
+        if (replay || cover == imin::kCoverStore) {
             DevArray<int32_t>* arrs[4] = {&store_node, &store_cnt, &store_par, &store_lab};
             return grow_store(arrs, used, used + more, store_budget);
         }
@@ -1102,6 +1113,9 @@ struct Session {
         out.xstore_len = xstore_len.p;
         out.work = work.p;
         out.work_stride = work_stride;
+        out.cover = cover;
+        out.mark = cover_mark;
+        out.unit_counts = unit_counts;
         return out;
     }
 
@@ -1219,6 +1233,9 @@ struct Session {
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
             const bool keep = store_mode && incremental && replay;
+            // entries carry parents and labels (replay) or parent positions
+            // and subtree sizes (coverage store)
+            const bool four = keep || cover == imin::kCoverStore;
             imin::TileOut out = tile_out();
             out.world_size = ws_out ? ws_out + done : world_size.p;
             out.world_sum = wsum_out ? wsum_out + done : nullptr;
@@ -1256,10 +1273,12 @@ struct Session {
                 big_cap = std::max<size_t>(big_cap, (size_t)(bc + bc / 8 + 1024));
                 IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
                 IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
-                if (keep) {
-                    xbig_cap = std::max<size_t>(xbig_cap, (size_t)(xc + xc / 8 + 1024));
+                if (four) {
                     IMIN_TRY(scr_par.alloc(scr_node.count));
                     IMIN_TRY(scr_lab.alloc(scr_node.count));
+                }
+                if (keep) {
+                    xbig_cap = std::max<size_t>(xbig_cap, (size_t)(xc + xc / 8 + 1024));
                     IMIN_TRY(xscr_v.alloc(tile_cap * xslot_cap0 + xbig_cap));
                     IMIN_TRY(xscr_u.alloc(tile_cap * xslot_cap0 + xbig_cap));
                 }
@@ -1276,9 +1295,11 @@ struct Session {
                 store_cnt.swap(scr_cnt);
                 store_off.swap(wloc);
                 store_len.swap(wlen);
-                if (keep) {
+                if (four) {
                     store_par.swap(scr_par);
                     store_lab.swap(scr_lab);
+                }
+                if (keep) {
                     xstore_v.swap(xscr_v);
                     xstore_u.swap(xscr_u);
                     xstore_off.swap(xloc);
@@ -1317,7 +1338,7 @@ struct Session {
                 cs.src[1] = scr_cnt.p;
                 cs.src[2] = scr_par.p;
                 cs.src[3] = scr_lab.p;
-                cs.nf = use_x ? 4 : 2;
+                cs.nf = (use_x || cover == imin::kCoverStore) ? 4 : 2;
                 cs.src_cap = scr_node.count;
                 cs.loc = wloc.p;
                 cs.len = wlen.p;
@@ -1459,6 +1480,20 @@ imin_status_t imin_graph_info(imin_graph_t g, int32_t* n, int64_t* m) {
     if (!g) return IMIN_ERR_INVALID;
     if (n) *n = g->g.n;
     if (m) *m = g->g.m;
+    return IMIN_OK;
+}
+
+imin_status_t imin_graph_export(imin_graph_t g, int64_t* row_ptr, int32_t* col, uint32_t* thr) {
+    if (!g || !row_ptr || !col || !thr) return IMIN_ERR_INVALID;
+    const size_t n = (size_t)g->g.n, m = (size_t)g->g.m;
+    std::vector<int32_t> off(n + 1);
+    if (hipMemcpy(off.data(), g->g.off, (n + 1) * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess ||
+        (m > 0 && hipMemcpy(col, g->g.col, m * sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) ||
+        (m > 0 && hipMemcpy(thr, g->g.thr, m * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess)) {
+        (void)hipGetLastError();
+        return IMIN_ERR_DEVICE;
+    }
+    for (size_t i = 0; i <= n; ++i) row_ptr[i] = off[i];
     return IMIN_OK;
 }
 
@@ -1743,6 +1778,166 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
     return IMIN_OK;
 }
 
+// ---- lower-bound coverage (Sections 4.1 and 5.1)
+
+static imin_status_t check_coverage_args(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta) {
+    if (!g || !seeds) return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n) return IMIN_ERR_INVALID;
+    if (theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
+    return IMIN_OK;
+}
+
+static int bit_length(unsigned long long v) {
+    int b = 0;
+    while (v) {
+        ++b;
+        v >>= 1;
+    }
+    return b;
+}
+
+static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
+                                       int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
+                                       int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected) {
+    g_last_flags = 0;
+    imin_status_t st = check_coverage_args(g, seeds, n_seeds, theta);
+    if (st != IMIN_OK) return st;
+    if (!blockers || !gains || !cov || !cov_upper || !n_selected || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s, g);
+    ss.cover = imin::kCoverStore;  // before init: HBM-tier slots carry preorder indexes
+    st = ss.init((uint64_t)theta, true);
+    if (st != IMIN_OK) return st;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(ss.world_size.alloc((size_t)theta));
+    // the store of dominator trees: positions are int32 in the index
+    ss.store_budget = std::min<size_t>(env_size("IMIN_COVER_STORE_CAP", (size_t)0x7FFFFFFF), (size_t)0x7FFFFFFF);
+    IMIN_TRY(ss.store_off.alloc((size_t)theta));
+    IMIN_TRY(ss.store_len.alloc((size_t)theta));
+    IMIN_TRY(ss.list0.alloc((size_t)theta));
+    IMIN_TRY(ss.scr_par.alloc(ss.scr_node.count));
+    IMIN_TRY(ss.scr_lab.alloc(ss.scr_node.count));
+    ss.incremental = true;
+    ss.label_rule = false;
+    IMIN_TRY(imin::launch_fill_i64(cov, -1, (size_t)k + 1, s));
+    IMIN_TRY(imin::launch_fill_i64(cov_upper, -1, (size_t)k + 1, s));
+    IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+    IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, true);
+    if (st != IMIN_OK) return st;
+    if (!ss.incremental) return IMIN_ERR_NOMEM;  // the store did not fit
+    st = ss.build_index((uint64_t)theta, nullptr);
+    if (st != IMIN_OK) return st;
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+        g_last_flags = ss.hctl.p->flags;
+        return IMIN_ERR_INTERNAL;
+    }
+    DevArray<uint32_t> hist_cnt;
+    DevArray<long long> hist_sum, state;
+    DevArray<int64_t> totals;
+    IMIN_TRY(hist_cnt.alloc(imin::kTopkBins));
+    IMIN_TRY(hist_sum.alloc(imin::kTopkBins));
+    IMIN_TRY(state.alloc(4));
+    IMIN_TRY(totals.alloc((size_t)k + 1));
+    IMIN_TRY(imin::launch_fill_i32((int32_t*)hist_cnt.p, 0, imin::kTopkBins, s));
+    IMIN_TRY(imin::launch_fill_i64((int64_t*)hist_sum.p, 0, imin::kTopkBins, s));
+    imin::CoverOut co{};
+    co.cov = cov;
+    co.cov_upper = cov_upper;
+    co.t0 = ss.hctl.p->total;
+    co.k = k;
+    co.hist_cnt = hist_cnt.p;
+    co.hist_sum = hist_sum.p;
+    co.state = state.p;
+    const int key_bits = std::max(1, bit_length((unsigned long long)std::max<long long>(co.t0, 1)));
+    const imin::SelectOut so = ss.select_out(k, blockers, gains, totals.p, n_selected);
+    const imin::TileOut out = ss.tile_out();
+    const int grid = std::min<int>(ss.dsz_n, cu_count() * 8);
+    for (int32_t r = 0; r <= k; ++r) {
+        IMIN_TRY(imin::launch_cover_round(g->g, ss.gain.p, ss.ctl.p, so, co, r, key_bits, out, ss.idx_off.p,
+                                          ss.idx_ent.p, ss.dsz.p, ss.dsz_n, grid, s));
+        if ((r & 31) == 31 || r == k) {
+            st = ss.read_ctl();
+            if (st != IMIN_OK) return st;
+            if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+                g_last_flags = ss.hctl.p->flags;
+                return IMIN_ERR_INTERNAL;
+            }
+            if (ss.hctl.p->stop) break;
+        }
+    }
+    ss.finish();
+    return IMIN_OK;
+}
+
+static imin_status_t coverage_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set,
+                                   int32_t n_set, int64_t theta, uint64_t rng_seed, void* stream, int64_t* covered) {
+    g_last_flags = 0;
+    imin_status_t st = check_coverage_args(g, seeds, n_seeds, theta);
+    if (st != IMIN_OK) return st;
+    if (!covered || n_set < 0 || (n_set > 0 && !set)) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s, g);
+    ss.cover = imin::kCoverCount;
+    st = ss.init((uint64_t)theta, false);
+    if (st != IMIN_OK) return st;
+    // the marked set, checked as a blocked set would be (in range, no seed)
+    DevArray<uint32_t> mark;
+    IMIN_TRY(mark.alloc(((size_t)g->g.n + 31) / 32));
+    IMIN_TRY(imin::launch_query_setup(g->g, seeds, n_seeds, set, n_set, mark.p, ss.ctl.p, s));
+    ss.cover_mark = mark.p;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+    IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    st = ss.evaluate(q, 0, (uint64_t)theta, nullptr, nullptr, nullptr);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(hipMemcpyAsync(covered, &ss.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+        g_last_flags = ss.hctl.p->flags;
+        return IMIN_ERR_INTERNAL;
+    }
+    ss.finish();
+    return IMIN_OK;
+}
+
+static imin_status_t reach_counts_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t w_begin,
+                                       int64_t w_count, uint64_t rng_seed, void* stream, int64_t* counts,
+                                       int32_t* world_size) {
+    g_last_flags = 0;
+    if (!g || !seeds || !counts) return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n) return IMIN_ERR_INVALID;
+    if (w_begin < 0 || w_count < 1 || w_begin + w_count > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s, g);
+    ss.unit_counts = 1;
+    imin_status_t st = ss.init((uint64_t)w_count, false);
+    if (st != IMIN_OK) return st;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+    IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    st = ss.evaluate(q, (uint64_t)w_begin, (uint64_t)w_count, world_size, nullptr, nullptr);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(hipMemcpyAsync(counts, ss.gain.p, (size_t)g->g.n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+        g_last_flags = ss.hctl.p->flags;
+        return IMIN_ERR_INTERNAL;
+    }
+    ss.finish();
+    return IMIN_OK;
+}
+
 // No C++ exception crosses the boundary: host allocations that fail inside a
 // call end it with IMIN_ERR_NOMEM (its session drains its stream while
 // unwinding).
@@ -1802,6 +1997,42 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     try {
         return evaluate_impl(g, seeds, n_seeds, blocked, n_blocked, w_begin, w_count, rng_seed, stream, gain, total,
                              world_size, world_sum, world_edges);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_max_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                                uint64_t rng_seed, void* stream, int32_t* blockers, int64_t* gains, int64_t* cov,
+                                int64_t* cov_upper, int32_t* n_selected) {
+    try {
+        return max_coverage_impl(g, seeds, n_seeds, k, theta, rng_seed, stream, blockers, gains, cov, cov_upper,
+                                 n_selected);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set, int32_t n_set,
+                            int64_t theta, uint64_t rng_seed, void* stream, int64_t* covered) {
+    try {
+        return coverage_impl(g, seeds, n_seeds, set, n_set, theta, rng_seed, stream, covered);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_reach_counts(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t w_begin,
+                                int64_t w_count, uint64_t rng_seed, void* stream, int64_t* counts,
+                                int32_t* world_size) {
+    try {
+        return reach_counts_impl(g, seeds, n_seeds, w_begin, w_count, rng_seed, stream, counts, world_size);
     } catch (const std::bad_alloc&) {
         return IMIN_ERR_NOMEM;
     } catch (...) {

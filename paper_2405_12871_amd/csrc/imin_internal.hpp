@@ -99,6 +99,7 @@ struct BigSlots {
     int32_t* parent;   // [slots][lid_cap]
     int32_t* idom;     // [slots][lid_cap]
     int32_t* aux;      // [slots][lid_cap]
+    int32_t* tin;      // [slots][lid_cap] dominator-tree preorder indexes (coverage store)
     int32_t* lvl;      // [slots][lid_cap+3]
     int32_t* xv;       // [slots][xcap]
     int32_t* xu;       // [slots][xcap]
@@ -199,7 +200,42 @@ struct TileOut {
     // (kernel, workgroup); summed and cleared by the selection.
     long long* dsz;
     int32_t dsz_off[7];   // slot ranges of tier 0, 1, 2, replay, label rule, wide replay, tier 3
+    // Lower-bound coverage (kCover*): worlds are sampled without blockers and
+    // their dominator trees kept (kCoverStore) or met against a set of
+    // marked nodes (kCoverCount); unit_counts makes every entry count 1, so
+    // that the reduced gains are per-node reach counts.
+    int cover;
+    const uint32_t* mark;  // [n bits] kCoverCount: the set whose coverage is counted
+    int unit_counts;
 };
+
+// World outputs for lower-bound coverage.
+enum : int {
+    kCoverNone = 0,
+    // entries in dominator-tree preorder: node, count (the subtree size, the
+    // node's marginal coverage so far), the parent's position in the world
+    // (-1 under a seed or the super-source) in scr_par and the subtree size
+    // in scr_lab, so that a node's subtree is the run of entries
+    // [position, position + size)
+    kCoverStore = 1,
+    // no entries: world_size gets the number of non-seeds whose CP set meets
+    // the marked set
+    kCoverCount = 2
+};
+
+// Coverage greedy state per round (device): the top-k search over the gains
+// and the coverage of each prefix of the selection.
+struct CoverOut {
+    int64_t* cov;        // [k+1] Cov(B_r), -1 where round r was never reached
+    int64_t* cov_upper;  // [k+1] Cov(B_r) + sum of the k largest marginals given B_r
+    long long t0;        // sum of |R_w| over the pool (Cov(B_r) = t0 - total)
+    int32_t k;
+    uint32_t* hist_cnt;  // [kTopkBins]
+    long long* hist_sum; // [kTopkBins]
+    long long* state;    // [4]: prefix, k remaining, sum of the bins above, matched total
+};
+constexpr int kTopkBits = 10;
+constexpr int kTopkBins = 1 << kTopkBits;
 
 // A compaction job: per-item ranges of up to four 32-bit fields are packed
 // densely into the destination, one counter update per workgroup.
@@ -370,6 +406,18 @@ hipError_t launch_sum_sizes(const int32_t* world_size, uint32_t count, RoundCtl*
 // next incremental round's search does.
 hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, const SelectOut& so, long long* dsz,
                          int32_t dsz_n, bool combine, hipStream_t s);
+
+// Coverage greedy, round r (all enqueued; every kernel returns at once after
+// the selection stopped): the selection over the coverage marginals (ties to
+// the smaller id; it stops when the best marginal is 0 or r == k), Cov(B_r)
+// into co.cov[r], the sum of the k largest marginals into co.cov_upper[r],
+// then the coverage update of the pick: in each world whose entry for it is
+// still uncovered its subtree's entries are covered and its ancestors lose
+// its count.  dsz (dsz_n slots, grid <= dsz_n) carries the newly covered
+// counts to the next round's selection.  key_bits bounds every gain.
+hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, const SelectOut& so,
+                              const CoverOut& co, int r, int key_bits, const TileOut& out, const int32_t* idx_off,
+                              const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, hipStream_t s);
 
 
 // An enqueued solve in a given workspace (imin_solve with a workspace),

@@ -62,6 +62,7 @@ struct WorldShared {
     long long edges;  // CSR slots of reached rows
     int ndelta;       // count changes reported (incremental rounds)
     int nlevels;      // BFS levels holding nodes
+    int covered;      // non-seeds whose CP set meets the marked set (coverage count)
     unsigned long long in_bytes;  // algorithmic bytes read by the BFS phase
     unsigned long long acc_worlds, acc_edges, acc_bytes;  // this workgroup's work so far
     unsigned long long acc_reached, acc_live;  // reached nodes (seeds included) and recorded live edges
@@ -254,10 +255,15 @@ struct HbmStore {
             xu_s[x] = xu_[x];
         }
     }
-    static constexpr bool kLabels = false;  // worlds of this tier carry no labels
-    __device__ int32_t* cur_ptr(int) { return nullptr; }
-    __device__ void set_tin(int, int) {}
-    __device__ int get_tin(int) const { return 0; }
+    // Worlds of this tier carry no labels for the incremental rounds.  The
+    // coverage store still places them in dominator-tree preorder: the
+    // preorder index in tin_, the placement cursors in parent_ (the BFS
+    // parents are not needed once the dominators are known).
+    static constexpr bool kLabels = false;
+    int32_t* tin_;
+    __device__ int32_t* cur_ptr(int lid) { return &parent_[lid]; }
+    __device__ void set_tin(int lid, int v) { tin_[lid] = v; }
+    __device__ int get_tin(int lid) const { return tin_[lid]; }
     // clear the bitset for the next world: whole when it is in LDS or the
     // world ran out of room (claimed nodes past lid_cap are not listed),
     // else the words of the world's reached nodes
@@ -677,6 +683,31 @@ __device__ void world_exits(const QueryDev& q, Store& st, WorldShared<NT>& sh) {
     exits_merge<NT>(ns, st, sh);
 }
 
+// Coverage of a marked set in one world (Section 4.1): a non-seed's CP set
+// is its chain of non-seed dominators up to and including itself, so it
+// meets the marked set when the node is marked or its immediate dominator's
+// set does.  Levels are walked shallowest first (a dominator lies on a
+// shallower level); the flags replace the subtree sizes in aux, and their
+// sum goes to sh.covered.
+template <int NT, class Store>
+__device__ void world_cover_marks(const QueryDev& q, const TileOut& out, Store& st, WorldShared<NT>& sh) {
+    const int t = threadIdx.x;
+    const int ns = q.n_seeds;
+    for (int L = 1; L < sh.nlevels; ++L) {
+        for (int v = st.lvl[L] + t; v < st.lvl[L + 1]; v += NT) {
+            const uint32_t u = (uint32_t)st.node(v);
+            const int p = st.get_idom(v);
+            const bool m = ((out.mark[u >> 5] >> (u & 31u)) & 1u) != 0u;
+            *st.aux_ptr(v) = (m || (p >= ns && *st.aux_ptr(p) != 0)) ? 1 : 0;
+        }
+        __syncthreads();
+    }
+    long long c = 0;
+    for (int i = ns + t; i < sh.count; i += NT) c += *st.aux_ptr(i);
+    c = block_sum_ll<NT>(c, sh.sum_tmp);
+    if (t == 0) sh.covered = (int)c;
+}
+
 // Phase 3 of a sampled world: the outputs of the mode.
 template <int NT, int TIER, class Store>
 __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi, const TileOut& out,
@@ -685,7 +716,7 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
     const int ns = q.n_seeds;
     const int R = sh.count;
     const int nx = sh.n_extra;
-    const int len = R - ns;
+    const int len = (out.cover == kCoverCount) ? 0 : R - ns;  // entries written
     int read_len = 0;  // stored entries read back (incremental rounds)
     if (out.mode == kModeDelta) {
         // The stored list keeps the round-0 order; an entry whose count is 0
@@ -728,10 +759,26 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
         }
         __syncthreads();
         const unsigned long long off = sh.pair_base;
-        if (off + (unsigned long long)len <= out.scr_cap) {
+        if (off + (unsigned long long)len <= out.scr_cap && out.cover == kCoverStore) {
+            // dominator-tree preorder: a subtree is a run of entries
+            for (int i = t; i < len; i += NT) {
+                const int lid = ns + i;
+                const int at = st.get_tin(lid);
+                const int p = st.get_idom(lid);
+                const int c = *st.aux_ptr(lid);
+                out.scr_node[off + at] = st.node(lid);
+                out.scr_cnt[off + at] = c;
+                out.scr_par[off + at] = (p >= ns) ? st.get_tin(p) : -1;
+                out.scr_lab[off + at] = (uint32_t)c;
+            }
+            if (t == 0) {
+                out.wloc[wi] = (int64_t)off;
+                out.wlen[wi] = len;
+            }
+        } else if (off + (unsigned long long)len <= out.scr_cap) {
             for (int i = t; i < len; i += NT) {
                 out.scr_node[off + i] = st.node(ns + i);
-                out.scr_cnt[off + i] = *st.aux_ptr(ns + i);
+                out.scr_cnt[off + i] = out.unit_counts ? 1 : *st.aux_ptr(ns + i);
                 if (out.keep_edges) {
                     out.scr_par[off + i] = st.get_parent(ns + i);
                     // A world without labels stores every entry with its exit
@@ -790,7 +837,7 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
     }
     if (t == 0) {
         if (out.mode == kModeDelta) sh.acc_dsize += (long long)out.world_size[wi] - (long long)R;
-        if (out.world_size) out.world_size[wi] = R;
+        if (out.world_size) out.world_size[wi] = (out.cover == kCoverCount) ? sh.covered : R;
         if (out.world_sum) out.world_sum[wi] = s + q.seed_sum;
         if (out.world_edges) out.world_edges[wi] = sh.edges;
         unsigned long long bytes = sh.in_bytes;
@@ -816,10 +863,16 @@ __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* c
                                const TileOut& out, Store& st, WorldShared<NT>& sh) {
     if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
     world_counts<NT>(q, ctl, st, sh);
-    if constexpr (Store::kLabels) {
-        if (out.keep_edges && out.mode != kModeDelta) {  // uniform
-            world_labels<NT>(q, st, sh);
-            if (sh.n_extra > 0) world_exits<NT>(q, st, sh);
+    if (out.cover == kCoverStore) {  // uniform
+        world_labels<NT>(q, st, sh);
+    } else if (out.cover == kCoverCount) {
+        world_cover_marks<NT>(q, out, st, sh);
+    } else {
+        if constexpr (Store::kLabels) {
+            if (out.keep_edges && out.mode != kModeDelta) {  // uniform
+                world_labels<NT>(q, st, sh);
+                if (sh.n_extra > 0) world_exits<NT>(q, st, sh);
+            }
         }
     }
     world_outputs<NT, TIER>(q, ctl, w, wi, out, st, sh);
@@ -950,6 +1003,7 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q_i
     st.parent_ = bs.parent + slot * lc;
     st.idom_ = bs.idom + slot * lc;
     st.aux = bs.aux + slot * lc;
+    st.tin_ = bs.tin ? bs.tin + slot * lc : nullptr;  // only the coverage store uses it
     st.lvl = bs.lvl + slot * (lc + 3);
     st.xv = bs.xv + slot * (size_t)bs.xcap;
     st.xu_ = bs.xu + slot * (size_t)bs.xcap;

@@ -368,3 +368,21 @@ def test_lsbm_end_to_end(oracle_mod):
     assert res["blockers"].tolist() == mc["blockers"].tolist()
     assert last["cov2"] == q.coverage(mc["blockers"], last["theta"], k2)
     assert last["cov1"] <= last["cov_upper"]
+
+
+def test_cover_marginals_match_the_greedy(oracle_mod):
+    """Marginals given each greedy prefix: their argmax (ties to the smaller id)
+    is the next pick, their maximum its gain, and the k largest plus Cov(B_r)
+    the upper-bound term; Cov(B_r) itself matches."""
+    g = synth.random_small_graph(200, 900, seed=12, prob="wc")
+    seeds = np.array([1, 77], np.int32)
+    q = oracle_mod.Query(g, seeds)
+    k, theta = 6, 300
+    res = q.max_coverage(k, theta, rng_seed=8)
+    for r in range(res["n_selected"] + 1):
+        marg, cov = q.cover_marginals(res["blockers"][:r], theta, rng_seed=8)
+        assert cov == res["cov"][r]
+        assert cov + int(np.sort(marg)[::-1][:k].sum()) == res["cov_upper"][r]
+        if r < res["n_selected"]:
+            assert int(np.argmax(marg)) == res["blockers"][r]
+            assert int(marg.max()) == res["gains"][r]
