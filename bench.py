@@ -28,11 +28,18 @@ With ``--serve N`` it replays N queries arriving at ``--rate`` per second
 5*10^4) against a server on ``--streams`` streams (``imin_server_*``), and
 reports the latency percentiles from arrival to result next to those of a
 single queue served one query at a time (each query's time measured alone).
+
+The default run also times LSBM (Algorithm 4: the stopping-rule estimate of
+the spread, OPT^L, Max-Coverage on doubling pools of CP sequences with the
+sigma bounds' stopping test) on the same graph and seeds with k = --lsbm-k,
+eps = --lsbm-eps, beta = 0.1, delta = 1/n; ``--lsbm-only`` does that alone on
+a named graph.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -178,7 +185,7 @@ def run_many(args, binding, dev):
         "higher_is_better": True,
         "data": "synthetic",
         "dtype": "u32+int64",
-        "config": {"workload": f"config B: {args.graph} weighted cascade (n={g.n}, m={g.m}), {len(queries)} queries: "
+        "config": {"workload": f"batched queries: {args.graph} weighted cascade (n={g.n}, m={g.m}), {len(queries)} queries: "
                                f"|S|~U{{10..500}}, k~U{{10..200}}, theta in {{1e4, 1e5}}, all submitted at once",
                    "streams": args.streams, "pool_GiB": args.pool_gib},
         "batch_seconds": t_par,
@@ -265,7 +272,7 @@ def run_serve(args, binding, dev):
         "higher_is_better": False,
         "data": "synthetic",
         "dtype": "u32+int64",
-        "config": {"workload": f"config V: graphs {names} (weighted cascade), {len(queries)} queries at {args.rate}/s "
+        "config": {"workload": f"served queries: graphs {names} (weighted cascade), {len(queries)} queries at {args.rate}/s "
                                f"(graph uniform, |S|~U{{10..1000}}, k~U{{10..500}}, theta=5e4)",
                    "streams": args.streams, "pool_GiB": args.pool_gib},
         "p50_ms": percentile(lat, 50) * 1e3,
@@ -314,6 +321,11 @@ def main():
     ap.add_argument("--serve", type=int, default=0, help="measure latency of this many arriving queries instead")
     ap.add_argument("--graphs", default="wc100k,wc1m,wc4m", help="graphs of --serve")
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
+    ap.add_argument("--lsbm-k", type=int, default=100, help="budget of the LSBM measurement")
+    ap.add_argument("--lsbm-eps", type=float, default=0.2, help="eps of the LSBM measurement")
+    ap.add_argument("--no-lsbm", action="store_true", help="skip the LSBM measurement")
+    ap.add_argument("--lsbm-only", action="store_true", help="measure LSBM alone on --graph")
+    ap.add_argument("--lsbm-seeds", type=int, default=10, help="uniform seeds of --lsbm-only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the estimator would shard "
@@ -333,6 +345,9 @@ def main():
         return
     if args.serve > 0:
         run_serve(args, binding, dev)
+        return
+    if args.lsbm_only:
+        run_lsbm(args, binding, dev)
         return
     cus = torch.cuda.get_device_properties(dev).multi_processor_count
     log(f"generating workload {args.workload}")
@@ -468,10 +483,62 @@ def main():
     }
     if args.solves > 0:
         res.update(solve_latency(args, binding, G, seeds_dev, k, theta, dev))
+    if not args.no_lsbm:
+        log(f"lsbm: k={args.lsbm_k} eps={args.lsbm_eps}")
+        res["lsbm"] = lsbm_measure(binding, G, seeds_dev, args.lsbm_k, args.lsbm_eps, 0.1, 1.0 / g.n, RNG_SEED)
+        log(f"  {res['lsbm']}")
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(g, seeds, theta, args.cpu_seconds, gpu_gain)
     print(json.dumps(res), flush=True)
+
+
+def lsbm_measure(binding, G, seeds_dev, k, eps, beta, delta, rng_seed, repeats=2):
+    """LSBM (Algorithm 4) wall time: the fastest of `repeats` calls; the
+    worlds it drew (stopping rule twice over N worlds, then both pools at
+    every iteration) per second."""
+    import torch
+    best, res = None, None
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = binding.lsbm(G, seeds_dev, k, eps=eps, beta=beta, delta=delta, rng_seed=rng_seed)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    info = res["info"]
+    out = {"k": k, "eps": eps, "beta": beta, "delta": delta, "seconds": best, "n_selected": res["n_selected"],
+           "returned_on": bool(info["returned_on"]), "on_size": info["on_size"]}
+    if not info["returned_on"]:
+        theta0 = int(math.ceil(info["theta_0"]))
+        pools = 2 * theta0 * ((1 << info["iterations"]) - 1)
+        worlds = 2 * info["sra_worlds"] + pools
+        out.update({"iterations": info["iterations"], "i_max": info["i_max"], "theta": info["theta"],
+                    "sra_worlds": info["sra_worlds"], "i_hat": info["i_hat"], "opt_l": info["opt_l"],
+                    "theta_0": info["theta_0"], "theta_max": info["theta_max"],
+                    "cov1": info["cov1"], "cov2": info["cov2"], "cov_upper": info["cov_upper"],
+                    "sigma_ratio": info["sigma_l"] / info["sigma_u"], "target_ratio": 1 - 1 / math.e - eps,
+                    "est_lower_bound_DL": info["cov2"] / info["theta"],
+                    "worlds_drawn": worlds, "worlds_per_s": worlds / best})
+    return out
+
+
+def run_lsbm(args, binding, dev):
+    """One JSON line: LSBM on a named graph with |S| = --lsbm-seeds uniform seeds."""
+    import torch
+    from paper_2405_12871_amd import synth
+    g = synth.named_graph(args.graph)
+    seeds = synth.seeds_uniform(g.n, args.lsbm_seeds, 7)
+    G = binding.Graph.from_synth(g, device=dev)
+    seeds_dev = torch.as_tensor(seeds).to(dev)
+    log(f"lsbm on {args.graph}: n={g.n} m={g.m} |S|={len(seeds)} k={args.lsbm_k}")
+    res = lsbm_measure(binding, G, seeds_dev, args.lsbm_k, args.lsbm_eps, 0.1, 1.0 / g.n, RNG_SEED)
+    log(f"  {res}")
+    print(json.dumps({"metric": "LSBM (Algorithm 4) time to solution", "value": res["seconds"], "unit": "s",
+                      "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "u32+int64",
+                      "config": {"workload": f"{args.graph}: n={g.n} m={g.m}, |S|={len(seeds)} uniform, "
+                                             f"k={args.lsbm_k}, eps={args.lsbm_eps}, beta=0.1, delta=1/n"},
+                      "lsbm": res}), flush=True)
 
 
 def solve_latency(args, binding, G, seeds_dev, k, theta, dev):

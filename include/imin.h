@@ -416,6 +416,114 @@ imin_status_t imin_lsbm(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, i
                         int32_t* n_selected, imin_lsbm_info_t* info);
 
 /*
+ * imin_world_sizes -- |R_w(B)| of every world in [w_begin, w_begin + w_count)
+ * with the blocked set B (Section 2.1), without dominators: the samples of
+ * the stopping rules of Algorithms 1 and 4.  blocked as for imin_evaluate;
+ * world_size: int32[w_count], device, out.  Errors as for imin_evaluate.
+ */
+imin_status_t imin_world_sizes(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                               int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed,
+                               void* stream, int32_t* world_size);
+
+/*
+ * Global Sampling (Section 4.2, Algorithm 3; Definition 4.3) and the upper
+ * bound D^U (Section 3.3).
+ *
+ * V'_s is the set of non-seed nodes reachable from S over edges that can be
+ * live (threshold > 0), ascending.  Sample i of key `key` is world i of that
+ * key; its target is v = V'_s[(r * |V'_s|) >> 32], with r word 0 of
+ * Philox4x32-10 at counter (0, i, 1, 0) and the same key (the coins use
+ * counter word 2 = 0).  Its LRR set is empty when v is not reached from S in
+ * the world, else the nodes that reach v in phi^s, the live subgraph
+ * induced by the reached non-seeds (v included).  Cov(B) over samples
+ * [0, theta) counts the sets that meet B, and |V'_s| Cov(B) / theta
+ * estimates D^U(B) without bias (Lemma 4.4).
+ *
+ * imin_vprime: V'_s into out (int32[count], device; may be NULL to ask for
+ * the count only); count: int32, HOST, out.
+ * imin_lrr_max_coverage: the procedure Max-Coverage over the LRR sets of
+ * samples [0, theta); outputs as imin_max_coverage.
+ * imin_lrr_coverage: Cov(set) over the LRR sets of samples [0, theta).
+ * The graph's in-edges and a host copy of the graph are made on a handle's
+ * first use here and kept until imin_graph_destroy.  Sampling takes 12 bytes
+ * per node per sampling slot (IMIN_LRR_BUDGET, default 4 GiB, bounds the
+ * slots).
+ */
+imin_status_t imin_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, void* stream, int32_t* out,
+                          int32_t* count);
+imin_status_t imin_lrr_max_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
+                                    int64_t theta, uint64_t key, void* stream, int32_t* blockers,
+                                    int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected);
+imin_status_t imin_lrr_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set,
+                                int32_t n_set, int64_t theta, uint64_t key, void* stream, int64_t* covered);
+
+/*
+ * imin_gsbm -- GSBM (Section 5.2): Algorithm 4's loop over LRR sets, with
+ *   theta_max = 2 |V'_s| ((1 - 1/e) sqrt(ln(6/delta)) +
+ *     sqrt((1 - 1/e)(ln C(n - |S|, k) + ln(6/delta))))^2 / (eps^2 OPT^L),
+ *   theta_0 = theta_max eps^2 OPT^L / |V'_s|, i_max and a_1 = a_2 as LSBM,
+ *   sigma^L = ((sqrt(Cov_2(B_U) + 2 a_1/9) - sqrt(a_1/2))^2 - a_1/18) |V'_s| / theta,
+ *   sigma^U = (sqrt(Cov^u_1 + a_2/2) + sqrt(a_2/2))^2 |V'_s| / theta,
+ * where the binomial follows the section's proof (n - |S| candidates), and ON
+ * and OPT^L are computed as for imin_lsbm (beta and delta set the stopping
+ * rule behind OPT^L).  Pool 1 uses key rng_seed ^ 0x2545F4914F6CDD1D, pool
+ * 2 rng_seed ^ 0x9FB21C651E98DF25.
+ *
+ * imin_lhga -- LHGA (Section 5.3): ON when |ON| <= k, else the k nodes of ON
+ * with the largest Pr[s -> v] deg(v), ties to the smaller id, with Pr[s -> v]
+ * the reach frequency over imin_lsbm's stopping-rule worlds (scores compare
+ * as count(v) * out-degree(v), exact integers; the out-degree counts CSR
+ * slots).  blockers in decreasing score order.
+ *
+ * imin_sandimin -- SandIMIN (Algorithm 1, Section 3.1): B_L = LSBM, B_U =
+ * GSBM, B_R = LHGA on the same stopping-rule worlds; for each, the
+ * (gamma, delta) estimate of E[I_{G[V \ B]}(s)] by the Stopping Rule
+ * Algorithm on |R_w(B)| / b over the worlds of key rng_seed ^
+ * 0xD6E8FEB86659FD93 (Upsilon from gamma and failure probability delta);
+ * the answer is the set with the smallest estimate (ties: L, then U, then
+ * R).  candidates: int32[3k], device, optional: B_L, B_U, B_R at offsets
+ * 0, k, 2k (their sizes in info->n_blockers).
+ */
+typedef struct imin_gsbm_info {
+    int32_t returned_on;
+    int32_t on_size;
+    int64_t nvp;          /* |V'_s| */
+    int64_t sra_worlds;   /* N of the stopping rule behind OPT^L */
+    double opt_l;
+    double theta_max;
+    double theta_0;
+    int32_t i_max;
+    int32_t iterations;
+    int64_t theta;
+    int64_t cov1;
+    int64_t cov2;
+    int64_t cov_upper;
+    double sigma_l;
+    double sigma_u;
+    double a1;
+} imin_gsbm_info_t;
+
+imin_status_t imin_gsbm(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, double eps,
+                        double beta, double delta, uint64_t rng_seed, void* stream, int32_t* blockers,
+                        int32_t* n_selected, imin_gsbm_info_t* info);
+imin_status_t imin_lhga(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, double beta,
+                        double delta, uint64_t rng_seed, void* stream, int32_t* blockers, int32_t* n_selected);
+
+typedef struct imin_sandimin_info {
+    int32_t choice;           /* 0: B_L, 1: B_U, 2: B_R */
+    int32_t n_blockers[3];
+    double estimate[3];       /* estimated E[I_{G[V \ B]}(s)] of B_L, B_U, B_R */
+    int64_t eval_worlds[3];   /* worlds each estimate drew */
+    imin_lsbm_info_t lsbm;
+    imin_gsbm_info_t gsbm;
+} imin_sandimin_info_t;
+
+imin_status_t imin_sandimin(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, double eps,
+                            double beta, double gamma, double delta, uint64_t rng_seed, void* stream,
+                            int32_t* blockers, int32_t* n_selected, int32_t* candidates,
+                            imin_sandimin_info_t* info);
+
+/*
  * Scratch device memory of imin_solve and imin_evaluate comes from a block
  * cache, per device: a block released at the end of a call stays allocated
  * for the next call (a request reuses a cached block of at most twice its

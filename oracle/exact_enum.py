@@ -151,3 +151,31 @@ def expected_lower_bound(n, src, dst, p, seeds, B):
         m1 += pr * len(lost)
         m2 += pr * len(lost) * len(lost)
     return m1, m2
+
+
+def expected_upper_bound(n, src, dst, p, seeds, B):
+    """(D^U(B), E[f^2]) exactly, where f(phi) = |M_phi(B)|, the nodes reachable
+    from B in phi^s: the live subgraph induced by the reached non-seeds
+    (Section 3.3, the upper bounding function)."""
+    B = [int(b) for b in B]
+    sset = set(int(s) for s in seeds)
+    m1 = Fraction(0)
+    m2 = Fraction(0)
+    for pr, edges, live in enumerate_worlds(n, src, dst, p):
+        base = _reach(n, edges, live, seeds, set())
+        inside = base - sset
+        adj = {}
+        for (u, v), on in zip(edges, live):
+            if on and u in inside and v in inside:
+                adj.setdefault(u, []).append(v)
+        seen = set(b for b in B if b in inside)
+        stack = list(seen)
+        while stack:
+            u = stack.pop()
+            for v in adj.get(u, ()):
+                if v not in seen:
+                    seen.add(v)
+                    stack.append(v)
+        m1 += pr * len(seen)
+        m2 += pr * len(seen) * len(seen)
+    return m1, m2

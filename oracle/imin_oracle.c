@@ -684,6 +684,11 @@ typedef struct {
     const uint8_t* in_b; /* [n] blocker flags (coverage of a given set) */
     int64_t count;     /* coverage counted by this thread */
     int status;
+    /* sets: 0 = the CP sets of every world (Section 4.1); 1 = one LRR set per */
+    /* sample (Section 4.2), its target drawn from vprime[0 .. nvp)            */
+    int kind;
+    const int32_t* vprime;
+    uint32_t nvp;
 } cov_job_t;
 
 static int grow(void** p, int64_t* cap, int64_t need, size_t elem) {
@@ -697,7 +702,11 @@ static int grow(void** p, int64_t* cap, int64_t need, size_t elem) {
     return 0;
 }
 
-/* Build every CP set of the job's worlds (Algorithm 2 on each world). */
+static int32_t world_lrr_set(const query_t* q, scratch_t* s, uint64_t w, const uint8_t* is_seed,
+                             const int32_t* vprime, uint32_t nvp, int32_t* out);
+
+/* Build every CP set of the job's worlds (Algorithm 2 on each world), or   */
+/* one LRR set per sample (Algorithm 3).                                    */
 static void* cov_build_job(void* arg) {
     cov_job_t* j = (cov_job_t*)arg;
     const query_t* q = j->q;
@@ -717,6 +726,24 @@ static void* cov_build_job(void* arg) {
     }
     j->set_off[0] = 0;
     for (uint64_t w = j->w_begin; w < j->w_end; ++w) {
+        if (j->kind == 1) {
+            /* one set: node_out holds its members */
+            int32_t len = world_lrr_set(q, &s, w, j->is_seed, j->vprime, j->nvp, node_out);
+            if (len < 0 || s.oom) { j->status = -1; break; }
+            if (len == 0) continue; /* an empty set is never covered */
+            int64_t base = j->set_off[j->n_sets];
+            if (grow((void**)&j->set_off, &off_cap, j->n_sets + 2, sizeof(int64_t)) ||
+                grow((void**)&j->cp, &cp_cap, base + len, sizeof(int32_t)) ||
+                grow((void**)&j->covered, &cov_cap, j->n_sets + 1, 1)) {
+                j->status = -1;
+                break;
+            }
+            memcpy(j->cp + base, node_out, (size_t)len * sizeof(int32_t));
+            j->set_off[j->n_sets + 1] = base + len;
+            j->covered[j->n_sets] = 0;
+            j->n_sets += 1;
+            continue;
+        }
         int32_t R = world_counts_dominator(q, &s, w);
         if (R < 0 || s.oom) { j->status = -1; break; }
         int32_t ne;
@@ -802,13 +829,17 @@ static void cov_free_jobs(cov_job_t* jobs, int nthreads) {
     free(jobs);
 }
 
-static cov_job_t* cov_build(const query_t* q, const uint8_t* is_seed, uint64_t theta, int nthreads, int with_marg) {
+static cov_job_t* cov_build_sets(const query_t* q, const uint8_t* is_seed, uint64_t theta, int nthreads,
+                                 int with_marg, int kind, const int32_t* vprime, uint32_t nvp) {
     cov_job_t* jobs = calloc((size_t)nthreads, sizeof(cov_job_t));
     if (!jobs) return NULL;
     int bad = 0;
     for (int t = 0; t < nthreads; ++t) {
         jobs[t].q = q;
         jobs[t].is_seed = is_seed;
+        jobs[t].kind = kind;
+        jobs[t].vprime = vprime;
+        jobs[t].nvp = nvp;
         jobs[t].w_begin = theta * (uint64_t)t / (uint64_t)nthreads;
         jobs[t].w_end = theta * (uint64_t)(t + 1) / (uint64_t)nthreads;
         if (with_marg && !(jobs[t].marg = malloc((size_t)q->n * sizeof(int64_t)))) bad = 1;
@@ -819,15 +850,19 @@ static cov_job_t* cov_build(const query_t* q, const uint8_t* is_seed, uint64_t t
     return jobs;
 }
 
+static cov_job_t* cov_build(const query_t* q, const uint8_t* is_seed, uint64_t theta, int nthreads, int with_marg) {
+    return cov_build_sets(q, is_seed, theta, nthreads, with_marg, 0, NULL, 0);
+}
+
 /* Public: Max-Coverage over the CP sequences of worlds [0, theta) (Section  */
 /* 5.1, procedure Max-Coverage of Algorithm 4), with the coverage of every   */
 /* prefix and its upper-bound term.  Outputs: blockers[k], gains[k] (the     */
 /* marginal coverage of each pick), cov[k+1] = Cov(B_0..B_{n_selected}),     */
 /* cov_upper[k+1] = Cov(B_i) + sum of the k largest marginals given B_i.     */
-int oracle_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
-                        const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
-                        int nthreads, int32_t* blockers, int64_t* gains, int64_t* cov, int64_t* cov_upper,
-                        int32_t* n_selected) {
+static int max_coverage_sets(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                             const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
+                             int nthreads, int kind, const int32_t* vprime, uint32_t nvp, int32_t* blockers,
+                             int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected) {
     if (k < 0 || theta < 1) return -1;
     if (check_query(n, seeds, n_seeds, NULL)) return -1;
     if (nthreads < 1) nthreads = 1;
@@ -843,7 +878,7 @@ int oracle_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int3
         return -1;
     }
     for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
-    cov_job_t* jobs = cov_build(&q, is_seed, theta, nthreads, 1);
+    cov_job_t* jobs = cov_build_sets(&q, is_seed, theta, nthreads, 1, kind, vprime, nvp);
     if (!jobs) { free(is_seed); free(in_b); free(chosen); free(marg); free(sorted); return -1; }
     for (int t = 0; t < nthreads; ++t) jobs[t].in_b = in_b;
     int64_t covered = 0;
@@ -889,10 +924,31 @@ int oracle_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int3
     return 0;
 }
 
+int oracle_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                        const int32_t* seeds, int32_t n_seeds, int32_t k, uint64_t theta, uint64_t rng_seed,
+                        int nthreads, int32_t* blockers, int64_t* gains, int64_t* cov, int64_t* cov_upper,
+                        int32_t* n_selected) {
+    return max_coverage_sets(n, m, row_ptr, col, thr, seeds, n_seeds, k, theta, rng_seed, nthreads, 0, NULL, 0,
+                             blockers, gains, cov, cov_upper, n_selected);
+}
+
+static int coverage_sets(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                         const int32_t* seeds, int32_t n_seeds, const int32_t* blockers, int32_t n_blockers,
+                         uint64_t theta, uint64_t rng_seed, int nthreads, int kind, const int32_t* vprime,
+                         uint32_t nvp, int64_t* cov);
+
 /* Public: Cov(B) over the CP sequences of worlds [0, theta) (Section 4.1). */
 int oracle_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
                     const int32_t* seeds, int32_t n_seeds, const int32_t* blockers, int32_t n_blockers,
                     uint64_t theta, uint64_t rng_seed, int nthreads, int64_t* cov) {
+    return coverage_sets(n, m, row_ptr, col, thr, seeds, n_seeds, blockers, n_blockers, theta, rng_seed, nthreads,
+                         0, NULL, 0, cov);
+}
+
+static int coverage_sets(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                         const int32_t* seeds, int32_t n_seeds, const int32_t* blockers, int32_t n_blockers,
+                         uint64_t theta, uint64_t rng_seed, int nthreads, int kind, const int32_t* vprime,
+                         uint32_t nvp, int64_t* cov) {
     if (theta < 1 || n_blockers < 0) return -1;
     if (check_query(n, seeds, n_seeds, NULL)) return -1;
     if (nthreads < 1) nthreads = 1;
@@ -907,7 +963,7 @@ int oracle_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t*
         if (blockers[i] < 0 || blockers[i] >= n) bad = 1;
         else in_b[blockers[i]] = 1;
     }
-    cov_job_t* jobs = bad ? NULL : cov_build(&q, is_seed, theta, nthreads, 0);
+    cov_job_t* jobs = bad ? NULL : cov_build_sets(&q, is_seed, theta, nthreads, 0, kind, vprime, nvp);
     if (!jobs) { free(is_seed); free(in_b); return -1; }
     for (int t = 0; t < nthreads; ++t) jobs[t].in_b = in_b;
     run_jobs(jobs, nthreads, cov_mark_job);
@@ -974,15 +1030,17 @@ int oracle_reach_counts(int32_t n, int64_t m, const int64_t* row_ptr, const int3
     return status;
 }
 
-/* Public: |R_w| of every world in [w0, w0+nw), no blockers (the samples of */
-/* the stopping-rule estimate of E[I_G(s)] in Algorithm 4).                  */
+/* Public: |R_w(B)| of every world in [w0, w0+nw) (blocked may be NULL): the */
+/* samples of the stopping-rule estimates of E[I_G(s)] in Algorithm 4 and of */
+/* E[I_{G[V\B]}(s)] in Algorithm 1.                                          */
 int oracle_world_sizes(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
-                       const int32_t* seeds, int32_t n_seeds, uint64_t rng_seed, uint64_t w0, uint64_t nw,
-                       int nthreads, int32_t* rsize) {
-    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+                       const int32_t* seeds, int32_t n_seeds, const uint8_t* blocked, uint64_t rng_seed,
+                       uint64_t w0, uint64_t nw, int nthreads, int32_t* rsize) {
+    if (check_query(n, seeds, n_seeds, blocked)) return -1;
     query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, rng_seed};
     uint8_t* blk = calloc((size_t)n, 1);
     if (!blk) return -1;
+    if (blocked) memcpy(blk, blocked, (size_t)n);
     int64_t total = 0;
     int st = run_eval(&q, blk, 0, 0, w0, nw, nthreads, NULL, &total, rsize, NULL);
     free(blk);
@@ -1024,4 +1082,118 @@ int oracle_cover_marginals(int32_t n, int64_t m, const int64_t* row_ptr, const i
     cov_free_jobs(jobs, nthreads);
     free(is_seed); free(in_b);
     return 0;
+}
+
+
+/* ======================================================================== */
+/* Global Sampling (Section 4.2, Algorithm 3; Definition 4.3).              */
+/*                                                                          */
+/*   V'_s     the non-seed nodes reachable from S in G over edges that can   */
+/*            be live (threshold > 0), ascending (the caller's vprime).      */
+/*   sample i world i of the key; its target v = vprime[(r * |V'_s|) >> 32]  */
+/*            with r = word 0 of Philox4x32-10 at counter (0, i, 1, 0) (the  */
+/*            edge coins use counter word 2 = 0, so the draws never meet).   */
+/*   LRR set  empty when v is not reached from S in world i; otherwise the  */
+/*            nodes that reach v in phi^s, the live subgraph induced by the  */
+/*            reached non-seeds (v included).                                */
+/*   Cov      sets that meet B; |V'_s| Cov(B) / theta is unbiased for the    */
+/*            upper bound D^U(B) (Lemma 4.4).                                */
+/* ======================================================================== */
+
+uint32_t oracle_lrr_pick(uint64_t key, uint64_t i, uint32_t nvp) {
+    uint32_t ctr[4] = {0u, (uint32_t)i, 1u, 0u};
+    uint32_t k[2] = {(uint32_t)key, (uint32_t)(key >> 32)};
+    uint32_t out[4];
+    oracle_philox4x32_10(ctr, k, out);
+    return (uint32_t)(((uint64_t)out[0] * (uint64_t)nvp) >> 32);
+}
+
+/* The LRR set of sample w into out (capacity n); returns its size, -1 on  */
+/* failure.                                                                 */
+static int32_t world_lrr_set(const query_t* q, scratch_t* s, uint64_t w, const uint8_t* is_seed,
+                             const int32_t* vprime, uint32_t nvp, int32_t* out) {
+    if (nvp == 0) return 0;
+    const int32_t v = vprime[oracle_lrr_pick(q->rng_seed, w, nvp)];
+    int32_t R = reach(q, s, w);
+    int32_t now = s->stamp_now;
+    if (s->stamp[v] != now) return 0; /* v is not reached: the empty set */
+    /* local ids 1..R over the reached nodes; the live edges of phi^s,      */
+    /* stored reversed (head -> tail) as a CSR over local ids               */
+    for (int32_t i = 0; i < R; ++i) s->local_of[s->queue[i]] = i + 1;
+    int64_t ne = 0;
+    for (int32_t i = 0; i < R; ++i) {
+        int32_t u = s->queue[i];
+        if (is_seed[u]) continue;
+        for (int64_t e = q->row_ptr[u]; e < q->row_ptr[u + 1]; ++e) {
+            int32_t x = q->col[e];
+            if (x == u || is_seed[x] || s->stamp[x] != now) continue;
+            if (!edge_live(q->thr[e], q->rng_seed, w, e)) continue;
+            if (push_edge(s, &ne, s->local_of[x], i + 1)) return -1;
+        }
+    }
+    int32_t N = R + 1;
+    for (int32_t x = 0; x <= N; ++x) s->pred_off[x] = 0;
+    for (int64_t i = 0; i < ne; ++i) s->pred_off[s->e_src[i] + 1]++;
+    for (int32_t x = 0; x < N; ++x) s->pred_off[x + 1] += s->pred_off[x];
+    for (int32_t x = 0; x < N; ++x) s->fill[x] = s->pred_off[x];
+    for (int64_t i = 0; i < ne; ++i) s->pred[s->fill[s->e_src[i]]++] = s->e_dst[i];
+    /* breadth-first search from v along the reversed edges */
+    int32_t* seen = s->idom;
+    for (int32_t x = 0; x < N; ++x) seen[x] = 0;
+    int32_t head = 0, tail = 0;
+    int32_t lv = s->local_of[v];
+    seen[lv] = 1;
+    s->stack[tail++] = lv;
+    while (head < tail) {
+        int32_t x = s->stack[head++];
+        for (int32_t j = s->pred_off[x]; j < s->pred_off[x + 1]; ++j) {
+            int32_t u = s->pred[j];
+            if (!seen[u]) {
+                seen[u] = 1;
+                s->stack[tail++] = u;
+            }
+        }
+    }
+    for (int32_t i = 0; i < tail; ++i) out[i] = s->queue[s->stack[i] - 1];
+    return tail;
+}
+
+/* Public: the LRR set of sample w (members in out, capacity n). */
+int32_t oracle_lrr_set(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                       const int32_t* seeds, int32_t n_seeds, uint64_t key, uint64_t w, const int32_t* vprime,
+                       uint32_t nvp, int32_t* out) {
+    if (check_query(n, seeds, n_seeds, NULL)) return -1;
+    query_t q = {n, m, row_ptr, col, thr, seeds, n_seeds, key};
+    scratch_t s;
+    if (scratch_init(&s, n, NULL)) return -1;
+    uint8_t* is_seed = calloc((size_t)n, 1);
+    int32_t r = -1;
+    if (is_seed) {
+        for (int32_t i = 0; i < n_seeds; ++i) is_seed[seeds[i]] = 1;
+        r = world_lrr_set(&q, &s, w, is_seed, vprime, nvp, out);
+        if (s.oom) r = -1;
+    }
+    free(is_seed);
+    scratch_free(&s);
+    return r;
+}
+
+/* Public: Max-Coverage over the LRR sets of samples [0, theta) (Section    */
+/* 5.2: GSBM runs the procedure of Algorithm 4 on LRR sets).  Outputs as   */
+/* oracle_max_coverage.                                                     */
+int oracle_lrr_max_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                            const int32_t* seeds, int32_t n_seeds, const int32_t* vprime, uint32_t nvp, int32_t k,
+                            uint64_t theta, uint64_t key, int nthreads, int32_t* blockers, int64_t* gains,
+                            int64_t* cov, int64_t* cov_upper, int32_t* n_selected) {
+    return max_coverage_sets(n, m, row_ptr, col, thr, seeds, n_seeds, k, theta, key, nthreads, 1, vprime, nvp,
+                             blockers, gains, cov, cov_upper, n_selected);
+}
+
+/* Public: Cov(B) over the LRR sets of samples [0, theta). */
+int oracle_lrr_coverage(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const uint32_t* thr,
+                        const int32_t* seeds, int32_t n_seeds, const int32_t* vprime, uint32_t nvp,
+                        const int32_t* blockers, int32_t n_blockers, uint64_t theta, uint64_t key, int nthreads,
+                        int64_t* cov) {
+    return coverage_sets(n, m, row_ptr, col, thr, seeds, n_seeds, blockers, n_blockers, theta, key, nthreads, 1,
+                         vprime, nvp, cov);
 }

@@ -90,11 +90,18 @@ def reach_bound(g, seeds) -> int:
     return int(seen.sum())
 
 
+def sra_upsilon(eps: float, fail: float):
+    """Upsilon = 4 (e - 2) ln(2 / fail) / eps^2 and Upsilon_1 = 1 + (1 + eps)
+    Upsilon of the Stopping Rule Algorithm (relative error eps, failure
+    probability fail)."""
+    ups = 4.0 * (E_CONST - 2.0) * math.log(2.0 / fail) / (eps * eps)
+    return ups, 1.0 + (1.0 + eps) * ups
+
+
 def sra_constants(beta: float, delta: float):
-    """Upsilon and Upsilon_1 of the Stopping Rule Algorithm for relative error
-    beta and failure probability delta / 6."""
-    ups = 4.0 * (E_CONST - 2.0) * math.log(2.0 / (delta / 6.0)) / (beta * beta)
-    return ups, 1.0 + (1.0 + beta) * ups
+    """The Stopping Rule Algorithm's constants for E[I_G(s)] in Algorithm 4:
+    relative error beta, failure probability delta / 6."""
+    return sra_upsilon(beta, delta / 6.0)
 
 
 def stopping_rule(q: "oracle.Query", key: int, b: int, beta: float, delta: float, batch: int = 1 << 16,

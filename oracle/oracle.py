@@ -64,10 +64,20 @@ def _load():
         lib.oracle_coverage.restype = ctypes.c_int
         lib.oracle_reach_counts.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, u64, ctypes.c_int, P]
         lib.oracle_reach_counts.restype = ctypes.c_int
-        lib.oracle_world_sizes.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, u64, ctypes.c_int, P]
+        lib.oracle_world_sizes.argtypes = [i32, i64, P, P, P, P, i32, P, u64, u64, u64, ctypes.c_int, P]
         lib.oracle_world_sizes.restype = ctypes.c_int
         lib.oracle_cover_marginals.argtypes = [i32, i64, P, P, P, P, i32, P, i32, u64, u64, ctypes.c_int, P, P]
         lib.oracle_cover_marginals.restype = ctypes.c_int
+        lib.oracle_lrr_pick.argtypes = [u64, u64, ctypes.c_uint32]
+        lib.oracle_lrr_pick.restype = ctypes.c_uint32
+        lib.oracle_lrr_set.argtypes = [i32, i64, P, P, P, P, i32, u64, u64, P, ctypes.c_uint32, P]
+        lib.oracle_lrr_set.restype = i32
+        lib.oracle_lrr_max_coverage.argtypes = [i32, i64, P, P, P, P, i32, P, ctypes.c_uint32, i32, u64, u64,
+                                                ctypes.c_int, P, P, P, P, P]
+        lib.oracle_lrr_max_coverage.restype = ctypes.c_int
+        lib.oracle_lrr_coverage.argtypes = [i32, i64, P, P, P, P, i32, P, ctypes.c_uint32, P, i32, u64, u64,
+                                            ctypes.c_int, P]
+        lib.oracle_lrr_coverage.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -236,12 +246,14 @@ class Query:
             raise ValueError("oracle_reach_counts rejected the query")
         return out
 
-    def world_sizes(self, rng_seed: int, w0: int, nw: int, threads: int | None = None) -> np.ndarray:
-        """int32[nw]: |R_w| of worlds [w0, w0+nw) with no blockers."""
+    def world_sizes(self, rng_seed: int, w0: int, nw: int, threads: int | None = None,
+                    blocked=()) -> np.ndarray:
+        """int32[nw]: |R_w(B)| of worlds [w0, w0+nw) with the blockers B."""
         lib = _load()
+        blk = self._blocked(blocked) if len(blocked) else None
         out = np.zeros(nw, dtype=np.int32)
         st = lib.oracle_world_sizes(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
-                                    _ptr(self.seeds), len(self.seeds), rng_seed, w0, nw,
+                                    _ptr(self.seeds), len(self.seeds), _ptr(blk), rng_seed, w0, nw,
                                     threads or default_threads(), _ptr(out))
         if st != 0:
             raise ValueError("oracle_world_sizes rejected the query")
@@ -260,3 +272,52 @@ class Query:
         if st != 0:
             raise ValueError("oracle_cover_marginals rejected the query")
         return marg, int(cov[0])
+
+    # ----------------------------------------------------- global sampling
+    def lrr_set(self, key: int, i: int, vprime) -> list:
+        """The LRR set of sample i (Algorithm 3): sorted members, [] when empty."""
+        lib = _load()
+        vp = np.ascontiguousarray(vprime, dtype=np.int32)
+        out = np.zeros(self.n, dtype=np.int32)
+        r = lib.oracle_lrr_set(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                               _ptr(self.seeds), len(self.seeds), key, i, _ptr(vp), len(vp), _ptr(out))
+        if r < 0:
+            raise ValueError("oracle_lrr_set rejected the query")
+        return sorted(int(x) for x in out[:r])
+
+    def lrr_max_coverage(self, vprime, k: int, theta: int, key: int, threads: int | None = None):
+        """Max-Coverage over the LRR sets of samples [0, theta); as max_coverage."""
+        lib = _load()
+        vp = np.ascontiguousarray(vprime, dtype=np.int32)
+        blockers = np.zeros(max(k, 1), dtype=np.int32)
+        gains = np.zeros(max(k, 1), dtype=np.int64)
+        cov = np.zeros(k + 1, dtype=np.int64)
+        cu = np.zeros(k + 1, dtype=np.int64)
+        nsel = np.zeros(1, dtype=np.int32)
+        st = lib.oracle_lrr_max_coverage(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                         _ptr(self.seeds), len(self.seeds), _ptr(vp), len(vp), k, theta, key,
+                                         threads or default_threads(), _ptr(blockers), _ptr(gains), _ptr(cov),
+                                         _ptr(cu), _ptr(nsel))
+        if st != 0:
+            raise ValueError("oracle_lrr_max_coverage rejected the query")
+        r = int(nsel[0])
+        return dict(blockers=blockers[:r].copy(), gains=gains[:r].copy(), cov=cov[:r + 1].copy(),
+                    cov_upper=cu[:r + 1].copy(), n_selected=r)
+
+    def lrr_coverage(self, vprime, blockers, theta: int, key: int, threads: int | None = None) -> int:
+        """Cov(B) over the LRR sets of samples [0, theta)."""
+        lib = _load()
+        vp = np.ascontiguousarray(vprime, dtype=np.int32)
+        b = np.ascontiguousarray(blockers, dtype=np.int32)
+        out = np.zeros(1, dtype=np.int64)
+        st = lib.oracle_lrr_coverage(self.n, self.m, _ptr(self.row_ptr), _ptr(self.col), _ptr(self.thr),
+                                     _ptr(self.seeds), len(self.seeds), _ptr(vp), len(vp), _ptr(b), len(b),
+                                     theta, key, threads or default_threads(), _ptr(out))
+        if st != 0:
+            raise ValueError("oracle_lrr_coverage rejected the query")
+        return int(out[0])
+
+
+def lrr_pick(key: int, i: int, nvp: int) -> int:
+    """Index into V'_s of sample i's target (Algorithm 3)."""
+    return int(_load().oracle_lrr_pick(key, i, nvp))

@@ -48,6 +48,29 @@ class LsbmInfo(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class GsbmInfo(ctypes.Structure):
+    """imin_gsbm_info_t."""
+    _fields_ = [("returned_on", ctypes.c_int32), ("on_size", ctypes.c_int32), ("nvp", ctypes.c_int64),
+                ("sra_worlds", ctypes.c_int64), ("opt_l", ctypes.c_double), ("theta_max", ctypes.c_double),
+                ("theta_0", ctypes.c_double), ("i_max", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("theta", ctypes.c_int64), ("cov1", ctypes.c_int64), ("cov2", ctypes.c_int64),
+                ("cov_upper", ctypes.c_int64), ("sigma_l", ctypes.c_double), ("sigma_u", ctypes.c_double),
+                ("a1", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class SandiminInfo(ctypes.Structure):
+    """imin_sandimin_info_t."""
+    _fields_ = [("choice", ctypes.c_int32), ("n_blockers", ctypes.c_int32 * 3), ("estimate", ctypes.c_double * 3),
+                ("eval_worlds", ctypes.c_int64 * 3), ("lsbm", LsbmInfo), ("gsbm", GsbmInfo)]
+
+    def as_dict(self) -> dict:
+        return dict(choice=self.choice, n_blockers=list(self.n_blockers), estimate=list(self.estimate),
+                    eval_worlds=list(self.eval_worlds), lsbm=self.lsbm.as_dict(), gsbm=self.gsbm.as_dict())
+
+
 class IminError(RuntimeError):
     def __init__(self, status: int, message: str, flags: int = 0):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message} (device flags 0x{flags:x})")
@@ -132,6 +155,22 @@ def load():
     lib.imin_lsbm.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, u64, P, P, P,
                               ctypes.POINTER(LsbmInfo)]
     lib.imin_lsbm.restype = st
+    lib.imin_world_sizes.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P]
+    lib.imin_world_sizes.restype = st
+    lib.imin_vprime.argtypes = [P, P, i32, P, P, ctypes.POINTER(i32)]
+    lib.imin_vprime.restype = st
+    lib.imin_lrr_max_coverage.argtypes = [P, P, i32, i32, i64, u64, P, P, P, P, P, P]
+    lib.imin_lrr_max_coverage.restype = st
+    lib.imin_lrr_coverage.argtypes = [P, P, i32, P, i32, i64, u64, P, P]
+    lib.imin_lrr_coverage.restype = st
+    lib.imin_gsbm.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, u64, P, P, P,
+                              ctypes.POINTER(GsbmInfo)]
+    lib.imin_gsbm.restype = st
+    lib.imin_lhga.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, u64, P, P, P]
+    lib.imin_lhga.restype = st
+    lib.imin_sandimin.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                  ctypes.c_double, u64, P, P, P, P, ctypes.POINTER(SandiminInfo)]
+    lib.imin_sandimin.restype = st
     _lib = lib
     return lib
 
@@ -659,3 +698,127 @@ def lsbm(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, delta
                              ctypes.byref(info)))
     r = int(nsel.cpu()[0])
     return dict(blockers=blockers.cpu().numpy()[:r], n_selected=r, info=info.as_dict())
+
+
+def world_sizes(graph: Graph, seeds, w_begin: int, w_count: int, rng_seed: int, blocked=()) -> np.ndarray:
+    """|R_w(B)| of worlds [w_begin, w_begin + w_count) (imin_world_sizes)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    b = np.asarray(list(blocked), dtype=np.int32)
+    bd = _dev(b, torch.int32, dev) if b.size else None
+    out = torch.zeros(w_count, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_world_sizes(graph.handle, _ptr(s), int(s.numel()), _ptr(bd), int(b.size), int(w_begin),
+                                    int(w_count), int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(out)))
+    return out.cpu().numpy()
+
+
+def vprime(graph: Graph, seeds) -> np.ndarray:
+    """V'_s (imin_vprime)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    cnt = ctypes.c_int32(0)
+    with torch.cuda.device(dev):
+        _check(lib.imin_vprime(graph.handle, _ptr(s), int(s.numel()), _stream(dev), None, ctypes.byref(cnt)))
+        out = torch.zeros(max(cnt.value, 1), dtype=torch.int32, device=dev)
+        _check(lib.imin_vprime(graph.handle, _ptr(s), int(s.numel()), _stream(dev), _ptr(out), ctypes.byref(cnt)))
+    return out.cpu().numpy()[:cnt.value]
+
+
+def lrr_max_coverage(graph: Graph, seeds, k: int, theta: int, key: int) -> dict:
+    """Max-Coverage over the LRR sets of samples [0, theta) (imin_lrr_max_coverage)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    gains = torch.zeros(max(k, 1), dtype=torch.int64, device=dev)
+    cov = torch.zeros(k + 1, dtype=torch.int64, device=dev)
+    cu = torch.zeros(k + 1, dtype=torch.int64, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_lrr_max_coverage(graph.handle, _ptr(s), int(s.numel()), int(k), int(theta),
+                                         int(key) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(blockers), _ptr(gains),
+                                         _ptr(cov), _ptr(cu), _ptr(nsel)))
+    r = int(nsel.cpu()[0])
+    return dict(blockers=blockers.cpu().numpy()[:r], gains=gains.cpu().numpy()[:r],
+                cov=cov.cpu().numpy()[:r + 1], cov_upper=cu.cpu().numpy()[:r + 1], n_selected=r)
+
+
+def lrr_coverage(graph: Graph, seeds, blockers, theta: int, key: int) -> int:
+    """Cov(blockers) over the LRR sets of samples [0, theta) (imin_lrr_coverage)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    b = np.asarray(blockers, dtype=np.int32)
+    bd = _dev(b, torch.int32, dev) if b.size else None
+    out = torch.zeros(1, dtype=torch.int64, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_lrr_coverage(graph.handle, _ptr(s), int(s.numel()), _ptr(bd), int(b.size), int(theta),
+                                     int(key) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(out)))
+    return int(out.cpu()[0])
+
+
+def gsbm(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, delta: float | None = None,
+         rng_seed: int = 0) -> dict:
+    """GSBM (imin_gsbm): dict(blockers, n_selected, info)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    if delta is None:
+        delta = 1.0 / graph.n
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    info = GsbmInfo()
+    with torch.cuda.device(dev):
+        _check(lib.imin_gsbm(graph.handle, _ptr(s), int(s.numel()), int(k), float(eps), float(beta), float(delta),
+                             int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(blockers), _ptr(nsel),
+                             ctypes.byref(info)))
+    r = int(nsel.cpu()[0])
+    return dict(blockers=blockers.cpu().numpy()[:r], n_selected=r, info=info.as_dict())
+
+
+def lhga(graph: Graph, seeds, k: int, beta: float = 0.1, delta: float | None = None, rng_seed: int = 0):
+    """LHGA (imin_lhga): the blockers in decreasing score order."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    if delta is None:
+        delta = 1.0 / graph.n
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    with torch.cuda.device(dev):
+        _check(lib.imin_lhga(graph.handle, _ptr(s), int(s.numel()), int(k), float(beta), float(delta),
+                             int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(blockers), _ptr(nsel)))
+    return blockers.cpu().numpy()[:int(nsel.cpu()[0])]
+
+
+def sandimin(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, gamma: float = 0.1,
+             delta: float | None = None, rng_seed: int = 0) -> dict:
+    """SandIMIN, Algorithm 1 (imin_sandimin): dict(blockers, choice, B_L, B_U, B_R, info)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    if delta is None:
+        delta = 1.0 / graph.n
+    blockers = torch.zeros(max(k, 1), dtype=torch.int32, device=dev)
+    nsel = torch.zeros(1, dtype=torch.int32, device=dev)
+    cand = torch.zeros(3 * max(k, 1), dtype=torch.int32, device=dev)
+    info = SandiminInfo()
+    with torch.cuda.device(dev):
+        _check(lib.imin_sandimin(graph.handle, _ptr(s), int(s.numel()), int(k), float(eps), float(beta),
+                                 float(gamma), float(delta), int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev),
+                                 _ptr(blockers), _ptr(nsel), _ptr(cand), ctypes.byref(info)))
+    d = info.as_dict()
+    c = cand.cpu().numpy()
+    sets = [c[i * k:i * k + d["n_blockers"][i]] for i in range(3)]
+    return dict(blockers=blockers.cpu().numpy()[:int(nsel.cpu()[0])], choice="LUR"[d["choice"]], B_L=sets[0],
+                B_U=sets[1], B_R=sets[2], info=d)

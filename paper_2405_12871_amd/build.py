@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libimin.so")
 SOURCES = ["imin_world.hip", "imin_kernels.hip", "imin_cover.hip", "imin_probe.hip", "imin_static.hip", "imin_api.cpp",
-           "imin_serve.cpp", "imin_lsbm.cpp"]
+           "imin_serve.cpp", "imin_sandwich.cpp", "imin_lrr.hip"]
 ARCH = "gfx950"
 
 # Packed FP32 instructions are kept out of every device build.

@@ -10,6 +10,7 @@
 #include <condition_variable>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -36,6 +37,13 @@ struct imin_graph {
     // the same four figures as raised on the device by enqueued solves
     // (bump entries and extra edges per world, tier-1 and tier-2 shares)
     unsigned long long* hints_dev = nullptr;
+    // made on first use and kept until destroy: host copies of the graph and
+    // the in-edges on the device (Global Sampling)
+    std::mutex aux_mu;
+    std::unique_ptr<imin::HostGraph> host;
+    int32_t* in_off = nullptr;
+    int32_t* in_src = nullptr;
+    int32_t* in_eid = nullptr;
 };
 
 namespace {
@@ -499,6 +507,44 @@ struct Session {
     int cover = imin::kCoverNone;
     const uint32_t* cover_mark = nullptr;
     int unit_counts = 0;
+    int sizes_only = 0;  // |R_w| per world only
+    // Global Sampling: samples are LRR sets (Algorithm 3) instead of worlds
+    bool lrr = false;
+    imin::LrrDev lrr_dev{};
+    DevArray<int32_t> lrr_stamp, lrr_cone, lrr_lst, lrr_epoch, lrr_vprime;
+
+    // the sampling slots and V'_s of Global Sampling: as many slots as
+    // IMIN_LRR_BUDGET (default 4 GiB) allows at 12 bytes per node, at most
+    // four per compute unit
+    imin_status_t setup_lrr(imin_graph_t h, const std::vector<int32_t>& vprime) {
+        const int32_t *in_off = nullptr, *in_src = nullptr, *in_eid = nullptr;
+        if (!imin::graph_in_edges(h, &in_off, &in_src, &in_eid)) return IMIN_ERR_NOMEM;
+        const size_t n = (size_t)g.n;
+        const size_t budget = env_size("IMIN_LRR_BUDGET", (size_t)4 << 30);
+        const size_t slots = std::max<size_t>(1, std::min<size_t>(budget / (12 * n), (size_t)cu_count() * 4));
+        IMIN_TRY(lrr_stamp.alloc(slots * n));
+        IMIN_TRY(lrr_cone.alloc(slots * n));
+        IMIN_TRY(lrr_lst.alloc(slots * n));
+        IMIN_TRY(lrr_epoch.alloc(slots));
+        IMIN_TRY(lrr_vprime.alloc(std::max<size_t>(vprime.size(), 1)));
+        IMIN_TRY(imin::launch_fill_i32(lrr_stamp.p, 0, slots * n, s));
+        IMIN_TRY(imin::launch_fill_i32(lrr_epoch.p, 0, slots, s));
+        if (!vprime.empty())
+            IMIN_TRY(hipMemcpyAsync(lrr_vprime.p, vprime.data(), vprime.size() * sizeof(int32_t),
+                                    hipMemcpyHostToDevice, s));
+        IMIN_TRY(hipStreamSynchronize(s));  // vprime is a host vector
+        lrr_dev.in_off = in_off;
+        lrr_dev.in_src = in_src;
+        lrr_dev.in_eid = in_eid;
+        lrr_dev.vprime = lrr_vprime.p;
+        lrr_dev.nvp = (uint32_t)vprime.size();
+        lrr_dev.n_slots = (int32_t)slots;
+        lrr_dev.stamp = lrr_stamp.p;
+        lrr_dev.cone = lrr_cone.p;
+        lrr_dev.lst = lrr_lst.p;
+        lrr_dev.epoch = lrr_epoch.p;
+        return IMIN_OK;
+    }
 
     Session(const imin::GraphDev& gd, hipStream_t st, imin_graph* h = nullptr) : g(gd), s(st), gh(h) {}
     imin_graph* gh;  // per-graph scratch hints (may be null)
@@ -863,7 +909,7 @@ struct Session {
         IMIN_TRY(list3.alloc(next_n));
         IMIN_TRY(list4.alloc(next_n));
         IMIN_TRY(list0.alloc(1));
-        slot_cap0 = (size_t)imin::world_tier0_capacity();
+        slot_cap0 = lrr ? 0 : (size_t)imin::world_tier0_capacity();  // LRR sets use the bump region only
         big_cap = hinted(gh ? &gh->big_per_world : nullptr, tile_cap, env_size("IMIN_BIG_SCRATCH", (size_t)1 << 20));
         IMIN_TRY(scr_node.alloc(tile_cap * slot_cap0 + big_cap));
         IMIN_TRY(scr_cnt.alloc(tile_cap * slot_cap0 + big_cap));
@@ -1116,6 +1162,7 @@ struct Session {
         out.cover = cover;
         out.mark = cover_mark;
         out.unit_counts = unit_counts;
+        out.sizes_only = sizes_only;
         return out;
     }
 
@@ -1242,7 +1289,9 @@ struct Session {
             out.world_edges = wedges_out ? wedges_out + done : nullptr;
             out.keep_edges = keep ? 1 : 0;
             IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            imin_status_t st = launch_tiers_checked(q, (uint32_t)(w_begin + done), (uint32_t)nw, out);
+            imin_status_t st = lrr ? (imin::launch_lrr(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, lrr_dev,
+                                                       out, s) == hipSuccess ? IMIN_OK : IMIN_ERR_DEVICE)
+                                   : launch_tiers_checked(q, (uint32_t)(w_begin + done), (uint32_t)nw, out);
             if (st != IMIN_OK) return st;
             IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)nw, &ctl.p->tile_total, ctl.p, s));
             if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)nw, &ctl.p->xtile_total, ctl.p, s));
@@ -1264,7 +1313,7 @@ struct Session {
                 g_last_flags = f;
                 return IMIN_ERR_INTERNAL;
             }
-            record_scratch(hctl.p->big_count, hctl.p->xbig_count, nw);
+            if (!lrr) record_scratch(hctl.p->big_count, hctl.p->xbig_count, nw);
             if (f & imin::kFlagPairOverflow) {
                 // a scratch bump region was too small: grow it, redo the tile
                 st = clear_flag(imin::kFlagPairOverflow);
@@ -1468,6 +1517,9 @@ imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, co
 
 imin_status_t imin_graph_destroy(imin_graph_t g) {
     if (!g) return IMIN_OK;
+    if (g->in_off) (void)hipFree(g->in_off);
+    if (g->in_src) (void)hipFree(g->in_src);
+    if (g->in_eid) (void)hipFree(g->in_eid);
     if (g->g.off) (void)hipFree(g->g.off);
     if (g->g.col) (void)hipFree(g->g.col);
     if (g->g.thr) (void)hipFree(g->g.thr);
@@ -1796,29 +1848,65 @@ static int bit_length(unsigned long long v) {
     return b;
 }
 
+// V'_s of a seed set given in device memory (Global Sampling): seeds are
+// checked on the host first (range), then the search runs on the handle's
+// host copy of the graph
+static imin_status_t lrr_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, hipStream_t s,
+                                std::vector<int32_t>& vp) {
+    std::vector<int32_t> hs((size_t)n_seeds);
+    IMIN_TRY(hipMemcpyAsync(hs.data(), seeds, hs.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    IMIN_TRY(hipStreamSynchronize(s));
+    for (int32_t v : hs)
+        if (v < 0 || v >= g->g.n) return IMIN_ERR_DATA;
+    const imin::HostGraph* h = imin::graph_host(g);
+    if (!h) return IMIN_ERR_DEVICE;
+    vp = imin::reachable_nonseeds(*h, hs);
+    return IMIN_OK;
+}
+
+// Max-Coverage over the CP sequences of worlds [0, theta) or, with lrr, over
+// the LRR sets of samples [0, theta)
 static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
                                        int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
-                                       int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected) {
+                                       int64_t* gains, int64_t* cov, int64_t* cov_upper, int32_t* n_selected,
+                                       bool lrr = false) {
     g_last_flags = 0;
     imin_status_t st = check_coverage_args(g, seeds, n_seeds, theta);
     if (st != IMIN_OK) return st;
     if (!blockers || !gains || !cov || !cov_upper || !n_selected || k < 0 || k > g->g.n) return IMIN_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> vp;
+    if (lrr && (st = lrr_vprime(g, seeds, n_seeds, s, vp)) != IMIN_OK) return st;
     Session ss(g->g, s, g);
-    ss.cover = imin::kCoverStore;  // before init: HBM-tier slots carry preorder indexes
+    ss.lrr = lrr;
+    // before init: HBM-tier slots carry preorder indexes for the trees
+    ss.cover = lrr ? imin::kCoverNone : imin::kCoverStore;
     st = ss.init((uint64_t)theta, true);
     if (st != IMIN_OK) return st;
     imin::QueryDev q{};
     st = setup_query(ss, seeds, n_seeds, nullptr, 0, rng_seed, q);
     if (st != IMIN_OK) return st;
+    if (lrr && vp.empty()) {
+        // no node can be reached: every set is empty, nothing is selected
+        IMIN_TRY(imin::launch_fill_i64(cov, -1, (size_t)k + 1, s));
+        IMIN_TRY(imin::launch_fill_i64(cov_upper, -1, (size_t)k + 1, s));
+        IMIN_TRY(imin::launch_fill_i64(cov, 0, 1, s));
+        IMIN_TRY(imin::launch_fill_i64(cov_upper, 0, 1, s));
+        IMIN_TRY(imin::launch_fill_i32(n_selected, 0, 1, s));
+        IMIN_TRY(hipStreamSynchronize(s));
+        return IMIN_OK;
+    }
+    if (lrr && (st = ss.setup_lrr(g, vp)) != IMIN_OK) return st;
     IMIN_TRY(ss.world_size.alloc((size_t)theta));
-    // the store of dominator trees: positions are int32 in the index
+    // the store (dominator trees, or LRR sets): positions are int32 in the index
     ss.store_budget = std::min<size_t>(env_size("IMIN_COVER_STORE_CAP", (size_t)0x7FFFFFFF), (size_t)0x7FFFFFFF);
     IMIN_TRY(ss.store_off.alloc((size_t)theta));
     IMIN_TRY(ss.store_len.alloc((size_t)theta));
     IMIN_TRY(ss.list0.alloc((size_t)theta));
-    IMIN_TRY(ss.scr_par.alloc(ss.scr_node.count));
-    IMIN_TRY(ss.scr_lab.alloc(ss.scr_node.count));
+    if (!lrr) {
+        IMIN_TRY(ss.scr_par.alloc(ss.scr_node.count));
+        IMIN_TRY(ss.scr_lab.alloc(ss.scr_node.count));
+    }
     ss.incremental = true;
     ss.label_rule = false;
     IMIN_TRY(imin::launch_fill_i64(cov, -1, (size_t)k + 1, s));
@@ -1828,6 +1916,10 @@ static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int
     st = ss.evaluate(q, 0, (uint64_t)theta, ss.world_size.p, nullptr, nullptr, true);
     if (st != IMIN_OK) return st;
     if (!ss.incremental) return IMIN_ERR_NOMEM;  // the store did not fit
+    // the index is sized from the store's entry count, which the last tile's
+    // compaction raised after the pass last read the counters
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
     st = ss.build_index((uint64_t)theta, nullptr);
     if (st != IMIN_OK) return st;
     st = ss.read_ctl();
@@ -1859,7 +1951,7 @@ static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int
     const int grid = std::min<int>(ss.dsz_n, cu_count() * 8);
     for (int32_t r = 0; r <= k; ++r) {
         IMIN_TRY(imin::launch_cover_round(g->g, ss.gain.p, ss.ctl.p, so, co, r, key_bits, out, ss.idx_off.p,
-                                          ss.idx_ent.p, ss.dsz.p, ss.dsz_n, grid, s));
+                                          ss.idx_ent.p, ss.dsz.p, ss.dsz_n, grid, lrr, s));
         if ((r & 31) == 31 || r == k) {
             st = ss.read_ctl();
             if (st != IMIN_OK) return st;
@@ -1875,16 +1967,26 @@ static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int
 }
 
 static imin_status_t coverage_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set,
-                                   int32_t n_set, int64_t theta, uint64_t rng_seed, void* stream, int64_t* covered) {
+                                   int32_t n_set, int64_t theta, uint64_t rng_seed, void* stream, int64_t* covered,
+                                   bool lrr = false) {
     g_last_flags = 0;
     imin_status_t st = check_coverage_args(g, seeds, n_seeds, theta);
     if (st != IMIN_OK) return st;
     if (!covered || n_set < 0 || (n_set > 0 && !set)) return IMIN_ERR_INVALID;
     hipStream_t s = (hipStream_t)stream;
+    std::vector<int32_t> vp;
+    if (lrr && (st = lrr_vprime(g, seeds, n_seeds, s, vp)) != IMIN_OK) return st;
     Session ss(g->g, s, g);
+    ss.lrr = lrr;
     ss.cover = imin::kCoverCount;
     st = ss.init((uint64_t)theta, false);
     if (st != IMIN_OK) return st;
+    if (lrr && vp.empty()) {
+        IMIN_TRY(imin::launch_fill_i64(covered, 0, 1, s));
+        IMIN_TRY(hipStreamSynchronize(s));
+        return IMIN_OK;
+    }
+    if (lrr && (st = ss.setup_lrr(g, vp)) != IMIN_OK) return st;
     // the marked set, checked as a blocked set would be (in range, no seed)
     DevArray<uint32_t> mark;
     IMIN_TRY(mark.alloc(((size_t)g->g.n + 31) / 32));
@@ -1898,6 +2000,35 @@ static imin_status_t coverage_impl(imin_graph_t g, const int32_t* seeds, int32_t
     st = ss.evaluate(q, 0, (uint64_t)theta, nullptr, nullptr, nullptr);
     if (st != IMIN_OK) return st;
     IMIN_TRY(hipMemcpyAsync(covered, &ss.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+    st = ss.read_ctl();
+    if (st != IMIN_OK) return st;
+    if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
+        g_last_flags = ss.hctl.p->flags;
+        return IMIN_ERR_INTERNAL;
+    }
+    ss.finish();
+    return IMIN_OK;
+}
+
+static imin_status_t world_sizes_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                                      int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed,
+                                      void* stream, int32_t* world_size) {
+    g_last_flags = 0;
+    if (!g || !seeds || !world_size) return IMIN_ERR_INVALID;
+    if (n_seeds < 1 || n_seeds > g->g.n || n_blocked < 0 || (n_blocked > 0 && !blocked)) return IMIN_ERR_INVALID;
+    if (w_begin < 0 || w_count < 1 || w_begin + w_count > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;
+    hipStream_t s = (hipStream_t)stream;
+    Session ss(g->g, s, g);
+    ss.sizes_only = 1;
+    imin_status_t st = ss.init((uint64_t)w_count, false);
+    if (st != IMIN_OK) return st;
+    imin::QueryDev q{};
+    st = setup_query(ss, seeds, n_seeds, blocked, n_blocked, rng_seed, q);
+    if (st != IMIN_OK) return st;
+    IMIN_TRY(imin::launch_fill_i64(ss.gain.p, 0, (size_t)g->g.n, s));
+    IMIN_TRY(imin::launch_ctl_reset_round(ss.ctl.p, s));
+    st = ss.evaluate(q, (uint64_t)w_begin, (uint64_t)w_count, world_size, nullptr, nullptr);
+    if (st != IMIN_OK) return st;
     st = ss.read_ctl();
     if (st != IMIN_OK) return st;
     if (ss.hctl.p->flags & ~imin::kFlagDataMask) {
@@ -1959,6 +2090,86 @@ imin_status_t solve_enqueued(imin_graph_t g, const int32_t* seeds, int32_t n_see
 }
 
 int graph_device(imin_graph_t g) { return g ? g->device : -1; }
+
+const HostGraph* graph_host(imin_graph_t g) {
+    if (!g) return nullptr;
+    std::lock_guard<std::mutex> lk(g->aux_mu);
+    if (g->host) return g->host.get();
+    auto h = std::make_unique<HostGraph>();
+    h->n = g->g.n;
+    h->m = g->g.m;
+    h->row_ptr.resize((size_t)h->n + 1);
+    h->col.resize((size_t)std::max<int64_t>(h->m, 1));
+    h->thr.resize((size_t)std::max<int64_t>(h->m, 1));
+    if (imin_graph_export(g, h->row_ptr.data(), h->col.data(), h->thr.data()) != IMIN_OK) return nullptr;
+    g->host = std::move(h);
+    return g->host.get();
+}
+
+bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int32_t** in_src, const int32_t** in_eid) {
+    const HostGraph* h = graph_host(g);
+    if (!h) return false;
+    std::lock_guard<std::mutex> lk(g->aux_mu);
+    if (!g->in_off) {
+        // counting sort of the edges by head
+        const size_t n = (size_t)h->n, m = (size_t)h->m;
+        std::vector<int32_t> off(n + 1, 0), src(std::max<size_t>(m, 1)), eid(std::max<size_t>(m, 1));
+        for (size_t e = 0; e < m; ++e) off[(size_t)h->col[e] + 1] += 1;
+        for (size_t v = 0; v < n; ++v) off[v + 1] += off[v];
+        std::vector<int32_t> cur(off.begin(), off.end() - 1);
+        for (size_t u = 0; u < n; ++u)
+            for (int64_t e = h->row_ptr[u]; e < h->row_ptr[u + 1]; ++e) {
+                const int32_t at = cur[(size_t)h->col[(size_t)e]]++;
+                src[(size_t)at] = (int32_t)u;
+                eid[(size_t)at] = (int32_t)e;
+            }
+        int32_t *a = nullptr, *b = nullptr, *c = nullptr;
+        if (hipMalloc((void**)&a, off.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void**)&b, src.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void**)&c, eid.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMemcpy(a, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(b, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(c, eid.data(), eid.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            if (a) (void)hipFree(a);
+            if (b) (void)hipFree(b);
+            if (c) (void)hipFree(c);
+            return false;
+        }
+        g->in_off = a;
+        g->in_src = b;
+        g->in_eid = c;
+    }
+    *in_off = g->in_off;
+    *in_src = g->in_src;
+    *in_eid = g->in_eid;
+    return true;
+}
+
+std::vector<int32_t> reachable_nonseeds(const HostGraph& h, const std::vector<int32_t>& seeds) {
+    std::vector<uint8_t> seen((size_t)h.n, 0), is_seed((size_t)h.n, 0);
+    std::vector<int32_t> queue;
+    for (int32_t v : seeds) {
+        is_seed[(size_t)v] = 1;
+        if (!seen[(size_t)v]) {
+            seen[(size_t)v] = 1;
+            queue.push_back(v);
+        }
+    }
+    for (size_t head = 0; head < queue.size(); ++head) {
+        const int32_t u = queue[head];
+        for (int64_t e = h.row_ptr[(size_t)u]; e < h.row_ptr[(size_t)u + 1]; ++e) {
+            const int32_t x = h.col[(size_t)e];
+            if (h.thr[(size_t)e] == 0u || seen[(size_t)x]) continue;
+            seen[(size_t)x] = 1;
+            queue.push_back(x);
+        }
+    }
+    std::vector<int32_t> out;
+    for (int32_t v = 0; v < h.n; ++v)
+        if (seen[(size_t)v] && !is_seed[(size_t)v]) out.push_back(v);
+    return out;
+}
 }  // namespace imin
 
 extern "C" {
@@ -2021,6 +2232,62 @@ imin_status_t imin_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seed
                             int64_t theta, uint64_t rng_seed, void* stream, int64_t* covered) {
     try {
         return coverage_impl(g, seeds, n_seeds, set, n_set, theta, rng_seed, stream, covered);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_lrr_max_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
+                                    uint64_t key, void* stream, int32_t* blockers, int64_t* gains, int64_t* cov,
+                                    int64_t* cov_upper, int32_t* n_selected) {
+    try {
+        return max_coverage_impl(g, seeds, n_seeds, k, theta, key, stream, blockers, gains, cov, cov_upper,
+                                 n_selected, true);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_lrr_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* set,
+                                int32_t n_set, int64_t theta, uint64_t key, void* stream, int64_t* covered) {
+    try {
+        return coverage_impl(g, seeds, n_seeds, set, n_set, theta, key, stream, covered, true);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, void* stream, int32_t* out,
+                          int32_t* count) {
+    if (!g || !seeds || !count || n_seeds < 1 || n_seeds > g->g.n) return IMIN_ERR_INVALID;
+    try {
+        std::vector<int32_t> vp;
+        const imin_status_t st = lrr_vprime(g, seeds, n_seeds, (hipStream_t)stream, vp);
+        if (st != IMIN_OK) return st;
+        *count = (int32_t)vp.size();
+        if (out && !vp.empty() &&
+            hipMemcpy(out, vp.data(), vp.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipGetLastError();
+            return IMIN_ERR_DEVICE;
+        }
+        return IMIN_OK;
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    }
+}
+
+imin_status_t imin_world_sizes(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, const int32_t* blocked,
+                               int32_t n_blocked, int64_t w_begin, int64_t w_count, uint64_t rng_seed, void* stream,
+                               int32_t* world_size) {
+    try {
+        return world_sizes_impl(g, seeds, n_seeds, blocked, n_blocked, w_begin, w_count, rng_seed, stream,
+                                world_size);
     } catch (const std::bad_alloc&) {
         return IMIN_ERR_NOMEM;
     } catch (...) {

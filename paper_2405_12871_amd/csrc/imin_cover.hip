@@ -25,6 +25,11 @@
 //               known exactly, and the top-k sum is the sums of the bins
 //               above it plus the rest at that value;
 //   update      the pick's index entries, one wave per world.
+//
+// The same rounds run over LRR sets (Section 4.2; GSBM, Section 5.2): each
+// stored item is one set with every member entry counting 1 while the set is
+// uncovered, so gain[v] is the number of uncovered sets holding v, and a pick
+// covers whole sets.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -184,6 +189,7 @@ __global__ __launch_bounds__(kPickNT) void k_topk_pick(CoverOut co, int r, int s
 
 // The pick's worlds: idx_ent[idx_off[u] .. idx_off[u+1]) are (position,
 // world) of u's entries; one wave per entry.
+template <bool SETS>
 __global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut out, const int32_t* __restrict__ idx_off,
                                                          const int2* __restrict__ idx_ent, int64_t* gain, long long* dsz,
                                                          uint32_t* excl) {
@@ -206,8 +212,25 @@ __global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut 
         if (c <= 0) continue;  // u is covered in this world already (uniform per wave)
         const long long base = out.store_off[w];
         const int len = out.store_len[w];
+        if (pos < base || pos >= base + len || (unsigned long long)(base + len) > out.store_cap) {
+            bad = true;
+            continue;
+        }
+        if constexpr (SETS) {
+            // an LRR set: every member entry is covered, and the set counts once
+            for (int j = lane; j < len; j += 64) {
+                const long long q = base + j;
+                const int cj = out.store_cnt[q];
+                if (cj > 0) {
+                    out.store_cnt[q] = 0;
+                    if (q != pos) atomicAdd((unsigned long long*)&gain[out.store_node[q]], (unsigned long long)(long long)-cj);
+                }
+            }
+            if (lane == 0) acc += 1;
+            continue;
+        }
         const int size = (int)out.store_lab[pos];
-        if (pos < base || pos + size > base + len || (unsigned long long)(base + len) > out.store_cap) {
+        if (pos + size > base + len) {
             bad = true;
             continue;
         }
@@ -253,7 +276,8 @@ __global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut 
 
 hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, const SelectOut& so,
                               const CoverOut& co, int r, int key_bits, const TileOut& out, const int32_t* idx_off,
-                              const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, hipStream_t s) {
+                              const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, bool sets,
+                              hipStream_t s) {
     if (grid < 1 || grid > dsz_n || key_bits < 1 || key_bits > 62) return hipErrorInvalidValue;
     hipError_t e = launch_select(g, gain, ctl, so, dsz, dsz_n, false, s);
     if (e != hipSuccess) return e;
@@ -269,7 +293,10 @@ hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, c
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (r < so.k) {
-        k_cover_update<<<(unsigned)grid, kUpdNT, 0, s>>>(ctl, out, idx_off, idx_ent, gain, dsz, so.excl);
+        if (sets)
+            k_cover_update<true><<<(unsigned)grid, kUpdNT, 0, s>>>(ctl, out, idx_off, idx_ent, gain, dsz, so.excl);
+        else
+            k_cover_update<false><<<(unsigned)grid, kUpdNT, 0, s>>>(ctl, out, idx_off, idx_ent, gain, dsz, so.excl);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;

@@ -8,11 +8,12 @@
 
 namespace imin {
 
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with counter words 2 and
-// 3 fixed at zero: counter (c0, c1, 0, 0), key (k0, k1).  Ten rounds of two
-// 32x32->64 products; the key advances by the Weyl increments between rounds.
-__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
-    uint32_t x0 = c0, x1 = c1, x2 = 0u, x3 = 0u;
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter (c0, c1, c2, c3),
+// key (k0, k1).  Ten rounds of two 32x32->64 products; the key advances by the
+// Weyl increments between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                               uint32_t k1) {
+    uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)x0 * 0xD2511F53ull;
@@ -27,6 +28,11 @@ __device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t
         k1 += 0xBB67AE85u;
     }
     return make_uint4(x0, x1, x2, x3);
+}
+
+// The coin blocks: counter words 2 and 3 are zero, counter (c0, c1, 0, 0).
+__device__ __forceinline__ uint4 philox_block(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
+    return philox4x32_10(c0, c1, 0u, 0u, k0, k1);
 }
 
 __device__ __forceinline__ bool bit_set(const uint32_t* bits, int32_t v) {

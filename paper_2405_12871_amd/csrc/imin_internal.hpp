@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace imin {
 
@@ -207,6 +208,8 @@ struct TileOut {
     int cover;
     const uint32_t* mark;  // [n bits] kCoverCount: the set whose coverage is counted
     int unit_counts;
+    // only |R_w| per world: no dominators, no entries (stopping rules)
+    int sizes_only;
 };
 
 // World outputs for lower-bound coverage.
@@ -221,6 +224,21 @@ enum : int {
     // no entries: world_size gets the number of non-seeds whose CP set meets
     // the marked set
     kCoverCount = 2
+};
+
+// Global Sampling (Algorithm 3): the graph's in-edges, the pool's V'_s, and
+// per-slot state (one slot per workgroup of the sampling launch).
+struct LrrDev {
+    const int32_t* in_off;  // [n+1] in-edges of each node
+    const int32_t* in_src;  // [m]   their tails
+    const int32_t* in_eid;  // [m]   their CSR slots (the edge id of the coin)
+    const int32_t* vprime;  // [nvp] V'_s ascending
+    uint32_t nvp;
+    int32_t n_slots;
+    int32_t* stamp;         // [slots][n] 2t+1: in the t-th sample's cone, 2t+2: in its LRR set (zero at start)
+    int32_t* cone;          // [slots][n]
+    int32_t* lst;           // [slots][n]
+    int32_t* epoch;         // [slots] samples the slot has taken (zero at start)
 };
 
 // Coverage greedy state per round (device): the top-k search over the gains
@@ -415,9 +433,19 @@ hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, 
 // still uncovered its subtree's entries are covered and its ancestors lose
 // its count.  dsz (dsz_n slots, grid <= dsz_n) carries the newly covered
 // counts to the next round's selection.  key_bits bounds every gain.
+// With `sets` the stored items are LRR sets (Section 4.2) instead of
+// dominator trees: covering a set zeroes every member entry, and the
+// newly covered count is one per set.
 hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, const SelectOut& so,
                               const CoverOut& co, int r, int key_bits, const TileOut& out, const int32_t* idx_off,
-                              const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, hipStream_t s);
+                              const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, bool sets,
+                              hipStream_t s);
+// LRR sets of samples [w_begin, w_begin + count) of the pool keyed by q's
+// key, as (node, 1) entries in the tile's bump region (wloc / wlen per
+// sample; world_size 1 for a non-empty set), or with out.cover ==
+// kCoverCount whether each set meets out.mark (world_size 0 or 1).
+hipError_t launch_lrr(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w_begin, uint32_t count,
+                      const LrrDev& L, const TileOut& out, hipStream_t s);
 
 
 // An enqueued solve in a given workspace (imin_solve with a workspace),
@@ -430,5 +458,21 @@ imin_status_t solve_enqueued(imin_graph_t g, const int32_t* seeds, int32_t n_see
                              int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
                              int32_t* device_status);
 int graph_device(imin_graph_t g);
+// Host copies of a handle's graph (CSR offsets, heads, thresholds), made on
+// first use and kept until the handle is destroyed; null on failure.
+struct HostGraph {
+    int32_t n = 0;
+    int64_t m = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col;
+    std::vector<uint32_t> thr;
+};
+const HostGraph* graph_host(imin_graph_t g);
+// The handle's in-edges on the device (made on first use): in_off [n+1],
+// in_src [m], in_eid [m]; false on failure.
+bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int32_t** in_src, const int32_t** in_eid);
+// V'_s: the non-seed nodes reachable from the seeds over edges that can be
+// live (threshold > 0), ascending (host arrays; seeds validated by the caller).
+std::vector<int32_t> reachable_nonseeds(const HostGraph& h, const std::vector<int32_t>& seeds);
 
 } // namespace imin

@@ -716,7 +716,7 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
     const int ns = q.n_seeds;
     const int R = sh.count;
     const int nx = sh.n_extra;
-    const int len = (out.cover == kCoverCount) ? 0 : R - ns;  // entries written
+    const int len = (out.cover == kCoverCount || out.sizes_only) ? 0 : R - ns;  // entries written
     int read_len = 0;  // stored entries read back (incremental rounds)
     if (out.mode == kModeDelta) {
         // The stored list keeps the round-0 order; an entry whose count is 0
@@ -862,7 +862,8 @@ template <int NT, int TIER, class Store>
 __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
                                const TileOut& out, Store& st, WorldShared<NT>& sh) {
     if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
-    world_counts<NT>(q, ctl, st, sh);
+    // reach counts and world sizes need no dominators (uniform)
+    if (!out.sizes_only && !out.unit_counts) world_counts<NT>(q, ctl, st, sh);
     if (out.cover == kCoverStore) {  // uniform
         world_labels<NT>(q, st, sh);
     } else if (out.cover == kCoverCount) {

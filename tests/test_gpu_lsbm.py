@@ -195,3 +195,26 @@ def test_lsbm_returns_on(B, oracle_mod):
     got = B.lsbm(G, np.array([0], np.int32), 2, rng_seed=1)
     _same_lsbm(got, lsbm.lsbm(g, np.array([0], np.int32), 2, rng_seed=1))
     assert got["blockers"].tolist() == [1, 2]  # the edge to 3 can never be live
+
+
+@pytest.mark.parametrize("workload,theta,k,rounds", [("large", 200000, 100, (0, 1, 37, 99, 100)),
+                                                      ("medium", 2000, 30, (0, 1, 15, 29, 30))])
+def test_max_coverage_at_full_graph_size(B, oracle_mod, workload, theta, k, rounds):
+    """On the 1M-node trivalency graph (200 seeds) and the 100K-node weighted
+    cascade graph (50 seeds): for sampled prefixes B_r of the GPU's selection,
+    the oracle's marginal coverages given B_r reproduce Cov(B_r), the next pick
+    (argmax, ties to the smaller id) and its gain, and the upper-bound term."""
+    g, seeds, _, _ = synth.workload(workload)
+    _log(f"max coverage at {workload}: n={g.n} theta={theta} k={k}")
+    G = B.Graph.from_synth(g)
+    got = B.max_coverage(G, seeds, k, theta, 3)
+    assert got["n_selected"] == k
+    q = oracle_mod.Query(g, seeds)
+    for r in rounds:
+        marg, cov = q.cover_marginals(got["blockers"][:r], theta, 3)
+        _log(f"  prefix {r}: Cov {cov}")
+        assert cov == got["cov"][r]
+        assert cov + int(np.sort(marg)[::-1][:k].sum()) == got["cov_upper"][r]
+        if r < k:
+            assert int(np.argmax(marg)) == got["blockers"][r]
+            assert int(marg.max()) == got["gains"][r]
