@@ -33,7 +33,8 @@ The default run also times LSBM (Algorithm 4: the stopping-rule estimate of
 the spread, OPT^L, Max-Coverage on doubling pools of CP sequences with the
 sigma bounds' stopping test) on the same graph and seeds with k = --lsbm-k,
 eps = --lsbm-eps, beta = 0.1, delta = 1/n; ``--lsbm-only`` does that alone on
-a named graph.
+a named graph or workload, and with ``--sandwich`` also GSBM, LHGA and
+SandIMIN (Algorithm 1).
 """
 from __future__ import annotations
 
@@ -325,7 +326,9 @@ def main():
     ap.add_argument("--lsbm-eps", type=float, default=0.2, help="eps of the LSBM measurement")
     ap.add_argument("--no-lsbm", action="store_true", help="skip the LSBM measurement")
     ap.add_argument("--lsbm-only", action="store_true", help="measure LSBM alone on --graph")
-    ap.add_argument("--lsbm-seeds", type=int, default=10, help="uniform seeds of --lsbm-only")
+    ap.add_argument("--lsbm-seeds", type=int, default=10, help="seeds of --lsbm-only on a named graph")
+    ap.add_argument("--lsbm-top", action="store_true", help="--lsbm-only seeds: the highest out-degrees")
+    ap.add_argument("--sandwich", action="store_true", help="--lsbm-only also times GSBM, LHGA and SandIMIN")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the estimator would shard "
@@ -523,22 +526,57 @@ def lsbm_measure(binding, G, seeds_dev, k, eps, beta, delta, rng_seed, repeats=2
     return out
 
 
+def timed_call(fn, repeats=2):
+    """(fastest wall time in s, last result) of `repeats` calls."""
+    import torch
+    best, res = None, None
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        best = dt if best is None else min(best, dt)
+    return best, res
+
+
 def run_lsbm(args, binding, dev):
-    """One JSON line: LSBM on a named graph with |S| = --lsbm-seeds uniform seeds."""
+    """One JSON line: LSBM (and with --sandwich also GSBM, LHGA and SandIMIN)
+    on a named graph or workload, |S| = --lsbm-seeds seeds (uniform, or the
+    highest out-degrees with --lsbm-top)."""
     import torch
     from paper_2405_12871_amd import synth
-    g = synth.named_graph(args.graph)
-    seeds = synth.seeds_uniform(g.n, args.lsbm_seeds, 7)
+    if args.graph in ("small", "medium", "large"):
+        g, seeds, _, _ = synth.workload(args.graph)
+    else:
+        g = synth.named_graph(args.graph)
+        seeds = synth.seeds_top_out(g, args.lsbm_seeds) if args.lsbm_top else \
+            synth.seeds_uniform(g.n, args.lsbm_seeds, 7)
     G = binding.Graph.from_synth(g, device=dev)
     seeds_dev = torch.as_tensor(seeds).to(dev)
-    log(f"lsbm on {args.graph}: n={g.n} m={g.m} |S|={len(seeds)} k={args.lsbm_k}")
-    res = lsbm_measure(binding, G, seeds_dev, args.lsbm_k, args.lsbm_eps, 0.1, 1.0 / g.n, RNG_SEED)
-    log(f"  {res}")
-    print(json.dumps({"metric": "LSBM (Algorithm 4) time to solution", "value": res["seconds"], "unit": "s",
-                      "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "u32+int64",
-                      "config": {"workload": f"{args.graph}: n={g.n} m={g.m}, |S|={len(seeds)} uniform, "
-                                             f"k={args.lsbm_k}, eps={args.lsbm_eps}, beta=0.1, delta=1/n"},
-                      "lsbm": res}), flush=True)
+    k, eps, delta = args.lsbm_k, args.lsbm_eps, 1.0 / g.n
+    log(f"lsbm on {args.graph}: n={g.n} m={g.m} |S|={len(seeds)} k={k}")
+    res = {"lsbm": lsbm_measure(binding, G, seeds_dev, k, eps, 0.1, delta, RNG_SEED)}
+    log(f"  {res['lsbm']}")
+    if args.sandwich:
+        sec, out = timed_call(lambda: binding.gsbm(G, seeds_dev, k, eps=eps, beta=0.1, delta=delta,
+                                                   rng_seed=RNG_SEED))
+        res["gsbm"] = {"seconds": sec, "n_selected": out["n_selected"], **out["info"]}
+        log(f"  gsbm {res['gsbm']}")
+        sec, out = timed_call(lambda: binding.lhga(G, seeds_dev, k, beta=0.1, delta=delta, rng_seed=RNG_SEED))
+        res["lhga"] = {"seconds": sec, "n_selected": int(len(out))}
+        sec, out = timed_call(lambda: binding.sandimin(G, seeds_dev, k, eps=eps, beta=0.1, gamma=0.1, delta=delta,
+                                                       rng_seed=RNG_SEED))
+        res["sandimin"] = {"seconds": sec, "choice": out["choice"], "estimates": out["info"]["estimate"],
+                           "eval_worlds": out["info"]["eval_worlds"], "n_blockers": out["info"]["n_blockers"]}
+        log(f"  sandimin {res['sandimin']}")
+    seed_rule = "top out-degree" if args.lsbm_top else "uniform"
+    print(json.dumps({"metric": "LSBM (Algorithm 4) time to solution", "value": res["lsbm"]["seconds"],
+                      "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+                      "dtype": "u32+int64",
+                      "config": {"workload": f"{args.graph}: n={g.n} m={g.m}, |S|={len(seeds)} ({seed_rule}), "
+                                             f"k={k}, eps={eps}, beta=0.1, gamma=0.1, delta=1/n"},
+                      **res}), flush=True)
 
 
 def solve_latency(args, binding, G, seeds_dev, k, theta, dev):
@@ -577,6 +615,7 @@ def solve_latency(args, binding, G, seeds_dev, k, theta, dev):
     return {
         "solve": {
             "k": k, "n_selected": n_sel, "solves": args.solves,
+            "incremental_rounds": binding.last_solve_incremental() == 1,
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "spread_T0_over_theta": float(spread[0]) / theta,
             "spread_final_over_theta": float(spread[n_sel]) / theta,

@@ -632,6 +632,14 @@ const char* imin_status_string(imin_status_t s);
  */
 uint32_t imin_last_device_flags(void);
 
+/*
+ * Whether this thread's last blocking imin_solve ran incremental rounds (1)
+ * or re-evaluated every world each round (0: its resident store would have
+ * exceeded IMIN_STORE_CAP entries or the device; the results are the same
+ * integers, only slower); -1 before any completed solve.
+ */
+int32_t imin_last_solve_incremental(void);
+
 #ifdef __cplusplus
 }
 #endif

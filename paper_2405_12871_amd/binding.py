@@ -155,6 +155,8 @@ def load():
     lib.imin_lsbm.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, u64, P, P, P,
                               ctypes.POINTER(LsbmInfo)]
     lib.imin_lsbm.restype = st
+    lib.imin_last_solve_incremental.argtypes = []
+    lib.imin_last_solve_incremental.restype = i32
     lib.imin_world_sizes.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P]
     lib.imin_world_sizes.restype = st
     lib.imin_vprime.argtypes = [P, P, i32, P, P, ctypes.POINTER(i32)]
@@ -822,3 +824,8 @@ def sandimin(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, g
     sets = [c[i * k:i * k + d["n_blockers"][i]] for i in range(3)]
     return dict(blockers=blockers.cpu().numpy()[:int(nsel.cpu()[0])], choice="LUR"[d["choice"]], B_L=sets[0],
                 B_U=sets[1], B_R=sets[2], info=d)
+
+
+def last_solve_incremental() -> int:
+    """1 when this thread's last blocking solve ran incremental rounds, 0 plain, -1 none."""
+    return int(load().imin_last_solve_incremental())

@@ -57,6 +57,8 @@ void raise_hint(std::atomic<uint64_t>& a, uint64_t v) {
 namespace {
 
 thread_local uint32_t g_last_flags = 0;
+// rounds of this thread's last blocking solve: 1 incremental, 0 plain, -1 none
+thread_local int32_t g_last_mode = -1;
 
 // ---- optional per-kernel timing with HIP events
 constexpr int kTimedKernels = 8;
@@ -1473,6 +1475,8 @@ const char* imin_status_string(imin_status_t s) {
 
 uint32_t imin_last_device_flags(void) { return g_last_flags; }
 
+int32_t imin_last_solve_incremental(void) { return g_last_mode; }
+
 imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
                                 const float* p, void* stream, imin_graph_t* out) {
     g_last_flags = 0;
@@ -1616,6 +1620,7 @@ static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_
     const size_t batch0 = env_size("IMIN_ROUND_BATCH", 32);
     size_t batch = batch0;
     const imin::SelectOut so = ss.select_out(k, blockers, gains, spread_totals, n_selected);
+    g_last_mode = -1;
     for (int32_t r = 0; r <= k;) {
         if (r > 0 && ss.incremental) {
             st = ss.build_index((uint64_t)theta, nullptr);  // built once
@@ -1650,6 +1655,7 @@ static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_
         }
         if (ss.hctl.p->stop) break;
     }
+    g_last_mode = ss.incremental ? 1 : 0;
     ss.finish();
     return IMIN_OK;
 }
