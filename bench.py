@@ -322,6 +322,7 @@ def main():
     ap.add_argument("--serve", type=int, default=0, help="measure latency of this many arriving queries instead")
     ap.add_argument("--graphs", default="wc100k,wc1m,wc4m", help="graphs of --serve")
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
     ap.add_argument("--lsbm-k", type=int, default=100, help="budget of the LSBM measurement")
     ap.add_argument("--lsbm-eps", type=float, default=0.2, help="eps of the LSBM measurement")
     ap.add_argument("--no-lsbm", action="store_true", help="skip the LSBM measurement")
@@ -379,6 +380,13 @@ def main():
     ceil = probe_ceilings(binding, dev, theta, float(E.mean()), cus)
     log(f"ceilings: Philox {ceil['philox_coins_per_s'] / 1e12:.3f} T coins/s, copy {ceil['copy_GBps']:.0f} GB/s")
 
+    tuned = None
+    if not args.no_autotune:
+        # launch-shape tuning on this query (results unchanged by any shape),
+        # before the warm-up and outside the timed region
+        pct, tms = binding.autotune(G, seeds_dev, theta, RNG_SEED)
+        tuned = {"grid0_pct_of_residency": pct, "best_pass_ms_while_tuning": tms}
+        log(f"autotune: tier-0 grid {pct}% of its LDS residency ({tms:.2f} ms per pass while tuning)")
     gain = torch.empty(g.n, dtype=torch.int64, device=dev)
     total = torch.empty(1, dtype=torch.int64, device=dev)
     for i in range(args.warmup):
@@ -483,6 +491,7 @@ def main():
         },
         "ceilings": ceil,
         "graph_ingest_ms": ingest_ms,
+        "autotune": tuned,
     }
     if args.solves > 0:
         res.update(solve_latency(args, binding, G, seeds_dev, k, theta, dev))

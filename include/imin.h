@@ -524,6 +524,23 @@ imin_status_t imin_sandimin(imin_graph_t g, const int32_t* seeds, int32_t n_seed
                             imin_sandimin_info_t* info);
 
 /*
+ * imin_autotune -- choose the launch shape of the from-scratch world passes
+ * for a graph: the tier-0 world launch's workgroup count, as a percentage
+ * (50, 75, 100, 150, 200 or 300) of its LDS residency on the device.  Each
+ * candidate runs from-scratch passes of the given query (worlds [0, theta),
+ * three each, the first warming the caches); every candidate must produce
+ * the same gains and total (a difference is IMIN_ERR_INTERNAL), and the
+ * fastest is kept on the handle for every later call on it.  grid0_pct: HOST,
+ * out; pass_ms: HOST, out, optional (the chosen shape's best pass time).
+ * imin_set_launch_shape sets the percentage directly (0: the default).
+ * Launch shapes never change any result; they only move time.  Calls given a
+ * workspace keep the default shape (their layout is fixed when sized).
+ */
+imin_status_t imin_autotune(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta,
+                            uint64_t rng_seed, void* stream, int32_t* grid0_pct, float* pass_ms);
+imin_status_t imin_set_launch_shape(imin_graph_t g, int32_t grid0_pct);
+
+/*
  * Scratch device memory of imin_solve and imin_evaluate comes from a block
  * cache, per device: a block released at the end of a call stays allocated
  * for the next call (a request reuses a cached block of at most twice its

@@ -155,6 +155,10 @@ def load():
     lib.imin_lsbm.argtypes = [P, P, i32, i32, ctypes.c_double, ctypes.c_double, ctypes.c_double, u64, P, P, P,
                               ctypes.POINTER(LsbmInfo)]
     lib.imin_lsbm.restype = st
+    lib.imin_autotune.argtypes = [P, P, i32, i64, u64, P, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_float)]
+    lib.imin_autotune.restype = st
+    lib.imin_set_launch_shape.argtypes = [P, i32]
+    lib.imin_set_launch_shape.restype = st
     lib.imin_last_solve_incremental.argtypes = []
     lib.imin_last_solve_incremental.restype = i32
     lib.imin_world_sizes.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P]
@@ -829,3 +833,22 @@ def sandimin(graph: Graph, seeds, k: int, eps: float = 0.2, beta: float = 0.1, g
 def last_solve_incremental() -> int:
     """1 when this thread's last blocking solve ran incremental rounds, 0 plain, -1 none."""
     return int(load().imin_last_solve_incremental())
+
+
+def autotune(graph: Graph, seeds, theta: int, rng_seed: int = 0):
+    """(grid0_pct, pass_ms): the tier-0 launch shape imin_autotune keeps for the graph."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    s = _dev(seeds, torch.int32, dev)
+    pct = ctypes.c_int32(0)
+    ms = ctypes.c_float(0.0)
+    with torch.cuda.device(dev):
+        _check(lib.imin_autotune(graph.handle, _ptr(s), int(s.numel()), int(theta),
+                                 int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), ctypes.byref(pct), ctypes.byref(ms)))
+    return int(pct.value), float(ms.value)
+
+
+def set_launch_shape(graph: Graph, grid0_pct: int):
+    """imin_set_launch_shape: 0 restores the default shape."""
+    _check(load().imin_set_launch_shape(graph.handle, int(grid0_pct)))

@@ -37,6 +37,9 @@ struct imin_graph {
     // the same four figures as raised on the device by enqueued solves
     // (bump entries and extra edges per world, tier-1 and tier-2 shares)
     unsigned long long* hints_dev = nullptr;
+    // launch shape chosen by imin_autotune: the tier-0 world launch's
+    // workgroups in percent of its LDS residency (0: the default, 100)
+    std::atomic<int32_t> tuned_grid0_pct{0};
     // made on first use and kept until destroy: host copies of the graph and
     // the in-edges on the device (Global Sampling)
     std::mutex aux_mu;
@@ -872,6 +875,10 @@ struct Session {
         if ((e = sel_u.alloc(sel_parts)) != hipSuccess) return e;
         if ((e = sel_d.alloc(sel_parts)) != hipSuccess) return e;
         grid0 = cus * imin::world_tier_blocks_per_cu(0);
+        if (gh && !ws) {  // an enqueued solve's layout is fixed when its workspace is sized
+            const int32_t pct = gh->tuned_grid0_pct.load(std::memory_order_relaxed);
+            if (pct > 0) grid0 = std::max(cus, (int)((long long)grid0 * pct / 100));
+        }
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
         // changed-world update: label-rule and replay workgroups of one launch
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
@@ -2075,6 +2082,78 @@ static imin_status_t reach_counts_impl(imin_graph_t g, const int32_t* seeds, int
     return IMIN_OK;
 }
 
+// Launch-shape tuning: from-scratch passes of the caller's query at several
+// tier-0 grid sizes, the fastest kept on the handle.  Every candidate must
+// give the same gains and total (the world-to-workgroup mapping never
+// changes an integer); a difference is reported as IMIN_ERR_INTERNAL.
+static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta,
+                                   uint64_t rng_seed, void* stream, int32_t* best_pct, float* best_ms) {
+    if (!g || !seeds || !best_pct || theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
+    static const int32_t kPct[] = {50, 75, 100, 150, 200, 300};
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n = (size_t)g->g.n;
+    DevArray<int64_t> gain, total;
+    IMIN_TRY(gain.alloc(n));
+    IMIN_TRY(total.alloc(1));
+    std::vector<int64_t> ref, cur;
+    int64_t ref_total = -1;
+    hipEvent_t e0 = event_acquire(), e1 = event_acquire();
+    if (!e0 || !e1) {
+        event_release(e0);
+        event_release(e1);
+        return IMIN_ERR_DEVICE;
+    }
+    const int32_t saved = g->tuned_grid0_pct.load();
+    int32_t best = 100;
+    float best_t = 0.f;
+    imin_status_t st = IMIN_OK;
+    for (int32_t pct : kPct) {
+        g->tuned_grid0_pct.store(pct);
+        float t_min = 0.f;
+        for (int rep = 0; rep < 3 && st == IMIN_OK; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) st = IMIN_ERR_DEVICE;
+            if (st == IMIN_OK)
+                st = evaluate_impl(g, seeds, n_seeds, nullptr, 0, 0, theta, rng_seed, stream, gain.p, total.p,
+                                   nullptr, nullptr, nullptr);
+            float t = 0.f;
+            if (st == IMIN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                                  hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+                st = IMIN_ERR_DEVICE;
+            if (rep > 0 && (t_min == 0.f || t < t_min)) t_min = t;  // the first call warms the caches
+        }
+        if (st != IMIN_OK) break;
+        cur.resize(n);
+        int64_t tot = 0;
+        if (hipMemcpy(cur.data(), gain.p, n * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(&tot, total.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess) {
+            st = IMIN_ERR_DEVICE;
+            break;
+        }
+        if (ref_total < 0) {
+            ref.swap(cur);
+            ref_total = tot;
+        } else if (tot != ref_total || cur != ref) {
+            st = IMIN_ERR_INTERNAL;
+            break;
+        }
+        if (best_t == 0.f || t_min < best_t) {
+            best_t = t_min;
+            best = pct;
+        }
+    }
+    event_release(e0);
+    event_release(e1);
+    (void)hipGetLastError();
+    if (st != IMIN_OK) {
+        g->tuned_grid0_pct.store(saved);
+        return st;
+    }
+    g->tuned_grid0_pct.store(best);
+    *best_pct = best;
+    if (best_ms) *best_ms = best_t;
+    return IMIN_OK;
+}
+
 // No C++ exception crosses the boundary: host allocations that fail inside a
 // call end it with IMIN_ERR_NOMEM (its session drains its stream while
 // unwinding).
@@ -2311,6 +2390,23 @@ imin_status_t imin_reach_counts(imin_graph_t g, const int32_t* seeds, int32_t n_
     } catch (...) {
         return IMIN_ERR_INTERNAL;
     }
+}
+
+imin_status_t imin_autotune(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta, uint64_t rng_seed,
+                            void* stream, int32_t* grid0_pct, float* pass_ms) {
+    try {
+        return autotune_impl(g, seeds, n_seeds, theta, rng_seed, stream, grid0_pct, pass_ms);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_set_launch_shape(imin_graph_t g, int32_t grid0_pct) {
+    if (!g || grid0_pct < 0 || grid0_pct > 1000) return IMIN_ERR_INVALID;
+    g->tuned_grid0_pct.store(grid0_pct);
+    return IMIN_OK;
 }
 
 imin_status_t imin_cache_release(void) {

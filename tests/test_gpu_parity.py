@@ -729,3 +729,25 @@ def test_solve_with_worlds_labelled_by_replays(B, oracle_mod, monkeypatch):
     np.testing.assert_array_equal(res.gains, base.gains)
     np.testing.assert_array_equal(res.spread_totals, base.spread_totals)
     _check_rounds_against_oracle(oracle_mod, g, seeds, theta, rng, res, (0, 1, 36))
+
+
+def test_autotune_keeps_every_result(B, oracle_mod):
+    """The launch-shape tuner times several tier-0 grid sizes (checking on the
+    device that each gives the same gains) and keeps the fastest; passes and
+    solves after it still equal the oracle."""
+    g = synth.random_small_graph(3000, 15000, seed=404, prob="mixed")
+    seeds = np.array([7, 700, 2900], np.int32)
+    G = B.Graph.from_synth(g)
+    pct, ms = B.autotune(G, seeds, 4000, 5)
+    _log(f"autotune: grid0 {pct}% of residency, {ms:.3f} ms per pass")
+    assert pct in (50, 75, 100, 150, 200, 300) and ms > 0
+    q = oracle_mod.Query(g, seeds)
+    gain, total = B.evaluate(G, seeds, 0, 4000, 5)
+    want_gain, want_total = q.eval(5, 0, 4000)
+    assert total == want_total
+    np.testing.assert_array_equal(gain, want_gain)
+    res = B.solve(G, seeds, 6, 4000, 5)
+    want = q.solve(6, 4000, 5)
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+    B.set_launch_shape(G, 0)
