@@ -147,7 +147,7 @@ def _solve_alone(binding, Gs, queries, label):
 
 
 def run_many(args, binding, dev):
-    """Config B: a batch of mixed queries on the weighted-cascade twin of the
+    """A batch of mixed queries on the weighted-cascade twin of the
     1M-node graph, solved one after another and then all submitted at once
     to the serving runtime (pool admission, several streams)."""
     import numpy as np
@@ -203,9 +203,10 @@ def run_many(args, binding, dev):
 
 
 def run_serve(args, binding, dev):
-    """Config V: Poisson arrivals over three resident weighted-cascade graphs
-    against the serving runtime, next to one queue served one query at a
-    time (each query's service time measured alone)."""
+    """Poisson arrivals over resident weighted-cascade graphs (default: the
+    100K-, 1M- and 4M-node ones) against the serving runtime, next to one
+    queue served one query at a time (each query's service time measured
+    alone)."""
     import threading
 
     import numpy as np

@@ -446,7 +446,7 @@ imin_status_t imin_world_sizes(imin_graph_t g, const int32_t* seeds, int32_t n_s
  * imin_lrr_coverage: Cov(set) over the LRR sets of samples [0, theta).
  * The graph's in-edges and a host copy of the graph are made on a handle's
  * first use here and kept until imin_graph_destroy.  Sampling takes 12 bytes
- * per node per sampling slot (IMIN_LRR_BUDGET, default 4 GiB, bounds the
+ * per node per sampling slot (IMIN_LRR_BUDGET, default 16 GiB, bounds the
  * slots).
  */
 imin_status_t imin_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, void* stream, int32_t* out,
@@ -527,11 +527,13 @@ imin_status_t imin_sandimin(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  * imin_autotune -- choose the launch shape of the from-scratch world passes
  * for a graph: the tier-0 world launch's workgroup count, as a percentage
  * (50, 75, 100, 150, 200 or 300) of its LDS residency on the device.  Each
- * candidate runs from-scratch passes of the given query (worlds [0, theta),
- * three each, the first warming the caches); every candidate must produce
- * the same gains and total (a difference is IMIN_ERR_INTERNAL), and the
- * fastest is kept on the handle for every later call on it.  grid0_pct: HOST,
- * out; pass_ms: HOST, out, optional (the chosen shape's best pass time).
+ * candidate runs seven from-scratch passes of the given query (worlds
+ * [0, theta)), the candidates taking turns, the first round warming the
+ * caches; every candidate must produce the same gains and total (a
+ * difference is IMIN_ERR_INTERNAL).  A shape replaces the default (100) only
+ * when its median pass is at least 3% faster, and the choice is kept on the
+ * handle for every later call on it.  grid0_pct: HOST, out; pass_ms: HOST,
+ * out, optional (the chosen shape's median pass time).
  * imin_set_launch_shape sets the percentage directly (0: the default).
  * Launch shapes never change any result; they only move time.  Calls given a
  * workspace keep the default shape (their layout is fixed when sized).

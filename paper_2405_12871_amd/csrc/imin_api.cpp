@@ -519,14 +519,15 @@ struct Session {
     DevArray<int32_t> lrr_stamp, lrr_cone, lrr_lst, lrr_epoch, lrr_vprime;
 
     // the sampling slots and V'_s of Global Sampling: as many slots as
-    // IMIN_LRR_BUDGET (default 4 GiB) allows at 12 bytes per node, at most
-    // four per compute unit
+    // IMIN_LRR_BUDGET (default 16 GiB) allows at 12 bytes per node, at most
+    // sixteen per compute unit (a sample is one wave and mostly waits on
+    // dependent loads, so many are kept in flight)
     imin_status_t setup_lrr(imin_graph_t h, const std::vector<int32_t>& vprime) {
         const int32_t *in_off = nullptr, *in_src = nullptr, *in_eid = nullptr;
         if (!imin::graph_in_edges(h, &in_off, &in_src, &in_eid)) return IMIN_ERR_NOMEM;
         const size_t n = (size_t)g.n;
-        const size_t budget = env_size("IMIN_LRR_BUDGET", (size_t)4 << 30);
-        const size_t slots = std::max<size_t>(1, std::min<size_t>(budget / (12 * n), (size_t)cu_count() * 4));
+        const size_t budget = env_size("IMIN_LRR_BUDGET", (size_t)16 << 30);
+        const size_t slots = std::max<size_t>(1, std::min<size_t>(budget / (12 * n), (size_t)cu_count() * 16));
         IMIN_TRY(lrr_stamp.alloc(slots * n));
         IMIN_TRY(lrr_cone.alloc(slots * n));
         IMIN_TRY(lrr_lst.alloc(slots * n));
@@ -2089,7 +2090,9 @@ static imin_status_t reach_counts_impl(imin_graph_t g, const int32_t* seeds, int
 static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta,
                                    uint64_t rng_seed, void* stream, int32_t* best_pct, float* best_ms) {
     if (!g || !seeds || !best_pct || theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
-    static const int32_t kPct[] = {50, 75, 100, 150, 200, 300};
+    static const int32_t kPct[] = {100, 50, 75, 150, 200, 300};  // the default first
+    constexpr int kCand = (int)(sizeof(kPct) / sizeof(kPct[0]));
+    constexpr int kReps = 7;  // the first round warms the caches
     hipStream_t s = (hipStream_t)stream;
     const size_t n = (size_t)g->g.n;
     DevArray<int64_t> gain, total;
@@ -2104,13 +2107,13 @@ static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t
         return IMIN_ERR_DEVICE;
     }
     const int32_t saved = g->tuned_grid0_pct.load();
-    int32_t best = 100;
-    float best_t = 0.f;
+    std::vector<std::vector<float>> times(kCand);
     imin_status_t st = IMIN_OK;
-    for (int32_t pct : kPct) {
-        g->tuned_grid0_pct.store(pct);
-        float t_min = 0.f;
-        for (int rep = 0; rep < 3 && st == IMIN_OK; ++rep) {
+    // candidates interleaved, so that drift in the device's state spreads
+    // over all of them
+    for (int rep = 0; rep < kReps && st == IMIN_OK; ++rep) {
+        for (int c = 0; c < kCand && st == IMIN_OK; ++c) {
+            g->tuned_grid0_pct.store(kPct[c]);
             if (hipEventRecord(e0, s) != hipSuccess) st = IMIN_ERR_DEVICE;
             if (st == IMIN_OK)
                 st = evaluate_impl(g, seeds, n_seeds, nullptr, 0, 0, theta, rng_seed, stream, gain.p, total.p,
@@ -2119,26 +2122,22 @@ static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t
             if (st == IMIN_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                                   hipEventElapsedTime(&t, e0, e1) != hipSuccess))
                 st = IMIN_ERR_DEVICE;
-            if (rep > 0 && (t_min == 0.f || t < t_min)) t_min = t;  // the first call warms the caches
-        }
-        if (st != IMIN_OK) break;
-        cur.resize(n);
-        int64_t tot = 0;
-        if (hipMemcpy(cur.data(), gain.p, n * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
-            hipMemcpy(&tot, total.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess) {
-            st = IMIN_ERR_DEVICE;
-            break;
-        }
-        if (ref_total < 0) {
-            ref.swap(cur);
-            ref_total = tot;
-        } else if (tot != ref_total || cur != ref) {
-            st = IMIN_ERR_INTERNAL;
-            break;
-        }
-        if (best_t == 0.f || t_min < best_t) {
-            best_t = t_min;
-            best = pct;
+            if (st != IMIN_OK) break;
+            if (rep > 0) times[(size_t)c].push_back(t);
+            if (rep == 0) {
+                // every shape gives the same integers
+                cur.resize(n);
+                int64_t tot = 0;
+                if (hipMemcpy(cur.data(), gain.p, n * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess ||
+                    hipMemcpy(&tot, total.p, sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess) {
+                    st = IMIN_ERR_DEVICE;
+                } else if (ref_total < 0) {
+                    ref.swap(cur);
+                    ref_total = tot;
+                } else if (tot != ref_total || cur != ref) {
+                    st = IMIN_ERR_INTERNAL;
+                }
+            }
         }
     }
     event_release(e0);
@@ -2148,8 +2147,23 @@ static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t
         g->tuned_grid0_pct.store(saved);
         return st;
     }
-    g->tuned_grid0_pct.store(best);
-    *best_pct = best;
+    auto median = [](std::vector<float> v) {
+        std::sort(v.begin(), v.end());
+        return v[v.size() / 2];
+    };
+    // another shape replaces the default only when its median pass is at
+    // least 3% faster
+    int best = 0;
+    float best_t = median(times[0]);
+    for (int c = 1; c < kCand; ++c) {
+        const float t = median(times[(size_t)c]);
+        if (t < best_t * 0.97f && (best == 0 || t < best_t)) {
+            best = c;
+            best_t = t;
+        }
+    }
+    g->tuned_grid0_pct.store(kPct[best]);
+    *best_pct = kPct[best];
     if (best_ms) *best_ms = best_t;
     return IMIN_OK;
 }

@@ -18,7 +18,7 @@
 // no entry edge exists.  Under weighted cascade probabilities the cone is
 // small, as a reverse random walk.
 //
-// One workgroup per sample.  Each slot (workgroup) owns a stamp per node and
+// One wave per sample.  Each slot (workgroup) owns a stamp per node and
 // two lists sized for the whole graph, so any cone fits; a stamp of 2t+1
 // marks the cone of the slot's t-th sample and 2t+2 its LRR set, so stamps
 // are never cleared between samples.
@@ -30,7 +30,7 @@
 namespace imin {
 namespace {
 
-constexpr int kLrrNT = 256;
+constexpr int kLrrNT = 64;  // one wave per sample: most cones are small
 
 __device__ __forceinline__ bool coin_live(const GraphDev& g, const QueryDev& q, uint32_t w, int32_t e) {
     const uint32_t t = g.thr[e];

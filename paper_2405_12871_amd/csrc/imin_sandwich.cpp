@@ -129,6 +129,10 @@ struct Estimates {
     std::vector<int64_t> counts;
 };
 
+// One pass draws each batch's worlds once for both the sizes and the reach
+// counts; the batch where the sum crosses the threshold is corrected to its
+// first N - w0 worlds by drawing its shorter part again (the counts of
+// disjoint world ranges add up).
 imin_status_t spread_estimate(const Query& q, double beta, double delta, uint64_t key_sra, Estimates& est) {
     const double ups1 = sra_upsilon1(beta, delta / 6.0);
     const double need = (double)q.b * ups1;
@@ -139,11 +143,19 @@ imin_status_t spread_estimate(const Query& q, double beta, double delta, uint64_
     const int64_t kMaxBatch = (int64_t)1 << 22;
     SW_TRY_HIP(sizes.alloc((size_t)kMaxBatch));
     std::vector<int32_t> hs;
+    std::vector<int64_t> hc;
+    est.counts.assign((size_t)n, 0);
+    auto add_counts = [&](int64_t sign) {
+        const imin_status_t st = to_host(hc, counts.p, (size_t)n);
+        if (st == IMIN_OK)
+            for (size_t v = 0; v < (size_t)n; ++v) est.counts[v] += sign * hc[v];
+        return st;
+    };
     int64_t total = 0, w0 = 0, batch = 4096, N = 0;
     while (N == 0) {
         batch = std::min(batch, kMaxBatch);
         if (w0 + batch > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;  // world ids are 32-bit
-        SW_TRY(imin_world_sizes(q.g, q.seeds_dev, q.n_seeds, nullptr, 0, w0, batch, key_sra, q.s, sizes.p));
+        SW_TRY(imin_reach_counts(q.g, q.seeds_dev, q.n_seeds, w0, batch, key_sra, q.s, counts.p, sizes.p));
         SW_TRY(to_host(hs, sizes.p, (size_t)batch));
         for (int64_t i = 0; i < batch; ++i) {
             total += hs[(size_t)i];
@@ -152,13 +164,27 @@ imin_status_t spread_estimate(const Query& q, double beta, double delta, uint64_
                 break;
             }
         }
+        if (N == 0) {
+            SW_TRY(add_counts(1));
+        } else if (N - w0 <= w0 + batch - N) {
+            // keep worlds [w0, N): draw them again
+            SW_TRY(imin_reach_counts(q.g, q.seeds_dev, q.n_seeds, w0, N - w0, key_sra, q.s, counts.p, nullptr));
+            SW_TRY(add_counts(1));
+        } else {
+            // drop worlds [N, w0 + batch) from the batch's counts
+            SW_TRY(add_counts(1));
+            if (w0 + batch > N) {
+                SW_TRY(imin_reach_counts(q.g, q.seeds_dev, q.n_seeds, N, w0 + batch - N, key_sra, q.s, counts.p,
+                                         nullptr));
+                SW_TRY(add_counts(-1));
+            }
+        }
         w0 += batch;
         batch *= 2;
     }
     est.N = N;
     est.i_hat = (double)q.b * ups1 / (double)N;
-    SW_TRY(imin_reach_counts(q.g, q.seeds_dev, q.n_seeds, 0, N, key_sra, q.s, counts.p, nullptr));
-    return to_host(est.counts, counts.p, (size_t)n);
+    return IMIN_OK;
 }
 
 double opt_lower(const Query& q, const Estimates& est, int32_t k) {
