@@ -67,11 +67,13 @@ __global__ __launch_bounds__(kLrrNT) void k_lrr(GraphDev g, QueryDev q, RoundCtl
         }
         __syncthreads();
         // reverse search: v's cone, and the cone nodes with a live edge from a seed
+        // (the wave's lanes share each frontier node's edges: most cones are
+        // a few nodes with a few dozen in-edges between them)
         int lo = 0, hi = 1;
         while (lo < hi) {
-            for (int c = lo + t; c < hi; c += kLrrNT) {
+            for (int c = lo; c < hi; ++c) {
                 const int32_t x = cone[c];
-                for (int32_t j = L.in_off[x]; j < L.in_off[x + 1]; ++j) {
+                for (int32_t j = L.in_off[x] + t; j < L.in_off[x + 1]; j += kLrrNT) {
                     const int32_t u = L.in_src[j];
                     const bool seed = bit_set(q.excl, u);
                     if (!seed && stamp[u] >= e1) continue;  // in the cone already (or a self-loop)
@@ -97,9 +99,9 @@ __global__ __launch_bounds__(kLrrNT) void k_lrr(GraphDev g, QueryDev q, RoundCtl
         // forward closure inside the cone from the entry nodes
         int flo = 0, fhi = min(s_nlst, g.n);
         while (flo < fhi) {
-            for (int c = flo + t; c < fhi; c += kLrrNT) {
+            for (int c = flo; c < fhi; ++c) {
                 const int32_t x = lst[c];
-                for (int32_t e = g.off[x]; e < g.off[x + 1]; ++e) {
+                for (int32_t e = g.off[x] + t; e < g.off[x + 1]; e += kLrrNT) {
                     const int32_t y = g.col[e];
                     if (stamp[y] != e1) continue;  // outside the cone, or in the set already
                     if (!coin_live(g, q, w, e)) continue;
