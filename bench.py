@@ -202,6 +202,68 @@ def run_many(args, binding, dev):
     }), flush=True)
 
 
+def run_packed(args, binding, dev):
+    """A batch of from-scratch passes on the 1M-node workload's graph: each
+    query its own 200 uniform seeds, world range and rng seed, and
+    --packed-worlds worlds.  Timed one after another (imin_evaluate per
+    query) and as one batch (imin_evaluate_batch, tier-0 launches packed);
+    every query's gains and total must be identical both ways."""
+    import numpy as np
+    import torch
+
+    from paper_2405_12871_amd import synth
+    g, seeds0, _, _ = synth.workload("large")
+    G = binding.Graph.from_synth(g, device=dev)
+    rng = np.random.default_rng(0xBA7C)
+    nq, nw = args.packed, args.packed_worlds
+    entries_a, entries_b = [], []
+    for j in range(nq):
+        sd = torch.from_numpy(rng.choice(g.n, 200, replace=False).astype(np.int32)).to(dev)
+        entries_a.append((sd, nw * j, nw, 100 + j, torch.empty(g.n, dtype=torch.int64, device=dev),
+                          torch.empty(1, dtype=torch.int64, device=dev)))
+        entries_b.append((sd, nw * j, nw, 100 + j, torch.empty(g.n, dtype=torch.int64, device=dev),
+                          torch.empty(1, dtype=torch.int64, device=dev)))
+
+    def one_by_one():
+        for sd, wb, wc, seed, gain, total in entries_a:
+            binding.evaluate_device(G, sd, wb, wc, seed, gain, total)
+
+    def batched():
+        binding.evaluate_batch_device(G, entries_b)
+
+    times = {"one_by_one": [], "batched": []}
+    for rep in range(args.packed_reps + 1):  # the first of each is a warm-up
+        for name, fn in (("one_by_one", one_by_one), ("batched", batched)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            if rep:
+                times[name].append(time.perf_counter() - t0)
+        log(f"rep {rep}: " + " ".join(f"{k} {v[-1] * 1e3:.1f} ms" for k, v in times.items() if v))
+    same = all(torch.equal(a[4], b[4]) and torch.equal(a[5], b[5]) for a, b in zip(entries_a, entries_b))
+    t_a, t_b = float(np.median(times["one_by_one"])), float(np.median(times["batched"]))
+    worlds = nq * nw
+    print(json.dumps({
+        "metric": "worlds/s, a batch of from-scratch passes (sample + BFS + dominators + gain sums)",
+        "value": worlds / t_b,
+        "unit": "worlds/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "dtype": "u32+int64",
+        "config": {"workload": f"batched passes: large graph (n={g.n}, m={g.m}, trivalency), {nq} queries of "
+                               f"{nw} worlds, |S| = 200 uniform each", "pack_queries": os.environ.get(
+                                   "IMIN_PACK_QUERIES", "64")},
+        "batched_ms": t_b * 1e3,
+        "one_by_one_ms": t_a * 1e3,
+        "one_by_one_worlds_per_s": worlds / t_a,
+        "speedup_over_one_by_one": t_a / t_b,
+        "reps": args.packed_reps,
+        "identical_to_one_by_one": bool(same),
+    }), flush=True)
+
+
 def run_serve(args, binding, dev):
     """Poisson arrivals over resident weighted-cascade graphs (default: the
     100K-, 1M- and 4M-node ones) against the serving runtime, next to one
@@ -324,6 +386,9 @@ def main():
     ap.add_argument("--graphs", default="wc100k,wc1m,wc4m", help="graphs of --serve")
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--packed", type=int, default=0, help="measure a batch of this many from-scratch passes instead")
+    ap.add_argument("--packed-worlds", type=int, default=2000, help="worlds per query of --packed")
+    ap.add_argument("--packed-reps", type=int, default=5, help="timed repetitions of --packed")
     ap.add_argument("--lsbm-k", type=int, default=100, help="budget of the LSBM measurement")
     ap.add_argument("--lsbm-eps", type=float, default=0.2, help="eps of the LSBM measurement")
     ap.add_argument("--no-lsbm", action="store_true", help="skip the LSBM measurement")
@@ -350,6 +415,9 @@ def main():
         return
     if args.serve > 0:
         run_serve(args, binding, dev)
+        return
+    if args.packed > 0:
+        run_packed(args, binding, dev)
         return
     if args.lsbm_only:
         run_lsbm(args, binding, dev)

@@ -302,6 +302,39 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
                             int64_t* world_edges);
 
 /*
+ * imin_evaluate_batch -- imin_evaluate for several queries on one graph
+ * (each its own seeds, blocked set, world range and rng_seed), whose passes
+ * share one world launch: the worlds of every query that fits one tile and
+ * whose worlds start at tier 0 are packed into a single tier-0 launch; the
+ * larger tiers, the gain reductions and every other query run per query.
+ * Each query's outputs are those imin_evaluate gives it alone.
+ *
+ *   queries     imin_eval_query_t[n_queries], HOST; the pointers in each
+ *               are device pointers, with the meanings of imin_evaluate's
+ *               arguments of the same names (world_size may be NULL)
+ *   n_queries   >= 0; at most IMIN_PACK_QUERIES (default 64) queries share
+ *               a launch, and larger batches are taken in groups
+ *
+ * Every query's pointers and sizes are checked before any work.  Errors
+ * as for imin_evaluate: the first failing query's status is returned, and
+ * the outputs of the other queries of its group are then not all written.
+ */
+typedef struct {
+    const int32_t* seeds;
+    int32_t n_seeds;
+    const int32_t* blocked;
+    int32_t n_blocked;
+    int64_t w_begin;
+    int64_t w_count;
+    uint64_t rng_seed;
+    int64_t* gain;
+    int64_t* total;
+    int32_t* world_size;
+} imin_eval_query_t;
+imin_status_t imin_evaluate_batch(imin_graph_t g, const imin_eval_query_t* queries, int32_t n_queries,
+                                  void* stream);
+
+/*
  * Lower-bound coverage (Section 3.2, the lower bounding function D^L;
  * Section 4.1, CP sequences and coverage; Section 5.1, Max-Coverage).
  *
@@ -445,9 +478,12 @@ imin_status_t imin_world_sizes(imin_graph_t g, const int32_t* seeds, int32_t n_s
  * samples [0, theta); outputs as imin_max_coverage.
  * imin_lrr_coverage: Cov(set) over the LRR sets of samples [0, theta).
  * The graph's in-edges and a host copy of the graph are made on a handle's
- * first use here and kept until imin_graph_destroy.  Sampling takes 12 bytes
- * per node per sampling slot (IMIN_LRR_BUDGET, default 16 GiB, bounds the
- * slots).
+ * first use here and kept until imin_graph_destroy.  Sampling takes 8 bytes
+ * per node per sampling slot: IMIN_LRR_BUDGET (default the smaller of 16 GiB
+ * and a quarter of the device memory free at the first call) bounds the
+ * slots.  The handle keeps them until imin_graph_destroy and lends them to
+ * one call at a time; a call that finds them lent takes its own, within
+ * IMIN_LRR_BUDGET (default 8 GiB), for its duration.
  */
 imin_status_t imin_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, void* stream, int32_t* out,
                           int32_t* count);

@@ -34,6 +34,14 @@ class Query(ctypes.Structure):
                 ("status", ctypes.c_int32), ("device_flags", ctypes.c_uint32)]
 
 
+class EvalQuery(ctypes.Structure):
+    """One entry of imin_evaluate_batch (imin_eval_query_t)."""
+    _fields_ = [("seeds", ctypes.c_void_p), ("n_seeds", ctypes.c_int32), ("blocked", ctypes.c_void_p),
+                ("n_blocked", ctypes.c_int32), ("w_begin", ctypes.c_int64), ("w_count", ctypes.c_int64),
+                ("rng_seed", ctypes.c_uint64), ("gain", ctypes.c_void_p), ("total", ctypes.c_void_p),
+                ("world_size", ctypes.c_void_p)]
+
+
 class LsbmInfo(ctypes.Structure):
     """imin_lsbm_info_t: every intermediate quantity of an LSBM call."""
     _fields_ = [("returned_on", ctypes.c_int32), ("on_size", ctypes.c_int32),
@@ -120,6 +128,8 @@ def load():
     lib.imin_server_destroy.restype = st
     lib.imin_evaluate.argtypes = [P, P, i32, P, i32, i64, i64, u64, P, P, P, P, P, P]
     lib.imin_evaluate.restype = st
+    lib.imin_evaluate_batch.argtypes = [P, ctypes.POINTER(EvalQuery), i32, P]
+    lib.imin_evaluate_batch.restype = st
     lib.imin_status_string.argtypes = [st]
     lib.imin_status_string.restype = ctypes.c_char_p
     lib.imin_last_device_flags.argtypes = []
@@ -548,6 +558,54 @@ def evaluate_device(graph: Graph, seeds_dev, w_begin: int, w_count: int, rng_see
         _check(lib.imin_evaluate(graph.handle, _ptr(seeds_dev), int(seeds_dev.numel()), None, 0, int(w_begin),
                                  int(w_count), int(rng_seed) & 0xFFFFFFFFFFFFFFFF, _stream(dev), _ptr(gain),
                                  _ptr(total), None, None, None))
+
+
+def evaluate_batch(graph: Graph, queries, per_world: bool = False):
+    """imin_evaluate_batch: one estimator pass per query, the tier-0 world
+    launches packed.  queries: a list of dicts with seeds, w_begin, w_count,
+    rng_seed and optionally blocked.  Returns a list of (gain, total) or, with
+    ``per_world``, (gain, total, world_size)."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    keep, out = [], []
+    arr = (EvalQuery * max(len(queries), 1))()
+    for j, qd in enumerate(queries):
+        s = _dev(qd["seeds"], torch.int32, dev)
+        blk = qd.get("blocked", ())
+        blk = list(blk) if not isinstance(blk, torch.Tensor) else blk
+        b = _dev(np.asarray(blk, dtype=np.int32), torch.int32, dev) if len(blk) else None
+        gain = torch.empty(graph.n, dtype=torch.int64, device=dev)
+        total = torch.empty(1, dtype=torch.int64, device=dev)
+        ws = torch.empty(int(qd["w_count"]), dtype=torch.int32, device=dev) if per_world else None
+        keep += [s, b]
+        out.append((gain, total, ws))
+        arr[j] = EvalQuery(_ptr(s), int(s.numel()), _ptr(b), int(b.numel()) if b is not None else 0,
+                           int(qd["w_begin"]), int(qd["w_count"]), int(qd["rng_seed"]) & 0xFFFFFFFFFFFFFFFF,
+                           _ptr(gain), _ptr(total), _ptr(ws))
+    with torch.cuda.device(dev):
+        _check(lib.imin_evaluate_batch(graph.handle, arr, len(queries), _stream(dev)))
+    res = []
+    for gain, total, ws in out:
+        r = [gain.cpu().numpy(), int(total.cpu()[0])]
+        if per_world:
+            r.append(ws.cpu().numpy())
+        res.append(tuple(r))
+    return res
+
+
+def evaluate_batch_device(graph: Graph, entries):
+    """imin_evaluate_batch on device tensors: entries is a list of (seeds_dev,
+    w_begin, w_count, rng_seed, gain, total), gain and total written in place."""
+    torch = _torch()
+    lib = load()
+    dev = graph.device
+    arr = (EvalQuery * max(len(entries), 1))()
+    for j, (sd, wb, wc, seed, gain, total) in enumerate(entries):
+        arr[j] = EvalQuery(_ptr(sd), int(sd.numel()), None, 0, int(wb), int(wc), int(seed) & 0xFFFFFFFFFFFFFFFF,
+                           _ptr(gain), _ptr(total), None)
+    with torch.cuda.device(dev):
+        _check(lib.imin_evaluate_batch(graph.handle, arr, len(entries), _stream(dev)))
 
 
 def cache_release():

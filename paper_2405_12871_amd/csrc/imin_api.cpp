@@ -45,8 +45,21 @@ struct imin_graph {
     std::mutex aux_mu;
     std::unique_ptr<imin::HostGraph> host;
     int32_t* in_off = nullptr;
-    int32_t* in_src = nullptr;
-    int32_t* in_eid = nullptr;
+    int4* in_rec = nullptr;
+    // Global Sampling's slots (a stamp and a list entry per node, an epoch
+    // per slot), kept from one call to the next under aux_mu and lent to one
+    // call at a time: a slot's epoch only grows, so its stamps stay valid and
+    // a later call starts without clearing them
+    int32_t* lrr_stamp = nullptr;
+    int32_t* lrr_list = nullptr;
+    int32_t* lrr_epoch = nullptr;
+    size_t lrr_slots = 0;
+    uint64_t lrr_epoch_bound = 0;  // no slot's epoch is above it
+    bool lrr_lent = false;
+    // V'_s of the last seed set (sorted) Global Sampling was called with
+    bool vp_valid = false;
+    std::vector<int32_t> vp_seeds;
+    std::vector<int32_t> vp_nodes;
 };
 
 namespace {
@@ -516,39 +529,101 @@ struct Session {
     // Global Sampling: samples are LRR sets (Algorithm 3) instead of worlds
     bool lrr = false;
     imin::LrrDev lrr_dev{};
-    DevArray<int32_t> lrr_stamp, lrr_cone, lrr_lst, lrr_epoch, lrr_vprime;
+    DevArray<int32_t> lrr_stamp, lrr_list, lrr_epoch, lrr_vprime;
+    imin_graph* lrr_from = nullptr;  // the graph whose kept slots this call borrowed
+    uint64_t lrr_epoch_bound = 0;    // no slot's epoch is above it
+
+    // Stamps are int32 (2 * epoch + 2), so the slots are cleared before an
+    // epoch could pass this.
+    static constexpr uint64_t kLrrEpochLimit = (uint64_t)1 << 29;
 
     // the sampling slots and V'_s of Global Sampling: as many slots as
-    // IMIN_LRR_BUDGET (default 16 GiB) allows at 12 bytes per node, at most
-    // sixteen per compute unit (a sample is one wave and mostly waits on
-    // dependent loads, so many are kept in flight)
+    // IMIN_LRR_BUDGET (default the smaller of 16 GiB and a quarter of the
+    // free device memory) allows at 8 bytes per node, at most 32 per compute
+    // unit (a sample is one wave and mostly waits on dependent loads, so many
+    // are kept in flight).  The graph keeps its slots for later calls; a call
+    // that finds them lent to another takes its own.
     imin_status_t setup_lrr(imin_graph_t h, const std::vector<int32_t>& vprime) {
-        const int32_t *in_off = nullptr, *in_src = nullptr, *in_eid = nullptr;
-        if (!imin::graph_in_edges(h, &in_off, &in_src, &in_eid)) return IMIN_ERR_NOMEM;
+        const int32_t* in_off = nullptr;
+        const int4* in_rec = nullptr;
+        if (!imin::graph_in_edges(h, &in_off, &in_rec)) return IMIN_ERR_NOMEM;
         const size_t n = (size_t)g.n;
-        const size_t budget = env_size("IMIN_LRR_BUDGET", (size_t)16 << 30);
-        const size_t slots = std::max<size_t>(1, std::min<size_t>(budget / (12 * n), (size_t)cu_count() * 16));
-        IMIN_TRY(lrr_stamp.alloc(slots * n));
-        IMIN_TRY(lrr_cone.alloc(slots * n));
-        IMIN_TRY(lrr_lst.alloc(slots * n));
-        IMIN_TRY(lrr_epoch.alloc(slots));
+        int32_t *stamp = nullptr, *list = nullptr, *epoch = nullptr;
+        size_t slots = 0;
+        {
+            std::lock_guard<std::mutex> lk(h->aux_mu);
+            if (!h->lrr_lent) {
+                if (h->lrr_slots == 0) {
+                    size_t free_b = 0, total_b = 0;
+                    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return IMIN_ERR_DEVICE;
+                    }
+                    const size_t budget = env_size("IMIN_LRR_BUDGET", std::min<size_t>((size_t)16 << 30, free_b / 4));
+                    const size_t want =
+                        std::max<size_t>(1, std::min<size_t>(budget / (8 * n), (size_t)cu_count() * 32));
+                    if (hipMalloc((void**)&h->lrr_stamp, want * n * sizeof(int32_t)) != hipSuccess ||
+                        hipMalloc((void**)&h->lrr_list, want * n * sizeof(int32_t)) != hipSuccess ||
+                        hipMalloc((void**)&h->lrr_epoch, want * sizeof(int32_t)) != hipSuccess) {
+                        (void)hipGetLastError();
+                        if (h->lrr_stamp) (void)hipFree(h->lrr_stamp);
+                        if (h->lrr_list) (void)hipFree(h->lrr_list);
+                        if (h->lrr_epoch) (void)hipFree(h->lrr_epoch);
+                        h->lrr_stamp = h->lrr_list = h->lrr_epoch = nullptr;
+                        return IMIN_ERR_NOMEM;
+                    }
+                    h->lrr_slots = want;
+                    h->lrr_epoch_bound = kLrrEpochLimit + 1;  // cleared before the first launch
+                }
+                h->lrr_lent = true;
+                lrr_from = h;
+                stamp = h->lrr_stamp;
+                list = h->lrr_list;
+                epoch = h->lrr_epoch;
+                slots = h->lrr_slots;
+                lrr_epoch_bound = h->lrr_epoch_bound;
+            }
+        }
+        if (!lrr_from) {
+            slots = std::max<size_t>(1, std::min<size_t>(env_size("IMIN_LRR_BUDGET", (size_t)8 << 30) / (8 * n),
+                                                         (size_t)cu_count() * 32));
+            IMIN_TRY(lrr_stamp.alloc(slots * n));
+            IMIN_TRY(lrr_list.alloc(slots * n));
+            IMIN_TRY(lrr_epoch.alloc(slots));
+            stamp = lrr_stamp.p;
+            list = lrr_list.p;
+            epoch = lrr_epoch.p;
+            lrr_epoch_bound = kLrrEpochLimit + 1;
+        }
         IMIN_TRY(lrr_vprime.alloc(std::max<size_t>(vprime.size(), 1)));
-        IMIN_TRY(imin::launch_fill_i32(lrr_stamp.p, 0, slots * n, s));
-        IMIN_TRY(imin::launch_fill_i32(lrr_epoch.p, 0, slots, s));
         if (!vprime.empty())
             IMIN_TRY(hipMemcpyAsync(lrr_vprime.p, vprime.data(), vprime.size() * sizeof(int32_t),
                                     hipMemcpyHostToDevice, s));
         IMIN_TRY(hipStreamSynchronize(s));  // vprime is a host vector
         lrr_dev.in_off = in_off;
-        lrr_dev.in_src = in_src;
-        lrr_dev.in_eid = in_eid;
+        lrr_dev.in_rec = in_rec;
         lrr_dev.vprime = lrr_vprime.p;
         lrr_dev.nvp = (uint32_t)vprime.size();
         lrr_dev.n_slots = (int32_t)slots;
-        lrr_dev.stamp = lrr_stamp.p;
-        lrr_dev.cone = lrr_cone.p;
-        lrr_dev.lst = lrr_lst.p;
-        lrr_dev.epoch = lrr_epoch.p;
+        lrr_dev.stamp = stamp;
+        lrr_dev.list = list;
+        lrr_dev.epoch = epoch;
+        return IMIN_OK;
+    }
+
+    // before a launch of `count` samples, each slot taking at most
+    // ceil(count / slots) of them: clear the slots first when an epoch could
+    // otherwise pass the limit
+    imin_status_t lrr_reserve(uint64_t count) {
+        const uint64_t slots = (uint64_t)lrr_dev.n_slots;
+        const uint64_t per = (count + slots - 1) / slots;
+        if (per > kLrrEpochLimit) return IMIN_ERR_INVALID;
+        if (lrr_epoch_bound + per > kLrrEpochLimit) {
+            IMIN_TRY(imin::launch_fill_i32(lrr_dev.stamp, 0, (size_t)slots * (size_t)g.n, s));
+            IMIN_TRY(imin::launch_fill_i32(lrr_dev.epoch, 0, (size_t)slots, s));
+            lrr_epoch_bound = 0;
+        }
+        lrr_epoch_bound += per;
         return IMIN_OK;
     }
 
@@ -586,7 +661,18 @@ struct Session {
     // an early return may leave work queued: drain it before any block can
     // be handed to another call
     ~Session() {
-        if (!ws && hipStreamSynchronize(s) != hipSuccess) (void)hipGetLastError();
+        bool drained = true;
+        if (!ws && hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipGetLastError();
+            drained = false;
+        }
+        if (lrr_from) {
+            // slots whose epochs a failed launch may not have written are
+            // cleared before their next use
+            std::lock_guard<std::mutex> lk(lrr_from->aux_mu);
+            lrr_from->lrr_epoch_bound = drained ? lrr_epoch_bound : kLrrEpochLimit + 1;
+            lrr_from->lrr_lent = false;
+        }
     }
     Session(const Session&) = delete;
     Session& operator=(const Session&) = delete;
@@ -1203,12 +1289,17 @@ struct Session {
     // All tiers of a tile in a call with the block cache: the HBM tiers'
     // slots are allocated (and their launches made) only once some world of
     // the tile has been handed to them.
-    imin_status_t launch_tiers_checked(const imin::QueryDev& q, uint32_t wb, uint32_t nw, const imin::TileOut& out) {
+    // With after_tier0 a packed launch has already run tier 0 over the tile
+    // (its worlds too large for it are in list1).
+    imin_status_t launch_tiers_checked(const imin::QueryDev& q, uint32_t wb, uint32_t nw, const imin::TileOut& out,
+                                       bool after_tier0 = false) {
         imin_status_t st;
         if (start_tier >= 2 && (st = ensure_t2()) != IMIN_OK) return st;
         const bool three = tier3_possible();
         const int ready_last = !t2.ready() ? 1 : ((!three || t3.ready()) ? 3 : 2);
-        if ((st = launch_tiers(q, wb, nw, nullptr, out, start_tier, 0, ready_last)) != IMIN_OK) return st;
+        st = after_tier0 ? launch_tiers(q, wb, 0, list1.p, out, 1, 1, ready_last)
+                         : launch_tiers(q, wb, nw, nullptr, out, start_tier, 0, ready_last);
+        if (st != IMIN_OK) return st;
         bool ran2 = ready_last >= 2;
         if (!t2.ready()) {
             if ((st = read_ctl()) != IMIN_OK) return st;
@@ -1280,28 +1371,71 @@ struct Session {
     // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
     // outputs are written at [0, count).  With store_mode (round 0 of a
     // solve) the per-world lists also become the resident store.
-    imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
-                           int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false) {
-        // the exclusions as they stand (blockers may have been added since
-        // the last pass) go into the query's thresholds
+    // The outputs of the tile whose first world is `done`.
+    imin::TileOut tile_out_at(uint64_t done, int32_t* ws_out, int64_t* wsum_out, int64_t* wedges_out, bool keep) {
+        imin::TileOut out = tile_out();
+        out.world_size = ws_out ? ws_out + done : world_size.p;
+        out.world_sum = wsum_out ? wsum_out + done : nullptr;
+        out.world_edges = wedges_out ? wedges_out + done : nullptr;
+        out.keep_edges = keep ? 1 : 0;
+        return out;
+    }
+
+    // Whether a from-scratch pass of `count` worlds can have its tier-0
+    // launch packed with other queries': one tile, worlds starting at tier 0.
+    bool packable(uint64_t count) const {
+        return !lrr && cover == imin::kCoverNone && !unit_counts && !sizes_only && start_tier == 0 &&
+               count <= (uint64_t)tile && count > 0;
+    }
+
+    // The set-up of such a pass (what evaluate does before its first tier-0
+    // launch) and its entry in the packed launch.
+    imin_status_t packed_prepare(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
+                                 imin::PackedQuery& pq) {
         IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.seed_cap, seed_col.p,
                                                seed_thr.p, s));
+        IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+        pq = imin::PackedQuery{};
+        pq.q = q;
+        pq.out = tile_out_at(0, ws_out, nullptr, nullptr, false);
+        pq.out.work = nullptr;  // no per-workgroup tallies for packed launches
+        pq.ctl = ctl.p;
+        pq.next_list = list1.p;
+        pq.w_begin = (uint32_t)w_begin;
+        pq.count = (uint32_t)count;
+        return IMIN_OK;
+    }
+
+    // With after_packed, packed_prepare and a packed tier-0 launch have
+    // already done the first tile's set-up and tier 0.
+    imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
+                           int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false,
+                           bool after_packed = false) {
+        // the exclusions as they stand (blockers may have been added since
+        // the last pass) go into the query's thresholds
+        if (!after_packed)
+            IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.seed_cap, seed_col.p,
+                                                   seed_thr.p, s));
         uint64_t done = 0;
+        bool packed_tile = after_packed;
         while (done < count) {
             const uint64_t nw = std::min<uint64_t>(tile, count - done);
             const bool keep = store_mode && incremental && replay;
             // entries carry parents and labels (replay) or parent positions
             // and subtree sizes (coverage store)
             const bool four = keep || cover == imin::kCoverStore;
-            imin::TileOut out = tile_out();
-            out.world_size = ws_out ? ws_out + done : world_size.p;
-            out.world_sum = wsum_out ? wsum_out + done : nullptr;
-            out.world_edges = wedges_out ? wedges_out + done : nullptr;
-            out.keep_edges = keep ? 1 : 0;
-            IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
-            imin_status_t st = lrr ? (imin::launch_lrr(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, lrr_dev,
-                                                       out, s) == hipSuccess ? IMIN_OK : IMIN_ERR_DEVICE)
-                                   : launch_tiers_checked(q, (uint32_t)(w_begin + done), (uint32_t)nw, out);
+            imin::TileOut out = tile_out_at(done, ws_out, wsum_out, wedges_out, keep);
+            if (!packed_tile) IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+            imin_status_t st = IMIN_OK;
+            if (lrr) {
+                st = lrr_reserve(nw);
+                if (st == IMIN_OK && imin::launch_lrr(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, lrr_dev,
+                                                      out, s) != hipSuccess)
+                    st = IMIN_ERR_DEVICE;
+            } else {
+                st = launch_tiers_checked(q, (uint32_t)(w_begin + done), (uint32_t)nw, out, packed_tile);
+            }
+            packed_tile = false;  // a redone tile runs every tier itself
             if (st != IMIN_OK) return st;
             IMIN_TRY(imin::launch_sum_lengths(wlen.p, (uint32_t)nw, &ctl.p->tile_total, ctl.p, s));
             if (keep) IMIN_TRY(imin::launch_sum_lengths(xlen.p, (uint32_t)nw, &ctl.p->xtile_total, ctl.p, s));
@@ -1530,8 +1664,10 @@ imin_status_t imin_graph_create(int32_t n, int64_t m, const int64_t* row_ptr, co
 imin_status_t imin_graph_destroy(imin_graph_t g) {
     if (!g) return IMIN_OK;
     if (g->in_off) (void)hipFree(g->in_off);
-    if (g->in_src) (void)hipFree(g->in_src);
-    if (g->in_eid) (void)hipFree(g->in_eid);
+    if (g->in_rec) (void)hipFree(g->in_rec);
+    if (g->lrr_stamp) (void)hipFree(g->lrr_stamp);
+    if (g->lrr_list) (void)hipFree(g->lrr_list);
+    if (g->lrr_epoch) (void)hipFree(g->lrr_epoch);
     if (g->g.off) (void)hipFree(g->g.off);
     if (g->g.col) (void)hipFree(g->g.col);
     if (g->g.thr) (void)hipFree(g->g.thr);
@@ -1844,6 +1980,92 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
     return IMIN_OK;
 }
 
+// Several from-scratch passes on one graph: every query is set up as
+// imin_evaluate would set it up; the tier-0 launches of those that fit one
+// tile starting at tier 0 become one packed launch, after which each query
+// finishes its pass (larger tiers, reduction) as usual.
+static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t* qs, int32_t nq, void* stream) {
+    g_last_flags = 0;
+    if (!g || nq < 0 || (nq > 0 && !qs)) return IMIN_ERR_INVALID;
+    for (int32_t j = 0; j < nq; ++j) {
+        const imin_eval_query_t& a = qs[j];
+        if (!a.seeds || !a.gain || !a.total) return IMIN_ERR_INVALID;
+        if (a.n_seeds < 1 || a.n_seeds > g->g.n || a.n_blocked < 0 || (a.n_blocked > 0 && !a.blocked))
+            return IMIN_ERR_INVALID;
+        if (a.w_begin < 0 || a.w_count < 1 || a.w_begin + a.w_count > ((int64_t)1 << 32)) return IMIN_ERR_INVALID;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t group = (int32_t)std::max<size_t>(1, std::min<size_t>(env_size("IMIN_PACK_QUERIES", 64), 4096));
+    // Sessions nest their release scopes (each defers the blocks released
+    // while it is the newest), so they end newest first, on every path.
+    struct SessionStack {
+        std::vector<std::unique_ptr<Session>> v;
+        ~SessionStack() {
+            while (!v.empty()) v.pop_back();
+        }
+        Session& back() { return *v.back(); }
+        Session& operator[](size_t i) { return *v[i]; }
+    };
+    for (int32_t j0 = 0; j0 < nq; j0 += group) {
+        const int32_t nb = std::min(group, nq - j0);
+        SessionStack ss;
+        std::vector<imin::QueryDev> qd((size_t)nb);
+        std::vector<imin::PackedQuery> pk;
+        std::vector<uint8_t> packed((size_t)nb, 0);
+        uint64_t first = 0;
+        int grid = 0;
+        for (int32_t j = 0; j < nb; ++j) {
+            const imin_eval_query_t& a = qs[j0 + j];
+            ss.v.push_back(std::make_unique<Session>(g->g, s, g));
+            Session& x = ss.back();
+            imin_status_t st = x.init((uint64_t)a.w_count, false);
+            if (st != IMIN_OK) return st;
+            st = setup_query(x, a.seeds, a.n_seeds, a.blocked, a.n_blocked, a.rng_seed, qd[(size_t)j]);
+            if (st != IMIN_OK) return st;
+            IMIN_TRY(imin::launch_fill_i64(x.gain.p, 0, (size_t)g->g.n, s));
+            IMIN_TRY(imin::launch_ctl_reset_round(x.ctl.p, s));
+            if (x.packable((uint64_t)a.w_count) && first + (uint64_t)a.w_count <= 0xFFFFFFFFull) {
+                imin::PackedQuery pq;
+                st = x.packed_prepare(qd[(size_t)j], (uint64_t)a.w_begin, (uint64_t)a.w_count, a.world_size, pq);
+                if (st != IMIN_OK) return st;
+                pq.first = (uint32_t)first;
+                first += (uint64_t)a.w_count;
+                pk.push_back(pq);
+                packed[(size_t)j] = 1;
+                grid = std::max(grid, x.grid0);
+            }
+        }
+        DevArray<imin::PackedQuery> pk_dev;
+        DevArray<uint32_t> counter;
+        if (!pk.empty()) {
+            IMIN_TRY(pk_dev.alloc(pk.size()));
+            IMIN_TRY(counter.alloc(1));
+            IMIN_TRY(hipMemcpyAsync(pk_dev.p, pk.data(), pk.size() * sizeof(imin::PackedQuery),
+                                    hipMemcpyHostToDevice, s));
+            IMIN_TRY(imin::launch_fill_i32((int32_t*)counter.p, 0, 1, s));
+            IMIN_TRY(imin::launch_world_tier0_packed(g->g, pk_dev.p, (int)pk.size(), (uint32_t)first, counter.p, grid,
+                                                     s));
+        }
+        for (int32_t j = 0; j < nb; ++j) {
+            const imin_eval_query_t& a = qs[j0 + j];
+            Session& x = ss[(size_t)j];
+            imin_status_t st = x.evaluate(qd[(size_t)j], (uint64_t)a.w_begin, (uint64_t)a.w_count, a.world_size,
+                                          nullptr, nullptr, false, packed[(size_t)j] != 0);
+            if (st != IMIN_OK) return st;
+            IMIN_TRY(hipMemcpyAsync(a.gain, x.gain.p, (size_t)g->g.n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+            IMIN_TRY(hipMemcpyAsync(a.total, &x.ctl.p->total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+            st = x.read_ctl();
+            if (st != IMIN_OK) return st;
+            if (x.hctl.p->flags & ~imin::kFlagDataMask) {
+                g_last_flags = x.hctl.p->flags;
+                return IMIN_ERR_INTERNAL;
+            }
+            x.finish();
+        }
+    }
+    return IMIN_OK;
+}
+
 // ---- lower-bound coverage (Sections 4.1 and 5.1)
 
 static imin_status_t check_coverage_args(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta) {
@@ -1864,7 +2086,9 @@ static int bit_length(unsigned long long v) {
 
 // V'_s of a seed set given in device memory (Global Sampling): seeds are
 // checked on the host first (range), then the search runs on the handle's
-// host copy of the graph
+// host copy of the graph.  The handle keeps the last seed set's V'_s, so the
+// calls of one solver (every iteration samples for the same seeds) search
+// once.
 static imin_status_t lrr_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, hipStream_t s,
                                 std::vector<int32_t>& vp) {
     std::vector<int32_t> hs((size_t)n_seeds);
@@ -1872,9 +2096,22 @@ static imin_status_t lrr_vprime(imin_graph_t g, const int32_t* seeds, int32_t n_
     IMIN_TRY(hipStreamSynchronize(s));
     for (int32_t v : hs)
         if (v < 0 || v >= g->g.n) return IMIN_ERR_DATA;
+    std::vector<int32_t> key(hs);
+    std::sort(key.begin(), key.end());
+    {
+        std::lock_guard<std::mutex> lk(g->aux_mu);
+        if (g->vp_valid && g->vp_seeds == key) {
+            vp = g->vp_nodes;
+            return IMIN_OK;
+        }
+    }
     const imin::HostGraph* h = imin::graph_host(g);
     if (!h) return IMIN_ERR_DEVICE;
     vp = imin::reachable_nonseeds(*h, hs);
+    std::lock_guard<std::mutex> lk(g->aux_mu);
+    g->vp_seeds = std::move(key);
+    g->vp_nodes = vp;
+    g->vp_valid = true;
     return IMIN_OK;
 }
 
@@ -2205,43 +2442,39 @@ const HostGraph* graph_host(imin_graph_t g) {
     return g->host.get();
 }
 
-bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int32_t** in_src, const int32_t** in_eid) {
+bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int4** in_rec) {
     const HostGraph* h = graph_host(g);
     if (!h) return false;
     std::lock_guard<std::mutex> lk(g->aux_mu);
     if (!g->in_off) {
         // counting sort of the edges by head
         const size_t n = (size_t)h->n, m = (size_t)h->m;
-        std::vector<int32_t> off(n + 1, 0), src(std::max<size_t>(m, 1)), eid(std::max<size_t>(m, 1));
+        std::vector<int32_t> off(n + 1, 0);
+        std::vector<int4> rec(std::max<size_t>(m, 1), int4{0, 0, 0, 0});
         for (size_t e = 0; e < m; ++e) off[(size_t)h->col[e] + 1] += 1;
         for (size_t v = 0; v < n; ++v) off[v + 1] += off[v];
         std::vector<int32_t> cur(off.begin(), off.end() - 1);
         for (size_t u = 0; u < n; ++u)
             for (int64_t e = h->row_ptr[u]; e < h->row_ptr[u + 1]; ++e) {
                 const int32_t at = cur[(size_t)h->col[(size_t)e]]++;
-                src[(size_t)at] = (int32_t)u;
-                eid[(size_t)at] = (int32_t)e;
+                rec[(size_t)at] = int4{(int32_t)u, (int32_t)e, (int32_t)h->thr[(size_t)e], 0};
             }
-        int32_t *a = nullptr, *b = nullptr, *c = nullptr;
+        int32_t* a = nullptr;
+        int4* b = nullptr;
         if (hipMalloc((void**)&a, off.size() * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc((void**)&b, src.size() * sizeof(int32_t)) != hipSuccess ||
-            hipMalloc((void**)&c, eid.size() * sizeof(int32_t)) != hipSuccess ||
+            hipMalloc((void**)&b, rec.size() * sizeof(int4)) != hipSuccess ||
             hipMemcpy(a, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(b, src.data(), src.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess ||
-            hipMemcpy(c, eid.data(), eid.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) {
+            hipMemcpy(b, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
             (void)hipGetLastError();
             if (a) (void)hipFree(a);
             if (b) (void)hipFree(b);
-            if (c) (void)hipFree(c);
             return false;
         }
         g->in_off = a;
-        g->in_src = b;
-        g->in_eid = c;
+        g->in_rec = b;
     }
     *in_off = g->in_off;
-    *in_src = g->in_src;
-    *in_eid = g->in_eid;
+    *in_rec = g->in_rec;
     return true;
 }
 
@@ -2307,6 +2540,17 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
     try {
         return evaluate_impl(g, seeds, n_seeds, blocked, n_blocked, w_begin, w_count, rng_seed, stream, gain, total,
                              world_size, world_sum, world_edges);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
+imin_status_t imin_evaluate_batch(imin_graph_t g, const imin_eval_query_t* queries, int32_t n_queries,
+                                  void* stream) {
+    try {
+        return evaluate_batch_impl(g, queries, n_queries, stream);
     } catch (const std::bad_alloc&) {
         return IMIN_ERR_NOMEM;
     } catch (...) {

@@ -230,15 +230,13 @@ enum : int {
 // per-slot state (one slot per workgroup of the sampling launch).
 struct LrrDev {
     const int32_t* in_off;  // [n+1] in-edges of each node
-    const int32_t* in_src;  // [m]   their tails
-    const int32_t* in_eid;  // [m]   their CSR slots (the edge id of the coin)
+    const int4* in_rec;     // [m]   each in-edge as {tail, CSR slot (the coin's edge id), threshold, 0}
     const int32_t* vprime;  // [nvp] V'_s ascending
     uint32_t nvp;
     int32_t n_slots;
-    int32_t* stamp;         // [slots][n] 2t+1: in the t-th sample's cone, 2t+2: in its LRR set (zero at start)
-    int32_t* cone;          // [slots][n]
-    int32_t* lst;           // [slots][n]
-    int32_t* epoch;         // [slots] samples the slot has taken (zero at start)
+    int32_t* stamp;         // [slots][n] 2t+1: in the slot's t-th sample's cone, 2t+2: in its LRR set
+    int32_t* list;          // [slots][n] the cone, then the LRR set over its front
+    int32_t* epoch;         // [slots] samples the slot has taken; every stamp is at most 2 * epoch + 2
 };
 
 // Coverage greedy state per round (device): the top-k search over the gains
@@ -333,6 +331,25 @@ struct LaunchEvents {
     hipEvent_t start = nullptr;
     hipEvent_t stop = nullptr;
 };
+
+// One query of a packed tier-0 launch (device memory): its worlds are
+// packed worlds [first, first + count), world first + i being its world
+// w_begin + i, evaluated as its own tier-0 launch would evaluate it.
+struct PackedQuery {
+    QueryDev q;
+    TileOut out;
+    RoundCtl* ctl;
+    int32_t* next_list;  // its tier-1 list (count ctl->list_n[1])
+    uint32_t w_begin;
+    uint32_t first;
+    uint32_t count;
+    uint32_t pad;
+};
+
+// Tier 0 over the worlds of nq queries (ascending `first`, n_items packed
+// worlds in all) in one launch; counter (zero at launch) deals out chunks.
+hipError_t launch_world_tier0_packed(const GraphDev& g, const PackedQuery* pq, int nq, uint32_t n_items,
+                                     uint32_t* counter, int grid, hipStream_t s);
 
 // Tiers 0 and 1 (LDS), 2 (HBM slots with bounded per-world arrays) and 3
 // (HBM slots with arrays for any world); bs gives the slots of tier 2 or 3.
@@ -468,9 +485,10 @@ struct HostGraph {
     std::vector<uint32_t> thr;
 };
 const HostGraph* graph_host(imin_graph_t g);
-// The handle's in-edges on the device (made on first use): in_off [n+1],
-// in_src [m], in_eid [m]; false on failure.
-bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int32_t** in_src, const int32_t** in_eid);
+// The handle's in-edges on the device (made on first use): in_off [n+1] and
+// in_rec [m] = {tail, CSR slot, threshold, 0} grouped by head; false on
+// failure.
+bool graph_in_edges(imin_graph_t g, const int32_t** in_off, const int4** in_rec);
 // V'_s: the non-seed nodes reachable from the seeds over edges that can be
 // live (threshold > 0), ascending (host arrays; seeds validated by the caller).
 std::vector<int32_t> reachable_nonseeds(const HostGraph& h, const std::vector<int32_t>& seeds);

@@ -976,6 +976,78 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q_in, Rou
     }
 }
 
+// Tier 0 over the worlds of several queries (a batch of from-scratch
+// passes).  A workgroup finds the query of its packed world by a binary
+// search over the queries' first worlds, once per change of query (chunks
+// are dealt in ascending order, so consecutive worlds mostly share one), and
+// then evaluates the world exactly as that query's own tier-0 launch would;
+// a world the tier cannot hold goes to that query's tier-1 list.  The
+// workgroup is one wave, so the world index is made uniform and the query's
+// fields are read with scalar loads.
+template <int NT, class Store>
+__global__ __launch_bounds__(NT) void k_world_lds_packed(GraphDev g, const PackedQuery* __restrict__ pq, int nq,
+                                                         uint32_t n_items, uint32_t* counter) {
+    static_assert(NT == 64, "the packed tier is one wave per workgroup");
+    __shared__ Store st;
+    __shared__ WorldShared<NT> sh;
+    const int t = threadIdx.x;
+    if (blockIdx.x >= n_items) return;  // no world for this workgroup
+    st.template clear<NT>();
+    if (t == 0) {
+        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_reached = sh.acc_live = 0;
+        sh.acc_dsize = 0;
+    }
+    __syncthreads();
+    const uint32_t rest = n_items > gridDim.x ? n_items - gridDim.x : 0u;
+    const uint32_t chunk = max(1u, min(kSchedChunk, rest / (gridDim.x * 4u)));
+    uint32_t k = blockIdx.x, kend = blockIdx.x + 1;
+    uint32_t lo = 1, hi = 0;  // the current query's packed range (none yet)
+    const PackedQuery* cur = pq;
+    QueryDev q{};
+    bool stopped = false;
+    while (k < n_items) {
+        if (k < lo || k >= hi) {
+            int a = 0, b = nq - 1;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (pq[mid].first <= k) a = mid;
+                else b = mid - 1;
+            }
+            cur = pq + __builtin_amdgcn_readfirstlane(a);
+            lo = cur->first;
+            hi = cur->first + cur->count;
+            q = query_at_run(cur->q, cur->ctl);
+            stopped = cur->ctl->stop != 0;
+        }
+        const uint32_t wi = k - lo;
+        if (!stopped) {
+            RoundCtl* ctl = cur->ctl;
+            const bool ok = evaluate_world<NT, 0>(g, q, ctl, cur->w_begin + wi, wi, cur->out, st, sh);
+            if (!ok && t == 0) {
+                const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
+                if (pos < cur->out.next_cap) cur->next_list[pos] = (int32_t)wi;
+                else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            }
+            st.template reset<NT>(0);
+        }
+        if (++k == kend) {
+            if (t == 0) sh.sched = gridDim.x + atomicAdd(counter, chunk);
+            __syncthreads();
+            k = (uint32_t)__builtin_amdgcn_readfirstlane((int)sh.sched);
+            kend = k + chunk;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_world_tier0_packed(const GraphDev& g, const PackedQuery* pq, int nq, uint32_t n_items,
+                                     uint32_t* counter, int grid, hipStream_t s) {
+    if (nq < 1 || grid < 1) return hipErrorInvalidValue;
+    k_world_lds_packed<kTier0NT, Tier0Store><<<(unsigned)grid, kTier0NT, 0, s>>>(g, pq, nq, n_items, counter);
+    return hipGetLastError();
+}
+
 // Tiers 2 and 3: per-world arrays in HBM, one slot per resident workgroup;
 // the visited bitset in LDS (VIS_LDS) or in the slot, and up to kStageX
 // extra edges staged in LDS, both in dynamic LDS.  Tier 2's slots hold

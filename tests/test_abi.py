@@ -52,6 +52,13 @@ def test_host_argument_checks(lib):
     assert lib.imin_solve_workspace_size(None, 1, 1, 10, ctypes.byref(nbytes)) == 1
     assert lib.imin_evaluate(None, dummy, 1, None, 0, 0, 10, 0, None, dummy, dummy, None, None, None) == 1
     assert lib.imin_graph_info(None, None, None) == 1
+    # imin_evaluate_batch: NULL graph, negative count, NULL queries; an empty
+    # batch does nothing
+    eq = (binding.EvalQuery * 1)()
+    assert lib.imin_evaluate_batch(None, eq, 1, None) == 1
+    assert lib.imin_evaluate_batch(dummy, eq, -1, None) == 1
+    assert lib.imin_evaluate_batch(dummy, None, 1, None) == 1
+    assert lib.imin_evaluate_batch(dummy, None, 0, None) == 0
     # imin_solve_many: NULL graph, no stream, a stream named twice, bad counts
     q = (binding.Query * 1)()
     s1 = (ctypes.c_void_p * 2)(0x10, 0x20)

@@ -84,7 +84,7 @@ def test_lrr_max_coverage_tiles(B, oracle_mod, monkeypatch, tile):
     sampling budget (few slots) give the same integers."""
     from oracle import sandwich
     monkeypatch.setenv("IMIN_TILE_WORLDS", tile)
-    monkeypatch.setenv("IMIN_LRR_BUDGET", str(3 * 12 * 4000))
+    monkeypatch.setenv("IMIN_LRR_BUDGET", str(3 * 8 * 4000))
     g = synth.random_small_graph(4000, 20000, seed=33, prob="wc")
     seeds = np.array([5, 900, 3100], np.int32)
     k, theta = 10, 6000
@@ -92,6 +92,63 @@ def test_lrr_max_coverage_tiles(B, oracle_mod, monkeypatch, tile):
     G = B.Graph.from_synth(g)
     got = B.lrr_max_coverage(G, seeds, k, theta, 17)
     _same_mc(got, oracle_mod.Query(g, seeds).lrr_max_coverage(sandwich.vprime(g, seeds), k, theta, 17))
+
+
+def test_lrr_slots_kept_between_calls(B, oracle_mod, monkeypatch):
+    """The handle keeps its sampling slots: later calls, other keys and other
+    seed sets on it start from the stamps earlier calls left (three slots,
+    so each takes thousands of samples) and still give the oracle's integers."""
+    from oracle import sandwich
+    monkeypatch.setenv("IMIN_LRR_BUDGET", str(3 * 8 * 3000))
+    g = synth.random_small_graph(3000, 15000, seed=71, prob="wc")
+    G = B.Graph.from_synth(g)
+    for j, (seeds, key, theta) in enumerate([([4, 700], 3, 5000), ([4, 700], 3, 5000), ([4, 700], 9, 7000),
+                                             ([11, 1200, 2500], 3, 4000)]):
+        seeds = np.array(seeds, np.int32)
+        _log(f"kept slots call {j}: |S|={len(seeds)} key={key} theta={theta}")
+        q = oracle_mod.Query(g, seeds)
+        vp = sandwich.vprime(g, seeds)
+        want = q.lrr_max_coverage(vp, 8, theta, key)
+        _same_mc(B.lrr_max_coverage(G, seeds, 8, theta, key), want)
+        blk = want["blockers"][:3].astype(np.int32)
+        assert B.lrr_coverage(G, seeds, blk, theta, key + 1) == q.lrr_coverage(vp, blk, theta, key + 1)
+
+
+def test_lrr_concurrent_calls_on_one_handle(B, oracle_mod):
+    """Two calls on one handle at once, each on its own stream: one borrows
+    the kept slots, the other takes its own, and both give the oracle's
+    integers."""
+    import threading
+    import torch
+    from oracle import sandwich
+    g = synth.random_small_graph(2500, 12000, seed=72, prob="wc")
+    G = B.Graph.from_synth(g)
+    seeds = np.array([3, 1000, 2000], np.int32)
+    q = oracle_mod.Query(g, seeds)
+    vp = sandwich.vprime(g, seeds)
+    keys = (21, 22)
+    want = {k: q.lrr_max_coverage(vp, 6, 20000, k) for k in keys}
+    got, errs = {}, []
+
+    def run(key):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    got[key] = B.lrr_max_coverage(G, seeds, 6, 20000, key)
+            s.synchronize()
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    _log("concurrent LRR calls on one handle")
+    th = [threading.Thread(target=run, args=(k,)) for k in keys]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for k in keys:
+        _same_mc(got[k], want[k])
 
 
 def test_lrr_large_cones(B, oracle_mod):
