@@ -315,6 +315,11 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  *   n_queries   >= 0; at most IMIN_PACK_QUERIES (default 64) queries share
  *               a launch, and larger batches are taken in groups
  *
+ * The queries of a group are set up together, each with its own arrays
+ * (thresholds, gains, scratch: about 4m + 8n bytes plus 8 bytes per world
+ * slot); they share the HBM tiers' slot budgets (IMIN_BIG_BUDGET,
+ * IMIN_HUGE_BUDGET) instead of each taking them whole.
+ *
  * Every query's pointers and sizes are checked before any work.  Errors
  * as for imin_evaluate: the first failing query's status is returned, and
  * the outputs of the other queries of its group are then not all written.

@@ -899,9 +899,11 @@ struct Session {
     // tier 2 as many as IMIN_BIG_BUDGET (default 8 GiB) allows, at most
     // max_slots; tier 3 as many as IMIN_HUGE_BUDGET (default 2 GiB) allows,
     // at most one per compute unit
+    // the HBM tiers' budgets; a batch's sessions, alive together, share them
+    int32_t budget_share = 1;
     imin_status_t ensure_t2() {
         if (t2.ready()) return IMIN_OK;
-        const size_t budget = env_size("IMIN_BIG_BUDGET", (size_t)8 << 30);
+        const size_t budget = env_size("IMIN_BIG_BUDGET", (size_t)8 << 30) / (size_t)budget_share;
         IMIN_TRY(alloc_slots(t2, std::min<size_t>(std::max<size_t>(budget / t2_slot_bytes(), 1),
                                                   (size_t)max_slots(cu_count())),
                              t2_lid_cap(), t2_xcap()));
@@ -910,7 +912,7 @@ struct Session {
     }
     imin_status_t ensure_t3() {
         if (t3.ready()) return IMIN_OK;
-        const size_t budget = env_size("IMIN_HUGE_BUDGET", (size_t)2 << 30);
+        const size_t budget = env_size("IMIN_HUGE_BUDGET", (size_t)2 << 30) / (size_t)budget_share;
         IMIN_TRY(alloc_slots(t3, std::min<size_t>(std::max<size_t>(budget / t3_slot_bytes(), 1), (size_t)cu_count()),
                              g.n, std::max<int64_t>(g.m, 1)));
         IMIN_TRY(imin::launch_fill_i32((int32_t*)t3.vis.p, 0, t3.vis.count, s));
@@ -2018,6 +2020,7 @@ static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t
             const imin_eval_query_t& a = qs[j0 + j];
             ss.v.push_back(std::make_unique<Session>(g->g, s, g));
             Session& x = ss.back();
+            x.budget_share = nb;  // the group's sessions hold their HBM-tier slots together
             imin_status_t st = x.init((uint64_t)a.w_count, false);
             if (st != IMIN_OK) return st;
             st = setup_query(x, a.seeds, a.n_seeds, a.blocked, a.n_blocked, a.rng_seed, qd[(size_t)j]);

@@ -103,6 +103,11 @@ def test_batch_worlds_overflowing_tier0(B, oracle_mod):
                                                      per_world=True)[2]
     assert (sizes > 256).any(), "the case must overflow tier 0"
     _check(B, oracle_mod, G, g, qs)
+    # the handle now knows its worlds need the HBM tier: a second batch starts
+    # its queries there (unpacked, slots taken at set-up, the group sharing
+    # the tier's budget)
+    _log("second batch on the same handle")
+    _check(B, oracle_mod, G, g, [dict(q, rng_seed=q["rng_seed"] + 50) for q in qs])
 
 
 def test_batch_large_workload(B, oracle_mod):
