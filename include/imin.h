@@ -304,10 +304,11 @@ imin_status_t imin_evaluate(imin_graph_t g, const int32_t* seeds, int32_t n_seed
 /*
  * imin_evaluate_batch -- imin_evaluate for several queries on one graph
  * (each its own seeds, blocked set, world range and rng_seed), whose passes
- * share one world launch: the worlds of every query that fits one tile and
- * whose worlds start at tier 0 are packed into a single tier-0 launch; the
- * larger tiers, the gain reductions and every other query run per query.
- * Each query's outputs are those imin_evaluate gives it alone.
+ * share their world launches: the worlds of every query that fits one tile
+ * and whose worlds start at tier 0 are packed into a single tier-0 launch,
+ * and the worlds those hand on into a single tier-1 launch; the HBM tiers,
+ * the gain reductions and every other query run per query.  Each query's
+ * outputs are those imin_evaluate gives it alone.
  *
  *   queries     imin_eval_query_t[n_queries], HOST; the pointers in each
  *               are device pointers, with the meanings of imin_evaluate's
@@ -633,6 +634,11 @@ imin_status_t imin_timing_mask(uint32_t kernel_mask);
 /* Time one launch in `every` (>= 1, default 1) of each selected kernel: the
  * events themselves take time on the stream.  IMIN_ERR_INVALID if every < 1. */
 imin_status_t imin_timing_sample(int every);
+/* Whether calls made while timing is enabled keep the work tallies that
+ * imin_timing_work reports (default 1).  Taking them costs each call a
+ * clear, a copy to the host and a sum of per-workgroup slots, which grow with
+ * the launch shapes; with 0 only the selected kernels' events are taken. */
+imin_status_t imin_timing_tallies(int on);
 /* Launches of a selected kernel while timing was enabled, timed or not, since
  * the last reset (host pointer). */
 imin_status_t imin_timing_launches(int kernel_id, int64_t* all);

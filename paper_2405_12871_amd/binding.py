@@ -140,6 +140,8 @@ def load():
     lib.imin_timing_mask.restype = st
     lib.imin_timing_sample.argtypes = [ctypes.c_int]
     lib.imin_timing_sample.restype = st
+    lib.imin_timing_tallies.argtypes = [ctypes.c_int]
+    lib.imin_timing_tallies.restype = st
     lib.imin_timing_launches.argtypes = [ctypes.c_int, ctypes.POINTER(i64)]
     lib.imin_timing_launches.restype = st
     lib.imin_cache_release.argtypes = []
@@ -615,6 +617,11 @@ def cache_release():
 
 def timing_enable(on: bool = True):
     _check(load().imin_timing_enable(1 if on else 0))
+
+
+def timing_tallies(on: bool = True):
+    """Keep the work tallies of timed calls (imin_timing_tallies)."""
+    _check(load().imin_timing_tallies(1 if on else 0))
 
 
 def timing_mask(kernel_ids=None):

@@ -83,6 +83,7 @@ struct Timing {
     std::atomic<bool> on{false};
     std::atomic<uint32_t> mask{0xFFFFFFFFu};  // kernels bracketed with events
     std::atomic<int> every{1};                // one launch in `every` of each selected kernel is timed
+    std::atomic<bool> tallies{true};          // per-workgroup work tallies, summed at each call's end
     std::atomic<int64_t> seen[kTimedKernels] = {};  // launches of selected kernels, timed or not
     std::mutex mu;
     int64_t launches[kTimedKernels] = {};
@@ -1027,7 +1028,7 @@ struct Session {
             const imin_status_t st = ensure_t2();
             if (st != IMIN_OK) return st;
         }
-        if (timed.on) {
+        if (timed.on && g_timing.tallies.load()) {
             work_stride = std::max(std::max(std::max(grid0, grid1), grid_r + grid_l), max_slots(cus));
             const size_t wn = (size_t)imin::kWorkFields * kWorkTiers * work_stride;
             IMIN_TRY(work.alloc(wn));
@@ -1041,6 +1042,7 @@ struct Session {
     void finish() {
         if (!timed.on) return;
         timed.flush();
+        if (!work.p) return;  // no tallies taken
         constexpr int F = imin::kWorkFields;
         std::vector<unsigned long long> h((size_t)F * kWorkTiers * work_stride);
         if (work.p && hipMemcpy(h.data(), work.p, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) !=
@@ -1291,16 +1293,16 @@ struct Session {
     // All tiers of a tile in a call with the block cache: the HBM tiers'
     // slots are allocated (and their launches made) only once some world of
     // the tile has been handed to them.
-    // With after_tier0 a packed launch has already run tier 0 over the tile
-    // (its worlds too large for it are in list1).
+    // With packed, packed launches have already run tiers 0 and 1 over the
+    // tile (its worlds too large for them are in list2).
     imin_status_t launch_tiers_checked(const imin::QueryDev& q, uint32_t wb, uint32_t nw, const imin::TileOut& out,
-                                       bool after_tier0 = false) {
-        imin_status_t st;
+                                       bool packed = false) {
+        imin_status_t st = IMIN_OK;
         if (start_tier >= 2 && (st = ensure_t2()) != IMIN_OK) return st;
         const bool three = tier3_possible();
         const int ready_last = !t2.ready() ? 1 : ((!three || t3.ready()) ? 3 : 2);
-        st = after_tier0 ? launch_tiers(q, wb, 0, list1.p, out, 1, 1, ready_last)
-                         : launch_tiers(q, wb, nw, nullptr, out, start_tier, 0, ready_last);
+        if (!packed) st = launch_tiers(q, wb, nw, nullptr, out, start_tier, 0, ready_last);
+        else if (ready_last >= 2) st = launch_tiers(q, wb, 0, list2.p, out, 2, 2, ready_last);
         if (st != IMIN_OK) return st;
         bool ran2 = ready_last >= 2;
         if (!t2.ready()) {
@@ -1383,10 +1385,14 @@ struct Session {
         return out;
     }
 
-    // Whether a from-scratch pass of `count` worlds can have its tier-0
-    // launch packed with other queries': one tile, worlds starting at tier 0.
+    // Whether a from-scratch pass of `count` worlds can have its tier-0 and
+    // tier-1 launches packed with other queries': one tile whose worlds do
+    // not start at the HBM tier.  (A query the graph's hints would start at
+    // tier 1 is packed from tier 0: its worlds that overflow go on to the
+    // packed tier-1 launch, and the hints, the largest share any earlier
+    // call handed to tier 1, may come from another seed set.)
     bool packable(uint64_t count) const {
-        return !lrr && cover == imin::kCoverNone && !unit_counts && !sizes_only && start_tier == 0 &&
+        return !lrr && cover == imin::kCoverNone && !unit_counts && !sizes_only && start_tier <= 1 &&
                count <= (uint64_t)tile && count > 0;
     }
 
@@ -1397,19 +1403,21 @@ struct Session {
         IMIN_TRY(imin::launch_query_thresholds(g, excl.p, thr_q.p, seed_table.p, ctl.p, q.seed_cap, seed_col.p,
                                                seed_thr.p, s));
         IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
+        start_tier = 0;  // the packed launches start at tier 0
         pq = imin::PackedQuery{};
         pq.q = q;
         pq.out = tile_out_at(0, ws_out, nullptr, nullptr, false);
         pq.out.work = nullptr;  // no per-workgroup tallies for packed launches
         pq.ctl = ctl.p;
-        pq.next_list = list1.p;
+        pq.list1 = list1.p;
+        pq.list2 = list2.p;
         pq.w_begin = (uint32_t)w_begin;
         pq.count = (uint32_t)count;
         return IMIN_OK;
     }
 
-    // With after_packed, packed_prepare and a packed tier-0 launch have
-    // already done the first tile's set-up and tier 0.
+    // With after_packed, packed_prepare and the packed tier-0 and tier-1
+    // launches have already done the first tile's set-up and those tiers.
     imin_status_t evaluate(const imin::QueryDev& q, uint64_t w_begin, uint64_t count, int32_t* ws_out,
                            int64_t* wsum_out, int64_t* wedges_out, bool store_mode = false,
                            bool after_packed = false) {
@@ -1983,9 +1991,9 @@ static imin_status_t evaluate_impl(imin_graph_t g, const int32_t* seeds, int32_t
 }
 
 // Several from-scratch passes on one graph: every query is set up as
-// imin_evaluate would set it up; the tier-0 launches of those that fit one
-// tile starting at tier 0 become one packed launch, after which each query
-// finishes its pass (larger tiers, reduction) as usual.
+// imin_evaluate would set it up; the tier-0 and tier-1 launches of those that
+// fit one tile starting at tier 0 become one packed launch each, after which
+// each query finishes its pass (HBM tiers, reduction) as usual.
 static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t* qs, int32_t nq, void* stream) {
     g_last_flags = 0;
     if (!g || nq < 0 || (nq > 0 && !qs)) return IMIN_ERR_INVALID;
@@ -2015,7 +2023,7 @@ static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t
         std::vector<imin::PackedQuery> pk;
         std::vector<uint8_t> packed((size_t)nb, 0);
         uint64_t first = 0;
-        int grid = 0;
+        int grid = 0, grid1 = 0;
         for (int32_t j = 0; j < nb; ++j) {
             const imin_eval_query_t& a = qs[j0 + j];
             ss.v.push_back(std::make_unique<Session>(g->g, s, g));
@@ -2036,6 +2044,7 @@ static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t
                 pk.push_back(pq);
                 packed[(size_t)j] = 1;
                 grid = std::max(grid, x.grid0);
+                grid1 = std::max(grid1, x.grid1);
             }
         }
         DevArray<imin::PackedQuery> pk_dev;
@@ -2048,6 +2057,7 @@ static imin_status_t evaluate_batch_impl(imin_graph_t g, const imin_eval_query_t
             IMIN_TRY(imin::launch_fill_i32((int32_t*)counter.p, 0, 1, s));
             IMIN_TRY(imin::launch_world_tier0_packed(g->g, pk_dev.p, (int)pk.size(), (uint32_t)first, counter.p, grid,
                                                      s));
+            IMIN_TRY(imin::launch_world_tier1_packed(g->g, pk_dev.p, (int)pk.size(), grid1, s));
         }
         for (int32_t j = 0; j < nb; ++j) {
             const imin_eval_query_t& a = qs[j0 + j];
@@ -2688,6 +2698,11 @@ imin_status_t imin_timing_mask(uint32_t kernel_mask) {
 imin_status_t imin_timing_sample(int every) {
     if (every < 1) return IMIN_ERR_INVALID;
     g_timing.every.store(every);
+    return IMIN_OK;
+}
+
+imin_status_t imin_timing_tallies(int on) {
+    g_timing.tallies.store(on != 0);
     return IMIN_OK;
 }
 

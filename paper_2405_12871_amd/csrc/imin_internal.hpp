@@ -339,7 +339,8 @@ struct PackedQuery {
     QueryDev q;
     TileOut out;
     RoundCtl* ctl;
-    int32_t* next_list;  // its tier-1 list (count ctl->list_n[1])
+    int32_t* list1;  // its tier-1 list (count ctl->list_n[1])
+    int32_t* list2;  // its tier-2 list (count ctl->list_n[2])
     uint32_t w_begin;
     uint32_t first;
     uint32_t count;
@@ -350,6 +351,8 @@ struct PackedQuery {
 // worlds in all) in one launch; counter (zero at launch) deals out chunks.
 hipError_t launch_world_tier0_packed(const GraphDev& g, const PackedQuery* pq, int nq, uint32_t n_items,
                                      uint32_t* counter, int grid, hipStream_t s);
+// Tier 1 over the tier-1 lists of the same queries, after that launch.
+hipError_t launch_world_tier1_packed(const GraphDev& g, const PackedQuery* pq, int nq, int grid, hipStream_t s);
 
 // Tiers 0 and 1 (LDS), 2 (HBM slots with bounded per-world arrays) and 3
 // (HBM slots with arrays for any world); bs gives the slots of tier 2 or 3.

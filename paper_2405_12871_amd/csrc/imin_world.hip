@@ -1026,7 +1026,7 @@ __global__ __launch_bounds__(NT) void k_world_lds_packed(GraphDev g, const Packe
             const bool ok = evaluate_world<NT, 0>(g, q, ctl, cur->w_begin + wi, wi, cur->out, st, sh);
             if (!ok && t == 0) {
                 const uint32_t pos = atomicAdd(&ctl->list_n[1], 1u);
-                if (pos < cur->out.next_cap) cur->next_list[pos] = (int32_t)wi;
+                if (pos < cur->out.next_cap) cur->list1[pos] = (int32_t)wi;
                 else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
             }
             st.template reset<NT>(0);
@@ -1041,10 +1041,69 @@ __global__ __launch_bounds__(NT) void k_world_lds_packed(GraphDev g, const Packe
     }
 }
 
+// Tier 1 over the tier-1 lists of several queries (those of a packed tier-0
+// launch).  The lists' lengths are read on the device; the items of the
+// lists in query order are dealt round-robin to the workgroups (item x to
+// workgroup x mod grid), so no counter is shared.  Each world is evaluated
+// as its query's own tier-1 launch would evaluate it, and one the tier
+// cannot hold goes to that query's tier-2 list.
+template <int NT, class Store>
+__global__ __launch_bounds__(NT) void k_world_lds_packed_list(GraphDev g, const PackedQuery* __restrict__ pq,
+                                                              int nq) {
+    __shared__ Store st;
+    __shared__ WorldShared<NT> sh;
+    const int t = threadIdx.x;
+    st.template clear<NT>();
+    if (t == 0) {
+        sh.acc_worlds = sh.acc_edges = sh.acc_bytes = 0;
+        sh.acc_reached = sh.acc_live = 0;
+        sh.acc_dsize = 0;
+    }
+    __syncthreads();
+    const uint32_t grid = gridDim.x;
+    uint64_t base = 0;  // items of the queries before this one
+    for (int j = 0; j < nq; ++j) {
+        const PackedQuery* cur = pq + j;
+        RoundCtl* ctl = cur->ctl;
+        const uint32_t n_items = min(ctl->list_n[1], cur->out.next_cap);
+        if (n_items == 0 || ctl->stop) continue;  // uniform
+        const QueryDev q = query_at_run(cur->q, ctl);
+        // this workgroup's first item of the query: the first i with
+        // (base + i) mod grid == blockIdx.x
+        const uint32_t first = (uint32_t)((blockIdx.x + grid - (uint32_t)(base % grid)) % grid);
+        for (uint32_t k = first; k < n_items; k += grid) {
+            const uint32_t wi = (uint32_t)cur->list1[k];
+            const bool ok = evaluate_world<NT, 1>(g, q, ctl, cur->w_begin + wi, wi, cur->out, st, sh);
+            if (!ok && t == 0) {
+                const uint32_t pos = atomicAdd(&ctl->list_n[2], 1u);
+                if (pos < cur->out.next_cap) cur->list2[pos] = (int32_t)wi;
+                else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            }
+            st.template reset<NT>(0);
+            __syncthreads();
+        }
+        base += n_items;
+    }
+}
+
+// The packed kernel's store: tier 0's, as a type of its own, so that the
+// packed kernel gets its own instances of the world functions and the
+// single-query tier-0 kernel is compiled as if it were their only caller
+// (sharing them changes the inliner's choices and costs that kernel two
+// registers, one occupancy step).
+struct PackedTier0Store : Tier0Store {};
+struct PackedTier1Store : Tier1Store {};
+
 hipError_t launch_world_tier0_packed(const GraphDev& g, const PackedQuery* pq, int nq, uint32_t n_items,
                                      uint32_t* counter, int grid, hipStream_t s) {
     if (nq < 1 || grid < 1) return hipErrorInvalidValue;
-    k_world_lds_packed<kTier0NT, Tier0Store><<<(unsigned)grid, kTier0NT, 0, s>>>(g, pq, nq, n_items, counter);
+    k_world_lds_packed<kTier0NT, PackedTier0Store><<<(unsigned)grid, kTier0NT, 0, s>>>(g, pq, nq, n_items, counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_world_tier1_packed(const GraphDev& g, const PackedQuery* pq, int nq, int grid, hipStream_t s) {
+    if (nq < 1 || grid < 1) return hipErrorInvalidValue;
+    k_world_lds_packed_list<kTier1NT, PackedTier1Store><<<(unsigned)grid, kTier1NT, 0, s>>>(g, pq, nq);
     return hipGetLastError();
 }
 

@@ -138,3 +138,22 @@ def test_empty_batch(B):
     g = synth.random_small_graph(30, 60, seed=1, prob="wc")
     G = B.Graph.from_synth(g)
     assert B.evaluate_batch(G, []) == []
+
+
+def test_batch_rejects_bad_data(B):
+    """A query with a repeated seed or a seed out of range fails the batch with
+    the data error, as imin_evaluate fails; a valid batch on the same handle
+    still gives the solo results afterwards."""
+    g = synth.random_small_graph(200, 800, seed=5, prob="wc")
+    G = B.Graph.from_synth(g)
+    good = {"seeds": np.array([1, 2], np.int32), "blocked": [], "w_begin": 0, "w_count": 300, "rng_seed": 9}
+    for bad_seeds in ([3, 3], [4, 200]):
+        bad = dict(good, seeds=np.array(bad_seeds, np.int32))
+        _log(f"batch with bad seeds {bad_seeds}")
+        with pytest.raises(B.IminError) as ei:
+            B.evaluate_batch(G, [good, bad])
+        assert ei.value.status == 2  # IMIN_ERR_DATA
+    got = B.evaluate_batch(G, [good])
+    alone = B.evaluate(G, good["seeds"], 0, 300, 9)
+    np.testing.assert_array_equal(got[0][0], alone[0])
+    assert got[0][1] == alone[1]
