@@ -602,7 +602,7 @@ imin_status_t imin_cache_release(void);
  * Kernel timing, for measurement.  While enabled, the library brackets its
  * own kernel launches with HIP events on the stream they run on and adds
  * each launch's duration to a per-kernel tally (process-wide).  The world
- * kernels (ids 0, 1, 4, 6, 7) take the events into their own launch
+ * kernels (ids 0, 1, 4, 6, 7, 8) take the events into their own launch
  * (hipExtLaunchKernel), so that the interval is the kernel's alone; the
  * others are bracketed by separate event records.  Kernel ids:
  *   0  world evaluation, small LDS tier (one wave per world)
@@ -624,6 +624,8 @@ imin_status_t imin_cache_release(void);
  *   7  the wide replay of an incremental round: worlds too large for kernel
  *      6's replay, one 1024-thread workgroup each, with four times its
  *      capacities (worlds too large for it go on to kernels 4 and 1)
+ *   8  level 0 drawn ahead: the live seed slots of a tile's worlds as bits,
+ *      read by the world kernels of that tile (from-scratch passes)
  * imin_timing_read returns the number of launches and their summed duration
  * in milliseconds (host pointers).  Enabling adds a small per-launch cost.
  */

@@ -77,7 +77,7 @@ thread_local uint32_t g_last_flags = 0;
 thread_local int32_t g_last_mode = -1;
 
 // ---- optional per-kernel timing with HIP events
-constexpr int kTimedKernels = 8;
+constexpr int kTimedKernels = 9;
 constexpr int kWorkTiers = 6;  // tiers 0-2, replay, label rule (rule workgroups), label rule (replay workgroups)
 struct Timing {
     std::atomic<bool> on{false};
@@ -1375,6 +1375,31 @@ struct Session {
     // gain += per-node sums, ctl.total += sum of sizes.  Optional per-world
     // outputs are written at [0, count).  With store_mode (round 0 of a
     // solve) the per-world lists also become the resident store.
+    // Level 0 of a tile's worlds drawn ahead (launch_level0_bits), when the
+    // tile gives every tier-0 workgroup four worlds or more (a smaller tile's
+    // tier-0 launch is bound by one world's latency, and the extra launch
+    // costs more than it saves), the bits fit IMIN_L0_BITS_BUDGET (default
+    // 1 GiB), and IMIN_LEVEL0_BITS is not 0 (1 draws every tile ahead); out
+    // then points the world kernels at them.
+    DevArray<uint32_t> l0_bits;
+    imin_status_t draw_level0(const imin::QueryDev& q, uint32_t wb, uint32_t nw, imin::TileOut& out) {
+        const char* e = std::getenv("IMIN_LEVEL0_BITS");
+        if ((e && e[0] == '0') || q.seed_cap < 1 || nw == 0) return IMIN_OK;
+        if (!(e && e[0] == '1') && (uint64_t)nw < 4ull * (uint64_t)std::max(grid0, 1)) return IMIN_OK;
+        const size_t words = ((size_t)q.seed_cap + 7) / 8;
+        if ((size_t)(q.seed_cap + 255) / 256 > 65535) return IMIN_OK;
+        const size_t need = (size_t)tile_cap * words;
+        if (need * sizeof(uint32_t) > env_size("IMIN_L0_BITS_BUDGET", (size_t)1 << 30)) return IMIN_OK;
+        if (l0_bits.count < need) IMIN_TRY(l0_bits.alloc(need));
+        const imin::LaunchEvents ev = timed.take(8);
+        const hipError_t le = imin::launch_level0_bits(q, ctl.p, wb, nw, l0_bits.p, (int)words, q.seed_cap, s, ev);
+        timed.taken(8, ev);
+        IMIN_TRY(le);
+        out.l0_bits = l0_bits.p;
+        out.l0_words = (int)words;
+        return IMIN_OK;
+    }
+
     // The outputs of the tile whose first world is `done`.
     imin::TileOut tile_out_at(uint64_t done, int32_t* ws_out, int64_t* wsum_out, int64_t* wedges_out, bool keep) {
         imin::TileOut out = tile_out();
@@ -1408,6 +1433,7 @@ struct Session {
         pq.q = q;
         pq.out = tile_out_at(0, ws_out, nullptr, nullptr, false);
         pq.out.work = nullptr;  // no per-workgroup tallies for packed launches
+
         pq.ctl = ctl.p;
         pq.list1 = list1.p;
         pq.list2 = list2.p;
@@ -1437,6 +1463,10 @@ struct Session {
             imin::TileOut out = tile_out_at(done, ws_out, wsum_out, wedges_out, keep);
             if (!packed_tile) IMIN_TRY(imin::launch_ctl_reset_tile(ctl.p, s));
             imin_status_t st = IMIN_OK;
+            if (!lrr && !packed_tile && q.excl_in_thr) {
+                st = draw_level0(q, (uint32_t)(w_begin + done), (uint32_t)nw, out);
+                if (st != IMIN_OK) return st;
+            }
             if (lrr) {
                 st = lrr_reserve(nw);
                 if (st == IMIN_OK && imin::launch_lrr(g, q, ctl.p, (uint32_t)(w_begin + done), (uint32_t)nw, lrr_dev,

@@ -210,6 +210,12 @@ struct TileOut {
     int unit_counts;
     // only |R_w| per world: no dominators, no entries (stopping rules)
     int sizes_only;
+    // Level 0 drawn ahead for the tile's worlds (or null): world i's live
+    // seed slots as bits, words [i * l0_words, (i + 1) * l0_words), bit
+    // 4j + q for slot q of level-0 slot group j.  Set only for tiles of
+    // consecutive worlds whose thresholds carry every exclusion.
+    const uint32_t* l0_bits;
+    int l0_words;
 };
 
 // World outputs for lower-bound coverage.
@@ -353,6 +359,13 @@ hipError_t launch_world_tier0_packed(const GraphDev& g, const PackedQuery* pq, i
                                      uint32_t* counter, int grid, hipStream_t s);
 // Tier 1 over the tier-1 lists of the same queries, after that launch.
 hipError_t launch_world_tier1_packed(const GraphDev& g, const PackedQuery* pq, int nq, int grid, hipStream_t s);
+
+// Level 0 of worlds [w_begin, w_begin + count) ahead of the world kernels:
+// their live seed slots as bits (TileOut::l0_bits; words = ceil(chunk_cap /
+// 8) per world).  q's thresholds must carry every exclusion.
+struct LaunchEvents;
+hipError_t launch_level0_bits(const QueryDev& q, const RoundCtl* ctl, uint32_t w_begin, uint32_t count,
+                              uint32_t* bits, int words, int32_t chunk_cap, hipStream_t s, const LaunchEvents& ev);
 
 // Tiers 0 and 1 (LDS), 2 (HBM slots with bounded per-world arrays) and 3
 // (HBM slots with arrays for any world); bs gives the slots of tier 2 or 3.

@@ -288,6 +288,28 @@ struct SlotGroup {
     bool valid;
 };
 
+// A live edge from local id ulid to node v: v is claimed (a new node of the
+// next level, with ulid as its BFS parent) or, when it is reached already,
+// the edge is kept as an extra edge; out of room, the world overflows.
+template <int NT, class Store>
+__device__ __forceinline__ void claim_live(Store& st, WorldShared<NT>& sh, int32_t v, int ulid) {
+    const int lid = st.claim(v, &sh.count);
+    if (lid >= 0) {
+        st.set_node(lid, v);
+        st.set_parent(lid, ulid);
+    } else if (lid == -1) {
+        const int x = atomicAdd(&sh.n_extra, 1);
+        if (x < st.cap_x()) {
+            st.xv[x] = v;
+            st.set_xu(x, ulid);
+        } else {
+            sh.overflow = 1;
+        }
+    } else {
+        sh.overflow = 1;
+    }
+}
+
 // Draw the coins of U slot groups whose columns (cv) and thresholds (tv) are
 // loaded, and claim or record every live edge.  Exclusions (seeds, blocked
 // nodes) are already in the per-query thresholds when q.excl_in_thr is set
@@ -327,21 +349,7 @@ __device__ __forceinline__ void claim_slot_groups(const QueryDev& q, uint32_t w,
             if (!lv[u][qd]) continue;
             const int32_t v = vv[u][qd];
             if ((ex[u][qd] >> ((uint32_t)v & 31u)) & 1u) continue;  // seed or blocker
-            const int lid = st.claim(v, &sh.count);
-            if (lid >= 0) {
-                st.set_node(lid, v);
-                st.set_parent(lid, gr[u].ulid);
-            } else if (lid == -1) {
-                const int x = atomicAdd(&sh.n_extra, 1);
-                if (x < st.cap_x()) {
-                    st.xv[x] = v;
-                    st.set_xu(x, gr[u].ulid);
-                } else {
-                    sh.overflow = 1;
-                }
-            } else {
-                sh.overflow = 1;
-            }
+            claim_live<NT>(st, sh, v, gr[u].ulid);
         }
     }
 }
@@ -368,7 +376,8 @@ constexpr int kGroupsPerLane = 2;
 // Phase 1 of a world evaluation by sampling: the BFS with coins.  Returns
 // false when the store ran out of room (uniform over the workgroup).
 template <int NT, class Store>
-__device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, Store& st, WorldShared<NT>& sh) {
+__device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, const uint32_t* l0, Store& st,
+                           WorldShared<NT>& sh) {
     const int t = threadIdx.x;
     const int ns = q.n_seeds;
     if (!st.fits(ns)) return false;  // uniform
@@ -386,8 +395,25 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, Sto
     __syncthreads();
 
     // ---- level 0: the seeds' slot groups from the per-query table, which
-    // carries each group's columns and thresholds (one round trip)
-    for (int j0 = t; j0 < q.n_seed_chunks; j0 += NT * kGroupsPerLane) {
+    // carries each group's columns and thresholds (one round trip); when the
+    // live slots were drawn ahead (l0), only those are read and claimed
+    if (l0) {
+        const int nwords = (q.n_seed_chunks + 7) >> 3;
+        for (int wd = t; wd < nwords; wd += NT) {
+            uint32_t m = l0[wd];
+            while (m) {
+                const int b = __ffs((int)m) - 1;
+                m &= m - 1u;
+                const int j = wd * 8 + (b >> 2);
+                const int qd = b & 3;
+                const int seed_lid = q.seed_chunk[j].y;
+                const int4 cv = q.seed_col[j];
+                const int32_t v = qd == 0 ? cv.x : qd == 1 ? cv.y : qd == 2 ? cv.z : cv.w;
+                claim_live<NT>(st, sh, v, seed_lid);
+            }
+        }
+    }
+    for (int j0 = l0 ? q.n_seed_chunks : t; j0 < q.n_seed_chunks; j0 += NT * kGroupsPerLane) {
         SlotGroup gr[kGroupsPerLane];
         int4 cv[kGroupsPerLane];
         uint4 tv[kGroupsPerLane];
@@ -861,7 +887,8 @@ __device__ void world_outputs(const QueryDev& q, RoundCtl* ctl, uint32_t w, uint
 template <int NT, int TIER, class Store>
 __device__ bool evaluate_world(const GraphDev& g, const QueryDev& q, RoundCtl* ctl, uint32_t w, uint32_t wi,
                                const TileOut& out, Store& st, WorldShared<NT>& sh) {
-    if (!bfs_sample<NT>(g, q, w, st, sh)) return false;
+    const uint32_t* l0 = out.l0_bits ? out.l0_bits + (size_t)wi * (size_t)out.l0_words : nullptr;
+    if (!bfs_sample<NT>(g, q, w, l0, st, sh)) return false;
     // reach counts and world sizes need no dominators (uniform)
     if (!out.sizes_only && !out.unit_counts) world_counts<NT>(q, ctl, st, sh);
     if (out.cover == kCoverStore) {  // uniform
@@ -1084,6 +1111,65 @@ __global__ __launch_bounds__(NT) void k_world_lds_packed_list(GraphDev g, const 
         }
         base += n_items;
     }
+}
+
+// Level 0 of a tile's worlds, drawn ahead of the world kernels.  A lane
+// holds one level-0 slot group (its table entry read once) and draws its
+// coins for kL0Worlds consecutive worlds, so the draws wait on no load; the
+// nibbles of eight neighbouring lanes make one word of a world's bits.  The
+// world kernels then read and claim only the live slots.
+constexpr int kL0NT = 256;
+constexpr int kL0Worlds = 32;
+__global__ __launch_bounds__(kL0NT) void k_level0_bits(QueryDev q_in, const RoundCtl* ctl, uint32_t w_begin,
+                                                       uint32_t count, uint32_t* bits, int words) {
+    if (ctl->stop) return;
+    const QueryDev q = query_at_run(q_in, ctl);
+    const int j = (int)(blockIdx.y * kL0NT + threadIdx.x);  // slot group
+    const int wd = j >> 3;                                   // its word
+    const uint32_t wi0 = blockIdx.x * (uint32_t)kL0Worlds;
+    uint32_t valid = 0u;  // slots of the group inside its seed's row
+    int4 d = make_int4(0, 0, 0, 0);
+    uint4 th = make_uint4(0u, 0u, 0u, 0u);
+    if (j < q.n_seed_chunks) {
+        d = q.seed_chunk[j];  // {blk, seed lid, e0, e1}
+        th = q.seed_thr[j];
+#pragma unroll
+        for (int qd = 0; qd < 4; ++qd) {
+            const int e = 4 * d.x + qd;
+            if (e >= d.z && e < d.w) valid |= 1u << qd;
+        }
+    }
+    const uint32_t ts[4] = {th.x, th.y, th.z, th.w};
+    for (int r = 0; r < kL0Worlds; ++r) {
+        const uint32_t wi = wi0 + (uint32_t)r;
+        if (wi >= count) break;  // uniform over the workgroup
+        uint32_t nib = 0u;
+        if (valid) {
+            const uint4 c = philox_block((uint32_t)d.x, w_begin + wi, q.key0, q.key1);
+            const uint32_t cs[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+            for (int qd = 0; qd < 4; ++qd)
+                if (((valid >> qd) & 1u) && (ts[qd] == kAlwaysLive || cs[qd] < ts[qd])) nib |= 1u << qd;
+        }
+        uint32_t word = nib << (4 * (threadIdx.x & 7));
+        word |= __shfl_xor(word, 1);
+        word |= __shfl_xor(word, 2);
+        word |= __shfl_xor(word, 4);
+        if ((threadIdx.x & 7) == 0 && wd < words) bits[(size_t)wi * (size_t)words + (size_t)wd] = word;
+    }
+}
+
+hipError_t launch_level0_bits(const QueryDev& q, const RoundCtl* ctl, uint32_t w_begin, uint32_t count,
+                              uint32_t* bits, int words, int32_t chunk_cap, hipStream_t s, const LaunchEvents& ev) {
+    const int gy = (chunk_cap + kL0NT - 1) / kL0NT;
+    if (count == 0 || chunk_cap < 1 || words < (chunk_cap + 7) / 8 || gy > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((count + kL0Worlds - 1) / kL0Worlds), (unsigned)gy);
+    if (ev.start)
+        hipExtLaunchKernelGGL(k_level0_bits, grid, dim3(kL0NT), 0, s, ev.start, ev.stop, 0, q, ctl, w_begin, count,
+                              bits, words);
+    else
+        k_level0_bits<<<grid, kL0NT, 0, s>>>(q, ctl, w_begin, count, bits, words);
+    return hipGetLastError();
 }
 
 // The packed kernel's store: tier 0's, as a type of its own, so that the

@@ -62,6 +62,37 @@ def test_evaluate_random_graphs(B, oracle_mod, case):
     _assert_same(got, want)
 
 
+@pytest.mark.parametrize("case", range(6))
+def test_level0_drawn_ahead_equals_inline(B, oracle_mod, monkeypatch, case):
+    """Level 0 drawn ahead as bits (the default) and drawn inline by the world
+    kernels give the oracle's worlds: rows that start and end inside a slot
+    group, p = 1 and p = 0 slots, seeds next to seeds, self-loops and
+    multi-edges, blocked nodes, and seeds whose rows span many groups."""
+    rng = np.random.default_rng(700 + case)
+    n = int(rng.integers(20, 400))
+    m = int(rng.integers(n, 10 * n))
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    # a few hub seeds with long rows, and edges between seeds
+    seeds = rng.choice(n, int(rng.integers(1, max(2, n // 6))), replace=False).astype(np.int32)
+    hub = int(seeds[0])
+    extra = rng.integers(0, n, 3 * n)
+    src = np.concatenate([src, np.full(extra.size, hub), seeds[:-1], [hub]])
+    dst = np.concatenate([dst, extra, seeds[1:], [hub]])
+    p = rng.choice([0.0, 1.0, 0.5, 0.05, 0.3], src.size).astype(np.float32)
+    g = synth.from_edges(n, src, dst, p, name=f"level0-{case}")
+    others = np.setdiff1d(np.arange(n), seeds)
+    blocked = rng.choice(others, min(len(others), int(rng.integers(0, 4))), replace=False).tolist()
+    w0, nw, key = int(rng.integers(0, 10000)), int(rng.integers(100, 3000)), 900 + case
+    want = oracle_mod.Query(g, seeds).eval(key, w0, nw, blocked=blocked, per_world=True)
+    G = B.Graph.from_synth(g)
+    for mode in ("1", "0"):
+        monkeypatch.setenv("IMIN_LEVEL0_BITS", mode)
+        _log(f"level 0 case {case} mode {mode}: n={n} m={g.m} seeds={len(seeds)} worlds={nw}")
+        got = B.evaluate(G, seeds, w0, nw, key, blocked=blocked, per_world=True)
+        _assert_same(got, want)
+
+
 def test_evaluate_small_workload(B, oracle_mod):
     g, seeds, k, theta = synth.workload("small")
     got, want = _eval_both(B, oracle_mod, g, seeds, 0, theta, 1)
