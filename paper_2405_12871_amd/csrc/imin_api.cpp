@@ -489,7 +489,7 @@ struct Session {
     // HBM-tier slots: tier 2's hold worlds of up to 2^16 nodes and 2^16
     // extra edges (many slots), tier 3's any world of the graph (a few)
     struct Slots {
-        DevArray<int32_t> lid, nodes, parent, idom, aux, tin, lvl, xv, xu;
+        DevArray<int32_t> lid, nodes, parent, idom, aux, tin, lvl, xv, xu, xv2, xu2;
         DevArray<uint32_t> vis;
         imin::BigSlots bs{};
         bool ready() const { return lid.p != nullptr; }
@@ -884,12 +884,13 @@ struct Session {
 
     // bytes of one HBM-tier slot: node -> local id, the visited bitset, four
     // per-node arrays (five with the coverage store's preorder indexes) and
-    // the level offsets, and two extra-edge arrays
+    // the level offsets, and four extra-edge arrays (as found, and sorted by
+    // head level)
     size_t slot_bytes(int32_t lid_cap, int64_t xcap) const {
         const size_t n = (size_t)g.n;
         const size_t per_node = cover == imin::kCoverStore ? 5 : 4;
         return n * 4 + (n + 31) / 32 * 4 + per_node * (size_t)lid_cap * 4 + ((size_t)lid_cap + 3) * 4 +
-               2 * (size_t)xcap * 4;
+               4 * (size_t)xcap * 4;
     }
     size_t t2_slot_bytes() const { return slot_bytes(t2_lid_cap(), t2_xcap()); }
     size_t t3_slot_bytes() const { return slot_bytes(g.n, std::max<int64_t>(g.m, 1)); }
@@ -939,6 +940,8 @@ struct Session {
         if ((e = S.lvl.alloc(slots * (lc + 3))) != hipSuccess) return e;
         if ((e = S.xv.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
         if ((e = S.xu.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
+        if ((e = S.xv2.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
+        if ((e = S.xu2.alloc(slots * (size_t)xcap)) != hipSuccess) return e;
         if ((e = S.vis.alloc(slots * (size_t)S.bs.vis_words)) != hipSuccess) return e;
         S.bs.vis = S.vis.p;
         S.bs.lid_of = S.lid.p;
@@ -950,6 +953,8 @@ struct Session {
         S.bs.lvl = S.lvl.p;
         S.bs.xv = S.xv.p;
         S.bs.xu = S.xu.p;
+        S.bs.xv2 = S.xv2.p;
+        S.bs.xu2 = S.xu2.p;
         return hipSuccess;
     }
 

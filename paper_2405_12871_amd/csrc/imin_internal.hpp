@@ -104,6 +104,8 @@ struct BigSlots {
     int32_t* lvl;      // [slots][lid_cap+3]
     int32_t* xv;       // [slots][xcap]
     int32_t* xu;       // [slots][xcap]
+    int32_t* xv2;      // [slots][xcap] the extra edges sorted by their head's BFS level
+    int32_t* xu2;      // [slots][xcap]
 };
 
 // Everything a tile of world evaluations writes.

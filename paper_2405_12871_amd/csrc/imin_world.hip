@@ -169,6 +169,7 @@ struct LdsStore {
     // once the labels are placed the cursors are free: the exit ranges of
     // the labels live there and in the rest of the table
     static_assert(kHash >= 2 * CAPNS, "room for the exit ranges");
+    static constexpr bool kSortExtras = false;  // the extra edges are in LDS already
     __device__ int32_t* lo_ptr(int lid) { return &keys[lid - ns]; }
     __device__ int32_t* hi_ptr(int lid) { return &keys[CAPNS + lid - ns]; }
     template <int NT>
@@ -244,6 +245,63 @@ struct HbmStore {
     }
     __device__ void resolve_xv(int64_t x) { set_xv(x, lookup(get_xv(x))); }
     __device__ int delta_lid(int /*i*/, int32_t u) const { return lookup(u); }
+    // Extra edges that are not staged in LDS are sorted by their head's BFS
+    // level (a counting sort into the slot's second pair of arrays, the level
+    // cursors in the unused staging area), so that a dominator sweep over a
+    // level reads only that level's extra edges instead of all of them.  The
+    // pairs then trade places: the sorted one is read from here on, and the
+    // other takes the next world's extra edges.
+    static constexpr bool kSortExtras = true;
+    int32_t* xv2;
+    int32_t* xu2;
+    bool sorted;
+    __device__ int32_t* level_cursors() { return xv_s; }  // 2 * xs_cap ints while not staged
+    __device__ int sort_cap() const { return 2 * xs_cap; }
+    // after every head's level was counted into level_cursors(): the cursors
+    // become level starts, every edge goes to its level's range, and the
+    // cursors end as level ends
+    template <int NT>
+    __device__ __forceinline__ void sort_by_level(int nx, int nlevels) {
+        int32_t* cur = level_cursors();
+        if (threadIdx.x == 0) {
+            int run = 0;
+            for (int L = 0; L <= nlevels; ++L) {
+                const int c = cur[L];
+                cur[L] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < nx; x += NT) {
+            const int v = xv[x];
+            int lo = 0, hi = nlevels - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (lvl[mid] <= v) lo = mid; else hi = mid - 1;
+            }
+            const int at = atomicAdd(&cur[lo], 1);
+            xv2[at] = v;
+            xu2[at] = xu_[x];
+        }
+        __syncthreads();
+        int32_t* const v2 = xv2;
+        int32_t* const u2 = xu2;
+        xv2 = xv;
+        xu2 = xu_;
+        xv = v2;
+        xu_ = u2;
+        sorted = true;
+    }
+    // the extra edges a sweep over level L reads
+    __device__ __forceinline__ void level_range(int L, int nx, int& xa, int& xb) {
+        if (sorted) {
+            xa = L == 0 ? 0 : level_cursors()[L - 1];
+            xb = level_cursors()[L];
+        } else {
+            xa = 0;
+            xb = nx;
+        }
+    }
     // the extra edges into LDS when they fit (every thread takes the same
     // decision); the caller synchronises before they are read
     template <int NT>
@@ -275,6 +333,7 @@ struct HbmStore {
             for (int i = threadIdx.x; i < count; i += NT) vis[(uint32_t)nodes[i] >> 5] = 0u;
         }
         staged = false;
+        sorted = false;
     }
 };
 
@@ -525,6 +584,13 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
         st.set_idom(i, p);
         *st.aux_ptr(i) = p;
     }
+    // extra edges that stay in HBM are sorted by head level (uniform)
+    bool sort = false;
+    if constexpr (Store::kSortExtras) {
+        sort = !st.staged && nx > 0 && nlevels + 1 <= st.sort_cap();
+        if (sort)
+            for (int i = t; i <= nlevels; i += NT) st.level_cursors()[i] = 0;
+    }
     if (t == 0) {
         sh.nonfwd = 0;
         sh.xlevels = 0;
@@ -541,8 +607,12 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
         const bool fwd = (lo >= 1) && (u >= st.lvl[lo - 1]) && (u < st.lvl[lo]);
         if (!fwd) sh.nonfwd = 1;
         atomicOr(&sh.xlevels, lo < 63 ? (1ull << lo) : (1ull << 63));  // levels holding an extra edge's head
+        if constexpr (Store::kSortExtras)
+            if (sort) atomicAdd(&st.level_cursors()[lo], 1);
     }
     __syncthreads();
+    if constexpr (Store::kSortExtras)
+        if (sort) st.template sort_by_level<NT>(nx, nlevels);
     if (nx > 0 && !sh.nonfwd) {
         // Every extra edge goes exactly one level down: the idom of a level-L
         // node depends only on final idoms of shallower levels, so one sweep
@@ -551,7 +621,9 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
         for (int L = 1; L < nlevels; ++L) {
             if (L < 63 && !((xl >> L) & 1ull)) continue;  // uniform
             const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
-            for (int x = t; x < nx; x += NT) {
+            int xa = 0, xb = nx;
+            if constexpr (Store::kSortExtras) st.level_range(L, nx, xa, xb);
+            for (int x = xa + t; x < xb; x += NT) {
                 const int v = st.get_xv(x);
                 if (v < v0 || v >= v1) continue;
                 int a = st.get_parent(v);
@@ -581,7 +653,9 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
                 // a level without extra heads keeps idom = BFS parent
                 if (L < 63 && !((xl >> L) & 1ull)) continue;  // uniform
                 const int v0 = st.lvl[L], v1 = st.lvl[L + 1];
-                for (int x = t; x < nx; x += NT) {
+                int xa = 0, xb = nx;
+                if constexpr (Store::kSortExtras) st.level_range(L, nx, xa, xb);
+                for (int x = xa + t; x < xb; x += NT) {
                     const int v = st.get_xv(x);
                     if (v < v0 || v >= v1) continue;
                     int a = st.get_parent(v);
@@ -592,7 +666,7 @@ __device__ void world_counts(const QueryDev& q, RoundCtl* ctl, Store& st, WorldS
                     atomicMin(st.aux_ptr(v), a);
                 }
                 __syncthreads();
-                for (int x = t; x < nx; x += NT) {
+                for (int x = xa + t; x < xb; x += NT) {
                     const int v = st.get_xv(x);
                     if (v < v0 || v >= v1) continue;
                     const int nv = *st.aux_ptr(v);
@@ -1225,6 +1299,9 @@ __global__ __launch_bounds__(kTier2NT) void k_world_hbm(GraphDev g, QueryDev q_i
     st.lvl = bs.lvl + slot * (lc + 3);
     st.xv = bs.xv + slot * (size_t)bs.xcap;
     st.xu_ = bs.xu + slot * (size_t)bs.xcap;
+    st.xv2 = bs.xv2 + slot * (size_t)bs.xcap;
+    st.xu2 = bs.xu2 + slot * (size_t)bs.xcap;
+    st.sorted = false;
     st.xv_s = t2_lds;
     st.xu_s = t2_lds + kStageX;
     st.xs_cap = kStageX;
@@ -1929,6 +2006,7 @@ struct ReplayStore {
     int32_t ns;
 
     static constexpr int kCap = CAP;
+    static constexpr bool kSortExtras = false;  // the extra edges are in LDS
     __device__ static constexpr int cap_lv() { return LVCAP; }
     __device__ static constexpr int cap_x() { return XCAP; }
     __device__ int get_parent(int lid) const { return lid < ns ? -1 : (int)parent[lid - ns]; }
