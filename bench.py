@@ -388,6 +388,8 @@ def main():
     ap.add_argument("--graphs", default="wc100k,wc1m,wc4m", help="graphs of --serve")
     ap.add_argument("--rate", type=float, default=200.0, help="arrivals per second for --serve")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shape")
+    ap.add_argument("--theta", type=int, default=0, help="worlds per pass instead of the workload's")
+    ap.add_argument("--k", type=int, default=-1, help="budget of the solves instead of the workload's")
     ap.add_argument("--packed", type=int, default=0, help="measure a batch of this many from-scratch passes instead")
     ap.add_argument("--packed-worlds", type=int, default=2000, help="worlds per query of --packed")
     ap.add_argument("--packed-reps", type=int, default=5, help="timed repetitions of --packed")
@@ -428,6 +430,10 @@ def main():
     log(f"generating workload {args.workload}")
     t0 = time.perf_counter()
     g, seeds, k, theta = synth.workload(args.workload)
+    if args.theta > 0:
+        theta = args.theta  # the workload's graph and seeds with another world count
+    if args.k >= 0:
+        k = args.k
     log(f"  n={g.n} m={g.m} |S|={len(seeds)} k={k} theta={theta} ({time.perf_counter() - t0:.1f} s)")
 
     # inputs resident in HBM
