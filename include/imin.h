@@ -368,7 +368,8 @@ imin_status_t imin_evaluate_batch(imin_graph_t g, const imin_eval_query_t* queri
  *
  * The worlds' dominator trees stay resident (16 bytes per reached non-seed
  * per world, plus 8 for the node index): IMIN_ERR_NOMEM when they exceed the
- * device or 2^31 - 1 entries.  Errors otherwise as for imin_solve.
+ * device or 0xFF000000 - 1 entries (store positions are unsigned 32-bit).
+ * Errors otherwise as for imin_solve.
  */
 imin_status_t imin_max_coverage(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k,
                                 int64_t theta, uint64_t rng_seed, void* stream, int32_t* blockers,
@@ -703,8 +704,9 @@ uint32_t imin_last_device_flags(void);
 /*
  * Whether this thread's last blocking imin_solve ran incremental rounds (1)
  * or re-evaluated every world each round (0: its resident store would have
- * exceeded IMIN_STORE_CAP entries or the device; the results are the same
- * integers, only slower); -1 before any completed solve.
+ * exceeded IMIN_STORE_CAP entries, at most 0xFF000000 - 1, or the device;
+ * the results are the same integers, only slower); -1 before any completed
+ * solve.
  */
 int32_t imin_last_solve_incremental(void);
 

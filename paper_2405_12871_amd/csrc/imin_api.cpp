@@ -476,7 +476,8 @@ struct Session {
     bool incremental = false;
     size_t store_budget = 0;
     // node -> stored entries (position, world), built after round 0
-    DevArray<int32_t> idx_off, idx_bcnt, idx_bbase, idx_bcur, idx_border;
+    DevArray<uint32_t> idx_off, idx_bcnt, idx_bbase, idx_bcur;  // positions and offsets: uint32
+    DevArray<int32_t> idx_border;
     DevArray<int4> idx_rec;  // the index build's entries grouped by bucket
     DevArray<int2> idx_ent;  // (store position, world) of each entry, grouped by node
     // level-0 slot groups of the seeds, with their columns and thresholds;
@@ -1089,8 +1090,9 @@ struct Session {
     // Resident store for incremental rounds: per-world offsets and lengths;
     // entries are allocated as round 0 produces them.
     imin_status_t enable_store(uint64_t theta) {
-        // the index keeps store positions as int32
-        store_budget = std::min<size_t>(env_size("IMIN_STORE_CAP", (size_t)1 << 30), (size_t)0x7FFFFFFF);
+        // the index keeps store positions as uint32
+        store_budget = std::min<size_t>(env_size("IMIN_STORE_CAP", (size_t)imin::kIndexPosLimit - 1),
+                                        (size_t)imin::kIndexPosLimit - 1);
         if (store_off.alloc(theta) != hipSuccess || store_len.alloc(theta) != hipSuccess ||
             list0.alloc(theta) != hipSuccess) {
             store_off.release();
@@ -1183,7 +1185,7 @@ struct Session {
         if (indexed) return IMIN_OK;
         if (!ws) {
             const unsigned long long entries = adopted ? adopted_entries : hctl.p->store_count;
-            if (entries > 0x7FFFFFFFull) return IMIN_ERR_INTERNAL;  // positions are int32
+            if (entries >= imin::kIndexPosLimit) return IMIN_ERR_INTERNAL;  // positions are uint32
             IMIN_TRY(alloc_index((size_t)entries));
         }
         imin::IndexBufs ib{};
@@ -1203,7 +1205,7 @@ struct Session {
         return IMIN_OK;
     }
 
-    // arrays of the node index for `entries` stored entries (< 2^31).
+    // arrays of the node index for `entries` stored entries (< kIndexPosLimit).
     // Nodes are grouped in buckets of 2^IMIN_INDEX_BUCKET_LOG ids (default
     // 10), widened until there are at most 8192 buckets.
     int idx_shift = 10;
@@ -1523,8 +1525,8 @@ struct Session {
                 continue;
             }
             const unsigned long long total = hctl.p->tile_total;
-            if (store_mode && incremental && done == 0 && nw == count && total < (1ull << 31) &&
-                scr_node.count < (1ull << 31)) {
+            if (store_mode && incremental && done == 0 && nw == count && total < imin::kIndexPosLimit &&
+                scr_node.count < imin::kIndexPosLimit) {
                 // One tile holds every world: its scratch becomes the store
                 // where it lies (fixed tier-0 slots and the bump region,
                 // located by wloc / wlen), with no copy.  The gains follow
@@ -1794,12 +1796,13 @@ static imin_status_t solve_impl(imin_graph_t g, const int32_t* seeds, int32_t n_
     // count lists when they fit (incremental rounds)
     IMIN_TRY(ss.world_size.alloc((size_t)theta));
     // the resident store when earlier calls on the graph suggest its entries
-    // can be indexed with 32-bit positions (else plain rounds from the start)
+    // can be indexed with 32-bit unsigned positions (else plain rounds from
+    // the start)
     const char* inc_env = std::getenv("IMIN_INCREMENTAL");
     const unsigned long long est =
         ((g->big_per_world.load() * (unsigned long long)theta) >> 10) +
         (unsigned long long)theta * (unsigned long long)imin::world_tier0_capacity();
-    if (!(inc_env && inc_env[0] == '0') && est < (1ull << 31)) {
+    if (!(inc_env && inc_env[0] == '0') && est < imin::kIndexPosLimit) {
         st = ss.enable_store((uint64_t)theta);
         if (st != IMIN_OK) return st;
     }
@@ -1891,11 +1894,11 @@ static void fixed_plan(imin_graph_t g, WsPlan& p, int32_t n_seeds, uint64_t thet
     else if (g->tier2_share.load(std::memory_order_relaxed) > 512) p.start_tier = 2;
 }
 
-// incremental rounds index every scratch entry with an int32 position
+// incremental rounds index every scratch entry with a uint32 position
 static bool incremental_fits(uint64_t theta, size_t big_cap) {
     const char* inc_env = std::getenv("IMIN_INCREMENTAL");
     if (inc_env && inc_env[0] == '0') return false;
-    return theta * (uint64_t)imin::world_tier0_capacity() + big_cap < ((uint64_t)1 << 31);
+    return theta * (uint64_t)imin::world_tier0_capacity() + big_cap < imin::kIndexPosLimit;
 }
 
 // The layout for a workspace of `bytes`: incremental rounds when they fit,
@@ -1912,7 +1915,8 @@ static imin_status_t plan_for(imin_graph_t g, int32_t n_seeds, uint64_t theta, s
         p.big_cap = (size_t)1 << 20;
         const size_t per = (plan_bytes(g, p, theta, n_seeds) - base + ((size_t)1 << 20) - 1) >> 20;
         size_t big = (bytes - base) / std::max<size_t>(per, 1);
-        if (p.incremental) big = std::min<size_t>(big, ((size_t)1 << 31) - 1 - theta * (size_t)imin::world_tier0_capacity());
+        if (p.incremental)
+            big = std::min<size_t>(big, (size_t)imin::kIndexPosLimit - 1 - theta * (size_t)imin::world_tier0_capacity());
         p.big_cap = big;
         while (p.big_cap > 0 && plan_bytes(g, p, theta, n_seeds) > bytes) p.big_cap -= std::min<size_t>(p.big_cap, 4096);
         out = p;
@@ -2197,8 +2201,9 @@ static imin_status_t max_coverage_impl(imin_graph_t g, const int32_t* seeds, int
     }
     if (lrr && (st = ss.setup_lrr(g, vp)) != IMIN_OK) return st;
     IMIN_TRY(ss.world_size.alloc((size_t)theta));
-    // the store (dominator trees, or LRR sets): positions are int32 in the index
-    ss.store_budget = std::min<size_t>(env_size("IMIN_COVER_STORE_CAP", (size_t)0x7FFFFFFF), (size_t)0x7FFFFFFF);
+    // the store (dominator trees, or LRR sets): positions are uint32 in the index
+    ss.store_budget = std::min<size_t>(env_size("IMIN_COVER_STORE_CAP", (size_t)imin::kIndexPosLimit - 1),
+                                       (size_t)imin::kIndexPosLimit - 1);
     IMIN_TRY(ss.store_off.alloc((size_t)theta));
     IMIN_TRY(ss.store_len.alloc((size_t)theta));
     IMIN_TRY(ss.list0.alloc((size_t)theta));

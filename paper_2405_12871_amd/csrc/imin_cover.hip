@@ -190,7 +190,7 @@ __global__ __launch_bounds__(kPickNT) void k_topk_pick(CoverOut co, int r, int s
 // The pick's worlds: idx_ent[idx_off[u] .. idx_off[u+1]) are (position,
 // world) of u's entries; one wave per entry.
 template <bool SETS>
-__global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut out, const int32_t* __restrict__ idx_off,
+__global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut out, const uint32_t* __restrict__ idx_off,
                                                          const int2* __restrict__ idx_ent, int64_t* gain, long long* dsz,
                                                          uint32_t* excl) {
     __shared__ long long part[kUpdNT / 64];
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut 
     const int nwaves = gridDim.x * (kUpdNT / 64);
     long long acc = 0;
     bool bad = false;
-    const int32_t a = idx_off[u], b = idx_off[u + 1];
-    for (int i = a + gw; i < b; i += nwaves) {
+    const uint32_t a = idx_off[u], b = idx_off[u + 1];
+    for (uint32_t i = a + (uint32_t)gw; i < b; i += (uint32_t)nwaves) {
         const int2 e = idx_ent[i];
-        const long long pos = e.x;
+        const long long pos = index_pos(e);
         const int w = e.y;
         const int c = out.store_cnt[pos];
         if (c <= 0) continue;  // u is covered in this world already (uniform per wave)
@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kUpdNT) void k_cover_update(RoundCtl* ctl, TileOut 
 }  // namespace
 
 hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, const SelectOut& so,
-                              const CoverOut& co, int r, int key_bits, const TileOut& out, const int32_t* idx_off,
+                              const CoverOut& co, int r, int key_bits, const TileOut& out, const uint32_t* idx_off,
                               const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, bool sets,
                               hipStream_t s) {
     if (grid < 1 || grid > dsz_n || key_bits < 1 || key_bits > 62) return hipErrorInvalidValue;

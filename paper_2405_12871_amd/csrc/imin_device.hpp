@@ -39,16 +39,18 @@ __device__ __forceinline__ bool bit_set(const uint32_t* bits, int32_t v) {
     return (bits[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u;
 }
 
-// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64);
-// `tmp` holds NT/64 ints of LDS.  All threads must call it.
-template <int NT>
-__device__ __forceinline__ int block_excl_scan(int x, int* tmp, int& total) {
+// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64)
+// of int, or of uint32_t where sums may pass 2^31 (they wrap modulo 2^32);
+// `tmp` holds NT/64 values of LDS.  All threads must call it.
+template <int NT, class T = int>
+__device__ __forceinline__ T block_excl_scan(T x, T* tmp, T& total) {
+    static_assert(sizeof(T) == 4, "32-bit sums");
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
-    int inc = x;
+    T inc = x;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(inc, d, 64);
+        const T y = __shfl_up(inc, d, 64);
         if (lane >= d) inc += y;
     }
     if constexpr (NT == 64) {
@@ -57,11 +59,11 @@ __device__ __forceinline__ int block_excl_scan(int x, int* tmp, int& total) {
     } else {
         if (lane == 63) tmp[wid] = inc;
         __syncthreads();
-        int pre = 0, tot = 0;
+        T pre = 0, tot = 0;
 #pragma unroll
         for (int i = 0; i < NT / 64; ++i) {
-            const int v = tmp[i];
-            pre += (i < wid) ? v : 0;
+            const T v = tmp[i];
+            pre += (i < wid) ? v : T(0);
             tot += v;
         }
         __syncthreads();

@@ -391,30 +391,38 @@ struct SelectOut;
 hipError_t launch_replay_wide(const QueryDev& q, RoundCtl* ctl, const TileOut& out, const int32_t* in_list,
                               int32_t* over_list, int grid, hipStream_t s, const LaunchEvents& ev = LaunchEvents());
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                               int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
+                               int rule_parts, int replay_parts, int lanes, const uint32_t* idx_off,
                                const int2* idx_ent, const SelectOut& so, hipStream_t s,
                                const LaunchEvents& ev = LaunchEvents());
 constexpr int kRuleNT = 256;  // four worlds at a time per workgroup
+// Store positions and index offsets are unsigned 32-bit: the first word of
+// an index entry or partition record is a position read as uint32_t.  The
+// store's capacity and the index's entries stay below kIndexPosLimit, which
+// leaves every cursor plus any launch's stride (< 2^24) below 2^32.
+constexpr unsigned long long kIndexPosLimit = 0xFF000000ull;
+__host__ __device__ constexpr uint32_t index_pos(int2 e) { return (uint32_t)e.x; }
+
 // Buffers of the index build: nodes fall in nb buckets of 2^shift ids
 // (nb <= 8192, nb << shift >= n); rec and idx_ent hold every stored entry.
 struct IndexBufs {
     int shift;
     int nb;
-    int32_t* bcnt;   // [nb] entries per bucket
-    int32_t* bbase;  // [nb + 1] first entry of each bucket
-    int32_t* bcur;   // [nb] partition cursors
+    uint32_t* bcnt;  // [nb] entries per bucket
+    uint32_t* bbase; // [nb + 1] first entry of each bucket
+    uint32_t* bcur;  // [nb] partition cursors
     int32_t* border; // [nb] buckets by decreasing size class
     int4* rec;       // [rec_cap] (position, world, node, count) grouped by bucket
     uint32_t rec_cap;
-    int32_t* idx_off;  // [n + 1] first index entry of each node
-    int2* idx_ent;     // [ent_cap] (store position, world) grouped by node
+    uint32_t* idx_off;  // [n + 1] first index entry of each node
+    int2* idx_ent;      // [ent_cap] (store position, world) grouped by node
     uint32_t ent_cap;
 };
 // node -> (store position, world) of every entry of the resident store;
 // with gain non-null also the from-scratch gains (gain[u] += every count of u)
 hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, const IndexBufs& ib, int64_t* gain,
                               RoundCtl* ctl, hipStream_t s);
-hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int2* idx_ent, int32_t* list, const SelectOut& so, hipStream_t s);
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const uint32_t* idx_off, const int2* idx_ent,
+                                  int32_t* list, const SelectOut& so, hipStream_t s);
 hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns, int32_t* cnt, RoundCtl* ctl,
                              hipStream_t s);
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
@@ -472,7 +480,7 @@ hipError_t launch_select(const GraphDev& g, const int64_t* gain, RoundCtl* ctl, 
 // dominator trees: covering a set zeroes every member entry, and the
 // newly covered count is one per set.
 hipError_t launch_cover_round(const GraphDev& g, int64_t* gain, RoundCtl* ctl, const SelectOut& so,
-                              const CoverOut& co, int r, int key_bits, const TileOut& out, const int32_t* idx_off,
+                              const CoverOut& co, int r, int key_bits, const TileOut& out, const uint32_t* idx_off,
                               const int2* idx_ent, long long* dsz, int32_t dsz_n, int grid, bool sets,
                               hipStream_t s);
 // LRR sets of samples [w_begin, w_begin + count) of the pool keyed by q's

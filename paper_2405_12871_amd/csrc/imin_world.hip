@@ -1587,7 +1587,7 @@ __device__ __forceinline__ void for_stored_entries(const TileOut& out, uint32_t 
 
 // entries per bucket
 __global__ __launch_bounds__(kIdxNT) void k_index_bucket_count(TileOut out, uint32_t theta, int shift, int nb,
-                                                              int32_t* bcnt, RoundCtl* ctl) {
+                                                              uint32_t* bcnt, RoundCtl* ctl) {
     __shared__ int32_t h[kIdxMaxBuckets];
     const uint32_t w0 = blockIdx.x * kIdxWorldsPerWG;
     const uint32_t w1 = min(theta, w0 + kIdxWorldsPerWG);
@@ -1602,37 +1602,37 @@ __global__ __launch_bounds__(kIdxNT) void k_index_bucket_count(TileOut out, uint
     if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += kIdxNT)
-        if (h[i]) atomicAdd(&bcnt[i], h[i]);
+        if (h[i]) atomicAdd(&bcnt[i], (uint32_t)h[i]);
 }
 
-__device__ __forceinline__ int bucket_size_class(int v) { return v > 0 ? 32 - __clz(v) : 0; }
+__device__ __forceinline__ int bucket_size_class(uint32_t v) { return v ? 32 - __clz((int)v) : 0; }
 
 // bucket bases: bbase[b] = entries of the buckets before b, bbase[nb] = all;
 // the partition's cursors start at the bases.  border lists the buckets by
 // decreasing size class (floor(log2(entries)) + 1), the order in which the
 // owning workgroups start.
-__global__ __launch_bounds__(1024) void k_index_bucket_scan(const int32_t* bcnt, int nb, int32_t* bbase,
-                                                           int32_t* bcur, int32_t* border) {
-    __shared__ int tmp[16];
+__global__ __launch_bounds__(1024) void k_index_bucket_scan(const uint32_t* bcnt, int nb, uint32_t* bbase,
+                                                           uint32_t* bcur, int32_t* border) {
+    __shared__ long long tmp[16];
     __shared__ int cls[33];
     if (threadIdx.x < 33) cls[threadIdx.x] = 0;
     __syncthreads();
-    int run = 0;
+    long long run = 0;  // the host keeps the total below kIndexPosLimit
     for (int c0 = 0; c0 < nb; c0 += 1024) {
         const int i = c0 + threadIdx.x;
-        const int v = i < nb ? bcnt[i] : 0;
-        int tot;
-        const int ex = block_excl_scan<1024>(v, tmp, tot);
+        const uint32_t v = i < nb ? bcnt[i] : 0u;
+        long long tot;
+        const long long ex = block_excl_scan_ll<1024>((long long)v, tmp, tot);
         if (i < nb) {
-            bbase[i] = run + ex;
-            bcur[i] = run + ex;
+            bbase[i] = (uint32_t)(run + ex);
+            bcur[i] = (uint32_t)(run + ex);
             atomicAdd(&cls[bucket_size_class(v)], 1);
         }
         run += tot;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        bbase[nb] = run;
+        bbase[nb] = (uint32_t)run;
         int start = 0;
         for (int k = 32; k >= 0; --k) {
             const int c = cls[k];
@@ -1660,14 +1660,14 @@ size_t index_partition_lds(int nb) {
 }
 
 __global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_t theta, int shift, int nb,
-                                                           int32_t* bcur, int4* rec, uint32_t rec_cap,
+                                                           uint32_t* bcur, int4* rec, uint32_t rec_cap,
                                                            RoundCtl* ctl) {
     extern __shared__ int4 part_lds[];
     int4* stage = part_lds;                                                      // [kPartStage]
     long long* woff = reinterpret_cast<long long*>(stage + kPartStage);          // [worlds]
     int32_t* wpre = reinterpret_cast<int32_t*>(woff + kIdxWorldsPerWG);         // [worlds + 1]
     int32_t* bnum = wpre + kIdxWorldsPerWG + 1;                                  // [nb] count, then base
-    int32_t* bdel = bnum + nb;                                                   // [nb] global - local
+    uint32_t* bdel = reinterpret_cast<uint32_t*>(bnum + nb);                     // [nb] global - local (mod 2^32)
     __shared__ int tmp[kIdxNT / 64];
     constexpr int kPer = kPartStage / kIdxNT;
     const int t = threadIdx.x;
@@ -1702,7 +1702,7 @@ __global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_
                     else hi = mid;
                 }
                 const long long pos = woff[lo] + (k - wpre[lo]);
-                rp[j] = (int32_t)pos;
+                rp[j] = (int32_t)(uint32_t)pos;
                 rw[j] = (int32_t)(w0 + (uint32_t)lo);
                 ru[j] = out.store_node[pos];
                 rc[j] = out.store_cnt[pos];
@@ -1726,7 +1726,7 @@ __global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_
         for (int bk = b0; bk < b1; ++bk) {
             const int c = bnum[bk];
             bnum[bk] = base;
-            if (c) bdel[bk] = atomicAdd(&bcur[bk], c) - base;
+            if (c) bdel[bk] = atomicAdd(&bcur[bk], (uint32_t)c) - (uint32_t)base;
             base += c;
         }
         __syncthreads();
@@ -1736,7 +1736,7 @@ __global__ __launch_bounds__(kIdxNT) void k_index_partition(TileOut out, uint32_
         __syncthreads();
         for (int i = t; i < staged; i += kIdxNT) {
             const int4 r = stage[i];
-            const uint32_t g = (uint32_t)(bdel[(uint32_t)r.z >> shift] + i);
+            const uint32_t g = bdel[(uint32_t)r.z >> shift] + (uint32_t)i;
             if (g < rec_cap) rec[g] = r;
             else bad = true;
         }
@@ -1774,25 +1774,25 @@ __device__ __forceinline__ int own_hot_slot(uint32_t d, bool ok) {
 // count and sum in registers while counting, and takes that node's ranks
 // with one counter update per instruction while placing.
 template <bool GAIN>
-__global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t rec_cap, const int32_t* bbase,
+__global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t rec_cap, const uint32_t* bbase,
                                                      const int32_t* border, int nb, int shift, int32_t n,
-                                                     int32_t* idx_off, int2* idx_ent, uint32_t ent_cap,
+                                                     uint32_t* idx_off, int2* idx_ent, uint32_t ent_cap,
                                                      int64_t* gain, RoundCtl* ctl) {
-    __shared__ int32_t cnt[kOwnSlots];
+    __shared__ uint32_t cnt[kOwnSlots];
     __shared__ unsigned long long gs[GAIN ? kOwnSlots : 1];
-    __shared__ int tmp[kOwnNT / 64];
+    __shared__ uint32_t tmp[kOwnNT / 64];
     const int b = border[blockIdx.x];
     if (b < 0 || b >= nb) {  // the order is a permutation of the buckets
         if (threadIdx.x == 0) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
         return;
     }
     // records [r0, r1) (within rec_cap even if the partition overflowed)
-    const uint32_t r0 = min((uint32_t)bbase[b], rec_cap), r1 = min((uint32_t)bbase[b + 1], rec_cap);
+    const uint32_t r0 = min(bbase[b], rec_cap), r1 = min(bbase[b + 1], rec_cap);
     const int32_t lo = (int32_t)((long long)b << shift);
     const int32_t hi = (int32_t)min((long long)n, (long long)lo + (1ll << shift));
     const int t = threadIdx.x;
     const int lane = t & 63;
-    int32_t run = (int32_t)r0;
+    uint32_t run = r0;
     bool bad = false;
     for (int32_t sub = lo; sub < hi; sub += kOwnSlots) {
         const int ns = min(kOwnSlots, hi - sub);
@@ -1820,7 +1820,7 @@ __global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t 
                         ++hot_n;
                         if (GAIN) hot_s += (uint32_t)e[j].w;
                     } else {
-                        atomicAdd(&cnt[d], 1);
+                        atomicAdd(&cnt[d], 1u);
                         if (GAIN) atomicAdd(&gs[d], (unsigned long long)(uint32_t)e[j].w);
                     }
                 }
@@ -1833,16 +1833,16 @@ __global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t 
                 if (GAIN) hot_s += __shfl_xor(hot_s, k, 64);
             }
             if (lane == 0 && hot_n) {
-                atomicAdd(&cnt[hot], hot_n);
+                atomicAdd(&cnt[hot], (uint32_t)hot_n);
                 if (GAIN) atomicAdd(&gs[hot], hot_s);
             }
         }
         __syncthreads();
         // two consecutive slots per thread
-        const int a0 = cnt[2 * t], a1 = cnt[2 * t + 1];
-        int tot;
-        const int32_t o0 = run + block_excl_scan<kOwnNT>(a0 + a1, tmp, tot);
-        const int32_t o1 = o0 + a0;
+        const uint32_t a0 = cnt[2 * t], a1 = cnt[2 * t + 1];
+        uint32_t tot;
+        const uint32_t o0 = run + block_excl_scan<kOwnNT, uint32_t>(a0 + a1, tmp, tot);
+        const uint32_t o1 = o0 + a0;
         cnt[2 * t] = o0;
         cnt[2 * t + 1] = o1;
         if (2 * t < ns) {
@@ -1880,11 +1880,11 @@ __global__ __launch_bounds__(kOwnNT) void k_index_own(const int4* rec, uint32_t 
                 if (m) {
                     const int leader = __ffsll((long long)m) - 1;
                     uint32_t base = 0;
-                    if (lane == leader) base = (uint32_t)atomicAdd(&cnt[hot], __popcll(m));
+                    if (lane == leader) base = atomicAdd(&cnt[hot], (uint32_t)__popcll(m));
                     base = __shfl(base, leader, 64);
                     p = base + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
                 }
-                if (ok && !is_hot) p = (uint32_t)atomicAdd(&cnt[d], 1);
+                if (ok && !is_hot) p = atomicAdd(&cnt[d], 1u);
                 if (ok) {
                     if (p < ent_cap) idx_ent[p] = make_int2(e[j].x, e[j].y);
                     else bad = true;
@@ -1911,7 +1911,7 @@ __device__ __forceinline__ bool label_rule_holds(uint8_t wflags, uint32_t lab) {
 // the last selection (the same result everywhere); workgroup 0 commits it.
 // Then the worlds whose entry for the new blocker u is live are listed in
 // list[0 .. list_n[0]) for the sampling tiers.
-__global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const int32_t* idx_off,
+__global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* ctl, const uint32_t* idx_off,
                                                          const int2* idx_ent,
                                                          int32_t* list, SelectOut so) {
     __shared__ int64_t sg[256];
@@ -1926,16 +1926,16 @@ __global__ __launch_bounds__(256) void k_affected_select(TileOut out, RoundCtl* 
     if (blockIdx.x == 0 && threadIdx.x == 0) select_commit(ctl, so, r, bg, bu, dl);
     if (select_stops(r, so.k, bu, bg) || r + 1 == so.k) return;  // no further round
     const int32_t u = bu;
-    const int32_t a = idx_off[u], b = idx_off[u + 1];
+    const uint32_t a = idx_off[u], b = idx_off[u + 1];
     const int lane = threadIdx.x & 63;
     const unsigned long long below = (1ull << lane) - 1ull;
-    for (int i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
-        const int k = i + lane;
+    for (uint32_t i = a + blockIdx.x * 256 + threadIdx.x - lane; i < b; i += gridDim.x * 256) {
+        const uint32_t k = i + lane;
         int32_t w = 0, c = 0;
         if (k < b) {
             const int2 e = idx_ent[k];
             w = e.y;
-            c = out.store_cnt[e.x];
+            c = out.store_cnt[index_pos(e)];
         }
         const bool live = c > 0;
         const unsigned long long mr = __ballot(live);
@@ -1954,7 +1954,7 @@ hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, con
                               RoundCtl* ctl, hipStream_t s) {
     if (ib.nb < 1 || ib.nb > kIdxMaxBuckets || ((long long)ib.nb << ib.shift) < (long long)n) return hipErrorInvalidValue;
     const unsigned groups = (theta + kIdxWorldsPerWG - 1) / kIdxWorldsPerWG;
-    hipError_t e = launch_fill_i32(ib.bcnt, 0, (size_t)ib.nb, s);
+    hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(ib.bcnt), 0, (size_t)ib.nb, s);
     if (e != hipSuccess) return e;
     if (groups > 0) {
         k_index_bucket_count<<<groups, kIdxNT, 0, s>>>(out, theta, ib.shift, ib.nb, ib.bcnt, ctl);
@@ -1979,7 +1979,8 @@ hipError_t launch_index_build(const TileOut& out, uint32_t theta, int32_t n, con
     return hipGetLastError();
 }
 
-hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const int32_t* idx_off, const int2* idx_ent, int32_t* list, const SelectOut& so, hipStream_t s) {
+hipError_t launch_affected_select(const TileOut& out, RoundCtl* ctl, const uint32_t* idx_off, const int2* idx_ent,
+                                  int32_t* list, const SelectOut& so, hipStream_t s) {
     k_affected_select<<<256, 256, 0, s>>>(out, ctl, idx_off, idx_ent, list, so);
     return hipGetLastError();
 }
@@ -2235,7 +2236,7 @@ __device__ __forceinline__ int bfs_replay(const QueryDev& q, int32_t ustar, cons
         }
         // local ids and extra-edge slots: one scan of (claims, extras)
         int tot;
-        const int ex = block_excl_scan<NT>(__popc(win) | (__popc(ext) << 16), sh.scan_tmp, tot);
+        const int ex = block_excl_scan<NT, int>(__popc(win) | (__popc(ext) << 16), sh.scan_tmp, tot);
         int lid = count + (ex & 0xFFFF);
         int xs = nx + (ex >> 16);
 #pragma unroll
@@ -2402,11 +2403,11 @@ __device__ __forceinline__ void replay_one(const QueryDev& q, RoundCtl* ctl, int
 }
 
 __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                                              const int32_t* idx_off, const int2* idx_ent, int32_t ustar,
+                                              const uint32_t* idx_off, const int2* idx_ent, int32_t ustar,
                                               ReplayShared& rs, uint32_t part, uint32_t parts) {
     static_assert(kReplaySlice <= kReplayNT, "one thread per entry of a slice");
     const int t = threadIdx.x;
-    const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
+    const uint32_t a = idx_off[ustar], b = idx_off[ustar + 1];
     if ((long long)a + (long long)part * kReplaySlice >= (long long)b) return;  // no slice for this workgroup
     ReplayAcc acc;
     for (long long base = (long long)a + (long long)part * kReplaySlice; base < (long long)b;
@@ -2415,7 +2416,7 @@ __device__ __forceinline__ void replay_worlds(const QueryDev& q, RoundCtl* ctl, 
         __syncthreads();
         if (t < kReplaySlice && base + t < (long long)b) {
             const int2 ie = idx_ent[base + t];
-            const int32_t pos = ie.x;
+            const uint32_t pos = index_pos(ie);
             const int32_t w = ie.y;
             // the world's record is read with u's entry, whether or not it
             // is listed: one round trip
@@ -2542,7 +2543,8 @@ struct RuleShared {
 
 // What is read of one index entry before deciding.
 struct RuleMeta {
-    int32_t pos, w, c;
+    uint32_t pos;
+    int32_t w, c;
     uint32_t lab;
     uint8_t flags;
     int64_t off;
@@ -2608,12 +2610,12 @@ __device__ __forceinline__ int rule_span(const TileOut& out, RuleSums& sums, siz
 }
 
 template <int LANES>
-__device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const int32_t* idx_off,
+__device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, const uint32_t* idx_off,
                                             const int2* idx_ent, int32_t ustar,
                                             RuleShared& fs, uint32_t part, uint32_t parts) {
     static_assert(LANES == 16 || LANES == 32 || LANES == 64, "a world per 16, 32 or 64 lanes");
     constexpr int kGroups = kRuleNT / LANES;  // worlds of a workgroup at a time
-    const int32_t a = idx_off[ustar], b = idx_off[ustar + 1];
+    const uint32_t a = idx_off[ustar], b = idx_off[ustar + 1];
     RuleSums& sums = fs.sums;
     sums.clear<kRuleNT>();  // while u's index range is on its way
     if (threadIdx.x < 4) fs.red[threadIdx.x] = 0;
@@ -2623,31 +2625,33 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
     const int gl = lane % LANES;  // lane within the world's group
     const int group = (int)threadIdx.x / LANES;
     const unsigned long long gmask = (LANES == 64) ? ~0ull : (((1ull << LANES) - 1ull) << (lane - gl));
-    const int stride = (int)parts * kGroups;
+    const uint32_t stride = parts * kGroups;
     unsigned long long acc_w = 0, acc_e = 0, acc_b = 0;
     long long acc_d = 0;
 
     // uniform over the group: entry k0 now, k1 next, k2 after that
-    int k0 = a + (int)part * kGroups + group;
+    uint32_t k0 = a + part * kGroups + (uint32_t)group;
     RuleMeta m0{};
     if (k0 < b) {
         const int2 e = idx_ent[k0];
-        m0.pos = e.x;
+        m0.pos = index_pos(e);
         m0.w = e.y;
         rule_meta(out, m0);
     }
-    int k1 = k0 + stride;
-    int32_t p1 = 0, w1 = 0;
+    uint32_t k1 = k0 + stride;
+    uint32_t p1 = 0;
+    int32_t w1 = 0;
     if (k1 < b) {
         const int2 e = idx_ent[k1];
-        p1 = e.x;
+        p1 = index_pos(e);
         w1 = e.y;
     }
     while (k0 < b) {
         // next entry's decision data, and the index of the one after
         RuleMeta m1{};
-        const int k2 = k1 + stride;
-        int32_t p2 = 0, w2 = 0;
+        const uint32_t k2 = k1 + stride;
+        uint32_t p2 = 0;
+        int32_t w2 = 0;
         if (k1 < b) {
             m1.pos = p1;
             m1.w = w1;
@@ -2655,7 +2659,7 @@ __device__ __forceinline__ void rule_worlds(RoundCtl* ctl, const TileOut& out, c
         }
         if (k2 < b) {
             const int2 e = idx_ent[k2];
-            p2 = e.x;
+            p2 = index_pos(e);
             w2 = e.y;
         }
         const size_t so0 = (size_t)m0.off;
@@ -2715,7 +2719,7 @@ union UpdateShared {
 
 template <int LANES>
 __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, RoundCtl* ctl, int32_t* next_list, TileOut out,
-                                                             uint32_t rule_parts, const int32_t* idx_off,
+                                                             uint32_t rule_parts, const uint32_t* idx_off,
                                                              const int2* idx_ent,
                                                              SelectOut so) {
     __shared__ UpdateShared u;
@@ -2739,10 +2743,13 @@ __global__ __launch_bounds__(kReplayNT, 5) void k_round_update(QueryDev q, Round
 }
 
 hipError_t launch_round_update(const QueryDev& q, RoundCtl* ctl, int32_t* next_list, const TileOut& out,
-                               int rule_parts, int replay_parts, int lanes, const int32_t* idx_off,
+                               int rule_parts, int replay_parts, int lanes, const uint32_t* idx_off,
                                const int2* idx_ent, const SelectOut& so, hipStream_t s, const LaunchEvents& ev) {
     const unsigned grid = (unsigned)(replay_parts + rule_parts);
-    if (grid == 0 || replay_parts < 1) return hipErrorInvalidValue;
+    if (grid == 0 || replay_parts < 1 || rule_parts < 0) return hipErrorInvalidValue;
+    // index cursors advance by the parts' stride, which must stay below 2^24
+    if ((long long)grid * kReplaySlice >= (1ll << 24) || (long long)rule_parts * kRuleNT >= (1ll << 24))
+        return hipErrorInvalidValue;
     const uint32_t rp = (uint32_t)rule_parts;
     if (lanes == 16)
         return launch_k(k_round_update<16>, grid, kReplayNT, s, ev, q, ctl, next_list, out, rp, idx_off, idx_ent, so);

@@ -704,15 +704,30 @@ def test_medium_workload_every_round_reduced_theta(B, oracle_mod):
 
 
 @pytest.mark.timeout(1200)
-def test_medium_workload_full_solve(B, oracle_mod):
-    """The full medium workload (k = 100, theta = 1e5): at rounds 1 and 99
+def test_medium_workload_full_solve(B, oracle_mod, monkeypatch):
+    """The full medium workload (k = 100, theta = 1e5).  Its round 0 stores
+    about 2.35e9 entries, so the incremental rounds index store positions
+    beyond 2^31: every round equals the solve with plain rounds (every world
+    re-evaluated each round, no store), and at rounds 1 and 99
     (IMIN_TEST_MEDIUM_ROUNDS adds others) the oracle's from-scratch pass under
     the GPU's blockers so far gives the same T_r, argmax and gain."""
     g, seeds, k, theta = synth.workload("medium")
-    _log("solve medium workload (full k, theta)")
-    res = B.solve(B.Graph.from_synth(g), seeds, k, theta, 2024)
+    G = B.Graph.from_synth(g)
+    _log("solve medium workload (full k, theta), incremental rounds")
+    res = B.solve(G, seeds, k, theta, 2024)
+    assert B.last_solve_incremental() == 1
     T = res.spread_totals
+    assert T[0] > 2**31  # entries of round 0's store, one per reached non-seed
     np.testing.assert_array_equal(T[1:res.n_selected + 1], T[:res.n_selected] - res.gains[:res.n_selected])
+    _log("solve medium workload (full k, theta), plain rounds")
+    monkeypatch.setenv("IMIN_INCREMENTAL", "0")
+    plain = B.solve(G, seeds, k, theta, 2024)
+    assert B.last_solve_incremental() == 0
+    monkeypatch.delenv("IMIN_INCREMENTAL")
+    assert plain.n_selected == res.n_selected
+    np.testing.assert_array_equal(plain.blockers, res.blockers)
+    np.testing.assert_array_equal(plain.gains, res.gains)
+    np.testing.assert_array_equal(plain.spread_totals, res.spread_totals)
     rounds = [int(x) for x in os.environ.get("IMIN_TEST_MEDIUM_ROUNDS", "1,99").split(",")]
     _check_rounds_against_oracle(oracle_mod, g, seeds, theta, 2024, res, rounds)
 
