@@ -138,8 +138,10 @@ imin_status_t imin_graph_export(imin_graph_t g, int64_t* row_ptr, int32_t* col, 
  * needed, so imin_solve_workspace_size returns enough next time),
  * IMIN_ERR_INTERNAL when a consistency check fails.  The layout takes
  * incremental rounds (a resident per-world store and a node index) when the
- * stored entries can be indexed with 32-bit positions, else every round
- * evaluates all theta worlds again; both give the same integers.
+ * stored entries can be indexed with unsigned 32-bit positions and the
+ * workspace holds that layout with the bump region the graph's record asks
+ * for, else every round evaluates all theta worlds again; both give the
+ * same integers.
  *
  * With workspace == NULL the call takes its scratch from the library's
  * block cache (see imin_cache_release), waits for its work and returns the
@@ -159,9 +161,10 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
  * depends on n, m, n_seeds and theta; the bump region for worlds beyond the
  * smallest world tier is data-dependent and sized from what earlier calls on
  * the graph needed per world (at least 2^20 entries), with an eighth more.
- * A solve given more bytes uses them for that region.  Waits for the
- * device (it reads the graph's device-side record of those needs).
- * IMIN_ERR_INVALID for bad arguments.
+ * A solve given more bytes uses them for that region.  The size is that of
+ * the incremental-rounds layout while it fits the device's memory, else that
+ * of the plain-rounds layout.  Waits for the device (it reads the graph's
+ * device-side record of those needs).  IMIN_ERR_INVALID for bad arguments.
  */
 imin_status_t imin_solve_workspace_size(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes);
 

@@ -1901,11 +1901,20 @@ static bool incremental_fits(uint64_t theta, size_t big_cap) {
     return theta * (uint64_t)imin::world_tier0_capacity() + big_cap < imin::kIndexPosLimit;
 }
 
-// The layout for a workspace of `bytes`: incremental rounds when they fit,
-// else plain rounds; the bump region takes what the fixed arrays leave.
+// bump-region entries (and as many extra edges) that earlier calls on the
+// graph needed for theta worlds beyond tier 0 (0 before any record)
+static unsigned long long hinted_bump(imin_graph_t g, uint64_t theta) {
+    const uint64_t per = std::max(g->big_per_world.load(), g->xbig_per_world.load());
+    return (per * (unsigned long long)theta) >> 10;
+}
+
+// The layout for a workspace of `bytes`: incremental rounds when they fit
+// with a bump region that holds what the graph's record asks for, else
+// plain rounds; the bump region takes what the fixed arrays leave.
 static imin_status_t plan_for(imin_graph_t g, int32_t n_seeds, uint64_t theta, size_t bytes, WsPlan& out) {
     WsPlan p;
     fixed_plan(g, p, n_seeds, theta);
+    const unsigned long long need = hinted_bump(g, theta);
     for (int inc = 1; inc >= 0; --inc) {
         p.incremental = inc == 1;
         if (p.incremental && !incremental_fits(theta, 0)) continue;
@@ -1919,6 +1928,9 @@ static imin_status_t plan_for(imin_graph_t g, int32_t n_seeds, uint64_t theta, s
             big = std::min<size_t>(big, (size_t)imin::kIndexPosLimit - 1 - theta * (size_t)imin::world_tier0_capacity());
         p.big_cap = big;
         while (p.big_cap > 0 && plan_bytes(g, p, theta, n_seeds) > bytes) p.big_cap -= std::min<size_t>(p.big_cap, 4096);
+        // the larger incremental layout only when its bump region is not the
+        // one to run out
+        if (p.incremental && p.big_cap < need) continue;
         out = p;
         return IMIN_OK;
     }
@@ -1951,7 +1963,11 @@ static void fold_device_hints(imin_graph_t g) {
     if (h[3] > 0) g->tier2_seen.store(true, std::memory_order_relaxed);
 }
 
-static imin_status_t workspace_size_impl(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes) {
+// The workspace of an enqueued solve: the incremental layout when its
+// entries can be indexed and it takes at most `limit` bytes, else the plain
+// one.
+static imin_status_t workspace_size_impl(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t limit,
+                                         size_t* bytes) {
     if (!g || !bytes || n_seeds < 1 || n_seeds > g->g.n || k < 0 || k > g->g.n || theta < 1 ||
         theta > (int64_t)0xFFFFFFFFll)
         return IMIN_ERR_INVALID;
@@ -1963,11 +1979,15 @@ static imin_status_t workspace_size_impl(imin_graph_t g, int32_t n_seeds, int32_
     fixed_plan(g, p, n_seeds, (uint64_t)theta);
     // bump entries (and as many extra edges) for the worlds beyond tier 0, from
     // what earlier calls on the graph needed, with an eighth more
-    const uint64_t per = std::max(g->big_per_world.load(), g->xbig_per_world.load());
-    const unsigned long long need = (per * (unsigned long long)theta) >> 10;
+    const unsigned long long need = hinted_bump(g, (uint64_t)theta);
     p.big_cap = std::max<size_t>((size_t)1 << 20, (size_t)(need + need / 8 + 1024));
     p.incremental = incremental_fits((uint64_t)theta, p.big_cap);
-    *bytes = plan_bytes(g, p, (uint64_t)theta, n_seeds);
+    size_t b = plan_bytes(g, p, (uint64_t)theta, n_seeds);
+    if (p.incremental && b > limit) {
+        p.incremental = false;
+        b = plan_bytes(g, p, (uint64_t)theta, n_seeds);
+    }
+    *bytes = b;
     if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
     return IMIN_OK;
 }
@@ -2464,6 +2484,17 @@ static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t
 }  // extern "C"
 
 namespace imin {
+imin_status_t solve_workspace_size_within(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t limit,
+                                          size_t* bytes) {
+    try {
+        return workspace_size_impl(g, n_seeds, k, theta, limit, bytes);
+    } catch (const std::bad_alloc&) {
+        return IMIN_ERR_NOMEM;
+    } catch (...) {
+        return IMIN_ERR_INTERNAL;
+    }
+}
+
 imin_status_t solve_enqueued(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int32_t k, int64_t theta,
                              uint64_t rng_seed, void* workspace, size_t workspace_bytes, void* stream,
                              int32_t* blockers, int64_t* gains, int64_t* spread_totals, int32_t* n_selected,
@@ -2578,7 +2609,18 @@ imin_status_t imin_solve(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, 
 
 imin_status_t imin_solve_workspace_size(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t* bytes) {
     try {
-        return workspace_size_impl(g, n_seeds, k, theta, bytes);
+        // the incremental layout while it fits the device's memory
+        size_t limit = SIZE_MAX;
+        if (g) {
+            int prev = -1;
+            (void)hipGetDevice(&prev);
+            if (prev != g->device) (void)hipSetDevice(g->device);
+            size_t free_b = 0, total_b = 0;
+            if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) limit = total_b;
+            else (void)hipGetLastError();
+            if (prev >= 0 && prev != g->device) (void)hipSetDevice(prev);
+        }
+        return workspace_size_impl(g, n_seeds, k, theta, limit, bytes);
     } catch (const std::bad_alloc&) {
         return IMIN_ERR_NOMEM;
     } catch (...) {

@@ -3,7 +3,8 @@
 // share a pool of device memory and a set of streams.
 //
 // A dispatcher admits a query when the workspace its layout needs
-// (imin_solve_workspace_size) fits a free range of the pool, enqueues its
+// (imin_solve_workspace_size, with the plain-rounds layout when the
+// incremental one exceeds the pool) fits a free range of the pool, enqueues its
 // whole solve on the least loaded stream and records an event after it; the
 // query's device_status word lives in pinned host memory, so once the event
 // has completed the dispatcher reads the outcome without a copy.  A query
@@ -29,6 +30,13 @@
 #include <new>
 #include <thread>
 #include <vector>
+
+namespace imin {
+// imin_solve_workspace_size for workspaces carved from a pool of `limit`
+// bytes: the incremental layout only when it fits that limit (imin_api.cpp)
+imin_status_t solve_workspace_size_within(imin_graph_t g, int32_t n_seeds, int32_t k, int64_t theta, size_t limit,
+                                          size_t* bytes);
+}  // namespace imin
 
 namespace {
 
@@ -169,7 +177,7 @@ struct Engine {
         };
         if (!g || imin::graph_device(g) != device) return fail(IMIN_ERR_INVALID);
         size_t bytes = 0;
-        imin_status_t st = imin_solve_workspace_size(g, q->n_seeds, q->k, q->theta, &bytes);
+        imin_status_t st = imin::solve_workspace_size_within(g, q->n_seeds, q->k, q->theta, pool_bytes, &bytes);
         if (st != IMIN_OK) return fail(st);
         if (bytes > pool_bytes) {
             if (debug_on())

@@ -110,3 +110,35 @@ def test_server_readmits_after_a_device_side_shortfall(B, oracle_mod, monkeypatc
     assert res.n_selected == want["n_selected"]
     np.testing.assert_array_equal(res.blockers, want["blockers"])
     np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
+
+
+def test_server_pool_too_small_for_incremental_rounds(B, oracle_mod, monkeypatch):
+    """A pool that holds the query's plain-rounds workspace but not its
+    incremental one: the server sizes the query with the plain layout
+    instead of refusing it, and returns the oracle's selection."""
+    g = synth.random_small_graph(3000, 12000, seed=79, prob="uniform")
+    G = B.Graph.from_synth(g)
+    seeds = np.array([3, 41, 700, 1500], np.int32)
+    k, theta = 4, 4000
+    # the same query alone first: the graph then records what its worlds
+    # need beyond tier 0, and both layouts are sized for it
+    alone = B.solve(G, seeds, k, theta, 8)
+    inc = B.workspace_size(G, len(seeds), k, theta)
+    monkeypatch.setenv("IMIN_INCREMENTAL", "0")
+    plain = B.workspace_size(G, len(seeds), k, theta)
+    monkeypatch.delenv("IMIN_INCREMENTAL")
+    _log(f"workspace: incremental {inc} bytes, plain {plain} bytes")
+    assert plain + 4096 < inc
+    srv = B.Server(G, n_streams=1, hbm_budget=(plain + 256 + inc) // 2)
+    try:
+        srv.submit(seeds, k, theta, 8)
+        _, res = srv.next()
+    finally:
+        srv.close()
+    assert not isinstance(res, B.IminError), res
+    _same(res, alone)
+    want = oracle_mod.Query(g, seeds).solve(k, theta, 8)
+    assert res.n_selected == want["n_selected"]
+    np.testing.assert_array_equal(res.blockers, want["blockers"])
+    np.testing.assert_array_equal(res.gains, want["gains"])
+    np.testing.assert_array_equal(res.spread_totals, want["spread_totals"])
