@@ -48,6 +48,22 @@ constexpr int kReplayCap = 512;
 constexpr int kReplayXCap = 256;
 constexpr int kReplayEdgeCap = 768;
 
+// The rows of one BFS step: frontier nodes, their CSR ranges and the first
+// slot group of each.
+template <int NT>
+struct BfsRows {
+    int lid[NT];
+    int node[NT];
+    int e0[NT];
+    int e1[NT];
+    int start[NT];
+};
+// A one-wave world (tier 0) keeps its rows in the LDS store's dominator
+// arrays, which the BFS leaves unused: 1.25 KB less LDS per wave, one more
+// resident wave per SIMD.  Wider workgroups keep them here.
+template <int NT>
+constexpr bool kRowsInShared = NT != 64;
+
 template <int NT>
 struct WorldShared {
     int count;    // local ids handed out (= nodes reached so far)
@@ -68,11 +84,7 @@ struct WorldShared {
     unsigned long long acc_reached, acc_live;  // reached nodes (seeds included) and recorded live edges
     long long acc_dsize;  // reached nodes lost by this workgroup's worlds (incremental rounds)
     uint32_t sched;       // first world of the chunk just taken
-    int row_lid[NT];
-    int row_node[NT];
-    int row_e0[NT];
-    int row_e1[NT];
-    int row_start[NT];
+    BfsRows<kRowsInShared<NT> ? NT : 1> rows;
     int scan_tmp[NT / 64];
     long long sum_tmp[NT / 64];
 };
@@ -91,7 +103,7 @@ struct LdsStore {
     int16_t vals[kHash];
     int32_t nodes[CAPNS];
     int16_t parent[CAPNS];
-    int16_t idom[CAPNS];
+    int16_t idom[CAPNS];  // idom and aux hold a one-wave BFS's rows until the dominator phase
     int32_t aux[CAPNS];
     int32_t xv[XCAP];
     int16_t xu[XCAP];
@@ -152,6 +164,12 @@ struct LdsStore {
     __device__ int get_idom(int lid) const { return lid < ns ? -1 : (int)idom[lid - ns]; }
     __device__ void set_idom(int lid, int p) { idom[lid - ns] = (int16_t)p; }
     __device__ int32_t* aux_ptr(int lid) { return &aux[lid - ns]; }
+    template <int NT>
+    __device__ BfsRows<NT>& bfs_rows() {
+        static_assert(sizeof(idom) % 4 == 0 && sizeof(BfsRows<NT>) <= sizeof(idom) + sizeof(aux),
+                      "the rows fit idom and aux, which follow each other");
+        return *reinterpret_cast<BfsRows<NT>*>(idom);
+    }
     __device__ int get_xu(int64_t x) const { return xu[x]; }
     __device__ void set_xu(int64_t x, int u) { xu[x] = (int16_t)u; }
     __device__ int get_xv(int64_t x) const { return xv[x]; }
@@ -498,6 +516,10 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, con
     __syncthreads();
 
     // ---- deeper levels
+    BfsRows<NT>* rows_p;
+    if constexpr (kRowsInShared<NT>) rows_p = &sh.rows;
+    else rows_p = &st.template bfs_rows<NT>();
+    BfsRows<NT>& rows = *rows_p;
     int nlev = 2;  // closed levels: lvl[0..nlev]
     for (;;) {
         const int f0 = st.lvl[nlev - 1];
@@ -515,11 +537,11 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, con
             int total;
             const int start = block_excl_scan<NT>(nb, sh.scan_tmp, total);
             if (e1 > e0) atomicAdd((unsigned long long*)&sh.edges, (unsigned long long)(e1 - e0));
-            sh.row_lid[t] = i;
-            sh.row_node[t] = u;
-            sh.row_e0[t] = e0;
-            sh.row_e1[t] = e1;
-            sh.row_start[t] = start;
+            rows.lid[t] = i;
+            rows.node[t] = u;
+            rows.e0[t] = e0;
+            rows.e1[t] = e1;
+            rows.start[t] = start;
             __syncthreads();
             const int nrows = (f1 - base < NT) ? (f1 - base) : NT;
             for (int j0 = t; j0 < total; j0 += NT * kGroupsPerLane) {
@@ -531,10 +553,10 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, con
                         int lo = 0, hi = nrows - 1;
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
-                            if (sh.row_start[mid] <= j) lo = mid; else hi = mid - 1;
+                            if (rows.start[mid] <= j) lo = mid; else hi = mid - 1;
                         }
-                        gr[u] = SlotGroup{(uint32_t)(sh.row_e0[lo] >> 2) + (uint32_t)(j - sh.row_start[lo]),
-                                          sh.row_lid[lo], sh.row_node[lo], sh.row_e0[lo], sh.row_e1[lo], true};
+                        gr[u] = SlotGroup{(uint32_t)(rows.e0[lo] >> 2) + (uint32_t)(j - rows.start[lo]),
+                                          rows.lid[lo], rows.node[lo], rows.e0[lo], rows.e1[lo], true};
                     } else {
                         gr[u] = SlotGroup{0u, 0, -1, 0, 0, false};
                     }
@@ -995,11 +1017,17 @@ __device__ __forceinline__ QueryDev query_at_run(QueryDev q, const RoundCtl* ctl
 // Tier 0 (one wave, small LDS store) and tier 1 (four waves, larger LDS
 // store).  With range_count > 0 the kernel takes worlds 0..range_count-1 of
 // the tile; otherwise it takes the list handed down by the previous tier.
-using Tier0Store = LdsStore<256, 9, 128, 30>;
+// (32 extra live edges: the large trivalency workload's worlds keep 0.2 on
+// average, and a world with more goes to tier 1)
+using Tier0Store = LdsStore<256, 9, 32, 30>;
 // tier 1 keeps a level slot for every node it can hold: a world that fitted it
 // in a from-scratch pass fits it again after any blockers are added
 using Tier1Store = LdsStore<2048, 12, 1024, 2050>;
 constexpr int kTier0NT = 64;
+// Tier 0 waits on dependent global loads level after level, so resident
+// waves matter most: 6 per SIMD needs at most 80 VGPRs (the compiler keeps
+// a few values in scratch) and at most 1/24 of the LDS per wave.
+constexpr int kTier0WavesPerSimd = 6;
 constexpr uint32_t kSchedChunk = 4;  // worlds per update of a tier's work counter
 constexpr int kTier1NT = 256;
 constexpr int kTier2NT = 256;
@@ -1027,9 +1055,9 @@ __device__ __forceinline__ void add_work(const TileOut& out, int tier, unsigned 
 
 // Worlds are dealt to workgroups by a fixed stride (no shared work counter).
 template <int NT, class Store, int TIER>
-__global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q_in, RoundCtl* ctl, uint32_t w_begin,
-                                                  uint32_t range_count, const int32_t* in_list, int count_idx,
-                                                  int32_t* next_list, TileOut out) {
+__global__ __launch_bounds__(NT, (NT == kTier0NT ? kTier0WavesPerSimd : 1))
+void k_world_lds(GraphDev g, QueryDev q_in, RoundCtl* ctl, uint32_t w_begin, uint32_t range_count,
+                 const int32_t* in_list, int count_idx, int32_t* next_list, TileOut out) {
     __shared__ Store st;
     __shared__ WorldShared<NT> sh;
     const int t = threadIdx.x;
@@ -1086,8 +1114,9 @@ __global__ __launch_bounds__(NT) void k_world_lds(GraphDev g, QueryDev q_in, Rou
 // workgroup is one wave, so the world index is made uniform and the query's
 // fields are read with scalar loads.
 template <int NT, class Store>
-__global__ __launch_bounds__(NT) void k_world_lds_packed(GraphDev g, const PackedQuery* __restrict__ pq, int nq,
-                                                         uint32_t n_items, uint32_t* counter) {
+__global__ __launch_bounds__(NT, kTier0WavesPerSimd)
+void k_world_lds_packed(GraphDev g, const PackedQuery* __restrict__ pq, int nq, uint32_t n_items,
+                        uint32_t* counter) {
     static_assert(NT == 64, "the packed tier is one wave per workgroup");
     __shared__ Store st;
     __shared__ WorldShared<NT> sh;
@@ -2797,19 +2826,24 @@ __global__ __launch_bounds__(1024) void k_seed_scan(int32_t* cnt, int32_t ns, Ro
     if (threadIdx.x == 0) ctl->seed_chunks = carry;
 }
 
+// A workgroup per seed: a hub's row has thousands of slot groups, which its
+// threads fill side by side.
 __global__ void k_seed_fill(GraphDev g, const int32_t* seeds, int32_t ns, const int32_t* start, int4* table,
                             int32_t cap, RoundCtl* ctl) {
     if (ctl->stop) return;  // bad seeds: nothing to read
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x; i < ns; i += gridDim.x) {
         const int32_t v = seeds[i];
         const int e0 = g.off[v], e1 = g.off[v + 1];
         if (e1 <= e0) continue;
         const int b0 = e0 >> 2, b1 = (e1 - 1) >> 2;
-        for (int b = b0; b <= b1; ++b) {
-            const int j = start[i] + (b - b0);
+        const int j0 = start[i];
+        bool bad = false;
+        for (int b = b0 + (int)threadIdx.x; b <= b1; b += (int)blockDim.x) {
+            const int j = j0 + (b - b0);
             if (j < cap) table[j] = make_int4(b, i, e0, e1);
-            else atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
+            else bad = true;
         }
+        if (bad) atomicOr(&ctl->flags, (uint32_t)kFlagBounds);
     }
 }
 
@@ -2863,7 +2897,7 @@ hipError_t launch_seed_count(const GraphDev& g, const int32_t* seeds, int32_t ns
 
 hipError_t launch_seed_fill(const GraphDev& g, const int32_t* seeds, int32_t ns, const int32_t* start,
                             int4* table, int32_t cap, RoundCtl* ctl, hipStream_t s) {
-    k_seed_fill<<<(ns + 255) / 256, 256, 0, s>>>(g, seeds, ns, start, table, cap, ctl);
+    k_seed_fill<<<(unsigned)std::max(1, std::min(ns, 65535)), 256, 0, s>>>(g, seeds, ns, start, table, cap, ctl);
     return hipGetLastError();
 }
 
