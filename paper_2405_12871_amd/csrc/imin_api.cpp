@@ -873,8 +873,10 @@ struct Session {
         return IMIN_OK;
     }
 
-    // most tier-2 slots a call uses (one per resident workgroup)
-    static int max_slots(int cus) { return cus * 4; }
+    // most tier-2 slots a call uses (one per resident workgroup: five per
+    // compute unit, the register limit, which the LDS allows too unless the
+    // visited bitset it holds is near its 16 KB maximum)
+    static int max_slots(int cus) { return cus * 5; }
 
     static constexpr int32_t kT2Nodes = 1 << 16;  // nodes a world may reach in a tier-2 slot
     static constexpr int64_t kT2Edges = 1 << 16;  // extra edges it may keep there

@@ -58,11 +58,9 @@ struct BfsRows {
     int e1[NT];
     int start[NT];
 };
-// A one-wave world (tier 0) keeps its rows in the LDS store's dominator
-// arrays, which the BFS leaves unused: 1.25 KB less LDS per wave, one more
-// resident wave per SIMD.  Wider workgroups keep them here.
-template <int NT>
-constexpr bool kRowsInShared = NT != 64;
+// The stores lend the rows LDS that the BFS leaves unused: the LDS stores
+// their dominator arrays, the HBM store its extra-edge staging.  (Tier 0
+// gains a resident wave per SIMD from it, tier 2 a workgroup per CU.)
 
 template <int NT>
 struct WorldShared {
@@ -84,7 +82,6 @@ struct WorldShared {
     unsigned long long acc_reached, acc_live;  // reached nodes (seeds included) and recorded live edges
     long long acc_dsize;  // reached nodes lost by this workgroup's worlds (incremental rounds)
     uint32_t sched;       // first world of the chunk just taken
-    BfsRows<kRowsInShared<NT> ? NT : 1> rows;
     int scan_tmp[NT / 64];
     long long sum_tmp[NT / 64];
 };
@@ -274,6 +271,9 @@ struct HbmStore {
     int32_t* xu2;
     bool sorted;
     __device__ int32_t* level_cursors() { return xv_s; }  // 2 * xs_cap ints while not staged
+    // the BFS rows, in the staging words (2 * xs_cap ints, not yet staged)
+    template <int NT>
+    __device__ BfsRows<NT>& bfs_rows() { return *reinterpret_cast<BfsRows<NT>*>(xv_s); }
     __device__ int sort_cap() const { return 2 * xs_cap; }
     // after every head's level was counted into level_cursors(): the cursors
     // become level starts, every edge goes to its level's range, and the
@@ -516,10 +516,7 @@ __device__ bool bfs_sample(const GraphDev& g, const QueryDev& q, uint32_t w, con
     __syncthreads();
 
     // ---- deeper levels
-    BfsRows<NT>* rows_p;
-    if constexpr (kRowsInShared<NT>) rows_p = &sh.rows;
-    else rows_p = &st.template bfs_rows<NT>();
-    BfsRows<NT>& rows = *rows_p;
+    BfsRows<NT>& rows = st.template bfs_rows<NT>();
     int nlev = 2;  // closed levels: lvl[0..nlev]
     for (;;) {
         const int f0 = st.lvl[nlev - 1];
@@ -1302,6 +1299,7 @@ hipError_t launch_world_tier1_packed(const GraphDev& g, const PackedQuery* pq, i
 // worlds of up to lid_cap nodes and xcap extra edges and hand larger ones
 // on to tier 3, whose few slots are sized for any world of the graph.
 constexpr int kStageX = 2048;
+static_assert(2 * kStageX * sizeof(int32_t) >= sizeof(BfsRows<kTier2NT>), "the BFS rows fit the staging words");
 constexpr int kVisLdsMaxWords = 4096;  // graphs of up to 2^17 nodes keep their bitset in LDS
 
 template <bool VIS_LDS, int TIER>
