@@ -576,7 +576,7 @@ imin_status_t imin_sandimin(imin_graph_t g, const int32_t* seeds, int32_t n_seed
  * candidate runs seven from-scratch passes of the given query (worlds
  * [0, theta)), the candidates taking turns, the first round warming the
  * caches; every candidate must produce the same gains and total (a
- * difference is IMIN_ERR_INTERNAL).  A shape replaces the default (100) only
+ * difference is IMIN_ERR_INTERNAL).  A shape replaces the default (200) only
  * when its median pass is at least 3% faster, and the choice is kept on the
  * handle for every later call on it.  grid0_pct: HOST, out; pass_ms: HOST,
  * out, optional (the chosen shape's median pass time).

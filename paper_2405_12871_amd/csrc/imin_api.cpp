@@ -418,6 +418,12 @@ int cu_count() {
 }
 
 // How an enqueued solve lays out its workspace.
+// The tier-0 world launch's workgroups, in percent of its LDS residency,
+// unless the graph's handle holds a tuned shape: twice the residency, whose
+// workgroups take smaller chunks of worlds as a pass ends (about 10% less
+// tier-0 time than once the residency on the 1M-node trivalency workload).
+constexpr int32_t kDefaultGrid0Pct = 200;
+
 struct WsPlan {
     bool incremental = true;  // resident store and node index (else every round evaluates all worlds)
     size_t big_cap = 0;       // bump-region entries for worlds beyond tier 0 (and as many extra edges)
@@ -972,11 +978,12 @@ struct Session {
         if ((e = sel_g.alloc(sel_parts)) != hipSuccess) return e;
         if ((e = sel_u.alloc(sel_parts)) != hipSuccess) return e;
         if ((e = sel_d.alloc(sel_parts)) != hipSuccess) return e;
-        grid0 = cus * imin::world_tier_blocks_per_cu(0);
+        int32_t pct = kDefaultGrid0Pct;
         if (gh && !ws) {  // an enqueued solve's layout is fixed when its workspace is sized
-            const int32_t pct = gh->tuned_grid0_pct.load(std::memory_order_relaxed);
-            if (pct > 0) grid0 = std::max(cus, (int)((long long)grid0 * pct / 100));
+            const int32_t tuned = gh->tuned_grid0_pct.load(std::memory_order_relaxed);
+            if (tuned > 0) pct = tuned;
         }
+        grid0 = std::max(cus, (int)((long long)cus * imin::world_tier_blocks_per_cu(0) * pct / 100));
         grid1 = cus * imin::world_tier_blocks_per_cu(1);
         // changed-world update: label-rule and replay workgroups of one launch
         grid_r = cus * (int)env_size("IMIN_REPLAY_WG_PER_CU", 3);
@@ -2402,7 +2409,7 @@ static imin_status_t reach_counts_impl(imin_graph_t g, const int32_t* seeds, int
 static imin_status_t autotune_impl(imin_graph_t g, const int32_t* seeds, int32_t n_seeds, int64_t theta,
                                    uint64_t rng_seed, void* stream, int32_t* best_pct, float* best_ms) {
     if (!g || !seeds || !best_pct || theta < 1 || theta > (int64_t)0xFFFFFFFFll) return IMIN_ERR_INVALID;
-    static const int32_t kPct[] = {100, 50, 75, 150, 200, 300};  // the default first
+    static const int32_t kPct[] = {kDefaultGrid0Pct, 50, 75, 100, 150, 300};  // the default first
     constexpr int kCand = (int)(sizeof(kPct) / sizeof(kPct[0]));
     constexpr int kReps = 7;  // the first round warms the caches
     hipStream_t s = (hipStream_t)stream;
