@@ -2863,6 +2863,45 @@ __global__ void k_query_thr(GraphDev g, const uint32_t* excl, uint32_t* thr_q, c
     }
 }
 
+// The same with the exclusion bits staged in LDS, for graphs whose bitset
+// fits (up to about 1.3M nodes): a test from global memory pulls a whole
+// L2 line into the compute unit for 4 bytes, and on the 10^7-slot graph
+// those lines outweigh the thresholds.  One workgroup per compute unit,
+// four slot groups in flight per thread.
+constexpr int kQueryThrNT = 1024;
+__global__ __launch_bounds__(kQueryThrNT) void k_query_thr_lds(GraphDev g, const uint32_t* excl, uint32_t* thr_q,
+                                                               const RoundCtl* ctl, int words) {
+    extern __shared__ uint32_t excl_lds[];
+    if (ctl->stop) return;
+    for (int i = threadIdx.x; i < words; i += kQueryThrNT) excl_lds[i] = excl[i];
+    __syncthreads();
+    const size_t groups = (size_t)g.m_pad / 4;
+    const size_t stride = (size_t)gridDim.x * kQueryThrNT;
+    for (size_t b0 = blockIdx.x * (size_t)kQueryThrNT + threadIdx.x; b0 < groups; b0 += 4 * stride) {
+        int4 c[4];
+        uint4 th[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t b = b0 + j * stride;
+            if (b < groups) {
+                c[j] = *reinterpret_cast<const int4*>(g.col + 4 * b);
+                th[j] = *reinterpret_cast<const uint4*>(g.thr + 4 * b);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const size_t b = b0 + j * stride;
+            if (b >= groups) continue;
+            const size_t e = 4 * b;
+            if (e + 0 < (size_t)g.m && bit_set(excl_lds, c[j].x)) th[j].x = 0u;
+            if (e + 1 < (size_t)g.m && bit_set(excl_lds, c[j].y)) th[j].y = 0u;
+            if (e + 2 < (size_t)g.m && bit_set(excl_lds, c[j].z)) th[j].z = 0u;
+            if (e + 3 < (size_t)g.m && bit_set(excl_lds, c[j].w)) th[j].w = 0u;
+            *reinterpret_cast<uint4*>(thr_q + 4 * b) = th[j];
+        }
+    }
+}
+
 __global__ void k_seed_slots(GraphDev g, const uint32_t* thr_q, const int4* table, const RoundCtl* ctl,
                              int32_t cap, int4* scol, uint4* sthr) {
     if (ctl->stop) return;  // bad seeds: the table is not filled
@@ -2877,8 +2916,21 @@ __global__ void k_seed_slots(GraphDev g, const uint32_t* thr_q, const int4* tabl
 hipError_t launch_query_thresholds(const GraphDev& g, const uint32_t* excl, uint32_t* thr_q, const int4* table,
                                    const RoundCtl* ctl, int32_t chunk_cap, int4* seed_col, uint4* seed_thr,
                                    hipStream_t s) {
-    k_query_thr<<<2048, 256, 0, s>>>(g, excl, thr_q, ctl);
-    hipError_t e = hipGetLastError();
+    const int words = (g.n + 31) / 32;
+    const size_t lds = (size_t)words * sizeof(uint32_t);
+    int dev = 0, cus = 0, lds_max = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    if (e != hipSuccess) return e;
+    if (lds <= (size_t)lds_max && cus > 0) {
+        e = hipFuncSetAttribute((const void*)k_query_thr_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_query_thr_lds<<<(unsigned)cus, kQueryThrNT, lds, s>>>(g, excl, thr_q, ctl, words);
+    } else {
+        k_query_thr<<<2048, 256, 0, s>>>(g, excl, thr_q, ctl);
+    }
+    e = hipGetLastError();
     if (e != hipSuccess || chunk_cap < 1) return e;
     k_seed_slots<<<(chunk_cap + 255) / 256, 256, 0, s>>>(g, thr_q, table, ctl, chunk_cap, seed_col, seed_thr);
     return hipGetLastError();
