@@ -35,6 +35,7 @@
 #include "imin_select.hpp"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace imin {
 
@@ -2923,7 +2924,10 @@ hipError_t launch_query_thresholds(const GraphDev& g, const uint32_t* excl, uint
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
     if (e != hipSuccess) return e;
-    if (lds <= (size_t)lds_max && cus > 0) {
+    // IMIN_QUERY_THR_LDS=0 keeps the bits in global memory (tests compare both ways)
+    const char* env = std::getenv("IMIN_QUERY_THR_LDS");
+    const bool lds_ok = !(env && env[0] == '0');
+    if (lds_ok && lds <= (size_t)lds_max && cus > 0) {
         e = hipFuncSetAttribute((const void*)k_query_thr_lds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         k_query_thr_lds<<<(unsigned)cus, kQueryThrNT, lds, s>>>(g, excl, thr_q, ctl, words);

@@ -93,6 +93,33 @@ def test_level0_drawn_ahead_equals_inline(B, oracle_mod, monkeypatch, case):
         _assert_same(got, want)
 
 
+@pytest.mark.parametrize("case", range(3))
+def test_query_thresholds_with_exclusions_in_lds_or_global(B, oracle_mod, monkeypatch, case):
+    """The query's thresholds with its seeds and blockers folded in, built
+    with the exclusion bits staged in LDS (the default where they fit) and
+    read from global memory (the path of larger graphs): both give the
+    oracle's worlds, with blocked heads next to seeds and rows ending inside a
+    slot group."""
+    rng = np.random.default_rng(720 + case)
+    n = int(rng.integers(50, 3000))
+    m = int(rng.integers(n, 8 * n))
+    src = rng.integers(0, n, m)
+    dst = rng.integers(0, n, m)
+    p = rng.choice([1.0, 0.5, 0.2, 0.05], m).astype(np.float32)
+    g = synth.from_edges(n, src, dst, p, name=f"qthr-{case}")
+    seeds = rng.choice(n, int(rng.integers(1, max(2, n // 20))), replace=False).astype(np.int32)
+    others = np.setdiff1d(np.arange(n), seeds)
+    blocked = rng.choice(others, min(len(others), int(rng.integers(1, 30))), replace=False).tolist()
+    w0, nw, key = int(rng.integers(0, 5000)), int(rng.integers(200, 2000)), 950 + case
+    want = oracle_mod.Query(g, seeds).eval(key, w0, nw, blocked=blocked, per_world=True)
+    G = B.Graph.from_synth(g)
+    for mode in ("1", "0"):
+        monkeypatch.setenv("IMIN_QUERY_THR_LDS", mode)
+        _log(f"query thresholds case {case} lds={mode}: n={n} m={g.m} seeds={len(seeds)} worlds={nw}")
+        got = B.evaluate(G, seeds, w0, nw, key, blocked=blocked, per_world=True)
+        _assert_same(got, want)
+
+
 def test_evaluate_small_workload(B, oracle_mod):
     g, seeds, k, theta = synth.workload("small")
     got, want = _eval_both(B, oracle_mod, g, seeds, 0, theta, 1)
